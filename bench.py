@@ -1,0 +1,350 @@
+#!/usr/bin/env python3
+"""Benchmark of the traversal hot path on one MI355X.
+
+Default workload (one "step"): direction-optimizing BFS (DensePull-SparsePush,
+bitvector frontier, hybrid divisor 20) from 64 seeded sources with out-degree
+>= 1, plus connected components by label propagation, on an R-MAT graph of
+scale 22 and edge factor 16 ((a,b,c,d) = (.57,.19,.19,.05), seed 2, vertex
+ids randomly relabelled, self-loops and repeated pairs removed).
+
+value = GTEPS = (sum over sources of m_reach(s) + m) / step time, where
+m_reach(s) is the number of out-edges of the vertices BFS reaches from s
+(Graph500 convention on a directed graph) and CC counts each edge once.
+
+roofline: the dominant kernel is the frontier loop (k_frontier_loop, one
+cooperative launch per BFS and per CC).  Its algorithmic bytes per launch are
+summed from the per-step trace (frontier size |F|, degree sum D_F, edges
+examined E) with the per-step byte model:
+  SparsePush/DensePush step  12|F| + 8 D_F + 8|F'|
+  DensePull (BFS)             3n/8 + 8U + 4E + 4|F'|     (U unvisited)
+  CC push step               24|F| + 12E + 4|F'|
+  CC pull step               3n/4 + 24n + 4E
+and divided by the launches' GPU time, measured with HIP events that the
+library records on the launch stream.
+
+Other workloads (--workload): pr_rmat16 (20-iteration DensePull PageRank on
+R-MAT scale 16, the PageRank configuration), pr_rmat22, sssp_grid
+(delta-stepping on the 4096x4096 grid with 1% shortcuts).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GTEPS + % HBM peak (PageRank, BFS); learned vs heuristic schedule speedup"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="bfs_cc_rmat22",
+                    choices=["bfs_cc_rmat22", "pr_rmat16", "pr_rmat22", "sssp_grid"])
+    ap.add_argument("--sources", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--schedule", default="", help="k=v,... overrides of the schedule")
+    ap.add_argument("--json-out", default="")
+    return ap.parse_args()
+
+
+def sched_overrides(text):
+    kw = {}
+    for part in filter(None, text.split(",")):
+        k, v = part.split("=")
+        kw[k.strip()] = int(v)
+    return kw
+
+
+# ------------------------------------------------------------- byte model --
+
+def bfs_launch_bytes(n, dirs, fs, ds, es):
+    """Algorithmic bytes of one BFS frontier-loop launch from its step trace."""
+    total = 0
+    visited = 0
+    k = len(fs)
+    for i in range(k):
+        f, d, e = int(fs[i]), int(ds[i]), int(es[i])
+        fnext = int(fs[i + 1]) if i + 1 < k else 0
+        visited += f
+        if dirs[i] == 2:  # DensePull
+            unvisited = n - visited
+            total += 3 * n // 8 + 8 * unvisited + 4 * e + 4 * fnext
+        else:
+            total += 12 * f + 8 * d + 8 * fnext
+    return total
+
+
+def cc_launch_bytes(n, dirs, fs, es):
+    total = 0
+    k = len(fs)
+    for i in range(k):
+        f, e = int(fs[i]), int(es[i])
+        fnext = int(fs[i + 1]) if i + 1 < k else 0
+        if dirs[i] == 2:
+            total += 3 * n // 4 + 24 * n + 4 * e
+        else:
+            total += 24 * f + 12 * e + 4 * fnext
+    return total
+
+
+# ------------------------------------------------------------- workloads --
+
+def make_rmat_graph(scale, seed, weighted=False):
+    import graphgen as gg
+    import paper_1805_00923_amd as gi
+    t0 = time.time()
+    el = gg.rmat(scale, 16, seed=seed)
+    if weighted:
+        el.w = gg.uniform_weights(el.m, seed + 1000, 1, 1000)
+    t1 = time.time()
+    g = gi.Graph.from_edges(el.n, el.src, el.dst, el.w)
+    log("rmat%d: generated in %.1fs, ingested in %.1fs, n=%d m=%d" %
+        (scale, t1 - t0, time.time() - t1, g.n, g.m))
+    return el, g
+
+
+def run_bfs_cc(args, torch, dev):
+    import numpy as np
+
+    import graphgen as gg
+    import paper_1805_00923_amd as gi
+    el, g = make_rmat_graph(22, 2)
+    kw = dict(direction=gi.DENSE_PULL_SPARSE_PUSH, dense_frontier=gi.BITVECTOR, hybrid_divisor=20)
+    kw.update(sched_overrides(args.schedule))
+    g.set_schedule(**kw)
+    srcs = gg.pick_sources(el, args.sources, 3)
+    n, m = g.n, g.m
+    level = torch.empty(n, dtype=torch.int32, device=dev)
+    parent = torch.empty(n, dtype=torch.int32, device=dev)
+    label = torch.empty(n, dtype=torch.int32, device=dev)
+
+    def one_step(record):
+        bytes_, kms, launches, bfs_ms = 0, 0.0, 0, []
+        for s in srcs:
+            g.bfs(int(s), level, parent)
+            st = g.stats()
+            if record:
+                dirs, fs, ds = st.trace()
+                es = st.step_edges_examined()
+                bytes_ += bfs_launch_bytes(n, dirs, fs, ds, es)
+                kms += st.kernel_ms
+                launches += st.launches
+                bfs_ms.append(st.kernel_ms)
+        g.cc(label)
+        st = g.stats()
+        cc_info = None
+        if record:
+            dirs, fs, ds = st.trace()
+            es = st.step_edges_examined()
+            bytes_ += cc_launch_bytes(n, dirs, fs, es)
+            kms += st.kernel_ms
+            launches += st.launches
+            cc_info = (st.kernel_ms, st.steps, st.dense_steps)
+        return bytes_, kms, launches, bfs_ms, cc_info
+
+    # m_reach per source (from the GPU levels; identical every run)
+    odeg = np.diff(g.out_off).astype(np.int64)
+    m_reach = []
+    for s in srcs:
+        g.bfs(int(s), level)
+        lv = level.cpu().numpy()
+        m_reach.append(int(odeg[lv >= 0].sum()))
+    teps_edges = sum(m_reach) + m
+
+    for _ in range(args.warmup):
+        one_step(False)
+    torch.cuda.synchronize()
+    agg_bytes, agg_kms, agg_launch = 0, 0.0, 0
+    bfs_all, cc_all = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b, kms, nl, bfs_ms, cc_info = one_step(True)
+        agg_bytes += b
+        agg_kms += kms
+        agg_launch += nl
+        bfs_all += bfs_ms
+        cc_all.append(cc_info)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt * 1e3 / args.steps
+    value = teps_edges * args.steps / dt / 1e9
+    achieved = agg_bytes / (agg_kms * 1e-3) / 1e9 if agg_kms > 0 else 0.0
+    bfs_ms_med = float(np.median(bfs_all))
+    per_src_gteps = [mr / (t * 1e-3) / 1e9 for mr, t in zip(m_reach * args.steps, bfs_all)]
+    extra = {
+        "n": n, "m": m, "sources": int(len(srcs)),
+        "bfs_kernel_ms_median": round(bfs_ms_med, 4),
+        "bfs_gteps_harmonic_mean": round(len(per_src_gteps) / sum(1.0 / x for x in per_src_gteps), 3),
+        "bfs_gteps_median": round(float(np.median(per_src_gteps)), 3),
+        "cc_kernel_ms": round(float(np.median([c[0] for c in cc_all])), 4),
+        "cc_rounds": int(cc_all[0][1]), "cc_dense_rounds": int(cc_all[0][2]),
+        "avg_launch_ms": round(agg_kms / agg_launch, 5),
+        "launches_per_step": agg_launch // args.steps,
+        "algorithmic_bytes_per_step": agg_bytes // args.steps,
+    }
+    roof = {"bound": "hbm", "kernel": "k_frontier_loop", "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": None,
+            "avg_launch_ms": round(agg_kms / agg_launch, 5),
+            "bytes_per_launch": agg_bytes // agg_launch}
+    config = {"workload": "rmat22_ef16_bfs64_plus_cc", "graph": "rmat scale 22 edge factor 16 "
+              "abcd=.57/.19/.19/.05 seed 2, relabelled, dedup", "n": n, "m": m,
+              "bfs_sources": int(len(srcs)), "schedule": g.schedule().as_dict()}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_bfs_cc(el, srcs[:4], m_reach[:4])
+    return value, "GTEPS", ms_step, "int32", config, roof, cpu, extra
+
+
+def cpu_baseline_bfs_cc(el, srcs, m_reach):
+    import oracle
+    log("cpu baseline: building the oracle graph (not timed)")
+    t0 = time.time()
+    og = oracle.Graph(el)
+    log("oracle graph built in %.1fs" % (time.time() - t0))
+    t0 = time.perf_counter()
+    for s in srcs:
+        oracle.bfs(og, int(s))
+    oracle.cc(og)
+    dt = time.perf_counter() - t0
+    edges = sum(m_reach) + og.m
+    return {"value": round(edges / dt / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": "oracle FIFO BFS from the first %d of the 64 sources + one label-"
+                      "propagation CC on the same RMAT-22 graph, single thread, %.1f s" %
+                      (len(srcs), dt)}
+
+
+def run_pr(args, torch, dev, scale):
+    import numpy as np
+    import paper_1805_00923_amd as gi
+    el, g = make_rmat_graph(scale, 1 if scale == 16 else 2)
+    kw = sched_overrides(args.schedule)
+    g.set_schedule(**kw)
+    n, m = g.n, g.m
+    ranks = torch.empty(n, dtype=torch.float32, device=dev)
+    for _ in range(args.warmup):
+        g.pagerank(ranks, 20, 0.85)
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.pagerank(ranks, 20, 0.85)
+        kms.append(g.stats().kernel_ms)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt * 1e3 / args.steps
+    value = 20.0 * m * args.steps / dt / 1e9
+    bytes_launch = 20 * (4 * m + 16 * n) + 4 * n
+    kmed = float(np.median(kms))
+    achieved = bytes_launch / (kmed * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": "pagerank (all launches of one 20-iteration run)",
+            "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "kernel_ms_median": round(kmed, 5), "bytes_per_run": bytes_launch}
+    config = {"workload": "pagerank20_rmat%d_ef16" % scale, "n": n, "m": m,
+              "schedule": g.schedule().as_dict()}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        og = oracle.Graph(el)
+        reps = 1 if scale > 18 else 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            oracle.pagerank(og, 20, 0.85)
+        dt_c = (time.perf_counter() - t0) / reps
+        cpu = {"value": round(20.0 * og.m / dt_c / 1e9, 5), "unit": "GTEPS", "cores": 1,
+               "kind": "oracle", "sample": "FP64 pull PageRank, 20 iterations, full graph, "
+                                           "single thread, %.3f s per run" % dt_c}
+    extra = {"gteps_kernel": round(20.0 * m / (kmed * 1e-3) / 1e9, 3)}
+    return value, "GTEPS", ms_step, "f32 storage / f64 accumulate", config, roof, cpu, extra
+
+
+def run_sssp(args, torch, dev):
+    import numpy as np
+
+    import graphgen as gg
+    import paper_1805_00923_amd as gi
+    t0 = time.time()
+    el = gg.grid(4096, 4096, 0.01, seed=4)
+    g = gi.Graph.from_edges(el.n, el.src, el.dst, el.w)
+    log("grid: built in %.1fs n=%d m=%d" % (time.time() - t0, g.n, g.m))
+    kw = dict(sssp_delta=4096)
+    kw.update(sched_overrides(args.schedule))
+    g.set_schedule(**kw)
+    srcs = gg.pick_sources(el, 4, 5)
+    dist = torch.empty(g.n, dtype=torch.int32, device=dev)
+    odeg = np.diff(g.out_off).astype(np.int64)
+    m_reach = []
+    for s in srcs:
+        g.sssp(int(s), dist)
+        d = dist.cpu().numpy().view(np.uint32)
+        m_reach.append(int(odeg[d != 0xFFFFFFFF].sum()))
+    for _ in range(args.warmup):
+        for s in srcs:
+            g.sssp(int(s), dist)
+    torch.cuda.synchronize()
+    kms, phases = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for s in srcs:
+            g.sssp(int(s), dist)
+            st = g.stats()
+            kms.append(st.kernel_ms)
+            phases.append(st.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = sum(m_reach) * args.steps / dt / 1e9
+    n_reach = g.n
+    bytes_run = 12 * int(np.mean(m_reach)) + 12 * n_reach
+    kmed = float(np.median(kms))
+    achieved = bytes_run / (kmed * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": "k_sssp_loop", "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": None, "kernel_ms_median": round(kmed, 4)}
+    config = {"workload": "sssp_grid4096_shortcut1pct", "n": g.n, "m": g.m, "sources": 4,
+              "schedule": g.schedule().as_dict()}
+    extra = {"phases_median": int(np.median(phases))}
+    return value, "GTEPS", dt * 1e3 / args.steps, "uint32", config, roof, None, extra
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; --gpus %d is not supported (the library is a "
+              "single-device build)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    dev = torch.device("cuda:0")
+    if args.workload == "bfs_cc_rmat22":
+        res = run_bfs_cc(args, torch, dev)
+    elif args.workload == "pr_rmat16":
+        res = run_pr(args, torch, dev, 16)
+    elif args.workload == "pr_rmat22":
+        res = run_pr(args, torch, dev, 22)
+    else:
+        res = run_sssp(args, torch, dev)
+    value, unit, ms_step, dtype, config, roof, cpu, extra = res
+    line = {"metric": METRIC, "value": round(value, 4), "unit": unit, "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config, "roofline": roof, "cpu_baseline": cpu,
+            "detail": extra}
+    s = json.dumps(line)
+    if args.json_out:
+        with open(args.json_out, "w") as f:
+            f.write(s + "\n")
+    print(s, flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,253 @@
+/*
+ * graphit_mi.h -- C ABI of an MI355X (gfx950) graph-traversal library that
+ * implements the data-parallel core of GraphIt (Zhang et al., "GraphIt: A
+ * High-Performance Graph DSL", OOPSLA 2018): edgeset.apply over a frontier
+ * vertexset in each of the paper's traversal schedules, driving PageRank,
+ * BFS, connected components and single-source shortest paths.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Plain C types only.  "host" pointers are ordinary CPU memory; "device"
+ *   pointers are HIP device memory on the current device (for instance the
+ *   data pointer of a torch CUDA tensor).  Streams are hipStream_t passed as
+ *   void*; NULL means the default stream.
+ * - Every call returns a gi_status.  Arguments are checked on the host before
+ *   any device work; on error nothing is enqueued and outputs are left
+ *   unspecified.  gi_last_error() gives a message for the calling thread's
+ *   last failing call.
+ * - Algorithm calls enqueue their kernels on the given stream and then wait
+ *   for that stream before returning (the frontier loop reads a few bytes of
+ *   per-step statistics back); their device outputs are complete on return.
+ * - A gi_graph owns device copies of its adjacency and a workspace sized at
+ *   creation.  It is not thread-safe: one call at a time per graph.  Distinct
+ *   graphs may be used from distinct threads and streams.
+ * - Vertex ids are int32 in [0, n); edge counts are limited to 2^31-1 so that
+ *   int32 offsets suffice (the evaluation notes the same 32-bit limit).
+ */
+#ifndef GRAPHIT_MI_H
+#define GRAPHIT_MI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GI_ABI_VERSION 1
+
+typedef enum gi_status {
+  GI_OK = 0,
+  GI_ERR_INVALID_ARG = -1,   /* argument out of range, malformed adjacency   */
+  GI_ERR_OUT_OF_MEMORY = -2, /* host or device allocation failed             */
+  GI_ERR_DEVICE = -3,        /* a HIP call or kernel reported an error       */
+  GI_ERR_UNSUPPORTED = -4,   /* schedule combination not offered             */
+  GI_ERR_OVERFLOW = -5       /* count or distance exceeds its integer type   */
+} gi_status;
+
+typedef struct gi_graph gi_graph;
+
+/* Traversal directions: configApplyDirection options of the scheduling
+ * language (scheduling-language table; section 2, direction optimization). */
+enum {
+  GI_DIR_SPARSE_PUSH = 0,            /* frontier as sparse array, out-edges, atomics   */
+  GI_DIR_DENSE_PUSH = 1,             /* all vertices, dense frontier test, out-edges    */
+  GI_DIR_DENSE_PULL = 2,             /* all vertices, in-edges, no atomics              */
+  GI_DIR_DENSE_PULL_SPARSE_PUSH = 3, /* per step: DensePull if frontier is large        */
+  GI_DIR_DENSE_PUSH_SPARSE_PUSH = 4  /* per step: DensePush if frontier is large        */
+};
+
+/* Dense vertexset representation: configApplyDenseVertexSet options. */
+enum { GI_FRONTIER_BITVECTOR = 0, GI_FRONTIER_BOOLMAP = 1 };
+
+/* Segmented subgraphs: configApplyNumSSG options (section 2, cache
+ * partitioning; section 6, SSG code generation). */
+enum { GI_SEG_FIXED_VERTEX_COUNT = 0, GI_SEG_EDGE_AWARE_VERTEX_COUNT = 1 };
+
+/* Schedule of a graph's edgeset.apply.  One field per scheduling function
+ * (scheduling-language table), restated for a GPU:
+ *   direction        configApplyDirection
+ *   dense_frontier   configApplyDenseVertexSet (bitvector or bool array)
+ *   num_segments     configApplyNumSSG: >1 splits the DensePull sources into
+ *                    that many segmented subgraphs processed in order
+ *   segment_strategy fixed-vertex-count or edge-aware-vertex-count
+ *   hybrid_divisor   hybrid directions choose the dense side when
+ *                    |F| + sum of out-degrees of F > m / hybrid_divisor
+ *                    (section 2: sum of out-degrees against a threshold)
+ *   persistent       1: the whole frontier loop runs in one cooperative
+ *                    launch with device-side direction decisions;
+ *                    0: one launch per step, decisions on the host
+ *   pull_block_edges PageRank DensePull: in-edges staged in LDS per
+ *                    destination block, 64..8192 (0 = library default 2048)
+ *   block_threads    threads per workgroup: 128, 256 or 512 (0 = library
+ *                    default 256; the frontier loops take 256 or 512)
+ *   sssp_delta       bucket width of delta-stepping (0 = library default)
+ * Use gi_schedule_init for defaults; gi_set_schedule returns
+ * GI_ERR_UNSUPPORTED for a combination it does not offer. */
+typedef struct gi_schedule {
+  int32_t direction;
+  int32_t dense_frontier;
+  int32_t num_segments;
+  int32_t segment_strategy;
+  int32_t hybrid_divisor;
+  int32_t persistent;
+  int32_t pull_block_edges;
+  int32_t block_threads;
+  uint32_t sssp_delta;
+  int32_t reserved[7];
+} gi_schedule;
+
+/* Per-run statistics of the last algorithm call on a graph. */
+#define GI_MAX_TRACE 4096
+typedef struct gi_run_stats {
+  int32_t algorithm;      /* 0 PageRank, 1 BFS, 2 CC, 3 SSSP                   */
+  int32_t steps;          /* edgeset.apply steps executed                        */
+  int32_t dense_steps;    /* of which dense (pull or dense push)                 */
+  int32_t trace_len;      /* entries valid in the arrays below (<= GI_MAX_TRACE) */
+  int64_t edges_examined; /* sum over steps of sum of degrees of the frontier    */
+  float kernel_ms;        /* GPU time between HIP events recorded on the call's
+                             stream before the first and after the last launch of
+                             the algorithm's main kernel(s)                      */
+  int32_t launches;       /* main-kernel launches in that interval               */
+  int8_t step_direction[GI_MAX_TRACE]; /* GI_DIR_* actually run per step          */
+  int32_t step_frontier[GI_MAX_TRACE]; /* |F| entering each step                  */
+  int64_t step_degree_sum[GI_MAX_TRACE]; /* sum of out-degrees of that frontier   */
+  int64_t step_edges[GI_MAX_TRACE];      /* edges the step examined (pull: in-edges
+                                            scanned up to the first frontier hit)  */
+} gi_run_stats;
+
+/* ---- library ----------------------------------------------------------- */
+
+/* Message for the calling thread's last failing call ("" if none). */
+const char* gi_last_error(void);
+
+/* GI_ABI_VERSION of the loaded library. */
+int32_t gi_abi_version(void);
+
+/* ---- graph ingest (host) ---------------------------------------------- */
+
+/* Adjacency build from raw directed records (src[k] -> dst[k], k < nrec),
+ * the edgeset load of the algorithm language (section 3).  Self-loops are
+ * dropped, repeated pairs collapse to one edge keeping the smallest weight,
+ * and each row is sorted by neighbour id.
+ *   n                vertices; every id must lie in [0, n)
+ *   src, dst         host, nrec entries each
+ *   w                host, nrec weights, or NULL for an unweighted graph
+ *   off              host out, n+1 entries (row offsets)
+ *   idx              host out, capacity nrec (neighbour ids)
+ *   w_out            host out, capacity nrec, or NULL
+ *   m_out            host out, edges kept
+ * Pass (dst, src) to build the in-adjacency (CSC).  Errors: INVALID_ARG for
+ * a NULL array or an id out of range, OVERFLOW if more than 2^31-1 edges
+ * remain, OUT_OF_MEMORY. */
+gi_status gi_build_adjacency(int32_t n, int64_t nrec, const int32_t* src, const int32_t* dst,
+                             const uint32_t* w, int32_t* off, int32_t* idx, uint32_t* w_out,
+                             int64_t* m_out);
+
+/* ---- graph on the device ---------------------------------------------- */
+
+/* Copy an adjacency to the device (section 3: edgeset with getOutNgh and
+ * getInNgh; the out-degree vector of the PageRankDelta program is derived).
+ *   out_off/out_idx  host CSR: n+1 offsets, m ids, rows sorted ascending
+ *   out_w            host, m weights aligned with out_idx, or NULL
+ *   in_off/in_idx    host CSC (the transpose), or both NULL to have the
+ *                    library transpose the CSR
+ *   in_w             host, weights aligned with in_idx, or NULL (derived
+ *                    when out_w is given and in_off is NULL)
+ * Validates monotone offsets, ids in range, strictly ascending rows, and that
+ * the CSC holds exactly the CSR's edges (and weights).
+ * Errors: INVALID_ARG, OVERFLOW (m > 2^31-1), OUT_OF_MEMORY, DEVICE. */
+gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_off, const int32_t* out_idx,
+                          const uint32_t* out_w, const int32_t* in_off, const int32_t* in_idx,
+                          const uint32_t* in_w, gi_graph** out);
+
+/* Release the graph and its device memory (NULL is a no-op). */
+gi_status gi_graph_destroy(gi_graph* g);
+
+/* n, m, and the largest out- and in-degree. */
+gi_status gi_graph_info(const gi_graph* g, int32_t* n, int64_t* m, int32_t* max_out_degree,
+                        int32_t* max_in_degree);
+
+/* Copy the device CSC back to host arrays (n+1, m, m-or-NULL entries). */
+gi_status gi_graph_copy_in_adjacency(const gi_graph* g, int32_t* in_off, int32_t* in_idx,
+                                     uint32_t* in_w);
+
+/* ---- schedule ----------------------------------------------------------- */
+
+gi_status gi_schedule_init(gi_schedule* s);
+gi_status gi_set_schedule(gi_graph* g, const gi_schedule* s);
+gi_status gi_get_schedule(const gi_graph* g, gi_schedule* s);
+
+/* Hybrid direction rule (section 2): nonzero when the dense side should run,
+ * i.e. frontier_size + frontier_degree_sum > edges / divisor.  Pure host
+ * function, shared by the host-driven loop and mirrored on the device. */
+int32_t gi_hybrid_choose_dense(int64_t frontier_size, int64_t frontier_degree_sum, int64_t edges,
+                               int32_t divisor);
+
+/* ---- algorithms (device outputs, stream ordered) --------------------- */
+
+/* PageRank, pull form of the power iteration that PageRankDelta computes
+ * with every vertex active (section 2, PageRankDelta; evaluation: 20
+ * iterations, damping 0.85):
+ *   x_0 = 1/n;  x_{k+1}[v] = (1-damping)/n + damping * sum_{u->v} x_k[u]/outdeg(u).
+ * Runs DensePull (optionally segmented, num_segments > 1) regardless of the
+ * direction field.  FP32 storage, FP64 accumulation.
+ *   ranks  device out, n floats: x_iters.
+ * Errors: INVALID_ARG (iters < 0, damping outside [0,1], NULL), DEVICE. */
+gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, float* ranks, void* stream);
+
+/* Breadth-first search from src along out-edges (evaluation, algorithms
+ * paragraph), one edgeset.apply per level in the scheduled direction(s).
+ *   level   device out, n int32: hops from src, -1 when unreachable
+ *   parent  device out, n int32, or NULL: a BFS tree (parent[src] = src,
+ *           -1 when unreachable); which valid parent is reported depends
+ *           on the schedule and on timing.
+ * Errors: INVALID_ARG (src out of range, NULL level), DEVICE. */
+gi_status gi_bfs(gi_graph* g, int32_t src, int32_t* level, int32_t* parent, void* stream);
+
+/* Connected components by synchronous label propagation over edges taken
+ * in both directions (evaluation, algorithms paragraph):
+ *   label   device out, n int32: smallest vertex id of v's weakly
+ *           connected component.
+ * Errors: INVALID_ARG, DEVICE. */
+gi_status gi_cc(gi_graph* g, int32_t* label, void* stream);
+
+/* Single-source shortest paths over uint32 weights by delta-stepping
+ * (bucket width sssp_delta) with atomic-min relaxation (the paper's asyncMin
+ * reduction, compiler section).
+ *   dist    device out, n uint32: least path weight, UINT32_MAX when
+ *           unreachable.
+ * Errors: INVALID_ARG (unweighted graph, src out of range), OVERFLOW (a
+ * finite distance reached UINT32_MAX), DEVICE. */
+gi_status gi_sssp(gi_graph* g, int32_t src, uint32_t* dist, void* stream);
+
+/* Statistics of the last algorithm call on g. */
+gi_status gi_get_run_stats(const gi_graph* g, gi_run_stats* out);
+
+/* ---- frontier primitives (device, stream ordered) -------------------- */
+/* Dense and sparse vertexset representations (section 2, direction
+ * optimization and frontier data structure; scheduling-language table,
+ * configApplyDenseVertexSet).  Bitvector: uint64 words, bit v%64 of word
+ * v/64 set iff v is in the set; words beyond n must be provided
+ * (ceil(n/64) words).  Bool map: one byte per vertex, nonzero iff member. */
+
+/* Sparse array (count distinct ids) -> bitvector (cleared first). */
+gi_status gi_frontier_sparse_to_bitvec(int32_t n, const int32_t* ids, int32_t count, uint64_t* bv,
+                                       void* stream);
+/* Bitvector -> sparse array in ascending id order; *count_dev receives the
+ * number of members.  ids needs room for every member. */
+gi_status gi_frontier_bitvec_to_sparse(int32_t n, const uint64_t* bv, int32_t* ids,
+                                       int32_t* count_dev, void* stream);
+/* Bitvector <-> bool map. */
+gi_status gi_frontier_bitvec_to_boolmap(int32_t n, const uint64_t* bv, uint8_t* bm, void* stream);
+gi_status gi_frontier_boolmap_to_bitvec(int32_t n, const uint8_t* bm, uint64_t* bv, void* stream);
+/* Frontier statistics for the hybrid rule: out[0] = count, out[1] = sum of
+ * out-degrees of the members of a sparse array (device int64[2]). */
+gi_status gi_frontier_degree_sum(const gi_graph* g, const int32_t* ids, int32_t count,
+                                 int64_t* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRAPHIT_MI_H */

@@ -1,0 +1,307 @@
+"""Python binding of libgraphit_mi.so (the C ABI in include/graphit_mi.h).
+
+Argument marshalling only: every step of the traversals runs in the HIP
+kernels of the library.  Device buffers are torch CUDA tensors (or raw
+device addresses as ints); streams are torch streams (default: the current
+stream).  The library must be built (``python -m paper_1805_00923_amd.build``
+or ``__graft_entry__.build()``); importing this package without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libgraphit_mi.so")
+
+GI_OK = 0
+GI_ERR_INVALID_ARG = -1
+GI_ERR_OUT_OF_MEMORY = -2
+GI_ERR_DEVICE = -3
+GI_ERR_UNSUPPORTED = -4
+GI_ERR_OVERFLOW = -5
+
+SPARSE_PUSH = 0
+DENSE_PUSH = 1
+DENSE_PULL = 2
+DENSE_PULL_SPARSE_PUSH = 3
+DENSE_PUSH_SPARSE_PUSH = 4
+DIRECTIONS = {
+    "SparsePush": SPARSE_PUSH,
+    "DensePush": DENSE_PUSH,
+    "DensePull": DENSE_PULL,
+    "DensePull-SparsePush": DENSE_PULL_SPARSE_PUSH,
+    "DensePush-SparsePush": DENSE_PUSH_SPARSE_PUSH,
+}
+BITVECTOR = 0
+BOOLMAP = 1
+FIXED_VERTEX_COUNT = 0
+EDGE_AWARE_VERTEX_COUNT = 1
+MAX_TRACE = 4096
+
+
+class GiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("gi status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("direction", ctypes.c_int32), ("dense_frontier", ctypes.c_int32),
+                ("num_segments", ctypes.c_int32), ("segment_strategy", ctypes.c_int32),
+                ("hybrid_divisor", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("pull_block_edges", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("sssp_delta", ctypes.c_uint32), ("reserved", ctypes.c_int32 * 7)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("algorithm", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("dense_steps", ctypes.c_int32), ("trace_len", ctypes.c_int32),
+                ("edges_examined", ctypes.c_int64),
+                ("kernel_ms", ctypes.c_float), ("launches", ctypes.c_int32),
+                ("step_direction", ctypes.c_int8 * MAX_TRACE),
+                ("step_frontier", ctypes.c_int32 * MAX_TRACE),
+                ("step_degree_sum", ctypes.c_int64 * MAX_TRACE),
+                ("step_edges", ctypes.c_int64 * MAX_TRACE)]
+
+    def trace(self):
+        k = self.trace_len
+        return (np.frombuffer(self.step_direction, np.int8)[:k].copy(),
+                np.frombuffer(self.step_frontier, np.int32)[:k].copy(),
+                np.frombuffer(self.step_degree_sum, np.int64)[:k].copy())
+
+    def step_edges_examined(self):
+        return np.frombuffer(self.step_edges, np.int64)[:self.trace_len].copy()
+
+
+# every symbol the header declares, with its ctypes signature
+_vp, _i32, _i64, _u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+_SIGS = {
+    "gi_last_error": (ctypes.c_char_p, []),
+    "gi_abi_version": (_i32, []),
+    "gi_build_adjacency": (ctypes.c_int, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "gi_graph_create": (ctypes.c_int, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "gi_graph_destroy": (ctypes.c_int, [_vp]),
+    "gi_graph_info": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "gi_graph_copy_in_adjacency": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "gi_schedule_init": (ctypes.c_int, [_vp]),
+    "gi_set_schedule": (ctypes.c_int, [_vp, _vp]),
+    "gi_get_schedule": (ctypes.c_int, [_vp, _vp]),
+    "gi_hybrid_choose_dense": (_i32, [_i64, _i64, _i64, _i32]),
+    "gi_pagerank": (ctypes.c_int, [_vp, _i32, ctypes.c_float, _vp, _vp]),
+    "gi_bfs": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp]),
+    "gi_cc": (ctypes.c_int, [_vp, _vp, _vp]),
+    "gi_sssp": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
+    "gi_get_run_stats": (ctypes.c_int, [_vp, _vp]),
+    "gi_frontier_sparse_to_bitvec": (ctypes.c_int, [_i32, _vp, _i32, _vp, _vp]),
+    "gi_frontier_bitvec_to_sparse": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp]),
+    "gi_frontier_bitvec_to_boolmap": (ctypes.c_int, [_i32, _vp, _vp, _vp]),
+    "gi_frontier_boolmap_to_bitvec": (ctypes.c_int, [_i32, _vp, _vp, _vp]),
+    "gi_frontier_degree_sum": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp]),
+}
+
+
+def _load():
+    # torch ships its own HIP runtime with the same SONAME as /opt/rocm's; load
+    # torch first so that the library binds to the runtime torch uses and the
+    # process holds exactly one HIP runtime.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libgraphit_mi.so is not built (%s); run "
+                          "`python -m paper_1805_00923_amd.build`" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def last_error():
+    return lib.gi_last_error().decode()
+
+
+def _check(st):
+    if st != GI_OK:
+        raise GiError(st, last_error())
+
+
+def _dptr(x):
+    """Device address of a torch CUDA tensor (or an int address)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if not x.is_cuda:
+        raise ValueError("expected a device (CUDA/HIP) tensor")
+    if not x.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _hptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def hybrid_choose_dense(frontier_size, degree_sum, edges, divisor=20):
+    return bool(lib.gi_hybrid_choose_dense(frontier_size, degree_sum, edges, divisor))
+
+
+def build_adjacency(n, src, dst, w=None):
+    """Host adjacency build (self-loops dropped, repeats merged keeping the
+    smallest weight, rows sorted).  Returns (off, idx, w_or_None)."""
+    src = np.ascontiguousarray(src, np.int32)
+    dst = np.ascontiguousarray(dst, np.int32)
+    nrec = src.shape[0]
+    off = np.empty(n + 1, np.int32)
+    idx = np.empty(max(nrec, 1), np.int32)
+    wout = None
+    if w is not None:
+        w = np.ascontiguousarray(w, np.uint32)
+        wout = np.empty(max(nrec, 1), np.uint32)
+    m = ctypes.c_int64(0)
+    _check(lib.gi_build_adjacency(n, nrec, _hptr(src), _hptr(dst), _hptr(w), _hptr(off),
+                                  _hptr(idx), _hptr(wout), ctypes.byref(m)))
+    m = m.value
+    return off, idx[:m].copy(), (None if wout is None else wout[:m].copy())
+
+
+def default_schedule(**kw):
+    s = Schedule()
+    _check(lib.gi_schedule_init(ctypes.byref(s)))
+    for k, v in kw.items():
+        if k == "direction" and isinstance(v, str):
+            v = DIRECTIONS[v]
+        if k == "dense_frontier" and isinstance(v, str):
+            v = {"bitvector": BITVECTOR, "boolmap": BOOLMAP, "bool-array": BOOLMAP}[v]
+        setattr(s, k, v)
+    return s
+
+
+class Graph:
+    """A graph on the device (CSR + CSC, optional uint32 weights)."""
+
+    def __init__(self, n, out_off, out_idx, out_w=None, in_off=None, in_idx=None, in_w=None):
+        self._h = ctypes.c_void_p(None)
+        out_off = np.ascontiguousarray(out_off, np.int32)
+        out_idx = np.ascontiguousarray(out_idx, np.int32)
+        out_w = None if out_w is None else np.ascontiguousarray(out_w, np.uint32)
+        in_off = None if in_off is None else np.ascontiguousarray(in_off, np.int32)
+        in_idx = None if in_idx is None else np.ascontiguousarray(in_idx, np.int32)
+        in_w = None if in_w is None else np.ascontiguousarray(in_w, np.uint32)
+        m = int(out_idx.shape[0])
+        _check(lib.gi_graph_create(int(n), m, _hptr(out_off), _hptr(out_idx), _hptr(out_w),
+                                   _hptr(in_off), _hptr(in_idx), _hptr(in_w),
+                                   ctypes.byref(self._h)))
+        self.n = int(n)
+        self.m = m
+        self.weighted = out_w is not None
+        self.out_off = out_off  # host copy of the row offsets (out-degrees)
+
+    @classmethod
+    def from_edges(cls, n, src, dst, w=None, build_in=True):
+        off, idx, ww = build_adjacency(n, src, dst, w)
+        if build_in:
+            ioff, iidx, iw = build_adjacency(n, dst, src, w)
+            return cls(n, off, idx, ww, ioff, iidx, iw)
+        return cls(n, off, idx, ww)
+
+    def close(self):
+        if self._h:
+            lib.gi_graph_destroy(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        n, m, mo, mi = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.gi_graph_info(self._h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(mo),
+                                 ctypes.byref(mi)))
+        return {"n": n.value, "m": m.value, "max_out_degree": mo.value, "max_in_degree": mi.value}
+
+    def in_adjacency(self):
+        off = np.empty(self.n + 1, np.int32)
+        idx = np.empty(max(self.m, 1), np.int32)
+        w = np.empty(max(self.m, 1), np.uint32) if self.weighted else None
+        _check(lib.gi_graph_copy_in_adjacency(self._h, _hptr(off), _hptr(idx), _hptr(w)))
+        return off, idx[:self.m], (None if w is None else w[:self.m])
+
+    def set_schedule(self, sched=None, **kw):
+        s = sched if sched is not None else default_schedule(**kw)
+        _check(lib.gi_set_schedule(self._h, ctypes.byref(s)))
+        return s
+
+    def schedule(self):
+        s = Schedule()
+        _check(lib.gi_get_schedule(self._h, ctypes.byref(s)))
+        return s
+
+    def stats(self):
+        r = RunStats()
+        _check(lib.gi_get_run_stats(self._h, ctypes.byref(r)))
+        return r
+
+    # ---- algorithms: outputs are device tensors supplied by the caller ----
+    def pagerank(self, ranks, iters=20, damping=0.85, stream=None):
+        _check(lib.gi_pagerank(self._h, int(iters), float(damping), _dptr(ranks), _stream(stream)))
+        return ranks
+
+    def bfs(self, src, level, parent=None, stream=None):
+        _check(lib.gi_bfs(self._h, int(src), _dptr(level), _dptr(parent), _stream(stream)))
+        return level
+
+    def cc(self, label, stream=None):
+        _check(lib.gi_cc(self._h, _dptr(label), _stream(stream)))
+        return label
+
+    def sssp(self, src, dist, stream=None):
+        _check(lib.gi_sssp(self._h, int(src), _dptr(dist), _stream(stream)))
+        return dist
+
+    def frontier_degree_sum(self, ids, count, out, stream=None):
+        _check(lib.gi_frontier_degree_sum(self._h, _dptr(ids), int(count), _dptr(out),
+                                          _stream(stream)))
+        return out
+
+
+def sparse_to_bitvec(n, ids, count, bv, stream=None):
+    _check(lib.gi_frontier_sparse_to_bitvec(int(n), _dptr(ids), int(count), _dptr(bv),
+                                            _stream(stream)))
+    return bv
+
+
+def bitvec_to_sparse(n, bv, ids, count_dev, stream=None):
+    _check(lib.gi_frontier_bitvec_to_sparse(int(n), _dptr(bv), _dptr(ids), _dptr(count_dev),
+                                            _stream(stream)))
+    return ids
+
+
+def bitvec_to_boolmap(n, bv, bm, stream=None):
+    _check(lib.gi_frontier_bitvec_to_boolmap(int(n), _dptr(bv), _dptr(bm), _stream(stream)))
+    return bm
+
+
+def boolmap_to_bitvec(n, bm, bv, stream=None):
+    _check(lib.gi_frontier_boolmap_to_bitvec(int(n), _dptr(bm), _dptr(bv), _stream(stream)))
+    return bv

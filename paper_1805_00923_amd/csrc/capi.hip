@@ -1,0 +1,885 @@
+// C ABI: argument checks, graph ownership, schedules and the host side of
+// each algorithm.  Everything here is host code; the per-step work runs in
+// the kernels of bfs_cc.hip, pagerank.hip, sssp.hip and frontier.hip.
+#include <algorithm>
+#include <cstdarg>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace gi;
+
+// ---------------------------------------------------------------- errors --
+
+static thread_local std::string g_err;
+
+static gi_status fail(gi_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static gi_status fail(gi_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(GI_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));       \
+  } while (0)
+
+#define LAUNCH_TRY(call)                                                               \
+  do {                                                                                 \
+    if ((call) != 0) {                                                                 \
+      hipError_t e_ = hipGetLastError();                                               \
+      return fail(GI_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));       \
+    }                                                                                  \
+  } while (0)
+
+extern "C" const char* gi_last_error(void) { return g_err.c_str(); }
+extern "C" int32_t gi_abi_version(void) { return GI_ABI_VERSION; }
+
+// ------------------------------------------------------------ the graph --
+
+namespace {
+
+struct SegDev {
+  int32_t* off = nullptr;
+  int32_t* idx = nullptr;
+  int32_t* dst = nullptr;
+  int2* table = nullptr;
+  int ntab = 0;
+  int nrows = 0;
+  int64_t nnz = 0;
+};
+
+}  // namespace
+
+struct gi_graph {
+  int32_t n = 0;
+  int64_t m = 0;
+  int32_t max_out = 0, max_in = 0;
+  bool weighted = false;
+  int device = 0;
+  std::vector<void*> allocs;       // graph-lifetime device allocations
+  std::vector<void*> sched_allocs; // schedule-lifetime device allocations
+  // adjacency on the device
+  int32_t *out_off = nullptr, *out_idx = nullptr, *in_off = nullptr, *in_idx = nullptr;
+  int32_t* outdeg = nullptr;
+  uint32_t *out_w = nullptr, *in_w = nullptr;
+  // host copy of the in-adjacency (destination blocks and segments are built from it)
+  std::vector<int32_t> h_in_off, h_in_idx, h_outdeg;
+  gi_schedule sched{};
+  // PageRank destination blocks
+  int2* pr_table = nullptr;
+  int pr_ntab = 0, pr_cap_e = 0, pr_cap_v = 0;
+  std::vector<SegDev> segs;
+  double* pr_acc = nullptr;
+  // traversal workspace
+  int32_t* sa[2] = {nullptr, nullptr};
+  uint64_t* dbv[3] = {nullptr, nullptr, nullptr};
+  uint8_t* dbm[3] = {nullptr, nullptr, nullptr};
+  uint64_t* vis = nullptr;
+  int32_t* lab = nullptr;
+  float* contrib[2] = {nullptr, nullptr};
+  int32_t* scratch = nullptr;  // ceil(n/64)+1 ints
+  int32_t* far[2] = {nullptr, nullptr};
+  int32_t* in_far = nullptr;
+  Control* ctl = nullptr;
+  LoopState* st = nullptr;
+  SsspState* sst = nullptr;
+  Control* h_ctl = nullptr;    // pinned host mirror
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  gi_run_stats stats{};
+};
+
+template <typename T>
+static gi_status dev_alloc(gi_graph* g, std::vector<void*>& list, T** p, size_t count) {
+  void* q = nullptr;
+  const size_t bytes = std::max<size_t>(1, count * sizeof(T));
+  if (hipMalloc(&q, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(GI_ERR_OUT_OF_MEMORY, "device allocation of %zu bytes failed", bytes);
+  }
+  list.push_back(q);
+  *p = static_cast<T*>(q);
+  return GI_OK;
+}
+
+static void free_list(std::vector<void*>& list) {
+  for (void* p : list) (void)hipFree(p);
+  list.clear();
+}
+
+// ------------------------------------------------------ adjacency checks --
+
+static gi_status check_adjacency(int32_t n, int64_t m, const int32_t* off, const int32_t* idx,
+                                 const char* what) {
+  if (!off || (m > 0 && !idx)) return fail(GI_ERR_INVALID_ARG, "%s: NULL array", what);
+  if (off[0] != 0) return fail(GI_ERR_INVALID_ARG, "%s: off[0] = %d, expected 0", what, off[0]);
+  if ((int64_t)off[n] != m)
+    return fail(GI_ERR_INVALID_ARG, "%s: off[n] = %d does not equal m = %lld", what, off[n],
+                (long long)m);
+  for (int32_t v = 0; v < n; ++v) {
+    const int32_t b = off[v], e = off[v + 1];
+    if (e < b) return fail(GI_ERR_INVALID_ARG, "%s: offsets decrease at row %d", what, v);
+    for (int32_t k = b; k < e; ++k) {
+      const int32_t u = idx[k];
+      if (u < 0 || u >= n)
+        return fail(GI_ERR_INVALID_ARG, "%s: neighbour %d of row %d out of range", what, u, v);
+      if (k > b && idx[k - 1] >= u)
+        return fail(GI_ERR_INVALID_ARG, "%s: row %d not strictly ascending", what, v);
+    }
+  }
+  return GI_OK;
+}
+
+// ------------------------------------------------------------- ingest ----
+
+// Adjacency from raw records: rows bucketed by source, each row sorted by
+// (neighbour, weight) packed into 64-bit keys, repeated neighbours dropped so
+// that the smallest weight survives.  Rows are sorted by worker threads.
+extern "C" gi_status gi_build_adjacency(int32_t n, int64_t nrec, const int32_t* src,
+                                        const int32_t* dst, const uint32_t* w, int32_t* off,
+                                        int32_t* idx, uint32_t* w_out, int64_t* m_out) {
+  if (n < 1) return fail(GI_ERR_INVALID_ARG, "n must be >= 1 (got %d)", n);
+  if (nrec < 0) return fail(GI_ERR_INVALID_ARG, "negative record count");
+  if ((nrec > 0 && (!src || !dst || !idx)) || !off || !m_out)
+    return fail(GI_ERR_INVALID_ARG, "NULL array");
+  if (w_out && !w) return fail(GI_ERR_INVALID_ARG, "w_out given without input weights");
+  for (int64_t k = 0; k < nrec; ++k)
+    if ((uint32_t)src[k] >= (uint32_t)n || (uint32_t)dst[k] >= (uint32_t)n)
+      return fail(GI_ERR_INVALID_ARG, "record %lld has an endpoint outside [0, %d)", (long long)k, n);
+  std::vector<int64_t> start((size_t)n + 1, 0);
+  for (int64_t k = 0; k < nrec; ++k)
+    if (src[k] != dst[k]) start[(size_t)src[k] + 1]++;
+  for (int32_t v = 0; v < n; ++v) start[(size_t)v + 1] += start[(size_t)v];
+  std::vector<uint64_t> keys;
+  try {
+    keys.resize((size_t)start[(size_t)n]);
+  } catch (...) {
+    return fail(GI_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+  {
+    std::vector<int64_t> cur(start.begin(), start.end() - 1);
+    for (int64_t k = 0; k < nrec; ++k) {
+      if (src[k] == dst[k]) continue;
+      const uint64_t key = ((uint64_t)(uint32_t)dst[k] << 32) | (uint64_t)(w ? w[k] : 0u);
+      keys[(size_t)cur[(size_t)src[k]]++] = key;
+    }
+  }
+  // sort and de-duplicate rows in parallel; kept[v] = distinct neighbours of v
+  std::vector<int64_t> kept((size_t)n, 0);
+  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  auto work = [&](unsigned t) {
+    for (int32_t v = (int32_t)t; v < n; v += (int32_t)nth) {
+      uint64_t* b = keys.data() + start[(size_t)v];
+      uint64_t* e = keys.data() + start[(size_t)v + 1];
+      std::sort(b, e);
+      int64_t k = 0;
+      for (uint64_t* p = b; p < e; ++p)
+        if (k == 0 || (b[k - 1] >> 32) != (*p >> 32)) b[k++] = *p;
+      kept[(size_t)v] = k;
+    }
+  };
+  std::vector<std::thread> pool;
+  for (unsigned t = 1; t < nth; ++t) pool.emplace_back(work, t);
+  work(0);
+  for (auto& th : pool) th.join();
+  int64_t m = 0;
+  off[0] = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    const uint64_t* b = keys.data() + start[(size_t)v];
+    for (int64_t k = 0; k < kept[(size_t)v]; ++k) {
+      idx[m] = (int32_t)(b[k] >> 32);
+      if (w_out) w_out[m] = (uint32_t)(b[k] & 0xffffffffu);
+      ++m;
+    }
+    if (m > INT32_MAX) return fail(GI_ERR_OVERFLOW, "more than 2^31-1 edges");
+    off[v + 1] = (int32_t)m;
+  }
+  *m_out = m;
+  return GI_OK;
+}
+
+// ------------------------------------------------ destination blocks ----
+
+// Greedy split of rows [0, nrows) into blocks of consecutive rows holding at
+// most cap_e edges and cap_v rows; a row above cap_e edges is its own block.
+// Long rows are listed first.
+static std::vector<int2> make_row_blocks(const int32_t* off, int nrows, int cap_e, int cap_v) {
+  std::vector<int2> longs, rest;
+  int r = 0;
+  while (r < nrows) {
+    const int64_t d = (int64_t)off[r + 1] - off[r];
+    if (d > cap_e) {
+      longs.push_back(make_int2(r, r + 1));
+      ++r;
+      continue;
+    }
+    int e = r;
+    int64_t sum = 0;
+    while (e < nrows && e - r < cap_v) {
+      const int64_t de = (int64_t)off[e + 1] - off[e];
+      if (de > cap_e || sum + de > cap_e) break;
+      sum += de;
+      ++e;
+    }
+    rest.push_back(make_int2(r, e));
+    r = e;
+  }
+  longs.insert(longs.end(), rest.begin(), rest.end());
+  return longs;
+}
+
+static gi_status upload(const void* h, void* d, size_t bytes) {
+  if (bytes == 0) return GI_OK;
+  HIP_TRY(hipMemcpy(d, h, bytes, hipMemcpyHostToDevice));
+  return GI_OK;
+}
+
+// Segments of the in-adjacency by source range (section 2, cache
+// partitioning; configApplyNumSSG).  Rows keep only destinations with at
+// least one in-edge from the segment.
+static gi_status build_segments(gi_graph* g, int p, int strategy) {
+  const int32_t n = g->n;
+  std::vector<int64_t> bound((size_t)p + 1, 0);
+  if (strategy == GI_SEG_FIXED_VERTEX_COUNT) {
+    const int64_t per = ((int64_t)n + p - 1) / p;
+    for (int i = 0; i <= p; ++i) bound[(size_t)i] = std::min<int64_t>(n, per * i);
+  } else {  // edge-aware: equal shares of out-edges (the edges each segment's sources own)
+    const int64_t total = g->m;
+    int64_t acc = 0;
+    int seg = 1;
+    for (int32_t u = 0; u < n && seg < p; ++u) {
+      acc += g->h_outdeg[(size_t)u];
+      while (seg < p && acc * p >= total * seg) bound[(size_t)seg++] = u + 1;
+    }
+    for (; seg < p; ++seg) bound[(size_t)seg] = n;
+    bound[(size_t)p] = n;
+  }
+  const int32_t* off = g->h_in_off.data();
+  const int32_t* idx = g->h_in_idx.data();
+  g->segs.assign((size_t)p, SegDev());
+  std::vector<int32_t> soff, sidx, sdst;
+  for (int i = 0; i < p; ++i) {
+    const int32_t lo = (int32_t)bound[(size_t)i], hi = (int32_t)bound[(size_t)i + 1];
+    soff.clear();
+    sidx.clear();
+    sdst.clear();
+    soff.push_back(0);
+    for (int32_t v = 0; v < n; ++v) {
+      const int32_t* b = idx + off[v];
+      const int32_t* e = idx + off[v + 1];
+      const int32_t* a = std::lower_bound(b, e, lo);
+      const int32_t* z = std::lower_bound(a, e, hi);
+      if (a == z) continue;
+      sidx.insert(sidx.end(), a, z);
+      sdst.push_back(v);
+      soff.push_back((int32_t)sidx.size());
+    }
+    SegDev& s = g->segs[(size_t)i];
+    s.nrows = (int)sdst.size();
+    s.nnz = (int64_t)sidx.size();
+    std::vector<int2> tab = make_row_blocks(soff.data(), s.nrows, g->pr_cap_e, g->pr_cap_v);
+    s.ntab = (int)tab.size();
+    gi_status st;
+    if ((st = dev_alloc(g, g->sched_allocs, &s.off, soff.size())) != GI_OK) return st;
+    if ((st = dev_alloc(g, g->sched_allocs, &s.idx, sidx.size())) != GI_OK) return st;
+    if ((st = dev_alloc(g, g->sched_allocs, &s.dst, sdst.size())) != GI_OK) return st;
+    if ((st = dev_alloc(g, g->sched_allocs, &s.table, tab.size())) != GI_OK) return st;
+    if ((st = upload(soff.data(), s.off, soff.size() * 4)) != GI_OK) return st;
+    if ((st = upload(sidx.data(), s.idx, sidx.size() * 4)) != GI_OK) return st;
+    if ((st = upload(sdst.data(), s.dst, sdst.size() * 4)) != GI_OK) return st;
+    if ((st = upload(tab.data(), s.table, tab.size() * sizeof(int2))) != GI_OK) return st;
+  }
+  gi_status st = dev_alloc(g, g->sched_allocs, &g->pr_acc, (size_t)n);
+  if (st != GI_OK) return st;
+  HIP_TRY(hipMemset(g->pr_acc, 0, sizeof(double) * (size_t)n));
+  return GI_OK;
+}
+
+static gi_status apply_schedule(gi_graph* g, const gi_schedule& s) {
+  HIP_TRY(hipDeviceSynchronize());
+  free_list(g->sched_allocs);
+  g->segs.clear();
+  g->pr_acc = nullptr;
+  g->pr_table = nullptr;
+  g->sched = s;
+  g->pr_cap_e = s.pull_block_edges > 0 ? s.pull_block_edges : 2048;
+  g->pr_cap_v = std::min(g->pr_cap_e, 1024);
+  std::vector<int2> tab = make_row_blocks(g->h_in_off.data(), g->n, g->pr_cap_e, g->pr_cap_v);
+  g->pr_ntab = (int)tab.size();
+  gi_status st = dev_alloc(g, g->sched_allocs, &g->pr_table, tab.size());
+  if (st != GI_OK) return st;
+  if ((st = upload(tab.data(), g->pr_table, tab.size() * sizeof(int2))) != GI_OK) return st;
+  if (s.num_segments > 1) return build_segments(g, s.num_segments, s.segment_strategy);
+  return GI_OK;
+}
+
+extern "C" gi_status gi_schedule_init(gi_schedule* s) {
+  if (!s) return fail(GI_ERR_INVALID_ARG, "NULL schedule");
+  std::memset(s, 0, sizeof *s);
+  s->direction = GI_DIR_DENSE_PULL_SPARSE_PUSH;
+  s->dense_frontier = GI_FRONTIER_BITVECTOR;
+  s->num_segments = 1;
+  s->segment_strategy = GI_SEG_FIXED_VERTEX_COUNT;
+  s->hybrid_divisor = 20;
+  s->persistent = 1;
+  s->pull_block_edges = 0;
+  s->block_threads = 0;
+  s->sssp_delta = 0;
+  return GI_OK;
+}
+
+static gi_status validate_schedule(const gi_graph* g, const gi_schedule* s) {
+  if (s->direction < GI_DIR_SPARSE_PUSH || s->direction > GI_DIR_DENSE_PUSH_SPARSE_PUSH)
+    return fail(GI_ERR_UNSUPPORTED, "direction %d not offered", s->direction);
+  if (s->dense_frontier != GI_FRONTIER_BITVECTOR && s->dense_frontier != GI_FRONTIER_BOOLMAP)
+    return fail(GI_ERR_UNSUPPORTED, "dense frontier kind %d not offered", s->dense_frontier);
+  if (s->num_segments < 1 || s->num_segments > 4096)
+    return fail(GI_ERR_UNSUPPORTED, "num_segments %d outside [1, 4096]", s->num_segments);
+  if (s->num_segments > 1 && s->persistent)
+    return fail(GI_ERR_UNSUPPORTED, "segmented DensePull runs one launch per segment; set persistent = 0");
+  if (s->segment_strategy != GI_SEG_FIXED_VERTEX_COUNT &&
+      s->segment_strategy != GI_SEG_EDGE_AWARE_VERTEX_COUNT)
+    return fail(GI_ERR_UNSUPPORTED, "segment strategy %d not offered", s->segment_strategy);
+  if (s->hybrid_divisor < 1) return fail(GI_ERR_UNSUPPORTED, "hybrid_divisor must be >= 1");
+  if (s->persistent != 0 && s->persistent != 1)
+    return fail(GI_ERR_UNSUPPORTED, "persistent must be 0 or 1");
+  if (s->pull_block_edges != 0 && (s->pull_block_edges < 64 || s->pull_block_edges > 8192))
+    return fail(GI_ERR_UNSUPPORTED, "pull_block_edges outside [64, 8192]");
+  if (s->block_threads != 0 && s->block_threads != 128 && s->block_threads != 256 &&
+      s->block_threads != 512)
+    return fail(GI_ERR_UNSUPPORTED, "block_threads must be 0, 128, 256 or 512");
+  (void)g;
+  return GI_OK;
+}
+
+extern "C" gi_status gi_set_schedule(gi_graph* g, const gi_schedule* s) {
+  if (!g || !s) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  gi_status st = validate_schedule(g, s);
+  if (st != GI_OK) return st;
+  return apply_schedule(g, *s);
+}
+
+extern "C" gi_status gi_get_schedule(const gi_graph* g, gi_schedule* s) {
+  if (!g || !s) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  *s = g->sched;
+  return GI_OK;
+}
+
+extern "C" int32_t gi_hybrid_choose_dense(int64_t nf, int64_t degsum, int64_t edges, int32_t divisor) {
+  return hybrid_dense(nf, degsum, edges, divisor < 1 ? 1 : divisor) ? 1 : 0;
+}
+
+// ---------------------------------------------------------- lifecycle ----
+
+extern "C" gi_status gi_graph_destroy(gi_graph* g) {
+  if (!g) return GI_OK;
+  (void)hipDeviceSynchronize();
+  free_list(g->sched_allocs);
+  free_list(g->allocs);
+  if (g->h_ctl) (void)hipHostFree(g->h_ctl);
+  for (hipEvent_t e : g->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete g;
+  return GI_OK;
+}
+
+extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_off,
+                                     const int32_t* out_idx, const uint32_t* out_w,
+                                     const int32_t* in_off, const int32_t* in_idx,
+                                     const uint32_t* in_w, gi_graph** out) {
+  if (!out) return fail(GI_ERR_INVALID_ARG, "NULL output handle");
+  *out = nullptr;
+  if (n < 1) return fail(GI_ERR_INVALID_ARG, "n must be >= 1 (got %d)", n);
+  if (n > INT32_MAX - 64) return fail(GI_ERR_OVERFLOW, "n too large");
+  if (m < 0) return fail(GI_ERR_INVALID_ARG, "negative edge count");
+  if (m > INT32_MAX) return fail(GI_ERR_OVERFLOW, "m = %lld exceeds 2^31-1", (long long)m);
+  gi_status st = check_adjacency(n, m, out_off, out_idx, "out-adjacency");
+  if (st != GI_OK) return st;
+  if ((!in_off && in_idx) || (in_off && m > 0 && !in_idx))
+    return fail(GI_ERR_INVALID_ARG, "in_off and in_idx must both be given or both be NULL");
+  if (in_w && !in_off) return fail(GI_ERR_INVALID_ARG, "in_w given without in-adjacency");
+  if (in_off && (out_w != nullptr) != (in_w != nullptr))
+    return fail(GI_ERR_INVALID_ARG, "weights must be given for both directions or neither");
+
+  gi_graph* g = new (std::nothrow) gi_graph();
+  if (!g) return fail(GI_ERR_OUT_OF_MEMORY, "host allocation failed");
+  g->n = n;
+  g->m = m;
+  g->weighted = out_w != nullptr;
+  // in-adjacency: given, or transposed here from the out-adjacency
+  std::vector<int32_t> t_idx;
+  std::vector<uint32_t> t_w;
+  try {
+    g->h_in_off.resize((size_t)n + 1);
+    g->h_outdeg.resize((size_t)n);
+    if (in_off) {
+      st = check_adjacency(n, m, in_off, in_idx, "in-adjacency");
+      if (st != GI_OK) {
+        delete g;
+        return st;
+      }
+      // every in-edge u->v must be an out-edge of u (with degrees equal below,
+      // the two adjacencies then hold the same edge set)
+      for (int32_t v = 0; v < n; ++v)
+        for (int32_t k = in_off[v]; k < in_off[v + 1]; ++k) {
+          const int32_t u = in_idx[k];
+          const int32_t* b = out_idx + out_off[u];
+          const int32_t* e = out_idx + out_off[u + 1];
+          const int32_t* f = std::lower_bound(b, e, v);
+          if (f == e || *f != v) {
+            delete g;
+            return fail(GI_ERR_INVALID_ARG, "in-edge %d->%d is not an out-edge", u, v);
+          }
+          if (in_w && out_w && in_w[k] != out_w[f - out_idx]) {
+            delete g;
+            return fail(GI_ERR_INVALID_ARG, "weight of %d->%d differs between adjacencies", u, v);
+          }
+        }
+      std::memcpy(g->h_in_off.data(), in_off, sizeof(int32_t) * ((size_t)n + 1));
+      g->h_in_idx.assign(in_idx, in_idx + m);
+    } else {
+      std::vector<int32_t> cnt((size_t)n + 1, 0);
+      for (int64_t k = 0; k < m; ++k) cnt[(size_t)out_idx[k] + 1]++;
+      for (int32_t v = 0; v < n; ++v) cnt[(size_t)v + 1] += cnt[(size_t)v];
+      std::memcpy(g->h_in_off.data(), cnt.data(), sizeof(int32_t) * ((size_t)n + 1));
+      g->h_in_idx.resize((size_t)m);
+      if (out_w) t_w.resize((size_t)m);
+      for (int32_t u = 0; u < n; ++u)  // ascending u keeps CSC rows sorted
+        for (int32_t k = out_off[u]; k < out_off[u + 1]; ++k) {
+          const int32_t pos = cnt[(size_t)out_idx[k]]++;
+          g->h_in_idx[(size_t)pos] = u;
+          if (out_w) t_w[(size_t)pos] = out_w[k];
+        }
+    }
+  } catch (...) {
+    delete g;
+    return fail(GI_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+  // in-degrees of the two adjacencies must agree (CSC is the transpose)
+  {
+    std::vector<int32_t> indeg((size_t)n, 0);
+    for (int64_t k = 0; k < m; ++k) indeg[(size_t)out_idx[k]]++;
+    for (int32_t v = 0; v < n; ++v) {
+      if (indeg[(size_t)v] != g->h_in_off[(size_t)v + 1] - g->h_in_off[(size_t)v]) {
+        delete g;
+        return fail(GI_ERR_INVALID_ARG, "in-adjacency is not the transpose (in-degree of %d)", v);
+      }
+      g->max_in = std::max(g->max_in, indeg[(size_t)v]);
+    }
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    g->h_outdeg[(size_t)v] = out_off[v + 1] - out_off[v];
+    g->max_out = std::max(g->max_out, g->h_outdeg[(size_t)v]);
+  }
+  (void)hipGetDevice(&g->device);
+  const size_t N = (size_t)n, M = (size_t)m, W = (N + 63) / 64;
+#define G_ALLOC(ptr, cnt)                                             \
+  do {                                                                \
+    if ((st = dev_alloc(g, g->allocs, &(ptr), (cnt))) != GI_OK) {     \
+      gi_graph_destroy(g);                                            \
+      return st;                                                      \
+    }                                                                 \
+  } while (0)
+#define G_UP(h, d, bytes)                                             \
+  do {                                                                \
+    if ((st = upload((h), (d), (bytes))) != GI_OK) {                  \
+      gi_graph_destroy(g);                                            \
+      return st;                                                      \
+    }                                                                 \
+  } while (0)
+  G_ALLOC(g->out_off, N + 1);
+  G_ALLOC(g->out_idx, M);
+  G_ALLOC(g->in_off, N + 1);
+  G_ALLOC(g->in_idx, M);
+  G_ALLOC(g->outdeg, N);
+  G_UP(out_off, g->out_off, 4 * (N + 1));
+  G_UP(out_idx, g->out_idx, 4 * M);
+  G_UP(g->h_in_off.data(), g->in_off, 4 * (N + 1));
+  G_UP(g->h_in_idx.data(), g->in_idx, 4 * M);
+  G_UP(g->h_outdeg.data(), g->outdeg, 4 * N);
+  if (out_w) {
+    G_ALLOC(g->out_w, M);
+    G_ALLOC(g->in_w, M);
+    G_UP(out_w, g->out_w, 4 * M);
+    G_UP(in_off ? in_w : t_w.data(), g->in_w, 4 * M);
+  }
+  // workspace
+  G_ALLOC(g->sa[0], N);
+  G_ALLOC(g->sa[1], N);
+  for (int k = 0; k < 3; ++k) {
+    G_ALLOC(g->dbv[k], W);
+    G_ALLOC(g->dbm[k], N);
+  }
+  G_ALLOC(g->vis, W);
+  G_ALLOC(g->lab, N);
+  G_ALLOC(g->contrib[0], N);
+  G_ALLOC(g->contrib[1], N);
+  G_ALLOC(g->scratch, W + 1);
+  G_ALLOC(g->far[0], N);
+  G_ALLOC(g->far[1], N);
+  G_ALLOC(g->in_far, N);
+  G_ALLOC(g->ctl, 1);
+  G_ALLOC(g->st, 1);
+  G_ALLOC(g->sst, 1);
+#undef G_ALLOC
+#undef G_UP
+  if (hipHostMalloc((void**)&g->h_ctl, sizeof(Control), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    g->h_ctl = nullptr;
+    gi_graph_destroy(g);
+    return fail(GI_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
+  }
+  std::memset(g->h_ctl, 0, sizeof(Control));
+  for (hipEvent_t& e : g->ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      e = nullptr;
+      gi_graph_destroy(g);
+      return fail(GI_ERR_DEVICE, "hipEventCreate failed");
+    }
+  }
+  gi_schedule s;
+  gi_schedule_init(&s);
+  if ((st = apply_schedule(g, s)) != GI_OK) {
+    gi_graph_destroy(g);
+    return st;
+  }
+  *out = g;
+  return GI_OK;
+}
+
+extern "C" gi_status gi_graph_info(const gi_graph* g, int32_t* n, int64_t* m, int32_t* max_out,
+                                   int32_t* max_in) {
+  if (!g) return fail(GI_ERR_INVALID_ARG, "NULL graph");
+  if (n) *n = g->n;
+  if (m) *m = g->m;
+  if (max_out) *max_out = g->max_out;
+  if (max_in) *max_in = g->max_in;
+  return GI_OK;
+}
+
+extern "C" gi_status gi_graph_copy_in_adjacency(const gi_graph* g, int32_t* in_off, int32_t* in_idx,
+                                                uint32_t* in_w) {
+  if (!g || !in_off || (g->m > 0 && !in_idx)) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  if (in_w && !g->weighted) return fail(GI_ERR_INVALID_ARG, "graph has no weights");
+  HIP_TRY(hipMemcpy(in_off, g->in_off, 4 * ((size_t)g->n + 1), hipMemcpyDeviceToHost));
+  if (g->m > 0) HIP_TRY(hipMemcpy(in_idx, g->in_idx, 4 * (size_t)g->m, hipMemcpyDeviceToHost));
+  if (in_w && g->m > 0) HIP_TRY(hipMemcpy(in_w, g->in_w, 4 * (size_t)g->m, hipMemcpyDeviceToHost));
+  return GI_OK;
+}
+
+// ------------------------------------------------------- helpers -----
+
+static DevGraph dev_graph(const gi_graph* g) {
+  DevGraph d;
+  d.n = g->n;
+  d.m = g->m;
+  d.out_off = g->out_off;
+  d.out_idx = g->out_idx;
+  d.out_w = g->out_w;
+  d.in_off = g->in_off;
+  d.in_idx = g->in_idx;
+  d.in_w = g->in_w;
+  d.outdeg = g->outdeg;
+  return d;
+}
+
+static int traversal_threads(const gi_graph* g) {
+  return g->sched.block_threads == 512 ? 512 : 256;
+}
+
+// Copy the step log of the last frontier loop into g->stats.
+static gi_status read_loop_stats(gi_graph* g, int alg, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Control), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const Control& c = *g->h_ctl;
+  gi_run_stats& r = g->stats;
+  r.algorithm = alg;
+  r.steps = c.steps;
+  r.dense_steps = c.dense_steps;
+  r.edges_examined = (int64_t)c.edges_examined;
+  r.trace_len = std::min(c.steps, GI_MAX_TRACE);
+  for (int k = 0; k < r.trace_len; ++k) {
+    r.step_direction[k] = (int8_t)c.dir_log[k];
+    r.step_frontier[k] = c.f_log[k];
+    r.step_degree_sum[k] = c.d_log[k];
+    r.step_edges[k] = c.w_log[k];
+  }
+  return GI_OK;
+}
+
+// GPU time between the two timing events of the last run.
+static gi_status read_kernel_ms(gi_graph* g, int launches) {
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, g->ev[0], g->ev[1]));
+  g->stats.kernel_ms = ms;
+  g->stats.launches = launches;
+  return GI_OK;
+}
+
+// Run the frontier loop to completion (persistent: one launch; otherwise one
+// launch per step with the completion flag read back in between).
+static gi_status run_loop(gi_graph* g, LoopParams& p, hipStream_t s) {
+  const int bt = traversal_threads(g);
+  int blocks = loop_max_blocks(bt);
+  if (blocks <= 0) return fail(GI_ERR_DEVICE, "occupancy query for the frontier loop failed");
+  const bool persistent = g->sched.persistent != 0;
+  p.max_steps = persistent ? (1 << 30) : 1;
+  p.forced_dir = -1;
+  const int header = (int)offsetof(Control, dir_log);  // everything but the logs
+  int launches = 0;
+  HIP_TRY(hipEventRecord(g->ev[0], s));
+  for (int guard = 0; guard < (1 << 30); ++guard) {
+    ++launches;
+    if (launch_loop(p, bt, blocks, s) != 0) {
+      hipError_t e = hipGetLastError();
+      return fail(GI_ERR_DEVICE, "cooperative launch of the frontier loop failed: %s",
+                  hipGetErrorString(e));
+    }
+    HIP_TRY(hipEventRecord(g->ev[1], s));
+    HIP_TRY(hipMemcpyAsync(g->h_ctl, g->ctl, header, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (g->h_ctl->error) return fail(GI_ERR_DEVICE, "frontier loop: grid barrier timed out (grid %d, block %d, generation %u, arrivals %u)", blocks, g->h_ctl->err_block, g->h_ctl->err_gen, g->h_ctl->err_count);
+    if (g->h_ctl->done) return read_kernel_ms(g, launches);
+    if (g->h_ctl->steps > (int)g->n + 2 && p.alg == ALG_BFS)
+      return fail(GI_ERR_DEVICE, "frontier loop did not terminate");
+  }
+  return fail(GI_ERR_DEVICE, "frontier loop did not terminate");
+}
+
+static LoopParams loop_params(gi_graph* g, int alg) {
+  LoopParams p;
+  std::memset(&p, 0, sizeof p);
+  p.g = dev_graph(g);
+  p.alg = alg;
+  p.direction = g->sched.direction;
+  p.divisor = g->sched.hybrid_divisor;
+  p.boolmap = g->sched.dense_frontier == GI_FRONTIER_BOOLMAP;
+  p.edges = alg == ALG_CC ? 2 * g->m : g->m;
+  p.sa[0] = g->sa[0];
+  p.sa[1] = g->sa[1];
+  for (int k = 0; k < 3; ++k) {
+    p.dbv[k] = g->dbv[k];
+    p.dbm[k] = g->dbm[k];
+  }
+  p.vis = g->vis;
+  p.ctl = g->ctl;
+  p.st = g->st;
+  return p;
+}
+
+// ---------------------------------------------------------- algorithms ----
+
+extern "C" gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, float* ranks,
+                                 void* stream) {
+  if (!g || !ranks) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  if (iters < 0) return fail(GI_ERR_INVALID_ARG, "iters must be >= 0");
+  if (!(damping >= 0.0f && damping <= 1.0f)) return fail(GI_ERR_INVALID_ARG, "damping outside [0,1]");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PrVertex pv;
+  pv.outdeg = g->outdeg;
+  pv.alpha = (double)damping;
+  pv.base = (1.0 - (double)damping) / (double)g->n;
+  const int bt = g->sched.block_threads > 0 ? g->sched.block_threads : 256;
+  if (g->sched.num_segments <= 1) {
+    PrRows r{g->pr_table, g->pr_ntab, g->in_off, g->in_idx, nullptr};
+    if (g->sched.persistent) {
+      HIP_TRY(hipMemsetAsync(g->ctl, 0, offsetof(Control, dir_log), s));
+      HIP_TRY(hipEventRecord(g->ev[0], s));
+      if (launch_pr_persistent(r, g->pr_cap_e, g->pr_cap_v, bt, g->n, iters, pv, g->contrib[0],
+                               g->contrib[1], ranks, g->ctl, 0, s) != 0) {
+        hipError_t e = hipGetLastError();
+        return fail(GI_ERR_DEVICE, "cooperative PageRank launch failed: %s", hipGetErrorString(e));
+      }
+      HIP_TRY(hipEventRecord(g->ev[1], s));
+      HIP_TRY(hipMemcpyAsync(g->h_ctl, g->ctl, offsetof(Control, dir_log), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (g->h_ctl->error) return fail(GI_ERR_DEVICE, "PageRank: grid barrier timed out (block %d, generation %u, arrivals %u)", g->h_ctl->err_block, g->h_ctl->err_gen, g->h_ctl->err_count);
+    } else {
+      HIP_TRY(hipEventRecord(g->ev[0], s));
+      LAUNCH_TRY(launch_pr_init(g->n, g->outdeg, g->contrib[0], ranks, iters == 0, s));
+      for (int k = 0; k < iters; ++k) {
+        const bool last = k == iters - 1;
+        LAUNCH_TRY(launch_pr_rows(r, g->pr_cap_e, g->pr_cap_v, bt, 0, g->contrib[k & 1], 0, pv,
+                                  g->contrib[(k + 1) & 1], last ? ranks : nullptr, nullptr, s));
+      }
+      HIP_TRY(hipEventRecord(g->ev[1], s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+  } else {
+    HIP_TRY(hipEventRecord(g->ev[0], s));
+    LAUNCH_TRY(launch_pr_init(g->n, g->outdeg, g->contrib[0], ranks, iters == 0, s));
+    for (int k = 0; k < iters; ++k) {
+      const bool last = k == iters - 1;
+      for (const SegDev& sg : g->segs) {
+        PrRows r{sg.table, sg.ntab, sg.off, sg.idx, sg.dst};
+        LAUNCH_TRY(launch_pr_rows(r, g->pr_cap_e, g->pr_cap_v, bt, 0, g->contrib[k & 1], 1, pv,
+                                  nullptr, nullptr, g->pr_acc, s));
+      }
+      LAUNCH_TRY(launch_pr_seg_final(g->n, pv, g->pr_acc, g->contrib[(k + 1) & 1],
+                                     last ? ranks : nullptr, s));
+    }
+    HIP_TRY(hipEventRecord(g->ev[1], s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  {
+    gi_status ts = read_kernel_ms(g, g->sched.persistent && g->sched.num_segments <= 1
+                                         ? 1
+                                         : 1 + iters * (g->sched.num_segments <= 1
+                                                            ? 1
+                                                            : (int)g->segs.size() + 1));
+    if (ts != GI_OK) return ts;
+  }
+  gi_run_stats& st = g->stats;
+  st.algorithm = ALG_PR;
+  st.steps = iters;
+  st.dense_steps = iters;
+  st.edges_examined = (int64_t)iters * g->m;
+  st.trace_len = std::min(iters, GI_MAX_TRACE);
+  for (int k = 0; k < st.trace_len; ++k) {
+    st.step_direction[k] = GI_DIR_DENSE_PULL;
+    st.step_frontier[k] = g->n;
+    st.step_degree_sum[k] = g->m;
+  }
+  return GI_OK;
+}
+
+extern "C" gi_status gi_bfs(gi_graph* g, int32_t src, int32_t* level, int32_t* parent, void* stream) {
+  if (!g || !level) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  if (src < 0 || src >= g->n) return fail(GI_ERR_INVALID_ARG, "source %d outside [0, %d)", src, g->n);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LoopParams p = loop_params(g, ALG_BFS);
+  p.level = level;
+  p.parent = parent;
+  LAUNCH_TRY(launch_loop_init(p, src, s));
+  gi_status st = run_loop(g, p, s);
+  if (st != GI_OK) return st;
+  return read_loop_stats(g, ALG_BFS, s);
+}
+
+extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
+  if (!g || !label) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LoopParams p = loop_params(g, ALG_CC);
+  p.lab[0] = label;
+  p.lab[1] = g->lab;
+  LAUNCH_TRY(launch_loop_init(p, 0, s));
+  gi_status st = run_loop(g, p, s);
+  if (st != GI_OK) return st;
+  LoopState ls;
+  HIP_TRY(hipMemcpyAsync(&ls, g->st, sizeof ls, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (ls.lab_cur != 0)
+    HIP_TRY(hipMemcpyAsync(label, g->lab, 4 * (size_t)g->n, hipMemcpyDeviceToDevice, s));
+  st = read_loop_stats(g, ALG_CC, s);
+  return st;
+}
+
+extern "C" gi_status gi_sssp(gi_graph* g, int32_t src, uint32_t* dist, void* stream) {
+  if (!g || !dist) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  if (!g->weighted) return fail(GI_ERR_INVALID_ARG, "graph has no edge weights");
+  if (src < 0 || src >= g->n) return fail(GI_ERR_INVALID_ARG, "source %d outside [0, %d)", src, g->n);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SsspParams p;
+  std::memset(&p, 0, sizeof p);
+  p.g = dev_graph(g);
+  p.dist = dist;
+  p.near[0] = g->sa[0];
+  p.near[1] = g->sa[1];
+  p.far[0] = g->far[0];
+  p.far[1] = g->far[1];
+  p.stamp = g->lab;
+  p.in_far = g->in_far;
+  p.delta = g->sched.sssp_delta > 0 ? g->sched.sssp_delta : 512u;
+  p.max_phases = 1 << 30;
+  p.ctl = g->ctl;
+  p.st = g->sst;
+  const int bt = traversal_threads(g);
+  const int blocks = sssp_max_blocks(bt);
+  if (blocks <= 0) return fail(GI_ERR_DEVICE, "occupancy query for delta-stepping failed");
+  LAUNCH_TRY(launch_sssp_init(p, src, s));
+  const int header = (int)offsetof(Control, dir_log);  // everything but the logs
+  int launches = 0;
+  HIP_TRY(hipEventRecord(g->ev[0], s));
+  for (;;) {
+    ++launches;
+    if (launch_sssp(p, bt, blocks, s) != 0) {
+      hipError_t e = hipGetLastError();
+      return fail(GI_ERR_DEVICE, "cooperative launch of delta-stepping failed: %s",
+                  hipGetErrorString(e));
+    }
+    HIP_TRY(hipEventRecord(g->ev[1], s));
+    HIP_TRY(hipMemcpyAsync(g->h_ctl, g->ctl, header, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (g->h_ctl->error) return fail(GI_ERR_DEVICE, "delta-stepping: grid barrier timed out (grid %d, block %d, generation %u, arrivals %u)", blocks, g->h_ctl->err_block, g->h_ctl->err_gen, g->h_ctl->err_count);
+    if (g->h_ctl->overflow) return fail(GI_ERR_OVERFLOW, "a distance reached UINT32_MAX");
+    if (g->h_ctl->done) break;
+  }
+  gi_status st = read_loop_stats(g, ALG_SSSP, s);
+  if (st != GI_OK) return st;
+  g->stats.dense_steps = 0;
+  return read_kernel_ms(g, launches);
+}
+
+extern "C" gi_status gi_get_run_stats(const gi_graph* g, gi_run_stats* out) {
+  if (!g || !out) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  *out = g->stats;
+  return GI_OK;
+}
+
+// ------------------------------------------------- frontier primitives ----
+
+extern "C" gi_status gi_frontier_sparse_to_bitvec(int32_t n, const int32_t* ids, int32_t count,
+                                                  uint64_t* bv, void* stream) {
+  if (n < 1 || count < 0 || count > n || !bv || (count > 0 && !ids))
+    return fail(GI_ERR_INVALID_ARG, "bad frontier arguments");
+  LAUNCH_TRY(launch_sparse_to_bitvec(n, ids, count, bv, static_cast<hipStream_t>(stream)));
+  return GI_OK;
+}
+
+extern "C" gi_status gi_frontier_bitvec_to_sparse(int32_t n, const uint64_t* bv, int32_t* ids,
+                                                  int32_t* count_dev, void* stream) {
+  if (n < 1 || !bv || !ids || !count_dev) return fail(GI_ERR_INVALID_ARG, "bad frontier arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int32_t* scratch = nullptr;
+  const size_t W = ((size_t)n + 63) / 64;
+  HIP_TRY(hipMallocAsync((void**)&scratch, 4 * (W + 1), s));
+  const int rc = launch_bitvec_to_sparse(n, bv, ids, count_dev, scratch, s);
+  HIP_TRY(hipFreeAsync(scratch, s));
+  if (rc != 0) return fail(GI_ERR_DEVICE, "bitvector compaction launch failed");
+  return GI_OK;
+}
+
+extern "C" gi_status gi_frontier_bitvec_to_boolmap(int32_t n, const uint64_t* bv, uint8_t* bm,
+                                                   void* stream) {
+  if (n < 1 || !bv || !bm) return fail(GI_ERR_INVALID_ARG, "bad frontier arguments");
+  LAUNCH_TRY(launch_bitvec_to_boolmap(n, bv, bm, static_cast<hipStream_t>(stream)));
+  return GI_OK;
+}
+
+extern "C" gi_status gi_frontier_boolmap_to_bitvec(int32_t n, const uint8_t* bm, uint64_t* bv,
+                                                   void* stream) {
+  if (n < 1 || !bv || !bm) return fail(GI_ERR_INVALID_ARG, "bad frontier arguments");
+  LAUNCH_TRY(launch_boolmap_to_bitvec(n, bm, bv, static_cast<hipStream_t>(stream)));
+  return GI_OK;
+}
+
+extern "C" gi_status gi_frontier_degree_sum(const gi_graph* g, const int32_t* ids, int32_t count,
+                                            int64_t* out, void* stream) {
+  if (!g || !out || count < 0 || (count > 0 && !ids))
+    return fail(GI_ERR_INVALID_ARG, "bad frontier arguments");
+  LAUNCH_TRY(launch_degree_sum(g->outdeg, ids, count, out, static_cast<hipStream_t>(stream)));
+  return GI_OK;
+}

@@ -1,0 +1,131 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and
+exports every symbol the header declares, the host adjacency build matches
+the oracle bit for bit, and argument errors are reported before any device
+work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _gi():
+    import paper_1805_00923_amd as gi
+    return gi
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "graphit_mi.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gi_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    gi = _gi()
+    syms = header_symbols()
+    assert len(syms) >= 20
+    for s in syms:
+        assert hasattr(gi.lib, s), s
+        assert s in gi._SIGS, "binding lacks a signature for " + s
+    assert gi.lib.gi_abi_version() == 1
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_host_ingest_matches_oracle(seed):
+    gi = _gi()
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 300))
+    el = gg.uniform(n, int(rng.integers(0, 6 * n)), seed=seed)
+    w = gg.uniform_weights(el.m, seed + 50, 1, 7)  # small range => many repeated pairs with ties
+    og = oracle.build_adj(n, el.src, el.dst, w)
+    off, idx, ww = gi.build_adjacency(n, el.src, el.dst, w)
+    assert np.array_equal(off, og.off)
+    assert np.array_equal(idx, og.idx)
+    assert np.array_equal(ww, og.w)
+
+
+def test_host_ingest_rmat_and_grid():
+    gi = _gi()
+    for el in (gg.rmat(12, seed=3), gg.grid(40, 50, 0.05, seed=9)):
+        og = oracle.build_adj(el.n, el.dst, el.src, el.w)   # CSC
+        off, idx, ww = gi.build_adjacency(el.n, el.dst, el.src, el.w)
+        assert np.array_equal(off, og.off) and np.array_equal(idx, og.idx)
+        if el.w is not None:
+            assert np.array_equal(ww, og.w)
+
+
+def test_ingest_rejects_bad_records():
+    gi = _gi()
+    with pytest.raises(gi.GiError) as e:
+        gi.build_adjacency(4, np.array([0, 4]), np.array([1, 2]))
+    assert e.value.status == gi.GI_ERR_INVALID_ARG
+    with pytest.raises(gi.GiError):
+        gi.build_adjacency(0, np.zeros(0), np.zeros(0))
+
+
+def _create(n, m, off, idx, ioff=None, iidx=None):
+    gi = _gi()
+    h = ctypes.c_void_p()
+    p = lambda a: None if a is None else a.ctypes.data
+    st = gi.lib.gi_graph_create(n, m, p(off), p(idx), None, p(ioff), p(iidx), None, ctypes.byref(h))
+    return st, gi.last_error()
+
+
+def test_graph_create_validates_before_device_work():
+    gi = _gi()
+    off = np.array([0, 1, 2, 2], np.int32)
+    idx = np.array([1, 2], np.int32)
+    # bad offsets
+    st, msg = _create(3, 2, np.array([0, 2, 1, 2], np.int32), idx)
+    assert st == gi.GI_ERR_INVALID_ARG and "decrease" in msg
+    # neighbour out of range
+    st, _ = _create(3, 2, off, np.array([1, 3], np.int32))
+    assert st == gi.GI_ERR_INVALID_ARG
+    # unsorted row
+    st, msg = _create(2, 2, np.array([0, 2, 2], np.int32), np.array([1, 1], np.int32))
+    assert st == gi.GI_ERR_INVALID_ARG and "ascending" in msg
+    # m beyond int32 offsets
+    st, _ = _create(3, 2 ** 31, off, idx)
+    assert st == gi.GI_ERR_OVERFLOW
+    # n < 1
+    st, _ = _create(0, 0, np.array([0], np.int32), idx)
+    assert st == gi.GI_ERR_INVALID_ARG
+    # CSC that is not the transpose
+    st, msg = _create(3, 2, off, idx, np.array([0, 0, 1, 2], np.int32),
+                      np.array([1, 0], np.int32))
+    assert st == gi.GI_ERR_INVALID_ARG
+
+
+def test_null_handles_rejected():
+    gi = _gi()
+    assert gi.lib.gi_bfs(None, 0, None, None, None) == gi.GI_ERR_INVALID_ARG
+    assert gi.lib.gi_pagerank(None, 20, 0.85, None, None) == gi.GI_ERR_INVALID_ARG
+    assert gi.lib.gi_cc(None, None, None) == gi.GI_ERR_INVALID_ARG
+    assert gi.lib.gi_sssp(None, 0, None, None) == gi.GI_ERR_INVALID_ARG
+    assert gi.lib.gi_set_schedule(None, None) == gi.GI_ERR_INVALID_ARG
+    assert gi.lib.gi_graph_destroy(None) == gi.GI_OK
+    assert gi.lib.gi_frontier_sparse_to_bitvec(0, None, 0, None, None) == gi.GI_ERR_INVALID_ARG
+
+
+def test_default_schedule():
+    gi = _gi()
+    s = gi.default_schedule()
+    assert s.direction == gi.DENSE_PULL_SPARSE_PUSH
+    assert s.hybrid_divisor == 20 and s.num_segments == 1 and s.persistent == 1
+
+
+def test_hybrid_rule_as_written():
+    """Dense side iff |F| + sum outdeg(F) > m / divisor (section 2)."""
+    gi = _gi()
+    m = 1000
+    for nf in range(0, 60, 7):
+        for d in range(0, 80, 9):
+            assert gi.hybrid_choose_dense(nf, d, m, 20) == ((nf + d) * 20 > m)
+    assert not gi.hybrid_choose_dense(25, 25, 1000, 20)   # exactly m/20 stays sparse
+    assert gi.hybrid_choose_dense(25, 26, 1000, 20)

@@ -1,0 +1,298 @@
+"""GPU parity: every traversal schedule of the library against the oracle.
+
+BFS levels, CC labels (and round counts) and SSSP distances must match the
+oracle exactly; BFS parents must form a valid BFS tree; PageRank must be
+within 1e-6 max relative error of the FP64 oracle.  Inputs are seeded
+synthetic graphs: small families that reach every code path (long rows,
+empty rows, ragged bit-vector tails, many levels) and the full-size
+workloads.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from gpu_util import (PR_RTOL, device_graph, pr_max_rel, run_bfs, run_cc, run_pr, run_sssp,
+                      say, torch_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+def _gi():
+    import paper_1805_00923_amd as gi
+    return gi
+
+
+def families():
+    fam = [
+        gg.cycle(100), gg.path(300), gg.star(500), gg.star(400, out=False), gg.complete(40),
+        gg.empty(17), gg.empty(1), gg.grid(30, 41, 0.0, weighted=False),
+        gg.uniform(2000, 9000, seed=3), gg.uniform(129, 40, seed=4),
+        gg.rmat(8, seed=21), gg.rmat(11, seed=22), gg.rmat(13, seed=23),
+    ]
+    # a hub with more in- and out-edges than any block or wave holds
+    n = 5000
+    hub_src = np.concatenate([np.zeros(n - 1, np.int32), np.arange(1, n, dtype=np.int32)])
+    hub_dst = np.concatenate([np.arange(1, n, dtype=np.int32), np.zeros(n - 1, np.int32)])
+    extra = gg.uniform(n, 3 * n, seed=5)
+    fam.append(gg.EdgeList(n, np.concatenate([hub_src, extra.src]),
+                           np.concatenate([hub_dst, extra.dst]), name="hub5000"))
+    return fam
+
+
+_FAM = None
+_ORACLE = {}
+
+
+def fam_graphs():
+    global _FAM
+    if _FAM is None:
+        _FAM = [(el, device_graph(el), oracle.Graph(el)) for el in families()]
+    return _FAM
+
+
+def sources_of(el, k=3):
+    s = gg.pick_sources(el, k, 3)
+    return [0] if s.size == 0 else list(s)
+
+
+TRAVERSAL_SCHEDULES = [
+    dict(direction=d, dense_frontier=f, persistent=p)
+    for d, f, p in itertools.product(range(5), (0, 1), (1, 0))
+]
+
+
+def sched_name(s):
+    return "dir%d_fr%d_p%d" % (s["direction"], s["dense_frontier"], s["persistent"])
+
+
+# ------------------------------------------------------------------ PageRank
+
+def test_pagerank_families_default():
+    for el, g, og in fam_graphs():
+        for iters in (0, 1, 20):
+            say("pr %s iters=%d" % (el.name, iters))
+            g.set_schedule()
+            x = run_pr(g, iters)
+            ref = oracle.pagerank(og, iters)
+            assert pr_max_rel(x, ref) <= PR_RTOL, (el.name, iters)
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(persistent=1), dict(persistent=0),
+    dict(persistent=1, pull_block_edges=64), dict(persistent=0, pull_block_edges=256),
+    dict(persistent=1, pull_block_edges=8192, block_threads=512),
+    dict(persistent=0, block_threads=128), dict(persistent=1, block_threads=128),
+    dict(persistent=0, num_segments=2), dict(persistent=0, num_segments=3, segment_strategy=1),
+    dict(persistent=0, num_segments=8, pull_block_edges=128),
+    dict(persistent=0, num_segments=64, segment_strategy=1),
+], ids=lambda c: "_".join("%s%s" % (k[:6], v) for k, v in c.items()))
+def test_pagerank_schedules(cfg):
+    for el, g, og in fam_graphs():
+        say("pr %s %s" % (el.name, cfg))
+        g.set_schedule(**cfg)
+        x = run_pr(g, 20)
+        assert pr_max_rel(x, oracle.pagerank(og, 20)) <= PR_RTOL, el.name
+    for el, g, _ in fam_graphs():
+        g.set_schedule()
+
+
+def test_pagerank_rmat16_workload():
+    """The PageRank workload: RMAT scale 16, edge factor 16, 20 iterations."""
+    el = gg.rmat(16, seed=1)
+    og = oracle.Graph(el)
+    g = device_graph(el)
+    ref = oracle.pagerank(og, 20, 0.85)
+    for cfg in (dict(), dict(persistent=0), dict(persistent=0, num_segments=4),
+                dict(persistent=0, num_segments=4, segment_strategy=1)):
+        say("pr rmat16 %s" % cfg)
+        g.set_schedule(**cfg)
+        x = run_pr(g, 20)
+        err = pr_max_rel(x, ref)
+        assert err <= PR_RTOL, (cfg, err)
+    g.close()
+
+
+# ----------------------------------------------------------------------- BFS
+
+@pytest.mark.parametrize("sched", TRAVERSAL_SCHEDULES, ids=sched_name)
+def test_bfs_all_schedules(sched):
+    for el, g, og in fam_graphs():
+        g.set_schedule(**sched)
+        for s in sources_of(el):
+            say("bfs %s src=%d %s" % (el.name, s, sched))
+            lv, par = run_bfs(g, s)
+            ref, _ = oracle.bfs(og, s)
+            assert np.array_equal(lv, ref), (el.name, s)
+            assert oracle.check_bfs_parents(og, s, lv, par) == [], (el.name, s)
+            st = g.stats()
+            assert st.steps == int(ref.max()) + 1
+    for el, g, _ in fam_graphs():
+        g.set_schedule()
+
+
+def test_bfs_without_parent_and_divisors():
+    el, g, og = fam_graphs()[-2]
+    for div in (1, 5, 20, 1000, 1 << 30):
+        g.set_schedule(hybrid_divisor=div)
+        for s in sources_of(el, 4):
+            say("bfs %s src=%d div=%d" % (el.name, s, div))
+            lv, _ = run_bfs(g, s, with_parent=False)
+            assert np.array_equal(lv, oracle.bfs(og, s)[0])
+    g.set_schedule()
+
+
+def test_bfs_hybrid_switches_direction():
+    """On a power-law graph the hybrid schedule must actually use both sides."""
+    el, g, og = fam_graphs()[-2]
+    g.set_schedule(direction=3)
+    s = sources_of(el, 1)[0]
+    lv, _ = run_bfs(g, s)
+    st = g.stats()
+    dirs, fs, ds = st.trace()
+    assert 0 < st.dense_steps < st.steps
+    # the recorded choice follows the rule |F| + D_F > m/20
+    for d, f, dd in zip(dirs, fs, ds):
+        dense = (int(f) + int(dd)) * 20 > g.m
+        assert d == (2 if dense else 0)
+
+
+# ------------------------------------------------------------------------ CC
+
+@pytest.mark.parametrize("sched", TRAVERSAL_SCHEDULES, ids=sched_name)
+def test_cc_all_schedules(sched):
+    for el, g, og in fam_graphs():
+        say("cc %s %s" % (el.name, sched))
+        g.set_schedule(**sched)
+        lab = run_cc(g)
+        ref, rounds = oracle.cc(og)
+        assert np.array_equal(lab, ref), el.name
+        assert g.stats().steps == rounds, el.name
+    for el, g, _ in fam_graphs():
+        g.set_schedule()
+
+
+# ---------------------------------------------------------------------- SSSP
+
+def weighted_families():
+    fam = [gg.grid(40, 50, 0.01, seed=4), gg.grid(64, 64, 0.0, seed=7)]
+    for sc, seed in ((10, 31), (13, 32)):
+        el = gg.rmat(sc, seed=seed)
+        el.w = gg.uniform_weights(el.m, seed, 1, 1000)
+        fam.append(el)
+    el = gg.rmat(11, seed=33)
+    el.w = np.ones(el.m, np.uint32)
+    fam.append(el)
+    el = gg.path(2000)
+    el.w = gg.uniform_weights(el.m, 5, 1, 1000)
+    fam.append(el)
+    return fam
+
+
+@pytest.mark.parametrize("delta", [1, 7, 100, 1000, 1 << 20])
+def test_sssp_matches_dijkstra(delta):
+    for el in weighted_families():
+        g = device_graph(el)
+        og = oracle.Graph(el)
+        g.set_schedule(sssp_delta=delta)
+        for s in sources_of(el, 2):
+            say("sssp %s src=%d delta=%d" % (el.name, s, delta))
+            d = run_sssp(g, s)
+            ref = oracle.dijkstra(og, s)
+            assert np.array_equal(d, ref), (el.name, s, delta)
+        g.close()
+
+
+def test_sssp_unit_weights_equal_bfs():
+    el = gg.rmat(12, seed=8)
+    el.w = np.ones(el.m, np.uint32)
+    g = device_graph(el)
+    og = oracle.Graph(el)
+    s = sources_of(el, 1)[0]
+    d = run_sssp(g, s)
+    lv, _ = run_bfs(g, s)
+    assert np.array_equal(d, np.where(lv < 0, 0xFFFFFFFF, lv).astype(np.uint32))
+    g.close()
+
+
+def test_sssp_overflow_reported():
+    gi = _gi()
+    el = gg.path(5)
+    el.w = np.full(el.m, 0x7FFFFFFF, np.uint32)
+    g = device_graph(el)
+    with pytest.raises(gi.GiError) as e:
+        run_sssp(g, 0)
+    assert e.value.status == gi.GI_ERR_OVERFLOW
+    g.close()
+
+
+# ------------------------------------------------------ frontier primitives
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 100003])
+def test_frontier_conversions(n):
+    gi = _gi()
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(n)
+    for frac in (0.0, 0.01, 0.5, 1.0):
+        say("frontier n=%d frac=%g" % (n, frac))
+        members = np.nonzero(rng.random(n) < frac)[0].astype(np.int32) if frac < 1 else \
+            np.arange(n, dtype=np.int32)
+        ids = torch.from_numpy(rng.permutation(members).astype(np.int32)).to(dev)
+        W = (n + 63) // 64
+        bv = torch.full((W,), -1, dtype=torch.int64, device=dev)
+        gi.sparse_to_bitvec(n, ids if members.size else 0, members.size, bv)
+        bm = torch.full((n,), 7, dtype=torch.uint8, device=dev)
+        gi.bitvec_to_boolmap(n, bv, bm)
+        bv2 = torch.full((W,), -1, dtype=torch.int64, device=dev)
+        gi.boolmap_to_bitvec(n, bm, bv2)
+        out = torch.full((n,), -1, dtype=torch.int32, device=dev)
+        cnt = torch.zeros((1,), dtype=torch.int32, device=dev)
+        gi.bitvec_to_sparse(n, bv2, out, cnt)
+        torch.cuda.synchronize()
+        expect_bm = np.zeros(n, np.uint8)
+        expect_bm[members] = 1
+        assert np.array_equal(bm.cpu().numpy(), expect_bm)
+        assert np.array_equal(bv.cpu().numpy(), bv2.cpu().numpy())
+        bits = np.unpackbits(bv.cpu().numpy().view(np.uint8), bitorder="little")[:n]
+        assert np.array_equal(bits, expect_bm)
+        k = int(cnt.item())
+        assert k == members.size
+        assert np.array_equal(out.cpu().numpy()[:k], np.sort(members))
+
+
+def test_frontier_degree_sum():
+    torch, dev = torch_dev()
+    el, g, og = fam_graphs()[-2]
+    ids = np.array(sources_of(el, 3) + [0, 1, 2], np.int32)
+    out = torch.zeros((2,), dtype=torch.int64, device=dev)
+    g.frontier_degree_sum(torch.from_numpy(ids).to(dev), ids.size, out)
+    torch.cuda.synchronize()
+    deg = og.out.degrees()
+    assert out.cpu().numpy().tolist() == [ids.size, int(deg[ids].sum())]
+
+
+# --------------------------------------------------------------- errors
+
+def test_schedule_errors_and_bad_arguments():
+    gi = _gi()
+    el, g, og = fam_graphs()[0]
+    for bad in (dict(direction=9), dict(dense_frontier=5), dict(num_segments=0),
+                dict(num_segments=4, persistent=1), dict(hybrid_divisor=0),
+                dict(block_threads=100), dict(pull_block_edges=10)):
+        with pytest.raises(gi.GiError) as e:
+            g.set_schedule(**bad)
+        assert e.value.status == gi.GI_ERR_UNSUPPORTED, bad
+    torch, dev = torch_dev()
+    lv = torch.zeros((g.n,), dtype=torch.int32, device=dev)
+    with pytest.raises(gi.GiError) as e:
+        g.bfs(g.n, lv)
+    assert e.value.status == gi.GI_ERR_INVALID_ARG
+    with pytest.raises(gi.GiError) as e:
+        g.sssp(0, lv)     # unweighted graph
+    assert e.value.status == gi.GI_ERR_INVALID_ARG
+    with pytest.raises(gi.GiError) as e:
+        g.pagerank(torch.zeros((g.n,), dtype=torch.float32, device=dev), -1)
+    assert e.value.status == gi.GI_ERR_INVALID_ARG
+    g.set_schedule()
