@@ -16,8 +16,9 @@
  *   unspecified.  gi_last_error() gives a message for the calling thread's
  *   last failing call.
  * - Algorithm calls enqueue their kernels on the given stream and then wait
- *   for that stream before returning (the frontier loop reads a few bytes of
- *   per-step statistics back); their device outputs are complete on return.
+ *   for that stream before returning (frontier loops read a completion flag
+ *   back once per steps_per_sync steps); their device outputs are complete
+ *   on return.
  * - A gi_graph owns device copies of its adjacency and a workspace sized at
  *   creation.  It is not thread-safe: one call at a time per graph.  Distinct
  *   graphs may be used from distinct threads and streams.
@@ -74,13 +75,15 @@ enum { GI_SEG_FIXED_VERTEX_COUNT = 0, GI_SEG_EDGE_AWARE_VERTEX_COUNT = 1 };
  *   hybrid_divisor   hybrid directions choose the dense side when
  *                    |F| + sum of out-degrees of F > m / hybrid_divisor
  *                    (section 2: sum of out-degrees against a threshold)
- *   persistent       1: the whole frontier loop runs in one cooperative
- *                    launch with device-side direction decisions;
- *                    0: one launch per step, decisions on the host
+ *   steps_per_sync   frontier loops (BFS, CC, SSSP) enqueue this many
+ *                    steps before reading the completion flag back; steps
+ *                    after completion return at once (0 = library default:
+ *                    8, or 64 for SSSP).  Directions are always decided on
+ *                    the device.
  *   pull_block_edges PageRank DensePull: in-edges staged in LDS per
  *                    destination block, 64..8192 (0 = library default 2048)
- *   block_threads    threads per workgroup: 128, 256 or 512 (0 = library
- *                    default 256; the frontier loops take 256 or 512)
+ *   block_threads    threads per workgroup of the PageRank DensePull
+ *                    kernel: 64, 128, 256 or 512 (0 = library default 256)
  *   sssp_delta       bucket width of delta-stepping (0 = library default)
  * Use gi_schedule_init for defaults; gi_set_schedule returns
  * GI_ERR_UNSUPPORTED for a combination it does not offer. */
@@ -90,7 +93,7 @@ typedef struct gi_schedule {
   int32_t num_segments;
   int32_t segment_strategy;
   int32_t hybrid_divisor;
-  int32_t persistent;
+  int32_t steps_per_sync;
   int32_t pull_block_edges;
   int32_t block_threads;
   uint32_t sssp_delta;

@@ -51,7 +51,7 @@ class GiError(RuntimeError):
 class Schedule(ctypes.Structure):
     _fields_ = [("direction", ctypes.c_int32), ("dense_frontier", ctypes.c_int32),
                 ("num_segments", ctypes.c_int32), ("segment_strategy", ctypes.c_int32),
-                ("hybrid_divisor", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("hybrid_divisor", ctypes.c_int32), ("steps_per_sync", ctypes.c_int32),
                 ("pull_block_edges", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("sssp_delta", ctypes.c_uint32), ("reserved", ctypes.c_int32 * 7)]
 

@@ -73,30 +73,34 @@ struct gi_graph {
   std::vector<void*> sched_allocs; // schedule-lifetime device allocations
   // adjacency on the device
   int32_t *out_off = nullptr, *out_idx = nullptr, *in_off = nullptr, *in_idx = nullptr;
-  int32_t* outdeg = nullptr;
+  int32_t *outdeg = nullptr, *udeg = nullptr;
   uint32_t *out_w = nullptr, *in_w = nullptr;
-  // host copy of the in-adjacency (destination blocks and segments are built from it)
-  std::vector<int32_t> h_in_off, h_in_idx, h_outdeg;
+  // host copies of the offsets (destination blocks and segments are built from them)
+  std::vector<int32_t> h_in_off, h_in_idx, h_out_off, h_outdeg;
   gi_schedule sched{};
-  // PageRank destination blocks
+  // destination blocks of the in-rows (PageRank, CC pull pass 0) and out-rows
   int2* pr_table = nullptr;
   int pr_ntab = 0, pr_cap_e = 0, pr_cap_v = 0;
+  int2* out_table = nullptr;
+  int out_ntab = 0;
   std::vector<SegDev> segs;
   double* pr_acc = nullptr;
-  // traversal workspace
-  int32_t* sa[2] = {nullptr, nullptr};
-  uint64_t* dbv[3] = {nullptr, nullptr, nullptr};
-  uint8_t* dbm[3] = {nullptr, nullptr, nullptr};
-  uint64_t* vis = nullptr;
-  int32_t* lab = nullptr;
+  // frontier-loop workspace
+  uint64_t* fbv[2] = {nullptr, nullptr};  // dense frontiers (bitvectors)
+  uint8_t* fbm[2] = {nullptr, nullptr};   // dense frontiers (bool maps, padded to 64)
+  uint64_t* vis = nullptr;                // BFS visited
+  uint64_t* far = nullptr;                // SSSP far set
+  int32_t* lab = nullptr;                 // CC second label buffer
   float* contrib[2] = {nullptr, nullptr};
-  int32_t* scratch = nullptr;  // ceil(n/64)+1 ints
-  int32_t* far[2] = {nullptr, nullptr};
-  int32_t* in_far = nullptr;
+  Part* part = nullptr;
+  long long* blk_cnt = nullptr;
+  long long* blk_deg = nullptr;
+  int32_t* ids = nullptr;
+  long long* excl = nullptr;
+  int32_t* chunk_item = nullptr;
   Control* ctl = nullptr;
-  LoopState* st = nullptr;
-  SsspState* sst = nullptr;
   Control* h_ctl = nullptr;    // pinned host mirror
+  Engine eng{};
   hipEvent_t ev[2] = {nullptr, nullptr};
   gi_run_stats stats{};
 };
@@ -321,6 +325,10 @@ static gi_status apply_schedule(gi_graph* g, const gi_schedule& s) {
   gi_status st = dev_alloc(g, g->sched_allocs, &g->pr_table, tab.size());
   if (st != GI_OK) return st;
   if ((st = upload(tab.data(), g->pr_table, tab.size() * sizeof(int2))) != GI_OK) return st;
+  std::vector<int2> otab = make_row_blocks(g->h_out_off.data(), g->n, g->pr_cap_e, g->pr_cap_v);
+  g->out_ntab = (int)otab.size();
+  if ((st = dev_alloc(g, g->sched_allocs, &g->out_table, otab.size())) != GI_OK) return st;
+  if ((st = upload(otab.data(), g->out_table, otab.size() * sizeof(int2))) != GI_OK) return st;
   if (s.num_segments > 1) return build_segments(g, s.num_segments, s.segment_strategy);
   return GI_OK;
 }
@@ -333,7 +341,7 @@ extern "C" gi_status gi_schedule_init(gi_schedule* s) {
   s->num_segments = 1;
   s->segment_strategy = GI_SEG_FIXED_VERTEX_COUNT;
   s->hybrid_divisor = 20;
-  s->persistent = 1;
+  s->steps_per_sync = 0;
   s->pull_block_edges = 0;
   s->block_threads = 0;
   s->sssp_delta = 0;
@@ -347,19 +355,17 @@ static gi_status validate_schedule(const gi_graph* g, const gi_schedule* s) {
     return fail(GI_ERR_UNSUPPORTED, "dense frontier kind %d not offered", s->dense_frontier);
   if (s->num_segments < 1 || s->num_segments > 4096)
     return fail(GI_ERR_UNSUPPORTED, "num_segments %d outside [1, 4096]", s->num_segments);
-  if (s->num_segments > 1 && s->persistent)
-    return fail(GI_ERR_UNSUPPORTED, "segmented DensePull runs one launch per segment; set persistent = 0");
   if (s->segment_strategy != GI_SEG_FIXED_VERTEX_COUNT &&
       s->segment_strategy != GI_SEG_EDGE_AWARE_VERTEX_COUNT)
     return fail(GI_ERR_UNSUPPORTED, "segment strategy %d not offered", s->segment_strategy);
   if (s->hybrid_divisor < 1) return fail(GI_ERR_UNSUPPORTED, "hybrid_divisor must be >= 1");
-  if (s->persistent != 0 && s->persistent != 1)
-    return fail(GI_ERR_UNSUPPORTED, "persistent must be 0 or 1");
+  if (s->steps_per_sync < 0 || s->steps_per_sync > 4096)
+    return fail(GI_ERR_UNSUPPORTED, "steps_per_sync outside [0, 4096]");
   if (s->pull_block_edges != 0 && (s->pull_block_edges < 64 || s->pull_block_edges > 8192))
     return fail(GI_ERR_UNSUPPORTED, "pull_block_edges outside [64, 8192]");
-  if (s->block_threads != 0 && s->block_threads != 128 && s->block_threads != 256 &&
-      s->block_threads != 512)
-    return fail(GI_ERR_UNSUPPORTED, "block_threads must be 0, 128, 256 or 512");
+  if (s->block_threads != 0 && s->block_threads != 64 && s->block_threads != 128 &&
+      s->block_threads != 256 && s->block_threads != 512)
+    return fail(GI_ERR_UNSUPPORTED, "block_threads must be 0, 64, 128, 256 or 512");
   (void)g;
   return GI_OK;
 }
@@ -479,9 +485,12 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
       g->max_in = std::max(g->max_in, indeg[(size_t)v]);
     }
   }
+  g->h_out_off.assign(out_off, out_off + (size_t)n + 1);
+  std::vector<int32_t> h_udeg((size_t)n);
   for (int32_t v = 0; v < n; ++v) {
     g->h_outdeg[(size_t)v] = out_off[v + 1] - out_off[v];
     g->max_out = std::max(g->max_out, g->h_outdeg[(size_t)v]);
+    h_udeg[(size_t)v] = g->h_outdeg[(size_t)v] + (g->h_in_off[(size_t)v + 1] - g->h_in_off[(size_t)v]);
   }
   (void)hipGetDevice(&g->device);
   const size_t N = (size_t)n, M = (size_t)m, W = (N + 63) / 64;
@@ -504,35 +513,57 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
   G_ALLOC(g->in_off, N + 1);
   G_ALLOC(g->in_idx, M);
   G_ALLOC(g->outdeg, N);
+  G_ALLOC(g->udeg, N);
   G_UP(out_off, g->out_off, 4 * (N + 1));
   G_UP(out_idx, g->out_idx, 4 * M);
   G_UP(g->h_in_off.data(), g->in_off, 4 * (N + 1));
   G_UP(g->h_in_idx.data(), g->in_idx, 4 * M);
   G_UP(g->h_outdeg.data(), g->outdeg, 4 * N);
+  G_UP(h_udeg.data(), g->udeg, 4 * N);
   if (out_w) {
     G_ALLOC(g->out_w, M);
     G_ALLOC(g->in_w, M);
     G_UP(out_w, g->out_w, 4 * M);
     G_UP(in_off ? in_w : t_w.data(), g->in_w, 4 * M);
   }
-  // workspace
-  G_ALLOC(g->sa[0], N);
-  G_ALLOC(g->sa[1], N);
-  for (int k = 0; k < 3; ++k) {
-    G_ALLOC(g->dbv[k], W);
-    G_ALLOC(g->dbm[k], N);
+  // frontier-loop workspace
+  const size_t nchunk = (2 * M) / (size_t)expand_chunk_size() + 2;
+  for (int k = 0; k < 2; ++k) {
+    G_ALLOC(g->fbv[k], W);
+    G_ALLOC(g->fbm[k], W * 64);
   }
   G_ALLOC(g->vis, W);
+  G_ALLOC(g->far, W);
   G_ALLOC(g->lab, N);
   G_ALLOC(g->contrib[0], N);
   G_ALLOC(g->contrib[1], N);
-  G_ALLOC(g->scratch, W + 1);
-  G_ALLOC(g->far[0], N);
-  G_ALLOC(g->far[1], N);
-  G_ALLOC(g->in_far, N);
+  G_ALLOC(g->part, kMaxParts);
+  G_ALLOC(g->blk_cnt, kMaxParts + 1);
+  G_ALLOC(g->blk_deg, kMaxParts + 1);
+  G_ALLOC(g->ids, N);
+  G_ALLOC(g->excl, N + 1);
+  G_ALLOC(g->chunk_item, nchunk);
   G_ALLOC(g->ctl, 1);
-  G_ALLOC(g->st, 1);
-  G_ALLOC(g->sst, 1);
+  {
+    // launch shapes: compaction workgroups own >= 256 words each (<= kMaxParts
+    // workgroups); word-, vertex- and block-parallel grids are capped so that
+    // every workgroup owns one statistics slot
+    Engine& e = g->eng;
+    e.n = n;
+    e.cgrid = (int)std::max<size_t>(1, std::min<size_t>(kMaxParts / 2, (W + 255) / 256));
+    e.tw = (int)((W + e.cgrid - 1) / e.cgrid);
+    e.xgrid = 2048;
+    e.vgrid = (int)std::max<size_t>(1, std::min<size_t>(kMaxParts, (N + 255) / 256));
+    e.wgrid = (int)std::max<size_t>(1, std::min<size_t>(kMaxParts, (W + 3) / 4));
+    e.rgrid = kMaxParts;
+    e.blk_cnt = g->blk_cnt;
+    e.blk_deg = g->blk_deg;
+    e.ids = g->ids;
+    e.excl = g->excl;
+    e.chunk_item = g->chunk_item;
+    e.chunk_cap = (long long)nchunk;
+    e.ctl = g->ctl;
+  }
 #undef G_ALLOC
 #undef G_UP
   if (hipHostMalloc((void**)&g->h_ctl, sizeof(Control), hipHostMallocDefault) != hipSuccess) {
@@ -593,17 +624,35 @@ static DevGraph dev_graph(const gi_graph* g) {
   d.in_idx = g->in_idx;
   d.in_w = g->in_w;
   d.outdeg = g->outdeg;
+  d.udeg = g->udeg;
   return d;
 }
 
-static int traversal_threads(const gi_graph* g) {
-  return g->sched.block_threads == 512 ? 512 : 256;
+static DenseSet frontier_set(const gi_graph* g, int k) {
+  DenseSet d;
+  const bool bm = g->sched.dense_frontier == GI_FRONTIER_BOOLMAP;
+  d.bv = bm ? nullptr : g->fbv[k & 1];
+  d.bm = bm ? g->fbm[k & 1] : nullptr;
+  return d;
 }
 
 // Copy the step log of the last frontier loop into g->stats.
 static gi_status read_loop_stats(gi_graph* g, int alg, hipStream_t s) {
-  HIP_TRY(hipMemcpyAsync(g->h_ctl, g->ctl, sizeof(Control), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(g->h_ctl, g->ctl, offsetof(Control, dir_log), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  const int steps = g->h_ctl->steps;
+  const int k = std::min(steps, kMaxLog);
+  if (k > 0) {
+    HIP_TRY(hipMemcpyAsync(g->h_ctl->dir_log, g->ctl->dir_log, sizeof(int) * k,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(g->h_ctl->f_log, g->ctl->f_log, sizeof(int) * k,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(g->h_ctl->d_log, g->ctl->d_log, sizeof(long long) * k,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(g->h_ctl->w_log, g->ctl->w_log, sizeof(long long) * k,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   const Control& c = *g->h_ctl;
   gi_run_stats& r = g->stats;
   r.algorithm = alg;
@@ -611,11 +660,11 @@ static gi_status read_loop_stats(gi_graph* g, int alg, hipStream_t s) {
   r.dense_steps = c.dense_steps;
   r.edges_examined = (int64_t)c.edges_examined;
   r.trace_len = std::min(c.steps, GI_MAX_TRACE);
-  for (int k = 0; k < r.trace_len; ++k) {
-    r.step_direction[k] = (int8_t)c.dir_log[k];
-    r.step_frontier[k] = c.f_log[k];
-    r.step_degree_sum[k] = c.d_log[k];
-    r.step_edges[k] = c.w_log[k];
+  for (int i = 0; i < r.trace_len; ++i) {
+    r.step_direction[i] = (int8_t)c.dir_log[i];
+    r.step_frontier[i] = c.f_log[i];
+    r.step_degree_sum[i] = c.d_log[i];
+    r.step_edges[i] = c.w_log[i];
   }
   return GI_OK;
 }
@@ -629,55 +678,36 @@ static gi_status read_kernel_ms(gi_graph* g, int launches) {
   return GI_OK;
 }
 
-// Run the frontier loop to completion (persistent: one launch; otherwise one
-// launch per step with the completion flag read back in between).
-static gi_status run_loop(gi_graph* g, LoopParams& p, hipStream_t s) {
-  const int bt = traversal_threads(g);
-  int blocks = loop_max_blocks(bt);
-  if (blocks <= 0) return fail(GI_ERR_DEVICE, "occupancy query for the frontier loop failed");
-  const bool persistent = g->sched.persistent != 0;
-  p.max_steps = persistent ? (1 << 30) : 1;
-  p.forced_dir = -1;
-  const int header = (int)offsetof(Control, dir_log);  // everything but the logs
+// Enqueue steps in batches until the device reports an empty frontier.
+// `step(k)` enqueues step k; it returns the number of kernels it launched
+// (negative on a launch error).
+template <class StepFn>
+static gi_status run_frontier_loop(gi_graph* g, hipStream_t s, int batch, long long max_steps,
+                                   StepFn step, const char* what) {
   int launches = 0;
+  long long k = 0;
   HIP_TRY(hipEventRecord(g->ev[0], s));
-  for (int guard = 0; guard < (1 << 30); ++guard) {
-    ++launches;
-    if (launch_loop(p, bt, blocks, s) != 0) {
-      hipError_t e = hipGetLastError();
-      return fail(GI_ERR_DEVICE, "cooperative launch of the frontier loop failed: %s",
-                  hipGetErrorString(e));
+  for (;;) {
+    for (int b = 0; b < batch; ++b, ++k) {
+      const int nl = step(k);
+      if (nl < 0) {
+        hipError_t e = hipGetLastError();
+        return fail(GI_ERR_DEVICE, "%s: kernel launch failed: %s", what, hipGetErrorString(e));
+      }
+      launches += nl;
     }
     HIP_TRY(hipEventRecord(g->ev[1], s));
-    HIP_TRY(hipMemcpyAsync(g->h_ctl, g->ctl, header, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(g->h_ctl, g->ctl, offsetof(Control, dir_log), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (g->h_ctl->error) return fail(GI_ERR_DEVICE, "frontier loop: grid barrier timed out (grid %d, block %d, generation %u, arrivals %u)", blocks, g->h_ctl->err_block, g->h_ctl->err_gen, g->h_ctl->err_count);
-    if (g->h_ctl->done) return read_kernel_ms(g, launches);
-    if (g->h_ctl->steps > (int)g->n + 2 && p.alg == ALG_BFS)
-      return fail(GI_ERR_DEVICE, "frontier loop did not terminate");
+    if (g->h_ctl->error) return fail(GI_ERR_DEVICE, "%s: internal size check failed", what);
+    if (g->h_ctl->done) break;
+    if (k > max_steps) return fail(GI_ERR_DEVICE, "%s did not terminate", what);
   }
-  return fail(GI_ERR_DEVICE, "frontier loop did not terminate");
+  return read_kernel_ms(g, launches);
 }
 
-static LoopParams loop_params(gi_graph* g, int alg) {
-  LoopParams p;
-  std::memset(&p, 0, sizeof p);
-  p.g = dev_graph(g);
-  p.alg = alg;
-  p.direction = g->sched.direction;
-  p.divisor = g->sched.hybrid_divisor;
-  p.boolmap = g->sched.dense_frontier == GI_FRONTIER_BOOLMAP;
-  p.edges = alg == ALG_CC ? 2 * g->m : g->m;
-  p.sa[0] = g->sa[0];
-  p.sa[1] = g->sa[1];
-  for (int k = 0; k < 3; ++k) {
-    p.dbv[k] = g->dbv[k];
-    p.dbm[k] = g->dbm[k];
-  }
-  p.vis = g->vis;
-  p.ctl = g->ctl;
-  p.st = g->st;
-  return p;
+static int batch_size(const gi_graph* g, int dflt) {
+  return g->sched.steps_per_sync > 0 ? g->sched.steps_per_sync : dflt;
 }
 
 // ---------------------------------------------------------- algorithms ----
@@ -693,55 +723,33 @@ extern "C" gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, floa
   pv.alpha = (double)damping;
   pv.base = (1.0 - (double)damping) / (double)g->n;
   const int bt = g->sched.block_threads > 0 ? g->sched.block_threads : 256;
-  if (g->sched.num_segments <= 1) {
-    PrRows r{g->pr_table, g->pr_ntab, g->in_off, g->in_idx, nullptr};
-    if (g->sched.persistent) {
-      HIP_TRY(hipMemsetAsync(g->ctl, 0, offsetof(Control, dir_log), s));
-      HIP_TRY(hipEventRecord(g->ev[0], s));
-      if (launch_pr_persistent(r, g->pr_cap_e, g->pr_cap_v, bt, g->n, iters, pv, g->contrib[0],
-                               g->contrib[1], ranks, g->ctl, 0, s) != 0) {
-        hipError_t e = hipGetLastError();
-        return fail(GI_ERR_DEVICE, "cooperative PageRank launch failed: %s", hipGetErrorString(e));
-      }
-      HIP_TRY(hipEventRecord(g->ev[1], s));
-      HIP_TRY(hipMemcpyAsync(g->h_ctl, g->ctl, offsetof(Control, dir_log), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      if (g->h_ctl->error) return fail(GI_ERR_DEVICE, "PageRank: grid barrier timed out (block %d, generation %u, arrivals %u)", g->h_ctl->err_block, g->h_ctl->err_gen, g->h_ctl->err_count);
+  int launches = 1;
+  HIP_TRY(hipEventRecord(g->ev[0], s));
+  LAUNCH_TRY(launch_pr_init(g->n, g->outdeg, g->contrib[0], ranks, iters == 0, s));
+  for (int k = 0; k < iters; ++k) {
+    const bool last = k == iters - 1;
+    float* cin = g->contrib[k & 1];
+    float* cout = g->contrib[(k + 1) & 1];
+    if (g->sched.num_segments <= 1) {
+      PrRows r{g->pr_table, g->pr_ntab, g->in_off, g->in_idx, nullptr};
+      LAUNCH_TRY(launch_pr_rows(r, g->pr_cap_e, g->pr_cap_v, bt, 0, cin, 0, pv, cout,
+                                last ? ranks : nullptr, nullptr, s));
+      ++launches;
     } else {
-      HIP_TRY(hipEventRecord(g->ev[0], s));
-      LAUNCH_TRY(launch_pr_init(g->n, g->outdeg, g->contrib[0], ranks, iters == 0, s));
-      for (int k = 0; k < iters; ++k) {
-        const bool last = k == iters - 1;
-        LAUNCH_TRY(launch_pr_rows(r, g->pr_cap_e, g->pr_cap_v, bt, 0, g->contrib[k & 1], 0, pv,
-                                  g->contrib[(k + 1) & 1], last ? ranks : nullptr, nullptr, s));
-      }
-      HIP_TRY(hipEventRecord(g->ev[1], s));
-      HIP_TRY(hipStreamSynchronize(s));
-    }
-  } else {
-    HIP_TRY(hipEventRecord(g->ev[0], s));
-    LAUNCH_TRY(launch_pr_init(g->n, g->outdeg, g->contrib[0], ranks, iters == 0, s));
-    for (int k = 0; k < iters; ++k) {
-      const bool last = k == iters - 1;
       for (const SegDev& sg : g->segs) {
         PrRows r{sg.table, sg.ntab, sg.off, sg.idx, sg.dst};
-        LAUNCH_TRY(launch_pr_rows(r, g->pr_cap_e, g->pr_cap_v, bt, 0, g->contrib[k & 1], 1, pv,
-                                  nullptr, nullptr, g->pr_acc, s));
+        LAUNCH_TRY(launch_pr_rows(r, g->pr_cap_e, g->pr_cap_v, bt, 0, cin, 1, pv, nullptr,
+                                  nullptr, g->pr_acc, s));
+        ++launches;
       }
-      LAUNCH_TRY(launch_pr_seg_final(g->n, pv, g->pr_acc, g->contrib[(k + 1) & 1],
-                                     last ? ranks : nullptr, s));
+      LAUNCH_TRY(launch_pr_seg_final(g->n, pv, g->pr_acc, cout, last ? ranks : nullptr, s));
+      ++launches;
     }
-    HIP_TRY(hipEventRecord(g->ev[1], s));
-    HIP_TRY(hipStreamSynchronize(s));
   }
-  {
-    gi_status ts = read_kernel_ms(g, g->sched.persistent && g->sched.num_segments <= 1
-                                         ? 1
-                                         : 1 + iters * (g->sched.num_segments <= 1
-                                                            ? 1
-                                                            : (int)g->segs.size() + 1));
-    if (ts != GI_OK) return ts;
-  }
+  HIP_TRY(hipEventRecord(g->ev[1], s));
+  HIP_TRY(hipStreamSynchronize(s));
+  gi_status ts = read_kernel_ms(g, launches);
+  if (ts != GI_OK) return ts;
   gi_run_stats& st = g->stats;
   st.algorithm = ALG_PR;
   st.steps = iters;
@@ -752,19 +760,46 @@ extern "C" gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, floa
     st.step_direction[k] = GI_DIR_DENSE_PULL;
     st.step_frontier[k] = g->n;
     st.step_degree_sum[k] = g->m;
+    st.step_edges[k] = g->m;
   }
   return GI_OK;
+}
+
+static DecideArgs decide_args(const gi_graph* g, long long edges) {
+  DecideArgs d;
+  d.part = g->part;
+  d.ctl = g->ctl;
+  d.direction = g->sched.direction;
+  d.divisor = g->sched.hybrid_divisor;
+  d.forced_dir = -1;
+  d.edges = edges;
+  return d;
 }
 
 extern "C" gi_status gi_bfs(gi_graph* g, int32_t src, int32_t* level, int32_t* parent, void* stream) {
   if (!g || !level) return fail(GI_ERR_INVALID_ARG, "NULL argument");
   if (src < 0 || src >= g->n) return fail(GI_ERR_INVALID_ARG, "source %d outside [0, %d)", src, g->n);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  LoopParams p = loop_params(g, ALG_BFS);
-  p.level = level;
-  p.parent = parent;
-  LAUNCH_TRY(launch_loop_init(p, src, s));
-  gi_status st = run_loop(g, p, s);
+  BfsArgs b;
+  b.g = dev_graph(g);
+  b.level = level;
+  b.parent = parent;
+  b.cur = frontier_set(g, 0);
+  b.next = frontier_set(g, 1);
+  b.vis = g->vis;
+  b.part = g->part;
+  b.ctl = g->ctl;
+  LAUNCH_TRY(launch_bfs_init(b, src, frontier_set(g, 0), frontier_set(g, 1), s));
+  const DecideArgs d = decide_args(g, g->m);
+  gi_status st = run_frontier_loop(
+      g, s, batch_size(g, 8), (long long)g->n + 2,
+      [&](long long k) {
+        BfsArgs bk = b;
+        bk.cur = frontier_set(g, (int)(k & 1));
+        bk.next = frontier_set(g, (int)((k + 1) & 1));
+        return enqueue_bfs_step(g->eng, d, bk, s) ? -1 : 7;
+      },
+      "BFS");
   if (st != GI_OK) return st;
   return read_loop_stats(g, ALG_BFS, s);
 }
@@ -772,19 +807,40 @@ extern "C" gi_status gi_bfs(gi_graph* g, int32_t src, int32_t* level, int32_t* p
 extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
   if (!g || !label) return fail(GI_ERR_INVALID_ARG, "NULL argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  LoopParams p = loop_params(g, ALG_CC);
-  p.lab[0] = label;
-  p.lab[1] = g->lab;
-  LAUNCH_TRY(launch_loop_init(p, 0, s));
-  gi_status st = run_loop(g, p, s);
+  int32_t* labs[2] = {label, g->lab};
+  CcArgs c;
+  c.g = dev_graph(g);
+  c.cur = labs[0];
+  c.nxt = labs[1];
+  c.fr = frontier_set(g, 0);
+  c.next = frontier_set(g, 1);
+  c.part = g->part;
+  c.ctl = g->ctl;
+  LAUNCH_TRY(launch_cc_init(c, frontier_set(g, 0), frontier_set(g, 1), labs[1], s));
+  const DecideArgs d = decide_args(g, 2 * g->m);
+  const RowBlocks in_rows{g->pr_table, g->pr_ntab, g->in_off, g->in_idx};
+  const RowBlocks out_rows{g->out_table, g->out_ntab, g->out_off, g->out_idx};
+  gi_status st = run_frontier_loop(
+      g, s, batch_size(g, 8), (long long)g->n + 2,
+      [&](long long k) {
+        CcArgs ck = c;
+        ck.cur = labs[k & 1];
+        ck.nxt = labs[(k + 1) & 1];
+        ck.fr = frontier_set(g, (int)(k & 1));
+        ck.next = frontier_set(g, (int)((k + 1) & 1));
+        return enqueue_cc_step(g->eng, d, ck, in_rows, out_rows, g->pr_cap_e, g->pr_cap_v, s) ? -1
+                                                                                              : 8;
+      },
+      "CC");
   if (st != GI_OK) return st;
-  LoopState ls;
-  HIP_TRY(hipMemcpyAsync(&ls, g->st, sizeof ls, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (ls.lab_cur != 0)
-    HIP_TRY(hipMemcpyAsync(label, g->lab, 4 * (size_t)g->n, hipMemcpyDeviceToDevice, s));
   st = read_loop_stats(g, ALG_CC, s);
-  return st;
+  if (st != GI_OK) return st;
+  // after `steps` rounds the labels sit in labs[steps & 1]
+  if (g->stats.steps & 1) {
+    HIP_TRY(hipMemcpyAsync(label, g->lab, 4 * (size_t)g->n, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return GI_OK;
 }
 
 extern "C" gi_status gi_sssp(gi_graph* g, int32_t src, uint32_t* dist, void* stream) {
@@ -792,45 +848,36 @@ extern "C" gi_status gi_sssp(gi_graph* g, int32_t src, uint32_t* dist, void* str
   if (!g->weighted) return fail(GI_ERR_INVALID_ARG, "graph has no edge weights");
   if (src < 0 || src >= g->n) return fail(GI_ERR_INVALID_ARG, "source %d outside [0, %d)", src, g->n);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  SsspParams p;
-  std::memset(&p, 0, sizeof p);
-  p.g = dev_graph(g);
-  p.dist = dist;
-  p.near[0] = g->sa[0];
-  p.near[1] = g->sa[1];
-  p.far[0] = g->far[0];
-  p.far[1] = g->far[1];
-  p.stamp = g->lab;
-  p.in_far = g->in_far;
-  p.delta = g->sched.sssp_delta > 0 ? g->sched.sssp_delta : 512u;
-  p.max_phases = 1 << 30;
-  p.ctl = g->ctl;
-  p.st = g->sst;
-  const int bt = traversal_threads(g);
-  const int blocks = sssp_max_blocks(bt);
-  if (blocks <= 0) return fail(GI_ERR_DEVICE, "occupancy query for delta-stepping failed");
-  LAUNCH_TRY(launch_sssp_init(p, src, s));
-  const int header = (int)offsetof(Control, dir_log);  // everything but the logs
-  int launches = 0;
-  HIP_TRY(hipEventRecord(g->ev[0], s));
-  for (;;) {
-    ++launches;
-    if (launch_sssp(p, bt, blocks, s) != 0) {
-      hipError_t e = hipGetLastError();
-      return fail(GI_ERR_DEVICE, "cooperative launch of delta-stepping failed: %s",
-                  hipGetErrorString(e));
-    }
-    HIP_TRY(hipEventRecord(g->ev[1], s));
-    HIP_TRY(hipMemcpyAsync(g->h_ctl, g->ctl, header, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (g->h_ctl->error) return fail(GI_ERR_DEVICE, "delta-stepping: grid barrier timed out (grid %d, block %d, generation %u, arrivals %u)", blocks, g->h_ctl->err_block, g->h_ctl->err_gen, g->h_ctl->err_count);
-    if (g->h_ctl->overflow) return fail(GI_ERR_OVERFLOW, "a distance reached UINT32_MAX");
-    if (g->h_ctl->done) break;
-  }
-  gi_status st = read_loop_stats(g, ALG_SSSP, s);
+  SsspArgs a;
+  a.g = dev_graph(g);
+  a.dist = dist;
+  a.cur = DenseSet{g->fbv[0], nullptr};
+  a.next = DenseSet{g->fbv[1], nullptr};
+  a.far = DenseSet{g->far, nullptr};
+  a.delta = g->sched.sssp_delta > 0 ? g->sched.sssp_delta : 512u;
+  a.part = g->part;
+  a.ctl = g->ctl;
+  LAUNCH_TRY(launch_sssp_init(a, src, a.cur, a.next, s));
+  gi_status st = run_frontier_loop(
+      g, s, batch_size(g, 64), 64LL * g->n + 1024,
+      [&](long long k) {
+        SsspArgs ak = a;
+        ak.cur = DenseSet{g->fbv[k & 1], nullptr};
+        ak.next = DenseSet{g->fbv[(k + 1) & 1], nullptr};
+        return enqueue_sssp_step(g->eng, ak, s) ? -1 : 8;
+      },
+      "SSSP");
   if (st != GI_OK) return st;
+  HIP_TRY(hipMemcpyAsync(g->h_ctl, g->ctl, offsetof(Control, dir_log), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (g->h_ctl->overflow) return fail(GI_ERR_OVERFLOW, "a distance reached UINT32_MAX");
+  const float kms = g->stats.kernel_ms;
+  const int nl = g->stats.launches;
+  st = read_loop_stats(g, ALG_SSSP, s);
+  g->stats.kernel_ms = kms;
+  g->stats.launches = nl;
   g->stats.dense_steps = 0;
-  return read_kernel_ms(g, launches);
+  return st;
 }
 
 extern "C" gi_status gi_get_run_stats(const gi_graph* g, gi_run_stats* out) {

@@ -1,5 +1,17 @@
 // Internal definitions shared by the HIP kernels and the host driver.
 // gfx950 (CDNA4): 64-lane wavefronts, 256 CUs in 8 XCDs, 160 KiB LDS per CU.
+//
+// Execution model of the frontier loops: one kernel launch per phase of a
+// step, all on one stream.  A single-workgroup "decide" kernel reads the
+// statistics the previous step left behind, picks the direction of the next
+// step and writes it to device memory; every other kernel of the step reads
+// that mode at entry and returns at once when it is not its turn.  The host
+// enqueues a batch of steps and looks at the completion flag once per batch.
+// Kernel boundaries order the phases, so no grid-wide barrier is needed.
+//
+// Statistics are reduced per workgroup and stored (plain stores, one slot
+// per workgroup) rather than accumulated with atomics on a single address:
+// device-scope atomics on one address serialize at the memory side.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,8 +22,8 @@
 namespace gi {
 
 constexpr int kWave = 64;
-// Persistent (cooperative) grids use at most this many workgroups per CU.
-constexpr int kMaxPersistentBlocksPerCU = 4;
+constexpr int kMaxParts = 4096;  // per-workgroup statistic slots
+constexpr int kMaxLog = 4096;    // per-step trace entries
 
 // ---------------------------------------------------------------------------
 // Device-side adjacency.  CSR rows (out-edges) and CSC rows (in-edges) are
@@ -27,63 +39,58 @@ struct DevGraph {
   const int32_t* in_idx;
   const uint32_t* in_w;
   const int32_t* outdeg;  // out_off[v+1]-out_off[v]
+  const int32_t* udeg;    // out-degree + in-degree
 };
 
-// Control block for one algorithm run, in device memory.  Counters for step
-// k live in slot k % 3 so that the slot for step k+2 can be cleared while
-// step k runs and step k-1's counts are no longer read.
-//
-// Words that several workgroups update during a kernel sit in cache lines of
-// their own and are only written with agent-scope atomics: the per-XCD L2
-// caches are not coherent with each other, so a plain store that leaves a
-// line dirty in one XCD must never share that line with words other XCDs
-// update.  Fields written by workgroup 0 alone and read by the host after
-// the kernel (the step log) live in separate lines.
-struct alignas(128) StepCounters {
-  unsigned long long count;   // |F'| produced by the step
-  unsigned long long degsum;  // sum of degrees of F'
-  unsigned long long work;    // edges examined by the step
-  unsigned long long pad;     // spare counter (frontier compaction)
-  unsigned long long fill[12];
+// Per-workgroup statistics of one phase.
+struct Part {
+  long long a;  // e.g. vertices added to the next frontier
+  long long b;  // e.g. their degree sum
+  long long c;  // e.g. edges examined
+  long long d;
 };
 
+// Step modes written by the decide kernels.
+enum : int {
+  MODE_NEVER = -100,  // "no second mode" in a gate; never written as a mode
+  MODE_NONE = -1,
+  MODE_SPARSE_PUSH = GI_DIR_SPARSE_PUSH,
+  MODE_DENSE_PUSH = GI_DIR_DENSE_PUSH,
+  MODE_DENSE_PULL = GI_DIR_DENSE_PULL,
+  MODE_SSSP_RELAX = 10,
+  MODE_SSSP_SPLIT = 11,
+};
+
+// Control block of one algorithm run (device memory).
 struct Control {
-  // grid barrier (line 0)
-  alignas(128) unsigned int bar_count;  // arrivals
-  unsigned int bar_gen;                 // generation
-  int error;                            // nonzero: a persistent kernel gave up
-  int err_block;                        // diagnostics of the first time-out
-  unsigned int err_gen;
-  unsigned int err_count;
-  StepCounters slot[3];                 // lines 1-3
-  // SSSP (line 4)
-  alignas(128) unsigned long long far_count[2];  // far piles
-  unsigned long long minreg[2];                  // smallest far distance
-  int overflow;                                  // a distance reached UINT32_MAX
-  // host-facing results, written by workgroup 0 only (line 5 on)
-  alignas(128) int steps;                        // steps executed
+  int mode;           // mode of the step being executed
+  int done;           // 1 once the frontier is empty
+  int steps;          // steps decided so far
   int dense_steps;
-  int done;
-  int buckets;                                   // SSSP bucket advances
-  unsigned long long edges_examined;
-  alignas(128) int dir_log[4096];  // per-step direction
-  int f_log[4096];                 // per-step frontier size
-  long long d_log[4096];           // per-step frontier degree sum
-  long long w_log[4096];           // per-step edges examined
+  long long nf;       // |F| entering the current step
+  long long dsum;     // sum of degrees of F
+  long long sa_count; // sparse items (degree > 0) after compaction
+  long long sa_slots; // their degree sum (edge slots of the expansion)
+  long long nchunks;  // expansion chunks
+  long long edges_examined;
+  // SSSP
+  unsigned long long thresh;   // current bucket ends below thresh
+  unsigned long long told;     // previous threshold (split phase)
+  long long far_count;
+  int overflow;
+  int buckets;
+  int error;          // an internal size invariant failed (the run is abandoned)
+  int pad;
+  // trace
+  int dir_log[kMaxLog];
+  int f_log[kMaxLog];
+  long long d_log[kMaxLog];
+  long long w_log[kMaxLog];
 };
 
-__device__ __forceinline__ void atomic_zero(unsigned long long* p) {
-  __hip_atomic_store(p, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long atomic_read(unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // ---------------------------------------------------------------------------
-// Wave helpers (wave64).
+// Wave / workgroup helpers (wave64).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
-
 __device__ __forceinline__ unsigned long long lanemask_lt() {
   const int l = __lane_id();
   return l == 0 ? 0ull : (~0ull >> (64 - l));
@@ -96,73 +103,82 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// Exclusive prefix sum across the wave (Hillis-Steele with shuffles).
-__device__ __forceinline__ int wave_excl_scan(int v, int* total) {
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const T y = __shfl_xor(v, o, kWave);
+    v = y < v ? y : v;
+  }
+  return v;
+}
+
+// Exclusive prefix sum across the wave.
+template <typename T>
+__device__ __forceinline__ T wave_excl_scan(T v, T* total) {
   const int l = __lane_id();
-  int x = v;
+  T x = v;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    int y = __shfl_up(x, o, kWave);
+    const T y = __shfl_up(x, o, kWave);
     if (l >= o) x += y;
   }
   *total = __shfl(x, 63, kWave);
   return x - v;
 }
 
-// Bounded-spin grid barrier for cooperative launches.  Every workgroup of
-// the grid must call it the same number of times.  Every work-item makes its
-// own global writes and atomics visible at agent scope before its workgroup
-// arrives (a workgroup barrier alone does not wait for other waves' memory
-// operations), and acquires after the release, so data written by any XCD
-// before the barrier is seen by every XCD after it.  Returns false (and sets
-// ctl->error) if the wait exceeds the spin limit, so that a kernel whose grid
-// is not fully resident still drains instead of hanging.
-__device__ __forceinline__ bool grid_barrier(Control* ctl, unsigned nblocks, unsigned* gen_lds) {
-  __shared__ int ok_lds;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int ok = 1;
-    const unsigned g = *gen_lds;
-    const unsigned arrived =
-        __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == nblocks - 1) {
-      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl->bar_gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      long long spins = 0;
-      while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > (1ll << 24)) {
-          ok = 0;
-          if (__hip_atomic_exchange(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-            __hip_atomic_store(&ctl->err_block, (int)blockIdx.x, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->err_gen, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->err_count,
-                               __hip_atomic_load(&ctl->bar_count, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
-          break;
-        }
-        if ((spins & 255) == 0 &&
-            __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-          ok = 0;
-          break;
-        }
-      }
-    }
-    *gen_lds = g + 1;
-    ok_lds = ok;
+// Sum of four counters over the workgroup; result valid in thread 0.
+template <int BT>
+__device__ __forceinline__ Part block_sum4(Part p) {
+  __shared__ long long sh[4][BT / kWave];
+  p.a = wave_sum(p.a);
+  p.b = wave_sum(p.b);
+  p.c = wave_sum(p.c);
+  p.d = wave_sum(p.d);
+  const int w = threadIdx.x / kWave;
+  if (__lane_id() == 0) {
+    sh[0][w] = p.a;
+    sh[1][w] = p.b;
+    sh[2][w] = p.c;
+    sh[3][w] = p.d;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return ok_lds != 0;
+  Part r{0, 0, 0, 0};
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < BT / kWave; ++i) {
+      r.a += sh[0][i];
+      r.b += sh[1][i];
+      r.c += sh[2][i];
+      r.d += sh[3][i];
+    }
+  }
+  __syncthreads();
+  return r;
+}
+
+// Workgroup exclusive scan of one value per thread (BT threads); returns
+// the exclusive prefix and writes the workgroup total to *total.
+template <int BT, typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T* total) {
+  __shared__ T wsum[BT / kWave];
+  T wt;
+  const T ex = wave_excl_scan(v, &wt);
+  const int w = threadIdx.x / kWave;
+  if (__lane_id() == 0) wsum[w] = wt;
+  __syncthreads();
+  T base = 0, tot = 0;
+  for (int i = 0; i < BT / kWave; ++i) {
+    if (i < w) base += wsum[i];
+    tot += wsum[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + ex;
 }
 
 // Hybrid rule of the paper (section 2): dense when |F| + sum deg(F) exceeds
-// edges / divisor.  Mirrors gi_hybrid_choose_dense on the device.
+// edges / divisor, evaluated as (|F| + D_F) * divisor > edges.  Mirrors
+// gi_hybrid_choose_dense on the device.
 __host__ __device__ __forceinline__ bool hybrid_dense(long long nf, long long degsum,
                                                       long long edges, int divisor) {
   return (nf + degsum) * (long long)divisor > edges;

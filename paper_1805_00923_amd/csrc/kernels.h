@@ -2,61 +2,36 @@
 #pragma once
 
 #include "common.h"
+#include "traverse.h"
 
 namespace gi {
 
 enum : int { ALG_PR = 0, ALG_BFS = 1, ALG_CC = 2, ALG_SSSP = 3 };
 
-// State that survives across launches of the frontier loop.
-struct LoopState {
-  int step;       // steps done (BFS: current level)
-  int rep;        // REP_SPARSE / REP_DENSE: where the current frontier lives
-  int sa_cur;     // which sparse buffer holds the current frontier
-  int vis_valid;  // BFS: visited bitvector matches the level array
-  int cc_fix;     // CC: next push step must first copy cur->nxt on F
-  int lab_cur;    // CC: which label buffer holds L_k (0: user array, 1: workspace)
-  int pad[2];
+// Rows of one adjacency split into destination blocks (PageRank and CC pull).
+struct RowBlocks {
+  const int2* table;    // (first row, end row) per block
+  int ntab;
+  const int32_t* off;
+  const int32_t* idx;
 };
 
-struct LoopParams {
-  DevGraph g;
-  int alg;
-  int direction;      // GI_DIR_*
-  int divisor;
-  int boolmap;        // dense frontier kind
-  int max_steps;      // steps to run in this launch
-  int forced_dir;     // >= 0: direction of the next step (trace/exhaustive)
-  long long edges;    // edge count of the traversal view (m, or 2m for CC)
-  int32_t* level;     // BFS
-  int32_t* parent;    // BFS, may be null
-  int32_t* lab[2];    // CC
-  int32_t* sa[2];
-  uint64_t* dbv[3];   // dense frontier rotation (bitvector)
-  uint8_t* dbm[3];    // dense frontier rotation (bool map)
-  uint64_t* vis;      // BFS visited bitvector
+// Scratch and launch shapes shared by the frontier loops of one graph.
+struct Engine {
+  int n;
+  int tw;           // compaction: words per workgroup
+  int cgrid;        // compaction / word-parallel grid
+  int xgrid;        // edge-balanced expansion grid
+  int vgrid;        // vertex-parallel grid (DensePush)
+  int wgrid;        // wave-per-word grid (DensePull)
+  int rgrid;        // destination-block grid cap
+  long long* blk_cnt;
+  long long* blk_deg;
+  int32_t* ids;
+  long long* excl;
+  int32_t* chunk_item;
+  long long chunk_cap;  // entries of chunk_item
   Control* ctl;
-  LoopState* st;
-};
-
-struct SsspState {
-  int phase;       // relaxation steps done
-  int near_cur;    // which near buffer holds the current pile
-  int far_cur;     // which far buffer holds the current pile
-  int pad;
-  unsigned long long thresh;  // current bucket ends below thresh
-};
-
-struct SsspParams {
-  DevGraph g;
-  uint32_t* dist;
-  int32_t* near[2];
-  int32_t* far[2];
-  int32_t* stamp;
-  int32_t* in_far;
-  unsigned long long delta;
-  int max_phases;
-  Control* ctl;
-  SsspState* st;
 };
 
 struct PrRows {
@@ -73,14 +48,56 @@ struct PrVertex {
   double alpha;
 };
 
-// ---- launchers (return 0 on success) ----
-int launch_loop_init(const LoopParams& p, int src, hipStream_t stream);
-int loop_max_blocks(int block_threads);
-int launch_loop(LoopParams p, int block_threads, int blocks, hipStream_t stream);
+struct DecideArgs {
+  Part* part;
+  Control* ctl;
+  int direction;   // GI_DIR_*
+  int divisor;
+  int forced_dir;  // >= 0: direction of every step (per-schedule timing)
+  long long edges; // m for BFS, 2m for CC (edges counted in both directions)
+};
 
-int launch_sssp_init(const SsspParams& p, int src, hipStream_t stream);
-int sssp_max_blocks(int bt);
-int launch_sssp(SsspParams p, int bt, int blocks, hipStream_t stream);
+struct BfsArgs {
+  DevGraph g;
+  int32_t* level;
+  int32_t* parent;  // may be null
+  DenseSet cur;     // frontier of the step
+  DenseSet next;    // frontier it produces
+  uint64_t* vis;    // visited bitvector
+  Part* part;
+  Control* ctl;
+};
+
+struct CcArgs {
+  DevGraph g;
+  int32_t* cur;        // labels L_k
+  int32_t* nxt;        // labels L_{k+1}
+  DenseSet fr;         // vertices whose label changed in the previous round
+  DenseSet next;       // vertices whose label changes in this round
+  Part* part;
+  Control* ctl;
+};
+
+struct SsspArgs {
+  DevGraph g;
+  uint32_t* dist;
+  DenseSet cur;        // near set relaxed by this phase
+  DenseSet next;       // near set of the next phase
+  DenseSet far;        // far set
+  unsigned long long delta;
+  Part* part;
+  Control* ctl;
+};
+
+// ---- launchers (return 0 on success) ----
+int expand_chunk_size();
+int launch_bfs_init(const BfsArgs& b, int src, DenseSet f0, DenseSet f1, hipStream_t s);
+int enqueue_bfs_step(const Engine& e, const DecideArgs& d, const BfsArgs& b, hipStream_t s);
+int launch_cc_init(const CcArgs& c, DenseSet f0, DenseSet f1, int32_t* lab_other, hipStream_t s);
+int enqueue_cc_step(const Engine& e, const DecideArgs& d, const CcArgs& c, const RowBlocks& in_rows,
+                    const RowBlocks& out_rows, int cap_e, int cap_v, hipStream_t s);
+int launch_sssp_init(const SsspArgs& sa, int src, DenseSet f0, DenseSet f1, hipStream_t s);
+int enqueue_sssp_step(const Engine& e, const SsspArgs& sa, hipStream_t s);
 
 int launch_pr_init(int n, const int32_t* outdeg, float* c0, float* rank, bool zero_iters,
                    hipStream_t s);
@@ -89,9 +106,6 @@ int launch_pr_rows(const PrRows& r, int cap_e, int cap_v, int bt, int grid, cons
                    hipStream_t s);
 int launch_pr_seg_final(int n, const PrVertex& pv, double* acc, float* cout, float* rank,
                         hipStream_t s);
-int launch_pr_persistent(const PrRows& r, int cap_e, int cap_v, int bt, int n, int iters,
-                         const PrVertex& pv, float* c0, float* c1, float* rank, Control* ctl,
-                         int max_blocks_per_cu, hipStream_t s);
 
 int launch_sparse_to_bitvec(int n, const int32_t* ids, int count, uint64_t* bv, hipStream_t s);
 int launch_bitvec_to_sparse(int n, const uint64_t* bv, int32_t* ids, int32_t* count,

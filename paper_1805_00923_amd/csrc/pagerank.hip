@@ -134,33 +134,6 @@ __global__ void k_pr_seg_final(int n, PrVertex pv, double* acc, float* cout, flo
   }
 }
 
-// Persistent form: all iterations in one cooperative launch, one grid
-// barrier per iteration (unsegmented only).
-template <int BT>
-__global__ __launch_bounds__(BT) void k_pr_persistent(PrRows r, int cap_e, int n, int iters,
-                                                      PrVertex pv, float* c0, float* c1,
-                                                      float* rank, Control* ctl) {
-  extern __shared__ float smem[];
-  __shared__ unsigned gen;
-  float* lds_val = smem;
-  int* lds_off = reinterpret_cast<int*>(smem + cap_e);
-  if (threadIdx.x == 0)
-    gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  pr_init_range(blockIdx.x * BT + threadIdx.x, gridDim.x * BT, n, pv.outdeg, c0, rank, iters == 0);
-  if (iters == 0) return;
-  if (!grid_barrier(ctl, gridDim.x, &gen)) return;
-  for (int k = 0; k < iters; ++k) {
-    const float* cin = (k & 1) ? c1 : c0;
-    float* cout = (k & 1) ? c0 : c1;
-    const bool last = k == iters - 1;
-    for (int t = blockIdx.x; t < r.ntab; t += gridDim.x)
-      pr_rows_block<BT>(r, t, cap_e, cin, 0, pv, cout, last ? rank : nullptr, nullptr, lds_val,
-                        lds_off);
-    if (!last && !grid_barrier(ctl, gridDim.x, &gen)) return;
-  }
-}
-
 // ------------------------------------------------------- host launchers ----
 
 static size_t pr_lds_bytes(int cap_e, int cap_v) {
@@ -197,42 +170,6 @@ int launch_pr_seg_final(int n, const PrVertex& pv, double* acc, float* cout, flo
   hipLaunchKernelGGL(k_pr_seg_final, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, n, pv, acc,
                      cout, rank);
   return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
-template <int BT>
-static int pr_persistent_blocks(size_t lds) {
-  int dev = 0, ncu = 0, per = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return -1;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_pr_persistent<BT>, BT, lds) != hipSuccess)
-    return -1;
-  return per > 0 ? ncu * std::min(per, kMaxPersistentBlocksPerCU) : -1;
-}
-
-int launch_pr_persistent(const PrRows& r, int cap_e, int cap_v, int bt, int n, int iters,
-                         const PrVertex& pv, float* c0, float* c1, float* rank, Control* ctl,
-                         int max_blocks_per_cu, hipStream_t s) {
-  size_t lds = pr_lds_bytes(cap_e, cap_v);
-  int blocks = -1;
-  const void* fn = nullptr;
-  switch (bt) {
-    case 128: blocks = pr_persistent_blocks<128>(lds); fn = reinterpret_cast<const void*>(k_pr_persistent<128>); break;
-    case 256: blocks = pr_persistent_blocks<256>(lds); fn = reinterpret_cast<const void*>(k_pr_persistent<256>); break;
-    case 512: blocks = pr_persistent_blocks<512>(lds); fn = reinterpret_cast<const void*>(k_pr_persistent<512>); break;
-    default: return -1;
-  }
-  if (blocks <= 0) return -1;
-  int dev = 0, ncu = 0;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (max_blocks_per_cu > 0 && ncu > 0) blocks = std::min(blocks, ncu * max_blocks_per_cu);
-  blocks = std::max(1, std::min(blocks, std::max(r.ntab, 1)));
-  PrRows rr = r;
-  int ce = cap_e;
-  PrVertex pvv = pv;
-  void* args[] = {&rr, &ce, &n, &iters, &pvv, &c0, &c1, &rank, &ctl};
-  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(bt), args, (unsigned)lds, s);
-  return e == hipSuccess ? 0 : -1;
 }
 
 }  // namespace gi

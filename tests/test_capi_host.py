@@ -117,7 +117,7 @@ def test_default_schedule():
     gi = _gi()
     s = gi.default_schedule()
     assert s.direction == gi.DENSE_PULL_SPARSE_PUSH
-    assert s.hybrid_divisor == 20 and s.num_segments == 1 and s.persistent == 1
+    assert s.hybrid_divisor == 20 and s.num_segments == 1 and s.steps_per_sync == 0
 
 
 def test_hybrid_rule_as_written():

@@ -31,6 +31,8 @@ def families():
         gg.empty(17), gg.empty(1), gg.grid(30, 41, 0.0, weighted=False),
         gg.uniform(2000, 9000, seed=3), gg.uniform(129, 40, seed=4),
         gg.rmat(8, seed=21), gg.rmat(11, seed=22), gg.rmat(13, seed=23),
+        # more than 256 bitvector words: several compaction workgroups
+        gg.rmat(15, seed=24), gg.uniform(300000, 1200000, seed=25),
     ]
     # a hub with more in- and out-edges than any block or wave holds
     n = 5000
@@ -59,13 +61,13 @@ def sources_of(el, k=3):
 
 
 TRAVERSAL_SCHEDULES = [
-    dict(direction=d, dense_frontier=f, persistent=p)
-    for d, f, p in itertools.product(range(5), (0, 1), (1, 0))
+    dict(direction=d, dense_frontier=f, steps_per_sync=p)
+    for d, f, p in itertools.product(range(5), (0, 1), (0, 1))
 ]
 
 
 def sched_name(s):
-    return "dir%d_fr%d_p%d" % (s["direction"], s["dense_frontier"], s["persistent"])
+    return "dir%d_fr%d_sync%d" % (s["direction"], s["dense_frontier"], s["steps_per_sync"])
 
 
 # ------------------------------------------------------------------ PageRank
@@ -81,13 +83,10 @@ def test_pagerank_families_default():
 
 
 @pytest.mark.parametrize("cfg", [
-    dict(persistent=1), dict(persistent=0),
-    dict(persistent=1, pull_block_edges=64), dict(persistent=0, pull_block_edges=256),
-    dict(persistent=1, pull_block_edges=8192, block_threads=512),
-    dict(persistent=0, block_threads=128), dict(persistent=1, block_threads=128),
-    dict(persistent=0, num_segments=2), dict(persistent=0, num_segments=3, segment_strategy=1),
-    dict(persistent=0, num_segments=8, pull_block_edges=128),
-    dict(persistent=0, num_segments=64, segment_strategy=1),
+    dict(), dict(pull_block_edges=64), dict(pull_block_edges=256),
+    dict(pull_block_edges=8192, block_threads=512), dict(block_threads=64),
+    dict(block_threads=128), dict(num_segments=2), dict(num_segments=3, segment_strategy=1),
+    dict(num_segments=8, pull_block_edges=128), dict(num_segments=64, segment_strategy=1),
 ], ids=lambda c: "_".join("%s%s" % (k[:6], v) for k, v in c.items()))
 def test_pagerank_schedules(cfg):
     for el, g, og in fam_graphs():
@@ -105,8 +104,7 @@ def test_pagerank_rmat16_workload():
     og = oracle.Graph(el)
     g = device_graph(el)
     ref = oracle.pagerank(og, 20, 0.85)
-    for cfg in (dict(), dict(persistent=0), dict(persistent=0, num_segments=4),
-                dict(persistent=0, num_segments=4, segment_strategy=1)):
+    for cfg in (dict(), dict(num_segments=4), dict(num_segments=4, segment_strategy=1)):
         say("pr rmat16 %s" % cfg)
         g.set_schedule(**cfg)
         x = run_pr(g, 20)
@@ -133,8 +131,12 @@ def test_bfs_all_schedules(sched):
         g.set_schedule()
 
 
+def by_name(name):
+    return next(x for x in fam_graphs() if x[0].name == name)
+
+
 def test_bfs_without_parent_and_divisors():
-    el, g, og = fam_graphs()[-2]
+    el, g, og = by_name("rmat13_ef16_s23")
     for div in (1, 5, 20, 1000, 1 << 30):
         g.set_schedule(hybrid_divisor=div)
         for s in sources_of(el, 4):
@@ -146,7 +148,7 @@ def test_bfs_without_parent_and_divisors():
 
 def test_bfs_hybrid_switches_direction():
     """On a power-law graph the hybrid schedule must actually use both sides."""
-    el, g, og = fam_graphs()[-2]
+    el, g, og = by_name("rmat13_ef16_s23")
     g.set_schedule(direction=3)
     s = sources_of(el, 1)[0]
     lv, _ = run_bfs(g, s)
@@ -177,7 +179,8 @@ def test_cc_all_schedules(sched):
 # ---------------------------------------------------------------------- SSSP
 
 def weighted_families():
-    fam = [gg.grid(40, 50, 0.01, seed=4), gg.grid(64, 64, 0.0, seed=7)]
+    fam = [gg.grid(40, 50, 0.01, seed=4), gg.grid(64, 64, 0.0, seed=7),
+           gg.grid(200, 300, 0.01, seed=6)]
     for sc, seed in ((10, 31), (13, 32)):
         el = gg.rmat(sc, seed=seed)
         el.w = gg.uniform_weights(el.m, seed, 1, 1000)
@@ -264,7 +267,7 @@ def test_frontier_conversions(n):
 
 def test_frontier_degree_sum():
     torch, dev = torch_dev()
-    el, g, og = fam_graphs()[-2]
+    el, g, og = by_name("rmat13_ef16_s23")
     ids = np.array(sources_of(el, 3) + [0, 1, 2], np.int32)
     out = torch.zeros((2,), dtype=torch.int64, device=dev)
     g.frontier_degree_sum(torch.from_numpy(ids).to(dev), ids.size, out)
@@ -279,7 +282,7 @@ def test_schedule_errors_and_bad_arguments():
     gi = _gi()
     el, g, og = fam_graphs()[0]
     for bad in (dict(direction=9), dict(dense_frontier=5), dict(num_segments=0),
-                dict(num_segments=4, persistent=1), dict(hybrid_divisor=0),
+                dict(steps_per_sync=-1), dict(hybrid_divisor=0),
                 dict(block_threads=100), dict(pull_block_edges=10)):
         with pytest.raises(gi.GiError) as e:
             g.set_schedule(**bad)
