@@ -55,7 +55,7 @@ struct SegDev {
   int32_t* off = nullptr;
   int32_t* idx = nullptr;
   int32_t* dst = nullptr;
-  int2* table = nullptr;
+  int4* table = nullptr;
   int ntab = 0;
   int nrows = 0;
   int64_t nnz = 0;
@@ -79,10 +79,16 @@ struct gi_graph {
   std::vector<int32_t> h_in_off, h_in_idx, h_out_off, h_outdeg;
   gi_schedule sched{};
   // destination blocks of the in-rows (PageRank, CC pull pass 0) and out-rows
-  int2* pr_table = nullptr;
+  int4* pr_table = nullptr;
   int pr_ntab = 0, pr_cap_e = 0, pr_cap_v = 0;
-  int2* out_table = nullptr;
-  int out_ntab = 0;
+  double* lr_acc = nullptr;
+  unsigned* lr_cnt = nullptr;
+  int32_t* lr_chunks = nullptr;
+  // symmetric adjacency and its destination blocks (CC; built on first use)
+  int32_t* sym_off = nullptr;
+  int32_t* sym_idx = nullptr;
+  int2* sym_table = nullptr;
+  int sym_ntab = 0;
   std::vector<SegDev> segs;
   double* pr_acc = nullptr;
   // frontier-loop workspace
@@ -93,13 +99,15 @@ struct gi_graph {
   int32_t* lab = nullptr;                 // CC second label buffer
   float* contrib[2] = {nullptr, nullptr};
   Part* part = nullptr;
-  long long* blk_cnt = nullptr;
-  long long* blk_deg = nullptr;
+  Blk* blk = nullptr;
+  unsigned long long* fmin = nullptr;
   int32_t* ids = nullptr;
   long long* excl = nullptr;
   int32_t* chunk_item = nullptr;
   Control* ctl = nullptr;
-  Control* h_ctl = nullptr;    // pinned host mirror
+  Control* h_ctl = nullptr;    // host copy of the control block (trace)
+  HostFlags* hflags = nullptr; // pinned, written by the decide kernels
+  HostFlags* dflags = nullptr; // device address of hflags
   Engine eng{};
   hipEvent_t ev[2] = {nullptr, nullptr};
   gi_run_stats stats{};
@@ -244,6 +252,39 @@ static std::vector<int2> make_row_blocks(const int32_t* off, int nrows, int cap_
   return longs;
 }
 
+// PageRank destination blocks: whole-row blocks as above, except that a
+// row longer than cap_e becomes ceil(len/cap_e) chunk entries (listed
+// first) sharing one long-row slot.
+static std::vector<int4> make_pr_table(const int32_t* off, int nrows, int cap_e, int cap_v,
+                                       std::vector<int32_t>* chunks) {
+  std::vector<int4> longs, rest;
+  chunks->clear();
+  int r = 0;
+  while (r < nrows) {
+    const int64_t d = (int64_t)off[r + 1] - off[r];
+    if (d > cap_e) {
+      const int slot = (int)chunks->size();
+      const int nc = (int)((d + cap_e - 1) / cap_e);
+      chunks->push_back(nc);
+      for (int c = 0; c < nc; ++c) longs.push_back(make_int4(r, r + 1, slot, c));
+      ++r;
+      continue;
+    }
+    int e = r;
+    int64_t sum = 0;
+    while (e < nrows && e - r < cap_v) {
+      const int64_t de = (int64_t)off[e + 1] - off[e];
+      if (de > cap_e || sum + de > cap_e) break;
+      sum += de;
+      ++e;
+    }
+    rest.push_back(make_int4(r, e, -1, 0));
+    r = e;
+  }
+  longs.insert(longs.end(), rest.begin(), rest.end());
+  return longs;
+}
+
 static gi_status upload(const void* h, void* d, size_t bytes) {
   if (bytes == 0) return GI_OK;
   HIP_TRY(hipMemcpy(d, h, bytes, hipMemcpyHostToDevice));
@@ -293,7 +334,9 @@ static gi_status build_segments(gi_graph* g, int p, int strategy) {
     SegDev& s = g->segs[(size_t)i];
     s.nrows = (int)sdst.size();
     s.nnz = (int64_t)sidx.size();
-    std::vector<int2> tab = make_row_blocks(soff.data(), s.nrows, g->pr_cap_e, g->pr_cap_v);
+    std::vector<int32_t> seg_chunks;
+    std::vector<int4> tab = make_pr_table(soff.data(), s.nrows, g->pr_cap_e, g->pr_cap_v,
+                                          &seg_chunks);
     s.ntab = (int)tab.size();
     gi_status st;
     if ((st = dev_alloc(g, g->sched_allocs, &s.off, soff.size())) != GI_OK) return st;
@@ -303,7 +346,7 @@ static gi_status build_segments(gi_graph* g, int p, int strategy) {
     if ((st = upload(soff.data(), s.off, soff.size() * 4)) != GI_OK) return st;
     if ((st = upload(sidx.data(), s.idx, sidx.size() * 4)) != GI_OK) return st;
     if ((st = upload(sdst.data(), s.dst, sdst.size() * 4)) != GI_OK) return st;
-    if ((st = upload(tab.data(), s.table, tab.size() * sizeof(int2))) != GI_OK) return st;
+    if ((st = upload(tab.data(), s.table, tab.size() * sizeof(int4))) != GI_OK) return st;
   }
   gi_status st = dev_alloc(g, g->sched_allocs, &g->pr_acc, (size_t)n);
   if (st != GI_OK) return st;
@@ -318,17 +361,30 @@ static gi_status apply_schedule(gi_graph* g, const gi_schedule& s) {
   g->pr_acc = nullptr;
   g->pr_table = nullptr;
   g->sched = s;
-  g->pr_cap_e = s.pull_block_edges > 0 ? s.pull_block_edges : 2048;
+  if (s.pull_block_edges > 0) {
+    g->pr_cap_e = s.pull_block_edges;
+  } else {
+    // about 8 destination blocks per CU-slot of work: m / 8192 edges per
+    // block, as a power of two in [256, 2048]
+    int cap = 256;
+    while (cap < 2048 && (int64_t)cap * 2 * 8192 <= g->m) cap *= 2;
+    g->pr_cap_e = cap;
+  }
   g->pr_cap_v = std::min(g->pr_cap_e, 1024);
-  std::vector<int2> tab = make_row_blocks(g->h_in_off.data(), g->n, g->pr_cap_e, g->pr_cap_v);
+  std::vector<int32_t> chunks;
+  std::vector<int4> tab = make_pr_table(g->h_in_off.data(), g->n, g->pr_cap_e, g->pr_cap_v,
+                                        &chunks);
   g->pr_ntab = (int)tab.size();
   gi_status st = dev_alloc(g, g->sched_allocs, &g->pr_table, tab.size());
   if (st != GI_OK) return st;
-  if ((st = upload(tab.data(), g->pr_table, tab.size() * sizeof(int2))) != GI_OK) return st;
-  std::vector<int2> otab = make_row_blocks(g->h_out_off.data(), g->n, g->pr_cap_e, g->pr_cap_v);
-  g->out_ntab = (int)otab.size();
-  if ((st = dev_alloc(g, g->sched_allocs, &g->out_table, otab.size())) != GI_OK) return st;
-  if ((st = upload(otab.data(), g->out_table, otab.size() * sizeof(int2))) != GI_OK) return st;
+  if ((st = upload(tab.data(), g->pr_table, tab.size() * sizeof(int4))) != GI_OK) return st;
+  const size_t nl = std::max<size_t>(1, chunks.size());
+  if ((st = dev_alloc(g, g->sched_allocs, &g->lr_acc, nl)) != GI_OK) return st;
+  if ((st = dev_alloc(g, g->sched_allocs, &g->lr_cnt, nl)) != GI_OK) return st;
+  if ((st = dev_alloc(g, g->sched_allocs, &g->lr_chunks, nl)) != GI_OK) return st;
+  HIP_TRY(hipMemset(g->lr_acc, 0, sizeof(double) * nl));
+  HIP_TRY(hipMemset(g->lr_cnt, 0, sizeof(unsigned) * nl));
+  if ((st = upload(chunks.data(), g->lr_chunks, 4 * chunks.size())) != GI_OK) return st;
   if (s.num_segments > 1) return build_segments(g, s.num_segments, s.segment_strategy);
   return GI_OK;
 }
@@ -395,6 +451,7 @@ extern "C" gi_status gi_graph_destroy(gi_graph* g) {
   free_list(g->sched_allocs);
   free_list(g->allocs);
   if (g->h_ctl) (void)hipHostFree(g->h_ctl);
+  if (g->hflags) (void)hipHostFree(g->hflags);
   for (hipEvent_t e : g->ev)
     if (e) (void)hipEventDestroy(e);
   delete g;
@@ -537,27 +594,21 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
   G_ALLOC(g->lab, N);
   G_ALLOC(g->contrib[0], N);
   G_ALLOC(g->contrib[1], N);
-  G_ALLOC(g->part, kMaxParts);
-  G_ALLOC(g->blk_cnt, kMaxParts + 1);
-  G_ALLOC(g->blk_deg, kMaxParts + 1);
+  G_ALLOC(g->part, kParts);
+  G_ALLOC(g->blk, kMaxCount);
+  G_ALLOC(g->fmin, kMaxCount);
   G_ALLOC(g->ids, N);
   G_ALLOC(g->excl, N + 1);
   G_ALLOC(g->chunk_item, nchunk);
   G_ALLOC(g->ctl, 1);
   {
-    // launch shapes: compaction workgroups own >= 256 words each (<= kMaxParts
-    // workgroups); word-, vertex- and block-parallel grids are capped so that
-    // every workgroup owns one statistics slot
+    // count/write workgroups own >= 256 bitvector words each (at most
+    // kMaxCount workgroups); step kernels always run kParts workgroups
     Engine& e = g->eng;
     e.n = n;
-    e.cgrid = (int)std::max<size_t>(1, std::min<size_t>(kMaxParts / 2, (W + 255) / 256));
+    e.cgrid = (int)std::max<size_t>(1, std::min<size_t>(kMaxCount, (W + 255) / 256));
     e.tw = (int)((W + e.cgrid - 1) / e.cgrid);
-    e.xgrid = 2048;
-    e.vgrid = (int)std::max<size_t>(1, std::min<size_t>(kMaxParts, (N + 255) / 256));
-    e.wgrid = (int)std::max<size_t>(1, std::min<size_t>(kMaxParts, (W + 3) / 4));
-    e.rgrid = kMaxParts;
-    e.blk_cnt = g->blk_cnt;
-    e.blk_deg = g->blk_deg;
+    e.blk = g->blk;
     e.ids = g->ids;
     e.excl = g->excl;
     e.chunk_item = g->chunk_item;
@@ -573,6 +624,14 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
     return fail(GI_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
   }
   std::memset(g->h_ctl, 0, sizeof(Control));
+  if (hipHostMalloc((void**)&g->hflags, sizeof(HostFlags),
+                    hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&g->dflags, g->hflags, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    gi_graph_destroy(g);
+    return fail(GI_ERR_OUT_OF_MEMORY, "pinned host flags allocation failed");
+  }
+  std::memset(g->hflags, 0, sizeof(HostFlags));
   for (hipEvent_t& e : g->ev) {
     if (hipEventCreate(&e) != hipSuccess) {
       (void)hipGetLastError();
@@ -636,23 +695,14 @@ static DenseSet frontier_set(const gi_graph* g, int k) {
   return d;
 }
 
-// Copy the step log of the last frontier loop into g->stats.
+// Copy the control block and the step log of the last frontier loop (one
+// copy) into g->stats.
 static gi_status read_loop_stats(gi_graph* g, int alg, hipStream_t s) {
-  HIP_TRY(hipMemcpyAsync(g->h_ctl, g->ctl, offsetof(Control, dir_log), hipMemcpyDeviceToHost, s));
+  const int hsteps = ((const volatile HostFlags*)g->hflags)->steps;
+  const int steps = std::min(hsteps, kMaxLog);
+  const size_t bytes = offsetof(Control, log) + sizeof(StepLog) * (size_t)std::max(steps, 0);
+  HIP_TRY(hipMemcpyAsync(g->h_ctl, g->ctl, bytes, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  const int steps = g->h_ctl->steps;
-  const int k = std::min(steps, kMaxLog);
-  if (k > 0) {
-    HIP_TRY(hipMemcpyAsync(g->h_ctl->dir_log, g->ctl->dir_log, sizeof(int) * k,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(g->h_ctl->f_log, g->ctl->f_log, sizeof(int) * k,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(g->h_ctl->d_log, g->ctl->d_log, sizeof(long long) * k,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(g->h_ctl->w_log, g->ctl->w_log, sizeof(long long) * k,
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-  }
   const Control& c = *g->h_ctl;
   gi_run_stats& r = g->stats;
   r.algorithm = alg;
@@ -661,10 +711,10 @@ static gi_status read_loop_stats(gi_graph* g, int alg, hipStream_t s) {
   r.edges_examined = (int64_t)c.edges_examined;
   r.trace_len = std::min(c.steps, GI_MAX_TRACE);
   for (int i = 0; i < r.trace_len; ++i) {
-    r.step_direction[i] = (int8_t)c.dir_log[i];
-    r.step_frontier[i] = c.f_log[i];
-    r.step_degree_sum[i] = c.d_log[i];
-    r.step_edges[i] = c.w_log[i];
+    r.step_direction[i] = (int8_t)c.log[i].dir;
+    r.step_frontier[i] = c.log[i].frontier;
+    r.step_degree_sum[i] = c.log[i].degsum;
+    r.step_edges[i] = c.log[i].edges;
   }
   return GI_OK;
 }
@@ -678,9 +728,9 @@ static gi_status read_kernel_ms(gi_graph* g, int launches) {
   return GI_OK;
 }
 
-// Enqueue steps in batches until the device reports an empty frontier.
-// `step(k)` enqueues step k; it returns the number of kernels it launched
-// (negative on a launch error).
+// Enqueue steps in batches until the device reports completion through the
+// pinned host flags.  `step(k)` enqueues step k and returns the number of
+// kernels it launched (negative on a launch error).
 template <class StepFn>
 static gi_status run_frontier_loop(gi_graph* g, hipStream_t s, int batch, long long max_steps,
                                    StepFn step, const char* what) {
@@ -697,13 +747,21 @@ static gi_status run_frontier_loop(gi_graph* g, hipStream_t s, int batch, long l
       launches += nl;
     }
     HIP_TRY(hipEventRecord(g->ev[1], s));
-    HIP_TRY(hipMemcpyAsync(g->h_ctl, g->ctl, offsetof(Control, dir_log), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (g->h_ctl->error) return fail(GI_ERR_DEVICE, "%s: internal size check failed", what);
-    if (g->h_ctl->done) break;
+    HIP_TRY(hipEventSynchronize(g->ev[1]));
+    const volatile HostFlags* f = g->hflags;
+    if (f->error) return fail(GI_ERR_DEVICE, "%s: internal size check failed", what);
+    if (f->done) break;
     if (k > max_steps) return fail(GI_ERR_DEVICE, "%s did not terminate", what);
   }
   return read_kernel_ms(g, launches);
+}
+
+// Reset the control block and the pinned flags before a run.
+static gi_status start_run(gi_graph* g, unsigned long long delta, hipStream_t s) {
+  HIP_TRY(hipStreamSynchronize(s));
+  std::memset((void*)g->hflags, 0, sizeof(HostFlags));
+  LAUNCH_TRY(launch_ctl_init(g->ctl, g->dflags, delta, s));
+  return GI_OK;
 }
 
 static int batch_size(const gi_graph* g, int dflt) {
@@ -731,13 +789,14 @@ extern "C" gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, floa
     float* cin = g->contrib[k & 1];
     float* cout = g->contrib[(k + 1) & 1];
     if (g->sched.num_segments <= 1) {
-      PrRows r{g->pr_table, g->pr_ntab, g->in_off, g->in_idx, nullptr};
+      PrRows r{g->pr_table, g->pr_ntab, g->in_off, g->in_idx, nullptr, g->lr_acc, g->lr_cnt,
+               g->lr_chunks};
       LAUNCH_TRY(launch_pr_rows(r, g->pr_cap_e, g->pr_cap_v, bt, 0, cin, 0, pv, cout,
                                 last ? ranks : nullptr, nullptr, s));
       ++launches;
     } else {
       for (const SegDev& sg : g->segs) {
-        PrRows r{sg.table, sg.ntab, sg.off, sg.idx, sg.dst};
+        PrRows r{sg.table, sg.ntab, sg.off, sg.idx, sg.dst, nullptr, nullptr, nullptr};
         LAUNCH_TRY(launch_pr_rows(r, g->pr_cap_e, g->pr_cap_v, bt, 0, cin, 1, pv, nullptr,
                                   nullptr, g->pr_acc, s));
         ++launches;
@@ -780,6 +839,8 @@ extern "C" gi_status gi_bfs(gi_graph* g, int32_t src, int32_t* level, int32_t* p
   if (!g || !level) return fail(GI_ERR_INVALID_ARG, "NULL argument");
   if (src < 0 || src >= g->n) return fail(GI_ERR_INVALID_ARG, "source %d outside [0, %d)", src, g->n);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  gi_status st = start_run(g, 0, s);
+  if (st != GI_OK) return st;
   BfsArgs b;
   b.g = dev_graph(g);
   b.level = level;
@@ -791,22 +852,46 @@ extern "C" gi_status gi_bfs(gi_graph* g, int32_t src, int32_t* level, int32_t* p
   b.ctl = g->ctl;
   LAUNCH_TRY(launch_bfs_init(b, src, frontier_set(g, 0), frontier_set(g, 1), s));
   const DecideArgs d = decide_args(g, g->m);
-  gi_status st = run_frontier_loop(
+  st = run_frontier_loop(
       g, s, batch_size(g, 8), (long long)g->n + 2,
       [&](long long k) {
         BfsArgs bk = b;
         bk.cur = frontier_set(g, (int)(k & 1));
         bk.next = frontier_set(g, (int)((k + 1) & 1));
-        return enqueue_bfs_step(g->eng, d, bk, s) ? -1 : 7;
+        const FrontierArgs f = frontier_args(g->eng, bk.cur, bk.next, g->outdeg, nullptr, nullptr);
+        return enqueue_bfs_step(g->eng, f, d, bk, s) ? -1 : 4;
       },
       "BFS");
   if (st != GI_OK) return st;
   return read_loop_stats(g, ALG_BFS, s);
 }
 
+// Symmetric adjacency for CC, built on the device on first use.
+static gi_status ensure_sym(gi_graph* g, hipStream_t s) {
+  if (g->sym_idx) return GI_OK;
+  const size_t N = (size_t)g->n;
+  std::vector<int32_t> off(N + 1, 0);
+  for (size_t v = 0; v < N; ++v)
+    off[v + 1] = off[v] + g->h_outdeg[v] + (g->h_in_off[v + 1] - g->h_in_off[v]);
+  std::vector<int2> tab = make_row_blocks(off.data(), g->n, kCcCapE, kCcCapV);
+  gi_status st;
+  if ((st = dev_alloc(g, g->allocs, &g->sym_off, N + 1)) != GI_OK) return st;
+  if ((st = dev_alloc(g, g->allocs, &g->sym_idx, (size_t)off[N])) != GI_OK) return st;
+  if ((st = dev_alloc(g, g->allocs, &g->sym_table, tab.size())) != GI_OK) return st;
+  if ((st = upload(off.data(), g->sym_off, 4 * (N + 1))) != GI_OK) return st;
+  if ((st = upload(tab.data(), g->sym_table, tab.size() * sizeof(int2))) != GI_OK) return st;
+  g->sym_ntab = (int)tab.size();
+  LAUNCH_TRY(launch_build_sym(dev_graph(g), g->sym_off, g->sym_idx, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return GI_OK;
+}
+
 extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
   if (!g || !label) return fail(GI_ERR_INVALID_ARG, "NULL argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  gi_status st = ensure_sym(g, s);
+  if (st != GI_OK) return st;
+  if ((st = start_run(g, 0, s)) != GI_OK) return st;
   int32_t* labs[2] = {label, g->lab};
   CcArgs c;
   c.g = dev_graph(g);
@@ -814,13 +899,14 @@ extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
   c.nxt = labs[1];
   c.fr = frontier_set(g, 0);
   c.next = frontier_set(g, 1);
+  c.sym_off = g->sym_off;
+  c.sym_idx = g->sym_idx;
+  c.rows = RowBlocks{g->sym_table, g->sym_ntab, g->sym_off, g->sym_idx};
   c.part = g->part;
   c.ctl = g->ctl;
   LAUNCH_TRY(launch_cc_init(c, frontier_set(g, 0), frontier_set(g, 1), labs[1], s));
   const DecideArgs d = decide_args(g, 2 * g->m);
-  const RowBlocks in_rows{g->pr_table, g->pr_ntab, g->in_off, g->in_idx};
-  const RowBlocks out_rows{g->out_table, g->out_ntab, g->out_off, g->out_idx};
-  gi_status st = run_frontier_loop(
+  st = run_frontier_loop(
       g, s, batch_size(g, 8), (long long)g->n + 2,
       [&](long long k) {
         CcArgs ck = c;
@@ -828,8 +914,8 @@ extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
         ck.nxt = labs[(k + 1) & 1];
         ck.fr = frontier_set(g, (int)(k & 1));
         ck.next = frontier_set(g, (int)((k + 1) & 1));
-        return enqueue_cc_step(g->eng, d, ck, in_rows, out_rows, g->pr_cap_e, g->pr_cap_v, s) ? -1
-                                                                                              : 8;
+        const FrontierArgs f = frontier_args(g->eng, ck.fr, ck.next, g->udeg, ck.cur, ck.nxt);
+        return enqueue_cc_step(g->eng, f, d, ck, s) ? -1 : 4;
       },
       "CC");
   if (st != GI_OK) return st;
@@ -848,34 +934,33 @@ extern "C" gi_status gi_sssp(gi_graph* g, int32_t src, uint32_t* dist, void* str
   if (!g->weighted) return fail(GI_ERR_INVALID_ARG, "graph has no edge weights");
   if (src < 0 || src >= g->n) return fail(GI_ERR_INVALID_ARG, "source %d outside [0, %d)", src, g->n);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const unsigned long long delta = g->sched.sssp_delta > 0 ? g->sched.sssp_delta : 512u;
+  gi_status st = start_run(g, delta, s);
+  if (st != GI_OK) return st;
   SsspArgs a;
   a.g = dev_graph(g);
   a.dist = dist;
   a.cur = DenseSet{g->fbv[0], nullptr};
   a.next = DenseSet{g->fbv[1], nullptr};
   a.far = DenseSet{g->far, nullptr};
-  a.delta = g->sched.sssp_delta > 0 ? g->sched.sssp_delta : 512u;
+  a.delta = delta;
+  a.fmin = g->fmin;
   a.part = g->part;
   a.ctl = g->ctl;
-  LAUNCH_TRY(launch_sssp_init(a, src, a.cur, a.next, s));
-  gi_status st = run_frontier_loop(
+  LAUNCH_TRY(launch_sssp_init(a, src, s));
+  st = run_frontier_loop(
       g, s, batch_size(g, 64), 64LL * g->n + 1024,
       [&](long long k) {
         SsspArgs ak = a;
         ak.cur = DenseSet{g->fbv[k & 1], nullptr};
         ak.next = DenseSet{g->fbv[(k + 1) & 1], nullptr};
-        return enqueue_sssp_step(g->eng, ak, s) ? -1 : 8;
+        const FrontierArgs f = frontier_args(g->eng, ak.cur, ak.next, g->outdeg, nullptr, nullptr);
+        return enqueue_sssp_step(g->eng, f, ak, s) ? -1 : 5;
       },
       "SSSP");
   if (st != GI_OK) return st;
-  HIP_TRY(hipMemcpyAsync(g->h_ctl, g->ctl, offsetof(Control, dir_log), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (g->h_ctl->overflow) return fail(GI_ERR_OVERFLOW, "a distance reached UINT32_MAX");
-  const float kms = g->stats.kernel_ms;
-  const int nl = g->stats.launches;
+  if (((const volatile HostFlags*)g->hflags)->overflow) return fail(GI_ERR_OVERFLOW, "a distance reached UINT32_MAX");
   st = read_loop_stats(g, ALG_SSSP, s);
-  g->stats.kernel_ms = kms;
-  g->stats.launches = nl;
   g->stats.dense_steps = 0;
   return st;
 }

@@ -22,7 +22,9 @@
 namespace gi {
 
 constexpr int kWave = 64;
-constexpr int kMaxParts = 4096;  // per-workgroup statistic slots
+constexpr int kParts = 2048;     // step kernels run exactly this many workgroups,
+                                 // one statistics slot each
+constexpr int kMaxCount = 2048;  // at most this many count/write workgroups
 constexpr int kMaxLog = 4096;    // per-step trace entries
 
 // ---------------------------------------------------------------------------
@@ -61,6 +63,23 @@ enum : int {
   MODE_SSSP_SPLIT = 11,
 };
 
+// One entry of the per-step trace.
+struct StepLog {
+  int dir;          // GI_DIR_* run by the step
+  int frontier;     // |F| entering the step
+  long long degsum; // sum of degrees of F
+  long long edges;  // edges the step examined
+};
+
+// Flags the host polls between batches; pinned host memory written by the
+// decide kernels, so no copy is needed to see them.
+struct HostFlags {
+  int done;
+  int error;
+  int overflow;
+  int steps;
+};
+
 // Control block of one algorithm run (device memory).
 struct Control {
   int mode;           // mode of the step being executed
@@ -81,12 +100,14 @@ struct Control {
   int buckets;
   int error;          // an internal size invariant failed (the run is abandoned)
   int pad;
-  // trace
-  int dir_log[kMaxLog];
-  int f_log[kMaxLog];
-  long long d_log[kMaxLog];
-  long long w_log[kMaxLog];
+  HostFlags* host;    // device address of the pinned host flags
+  StepLog log[kMaxLog];
 };
+
+// Publish a flag to the pinned host copy.
+__device__ __forceinline__ void host_flag(int* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 // ---------------------------------------------------------------------------
 // Wave / workgroup helpers (wave64).

@@ -16,17 +16,17 @@ struct RowBlocks {
   const int32_t* idx;
 };
 
+// CC pull: destination blocks of the symmetric adjacency hold at most this
+// many edges and rows.
+constexpr int kCcCapE = 2048;
+constexpr int kCcCapV = 1024;
+
 // Scratch and launch shapes shared by the frontier loops of one graph.
 struct Engine {
   int n;
-  int tw;           // compaction: words per workgroup
-  int cgrid;        // compaction / word-parallel grid
-  int xgrid;        // edge-balanced expansion grid
-  int vgrid;        // vertex-parallel grid (DensePush)
-  int wgrid;        // wave-per-word grid (DensePull)
-  int rgrid;        // destination-block grid cap
-  long long* blk_cnt;
-  long long* blk_deg;
+  int tw;           // count/write: words per workgroup
+  int cgrid;        // count/write workgroups (<= kMaxCount)
+  Blk* blk;
   int32_t* ids;
   long long* excl;
   int32_t* chunk_item;
@@ -34,12 +34,18 @@ struct Engine {
   Control* ctl;
 };
 
+// PageRank destination blocks.  table[t] = (first row, end row, -1, 0) for
+// a block of whole rows, or (row, row + 1, slot, chunk) for chunk `chunk` of
+// a row longer than cap_e; `slot` indexes the long-row arrays.
 struct PrRows {
-  const int2* table;    // (first row, end row) per destination block
+  const int4* table;
   int ntab;
   const int32_t* off;   // row offsets into idx
   const int32_t* idx;   // source ids
   const int32_t* dst;   // row -> destination, or null when row == destination
+  double* lr_acc;       // per long row: partial-sum accumulator (zero between uses)
+  unsigned* lr_cnt;     // per long row: chunks finished (zero between uses)
+  const int32_t* lr_chunks;  // per long row: number of chunks
 };
 
 struct PrVertex {
@@ -53,7 +59,7 @@ struct DecideArgs {
   Control* ctl;
   int direction;   // GI_DIR_*
   int divisor;
-  int forced_dir;  // >= 0: direction of every step (per-schedule timing)
+  int forced_dir;  // >= 0: direction of every step
   long long edges; // m for BFS, 2m for CC (edges counted in both directions)
 };
 
@@ -70,10 +76,13 @@ struct BfsArgs {
 
 struct CcArgs {
   DevGraph g;
-  int32_t* cur;        // labels L_k
-  int32_t* nxt;        // labels L_{k+1}
-  DenseSet fr;         // vertices whose label changed in the previous round
-  DenseSet next;       // vertices whose label changes in this round
+  int32_t* cur;            // labels L_k
+  int32_t* nxt;            // labels L_{k+1}
+  DenseSet fr;             // vertices whose label changed in the previous round
+  DenseSet next;           // vertices whose label changes in this round
+  const int32_t* sym_off;  // symmetric adjacency (out-row then in-row)
+  const int32_t* sym_idx;
+  RowBlocks rows;          // destination blocks of the symmetric adjacency
   Part* part;
   Control* ctl;
 };
@@ -85,19 +94,25 @@ struct SsspArgs {
   DenseSet next;       // near set of the next phase
   DenseSet far;        // far set
   unsigned long long delta;
+  unsigned long long* fmin;  // per count-workgroup smallest far distance
   Part* part;
   Control* ctl;
 };
 
 // ---- launchers (return 0 on success) ----
 int expand_chunk_size();
+FrontierArgs frontier_args(const Engine& e, DenseSet cur, DenseSet next, const int32_t* deg,
+                           const int32_t* fix_src, int32_t* fix_dst);
+int launch_ctl_init(Control* c, HostFlags* host, unsigned long long delta, hipStream_t s);
 int launch_bfs_init(const BfsArgs& b, int src, DenseSet f0, DenseSet f1, hipStream_t s);
-int enqueue_bfs_step(const Engine& e, const DecideArgs& d, const BfsArgs& b, hipStream_t s);
+int enqueue_bfs_step(const Engine& e, const FrontierArgs& f, const DecideArgs& d,
+                     const BfsArgs& b, hipStream_t s);
 int launch_cc_init(const CcArgs& c, DenseSet f0, DenseSet f1, int32_t* lab_other, hipStream_t s);
-int enqueue_cc_step(const Engine& e, const DecideArgs& d, const CcArgs& c, const RowBlocks& in_rows,
-                    const RowBlocks& out_rows, int cap_e, int cap_v, hipStream_t s);
-int launch_sssp_init(const SsspArgs& sa, int src, DenseSet f0, DenseSet f1, hipStream_t s);
-int enqueue_sssp_step(const Engine& e, const SsspArgs& sa, hipStream_t s);
+int launch_build_sym(const DevGraph& g, const int32_t* sym_off, int32_t* sym_idx, hipStream_t s);
+int enqueue_cc_step(const Engine& e, const FrontierArgs& f, const DecideArgs& d, const CcArgs& c,
+                    hipStream_t s);
+int launch_sssp_init(const SsspArgs& sa, int src, hipStream_t s);
+int enqueue_sssp_step(const Engine& e, const FrontierArgs& f, const SsspArgs& sa, hipStream_t s);
 
 int launch_pr_init(int n, const int32_t* outdeg, float* c0, float* rank, bool zero_iters,
                    hipStream_t s);

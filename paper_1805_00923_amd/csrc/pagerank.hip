@@ -7,10 +7,12 @@
 //
 // Destination blocks: the in-edge range of a run of consecutive destinations
 // (at most cap_e edges) is staged in LDS with coalesced index loads and
-// contrib gathers, then reduced per destination by a power-of-two group of
-// threads.  A destination with more than cap_e in-edges is a block of its
-// own and is summed by the whole workgroup.  Long rows come first in the
-// table so that they start early.
+// contrib gathers (four of each in flight per thread), then reduced per
+// destination by a power-of-two group of threads.  A destination with more
+// than cap_e in-edges is cut into chunks of cap_e edges, each summed by one
+// workgroup; the chunks' partial sums meet in an FP64 accumulator and the
+// last chunk to finish applies the vertex update.  Chunks of long rows come
+// first in the table so that they start early.
 //
 // Segmented (cache-partitioned) form, section 2 and the SSG code of section
 // 6: sources are split into segments V_0..V_{p-1}; segment i holds the
@@ -37,15 +39,31 @@ __device__ __forceinline__ double block_sum(double v) {
   return t;  // valid in thread 0
 }
 
+// Sum over the edge range [eb, ee) of cin[idx[e]] by the whole workgroup,
+// four independent loads in flight per thread; result valid in thread 0.
+template <int BT>
+__device__ __forceinline__ double range_sum(const int32_t* __restrict__ idx,
+                                            const float* __restrict__ cin, int eb, int ee) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int e = eb + (int)threadIdx.x;
+  for (; e + 3 * BT < ee; e += 4 * BT) {
+    const int a0 = idx[e], a1 = idx[e + BT], a2 = idx[e + 2 * BT], a3 = idx[e + 3 * BT];
+    s0 += (double)cin[a0];
+    s1 += (double)cin[a1];
+    s2 += (double)cin[a2];
+    s3 += (double)cin[a3];
+  }
+  for (; e < ee; e += BT) s0 += (double)cin[idx[e]];
+  return block_sum<BT>((s0 + s1) + (s2 + s3));
+}
+
 // mode 0: final vertex update from the full sum; mode 1: acc[dst] += sum.
 template <int BT>
 __device__ void pr_rows_block(const PrRows& r, int t, int cap_e, const float* __restrict__ cin,
                               int mode, const PrVertex& pv, float* __restrict__ cout,
                               float* __restrict__ rank, double* __restrict__ acc, float* lds_val,
                               int* lds_off) {
-  const int2 rb = r.table[t];
-  const int kb = rb.x, ke = rb.y, nr = ke - kb;
-  const int e0 = r.off[kb], e1 = r.off[ke], ne = e1 - e0;
+  const int4 en = r.table[t];
   const int tid = threadIdx.x;
   auto finish = [&](int row, double s) {
     const int v = r.dst ? r.dst[row] : row;
@@ -61,14 +79,34 @@ __device__ void pr_rows_block(const PrRows& r, int t, int cap_e, const float* __
       }
     }
   };
-  if (ne > cap_e) {  // one long row
-    double s = 0.0;
-    for (int e = e0 + tid; e < e1; e += BT) s += (double)cin[r.idx[e]];
-    s = block_sum<BT>(s);
-    if (tid == 0) finish(kb, s);
+  if (en.z >= 0) {
+    // one chunk of a row longer than cap_e: partial sums meet in an FP64
+    // accumulator; the chunk that arrives last applies the vertex update
+    const int row = en.x;
+    const int rb = r.off[row], re = r.off[row + 1];
+    const int eb = rb + en.w * cap_e, ee = min(re, eb + cap_e);
+    const double s = range_sum<BT>(r.idx, cin, eb, ee);
+    if (tid == 0) {
+      if (mode == 1) {
+        atomicAdd(&acc[r.dst ? r.dst[row] : row], s);
+      } else {
+        atomicAdd(&r.lr_acc[en.z], s);
+        __threadfence();
+        const unsigned done = atomicAdd(&r.lr_cnt[en.z], 1u);
+        if (done == (unsigned)r.lr_chunks[en.z] - 1u) {
+          __threadfence();
+          const double tot = atomicAdd(&r.lr_acc[en.z], 0.0);
+          __hip_atomic_store(&r.lr_acc[en.z], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&r.lr_cnt[en.z], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          finish(row, tot);
+        }
+      }
+    }
     return;
   }
-  for (int j = tid; j < ne; j += BT) lds_val[j] = cin[r.idx[e0 + j]];
+  const int kb = en.x, ke = en.y, nr = ke - kb;
+  const int e0 = r.off[kb], e1 = r.off[ke], ne = e1 - e0;
+  gather_block<BT, float>(r.idx, e0, ne, lds_val, [cin](int u) { return cin[u]; });
   for (int k = tid; k <= nr; k += BT) lds_off[k] = r.off[kb + k] - e0;
   __syncthreads();
   int tpv = 1;

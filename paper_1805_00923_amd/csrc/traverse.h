@@ -7,27 +7,35 @@
 // and needs no atomics.
 //
 // Frontiers live as dense sets (bitvector or bool map, the two options of
-// configApplyDenseVertexSet).  A SparsePush step first compacts the dense
-// set into a sparse array with an exclusive scan of the members' degrees
-// (three small kernels, no atomics), and then spreads the frontier's edges
-// evenly over all workgroups: chunk c of CH consecutive edge slots starts in
-// the frontier item recorded by the compaction (a merge-path split of the
-// degree prefix sum), so a handful of hub vertices no longer lands on one
-// workgroup.
+// configApplyDenseVertexSet).  Each step runs four launches:
+//   count  - every workgroup counts the frontier members of its word range
+//            (|F|, sum of degrees, and the members that own edges), clears
+//            the next frontier and, for CC, copies the current labels of F
+//            into the next-label buffer;
+//   decide - one workgroup reduces those counts, picks the direction, and
+//            for SparsePush turns the counts into exclusive offsets;
+//   write  - SparsePush only: the members with edges are written as a sparse
+//            array with an exclusive prefix sum of their degrees, and chunk c
+//            of CH consecutive edge slots records the item it starts in (a
+//            merge-path split of the prefix sum);
+//   step   - the edgeset.apply itself in the chosen direction.  SparsePush
+//            spreads the frontier's edges evenly over all workgroups, so a
+//            few hub vertices do not serialize on one workgroup.
 #pragma once
 
 #include "common.h"
 
 namespace gi {
 
-// Dense vertexset: bitvector (bit v%64 of word v/64) or bool map (byte v).
+// Dense vertexset: bitvector (bit v%64 of word v/64) or bool map (byte v,
+// padded to whole 64-byte words).
 struct DenseSet {
   uint64_t* bv;
   uint8_t* bm;
   __device__ __forceinline__ bool test(int u) const {
     return bm ? bm[u] != 0 : ((bv[u >> 6] >> (u & 63)) & 1ull) != 0;
   }
-  // 64-member mask of word w (members beyond n must be clear)
+  // 64-member mask of word w (members beyond n are clear)
   __device__ __forceinline__ uint64_t word(int w) const {
     if (!bm) return bv[w];
     const uint64_t* p = reinterpret_cast<const uint64_t*>(bm + ((size_t)w << 6));
@@ -40,12 +48,19 @@ struct DenseSet {
     }
     return m;
   }
+  __device__ __forceinline__ void clear_word(int w) const {
+    if (bv) bv[w] = 0ull;
+    if (bm) {
+      uint64_t* p = reinterpret_cast<uint64_t*>(bm + ((size_t)w << 6));
+#pragma unroll
+      for (int k = 0; k < 8; ++k) p[k] = 0ull;
+    }
+  }
   // set member v; true when it was not a member before
   __device__ __forceinline__ bool insert(int v) const {
     if (bm) {
       const unsigned sh = 8u * (unsigned)(v & 3);
-      const unsigned old =
-          atomicOr(reinterpret_cast<unsigned*>(bm + (v & ~3)), 1u << sh);
+      const unsigned old = atomicOr(reinterpret_cast<unsigned*>(bm + (v & ~3)), 1u << sh);
       return ((old >> sh) & 0xffu) == 0;
     }
     const unsigned long long bit = 1ull << (v & 63);
@@ -53,110 +68,124 @@ struct DenseSet {
   }
 };
 
-// Wave-aggregated append of the lanes with p set: one atomic per wave.
-// Must be called by all lanes of the wave together.
-__device__ __forceinline__ void wave_append(bool p, int v, int32_t* out,
-                                            unsigned long long* counter) {
-  const unsigned long long mk = __ballot(p);
-  if (mk == 0ull) return;
-  const int leader = __ffsll((long long)mk) - 1;
-  unsigned long long base = 0;
-  if (__lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mk));
-  base = __shfl(base, leader, kWave);
-  if (p) out[base + __popcll(mk & lanemask_lt())] = v;
-}
-
-// ------------------------------------------------------------ compaction --
-//
-// Workgroup b owns the words [b*tw, (b+1)*tw) of the dense set; thread t
-// visits words b*tw + it*BT + t for it = 0, 1, ... so that the (it, t) order
-// is the word order.  Members with degree 0 are left out of the sparse array
-// (they own no edge slots).
-
-struct CompactArgs {
-  DenseSet in;
-  int n;
-  int tw;                      // words per workgroup
-  const int32_t* deg;          // degree of each vertex
-  long long* blk_cnt;          // per-workgroup item counts (pass 1)
-  long long* blk_deg;          // per-workgroup degree sums (pass 1)
-  int32_t* ids;                // sparse items (pass 3)
-  long long* excl;             // exclusive degree prefix per item (pass 3)
-  int32_t* chunk_item;         // first item of each chunk of `chunk` slots
-  int chunk;
-  long long chunk_cap;         // entries allocated for chunk_item
-  DenseSet clear;              // dense set to clear (bitvector words), or none
-  const int32_t* fix_src;      // optional: fix_dst[v] = fix_src[v] for members
-  int32_t* fix_dst;
-  Control* ctl;
-  int active_mode;             // pass runs only when ctl->mode equals this
-  int active_mode2;            // ... or this
+// Per-workgroup counts of the count pass.
+struct Blk {
+  long long items;    // members with degree > 0 (sparse items)
+  long long slots;    // their degree sum (edge slots)
+  long long members;  // all members (|F|)
+  long long degsum;   // degree sum of all members
 };
 
-__device__ __forceinline__ bool mode_on(const Control* ctl, int m1, int m2) {
-  const int m = ctl->mode;
-  return m == m1 || m == m2;
-}
+struct FrontierArgs {
+  DenseSet cur;                // frontier of the step
+  DenseSet next;               // frontier the step produces (cleared by count)
+  int n;
+  int tw;                      // words per count/write workgroup
+  int cgrid;                   // count/write workgroups
+  const int32_t* deg;          // degree of each vertex (edge slots it owns)
+  const int32_t* fix_src;      // CC: fix_dst[v] = fix_src[v] for members of cur
+  int32_t* fix_dst;
+  Blk* blk;                    // [cgrid]
+  int32_t* ids;                // sparse items
+  long long* excl;             // exclusive degree prefix per item
+  int32_t* chunk_item;         // first item of each chunk of CH slots
+  long long chunk_cap;         // entries allocated for chunk_item
+  Control* ctl;
+};
 
 template <int BT>
-__device__ __forceinline__ void word_stats(const CompactArgs& a, int w, long long& c,
-                                           long long& d) {
-  uint64_t x = a.in.word(w);
-  while (x) {
-    const int b = __ffsll((long long)x) - 1;
-    x &= x - 1;
-    const int v = (w << 6) + b;
-    const int dv = a.deg[v];
-    if (dv > 0) {
-      c += 1;
-      d += dv;
-    }
-  }
-}
-
-template <int BT>
-__global__ __launch_bounds__(BT) void k_compact_count(CompactArgs a) {
-  if (!mode_on(a.ctl, a.active_mode, a.active_mode2)) return;
+__global__ __launch_bounds__(BT) void k_count(FrontierArgs a) {
+  if (a.ctl->done) return;
   const int W = (a.n + 63) >> 6;
   const int w0 = blockIdx.x * a.tw, w1 = min(W, w0 + a.tw);
-  long long c = 0, d = 0;
-  for (int w = w0 + threadIdx.x; w < w1; w += BT) {
-    if (a.clear.bv) a.clear.bv[w] = 0ull;
-    if (a.clear.bm) {
-      uint64_t* p = reinterpret_cast<uint64_t*>(a.clear.bm + ((size_t)w << 6));
-#pragma unroll
-      for (int k = 0; k < 8; ++k) p[k] = 0ull;
-    }
-    if (a.fix_dst) {  // CC push: next labels start equal to the current ones on F
-      uint64_t x = a.in.word(w);
-      while (x) {
-        const int v = (w << 6) + __ffsll((long long)x) - 1;
-        x &= x - 1;
-        a.fix_dst[v] = a.fix_src[v];
+  long long items = 0, slots = 0, members = 0, degsum = 0;
+  for (int w = w0 + (int)threadIdx.x; w < w1; w += BT) {
+    a.next.clear_word(w);
+    uint64_t x = a.cur.word(w);
+    while (x) {
+      const int v = (w << 6) + __ffsll((long long)x) - 1;
+      x &= x - 1;
+      if (a.fix_dst) a.fix_dst[v] = a.fix_src[v];
+      const int d = a.deg[v];
+      ++members;
+      degsum += d;
+      if (d > 0) {
+        ++items;
+        slots += d;
       }
     }
-    if (a.blk_cnt) word_stats<BT>(a, w, c, d);
   }
-  if (!a.blk_cnt) return;
-  Part p{c, d, 0, 0};
-  p = block_sum4<BT>(p);
-  if (threadIdx.x == 0) {
-    a.blk_cnt[blockIdx.x] = p.a;
-    a.blk_deg[blockIdx.x] = p.b;
-  }
+  Part p = block_sum4<BT>(Part{items, slots, members, degsum});
+  if (threadIdx.x == 0) a.blk[blockIdx.x] = Blk{p.a, p.b, p.c, p.d};
 }
 
-// Exclusive scan of the per-workgroup counts by one workgroup of 1024.
-static __global__ __launch_bounds__(1024) void k_compact_scan(CompactArgs a, int nblk) {
-  if (!mode_on(a.ctl, a.active_mode, a.active_mode2)) return;
-  __shared__ long long sc[1024], sd[1024];
+// Sum of the count pass (one workgroup of 1024 threads).
+__device__ __forceinline__ Blk reduce_blk(const FrontierArgs& a) {
+  __shared__ long long s[4][1024];
   const int t = threadIdx.x;
-  const int per = (nblk + 1023) / 1024;
-  const int b = t * per, e = min(nblk, b + per);
+  long long x0 = 0, x1 = 0, x2 = 0, x3 = 0;
+  for (int i = t; i < a.cgrid; i += 1024) {
+    const Blk b = a.blk[i];
+    x0 += b.items;
+    x1 += b.slots;
+    x2 += b.members;
+    x3 += b.degsum;
+  }
+  s[0][t] = x0;
+  s[1][t] = x1;
+  s[2][t] = x2;
+  s[3][t] = x3;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (t < o) {
+      s[0][t] += s[0][t + o];
+      s[1][t] += s[1][t + o];
+      s[2][t] += s[2][t + o];
+      s[3][t] += s[3][t + o];
+    }
+    __syncthreads();
+  }
+  const Blk tot{s[0][0], s[1][0], s[2][0], s[3][0]};
+  __syncthreads();
+  return tot;
+}
+
+// Sum of one field over the kParts step-kernel slots (one workgroup of 1024).
+__device__ __forceinline__ long long reduce_parts(const Part* part, int field) {
+  __shared__ long long s[1024];
+  const int t = threadIdx.x;
+  long long x = 0;
+  for (int i = t; i < kParts; i += 1024) {
+    const Part p = part[i];
+    x += field == 0 ? p.a : field == 1 ? p.b : field == 2 ? p.c : p.d;
+  }
+  s[t] = x;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (t < o) s[t] += s[t + o];
+    __syncthreads();
+  }
+  const long long r = s[0];
+  __syncthreads();
+  return r;
+}
+
+// Turn the per-workgroup item and slot counts into exclusive offsets and
+// publish the expansion shape (one workgroup of 1024, all threads call it).
+// Returns false when the sizes break an invariant; the caller then abandons
+// the run instead of writing past the arrays.
+template <int CH>
+__device__ bool scan_blk(const FrontierArgs& a, const Blk& tot) {
+  __shared__ long long sc[1024], sd[1024];
+  const long long nch = (tot.slots + CH - 1) / CH;
+  if (tot.items < 0 || tot.items > a.n || nch + 1 > a.chunk_cap) return false;
+  const int t = threadIdx.x;
+  const int per = (a.cgrid + 1023) / 1024;
+  const int b = t * per, e = min(a.cgrid, b + per);
   long long c = 0, d = 0;
   for (int i = b; i < e; ++i) {
-    c += a.blk_cnt[i];
-    d += a.blk_deg[i];
+    c += a.blk[i].items;
+    d += a.blk[i].slots;
   }
   sc[t] = c;
   sd[t] = d;
@@ -170,65 +199,65 @@ static __global__ __launch_bounds__(1024) void k_compact_scan(CompactArgs a, int
   }
   long long rc = sc[t] - c, rd = sd[t] - d;
   for (int i = b; i < e; ++i) {
-    const long long ci = a.blk_cnt[i], di = a.blk_deg[i];
-    a.blk_cnt[i] = rc;
-    a.blk_deg[i] = rd;
+    const long long ci = a.blk[i].items, di = a.blk[i].slots;
+    a.blk[i].items = rc;
+    a.blk[i].slots = rd;
     rc += ci;
     rd += di;
   }
-  if (t == 1023) {
-    const long long items = sc[1023], slots = sd[1023];
-    const long long nch = (slots + a.chunk - 1) / a.chunk;
-    if (items < 0 || items > a.n || nch + 1 > a.chunk_cap) {
-      // cannot happen for a consistent dense set; refuse rather than write
-      a.ctl->error = 1;
-      a.ctl->done = 1;
-      a.ctl->mode = MODE_NONE;
-      a.ctl->sa_count = 0;
-      a.ctl->sa_slots = 0;
-      a.ctl->nchunks = 0;
-      return;
-    }
-    a.ctl->sa_count = items;
-    a.ctl->sa_slots = slots;
+  if (t == 0) {
+    a.ctl->sa_count = tot.items;
+    a.ctl->sa_slots = tot.slots;
     a.ctl->nchunks = nch;
-    a.chunk_item[nch] = (int)items;  // sentinel
+    a.chunk_item[nch] = (int)tot.items;  // sentinel
   }
+  return true;
 }
 
-template <int BT>
-__global__ __launch_bounds__(BT) void k_compact_write(CompactArgs a) {
-  if (!mode_on(a.ctl, a.active_mode, a.active_mode2) || a.ctl->error) return;
+// Sparse array of the members with edges (after scan_blk turned the counts
+// into offsets).  Word order within a workgroup follows (iteration, thread).
+template <int BT, int CH>
+__device__ void write_body(const FrontierArgs& a) {
   const int W = (a.n + 63) >> 6;
   const int w0 = blockIdx.x * a.tw, w1 = min(W, w0 + a.tw);
-  long long run_c = a.blk_cnt[blockIdx.x], run_d = a.blk_deg[blockIdx.x];
+  long long run_c = a.blk[blockIdx.x].items, run_d = a.blk[blockIdx.x].slots;
   for (int base = w0; base < w1; base += BT) {
-    const int w = base + threadIdx.x;
+    const int w = base + (int)threadIdx.x;
+    uint64_t x = w < w1 ? a.cur.word(w) : 0ull;
     long long c = 0, d = 0;
-    if (w < w1) word_stats<BT>(a, w, c, d);
+    for (uint64_t y = x; y;) {
+      const int v = (w << 6) + __ffsll((long long)y) - 1;
+      y &= y - 1;
+      const int dv = a.deg[v];
+      if (dv > 0) {
+        ++c;
+        d += dv;
+      }
+    }
     long long tc, td;
     long long pc = block_excl_scan<BT>(c, &tc) + run_c;
     long long pd = block_excl_scan<BT>(d, &td) + run_d;
-    if (w < w1) {
-      uint64_t x = a.in.word(w);
-      while (x) {
-        const int b = __ffsll((long long)x) - 1;
-        x &= x - 1;
-        const int v = (w << 6) + b;
-        const int dv = a.deg[v];
-        if (dv <= 0) continue;
-        a.ids[pc] = v;
-        a.excl[pc] = pd;
-        // chunks whose first slot falls in [pd, pd + dv) start at this item
-        long long c0 = (pd + a.chunk - 1) / a.chunk;
-        for (long long k = c0; k * a.chunk < pd + dv; ++k) a.chunk_item[k] = (int)pc;
-        ++pc;
-        pd += dv;
-      }
+    while (x) {
+      const int v = (w << 6) + __ffsll((long long)x) - 1;
+      x &= x - 1;
+      const int dv = a.deg[v];
+      if (dv <= 0) continue;
+      a.ids[pc] = v;
+      a.excl[pc] = pd;
+      // chunks whose first slot falls in [pd, pd + dv) start at this item
+      for (long long k = (pd + CH - 1) / CH; k * CH < pd + dv; ++k) a.chunk_item[k] = (int)pc;
+      ++pc;
+      pd += dv;
     }
     run_c += tc;
     run_d += td;
   }
+}
+
+template <int BT, int CH>
+__global__ __launch_bounds__(BT) void k_write(FrontierArgs a, int active_mode) {
+  if (a.ctl->mode != active_mode) return;
+  write_body<BT, CH>(a);
 }
 
 // ------------------------------------------------ edge-balanced expansion --
@@ -237,62 +266,49 @@ __global__ __launch_bounds__(BT) void k_compact_write(CompactArgs a) {
 // are [chunk_item[c], chunk_item[c+1]] (each item owns >= 1 slot, so at most
 // CH+1 items).  The items' (vertex, first slot, row start) are staged in LDS,
 // then each thread binary-searches its slots.  vis(u, e, valid) is called by
-// full waves.
+// whole workgroups; `valid` is false for padding lanes.
 
 struct ExpandArgs {
   const int32_t* ids;
   const long long* excl;
   const int32_t* chunk_item;
   const int32_t* off;     // row offsets of the adjacency being expanded
-  const int32_t* off2;    // CC: second adjacency (slots beyond outdeg)
-  const int32_t* deg1;    // CC: degree in the first adjacency
   Control* ctl;
-  int active_mode;
 };
 
+// LDS the expansion needs (ints); a step kernel may reuse it for other modes.
+template <int CH>
+constexpr int expand_lds_ints() { return 3 * (CH + 1); }
+
 template <int BT, int CH, class Visit>
-__device__ void expand_chunks(const ExpandArgs& a, Visit& vis) {
-  __shared__ int s_u[CH + 1];
-  __shared__ int s_start[CH + 1];  // first slot of the item, relative to the chunk
-  __shared__ int s_row[CH + 1];
-  __shared__ int s_n;
+__device__ void expand_chunks(const ExpandArgs& a, Visit& vis, int* lds) {
+  int* s_u = lds;
+  int* s_start = lds + (CH + 1);  // first slot of the item, relative to the chunk
+  int* s_row = lds + 2 * (CH + 1);
   const long long nch = a.ctl->nchunks;
   const long long slots = a.ctl->sa_slots;
+  const int last = (int)a.ctl->sa_count - 1;
   for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
     const long long s0 = c * CH;
     const int s_end = (int)min((long long)CH, slots - s0);
     const int i0 = a.chunk_item[c];
-    const int i1 = min(a.chunk_item[c + 1], (int)a.ctl->sa_count - 1);
-    const int ni = i1 - i0 + 1;
+    const int ni = min(a.chunk_item[c + 1], last) - i0 + 1;
     for (int k = threadIdx.x; k < ni; k += BT) {
       const int u = a.ids[i0 + k];
       s_u[k] = u;
       s_start[k] = (int)(a.excl[i0 + k] - s0);
       s_row[k] = a.off[u];
     }
-    if (threadIdx.x == 0) s_n = ni;
     __syncthreads();
-    const int nitems = s_n;
     for (int r = 0; r < s_end; r += BT) {
-      const int j = r + threadIdx.x;  // slot within the chunk
-      int lo = 0, hi = nitems - 1;      // last item with start <= j
+      const int j = r + (int)threadIdx.x;  // slot within the chunk
+      int lo = 0, hi = ni - 1;             // last item with start <= j
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (s_start[mid] <= j) lo = mid;
         else hi = mid - 1;
       }
-      const bool valid = j < s_end;
-      const int u = s_u[lo];
-      int k = j - s_start[lo];
-      int e;
-      if (a.off2) {  // undirected view: out-edges first, then in-edges
-        const int d1 = a.deg1[u];
-        e = k < d1 ? s_row[lo] + k : a.off2[u] + (k - d1);
-        vis(u, e, valid, k < d1);
-      } else {
-        e = s_row[lo] + k;
-        vis(u, e, valid, true);
-      }
+      vis(s_u[lo], s_row[lo] + (j - s_start[lo]), j < s_end);
     }
     __syncthreads();
   }
@@ -300,14 +316,13 @@ __device__ void expand_chunks(const ExpandArgs& a, Visit& vis) {
 
 // ------------------------------------------------------- dense push ----
 //
-// Every vertex whose bit is set expands its out-edges; rows with >= BT edges
-// are walked by the whole workgroup, rows with >= 64 edges by one wave, and
-// the remaining short rows of a wave are gathered with a wave prefix sum so
-// that 64 consecutive lanes take 64 consecutive edge slots.
+// Every vertex whose bit is set expands its row; rows with >= BT edges are
+// walked by the whole workgroup, rows with >= 64 edges by one wave, and the
+// remaining short rows of a wave are gathered with a wave prefix sum so that
+// 64 consecutive lanes take 64 consecutive edge slots.
 
 template <int BT, class Visit>
-__device__ void dense_push_expand(const DenseSet& fr, int n, const int32_t* off, Visit& vis,
-                                  bool first_adj) {
+__device__ void dense_push_expand(const DenseSet& fr, int n, const int32_t* off, Visit& vis) {
   __shared__ int sh_owner, sh_u, sh_b, sh_e;
   const int tid = threadIdx.x;
   const int lane = __lane_id();
@@ -332,7 +347,7 @@ __device__ void dense_push_expand(const DenseSet& fr, int n, const int32_t* off,
       const int cu = sh_u, cb = sh_b, ce = sh_e;
       for (int k = cb; k < ce; k += BT) {
         const int e = k + tid;
-        vis(cu, e, e < ce, first_adj);
+        vis(cu, e, e < ce);
       }
       __syncthreads();
     }
@@ -346,7 +361,7 @@ __device__ void dense_push_expand(const DenseSet& fr, int n, const int32_t* off,
       if (lane == leader) beg = end;
       for (int k = cb; k < ce; k += kWave) {
         const int e = k + lane;
-        vis(cu, e, e < ce, first_adj);
+        vis(cu, e, e < ce);
       }
     }
     int total;
@@ -364,9 +379,33 @@ __device__ void dense_push_expand(const DenseSet& fr, int n, const int32_t* off,
       const int cu = __shfl(u, lo, kWave);
       const int cb = __shfl(beg, lo, kWave);
       const int ex = __shfl(excl, lo, kWave);
-      vis(cu, cb + (j - ex), j < total, first_adj);
+      vis(cu, cb + (j - ex), j < total);
     }
   }
+}
+
+// --------------------------------------------------- row-block gathers ----
+//
+// A destination block is a run of consecutive rows holding at most cap_e
+// edges (or one longer row).  gather_block stages f(idx[e]) for the block's
+// edges in LDS with four independent index loads and four independent
+// gathers in flight per thread, so a workgroup keeps many requests
+// outstanding instead of one dependent chain.
+
+template <int BT, typename T, class F>
+__device__ __forceinline__ void gather_block(const int32_t* __restrict__ idx, int e0, int ne,
+                                             T* lds, F f) {
+  int j = threadIdx.x;
+  for (; j + 3 * BT < ne; j += 4 * BT) {
+    const int a0 = idx[e0 + j], a1 = idx[e0 + j + BT], a2 = idx[e0 + j + 2 * BT],
+              a3 = idx[e0 + j + 3 * BT];
+    const T v0 = f(a0), v1 = f(a1), v2 = f(a2), v3 = f(a3);
+    lds[j] = v0;
+    lds[j + BT] = v1;
+    lds[j + 2 * BT] = v2;
+    lds[j + 3 * BT] = v3;
+  }
+  for (; j < ne; j += BT) lds[j] = f(idx[e0 + j]);
 }
 
 }  // namespace gi
