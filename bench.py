@@ -11,16 +11,13 @@ value = GTEPS = (sum over sources of m_reach(s) + m) / step time, where
 m_reach(s) is the number of out-edges of the vertices BFS reaches from s
 (Graph500 convention on a directed graph) and CC counts each edge once.
 
-roofline: the dominant kernel is the frontier loop (k_frontier_loop, one
-cooperative launch per BFS and per CC).  Its algorithmic bytes per launch are
-summed from the per-step trace (frontier size |F|, degree sum D_F, edges
-examined E) with the per-step byte model:
-  SparsePush/DensePush step  12|F| + 8 D_F + 8|F'|
-  DensePull (BFS)             3n/8 + 8U + 4E + 4|F'|     (U unvisited)
-  CC push step               24|F| + 12E + 4|F'|
-  CC pull step               3n/4 + 24n + 4E
-and divided by the launches' GPU time, measured with HIP events that the
-library records on the launch stream.
+roofline: the dominant kernel is whichever step (edge-traversal) kernel,
+k_bfs_step or k_cc_step, has the larger summed GPU time.  Each launch is timed
+with HIP events the library records on the launch stream around it (per-step
+timing); every launch counts, including the no-op steps enqueued after the
+frontier emptied.  Algorithmic bytes per launch come from the step's trace
+entry (|F|, D_F, edges examined) with the byte models below
+(bfs_step_bytes, cc_step_bytes); achieved = bytes per launch / mean launch time.
 
 Other workloads (--workload): pr_rmat16 (20-iteration DensePull PageRank on
 R-MAT scale 16, the PageRank configuration), pr_rmat22, sssp_grid
@@ -66,35 +63,80 @@ def sched_overrides(text):
 
 
 # ------------------------------------------------------------- byte model --
+# Algorithmic bytes of one launch of a step (edge-traversal) kernel, from the
+# step's trace entry.  Compulsory traffic only: every array element the step
+# must touch is counted once, random gathers of vertex data at their
+# compulsory size.
 
-def bfs_launch_bytes(n, dirs, fs, ds, es):
-    """Algorithmic bytes of one BFS frontier-loop launch from its step trace."""
-    total = 0
+def bfs_step_bytes(n, dirs, fs, ds, es):
+    """Per-step bytes of the BFS step kernel.
+      SparsePush/DensePush  12|F| + 8 D_F + 8|F'|   (ids+offsets, index stream +
+                                                    level CAS, level+parent of F')
+      DensePull             3n/8 + 8U + 4E + 4|F'|  (visited, frontier and next
+                                                    bitvectors; offsets of the U
+                                                    unvisited rows; E in-edges
+                                                    scanned up to the first hit)"""
+    out = []
     visited = 0
     k = len(fs)
     for i in range(k):
         f, d, e = int(fs[i]), int(ds[i]), int(es[i])
         fnext = int(fs[i + 1]) if i + 1 < k else 0
         visited += f
-        if dirs[i] == 2:  # DensePull
-            unvisited = n - visited
-            total += 3 * n // 8 + 8 * unvisited + 4 * e + 4 * fnext
+        if dirs[i] == 2:
+            out.append(3 * n // 8 + 8 * (n - visited) + 4 * e + 4 * fnext)
         else:
-            total += 12 * f + 8 * d + 8 * fnext
-    return total
+            out.append(12 * f + 8 * d + 8 * fnext)
+    return out
 
 
-def cc_launch_bytes(n, dirs, fs, es):
-    total = 0
+def cc_step_bytes(n, dirs, fs, ds, es):
+    """Per-step bytes of the CC step kernel (symmetric adjacency, E = edges
+    examined, both directions of every edge).
+      push  16|F| + 8E + 8|F'|        (ids+offsets+own label, index stream +
+                                       atomic-min target, changed labels)
+      pull  4(n+1) + 4E + 12n + n/4   (offsets, index stream, label gather
+                                       (compulsory 4n), own label, new label,
+                                       frontier in and out)"""
+    out = []
     k = len(fs)
     for i in range(k):
         f, e = int(fs[i]), int(es[i])
         fnext = int(fs[i + 1]) if i + 1 < k else 0
         if dirs[i] == 2:
-            total += 3 * n // 4 + 24 * n + 4 * e
+            out.append(4 * (n + 1) + 4 * e + 12 * n + n // 4)
         else:
-            total += 24 * f + 12 * e + 4 * fnext
-    return total
+            out.append(16 * f + 8 * e + 8 * fnext)
+    return out
+
+
+def sssp_step_bytes(dirs, fs, ds, es):
+    """Per-step bytes of the SSSP step kernel: a relaxation step reads the
+    items' ids and offsets and the distances of F (12|F|) and per edge the
+    index, the weight and the atomic-min target (12 E)."""
+    return [12 * int(f) + 12 * int(e) for f, e in zip(fs, es)]
+
+
+class KernelTally:
+    """Launch count, summed HIP-event duration and algorithmic bytes of one
+    step kernel over the timed region."""
+
+    def __init__(self, name):
+        self.name, self.launches, self.ms, self.bytes = name, 0, 0.0, 0
+
+    def add(self, main_ms, step_bytes):
+        self.launches += len(main_ms)
+        self.ms += float(sum(main_ms))
+        self.bytes += int(sum(step_bytes))
+
+    def roofline(self):
+        avg = self.ms / max(self.launches, 1)
+        bpl = self.bytes / max(self.launches, 1)
+        achieved = bpl / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
+        return {"bound": "hbm", "kernel": self.name, "achieved": round(achieved, 2),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": None, "avg_launch_ms": round(avg, 5),
+                "bytes_per_launch": int(bpl), "launches": self.launches}
 
 
 # ------------------------------------------------------------- workloads --
@@ -127,30 +169,27 @@ def run_bfs_cc(args, torch, dev):
     level = torch.empty(n, dtype=torch.int32, device=dev)
     parent = torch.empty(n, dtype=torch.int32, device=dev)
     label = torch.empty(n, dtype=torch.int32, device=dev)
+    bfs_k = KernelTally("k_bfs_step")
+    cc_k = KernelTally("k_cc_step")
 
     def one_step(record):
-        bytes_, kms, launches, bfs_ms = 0, 0.0, 0, []
+        bfs_ms, cc_info = [], None
         for s in srcs:
             g.bfs(int(s), level, parent)
-            st = g.stats()
             if record:
+                st = g.stats()
                 dirs, fs, ds = st.trace()
-                es = st.step_edges_examined()
-                bytes_ += bfs_launch_bytes(n, dirs, fs, ds, es)
-                kms += st.kernel_ms
-                launches += st.launches
+                _, mm = g.step_times()
+                bfs_k.add(mm, bfs_step_bytes(n, dirs, fs, ds, st.step_edges_examined()))
                 bfs_ms.append(st.kernel_ms)
         g.cc(label)
-        st = g.stats()
-        cc_info = None
         if record:
+            st = g.stats()
             dirs, fs, ds = st.trace()
-            es = st.step_edges_examined()
-            bytes_ += cc_launch_bytes(n, dirs, fs, es)
-            kms += st.kernel_ms
-            launches += st.launches
+            _, mm = g.step_times()
+            cc_k.add(mm, cc_step_bytes(n, dirs, fs, ds, st.step_edges_examined()))
             cc_info = (st.kernel_ms, st.steps, st.dense_steps)
-        return bytes_, kms, launches, bfs_ms, cc_info
+        return bfs_ms, cc_info
 
     # m_reach per source (from the GPU levels; identical every run)
     odeg = np.diff(g.out_off).astype(np.int64)
@@ -161,96 +200,89 @@ def run_bfs_cc(args, torch, dev):
         m_reach.append(int(odeg[lv >= 0].sum()))
     teps_edges = sum(m_reach) + m
 
+    g.set_step_timing(True)
     for _ in range(args.warmup):
         one_step(False)
     torch.cuda.synchronize()
-    agg_bytes, agg_kms, agg_launch = 0, 0.0, 0
     bfs_all, cc_all = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        b, kms, nl, bfs_ms, cc_info = one_step(True)
-        agg_bytes += b
-        agg_kms += kms
-        agg_launch += nl
+        bfs_ms, cc_info = one_step(True)
         bfs_all += bfs_ms
         cc_all.append(cc_info)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = dt * 1e3 / args.steps
     value = teps_edges * args.steps / dt / 1e9
-    achieved = agg_bytes / (agg_kms * 1e-3) / 1e9 if agg_kms > 0 else 0.0
-    bfs_ms_med = float(np.median(bfs_all))
     per_src_gteps = [mr / (t * 1e-3) / 1e9 for mr, t in zip(m_reach * args.steps, bfs_all)]
+    dominant = bfs_k if bfs_k.ms >= cc_k.ms else cc_k
+    other = cc_k if dominant is bfs_k else bfs_k
     extra = {
         "n": n, "m": m, "sources": int(len(srcs)),
-        "bfs_kernel_ms_median": round(bfs_ms_med, 4),
+        "bfs_ms_median": round(float(np.median(bfs_all)), 4),
         "bfs_gteps_harmonic_mean": round(len(per_src_gteps) / sum(1.0 / x for x in per_src_gteps), 3),
         "bfs_gteps_median": round(float(np.median(per_src_gteps)), 3),
-        "cc_kernel_ms": round(float(np.median([c[0] for c in cc_all])), 4),
+        "cc_ms": round(float(np.median([c[0] for c in cc_all])), 4),
         "cc_rounds": int(cc_all[0][1]), "cc_dense_rounds": int(cc_all[0][2]),
-        "avg_launch_ms": round(agg_kms / agg_launch, 5),
-        "launches_per_step": agg_launch // args.steps,
-        "algorithmic_bytes_per_step": agg_bytes // args.steps,
+        "other_step_kernel": other.roofline(),
     }
-    roof = {"bound": "hbm", "kernel": "k_frontier_loop", "achieved": round(achieved, 2),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": None,
-            "avg_launch_ms": round(agg_kms / agg_launch, 5),
-            "bytes_per_launch": agg_bytes // agg_launch}
     config = {"workload": "rmat22_ef16_bfs64_plus_cc", "graph": "rmat scale 22 edge factor 16 "
               "abcd=.57/.19/.19/.05 seed 2, relabelled, dedup", "n": n, "m": m,
               "bfs_sources": int(len(srcs)), "schedule": g.schedule().as_dict()}
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline_bfs_cc(el, srcs[:4], m_reach[:4])
-    return value, "GTEPS", ms_step, "int32", config, roof, cpu, extra
+        cpu = cpu_baseline_bfs_cc(el, srcs, m_reach)
+    return value, "GTEPS", ms_step, "int32", config, dominant.roofline(), cpu, extra
 
 
-def cpu_baseline_bfs_cc(el, srcs, m_reach):
+def cpu_baseline_bfs_cc(el, srcs, m_reach, budget_s=12.0):
+    """The oracle, single-threaded, on a bounded sample of the same workload:
+    BFS from the sources in order until the budget is spent (at least 2),
+    then one CC.  TEPS counted as for the GPU line."""
     import oracle
     log("cpu baseline: building the oracle graph (not timed)")
     t0 = time.time()
     og = oracle.Graph(el)
     log("oracle graph built in %.1fs" % (time.time() - t0))
     t0 = time.perf_counter()
+    done = 0
     for s in srcs:
         oracle.bfs(og, int(s))
+        done += 1
+        if done >= 2 and time.perf_counter() - t0 > budget_s:
+            break
     oracle.cc(og)
     dt = time.perf_counter() - t0
-    edges = sum(m_reach) + og.m
+    edges = sum(m_reach[:done]) + og.m
     return {"value": round(edges / dt / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": "oracle FIFO BFS from the first %d of the 64 sources + one label-"
-                      "propagation CC on the same RMAT-22 graph, single thread, %.1f s" %
-                      (len(srcs), dt)}
+                      "propagation CC on the same RMAT-22 graph, one thread, %.1f s" % (done, dt)}
 
 
 def run_pr(args, torch, dev, scale):
     import numpy as np
-    import paper_1805_00923_amd as gi
     el, g = make_rmat_graph(scale, 1 if scale == 16 else 2)
     kw = sched_overrides(args.schedule)
     g.set_schedule(**kw)
     n, m = g.n, g.m
     ranks = torch.empty(n, dtype=torch.float32, device=dev)
+    g.set_step_timing(True)
     for _ in range(args.warmup):
         g.pagerank(ranks, 20, 0.85)
     torch.cuda.synchronize()
     kms = []
+    tally = KernelTally("k_pr_rows" if g.schedule().num_segments <= 1 else "pagerank iteration")
     t0 = time.perf_counter()
     for _ in range(args.steps):
         g.pagerank(ranks, 20, 0.85)
         kms.append(g.stats().kernel_ms)
+        _, mm = g.step_times()
+        tally.add(mm, [4 * m + 16 * n] * len(mm))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = dt * 1e3 / args.steps
     value = 20.0 * m * args.steps / dt / 1e9
-    bytes_launch = 20 * (4 * m + 16 * n) + 4 * n
     kmed = float(np.median(kms))
-    achieved = bytes_launch / (kmed * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": "pagerank (all launches of one 20-iteration run)",
-            "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-            "kernel_ms_median": round(kmed, 5), "bytes_per_run": bytes_launch}
     config = {"workload": "pagerank20_rmat%d_ef16" % scale, "n": n, "m": m,
               "schedule": g.schedule().as_dict()}
     cpu = None
@@ -264,9 +296,11 @@ def run_pr(args, torch, dev, scale):
         dt_c = (time.perf_counter() - t0) / reps
         cpu = {"value": round(20.0 * og.m / dt_c / 1e9, 5), "unit": "GTEPS", "cores": 1,
                "kind": "oracle", "sample": "FP64 pull PageRank, 20 iterations, full graph, "
-                                           "single thread, %.3f s per run" % dt_c}
-    extra = {"gteps_kernel": round(20.0 * m / (kmed * 1e-3) / 1e9, 3)}
-    return value, "GTEPS", ms_step, "f32 storage / f64 accumulate", config, roof, cpu, extra
+                                           "one thread, %.3f s per run" % dt_c}
+    extra = {"run_ms_median": round(kmed, 4),
+             "gteps_kernel": round(20.0 * m / (kmed * 1e-3) / 1e9, 3),
+             "bytes_per_run": 20 * (4 * m + 16 * n) + 4 * n}
+    return value, "GTEPS", ms_step, "f32 storage / f64 accumulate", config, tally.roofline(), cpu, extra
 
 
 def run_sssp(args, torch, dev):
@@ -289,11 +323,13 @@ def run_sssp(args, torch, dev):
         g.sssp(int(s), dist)
         d = dist.cpu().numpy().view(np.uint32)
         m_reach.append(int(odeg[d != 0xFFFFFFFF].sum()))
+    g.set_step_timing(True)
     for _ in range(args.warmup):
         for s in srcs:
             g.sssp(int(s), dist)
     torch.cuda.synchronize()
     kms, phases = [], []
+    tally = KernelTally("k_sssp_step")
     t0 = time.perf_counter()
     for _ in range(args.steps):
         for s in srcs:
@@ -301,16 +337,16 @@ def run_sssp(args, torch, dev):
             st = g.stats()
             kms.append(st.kernel_ms)
             phases.append(st.steps)
+            dirs, fs, ds = st.trace()
+            _, mm = g.step_times()
+            sb = sssp_step_bytes(dirs, fs, ds, st.step_edges_examined())
+            if len(mm) >= len(sb):   # traces longer than the event capacity are skipped
+                tally.add(mm, sb)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = sum(m_reach) * args.steps / dt / 1e9
-    n_reach = g.n
-    bytes_run = 12 * int(np.mean(m_reach)) + 12 * n_reach
     kmed = float(np.median(kms))
-    achieved = bytes_run / (kmed * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": "k_sssp_loop", "achieved": round(achieved, 2),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": None, "kernel_ms_median": round(kmed, 4)}
+    roof = tally.roofline()
     config = {"workload": "sssp_grid4096_shortcut1pct", "n": g.n, "m": g.m, "sources": 4,
               "schedule": g.schedule().as_dict()}
     extra = {"phases_median": int(np.median(phases))}

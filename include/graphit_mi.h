@@ -227,6 +227,23 @@ gi_status gi_sssp(gi_graph* g, int32_t src, uint32_t* dist, void* stream);
 /* Statistics of the last algorithm call on g. */
 gi_status gi_get_run_stats(const gi_graph* g, gi_run_stats* out);
 
+/* Per-step timing, the cost record that schedule tuning needs (the paper's
+ * autotuner, section 5, times whole runs; this times every edgeset.apply
+ * step).  When enabled, each later call records HIP events on its stream
+ * around every step it enqueues (one step = one PageRank iteration, or one
+ * frontier step of BFS/CC/SSSP, counting the no-op steps enqueued after the
+ * frontier emptied).  Errors: INVALID_ARG (enable not 0/1). */
+gi_status gi_set_step_timing(gi_graph* g, int32_t enable);
+
+/* Times of the steps of the last call (it has returned, so its work is
+ * complete).  step_ms[k]: from the first kernel of step k (frontier count,
+ * direction decision, compaction) to the end of its edge-traversal kernel;
+ * main_ms[k]: that traversal kernel alone.  Writes min(cap, *count) entries;
+ * *count = steps recorded (at most 4096).
+ * Errors: INVALID_ARG (NULL count, cap < 0, NULL arrays with cap > 0), DEVICE. */
+gi_status gi_get_step_times(const gi_graph* g, float* step_ms, float* main_ms, int32_t cap,
+                            int32_t* count);
+
 /* ---- frontier primitives (device, stream ordered) -------------------- */
 /* Dense and sparse vertexset representations (section 2, direction
  * optimization and frontier data structure; scheduling-language table,

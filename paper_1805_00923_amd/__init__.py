@@ -98,6 +98,8 @@ _SIGS = {
     "gi_cc": (ctypes.c_int, [_vp, _vp, _vp]),
     "gi_sssp": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
     "gi_get_run_stats": (ctypes.c_int, [_vp, _vp]),
+    "gi_set_step_timing": (ctypes.c_int, [_vp, _i32]),
+    "gi_get_step_times": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp]),
     "gi_frontier_sparse_to_bitvec": (ctypes.c_int, [_i32, _vp, _i32, _vp, _vp]),
     "gi_frontier_bitvec_to_sparse": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp]),
     "gi_frontier_bitvec_to_boolmap": (ctypes.c_int, [_i32, _vp, _vp, _vp]),
@@ -261,6 +263,19 @@ class Graph:
         r = RunStats()
         _check(lib.gi_get_run_stats(self._h, ctypes.byref(r)))
         return r
+
+    def set_step_timing(self, enable=True):
+        _check(lib.gi_set_step_timing(self._h, 1 if enable else 0))
+
+    def step_times(self):
+        """(step_ms, main_ms) float32 arrays of the last call's steps."""
+        cnt = ctypes.c_int32()
+        _check(lib.gi_get_step_times(self._h, None, None, 0, ctypes.byref(cnt)))
+        k = cnt.value
+        a = np.zeros(max(k, 1), np.float32)
+        b = np.zeros(max(k, 1), np.float32)
+        _check(lib.gi_get_step_times(self._h, a.ctypes.data, b.ctypes.data, k, ctypes.byref(cnt)))
+        return a[:k], b[:k]
 
     # ---- algorithms: outputs are device tensors supplied by the caller ----
     def pagerank(self, ranks, iters=20, damping=0.85, stream=None):

@@ -619,14 +619,22 @@ int launch_bfs_init(const BfsArgs& b, int src, DenseSet f0, DenseSet f1, hipStre
   return GI_OK_LAUNCH();
 }
 
+static void mark(const StepEvents* te, int which, hipStream_t s) {
+  if (!te) return;
+  (void)hipEventRecord(which == 0 ? te->start : which == 1 ? te->main : te->end, s);
+}
+
 int enqueue_bfs_step(const Engine& e, const FrontierArgs& f, const DecideArgs& d,
-                     const BfsArgs& b, hipStream_t s) {
+                     const BfsArgs& b, const StepEvents* te, hipStream_t s) {
+  mark(te, 0, s);
   hipLaunchKernelGGL(k_count<kBT>, dim3(e.cgrid), dim3(kBT), 0, s, f);
   hipLaunchKernelGGL(k_decide_frontier, dim3(1), dim3(1024), 0, s, f, d);
   hipLaunchKernelGGL((k_write<kBT, kCH>), dim3(e.cgrid), dim3(kBT), 0, s, f,
                      (int)MODE_SPARSE_PUSH);
+  mark(te, 1, s);
   hipLaunchKernelGGL((k_bfs_step<kBT, kCH>), dim3(kParts), dim3(kBT), 0, s, b,
                      expand_args(e, b.g.out_off));
+  mark(te, 2, s);
   return GI_OK_LAUNCH();
 }
 
@@ -643,13 +651,16 @@ int launch_build_sym(const DevGraph& g, const int32_t* sym_off, int32_t* sym_idx
 }
 
 int enqueue_cc_step(const Engine& e, const FrontierArgs& f, const DecideArgs& d, const CcArgs& c,
-                    hipStream_t s) {
+                    const StepEvents* te, hipStream_t s) {
+  mark(te, 0, s);
   hipLaunchKernelGGL(k_count<kBT>, dim3(e.cgrid), dim3(kBT), 0, s, f);
   hipLaunchKernelGGL(k_decide_frontier, dim3(1), dim3(1024), 0, s, f, d);
   hipLaunchKernelGGL((k_write<kBT, kCH>), dim3(e.cgrid), dim3(kBT), 0, s, f,
                      (int)MODE_SPARSE_PUSH);
+  mark(te, 1, s);
   hipLaunchKernelGGL((k_cc_step<kBT, kCH>), dim3(kParts), dim3(kBT), 0, s, c,
                      expand_args(e, c.sym_off));
+  mark(te, 2, s);
   return GI_OK_LAUNCH();
 }
 
@@ -658,13 +669,17 @@ int launch_sssp_init(const SsspArgs& sa, int src, hipStream_t s) {
   return GI_OK_LAUNCH();
 }
 
-int enqueue_sssp_step(const Engine& e, const FrontierArgs& f, const SsspArgs& sa, hipStream_t s) {
+int enqueue_sssp_step(const Engine& e, const FrontierArgs& f, const SsspArgs& sa,
+                      const StepEvents* te, hipStream_t s) {
+  mark(te, 0, s);
   hipLaunchKernelGGL(k_count<kBT>, dim3(e.cgrid), dim3(kBT), 0, s, f);
   hipLaunchKernelGGL(k_decide_sssp, dim3(1), dim3(1024), 0, s, f, sa);
   hipLaunchKernelGGL((k_sssp_prepare<kBT, kCH>), dim3(e.cgrid), dim3(kBT), 0, s, f, sa);
   hipLaunchKernelGGL(k_sssp_threshold, dim3(1), dim3(1024), 0, s, sa, e.cgrid);
+  mark(te, 1, s);
   hipLaunchKernelGGL((k_sssp_step<kBT, kCH>), dim3(kParts), dim3(kBT), 0, s, sa,
                      expand_args(e, sa.g.out_off));
+  mark(te, 2, s);
   return GI_OK_LAUNCH();
 }
 

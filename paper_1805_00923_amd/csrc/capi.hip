@@ -110,7 +110,14 @@ struct gi_graph {
   HostFlags* dflags = nullptr; // device address of hflags
   Engine eng{};
   hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t evb[2] = {nullptr, nullptr};  // batch completion events
   gi_run_stats stats{};
+  // per-step timing (optional)
+  int step_timing = 0;
+  bool timing_failed = false;
+  std::vector<StepEvents> tev;
+  int tev_count = 0;        // steps of the last run that carry events
+  int last_steps[4] = {0, 0, 0, 0};  // steps of the previous run, per algorithm
 };
 
 template <typename T>
@@ -454,6 +461,13 @@ extern "C" gi_status gi_graph_destroy(gi_graph* g) {
   if (g->hflags) (void)hipHostFree(g->hflags);
   for (hipEvent_t e : g->ev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : g->evb)
+    if (e) (void)hipEventDestroy(e);
+  for (StepEvents& t : g->tev) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.main);
+    (void)hipEventDestroy(t.end);
+  }
   delete g;
   return GI_OK;
 }
@@ -632,10 +646,10 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
     return fail(GI_ERR_OUT_OF_MEMORY, "pinned host flags allocation failed");
   }
   std::memset(g->hflags, 0, sizeof(HostFlags));
-  for (hipEvent_t& e : g->ev) {
-    if (hipEventCreate(&e) != hipSuccess) {
+  for (hipEvent_t* e : {&g->ev[0], &g->ev[1], &g->evb[0], &g->evb[1]}) {
+    if (hipEventCreate(e) != hipSuccess) {
       (void)hipGetLastError();
-      e = nullptr;
+      *e = nullptr;
       gi_graph_destroy(g);
       return fail(GI_ERR_DEVICE, "hipEventCreate failed");
     }
@@ -697,6 +711,26 @@ static DenseSet frontier_set(const gi_graph* g, int k) {
 
 // Copy the control block and the step log of the last frontier loop (one
 // copy) into g->stats.
+// Events of step k when per-step timing is on (nullptr otherwise, or past
+// the trace capacity).  Events are created on first use and kept.
+static const StepEvents* step_events(gi_graph* g, long long k) {
+  if (!g->step_timing || k >= kMaxLog || g->timing_failed) return nullptr;
+  while ((long long)g->tev.size() <= k) {
+    StepEvents t{nullptr, nullptr, nullptr};
+    if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.main) != hipSuccess ||
+        hipEventCreate(&t.end) != hipSuccess) {
+      (void)hipGetLastError();
+      for (hipEvent_t e : {t.start, t.main, t.end})
+        if (e) (void)hipEventDestroy(e);
+      g->timing_failed = true;
+      return nullptr;
+    }
+    g->tev.push_back(t);
+  }
+  g->tev_count = std::max(g->tev_count, (int)k + 1);
+  return &g->tev[(size_t)k];
+}
+
 static gi_status read_loop_stats(gi_graph* g, int alg, hipStream_t s) {
   const int hsteps = ((const volatile HostFlags*)g->hflags)->steps;
   const int steps = std::min(hsteps, kMaxLog);
@@ -710,6 +744,7 @@ static gi_status read_loop_stats(gi_graph* g, int alg, hipStream_t s) {
   r.dense_steps = c.dense_steps;
   r.edges_examined = (int64_t)c.edges_examined;
   r.trace_len = std::min(c.steps, GI_MAX_TRACE);
+  g->last_steps[alg] = c.steps;
   for (int i = 0; i < r.trace_len; ++i) {
     r.step_direction[i] = (int8_t)c.log[i].dir;
     r.step_frontier[i] = c.log[i].frontier;
@@ -730,15 +765,26 @@ static gi_status read_kernel_ms(gi_graph* g, int launches) {
 
 // Enqueue steps in batches until the device reports completion through the
 // pinned host flags.  `step(k)` enqueues step k and returns the number of
-// kernels it launched (negative on a launch error).
+// kernels it launched (negative on a launch error).  The first batch is
+// sized from the previous run of the same algorithm, so a run of the usual
+// length needs one host synchronisation; longer runs continue with two
+// batches in flight, so the stream never drains while the host looks at the
+// flags.  Steps enqueued after completion see the finished state and return
+// at once.
 template <class StepFn>
-static gi_status run_frontier_loop(gi_graph* g, hipStream_t s, int batch, long long max_steps,
-                                   StepFn step, const char* what) {
+static gi_status run_frontier_loop(gi_graph* g, hipStream_t s, int alg, int dflt,
+                                   long long max_steps, StepFn step, const char* what) {
   int launches = 0;
   long long k = 0;
-  HIP_TRY(hipEventRecord(g->ev[0], s));
-  for (;;) {
-    for (int b = 0; b < batch; ++b, ++k) {
+  g->tev_count = 0;
+  const int fixed = g->sched.steps_per_sync;
+  const int first = fixed > 0 ? fixed
+                              : (g->last_steps[alg] > 0 ? std::min(g->last_steps[alg] + 1, kMaxLog)
+                                                        : dflt);
+  const int batch = fixed > 0 ? fixed : dflt;
+  long long kmark[2] = {0, 0};  // steps enqueued when each batch event was recorded
+  auto enqueue = [&](int nb, int j) -> gi_status {
+    for (int b = 0; b < nb; ++b, ++k) {
       const int nl = step(k);
       if (nl < 0) {
         hipError_t e = hipGetLastError();
@@ -746,13 +792,34 @@ static gi_status run_frontier_loop(gi_graph* g, hipStream_t s, int batch, long l
       }
       launches += nl;
     }
-    HIP_TRY(hipEventRecord(g->ev[1], s));
-    HIP_TRY(hipEventSynchronize(g->ev[1]));
+    HIP_TRY(hipEventRecord(g->evb[j], s));
+    kmark[j] = k;
+    return GI_OK;
+  };
+  // Waits for batch event j; *done once the device reported completion.
+  auto finished = [&](int j, bool* done) -> gi_status {
+    HIP_TRY(hipEventSynchronize(g->evb[j]));
     const volatile HostFlags* f = g->hflags;
     if (f->error) return fail(GI_ERR_DEVICE, "%s: internal size check failed", what);
-    if (f->done) break;
-    if (k > max_steps) return fail(GI_ERR_DEVICE, "%s did not terminate", what);
+    *done = f->done != 0;
+    if (!*done && kmark[j] > max_steps) return fail(GI_ERR_DEVICE, "%s did not terminate", what);
+    return GI_OK;
+  };
+  HIP_TRY(hipEventRecord(g->ev[0], s));
+  gi_status st = enqueue(first, 0);
+  bool done = false;
+  if (st == GI_OK) st = finished(0, &done);
+  if (st == GI_OK && !done) {
+    st = enqueue(batch, 0);
+    for (int i = 1; st == GI_OK; ++i) {
+      if ((st = enqueue(batch, i & 1)) != GI_OK) break;
+      if ((st = finished((i - 1) & 1, &done)) != GI_OK || done) break;
+    }
   }
+  HIP_TRY(hipEventRecord(g->ev[1], s));
+  HIP_TRY(hipEventSynchronize(g->ev[1]));
+  if (st != GI_OK) return st;
+  if (g->timing_failed) return fail(GI_ERR_DEVICE, "%s: could not create timing events", what);
   return read_kernel_ms(g, launches);
 }
 
@@ -764,9 +831,6 @@ static gi_status start_run(gi_graph* g, unsigned long long delta, hipStream_t s)
   return GI_OK;
 }
 
-static int batch_size(const gi_graph* g, int dflt) {
-  return g->sched.steps_per_sync > 0 ? g->sched.steps_per_sync : dflt;
-}
 
 // ---------------------------------------------------------- algorithms ----
 
@@ -784,10 +848,16 @@ extern "C" gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, floa
   int launches = 1;
   HIP_TRY(hipEventRecord(g->ev[0], s));
   LAUNCH_TRY(launch_pr_init(g->n, g->outdeg, g->contrib[0], ranks, iters == 0, s));
+  g->tev_count = 0;
   for (int k = 0; k < iters; ++k) {
     const bool last = k == iters - 1;
     float* cin = g->contrib[k & 1];
     float* cout = g->contrib[(k + 1) & 1];
+    const StepEvents* te = step_events(g, k);
+    if (te) {
+      HIP_TRY(hipEventRecord(te->start, s));
+      HIP_TRY(hipEventRecord(te->main, s));
+    }
     if (g->sched.num_segments <= 1) {
       PrRows r{g->pr_table, g->pr_ntab, g->in_off, g->in_idx, nullptr, g->lr_acc, g->lr_cnt,
                g->lr_chunks};
@@ -804,9 +874,11 @@ extern "C" gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, floa
       LAUNCH_TRY(launch_pr_seg_final(g->n, pv, g->pr_acc, cout, last ? ranks : nullptr, s));
       ++launches;
     }
+    if (te) HIP_TRY(hipEventRecord(te->end, s));
   }
   HIP_TRY(hipEventRecord(g->ev[1], s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (g->timing_failed) return fail(GI_ERR_DEVICE, "PageRank: could not create timing events");
   gi_status ts = read_kernel_ms(g, launches);
   if (ts != GI_OK) return ts;
   gi_run_stats& st = g->stats;
@@ -853,13 +925,13 @@ extern "C" gi_status gi_bfs(gi_graph* g, int32_t src, int32_t* level, int32_t* p
   LAUNCH_TRY(launch_bfs_init(b, src, frontier_set(g, 0), frontier_set(g, 1), s));
   const DecideArgs d = decide_args(g, g->m);
   st = run_frontier_loop(
-      g, s, batch_size(g, 8), (long long)g->n + 2,
+      g, s, ALG_BFS, 8, (long long)g->n + 2,
       [&](long long k) {
         BfsArgs bk = b;
         bk.cur = frontier_set(g, (int)(k & 1));
         bk.next = frontier_set(g, (int)((k + 1) & 1));
         const FrontierArgs f = frontier_args(g->eng, bk.cur, bk.next, g->outdeg, nullptr, nullptr);
-        return enqueue_bfs_step(g->eng, f, d, bk, s) ? -1 : 4;
+        return enqueue_bfs_step(g->eng, f, d, bk, step_events(g, k), s) ? -1 : 4;
       },
       "BFS");
   if (st != GI_OK) return st;
@@ -907,7 +979,7 @@ extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
   LAUNCH_TRY(launch_cc_init(c, frontier_set(g, 0), frontier_set(g, 1), labs[1], s));
   const DecideArgs d = decide_args(g, 2 * g->m);
   st = run_frontier_loop(
-      g, s, batch_size(g, 8), (long long)g->n + 2,
+      g, s, ALG_CC, 8, (long long)g->n + 2,
       [&](long long k) {
         CcArgs ck = c;
         ck.cur = labs[k & 1];
@@ -915,7 +987,7 @@ extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
         ck.fr = frontier_set(g, (int)(k & 1));
         ck.next = frontier_set(g, (int)((k + 1) & 1));
         const FrontierArgs f = frontier_args(g->eng, ck.fr, ck.next, g->udeg, ck.cur, ck.nxt);
-        return enqueue_cc_step(g->eng, f, d, ck, s) ? -1 : 4;
+        return enqueue_cc_step(g->eng, f, d, ck, step_events(g, k), s) ? -1 : 4;
       },
       "CC");
   if (st != GI_OK) return st;
@@ -949,13 +1021,13 @@ extern "C" gi_status gi_sssp(gi_graph* g, int32_t src, uint32_t* dist, void* str
   a.ctl = g->ctl;
   LAUNCH_TRY(launch_sssp_init(a, src, s));
   st = run_frontier_loop(
-      g, s, batch_size(g, 64), 64LL * g->n + 1024,
+      g, s, ALG_SSSP, 64, 64LL * g->n + 1024,
       [&](long long k) {
         SsspArgs ak = a;
         ak.cur = DenseSet{g->fbv[k & 1], nullptr};
         ak.next = DenseSet{g->fbv[(k + 1) & 1], nullptr};
         const FrontierArgs f = frontier_args(g->eng, ak.cur, ak.next, g->outdeg, nullptr, nullptr);
-        return enqueue_sssp_step(g->eng, f, ak, s) ? -1 : 5;
+        return enqueue_sssp_step(g->eng, f, ak, step_events(g, k), s) ? -1 : 5;
       },
       "SSSP");
   if (st != GI_OK) return st;
@@ -968,6 +1040,29 @@ extern "C" gi_status gi_sssp(gi_graph* g, int32_t src, uint32_t* dist, void* str
 extern "C" gi_status gi_get_run_stats(const gi_graph* g, gi_run_stats* out) {
   if (!g || !out) return fail(GI_ERR_INVALID_ARG, "NULL argument");
   *out = g->stats;
+  return GI_OK;
+}
+
+extern "C" gi_status gi_set_step_timing(gi_graph* g, int32_t enable) {
+  if (!g) return fail(GI_ERR_INVALID_ARG, "NULL graph");
+  if (enable != 0 && enable != 1) return fail(GI_ERR_INVALID_ARG, "enable must be 0 or 1");
+  g->step_timing = enable;
+  g->timing_failed = false;
+  g->tev_count = 0;
+  return GI_OK;
+}
+
+extern "C" gi_status gi_get_step_times(const gi_graph* g, float* step_ms, float* main_ms,
+                                       int32_t cap, int32_t* count) {
+  if (!g || !count || cap < 0 || (cap > 0 && (!step_ms || !main_ms)))
+    return fail(GI_ERR_INVALID_ARG, "bad step-time arguments");
+  const int nk = std::min(g->tev_count, (int)cap);
+  for (int k = 0; k < nk; ++k) {
+    const StepEvents& t = g->tev[(size_t)k];
+    HIP_TRY(hipEventElapsedTime(&step_ms[k], t.start, t.end));
+    HIP_TRY(hipEventElapsedTime(&main_ms[k], t.main, t.end));
+  }
+  *count = g->tev_count;
   return GI_OK;
 }
 

@@ -103,16 +103,23 @@ struct SsspArgs {
 int expand_chunk_size();
 FrontierArgs frontier_args(const Engine& e, DenseSet cur, DenseSet next, const int32_t* deg,
                            const int32_t* fix_src, int32_t* fix_dst);
+// Optional timing events around one step: `start` before the step's first
+// kernel, `main` before its edge-traversal kernel, `end` after it.
+struct StepEvents {
+  hipEvent_t start, main, end;
+};
+
 int launch_ctl_init(Control* c, HostFlags* host, unsigned long long delta, hipStream_t s);
 int launch_bfs_init(const BfsArgs& b, int src, DenseSet f0, DenseSet f1, hipStream_t s);
 int enqueue_bfs_step(const Engine& e, const FrontierArgs& f, const DecideArgs& d,
-                     const BfsArgs& b, hipStream_t s);
+                     const BfsArgs& b, const StepEvents* te, hipStream_t s);
 int launch_cc_init(const CcArgs& c, DenseSet f0, DenseSet f1, int32_t* lab_other, hipStream_t s);
 int launch_build_sym(const DevGraph& g, const int32_t* sym_off, int32_t* sym_idx, hipStream_t s);
 int enqueue_cc_step(const Engine& e, const FrontierArgs& f, const DecideArgs& d, const CcArgs& c,
-                    hipStream_t s);
+                    const StepEvents* te, hipStream_t s);
 int launch_sssp_init(const SsspArgs& sa, int src, hipStream_t s);
-int enqueue_sssp_step(const Engine& e, const FrontierArgs& f, const SsspArgs& sa, hipStream_t s);
+int enqueue_sssp_step(const Engine& e, const FrontierArgs& f, const SsspArgs& sa,
+                      const StepEvents* te, hipStream_t s);
 
 int launch_pr_init(int n, const int32_t* outdeg, float* c0, float* rank, bool zero_iters,
                    hipStream_t s);

@@ -299,3 +299,35 @@ def test_schedule_errors_and_bad_arguments():
         g.pagerank(torch.zeros((g.n,), dtype=torch.float32, device=dev), -1)
     assert e.value.status == gi.GI_ERR_INVALID_ARG
     g.set_schedule()
+
+
+# ------------------------------------------------------------- step timing
+
+def test_step_timing_covers_every_step_and_changes_nothing():
+    el, g, og = by_name("rmat13_ef16_s23")
+    s = sources_of(el, 1)[0]
+    ref = oracle.bfs(og, s)[0]
+    g.set_schedule(direction=3)
+    g.set_step_timing(True)
+    try:
+        for rep in range(3):   # the first batch size adapts after the first run
+            say("timed bfs rep %d" % rep)
+            lv, par = run_bfs(g, s)
+            assert np.array_equal(lv, ref)
+            assert oracle.check_bfs_parents(og, s, lv, par) == []
+            st = g.stats()
+            step_ms, main_ms = g.step_times()
+            assert len(step_ms) >= st.trace_len > 0
+            assert np.all(main_ms >= 0) and np.all(step_ms >= main_ms - 1e-3)
+        ranks = run_pr(g, 7)
+        assert pr_max_rel(ranks, oracle.pagerank(og, 7, 0.85)) <= PR_RTOL
+        step_ms, main_ms = g.step_times()
+        assert len(main_ms) == 7 and np.all(main_ms > 0)
+        lab = run_cc(g)
+        assert np.array_equal(lab, oracle.cc(og)[0])
+        assert len(g.step_times()[1]) >= g.stats().trace_len
+    finally:
+        g.set_step_timing(False)
+        g.set_schedule()
+    g.bfs(int(s), __import__("torch").empty(g.n, dtype=__import__("torch").int32, device="cuda:0"))
+    assert len(g.step_times()[0]) == 0

@@ -1,0 +1,83 @@
+"""Parity at the full benchmark sizes, in the launch configuration bench.py
+times (default hybrid schedule, bitvector frontier, adaptive batching,
+per-step timing on): RMAT scale 22 BFS from sampled sources and CC, checked
+exactly against the oracle; PageRank on RMAT scale 22 within 1e-6; and
+delta-stepping on the 4096 x 4096 grid with 1% shortcuts against Dijkstra
+from sampled sources."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from gpu_util import (PR_RTOL, device_graph, pr_max_rel, run_bfs, run_cc, run_pr, run_sssp,
+                      say)
+
+pytestmark = pytest.mark.gpu
+
+_G = {}
+
+
+def rmat22():
+    if "rmat22" not in _G:
+        say("building rmat22")
+        el = gg.rmat(22, 16, seed=2)
+        g = device_graph(el)
+        og = oracle.Graph(el)
+        _G["rmat22"] = (el, g, og)
+    return _G["rmat22"]
+
+
+def test_rmat22_bfs_sampled_sources():
+    el, g, og = rmat22()
+    g.set_schedule(direction=3, dense_frontier=1, hybrid_divisor=20)
+    g.set_step_timing(True)
+    srcs = gg.pick_sources(el, 64, 3)
+    # first, middle and last of the 64 benchmark sources
+    for s in (srcs[0], srcs[31], srcs[63]):
+        say("rmat22 bfs src=%d" % s)
+        lv, par = run_bfs(g, s)
+        ref = oracle.bfs(og, int(s))[0]
+        assert np.array_equal(lv, ref)
+        assert oracle.check_bfs_parents(og, int(s), lv, par) == []
+        assert g.stats().dense_steps > 0
+    g.set_step_timing(False)
+
+
+def test_rmat22_cc():
+    el, g, og = rmat22()
+    g.set_schedule(direction=3, dense_frontier=1, hybrid_divisor=20)
+    say("rmat22 cc")
+    lab = run_cc(g)
+    ref, rounds = oracle.cc(og)
+    assert np.array_equal(lab, ref)
+    assert g.stats().steps == rounds
+
+
+def test_rmat22_pagerank():
+    el, g, og = rmat22()
+    g.set_schedule()
+    say("rmat22 pagerank")
+    x = run_pr(g, 20)
+    assert pr_max_rel(x, oracle.pagerank(og, 20, 0.85)) <= PR_RTOL
+    g.set_schedule(num_segments=8)
+    say("rmat22 pagerank 8 segments")
+    x = run_pr(g, 20)
+    assert pr_max_rel(x, oracle.pagerank(og, 20, 0.85)) <= PR_RTOL
+    g.set_schedule()
+    _G.pop("rmat22", None)
+
+
+def test_grid4096_sssp_sampled_sources():
+    say("building grid4096")
+    el = gg.grid(4096, 4096, 0.01, seed=4)
+    g = device_graph(el)
+    og = oracle.Graph(el)
+    srcs = gg.pick_sources(el, 4, 5)
+    for delta in (4096,):
+        g.set_schedule(sssp_delta=delta)
+        g.set_step_timing(True)
+        for s in srcs[:2]:
+            say("grid4096 sssp src=%d delta=%d" % (s, delta))
+            d = run_sssp(g, s)
+            assert np.array_equal(d, oracle.dijkstra(og, int(s)))
+    g.set_step_timing(False)
