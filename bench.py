@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", default="", help="k=v,... overrides of the schedule")
     ap.add_argument("--json-out", default="")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="first run one elementwise copy of this many MiB (read once, written "
+                         "once), a reference dispatch for hardware byte counters")
     return ap.parse_args()
 
 
@@ -361,6 +364,12 @@ def main():
         sys.exit(2)
     import torch
     dev = torch.device("cuda:0")
+    if args.copy_calib_mb > 0:
+        src = torch.ones(args.copy_calib_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "bfs_cc_rmat22":
         res = run_bfs_cc(args, torch, dev)
     elif args.workload == "pr_rmat16":

@@ -55,13 +55,12 @@ __global__ __launch_bounds__(1024) void k_decide_frontier(FrontierArgs f, Decide
     if (!c->done) {
       const int k = c->steps;
       if (k > 0) {
-        if (k <= kMaxLog) c->log[k - 1].edges = work;
+        if (k <= kMaxLog) c->host->log[k - 1].edges = work;
         c->edges_examined += work;
       }
       if (tot.members == 0) {
         c->done = 1;
-        host_flag(&c->host->steps, k);
-        host_flag(&c->host->done, 1);
+        publish_done(c, k);
       } else {
         int dir = d.direction;
         if (d.forced_dir >= 0) dir = d.forced_dir;
@@ -71,7 +70,7 @@ __global__ __launch_bounds__(1024) void k_decide_frontier(FrontierArgs f, Decide
         else if (dir == GI_DIR_DENSE_PUSH_SPARSE_PUSH)
           dir = hybrid_dense(tot.members, tot.degsum, d.edges, d.divisor) ? GI_DIR_DENSE_PUSH
                                                                           : GI_DIR_SPARSE_PUSH;
-        if (k < kMaxLog) c->log[k] = StepLog{dir, (int)tot.members, tot.degsum, 0};
+        if (k < kMaxLog) c->host->log[k] = StepLog{dir, (int)tot.members, tot.degsum, 0};
         c->steps = k + 1;
         if (dir != GI_DIR_SPARSE_PUSH) c->dense_steps++;
         c->nf = tot.members;
@@ -108,12 +107,15 @@ struct BfsVisit {
   }
 };
 
-// DensePull: one wave per 64-vertex word.  Unvisited lanes test their first
-// in-edges in batches of four independent loads, then the wave walks each
-// remaining long row 64 edges at a time; both stop at the first source in
-// the frontier, in in-edge order.  The next frontier word and the visited
-// word are written whole, without atomics.
-template <int BT>
+// DensePull: a wave owns 64-vertex words and takes G of them at a time, so
+// the dependent load chains of G words (visited word -> in-row bounds ->
+// in-neighbour ids -> frontier bits) overlap instead of running one after
+// another.  Unvisited lanes test their first in-edges in two batches of
+// four independent loads; the rows still open are then concatenated and
+// walked 64 edges per round across the wave.  Every row stops at its first
+// source in the frontier, in in-edge order.  The next frontier word and the
+// visited word are written whole, without atomics.
+template <int BT, int G = 4>
 __device__ long long bfs_pull(const BfsArgs& b, int l1) {
   const DevGraph& g = b.g;
   const int n = g.n, W = (n + 63) >> 6, lane = __lane_id();
@@ -121,73 +123,133 @@ __device__ long long bfs_pull(const BfsArgs& b, int l1) {
   long long work = 0;
   const int wave0 = blockIdx.x * (BT / kWave) + (int)(threadIdx.x / kWave);
   const int nwaves = gridDim.x * (BT / kWave);
-  for (int w = wave0; w < W; w += nwaves) {
-    const int v = (w << 6) + lane;
-    const uint64_t vw = b.vis[w];
-    const bool cand = v < n && !((vw >> lane) & 1ull);
-    bool found = false;
-    int par = -1;
-    if (__ballot(cand) != 0ull) {
-      int j = 0, e = 0;
-      if (cand) {
-        j = g.in_off[v];
-        e = g.in_off[v + 1];
+  for (int wb = wave0; wb < W; wb += G * nwaves) {
+    uint64_t vw[G];
+    bool cand[G], found[G];
+    int j[G], e[G], par[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      const int w = wb + q * nwaves;  // wave-uniform
+      const int v = (w << 6) + lane;
+      vw[q] = w < W ? b.vis[w] : ~0ull;
+      cand[q] = w < W && v < n && !((vw[q] >> lane) & 1ull);
+      found[q] = false;
+      par[q] = -1;
+      j[q] = 0;
+      e[q] = 0;
+    }
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      if (cand[q]) {
+        const int v = ((wb + q * nwaves) << 6) + lane;
+        j[q] = g.in_off[v];
+        e[q] = g.in_off[v + 1];
       }
+    }
 #pragma unroll
-      for (int batch = 0; batch < 2; ++batch) {
-        int u[4];
-        bool h[4];
+    for (int batch = 0; batch < 2; ++batch) {
+      int u[G][4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) u[q] = (!found && j + q < e) ? g.in_idx[j + q] : -1;
+      for (int q = 0; q < G; ++q)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) h[q] = u[q] >= 0 && cur.test(u[q]);
+        for (int r = 0; r < 4; ++r)
+          u[q][r] = (cand[q] && !found[q] && j[q] + r < e[q]) ? g.in_idx[j[q] + r] : -1;
+      bool h[G][4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (!found && u[q] >= 0) {
+      for (int q = 0; q < G; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h[q][r] = u[q][r] >= 0 && cur.test(u[q][r]);
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (!found[q] && u[q][r] >= 0) {
             ++work;
-            if (h[q]) {
-              found = true;
-              par = u[q];
+            if (h[q][r]) {
+              found[q] = true;
+              par[q] = u[q][r];
             }
           }
         }
-        if (!found) j = min(e, j + 4);
+        if (!found[q]) j[q] = min(e[q], j[q] + 4);
       }
-      unsigned long long rm = __ballot(cand && !found && j < e);
-      while (rm) {
-        const int leader = __ffsll((long long)rm) - 1;
-        rm &= rm - 1;
-        const int lb = __shfl(j, leader, kWave);
-        const int le = __shfl(e, leader, kWave);
-        for (int j0 = lb; j0 < le; j0 += kWave) {
-          const int jj = j0 + lane;
-          const int uu = jj < le ? g.in_idx[jj] : 0;
-          const bool hit = jj < le && cur.test(uu);
-          const unsigned long long hm = __ballot(hit);
-          // edges a sequential scan examines: up to and including the first hit
-          if (jj < le && (hm == 0ull || lane <= __ffsll((long long)hm) - 1)) ++work;
-          if (hm) {
-            const int pu = __shfl(uu, __ffsll((long long)hm) - 1, kWave);
-            if (lane == leader) {
-              found = true;
-              par = pu;
-            }
-            break;
+    }
+    // Rows still open are walked as one concatenated edge list per word,
+    // 64 edges per round spread over the lanes; a row leaves the list at
+    // its first frontier hit.
+    for (;;) {
+      int rem[G], ex[G], tot[G];
+      bool more = false;
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        rem[q] = (cand[q] && !found[q]) ? e[q] - j[q] : 0;
+        ex[q] = wave_excl_scan(rem[q], &tot[q]);
+        more |= tot[q] > 0;
+      }
+      if (!more) break;  // wave-uniform
+      int uu[G];
+      bool hit[G];
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        // owner of list position `lane`: the last lane whose list starts at
+        // or before it (later lanes with empty rows start after it)
+        int own = 0;
+#pragma unroll
+        for (int st = 32; st > 0; st >>= 1) {
+          const int c = own + st;
+          const int exc = __shfl(ex[q], c < kWave ? c : kWave - 1, kWave);
+          if (c < kWave && exc <= lane) own = c;
+        }
+        const int jo = __shfl(j[q], own, kWave);
+        const int eo = __shfl(ex[q], own, kWave);
+        const bool act = lane < tot[q];
+        uu[q] = act ? g.in_idx[jo + (lane - eo)] : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < G; ++q) hit[q] = lane < tot[q] && cur.test(uu[q]);
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const unsigned long long hm = __ballot(hit[q]);
+        // this lane's positions in the round: [a, b)
+        const int a = ex[q], b = min(kWave, ex[q] + rem[q]);
+        const bool mine = rem[q] > 0 && a < kWave;
+        unsigned long long span = 0ull;
+        if (mine) {
+          const unsigned long long hi = b >= kWave ? ~0ull : ((1ull << b) - 1ull);
+          span = hi & ~((1ull << a) - 1ull);
+        }
+        const unsigned long long mh = hm & span;
+        const int first = mh ? __ffsll((long long)mh) - 1 : 0;
+        const int pu = __shfl(uu[q], first, kWave);
+        if (mine) {
+          if (mh) {
+            found[q] = true;
+            par[q] = pu;
+            work += first - a + 1;
+          } else {
+            work += b - a;
+            j[q] += b - a;
           }
         }
       }
     }
-    const unsigned long long fm = __ballot(found);
-    if (found) {
-      b.level[v] = l1;
-      if (b.parent) b.parent[v] = par;
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      const int w = wb + q * nwaves;
+      if (w >= W) break;  // wave-uniform
+      const int v = (w << 6) + lane;
+      const unsigned long long fm = __ballot(found[q]);
+      if (found[q]) {
+        b.level[v] = l1;
+        if (b.parent) b.parent[v] = par[q];
+      }
+      if (nxt.bm) {
+        nxt.bm[v] = found[q] ? 1 : 0;  // the bool map is padded to whole words
+      } else if (lane == 0) {
+        nxt.bv[w] = fm;
+      }
+      if (lane == 0) b.vis[w] = vw[q] | fm;
     }
-    if (nxt.bm) {
-      nxt.bm[v] = found ? 1 : 0;  // the bool map is padded to whole words
-    } else if (lane == 0) {
-      nxt.bv[w] = fm;
-    }
-    if (lane == 0) b.vis[w] = vw | fm;
   }
   return work;
 }
@@ -264,6 +326,12 @@ __device__ long long cc_pull(const CcArgs& c, int* lds) {
   long long work = 0;
   const RowBlocks& rb = c.rows;
   const int32_t* cur = c.cur;
+  // In the first round every label is still the vertex id, so a
+  // neighbour's label is its id and nothing needs gathering.  (A neighbour
+  // outside the frontier cannot lower a label, but testing the frontier bit
+  // before the gather measured slower than gathering every label.)
+  const bool ids = c.ctl->steps == 1;
+  auto label_of = [cur, ids](int u) -> int { return ids ? u : cur[u]; };
   auto finish = [&](int v, int mn) {
     const int lv = cur[v];
     const int x = mn < lv ? mn : lv;
@@ -277,7 +345,7 @@ __device__ long long cc_pull(const CcArgs& c, int* lds) {
     if (threadIdx.x == 0) work += ne;
     if (ne > kCcCapE) {  // one long row: workgroup-wide minimum
       int mn = 0x7fffffff;
-      for (int e = e0 + (int)threadIdx.x; e < e1; e += BT) mn = min(mn, cur[rb.idx[e]]);
+      for (int e = e0 + (int)threadIdx.x; e < e1; e += BT) mn = min(mn, label_of(rb.idx[e]));
       mn = wave_min(mn);
       if (__lane_id() == 0) red[threadIdx.x / kWave] = mn;
       __syncthreads();
@@ -288,7 +356,7 @@ __device__ long long cc_pull(const CcArgs& c, int* lds) {
       __syncthreads();
       continue;
     }
-    gather_block<BT, int>(rb.idx, e0, ne, lds_val, [cur](int u) { return cur[u]; });
+    gather_block<BT, int>(rb.idx, e0, ne, lds_val, label_of);
     for (int k = threadIdx.x; k <= nr; k += BT) lds_off[k] = rb.off[kb + k] - e0;
     __syncthreads();
     int tpv = 1;
@@ -381,7 +449,7 @@ __global__ __launch_bounds__(1024) void k_decide_sssp(FrontierArgs f, SsspArgs s
     const int k = c->steps;
     if (prev == MODE_SSSP_RELAX) {
       c->far_count += pa;  // far members added by the relaxation
-      if (k > 0 && k <= kMaxLog) c->log[k - 1].edges = pc;
+      if (k > 0 && k <= kMaxLog) c->host->log[k - 1].edges = pc;
       c->edges_examined += pc;
     } else if (prev == MODE_SSSP_SPLIT) {
       c->far_count = pa;   // far members kept by the split
@@ -393,7 +461,7 @@ __global__ __launch_bounds__(1024) void k_decide_sssp(FrontierArgs f, SsspArgs s
       host_flag(&c->host->overflow, 1);
       host_flag(&c->host->done, 1);
     } else if (tot.members > 0) {
-      if (k < kMaxLog) c->log[k] = StepLog{GI_DIR_SPARSE_PUSH, (int)tot.members, tot.degsum, 0};
+      if (k < kMaxLog) c->host->log[k] = StepLog{GI_DIR_SPARSE_PUSH, (int)tot.members, tot.degsum, 0};
       c->steps = k + 1;
       c->nf = tot.members;
       mode = MODE_SSSP_RELAX;
@@ -401,8 +469,7 @@ __global__ __launch_bounds__(1024) void k_decide_sssp(FrontierArgs f, SsspArgs s
       mode = MODE_SSSP_SPLIT;
     } else {
       c->done = 1;
-      host_flag(&c->host->steps, k);
-      host_flag(&c->host->done, 1);
+      publish_done(c, k);
     }
     c->mode = mode;
     s_mode = mode;
@@ -558,6 +625,7 @@ __global__ void k_ctl_init(Control* c, HostFlags* host, unsigned long long delta
   c->sa_count = 0;
   c->sa_slots = 0;
   c->nchunks = 0;
+  c->chunk = kMinChunk;
   c->edges_examined = 0;
   c->thresh = delta;
   c->told = 0;

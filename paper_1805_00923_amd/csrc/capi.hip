@@ -105,7 +105,6 @@ struct gi_graph {
   long long* excl = nullptr;
   int32_t* chunk_item = nullptr;
   Control* ctl = nullptr;
-  Control* h_ctl = nullptr;    // host copy of the control block (trace)
   HostFlags* hflags = nullptr; // pinned, written by the decide kernels
   HostFlags* dflags = nullptr; // device address of hflags
   Engine eng{};
@@ -457,7 +456,6 @@ extern "C" gi_status gi_graph_destroy(gi_graph* g) {
   (void)hipDeviceSynchronize();
   free_list(g->sched_allocs);
   free_list(g->allocs);
-  if (g->h_ctl) (void)hipHostFree(g->h_ctl);
   if (g->hflags) (void)hipHostFree(g->hflags);
   for (hipEvent_t e : g->ev)
     if (e) (void)hipEventDestroy(e);
@@ -598,7 +596,9 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
     G_UP(in_off ? in_w : t_w.data(), g->in_w, 4 * M);
   }
   // frontier-loop workspace
-  const size_t nchunk = (2 * M) / (size_t)expand_chunk_size() + 2;
+  // chunks of at least kMinChunk slots, at most kParts of them below the
+  // largest chunk size
+  const size_t nchunk = std::max((2 * M) / (size_t)expand_chunk_size(), (size_t)kParts) + 2;
   for (int k = 0; k < 2; ++k) {
     G_ALLOC(g->fbv[k], W);
     G_ALLOC(g->fbm[k], W * 64);
@@ -631,13 +631,7 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
   }
 #undef G_ALLOC
 #undef G_UP
-  if (hipHostMalloc((void**)&g->h_ctl, sizeof(Control), hipHostMallocDefault) != hipSuccess) {
-    (void)hipGetLastError();
-    g->h_ctl = nullptr;
-    gi_graph_destroy(g);
-    return fail(GI_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
-  }
-  std::memset(g->h_ctl, 0, sizeof(Control));
+
   if (hipHostMalloc((void**)&g->hflags, sizeof(HostFlags),
                     hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
       hipHostGetDevicePointer((void**)&g->dflags, g->hflags, 0) != hipSuccess) {
@@ -717,8 +711,11 @@ static const StepEvents* step_events(gi_graph* g, long long k) {
   if (!g->step_timing || k >= kMaxLog || g->timing_failed) return nullptr;
   while ((long long)g->tev.size() <= k) {
     StepEvents t{nullptr, nullptr, nullptr};
-    if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.main) != hipSuccess ||
-        hipEventCreate(&t.end) != hipSuccess) {
+    // timing-only events: no system-scope cache writeback at each record
+    const unsigned fl = hipEventDisableSystemFence;
+    if (hipEventCreateWithFlags(&t.start, fl) != hipSuccess ||
+        hipEventCreateWithFlags(&t.main, fl) != hipSuccess ||
+        hipEventCreateWithFlags(&t.end, fl) != hipSuccess) {
       (void)hipGetLastError();
       for (hipEvent_t e : {t.start, t.main, t.end})
         if (e) (void)hipEventDestroy(e);
@@ -731,25 +728,20 @@ static const StepEvents* step_events(gi_graph* g, long long k) {
   return &g->tev[(size_t)k];
 }
 
-static gi_status read_loop_stats(gi_graph* g, int alg, hipStream_t s) {
-  const int hsteps = ((const volatile HostFlags*)g->hflags)->steps;
-  const int steps = std::min(hsteps, kMaxLog);
-  const size_t bytes = offsetof(Control, log) + sizeof(StepLog) * (size_t)std::max(steps, 0);
-  HIP_TRY(hipMemcpyAsync(g->h_ctl, g->ctl, bytes, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  const Control& c = *g->h_ctl;
+static gi_status read_loop_stats(gi_graph* g, int alg) {
+  const volatile HostFlags* h = g->hflags;
   gi_run_stats& r = g->stats;
   r.algorithm = alg;
-  r.steps = c.steps;
-  r.dense_steps = c.dense_steps;
-  r.edges_examined = (int64_t)c.edges_examined;
-  r.trace_len = std::min(c.steps, GI_MAX_TRACE);
-  g->last_steps[alg] = c.steps;
+  r.steps = h->steps;
+  r.dense_steps = h->dense_steps;
+  r.edges_examined = (int64_t)h->edges_examined;
+  r.trace_len = std::min(r.steps, GI_MAX_TRACE);
+  g->last_steps[alg] = r.steps;
   for (int i = 0; i < r.trace_len; ++i) {
-    r.step_direction[i] = (int8_t)c.log[i].dir;
-    r.step_frontier[i] = c.log[i].frontier;
-    r.step_degree_sum[i] = c.log[i].degsum;
-    r.step_edges[i] = c.log[i].edges;
+    r.step_direction[i] = (int8_t)h->log[i].dir;
+    r.step_frontier[i] = h->log[i].frontier;
+    r.step_degree_sum[i] = h->log[i].degsum;
+    r.step_edges[i] = h->log[i].edges;
   }
   return GI_OK;
 }
@@ -826,7 +818,7 @@ static gi_status run_frontier_loop(gi_graph* g, hipStream_t s, int alg, int dflt
 // Reset the control block and the pinned flags before a run.
 static gi_status start_run(gi_graph* g, unsigned long long delta, hipStream_t s) {
   HIP_TRY(hipStreamSynchronize(s));
-  std::memset((void*)g->hflags, 0, sizeof(HostFlags));
+  std::memset((void*)g->hflags, 0, offsetof(HostFlags, log));
   LAUNCH_TRY(launch_ctl_init(g->ctl, g->dflags, delta, s));
   return GI_OK;
 }
@@ -935,7 +927,7 @@ extern "C" gi_status gi_bfs(gi_graph* g, int32_t src, int32_t* level, int32_t* p
       },
       "BFS");
   if (st != GI_OK) return st;
-  return read_loop_stats(g, ALG_BFS, s);
+  return read_loop_stats(g, ALG_BFS);
 }
 
 // Symmetric adjacency for CC, built on the device on first use.
@@ -991,7 +983,7 @@ extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
       },
       "CC");
   if (st != GI_OK) return st;
-  st = read_loop_stats(g, ALG_CC, s);
+  st = read_loop_stats(g, ALG_CC);
   if (st != GI_OK) return st;
   // after `steps` rounds the labels sit in labs[steps & 1]
   if (g->stats.steps & 1) {
@@ -1032,7 +1024,7 @@ extern "C" gi_status gi_sssp(gi_graph* g, int32_t src, uint32_t* dist, void* str
       "SSSP");
   if (st != GI_OK) return st;
   if (((const volatile HostFlags*)g->hflags)->overflow) return fail(GI_ERR_OVERFLOW, "a distance reached UINT32_MAX");
-  st = read_loop_stats(g, ALG_SSSP, s);
+  st = read_loop_stats(g, ALG_SSSP);
   g->stats.dense_steps = 0;
   return st;
 }

@@ -26,6 +26,7 @@ constexpr int kParts = 2048;     // step kernels run exactly this many workgroup
                                  // one statistics slot each
 constexpr int kMaxCount = 2048;  // at most this many count/write workgroups
 constexpr int kMaxLog = 4096;    // per-step trace entries
+constexpr int kMinChunk = 256;   // smallest expansion chunk (slots)
 
 // ---------------------------------------------------------------------------
 // Device-side adjacency.  CSR rows (out-edges) and CSC rows (in-edges) are
@@ -71,13 +72,18 @@ struct StepLog {
   long long edges;  // edges the step examined
 };
 
-// Flags the host polls between batches; pinned host memory written by the
-// decide kernels, so no copy is needed to see them.
+// Completion flags and the per-step trace, in pinned host memory written by
+// the decide kernels: the host reads them after the batch event without a
+// device-to-host copy.
 struct HostFlags {
   int done;
   int error;
   int overflow;
-  int steps;
+  int steps;            // steps executed (valid once done)
+  int dense_steps;      // valid once done
+  int pad;
+  long long edges_examined;  // valid once done
+  StepLog log[kMaxLog];
 };
 
 // Control block of one algorithm run (device memory).
@@ -99,14 +105,22 @@ struct Control {
   int overflow;
   int buckets;
   int error;          // an internal size invariant failed (the run is abandoned)
-  int pad;
-  HostFlags* host;    // device address of the pinned host flags
-  StepLog log[kMaxLog];
+  int chunk;          // slots per expansion chunk of the current sparse step
+  HostFlags* host;    // device address of the pinned host flags and trace
 };
 
 // Publish a flag to the pinned host copy.
 __device__ __forceinline__ void host_flag(int* p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Completion: the run's totals, then the flag the host polls.
+__device__ __forceinline__ void publish_done(Control* c, int steps) {
+  HostFlags* h = c->host;
+  h->dense_steps = c->dense_steps;
+  h->edges_examined = c->edges_examined;
+  host_flag(&h->steps, steps);
+  host_flag(&h->done, 1);
 }
 
 // ---------------------------------------------------------------------------

@@ -177,7 +177,12 @@ __device__ __forceinline__ long long reduce_parts(const Part* part, int field) {
 template <int CH>
 __device__ bool scan_blk(const FrontierArgs& a, const Blk& tot) {
   __shared__ long long sc[1024], sd[1024];
-  const long long nch = (tot.slots + CH - 1) / CH;
+  // chunk size: the smallest power of two in [kMinChunk, CH] that needs at
+  // most kParts chunks, so that a small step still spreads over the grid
+  // with one or two slots per thread
+  int cs = kMinChunk;
+  while (cs < CH && (long long)cs * kParts < tot.slots) cs <<= 1;
+  const long long nch = (tot.slots + cs - 1) / cs;
   if (tot.items < 0 || tot.items > a.n || nch + 1 > a.chunk_cap) return false;
   const int t = threadIdx.x;
   const int per = (a.cgrid + 1023) / 1024;
@@ -209,6 +214,7 @@ __device__ bool scan_blk(const FrontierArgs& a, const Blk& tot) {
     a.ctl->sa_count = tot.items;
     a.ctl->sa_slots = tot.slots;
     a.ctl->nchunks = nch;
+    a.ctl->chunk = cs;
     a.chunk_item[nch] = (int)tot.items;  // sentinel
   }
   return true;
@@ -220,6 +226,7 @@ template <int BT, int CH>
 __device__ void write_body(const FrontierArgs& a) {
   const int W = (a.n + 63) >> 6;
   const int w0 = blockIdx.x * a.tw, w1 = min(W, w0 + a.tw);
+  const long long cs = a.ctl->chunk;
   long long run_c = a.blk[blockIdx.x].items, run_d = a.blk[blockIdx.x].slots;
   for (int base = w0; base < w1; base += BT) {
     const int w = base + (int)threadIdx.x;
@@ -245,7 +252,7 @@ __device__ void write_body(const FrontierArgs& a) {
       a.ids[pc] = v;
       a.excl[pc] = pd;
       // chunks whose first slot falls in [pd, pd + dv) start at this item
-      for (long long k = (pd + CH - 1) / CH; k * CH < pd + dv; ++k) a.chunk_item[k] = (int)pc;
+      for (long long k = (pd + cs - 1) / cs; k * cs < pd + dv; ++k) a.chunk_item[k] = (int)pc;
       ++pc;
       pd += dv;
     }
@@ -262,9 +269,10 @@ __global__ __launch_bounds__(BT) void k_write(FrontierArgs a, int active_mode) {
 
 // ------------------------------------------------ edge-balanced expansion --
 //
-// Slots [c*CH, (c+1)*CH) of the frontier's edges belong to chunk c; its items
-// are [chunk_item[c], chunk_item[c+1]] (each item owns >= 1 slot, so at most
-// CH+1 items).  The items' (vertex, first slot, row start) are staged in LDS,
+// Slots [c*cs, (c+1)*cs) of the frontier's edges belong to chunk c, where
+// the chunk size cs <= CH was chosen by the scan; its items are
+// [chunk_item[c], chunk_item[c+1]] (each item owns >= 1 slot, so at most
+// cs+1 items).  The items' (vertex, first slot, row start) are staged in LDS,
 // then each thread binary-searches its slots.  vis(u, e, valid) is called by
 // whole workgroups; `valid` is false for padding lanes.
 
@@ -287,10 +295,11 @@ __device__ void expand_chunks(const ExpandArgs& a, Visit& vis, int* lds) {
   int* s_row = lds + 2 * (CH + 1);
   const long long nch = a.ctl->nchunks;
   const long long slots = a.ctl->sa_slots;
+  const long long cs = a.ctl->chunk;
   const int last = (int)a.ctl->sa_count - 1;
   for (long long c = blockIdx.x; c < nch; c += gridDim.x) {
-    const long long s0 = c * CH;
-    const int s_end = (int)min((long long)CH, slots - s0);
+    const long long s0 = c * cs;
+    const int s_end = (int)min(cs, slots - s0);
     const int i0 = a.chunk_item[c];
     const int ni = min(a.chunk_item[c + 1], last) - i0 + 1;
     for (int k = threadIdx.x; k < ni; k += BT) {

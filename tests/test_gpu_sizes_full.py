@@ -29,7 +29,7 @@ def rmat22():
 
 def test_rmat22_bfs_sampled_sources():
     el, g, og = rmat22()
-    g.set_schedule(direction=3, dense_frontier=1, hybrid_divisor=20)
+    g.set_schedule(direction=3, dense_frontier=0, hybrid_divisor=20)  # bitvector
     g.set_step_timing(True)
     srcs = gg.pick_sources(el, 64, 3)
     # first, middle and last of the 64 benchmark sources
@@ -45,7 +45,7 @@ def test_rmat22_bfs_sampled_sources():
 
 def test_rmat22_cc():
     el, g, og = rmat22()
-    g.set_schedule(direction=3, dense_frontier=1, hybrid_divisor=20)
+    g.set_schedule(direction=3, dense_frontier=0, hybrid_divisor=20)  # bitvector
     say("rmat22 cc")
     lab = run_cc(g)
     ref, rounds = oracle.cc(og)
