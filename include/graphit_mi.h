@@ -228,7 +228,7 @@ gi_status gi_sssp(gi_graph* g, int32_t src, uint32_t* dist, void* stream);
 gi_status gi_get_run_stats(const gi_graph* g, gi_run_stats* out);
 
 /* Per-step timing, the cost record that schedule tuning needs (the paper's
- * autotuner, section 5, times whole runs; this times every edgeset.apply
+ * autotuner, section 6.4, times whole runs; this times every edgeset.apply
  * step).  When enabled, each later call records HIP events on its stream
  * around every step it enqueues (one step = one PageRank iteration, or one
  * frontier step of BFS/CC/SSSP, counting the no-op steps enqueued after the

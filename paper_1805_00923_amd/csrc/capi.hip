@@ -370,10 +370,10 @@ static gi_status apply_schedule(gi_graph* g, const gi_schedule& s) {
   if (s.pull_block_edges > 0) {
     g->pr_cap_e = s.pull_block_edges;
   } else {
-    // about 8 destination blocks per CU-slot of work: m / 8192 edges per
-    // block, as a power of two in [256, 2048]
+    // about 2048 destination blocks (eight per CU): the power of two in
+    // [256, 2048] nearest above m / 2048 edges per block
     int cap = 256;
-    while (cap < 2048 && (int64_t)cap * 2 * 8192 <= g->m) cap *= 2;
+    while (cap < 2048 && (int64_t)cap * 2048 < g->m) cap *= 2;
     g->pr_cap_e = cap;
   }
   g->pr_cap_v = std::min(g->pr_cap_e, 1024);
