@@ -55,7 +55,10 @@ enum {
   GI_DIR_DENSE_PUSH = 1,             /* all vertices, dense frontier test, out-edges    */
   GI_DIR_DENSE_PULL = 2,             /* all vertices, in-edges, no atomics              */
   GI_DIR_DENSE_PULL_SPARSE_PUSH = 3, /* per step: DensePull if frontier is large        */
-  GI_DIR_DENSE_PUSH_SPARSE_PUSH = 4  /* per step: DensePush if frontier is large        */
+  GI_DIR_DENSE_PUSH_SPARSE_PUSH = 4, /* per step: DensePush if frontier is large        */
+  GI_DIR_LEARNED = 5                 /* per step: the attached selector's choice among
+                                        SparsePush, DensePush and DensePull (BFS, CC);
+                                        PageRank: unsegmented or segmented DensePull  */
 };
 
 /* Dense vertexset representation: configApplyDenseVertexSet options. */
@@ -78,10 +81,13 @@ enum { GI_SEG_FIXED_VERTEX_COUNT = 0, GI_SEG_EDGE_AWARE_VERTEX_COUNT = 1 };
  *   steps_per_sync   frontier loops (BFS, CC, SSSP) enqueue this many
  *                    steps before reading the completion flag back; steps
  *                    after completion return at once (0 = library default:
- *                    8, or 64 for SSSP).  Directions are always decided on
- *                    the device.
+ *                    first batch one step longer than the previous run of
+ *                    the same algorithm on this graph, then 8 (64 for
+ *                    SSSP) with two batches in flight).  Directions are
+ *                    always decided on the device.
  *   pull_block_edges PageRank DensePull: in-edges staged in LDS per
- *                    destination block, 64..8192 (0 = library default 2048)
+ *                    destination block, 64..8192 (0 = library default: the
+ *                    power of two in [256, 2048] nearest above m / 2048)
  *   block_threads    threads per workgroup of the PageRank DensePull
  *                    kernel: 64, 128, 256 or 512 (0 = library default 256)
  *   sssp_delta       bucket width of delta-stepping (0 = library default)
@@ -243,6 +249,95 @@ gi_status gi_set_step_timing(gi_graph* g, int32_t enable);
  * Errors: INVALID_ARG (NULL count, cap < 0, NULL arrays with cap > 0), DEVICE. */
 gi_status gi_get_step_times(const gi_graph* g, float* step_ms, float* main_ms, int32_t cap,
                             int32_t* count);
+
+/* ---- learned schedule selector ------------------------------------------ */
+/* A multilayer perceptron 12 -> 64 -> 64 -> 4 (ReLU) predicting the natural
+ * log of the time in ms of the next step under each of four schedules:
+ *   S0 SparsePush, S1 DensePush, S2 DensePull, S3 DensePull over segments.
+ * It stands in for the hybrid rule's fixed threshold (section 2) and is
+ * trained on the per-step timings the library records (the paper's
+ * autotuner, section 6.4, searches whole-run timings instead).  Training
+ * runs on the device in FP32 (mean squared error on log-time over the valid
+ * schedules, Adam); inference inside a run uses BF16 weights with FP32
+ * accumulation.  Parameters, row-major fp32:
+ *   W1[12][64] b1[64] W2[64][64] b2[64] W3[64][4] b3[4]
+ * Features are standardised as (x - mu) / sd before the first layer.
+ *
+ * Step features (one row of 12 floats per step):
+ *   0 log2 n            1 log2 E (E = m; 2m for CC)   2 E / n
+ *   3 log2(1 + max degree)   4 degree coefficient of variation (out-degree;
+ *     out+in degree for CC)   5 |F| / n   6 sum deg(F) / E
+ *   7 BFS: fraction of vertices not yet visited after this step's frontier;
+ *     CC, PageRank: sum deg(F) / E
+ *   8 log2(1 + |F|)     9 log2(1 + sum deg(F))
+ *   10 |F_k| / max(1, |F_{k-1}|) clipped to [0, 64] (PageRank: 1)
+ *   11 algorithm: BFS 0, CC 0.5, PageRank 1 */
+#define GI_SEL_FEATURES 12
+#define GI_SEL_SCHEDULES 4
+#define GI_SEL_PARAMS 5252
+
+enum { GI_ALG_PAGERANK = 0, GI_ALG_BFS = 1, GI_ALG_CC = 2 };
+
+typedef struct gi_selector gi_selector;
+
+/* New selector with weights drawn He-uniform from a counter-based stream
+ * (seed), zero biases, mu = 0, sd = 1.  Errors: INVALID_ARG, OUT_OF_MEMORY. */
+gi_status gi_selector_create(uint64_t seed, gi_selector** out);
+gi_status gi_selector_destroy(gi_selector* s);
+
+/* Host copies of the parameters (GI_SEL_PARAMS floats) and of the feature
+ * standardisation (GI_SEL_FEATURES floats each); any pointer may be NULL. */
+gi_status gi_selector_get_params(const gi_selector* s, float* params, float* mu, float* sd);
+/* Replace them (NULL leaves that part unchanged; sd entries must be > 0).
+ * Resets the Adam moments.  Errors: INVALID_ARG. */
+gi_status gi_selector_set_params(gi_selector* s, const float* params, const float* mu,
+                                 const float* sd);
+
+/* Train on `count` host records: feats[count][12], log_ms[count][4],
+ * valid[count][4] (nonzero where the schedule was timed; rows need at least
+ * one).  Minibatches of 32 records in a seeded order (the same order every
+ * epoch); one device launch runs all epochs.  If standardise is nonzero, mu
+ * and sd are first set from the records (sd of a constant feature = 1).
+ * loss (host, may be NULL) receives the mean loss of each epoch.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+gi_status gi_selector_train(gi_selector* s, const float* feats, const float* log_ms,
+                            const uint8_t* valid, int64_t count, int32_t epochs, float lr,
+                            uint64_t seed, int32_t standardise, float* loss);
+
+/* Gradient of the loss of one minibatch (1 <= count <= 32 host records)
+ * with respect to the parameters, without updating them (host out,
+ * GI_SEL_PARAMS floats), and the loss.  Errors: INVALID_ARG, DEVICE. */
+gi_status gi_selector_gradient(gi_selector* s, const float* feats, const float* log_ms,
+                               const uint8_t* valid, int32_t count, float* grad, float* loss);
+
+/* Predicted log-times (host out, count x 4) for host feature rows, by the
+ * device inference kernel with FP32 (bf16 = 0) or BF16 (bf16 = 1) weights.
+ * Errors: INVALID_ARG, DEVICE. */
+gi_status gi_selector_predict(const gi_selector* s, const float* feats, int64_t count,
+                              int32_t bf16, float* out);
+
+/* Attach a copy of the selector's current weights to g for
+ * GI_DIR_LEARNED (NULL detaches).  Errors: INVALID_ARG, OUT_OF_MEMORY. */
+gi_status gi_selector_attach(gi_graph* g, const gi_selector* s);
+
+/* Features of the steps of the last BFS or CC call on g, as the device
+ * computed them (host out, cap x 12); *count = steps recorded.
+ * Errors: INVALID_ARG. */
+gi_status gi_get_step_features(const gi_graph* g, float* feats, int32_t cap, int32_t* count);
+
+/* Exhaustive per-step timing for selector training.  Runs `algorithm` on g
+ * once per schedule S0..S3 that it offers, with per-step timing on (BFS and
+ * CC: S0, S1, S2 with a bitvector frontier; PageRank, 20 iterations: S2 and
+ * S3 with the graph's num_segments, or n*4/2 MiB segments when that is 1).
+ * The frontiers of BFS and of synchronous CC do not depend on the schedule,
+ * so step k of every run meets the same frontier (checked: a mismatch is
+ * GI_ERR_DEVICE).  Writes per step k < min(cap, *count): feats[k][12],
+ * step_ms[k][4] (whole step: count, decide, compaction and traversal
+ * kernels), valid[k][4].  The graph's schedule is restored afterwards.
+ * src: BFS source (ignored otherwise).  Scratch outputs are allocated and
+ * freed inside.  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+gi_status gi_trace_exhaustive(gi_graph* g, int32_t algorithm, int32_t src, float* feats,
+                              float* step_ms, uint8_t* valid, int32_t cap, int32_t* count);
 
 /* ---- frontier primitives (device, stream ordered) -------------------- */
 /* Dense and sparse vertexset representations (section 2, direction

@@ -28,13 +28,21 @@ DENSE_PUSH = 1
 DENSE_PULL = 2
 DENSE_PULL_SPARSE_PUSH = 3
 DENSE_PUSH_SPARSE_PUSH = 4
+LEARNED = 5
 DIRECTIONS = {
     "SparsePush": SPARSE_PUSH,
     "DensePush": DENSE_PUSH,
     "DensePull": DENSE_PULL,
     "DensePull-SparsePush": DENSE_PULL_SPARSE_PUSH,
     "DensePush-SparsePush": DENSE_PUSH_SPARSE_PUSH,
+    "Learned": LEARNED,
 }
+ALG_PAGERANK = 0
+ALG_BFS = 1
+ALG_CC = 2
+SEL_FEATURES = 12
+SEL_SCHEDULES = 4
+SEL_PARAMS = 5252
 BITVECTOR = 0
 BOOLMAP = 1
 FIXED_VERTEX_COUNT = 0
@@ -99,6 +107,17 @@ _SIGS = {
     "gi_sssp": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
     "gi_get_run_stats": (ctypes.c_int, [_vp, _vp]),
     "gi_set_step_timing": (ctypes.c_int, [_vp, _i32]),
+    "gi_selector_create": (ctypes.c_int, [ctypes.c_uint64, _vp]),
+    "gi_selector_destroy": (ctypes.c_int, [_vp]),
+    "gi_selector_get_params": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "gi_selector_set_params": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "gi_selector_train": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, ctypes.c_float,
+                                         ctypes.c_uint64, _i32, _vp]),
+    "gi_selector_gradient": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _vp, _vp]),
+    "gi_selector_predict": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp]),
+    "gi_selector_attach": (ctypes.c_int, [_vp, _vp]),
+    "gi_get_step_features": (ctypes.c_int, [_vp, _vp, _i32, _vp]),
+    "gi_trace_exhaustive": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i32, _vp]),
     "gi_get_step_times": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp]),
     "gi_frontier_sparse_to_bitvec": (ctypes.c_int, [_i32, _vp, _i32, _vp, _vp]),
     "gi_frontier_bitvec_to_sparse": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp]),
@@ -264,6 +283,30 @@ class Graph:
         _check(lib.gi_get_run_stats(self._h, ctypes.byref(r)))
         return r
 
+    def attach_selector(self, sel):
+        """Attach a copy of a Selector's weights (None detaches)."""
+        _check(lib.gi_selector_attach(self._h, None if sel is None else sel._h))
+
+    def step_features(self):
+        """float32 [steps, 12]: selector features of the last BFS/CC call."""
+        cnt = ctypes.c_int32()
+        _check(lib.gi_get_step_features(self._h, None, 0, ctypes.byref(cnt)))
+        out = np.zeros((max(cnt.value, 1), SEL_FEATURES), np.float32)
+        _check(lib.gi_get_step_features(self._h, out.ctypes.data, cnt.value, ctypes.byref(cnt)))
+        return out[:cnt.value]
+
+    def trace_exhaustive(self, algorithm, src=0, cap=MAX_TRACE):
+        """Per-step features, whole-step times of S0..S3 (ms) and validity
+        mask of one run per offered schedule."""
+        f = np.zeros((cap, SEL_FEATURES), np.float32)
+        t = np.zeros((cap, SEL_SCHEDULES), np.float32)
+        v = np.zeros((cap, SEL_SCHEDULES), np.uint8)
+        cnt = ctypes.c_int32()
+        _check(lib.gi_trace_exhaustive(self._h, int(algorithm), int(src), f.ctypes.data,
+                                       t.ctypes.data, v.ctypes.data, cap, ctypes.byref(cnt)))
+        k = min(cnt.value, cap)
+        return f[:k], t[:k], v[:k]
+
     def set_step_timing(self, enable=True):
         _check(lib.gi_set_step_timing(self._h, 1 if enable else 0))
 
@@ -320,3 +363,66 @@ def bitvec_to_boolmap(n, bv, bm, stream=None):
 def boolmap_to_bitvec(n, bm, bv, stream=None):
     _check(lib.gi_frontier_boolmap_to_bitvec(int(n), _dptr(bm), _dptr(bv), _stream(stream)))
     return bv
+
+
+class Selector:
+    """Learned schedule selector (MLP 12 -> 64 -> 64 -> 4) trained and
+    evaluated by the library's device kernels."""
+
+    def __init__(self, seed=1):
+        self._h = ctypes.c_void_p(None)
+        _check(lib.gi_selector_create(int(seed), ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            lib.gi_selector_destroy(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        p = np.zeros(SEL_PARAMS, np.float32)
+        mu = np.zeros(SEL_FEATURES, np.float32)
+        sd = np.zeros(SEL_FEATURES, np.float32)
+        _check(lib.gi_selector_get_params(self._h, p.ctypes.data, mu.ctypes.data, sd.ctypes.data))
+        return p, mu, sd
+
+    def set_params(self, params=None, mu=None, sd=None):
+        arrs = [None if a is None else np.ascontiguousarray(a, np.float32) for a in (params, mu, sd)]
+        _check(lib.gi_selector_set_params(self._h, *[_hptr(a) for a in arrs]))
+
+    @staticmethod
+    def _records(feats, log_ms, valid):
+        f = np.ascontiguousarray(feats, np.float32).reshape(-1, SEL_FEATURES)
+        y = np.ascontiguousarray(log_ms, np.float32).reshape(-1, SEL_SCHEDULES)
+        v = np.ascontiguousarray(valid, np.uint8).reshape(-1, SEL_SCHEDULES)
+        if not (f.shape[0] == y.shape[0] == v.shape[0]):
+            raise ValueError("record arrays disagree in length")
+        return f, y, v
+
+    def train(self, feats, log_ms, valid, epochs=200, lr=1e-3, seed=7, standardise=True):
+        f, y, v = self._records(feats, log_ms, valid)
+        loss = np.zeros(epochs, np.float32)
+        _check(lib.gi_selector_train(self._h, f.ctypes.data, y.ctypes.data, v.ctypes.data,
+                                     f.shape[0], int(epochs), float(lr), int(seed),
+                                     1 if standardise else 0, loss.ctypes.data))
+        return loss
+
+    def gradient(self, feats, log_ms, valid):
+        f, y, v = self._records(feats, log_ms, valid)
+        g = np.zeros(SEL_PARAMS, np.float32)
+        loss = ctypes.c_float()
+        _check(lib.gi_selector_gradient(self._h, f.ctypes.data, y.ctypes.data, v.ctypes.data,
+                                        f.shape[0], g.ctypes.data, ctypes.byref(loss)))
+        return g, float(loss.value)
+
+    def predict(self, feats, bf16=False):
+        f = np.ascontiguousarray(feats, np.float32).reshape(-1, SEL_FEATURES)
+        out = np.zeros((f.shape[0], SEL_SCHEDULES), np.float32)
+        _check(lib.gi_selector_predict(self._h, f.ctypes.data, f.shape[0], 1 if bf16 else 0,
+                                       out.ctypes.data))
+        return out

@@ -45,15 +45,19 @@ __device__ __forceinline__ void abandon(Control* c) {
 
 // Reduce the count pass, log the step that just ran, choose the direction of
 // the next one (BFS and CC), and prepare the sparse array for SparsePush.
+// Every decided step's selector features go to the host trace; with the
+// learned direction the attached selector picks the schedule of least
+// predicted time among SparsePush, DensePush and DensePull.
 __global__ __launch_bounds__(1024) void k_decide_frontier(FrontierArgs f, DecideArgs d) {
   const Blk tot = reduce_blk(f);
   const long long work = reduce_parts(d.part, 2);
-  __shared__ int s_mode;
+  __shared__ int s_mode, s_learn, s_k;
+  __shared__ float s_x[kFeat], s_xn[kFeat], s_h1[kHid], s_h2[kHid], s_y[kOut];
+  Control* c = d.ctl;
   if (threadIdx.x == 0) {
-    Control* c = d.ctl;
-    int mode = MODE_NONE;
+    int mode = MODE_NONE, learn = 0;
+    const int k = c->steps;
     if (!c->done) {
-      const int k = c->steps;
       if (k > 0) {
         if (k <= kMaxLog) c->host->log[k - 1].edges = work;
         c->edges_examined += work;
@@ -62,6 +66,11 @@ __global__ __launch_bounds__(1024) void k_decide_frontier(FrontierArgs f, Decide
         c->done = 1;
         publish_done(c, k);
       } else {
+        const float unv = d.is_bfs ? (float)(1.0 - (double)(c->visited + tot.members) / (double)f.n)
+                                   : (float)((double)tot.degsum / (double)(d.edges > 0 ? d.edges : 1));
+        step_features(d.fc, f.n, d.edges, tot.members, tot.degsum, c->nf, unv, s_x);
+        if (k < kMaxLog)
+          for (int i = 0; i < kFeat; ++i) c->host->feat[k][i] = s_x[i];
         int dir = d.direction;
         if (d.forced_dir >= 0) dir = d.forced_dir;
         else if (dir == GI_DIR_DENSE_PULL_SPARSE_PUSH)
@@ -70,16 +79,37 @@ __global__ __launch_bounds__(1024) void k_decide_frontier(FrontierArgs f, Decide
         else if (dir == GI_DIR_DENSE_PUSH_SPARSE_PUSH)
           dir = hybrid_dense(tot.members, tot.degsum, d.edges, d.divisor) ? GI_DIR_DENSE_PUSH
                                                                           : GI_DIR_SPARSE_PUSH;
-        if (k < kMaxLog) c->host->log[k] = StepLog{dir, (int)tot.members, tot.degsum, 0};
-        c->steps = k + 1;
-        if (dir != GI_DIR_SPARSE_PUSH) c->dense_steps++;
-        c->nf = tot.members;
-        c->dsum = tot.degsum;
-        mode = dir;
+        if (dir == GI_DIR_LEARNED) learn = 1;
+        else mode = dir;
       }
     }
-    c->mode = mode;
+    s_learn = learn;
     s_mode = mode;
+    s_k = k;
+  }
+  __syncthreads();
+  if (s_learn) {  // workgroup-uniform
+    mlp_forward_block(d.sel, s_x, s_xn, s_h1, s_h2, s_y);
+    if (threadIdx.x == 0) {
+      int best = GI_DIR_SPARSE_PUSH;
+      for (int q = GI_DIR_DENSE_PUSH; q <= GI_DIR_DENSE_PULL; ++q)
+        if (s_y[q] < s_y[best]) best = q;
+      s_mode = best;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int mode = s_mode;
+    if (mode >= 0) {
+      const int k = s_k;
+      if (k < kMaxLog) c->host->log[k] = StepLog{mode, (int)tot.members, tot.degsum, 0};
+      c->steps = k + 1;
+      if (mode != GI_DIR_SPARSE_PUSH) c->dense_steps++;
+      c->nf = tot.members;
+      c->dsum = tot.degsum;
+      c->visited += tot.members;
+    }
+    c->mode = mode;
   }
   __syncthreads();
   if (s_mode == MODE_SPARSE_PUSH && !scan_blk<kCH>(f, tot) && threadIdx.x == 0) abandon(d.ctl);
@@ -626,6 +656,7 @@ __global__ void k_ctl_init(Control* c, HostFlags* host, unsigned long long delta
   c->sa_slots = 0;
   c->nchunks = 0;
   c->chunk = kMinChunk;
+  c->visited = 0;
   c->edges_examined = 0;
   c->thresh = delta;
   c->told = 0;

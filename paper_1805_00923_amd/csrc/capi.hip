@@ -2,6 +2,7 @@
 // each algorithm.  Everything here is host code; the per-step work runs in
 // the kernels of bfs_cc.hip, pagerank.hip, sssp.hip and frontier.hip.
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstddef>
 #include <cstdio>
@@ -117,6 +118,11 @@ struct gi_graph {
   std::vector<StepEvents> tev;
   int tev_count = 0;        // steps of the last run that carry events
   int last_steps[4] = {0, 0, 0, 0};  // steps of the previous run, per algorithm
+  // selector features (graph level) and the attached selector
+  FeatConst fc_bfs{}, fc_cc{}, fc_pr{};
+  float* sel_p = nullptr;      // fp32 parameters, then mu[12], isd[12]
+  uint16_t* sel_wb = nullptr;  // bf16 parameters
+  float* sel_io = nullptr;     // PageRank decision: 12 features in, 4 predictions out
 };
 
 template <typename T>
@@ -291,6 +297,27 @@ static std::vector<int4> make_pr_table(const int32_t* off, int nrows, int cap_e,
   return longs;
 }
 
+// Graph-level selector features: log2 n, log2 E, E/n, log2(1 + max deg),
+// coefficient of variation of the degrees; and the algorithm id.
+static FeatConst feat_const(const int32_t* deg, int32_t n, int64_t edges, float alg) {
+  FeatConst c{};
+  double sum = 0.0, sq = 0.0;
+  int32_t mx = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    sum += deg[v];
+    sq += (double)deg[v] * deg[v];
+    mx = std::max(mx, deg[v]);
+  }
+  const double mean = sum / n, var = std::max(0.0, sq / n - mean * mean);
+  c.g[0] = (float)std::log2((double)n);
+  c.g[1] = (float)std::log2((double)std::max<int64_t>(edges, 1));
+  c.g[2] = (float)((double)edges / n);
+  c.g[3] = (float)std::log2(1.0 + mx);
+  c.g[4] = mean > 0.0 ? (float)(std::sqrt(var) / mean) : 0.0f;
+  c.alg = alg;
+  return c;
+}
+
 static gi_status upload(const void* h, void* d, size_t bytes) {
   if (bytes == 0) return GI_OK;
   HIP_TRY(hipMemcpy(d, h, bytes, hipMemcpyHostToDevice));
@@ -411,7 +438,7 @@ extern "C" gi_status gi_schedule_init(gi_schedule* s) {
 }
 
 static gi_status validate_schedule(const gi_graph* g, const gi_schedule* s) {
-  if (s->direction < GI_DIR_SPARSE_PUSH || s->direction > GI_DIR_DENSE_PUSH_SPARSE_PUSH)
+  if (s->direction < GI_DIR_SPARSE_PUSH || s->direction > GI_DIR_LEARNED)
     return fail(GI_ERR_UNSUPPORTED, "direction %d not offered", s->direction);
   if (s->dense_frontier != GI_FRONTIER_BITVECTOR && s->dense_frontier != GI_FRONTIER_BOOLMAP)
     return fail(GI_ERR_UNSUPPORTED, "dense frontier kind %d not offered", s->dense_frontier);
@@ -456,6 +483,8 @@ extern "C" gi_status gi_graph_destroy(gi_graph* g) {
   (void)hipDeviceSynchronize();
   free_list(g->sched_allocs);
   free_list(g->allocs);
+  for (void* q : {(void*)g->sel_p, (void*)g->sel_wb, (void*)g->sel_io})
+    if (q) (void)hipFree(q);
   if (g->hflags) (void)hipHostFree(g->hflags);
   for (hipEvent_t e : g->ev)
     if (e) (void)hipEventDestroy(e);
@@ -561,6 +590,9 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
     g->max_out = std::max(g->max_out, g->h_outdeg[(size_t)v]);
     h_udeg[(size_t)v] = g->h_outdeg[(size_t)v] + (g->h_in_off[(size_t)v + 1] - g->h_in_off[(size_t)v]);
   }
+  g->fc_bfs = feat_const(g->h_outdeg.data(), n, m, 0.0f);
+  g->fc_cc = feat_const(h_udeg.data(), n, 2 * m, 0.5f);
+  g->fc_pr = feat_const(g->h_outdeg.data(), n, m, 1.0f);
   (void)hipGetDevice(&g->device);
   const size_t N = (size_t)n, M = (size_t)m, W = (N + 63) / 64;
 #define G_ALLOC(ptr, cnt)                                             \
@@ -826,12 +858,58 @@ static gi_status start_run(gi_graph* g, unsigned long long delta, hipStream_t s)
 
 // ---------------------------------------------------------- algorithms ----
 
-extern "C" gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, float* ranks,
-                                 void* stream) {
-  if (!g || !ranks) return fail(GI_ERR_INVALID_ARG, "NULL argument");
-  if (iters < 0) return fail(GI_ERR_INVALID_ARG, "iters must be >= 0");
-  if (!(damping >= 0.0f && damping <= 1.0f)) return fail(GI_ERR_INVALID_ARG, "damping outside [0,1]");
-  hipStream_t s = static_cast<hipStream_t>(stream);
+static SelDev sel_dev(const gi_graph* g) {
+  SelDev d;
+  d.p = g->sel_p;
+  d.wb = g->sel_wb;
+  d.mu = g->sel_p ? g->sel_p + kParams : nullptr;
+  d.isd = g->sel_p ? g->sel_p + kParams + kFeat : nullptr;
+  return d;
+}
+
+static DecideArgs decide_args(const gi_graph* g, int alg) {
+  DecideArgs d;
+  d.part = g->part;
+  d.ctl = g->ctl;
+  d.direction = g->sched.direction;
+  d.divisor = g->sched.hybrid_divisor;
+  d.forced_dir = -1;
+  d.edges = alg == ALG_CC ? 2 * g->m : g->m;
+  d.is_bfs = alg == ALG_BFS;
+  d.fc = alg == ALG_CC ? g->fc_cc : g->fc_bfs;
+  d.sel = sel_dev(g);
+  return d;
+}
+
+static gi_status check_learned(const gi_graph* g) {
+  if (g->sched.direction == GI_DIR_LEARNED && !g->sel_p)
+    return fail(GI_ERR_INVALID_ARG, "learned direction without an attached selector");
+  return GI_OK;
+}
+
+// Segment count used when the segmented schedule is chosen without one:
+// contrib segments of at most 2 MiB (half of one XCD's L2).
+static int auto_segments(const gi_graph* g) {
+  const long long bytes = 4LL * g->n;
+  return (int)std::max<long long>(2, (bytes + (2LL << 20) - 1) / (2LL << 20));
+}
+
+// The 12 selector features of a PageRank iteration (every vertex active).
+static void pr_features(const gi_graph* g, float* x) {
+  for (int i = 0; i < 5; ++i) x[i] = g->fc_pr.g[i];
+  x[5] = 1.0f;
+  x[6] = 1.0f;
+  x[7] = 1.0f;
+  x[8] = std::log2(1.0f + (float)g->n);
+  x[9] = std::log2(1.0f + (float)g->m);
+  x[10] = 1.0f;
+  x[11] = g->fc_pr.alg;
+}
+
+// 20-iteration (or `iters`) DensePull PageRank, unsegmented or over the
+// graph's segments.
+static gi_status pr_run(gi_graph* g, int32_t iters, float damping, float* ranks, hipStream_t s,
+                        bool segmented) {
   PrVertex pv;
   pv.outdeg = g->outdeg;
   pv.alpha = (double)damping;
@@ -850,7 +928,7 @@ extern "C" gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, floa
       HIP_TRY(hipEventRecord(te->start, s));
       HIP_TRY(hipEventRecord(te->main, s));
     }
-    if (g->sched.num_segments <= 1) {
+    if (!segmented) {
       PrRows r{g->pr_table, g->pr_ntab, g->in_off, g->in_idx, nullptr, g->lr_acc, g->lr_cnt,
                g->lr_chunks};
       LAUNCH_TRY(launch_pr_rows(r, g->pr_cap_e, g->pr_cap_v, bt, 0, cin, 0, pv, cout,
@@ -888,22 +966,45 @@ extern "C" gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, floa
   return GI_OK;
 }
 
-static DecideArgs decide_args(const gi_graph* g, long long edges) {
-  DecideArgs d;
-  d.part = g->part;
-  d.ctl = g->ctl;
-  d.direction = g->sched.direction;
-  d.divisor = g->sched.hybrid_divisor;
-  d.forced_dir = -1;
-  d.edges = edges;
-  return d;
+// Segments for the segmented schedule (built on first use when the
+// schedule itself has one segment).
+static gi_status ensure_segments(gi_graph* g) {
+  if (!g->segs.empty()) return GI_OK;
+  return build_segments(g, auto_segments(g), GI_SEG_FIXED_VERTEX_COUNT);
 }
+
+extern "C" gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, float* ranks,
+                                 void* stream) {
+  if (!g || !ranks) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  if (iters < 0) return fail(GI_ERR_INVALID_ARG, "iters must be >= 0");
+  if (!(damping >= 0.0f && damping <= 1.0f)) return fail(GI_ERR_INVALID_ARG, "damping outside [0,1]");
+  gi_status st = check_learned(g);
+  if (st != GI_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  bool segmented = g->sched.num_segments > 1;
+  if (g->sched.direction == GI_DIR_LEARNED) {
+    // one inference for the whole run: every iteration meets the same state
+    float io[kFeat + kOut];
+    pr_features(g, io);
+    HIP_TRY(hipMemcpyAsync(g->sel_io, io, sizeof(float) * kFeat, hipMemcpyHostToDevice, s));
+    LAUNCH_TRY(launch_mlp_predict(sel_dev(g), g->sel_io, 1, true, g->sel_io + kFeat, s));
+    HIP_TRY(hipMemcpyAsync(io + kFeat, g->sel_io + kFeat, sizeof(float) * kOut,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    segmented = io[kFeat + 3] < io[kFeat + 2];
+    if (segmented && (st = ensure_segments(g)) != GI_OK) return st;
+  }
+  return pr_run(g, iters, damping, ranks, s, segmented);
+}
+
 
 extern "C" gi_status gi_bfs(gi_graph* g, int32_t src, int32_t* level, int32_t* parent, void* stream) {
   if (!g || !level) return fail(GI_ERR_INVALID_ARG, "NULL argument");
   if (src < 0 || src >= g->n) return fail(GI_ERR_INVALID_ARG, "source %d outside [0, %d)", src, g->n);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  gi_status st = start_run(g, 0, s);
+  gi_status st = check_learned(g);
+  if (st != GI_OK) return st;
+  st = start_run(g, 0, s);
   if (st != GI_OK) return st;
   BfsArgs b;
   b.g = dev_graph(g);
@@ -915,7 +1016,7 @@ extern "C" gi_status gi_bfs(gi_graph* g, int32_t src, int32_t* level, int32_t* p
   b.part = g->part;
   b.ctl = g->ctl;
   LAUNCH_TRY(launch_bfs_init(b, src, frontier_set(g, 0), frontier_set(g, 1), s));
-  const DecideArgs d = decide_args(g, g->m);
+  const DecideArgs d = decide_args(g, ALG_BFS);
   st = run_frontier_loop(
       g, s, ALG_BFS, 8, (long long)g->n + 2,
       [&](long long k) {
@@ -953,7 +1054,9 @@ static gi_status ensure_sym(gi_graph* g, hipStream_t s) {
 extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
   if (!g || !label) return fail(GI_ERR_INVALID_ARG, "NULL argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  gi_status st = ensure_sym(g, s);
+  gi_status st = check_learned(g);
+  if (st != GI_OK) return st;
+  st = ensure_sym(g, s);
   if (st != GI_OK) return st;
   if ((st = start_run(g, 0, s)) != GI_OK) return st;
   int32_t* labs[2] = {label, g->lab};
@@ -969,7 +1072,7 @@ extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
   c.part = g->part;
   c.ctl = g->ctl;
   LAUNCH_TRY(launch_cc_init(c, frontier_set(g, 0), frontier_set(g, 1), labs[1], s));
-  const DecideArgs d = decide_args(g, 2 * g->m);
+  const DecideArgs d = decide_args(g, ALG_CC);
   st = run_frontier_loop(
       g, s, ALG_CC, 8, (long long)g->n + 2,
       [&](long long k) {
@@ -1100,5 +1203,401 @@ extern "C" gi_status gi_frontier_degree_sum(const gi_graph* g, const int32_t* id
   if (!g || !out || count < 0 || (count > 0 && !ids))
     return fail(GI_ERR_INVALID_ARG, "bad frontier arguments");
   LAUNCH_TRY(launch_degree_sum(g->outdeg, ids, count, out, static_cast<hipStream_t>(stream)));
+  return GI_OK;
+}
+
+// ------------------------------------------------------------- selector ----
+
+struct gi_selector {
+  std::vector<float> p;   // host copy of the parameters
+  std::vector<float> mu, sd;
+  float* d_p = nullptr;   // parameters, then mu[12], isd[12]
+  float* d_m1 = nullptr;  // Adam moments
+  float* d_m2 = nullptr;
+  float* d_grad = nullptr;
+  uint16_t* d_wb = nullptr;
+  long long adam_t = 0;
+};
+
+// splitmix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014) as a counter-based stream.
+static uint64_t sel_mix(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+static uint16_t f32_to_bf16(float f) {  // round to nearest even
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Push the host parameters and standardisation to the device copies.
+static gi_status sel_upload(gi_selector* s) {
+  std::vector<float> buf(s->p);
+  for (int i = 0; i < kFeat; ++i) buf.push_back(s->mu[(size_t)i]);
+  for (int i = 0; i < kFeat; ++i) buf.push_back(1.0f / s->sd[(size_t)i]);
+  HIP_TRY(hipMemcpy(s->d_p, buf.data(), sizeof(float) * buf.size(), hipMemcpyHostToDevice));
+  std::vector<uint16_t> wb((size_t)kParams);
+  for (int i = 0; i < kParams; ++i) wb[(size_t)i] = f32_to_bf16(s->p[(size_t)i]);
+  HIP_TRY(hipMemcpy(s->d_wb, wb.data(), 2 * wb.size(), hipMemcpyHostToDevice));
+  return GI_OK;
+}
+
+static gi_status sel_reset_moments(gi_selector* s) {
+  HIP_TRY(hipMemset(s->d_m1, 0, sizeof(float) * kParams));
+  HIP_TRY(hipMemset(s->d_m2, 0, sizeof(float) * kParams));
+  s->adam_t = 0;
+  return GI_OK;
+}
+
+extern "C" gi_status gi_selector_destroy(gi_selector* s) {
+  if (!s) return GI_OK;
+  for (void* q : {(void*)s->d_p, (void*)s->d_m1, (void*)s->d_m2, (void*)s->d_grad, (void*)s->d_wb})
+    if (q) (void)hipFree(q);
+  delete s;
+  return GI_OK;
+}
+
+extern "C" gi_status gi_selector_create(uint64_t seed, gi_selector** out) {
+  if (!out) return fail(GI_ERR_INVALID_ARG, "NULL output handle");
+  *out = nullptr;
+  gi_selector* s = new (std::nothrow) gi_selector();
+  if (!s) return fail(GI_ERR_OUT_OF_MEMORY, "host allocation failed");
+  s->p.assign((size_t)kParams, 0.0f);
+  s->mu.assign((size_t)kFeat, 0.0f);
+  s->sd.assign((size_t)kFeat, 1.0f);
+  // He-uniform weights: U(-b, b), b = sqrt(6 / fan_in); zero biases
+  auto fill = [&](int off, int count, int fan_in) {
+    const double b = std::sqrt(6.0 / fan_in);
+    for (int i = 0; i < count; ++i) {
+      const double u = (double)(sel_mix(seed * 0x100000001B3ull + (uint64_t)(off + i)) >> 11) *
+                       (1.0 / 9007199254740992.0);
+      s->p[(size_t)(off + i)] = (float)((2.0 * u - 1.0) * b);
+    }
+  };
+  fill(kOffW1, kFeat * kHid, kFeat);
+  fill(kOffW2, kHid * kHid, kHid);
+  fill(kOffW3, kHid * kOut, kHid);
+  if (hipMalloc((void**)&s->d_p, sizeof(float) * (kParams + 2 * kFeat)) != hipSuccess ||
+      hipMalloc((void**)&s->d_m1, sizeof(float) * kParams) != hipSuccess ||
+      hipMalloc((void**)&s->d_m2, sizeof(float) * kParams) != hipSuccess ||
+      hipMalloc((void**)&s->d_grad, sizeof(float) * kParams) != hipSuccess ||
+      hipMalloc((void**)&s->d_wb, 2 * (size_t)kParams) != hipSuccess) {
+    (void)hipGetLastError();
+    gi_selector_destroy(s);
+    return fail(GI_ERR_OUT_OF_MEMORY, "selector device allocation failed");
+  }
+  gi_status st = sel_upload(s);
+  if (st == GI_OK) st = sel_reset_moments(s);
+  if (st != GI_OK) {
+    gi_selector_destroy(s);
+    return st;
+  }
+  *out = s;
+  return GI_OK;
+}
+
+extern "C" gi_status gi_selector_get_params(const gi_selector* s, float* params, float* mu,
+                                            float* sd) {
+  if (!s) return fail(GI_ERR_INVALID_ARG, "NULL selector");
+  if (params) std::memcpy(params, s->p.data(), sizeof(float) * kParams);
+  if (mu) std::memcpy(mu, s->mu.data(), sizeof(float) * kFeat);
+  if (sd) std::memcpy(sd, s->sd.data(), sizeof(float) * kFeat);
+  return GI_OK;
+}
+
+extern "C" gi_status gi_selector_set_params(gi_selector* s, const float* params, const float* mu,
+                                            const float* sd) {
+  if (!s) return fail(GI_ERR_INVALID_ARG, "NULL selector");
+  if (sd)
+    for (int i = 0; i < kFeat; ++i)
+      if (!(sd[i] > 0.0f)) return fail(GI_ERR_INVALID_ARG, "sd[%d] must be > 0", i);
+  if (params) std::memcpy(s->p.data(), params, sizeof(float) * kParams);
+  if (mu) std::memcpy(s->mu.data(), mu, sizeof(float) * kFeat);
+  if (sd) std::memcpy(s->sd.data(), sd, sizeof(float) * kFeat);
+  gi_status st = sel_upload(s);
+  return st != GI_OK ? st : sel_reset_moments(s);
+}
+
+// Device copies of training records, released on scope exit.
+struct DevRecords {
+  float* x = nullptr;
+  float* y = nullptr;
+  uint8_t* v = nullptr;
+  int32_t* order = nullptr;
+  float* loss = nullptr;
+  ~DevRecords() {
+    for (void* q : {(void*)x, (void*)y, (void*)v, (void*)order, (void*)loss})
+      if (q) (void)hipFree(q);
+  }
+};
+
+static gi_status sel_records(DevRecords& r, const float* feats, const float* log_ms,
+                             const uint8_t* valid, int64_t count, const std::vector<int32_t>& order,
+                             int loss_len) {
+  const size_t n = (size_t)count;
+  if (hipMalloc((void**)&r.x, sizeof(float) * n * kFeat) != hipSuccess ||
+      hipMalloc((void**)&r.y, sizeof(float) * n * kOut) != hipSuccess ||
+      hipMalloc((void**)&r.v, n * kOut) != hipSuccess ||
+      hipMalloc((void**)&r.order, sizeof(int32_t) * n) != hipSuccess ||
+      hipMalloc((void**)&r.loss, sizeof(float) * (size_t)std::max(loss_len, 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(GI_ERR_OUT_OF_MEMORY, "selector record allocation failed");
+  }
+  HIP_TRY(hipMemcpy(r.x, feats, sizeof(float) * n * kFeat, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(r.y, log_ms, sizeof(float) * n * kOut, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(r.v, valid, n * kOut, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(r.order, order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+  return GI_OK;
+}
+
+static gi_status sel_check_records(const float* feats, const float* log_ms, const uint8_t* valid,
+                                   int64_t count) {
+  if (!feats || !log_ms || !valid || count < 1 || count > INT32_MAX)
+    return fail(GI_ERR_INVALID_ARG, "bad selector records");
+  for (int64_t r = 0; r < count; ++r) {
+    int any = 0;
+    for (int q = 0; q < kOut; ++q) {
+      if (valid[r * kOut + q]) {
+        any = 1;
+        if (!std::isfinite(log_ms[r * kOut + q]))
+          return fail(GI_ERR_INVALID_ARG, "record %lld: non-finite target", (long long)r);
+      }
+    }
+    if (!any) return fail(GI_ERR_INVALID_ARG, "record %lld has no valid schedule", (long long)r);
+    for (int f = 0; f < kFeat; ++f)
+      if (!std::isfinite(feats[r * kFeat + f]))
+        return fail(GI_ERR_INVALID_ARG, "record %lld: non-finite feature", (long long)r);
+  }
+  return GI_OK;
+}
+
+static TrainArgs train_args(gi_selector* s, const DevRecords& r, int n, int epochs, float lr,
+                            int apply) {
+  TrainArgs a;
+  a.p = s->d_p;
+  a.m1 = s->d_m1;
+  a.m2 = s->d_m2;
+  a.grad = s->d_grad;
+  a.x = r.x;
+  a.y = r.y;
+  a.valid = r.v;
+  a.order = r.order;
+  a.n = n;
+  a.mu = s->d_p + kParams;
+  a.isd = s->d_p + kParams + kFeat;
+  a.epochs = epochs;
+  a.lr = lr;
+  a.beta1 = 0.9f;
+  a.beta2 = 0.999f;
+  a.eps = 1e-8f;
+  a.apply = apply;
+  a.t0 = s->adam_t;
+  a.loss = r.loss;
+  return a;
+}
+
+extern "C" gi_status gi_selector_train(gi_selector* s, const float* feats, const float* log_ms,
+                                       const uint8_t* valid, int64_t count, int32_t epochs,
+                                       float lr, uint64_t seed, int32_t standardise, float* loss) {
+  if (!s) return fail(GI_ERR_INVALID_ARG, "NULL selector");
+  if (epochs < 1 || !(lr > 0.0f)) return fail(GI_ERR_INVALID_ARG, "epochs >= 1 and lr > 0 required");
+  gi_status st = sel_check_records(feats, log_ms, valid, count);
+  if (st != GI_OK) return st;
+  if (standardise) {
+    for (int f = 0; f < kFeat; ++f) {
+      double sum = 0.0, sq = 0.0;
+      for (int64_t r = 0; r < count; ++r) {
+        const double x = feats[r * kFeat + f];
+        sum += x;
+        sq += x * x;
+      }
+      const double mean = sum / count, var = std::max(0.0, sq / count - mean * mean);
+      s->mu[(size_t)f] = (float)mean;
+      s->sd[(size_t)f] = var > 1e-12 ? (float)std::sqrt(var) : 1.0f;
+    }
+    if ((st = sel_upload(s)) != GI_OK) return st;
+  }
+  // seeded Fisher-Yates order (the same every epoch)
+  std::vector<int32_t> order((size_t)count);
+  for (int64_t i = 0; i < count; ++i) order[(size_t)i] = (int32_t)i;
+  for (int64_t i = count - 1; i > 0; --i) {
+    const uint64_t j = sel_mix(seed ^ (0xD1B54A32D192ED03ull * (uint64_t)i)) % (uint64_t)(i + 1);
+    std::swap(order[(size_t)i], order[(size_t)j]);
+  }
+  DevRecords r;
+  if ((st = sel_records(r, feats, log_ms, valid, count, order, epochs)) != GI_OK) return st;
+  const TrainArgs a = train_args(s, r, (int)count, epochs, lr, 1);
+  LAUNCH_TRY(launch_mlp_train(a, nullptr));
+  HIP_TRY(hipDeviceSynchronize());
+  s->adam_t += (long long)epochs * ((count + 31) / 32);
+  HIP_TRY(hipMemcpy(s->p.data(), s->d_p, sizeof(float) * kParams, hipMemcpyDeviceToHost));
+  if (loss) HIP_TRY(hipMemcpy(loss, r.loss, sizeof(float) * (size_t)epochs, hipMemcpyDeviceToHost));
+  // refresh the bf16 copy from the trained weights
+  return sel_upload(s);
+}
+
+extern "C" gi_status gi_selector_gradient(gi_selector* s, const float* feats, const float* log_ms,
+                                          const uint8_t* valid, int32_t count, float* grad,
+                                          float* loss) {
+  if (!s || !grad) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  if (count < 1 || count > 32) return fail(GI_ERR_INVALID_ARG, "count must be in [1, 32]");
+  gi_status st = sel_check_records(feats, log_ms, valid, count);
+  if (st != GI_OK) return st;
+  std::vector<int32_t> order((size_t)count);
+  for (int i = 0; i < count; ++i) order[(size_t)i] = i;
+  DevRecords r;
+  if ((st = sel_records(r, feats, log_ms, valid, count, order, 1)) != GI_OK) return st;
+  const TrainArgs a = train_args(s, r, count, 1, 0.0f, 0);
+  LAUNCH_TRY(launch_mlp_train(a, nullptr));
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(grad, s->d_grad, sizeof(float) * kParams, hipMemcpyDeviceToHost));
+  if (loss) HIP_TRY(hipMemcpy(loss, r.loss, sizeof(float), hipMemcpyDeviceToHost));
+  return GI_OK;
+}
+
+extern "C" gi_status gi_selector_predict(const gi_selector* s, const float* feats, int64_t count,
+                                         int32_t bf16, float* out) {
+  if (!s || !feats || !out || count < 0) return fail(GI_ERR_INVALID_ARG, "bad arguments");
+  if (count == 0) return GI_OK;
+  float* dx = nullptr;
+  float* dy = nullptr;
+  if (hipMalloc((void**)&dx, sizeof(float) * (size_t)count * kFeat) != hipSuccess ||
+      hipMalloc((void**)&dy, sizeof(float) * (size_t)count * kOut) != hipSuccess) {
+    (void)hipGetLastError();
+    if (dx) (void)hipFree(dx);
+    return fail(GI_ERR_OUT_OF_MEMORY, "prediction buffers");
+  }
+  SelDev d;
+  d.p = s->d_p;
+  d.wb = s->d_wb;
+  d.mu = s->d_p + kParams;
+  d.isd = s->d_p + kParams + kFeat;
+  gi_status st = GI_OK;
+  if (hipMemcpy(dx, feats, sizeof(float) * (size_t)count * kFeat, hipMemcpyHostToDevice) != hipSuccess)
+    st = fail(GI_ERR_DEVICE, "copy of features failed");
+  else if (launch_mlp_predict(d, dx, count, bf16 != 0, dy, nullptr) != 0)
+    st = fail(GI_ERR_DEVICE, "prediction launch failed: %s", hipGetErrorString(hipGetLastError()));
+  else if (hipMemcpy(out, dy, sizeof(float) * (size_t)count * kOut, hipMemcpyDeviceToHost) != hipSuccess)
+    st = fail(GI_ERR_DEVICE, "copy of predictions failed");
+  (void)hipFree(dx);
+  (void)hipFree(dy);
+  return st;
+}
+
+extern "C" gi_status gi_selector_attach(gi_graph* g, const gi_selector* s) {
+  if (!g) return fail(GI_ERR_INVALID_ARG, "NULL graph");
+  HIP_TRY(hipDeviceSynchronize());
+  for (void* q : {(void*)g->sel_p, (void*)g->sel_wb, (void*)g->sel_io})
+    if (q) (void)hipFree(q);
+  g->sel_p = nullptr;
+  g->sel_wb = nullptr;
+  g->sel_io = nullptr;
+  if (!s) return GI_OK;
+  if (hipMalloc((void**)&g->sel_p, sizeof(float) * (kParams + 2 * kFeat)) != hipSuccess ||
+      hipMalloc((void**)&g->sel_wb, 2 * (size_t)kParams) != hipSuccess ||
+      hipMalloc((void**)&g->sel_io, sizeof(float) * (kFeat + kOut)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(GI_ERR_OUT_OF_MEMORY, "selector copy allocation failed");
+  }
+  HIP_TRY(hipMemcpy(g->sel_p, s->d_p, sizeof(float) * (kParams + 2 * kFeat),
+                    hipMemcpyDeviceToDevice));
+  HIP_TRY(hipMemcpy(g->sel_wb, s->d_wb, 2 * (size_t)kParams, hipMemcpyDeviceToDevice));
+  return GI_OK;
+}
+
+extern "C" gi_status gi_get_step_features(const gi_graph* g, float* feats, int32_t cap,
+                                          int32_t* count) {
+  if (!g || !count || cap < 0 || (cap > 0 && !feats))
+    return fail(GI_ERR_INVALID_ARG, "bad step-feature arguments");
+  const int alg = g->stats.algorithm;
+  const int k = (alg == ALG_BFS || alg == ALG_CC) ? std::min(g->stats.trace_len, kMaxLog) : 0;
+  const volatile HostFlags* h = g->hflags;
+  for (int i = 0; i < std::min(k, (int)cap); ++i)
+    for (int f = 0; f < kFeat; ++f) feats[(size_t)i * kFeat + f] = h->feat[i][f];
+  *count = k;
+  return GI_OK;
+}
+
+extern "C" gi_status gi_trace_exhaustive(gi_graph* g, int32_t algorithm, int32_t src, float* feats,
+                                         float* step_ms, uint8_t* valid, int32_t cap,
+                                         int32_t* count) {
+  if (!g || !count || cap < 0 || (cap > 0 && (!feats || !step_ms || !valid)))
+    return fail(GI_ERR_INVALID_ARG, "bad trace arguments");
+  if (algorithm != GI_ALG_PAGERANK && algorithm != GI_ALG_BFS && algorithm != GI_ALG_CC)
+    return fail(GI_ERR_INVALID_ARG, "algorithm %d has no schedule choice", algorithm);
+  if (algorithm == GI_ALG_BFS && (src < 0 || src >= g->n))
+    return fail(GI_ERR_INVALID_ARG, "source %d outside [0, %d)", src, g->n);
+  int32_t* out = nullptr;
+  if (hipMalloc((void**)&out, sizeof(float) * (size_t)g->n) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(GI_ERR_OUT_OF_MEMORY, "trace output buffer");
+  }
+  const gi_schedule saved = g->sched;
+  const int saved_timing = g->step_timing;
+  g->step_timing = 1;
+  g->timing_failed = false;
+  gi_status st = GI_OK;
+  int steps = -1;
+  std::vector<int32_t> fr0;
+  std::vector<float> t((size_t)kMaxLog * kOut, 0.0f);
+  std::vector<uint8_t> ok((size_t)kMaxLog * kOut, 0);
+  std::vector<float> x((size_t)kMaxLog * kFeat, 0.0f);
+  const int nsched = algorithm == GI_ALG_PAGERANK ? 2 : 3;
+  for (int q = 0; q < nsched && st == GI_OK; ++q) {
+    const int sched = algorithm == GI_ALG_PAGERANK ? 2 + q : q;  // S index
+    if (algorithm == GI_ALG_PAGERANK) {
+      g->sched.direction = GI_DIR_DENSE_PULL;
+      const bool seg = sched == 3;
+      if (seg && (st = ensure_segments(g)) != GI_OK) break;
+      st = pr_run(g, 20, 0.85f, reinterpret_cast<float*>(out), nullptr, seg);
+    } else {
+      g->sched.direction = sched;  // GI_DIR_SPARSE_PUSH, DENSE_PUSH, DENSE_PULL
+      g->sched.dense_frontier = GI_FRONTIER_BITVECTOR;
+      st = algorithm == GI_ALG_BFS ? gi_bfs(g, src, out, nullptr, nullptr) : gi_cc(g, out, nullptr);
+    }
+    if (st != GI_OK) break;
+    const gi_run_stats& rs = g->stats;
+    const int k = std::min(rs.trace_len, kMaxLog);
+    if (q == 0) {
+      steps = k;
+      fr0.assign(rs.step_frontier, rs.step_frontier + k);
+      if (algorithm == GI_ALG_PAGERANK) {
+        for (int i = 0; i < k; ++i) pr_features(g, &x[(size_t)i * kFeat]);
+      } else {
+        const volatile HostFlags* h = g->hflags;
+        for (int i = 0; i < k; ++i)
+          for (int f = 0; f < kFeat; ++f) x[(size_t)i * kFeat + f] = h->feat[i][f];
+      }
+    } else if (k != steps || !std::equal(fr0.begin(), fr0.end(), rs.step_frontier)) {
+      st = fail(GI_ERR_DEVICE, "frontier sequence differs between schedules");
+      break;
+    }
+    const int ne = std::min(g->tev_count, k);
+    for (int i = 0; i < ne; ++i) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, g->tev[(size_t)i].start, g->tev[(size_t)i].end) != hipSuccess) {
+        st = fail(GI_ERR_DEVICE, "event timing failed");
+        break;
+      }
+      t[(size_t)i * kOut + sched] = ms;
+      ok[(size_t)i * kOut + sched] = 1;
+    }
+  }
+  g->sched = saved;
+  g->step_timing = saved_timing;
+  (void)hipFree(out);
+  if (st != GI_OK) return st;
+  const int k = std::max(steps, 0);
+  for (int i = 0; i < std::min(k, (int)cap); ++i) {
+    std::memcpy(&feats[(size_t)i * kFeat], &x[(size_t)i * kFeat], sizeof(float) * kFeat);
+    std::memcpy(&step_ms[(size_t)i * kOut], &t[(size_t)i * kOut], sizeof(float) * kOut);
+    std::memcpy(&valid[(size_t)i * kOut], &ok[(size_t)i * kOut], kOut);
+  }
+  *count = k;
   return GI_OK;
 }

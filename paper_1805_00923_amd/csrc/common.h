@@ -27,6 +27,7 @@ constexpr int kParts = 2048;     // step kernels run exactly this many workgroup
 constexpr int kMaxCount = 2048;  // at most this many count/write workgroups
 constexpr int kMaxLog = 4096;    // per-step trace entries
 constexpr int kMinChunk = 256;   // smallest expansion chunk (slots)
+constexpr int kFeat = GI_SEL_FEATURES;  // selector features per step
 
 // ---------------------------------------------------------------------------
 // Device-side adjacency.  CSR rows (out-edges) and CSC rows (in-edges) are
@@ -84,6 +85,7 @@ struct HostFlags {
   int pad;
   long long edges_examined;  // valid once done
   StepLog log[kMaxLog];
+  float feat[kMaxLog][kFeat];  // selector features of each step (BFS, CC)
 };
 
 // Control block of one algorithm run (device memory).
@@ -98,6 +100,7 @@ struct Control {
   long long sa_slots; // their degree sum (edge slots of the expansion)
   long long nchunks;  // expansion chunks
   long long edges_examined;
+  long long visited;  // sum of |F| over the steps decided so far (BFS)
   // SSSP
   unsigned long long thresh;   // current bucket ends below thresh
   unsigned long long told;     // previous threshold (split phase)

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "common.h"
+#include "selector.h"
 #include "traverse.h"
 
 namespace gi {
@@ -61,6 +62,9 @@ struct DecideArgs {
   int divisor;
   int forced_dir;  // >= 0: direction of every step
   long long edges; // m for BFS, 2m for CC (edges counted in both directions)
+  int is_bfs;      // feature 7 is the unvisited fraction
+  FeatConst fc;    // graph-level features
+  SelDev sel;      // attached selector (GI_DIR_LEARNED)
 };
 
 struct BfsArgs {
@@ -120,6 +124,31 @@ int enqueue_cc_step(const Engine& e, const FrontierArgs& f, const DecideArgs& d,
 int launch_sssp_init(const SsspArgs& sa, int src, hipStream_t s);
 int enqueue_sssp_step(const Engine& e, const FrontierArgs& f, const SsspArgs& sa,
                       const StepEvents* te, hipStream_t s);
+
+// Selector training (selector.hip): parameters, Adam moments and the
+// gradient buffer in device memory; records x[n][12], y[n][4] (log ms),
+// valid[n][4]; minibatches follow `order`.
+struct TrainArgs {
+  float* p;
+  float* m1;
+  float* m2;
+  float* grad;
+  const float* x;
+  const float* y;
+  const uint8_t* valid;
+  const int32_t* order;
+  int n;
+  const float* mu;
+  const float* isd;
+  int epochs;
+  float lr, beta1, beta2, eps;
+  int apply;       // 0: gradient only
+  long long t0;    // Adam steps taken before this launch
+  float* loss;     // per-epoch mean minibatch loss (may be null)
+};
+int launch_mlp_train(const TrainArgs& a, hipStream_t s);
+int launch_mlp_predict(const SelDev& sd, const float* x, long long n, bool bf16, float* out,
+                       hipStream_t s);
 
 int launch_pr_init(int n, const int32_t* outdeg, float* c0, float* rank, bool zero_iters,
                    hipStream_t s);
