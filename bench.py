@@ -46,7 +46,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="bfs_cc_rmat22",
-                    choices=["bfs_cc_rmat22", "pr_rmat16", "pr_rmat22", "sssp_grid"])
+                    choices=["bfs_cc_rmat22", "pr_rmat16", "pr_rmat22", "sssp_grid", "selector"])
+    ap.add_argument("--heldout", default="small", choices=["small", "full"],
+                    help="selector workload: held-out Chung-Lu graph with 4M vertices (small) "
+                         "or 41M vertices and ~1.4B edges (full)")
+    ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--sources", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", default="", help="k=v,... overrides of the schedule")
@@ -356,6 +360,138 @@ def run_sssp(args, torch, dev):
     return value, "GTEPS", dt * 1e3 / args.steps, "uint32", config, roof, None, extra
 
 
+def selector_records(g, gi, alg, src=0):
+    f, t, v = g.trace_exhaustive(alg, src)
+    import numpy as np
+    y = np.where(v > 0, np.log(np.maximum(t, 1e-6)), 0.0).astype(np.float32)
+    return f, y, v, t
+
+
+def run_selector(args, torch, dev):
+    """Train the selector on exhaustive per-step timings of training graphs,
+    then compare, on a held-out Chung-Lu graph (exponent 2.0), the hybrid
+    heuristic, the learned selector and the per-step best schedule."""
+    import numpy as np
+
+    import graphgen as gg
+    import paper_1805_00923_amd as gi
+    t_all = time.time()
+    train = [("rmat", 16, 316), ("rmat", 18, 318), ("rmat", 20, 320), ("rmat", 22, 322),
+             ("chunglu", 1 << 20, 2.2, 401), ("chunglu", 1 << 20, 2.5, 402),
+             ("chunglu", 1 << 21, 3.0, 403), ("chunglu", 1 << 22, 2.2, 404)]
+    F, Y, V = [], [], []
+    for spec in train:
+        if spec[0] == "rmat":
+            el = gg.rmat(spec[1], 16, seed=spec[2])
+        else:
+            n = spec[1]
+            el = gg.chung_lu(n, 20 * n, spec[2], min(1e5, n / 8), seed=spec[3])
+        g = gi.Graph.from_edges(el.n, el.src, el.dst)
+        g.set_schedule(direction=gi.DENSE_PULL_SPARSE_PUSH)
+        for s in gg.pick_sources(el, 24, spec[-1]):
+            f, y, v, _ = selector_records(g, gi, gi.ALG_BFS, int(s))
+            F.append(f), Y.append(y), V.append(v)
+        for alg in (gi.ALG_CC, gi.ALG_PAGERANK):
+            f, y, v, _ = selector_records(g, gi, alg)
+            F.append(f), Y.append(y), V.append(v)
+        log("training graph %s: n=%d m=%d, %d records so far" % (el.name, g.n, g.m,
+                                                                sum(len(x) for x in F)))
+        g.close()
+    X, Yl, Vm = np.concatenate(F), np.concatenate(Y), np.concatenate(V)
+    sel = gi.Selector(seed=1)
+    t0 = time.time()
+    loss = sel.train(X, Yl, Vm, epochs=args.epochs, lr=1e-3, seed=7)
+    t_train = time.time() - t0
+    log("trained on %d records, %d epochs in %.1fs: loss %.4f -> %.4f" %
+        (len(X), args.epochs, t_train, loss[0], loss[-1]))
+
+    # held-out graph
+    if args.heldout == "full":
+        n_h, samples, dmax = 41_000_000, 1_500_000_000, 1e6
+    else:
+        n_h, samples, dmax = 1 << 22, 34 * (1 << 22), 1e6 * (1 << 22) / 41e6
+    t0 = time.time()
+    el = gg.chung_lu(n_h, samples, 2.0, dmax, seed=999)
+    g = gi.Graph.from_edges(el.n, el.src, el.dst)
+    log("held-out %s: n=%d m=%d built in %.1fs" % (el.name, g.n, g.m, time.time() - t0))
+    srcs = gg.pick_sources(el, 16, 1000)
+    del el
+    out = torch.empty(g.n, dtype=torch.int32, device=dev)
+    ranks = torch.empty(g.n, dtype=torch.float32, device=dev)
+    g.attach_selector(sel)
+
+    def timed(alg, direction, src=0, reps=3):
+        g.set_schedule(direction=direction)
+        ms, dirs = [], None
+        for _ in range(reps):
+            if alg == gi.ALG_BFS:
+                g.bfs(int(src), out)
+            elif alg == gi.ALG_CC:
+                g.cc(out)
+            else:
+                g.pagerank(ranks, 20, 0.85)
+            ms.append(g.stats().kernel_ms)
+            dirs = g.stats().trace()[0]
+        return float(np.median(ms)), dirs
+
+    rows = []
+    cases = [(gi.ALG_BFS, int(s)) for s in srcs] + [(gi.ALG_CC, 0), (gi.ALG_PAGERANK, 0)]
+    regret_l, regret_h, best_steps = [], [], []
+    t_heur = t_learn = t_best = 0.0
+    for alg, s in cases:
+        g.set_schedule(direction=gi.DENSE_PULL_SPARSE_PUSH)
+        _, _, v, tt = selector_records(g, gi, alg, s)
+        tt = np.where(v > 0, tt, np.inf)
+        best = tt.min(1)
+        if alg == gi.ALG_PAGERANK:
+            heur_ms, _ = timed(alg, gi.DENSE_PULL)          # the plain schedule: unsegmented
+            learn_ms, _ = timed(alg, gi.LEARNED)
+            pred = sel.predict(g.trace_exhaustive(alg)[0][:1], bf16=True)[0]
+            pick = 3 if pred[2] - pred[3] > 0.14 else 2   # the library's margin
+            lchoice = np.full(len(best), pick)
+            hchoice = np.full(len(best), 2)
+        else:
+            heur_ms, hd = timed(alg, gi.DENSE_PULL_SPARSE_PUSH, s)
+            learn_ms, ld = timed(alg, gi.LEARNED, s)
+            hchoice, lchoice = hd.astype(int), ld.astype(int)
+        k = len(best)
+        rl = tt[np.arange(k), lchoice[:k]] - best
+        rh = tt[np.arange(k), hchoice[:k]] - best
+        regret_l += list(rl)
+        regret_h += list(rh)
+        best_steps += list(best)
+        t_heur += heur_ms
+        t_learn += learn_ms
+        t_best += float(best.sum())
+        rows.append({"alg": {0: "pagerank", 1: "bfs", 2: "cc"}[alg], "src": s,
+                     "heuristic_ms": round(heur_ms, 4), "learned_ms": round(learn_ms, 4),
+                     "best_steps_ms": round(float(best.sum()), 4), "steps": k})
+    regret_l, regret_h = np.array(regret_l), np.array(regret_h)
+    speedup = t_heur / t_learn
+    detail = {
+        "train_records": int(len(X)), "epochs": args.epochs, "train_s": round(t_train, 2),
+        "loss_first_last": [round(float(loss[0]), 4), round(float(loss[-1]), 4)],
+        "heldout": {"n": g.n, "m": g.m, "gamma": 2.0, "bfs_sources": int(len(srcs))},
+        "total_ms": {"heuristic": round(t_heur, 3), "learned": round(t_learn, 3),
+                     "per_step_best": round(t_best, 3)},
+        "regret_learned_us": {"mean": round(1e3 * regret_l.mean(), 3),
+                              "p50": round(1e3 * float(np.percentile(regret_l, 50)), 3),
+                              "p95": round(1e3 * float(np.percentile(regret_l, 95)), 3),
+                              "total_pct": round(100 * regret_l.sum() / sum(best_steps), 2)},
+        "regret_heuristic_us": {"mean": round(1e3 * regret_h.mean(), 3),
+                                "p50": round(1e3 * float(np.percentile(regret_h, 50)), 3),
+                                "p95": round(1e3 * float(np.percentile(regret_h, 95)), 3),
+                                "total_pct": round(100 * regret_h.sum() / sum(best_steps), 2)},
+        "per_case": rows, "wall_s": round(time.time() - t_all, 1),
+    }
+    config = {"workload": "selector_chunglu_g2.0_%s" % args.heldout, "n": g.n, "m": g.m,
+              "train_graphs": ["rmat16", "rmat18", "rmat20", "rmat22", "chunglu1M_g2.2",
+                               "chunglu1M_g2.5", "chunglu2M_g3.0", "chunglu4M_g2.2"]}
+    roof = None
+    return speedup, "x (heuristic time / learned time)", t_learn, "f32 train / bf16 infer", \
+        config, roof, None, detail
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -376,6 +512,8 @@ def main():
         res = run_pr(args, torch, dev, 16)
     elif args.workload == "pr_rmat22":
         res = run_pr(args, torch, dev, 22)
+    elif args.workload == "selector":
+        res = run_selector(args, torch, dev)
     else:
         res = run_sssp(args, torch, dev)
     value, unit, ms_step, dtype, config, roof, cpu, extra = res
@@ -384,7 +522,7 @@ def main():
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
             "data": "synthetic", "config": config, "roofline": roof, "cpu_baseline": cpu,
             "detail": extra}
-    s = json.dumps(line)
+    s = json.dumps(line, default=lambda o: o.item() if hasattr(o, "item") else str(o))
     if args.json_out:
         with open(args.json_out, "w") as f:
             f.write(s + "\n")

@@ -58,7 +58,11 @@ enum {
   GI_DIR_DENSE_PUSH_SPARSE_PUSH = 4, /* per step: DensePush if frontier is large        */
   GI_DIR_LEARNED = 5                 /* per step: the attached selector's choice among
                                         SparsePush, DensePush and DensePull (BFS, CC);
-                                        PageRank: unsegmented or segmented DensePull  */
+                                        PageRank: unsegmented or segmented DensePull.
+                                        The fallback (the hybrid rule with the
+                                        schedule's divisor; unsegmented for PageRank)
+                                        is kept unless the selector predicts it to be
+                                        more than 15% slower (log-time margin 0.14) */
 };
 
 /* Dense vertexset representation: configApplyDenseVertexSet options. */

@@ -94,7 +94,10 @@ __global__ __launch_bounds__(1024) void k_decide_frontier(FrontierArgs f, Decide
       int best = GI_DIR_SPARSE_PUSH;
       for (int q = GI_DIR_DENSE_PUSH; q <= GI_DIR_DENSE_PULL; ++q)
         if (s_y[q] < s_y[best]) best = q;
-      s_mode = best;
+      // the hybrid rule stays unless the model predicts a clear gain
+      const int h = hybrid_dense(tot.members, tot.degsum, d.edges, d.divisor) ? GI_DIR_DENSE_PULL
+                                                                              : GI_DIR_SPARSE_PUSH;
+      s_mode = s_y[h] - s_y[best] > kLearnedMargin ? best : h;
     }
     __syncthreads();
   }

@@ -991,7 +991,7 @@ extern "C" gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, floa
     HIP_TRY(hipMemcpyAsync(io + kFeat, g->sel_io + kFeat, sizeof(float) * kOut,
                            hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    segmented = io[kFeat + 3] < io[kFeat + 2];
+    segmented = io[kFeat + 2] - io[kFeat + 3] > kLearnedMargin;
     if (segmented && (st = ensure_segments(g)) != GI_OK) return st;
   }
   return pr_run(g, iters, damping, ranks, s, segmented);

@@ -29,6 +29,11 @@ constexpr int kOffB3 = kOffW3 + kHid * kOut;
 constexpr int kParams = kOffB3 + kOut;  // 5252
 static_assert(kParams == GI_SEL_PARAMS, "parameter count");
 
+// The learned choice replaces the fallback (the hybrid rule; unsegmented
+// DensePull for PageRank) only when its predicted log-time is lower by more
+// than this (about 15%).
+constexpr float kLearnedMargin = 0.14f;
+
 // Device copy of a selector for inference.
 struct SelDev {
   const float* p;      // fp32 parameters (biases are read from here)
