@@ -343,6 +343,63 @@ gi_status gi_get_step_features(const gi_graph* g, float* feats, int32_t cap, int
 gi_status gi_trace_exhaustive(gi_graph* g, int32_t algorithm, int32_t src, float* feats,
                               float* step_ms, uint8_t* valid, int32_t cap, int32_t* count);
 
+/* ---- batched persistent execution -------------------------------------- */
+/* Many BFS and PageRank instances over graphs of uneven size in one
+ * persistent kernel launch (optionally replayed as a HIP graph).  Each task
+ * runs on its own set of workgroups that meet at task-local barriers between
+ * BFS levels and PageRank iterations, so no step costs a kernel launch and
+ * small instances do not wait for the whole device.  BFS tasks choose
+ * DensePull or push per level by the hybrid rule (section 2) with divisor
+ * 20 and produce levels only; PageRank tasks use the DensePull
+ * destination-block kernel with the graph's current block size.  Results
+ * equal the plain entry points' (levels bit for bit; ranks within the
+ * PageRank tolerance).  A barrier that waits more than two seconds fails
+ * the batch (GI_ERR_DEVICE) instead of hanging. */
+typedef struct gi_task {
+  int32_t graph;      /* index into the batch's graphs                          */
+  int32_t algorithm;  /* GI_ALG_BFS or GI_ALG_PAGERANK                          */
+  int32_t src;        /* BFS source                                             */
+  int32_t iters;      /* PageRank iterations (>= 0)                             */
+  float damping;      /* PageRank damping in [0, 1]                             */
+  int32_t workgroups; /* workgroups of this task, 1..1024; 0 = the plan's choice
+                         (a size rule at creation, then gi_batch_autotune)      */
+  void* out;          /* device out, n entries: int32 levels (-1 unreachable)
+                         for BFS, float ranks for PageRank; kept by the caller  */
+} gi_task;
+
+typedef struct gi_batch gi_batch;
+
+/* Plan a batch: validates the tasks, allocates each task's workspace and
+ * deals the tasks' workgroups over a grid no larger than the kernel's
+ * resident capacity.  The graphs must outlive the batch and keep the
+ * schedule they had at creation (a changed PageRank block layout makes
+ * gi_batch_run return INVALID_ARG).
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, const gi_task* tasks,
+                          int32_t ntasks, gi_batch** out);
+
+/* Autotuner: times each (graph, algorithm) class alone on 1, 2, 4, ... 64
+ * workgroups (median of reps launches), keeps the size with the least
+ * workgroup-time unless it is more than twice as slow as the fastest,
+ * gives tasks longer than the balanced share of the grid their fastest
+ * size, and re-plans.  Tasks with fixed workgroups keep them.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+gi_status gi_batch_autotune(gi_batch* b, int32_t reps);
+
+/* Run every task once: one launch of the reset kernel and the persistent
+ * kernel, captured once into a HIP graph and replayed when use_graph is
+ * nonzero (on the batch's own stream, after `stream` has drained), else
+ * launched on `stream`.  Returns after completion.
+ * Errors: INVALID_ARG, DEVICE (including a barrier timeout). */
+gi_status gi_batch_run(gi_batch* b, int32_t use_graph, void* stream);
+
+/* GPU time of the last run (ms), grid size, and per task (arrays of the
+ * batch's task count, may be NULL) its workgroups and its completed BFS
+ * levels or PageRank iterations.  Errors: INVALID_ARG, DEVICE. */
+gi_status gi_batch_info(const gi_batch* b, float* last_ms, int32_t* grid, int32_t* workgroups,
+                        int32_t* levels);
+gi_status gi_batch_destroy(gi_batch* b);
+
 /* ---- frontier primitives (device, stream ordered) -------------------- */
 /* Dense and sparse vertexset representations (section 2, direction
  * optimization and frontier data structure; scheduling-language table,

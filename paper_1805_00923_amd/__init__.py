@@ -118,6 +118,11 @@ _SIGS = {
     "gi_selector_attach": (ctypes.c_int, [_vp, _vp]),
     "gi_get_step_features": (ctypes.c_int, [_vp, _vp, _i32, _vp]),
     "gi_trace_exhaustive": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i32, _vp]),
+    "gi_batch_create": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp]),
+    "gi_batch_autotune": (ctypes.c_int, [_vp, _i32]),
+    "gi_batch_run": (ctypes.c_int, [_vp, _i32, _vp]),
+    "gi_batch_info": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "gi_batch_destroy": (ctypes.c_int, [_vp]),
     "gi_get_step_times": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp]),
     "gi_frontier_sparse_to_bitvec": (ctypes.c_int, [_i32, _vp, _i32, _vp, _vp]),
     "gi_frontier_bitvec_to_sparse": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp]),
@@ -426,3 +431,56 @@ class Selector:
         _check(lib.gi_selector_predict(self._h, f.ctypes.data, f.shape[0], 1 if bf16 else 0,
                                        out.ctypes.data))
         return out
+
+
+class Task(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_int32), ("algorithm", ctypes.c_int32), ("src", ctypes.c_int32),
+                ("iters", ctypes.c_int32), ("damping", ctypes.c_float),
+                ("workgroups", ctypes.c_int32), ("out", ctypes.c_void_p)]
+
+
+class Batch:
+    """Batched persistent execution of BFS / PageRank tasks.
+
+    tasks: sequence of dicts with keys graph (index), algorithm (ALG_BFS or
+    ALG_PAGERANK), out (device tensor of n int32 or float32), and src /
+    iters / damping / workgroups as needed."""
+
+    def __init__(self, graphs, tasks):
+        self.graphs = list(graphs)
+        self._outs = [t["out"] for t in tasks]   # keep the tensors alive
+        arr = (Task * len(tasks))()
+        for i, t in enumerate(tasks):
+            arr[i] = Task(int(t["graph"]), int(t["algorithm"]), int(t.get("src", 0)),
+                          int(t.get("iters", 20)), float(t.get("damping", 0.85)),
+                          int(t.get("workgroups", 0)), _dptr(t["out"]))
+        hs = (ctypes.c_void_p * len(self.graphs))(*[g._h.value for g in self.graphs])
+        self._h = ctypes.c_void_p(None)
+        self.ntasks = len(tasks)
+        _check(lib.gi_batch_create(hs, len(self.graphs), arr, len(tasks), ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            lib.gi_batch_destroy(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def autotune(self, reps=3):
+        _check(lib.gi_batch_autotune(self._h, int(reps)))
+
+    def run(self, use_graph=True, stream=None):
+        _check(lib.gi_batch_run(self._h, 1 if use_graph else 0, _stream(stream)))
+
+    def info(self):
+        ms = ctypes.c_float()
+        grid = ctypes.c_int32()
+        wg = np.zeros(self.ntasks, np.int32)
+        lv = np.zeros(self.ntasks, np.int32)
+        _check(lib.gi_batch_info(self._h, ctypes.byref(ms), ctypes.byref(grid), wg.ctypes.data,
+                                 lv.ctypes.data))
+        return {"ms": ms.value, "grid": grid.value, "workgroups": wg, "levels": lv}

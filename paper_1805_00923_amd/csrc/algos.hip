@@ -22,6 +22,7 @@
 // SparsePush steps and a far set for everything improved at or beyond it;
 // when the near set empties the threshold moves to the end of the bucket of
 // the smallest far distance and the far set is split.
+#include "bfs_dev.h"
 #include "kernels.h"
 #include "traverse.h"
 
@@ -120,173 +121,6 @@ __global__ __launch_bounds__(1024) void k_decide_frontier(FrontierArgs f, Decide
 
 // ------------------------------------------------------------------- BFS --
 
-struct BfsVisit {
-  const int32_t* idx;
-  int32_t* level;
-  int32_t* parent;
-  int l1;
-  DenseSet next;
-  uint64_t* vis;
-  long long work = 0;
-  __device__ __forceinline__ void operator()(int u, int e, bool valid) {
-    if (!valid) return;
-    const int v = idx[e];
-    ++work;
-    if (level[v] >= 0) return;
-    if (atomicCAS(&level[v], -1, l1) != -1) return;
-    if (parent) parent[v] = u;
-    next.insert(v);
-    atomicOr((unsigned long long*)&vis[v >> 6], 1ull << (v & 63));
-  }
-};
-
-// DensePull: a wave owns 64-vertex words and takes G of them at a time, so
-// the dependent load chains of G words (visited word -> in-row bounds ->
-// in-neighbour ids -> frontier bits) overlap instead of running one after
-// another.  Unvisited lanes test their first in-edges in two batches of
-// four independent loads; the rows still open are then concatenated and
-// walked 64 edges per round across the wave.  Every row stops at its first
-// source in the frontier, in in-edge order.  The next frontier word and the
-// visited word are written whole, without atomics.
-template <int BT, int G = 4>
-__device__ long long bfs_pull(const BfsArgs& b, int l1) {
-  const DevGraph& g = b.g;
-  const int n = g.n, W = (n + 63) >> 6, lane = __lane_id();
-  const DenseSet cur = b.cur, nxt = b.next;
-  long long work = 0;
-  const int wave0 = blockIdx.x * (BT / kWave) + (int)(threadIdx.x / kWave);
-  const int nwaves = gridDim.x * (BT / kWave);
-  for (int wb = wave0; wb < W; wb += G * nwaves) {
-    uint64_t vw[G];
-    bool cand[G], found[G];
-    int j[G], e[G], par[G];
-#pragma unroll
-    for (int q = 0; q < G; ++q) {
-      const int w = wb + q * nwaves;  // wave-uniform
-      const int v = (w << 6) + lane;
-      vw[q] = w < W ? b.vis[w] : ~0ull;
-      cand[q] = w < W && v < n && !((vw[q] >> lane) & 1ull);
-      found[q] = false;
-      par[q] = -1;
-      j[q] = 0;
-      e[q] = 0;
-    }
-#pragma unroll
-    for (int q = 0; q < G; ++q) {
-      if (cand[q]) {
-        const int v = ((wb + q * nwaves) << 6) + lane;
-        j[q] = g.in_off[v];
-        e[q] = g.in_off[v + 1];
-      }
-    }
-#pragma unroll
-    for (int batch = 0; batch < 2; ++batch) {
-      int u[G][4];
-#pragma unroll
-      for (int q = 0; q < G; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          u[q][r] = (cand[q] && !found[q] && j[q] + r < e[q]) ? g.in_idx[j[q] + r] : -1;
-      bool h[G][4];
-#pragma unroll
-      for (int q = 0; q < G; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) h[q][r] = u[q][r] >= 0 && cur.test(u[q][r]);
-#pragma unroll
-      for (int q = 0; q < G; ++q) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (!found[q] && u[q][r] >= 0) {
-            ++work;
-            if (h[q][r]) {
-              found[q] = true;
-              par[q] = u[q][r];
-            }
-          }
-        }
-        if (!found[q]) j[q] = min(e[q], j[q] + 4);
-      }
-    }
-    // Rows still open are walked as one concatenated edge list per word,
-    // 64 edges per round spread over the lanes; a row leaves the list at
-    // its first frontier hit.
-    for (;;) {
-      int rem[G], ex[G], tot[G];
-      bool more = false;
-#pragma unroll
-      for (int q = 0; q < G; ++q) {
-        rem[q] = (cand[q] && !found[q]) ? e[q] - j[q] : 0;
-        ex[q] = wave_excl_scan(rem[q], &tot[q]);
-        more |= tot[q] > 0;
-      }
-      if (!more) break;  // wave-uniform
-      int uu[G];
-      bool hit[G];
-#pragma unroll
-      for (int q = 0; q < G; ++q) {
-        // owner of list position `lane`: the last lane whose list starts at
-        // or before it (later lanes with empty rows start after it)
-        int own = 0;
-#pragma unroll
-        for (int st = 32; st > 0; st >>= 1) {
-          const int c = own + st;
-          const int exc = __shfl(ex[q], c < kWave ? c : kWave - 1, kWave);
-          if (c < kWave && exc <= lane) own = c;
-        }
-        const int jo = __shfl(j[q], own, kWave);
-        const int eo = __shfl(ex[q], own, kWave);
-        const bool act = lane < tot[q];
-        uu[q] = act ? g.in_idx[jo + (lane - eo)] : 0;
-      }
-#pragma unroll
-      for (int q = 0; q < G; ++q) hit[q] = lane < tot[q] && cur.test(uu[q]);
-#pragma unroll
-      for (int q = 0; q < G; ++q) {
-        const unsigned long long hm = __ballot(hit[q]);
-        // this lane's positions in the round: [a, b)
-        const int a = ex[q], b = min(kWave, ex[q] + rem[q]);
-        const bool mine = rem[q] > 0 && a < kWave;
-        unsigned long long span = 0ull;
-        if (mine) {
-          const unsigned long long hi = b >= kWave ? ~0ull : ((1ull << b) - 1ull);
-          span = hi & ~((1ull << a) - 1ull);
-        }
-        const unsigned long long mh = hm & span;
-        const int first = mh ? __ffsll((long long)mh) - 1 : 0;
-        const int pu = __shfl(uu[q], first, kWave);
-        if (mine) {
-          if (mh) {
-            found[q] = true;
-            par[q] = pu;
-            work += first - a + 1;
-          } else {
-            work += b - a;
-            j[q] += b - a;
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < G; ++q) {
-      const int w = wb + q * nwaves;
-      if (w >= W) break;  // wave-uniform
-      const int v = (w << 6) + lane;
-      const unsigned long long fm = __ballot(found[q]);
-      if (found[q]) {
-        b.level[v] = l1;
-        if (b.parent) b.parent[v] = par[q];
-      }
-      if (nxt.bm) {
-        nxt.bm[v] = found[q] ? 1 : 0;  // the bool map is padded to whole words
-      } else if (lane == 0) {
-        nxt.bv[w] = fm;
-      }
-      if (lane == 0) b.vis[w] = vw[q] | fm;
-    }
-  }
-  return work;
-}
-
 template <int BT, int CH>
 __global__ __launch_bounds__(BT) void k_bfs_step(BfsArgs b, ExpandArgs x) {
   __shared__ int lds[expand_lds_ints<CH>()];
@@ -295,7 +129,9 @@ __global__ __launch_bounds__(BT) void k_bfs_step(BfsArgs b, ExpandArgs x) {
   const int l1 = b.ctl->steps;
   long long work = 0;
   if (mode == MODE_DENSE_PULL) {
-    work = bfs_pull<BT>(b, l1);
+    const int W = (b.g.n + 63) >> 6;
+    work = bfs_pull_range<BT>(b, l1, 0, W, blockIdx.x * (BT / kWave) + (int)(threadIdx.x / kWave),
+                              gridDim.x * (BT / kWave), nullptr, nullptr, nullptr);
   } else {
     BfsVisit vis{b.g.out_idx, b.level, b.parent, l1, b.next, b.vis};
     if (mode == MODE_SPARSE_PUSH) expand_chunks<BT, CH>(x, vis, lds);

@@ -1,0 +1,230 @@
+// Batched persistent execution: many BFS and PageRank instances over graphs
+// of uneven size in one kernel launch.
+//
+// Every instance ("task") owns k workgroups; a task's workgroups meet at a
+// task-local barrier between BFS levels and between PageRank iterations,
+// so a small instance never waits for the grid and no step costs a kernel
+// launch.  Each workgroup runs its (task, rank) list in one global order
+// shared by all lists, and every workgroup of the grid is resident at once
+// (the grid is sized from the occupancy); so the lowest unfinished task in
+// that order always has all its workgroups either at its barriers or
+// finished with earlier tasks, and every barrier is reached.  Barrier waits
+// are bounded in wall-clock time: past the bound the batch sets an error
+// flag, every later wait returns at once, and the kernel drains.
+//
+// BFS tasks: level-synchronous, direction chosen per level by the hybrid
+// rule of the frontier engine (DensePull when |F| + sum deg(F) > m / 20,
+// else push of the frontier members in the workgroup's vertex range with
+// degree binning); bitvector frontiers in three rotating buffers, so the
+// buffer cleared during a level is neither read nor written in it.
+// PageRank tasks: the destination-block DensePull of pagerank.hip, blocks
+// dealt round-robin over the task's workgroups.
+#include "bfs_dev.h"
+#include "kernels.h"
+#include "pr_block.h"
+
+namespace gi {
+
+constexpr int kBB = 256;  // threads per workgroup
+
+__device__ __forceinline__ long long wall_ticks() { return (long long)wall_clock64(); }
+
+// Barrier of the k workgroups of one task.  Returns false once the batch
+// has failed (timeout here or elsewhere).
+__device__ bool task_barrier(TaskCtl* c, int k, int* gerr, long long limit) {
+  __shared__ int s_ok;
+  __threadfence();  // release this thread's writes
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = __hip_atomic_load(gerr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    if (ok && k > 1) {
+      const unsigned g = __hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned a = atomicAdd(&c->bar_cnt, 1u);
+      if (a == (unsigned)k - 1u) {
+        __hip_atomic_store(&c->bar_cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&c->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        const long long t0 = wall_ticks();
+        while (__hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+          if (__hip_atomic_load(gerr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            ok = 0;
+            break;
+          }
+          if (wall_ticks() - t0 > limit) {
+            __hip_atomic_store(gerr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  __threadfence();  // acquire: later loads see the other workgroups' writes
+  return s_ok != 0;
+}
+
+__device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const BatchArgs& a) {
+  const int n = G.n, k = t.k, W = (n + 63) >> 6, tid = threadIdx.x;
+  int32_t* level = static_cast<int32_t*>(t.out);
+  TaskCtl* c = t.ctl;
+  uint64_t* bv[3] = {t.bv0, t.bv1, t.bv2};
+  // this workgroup's words and vertices
+  const int w0 = (int)((long long)W * r / k), w1 = (int)((long long)W * (r + 1) / k);
+  const int v0 = w0 * 64, v1 = min(n, w1 * 64);
+  for (int v = v0 + tid; v < v1; v += kBB) level[v] = -1;
+  for (int w = w0 + tid; w < w1; w += kBB) {
+    t.vis[w] = 0ull;
+    t.bv0[w] = 0ull;
+    t.bv1[w] = 0ull;
+    t.bv2[w] = 0ull;
+  }
+  if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+  if (r == 0 && tid == 0) {
+    const int s = t.src;
+    level[s] = 0;
+    t.bv0[s >> 6] = 1ull << (s & 63);
+    t.vis[s >> 6] = 1ull << (s & 63);
+    c->qn[0] = 1;
+    c->ds[0] = G.outdeg[s];
+  }
+  if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+  DevGraph dg{};
+  dg.n = n;
+  dg.m = G.m;
+  dg.out_off = G.out_off;
+  dg.out_idx = G.out_idx;
+  dg.in_off = G.in_off;
+  dg.in_idx = G.in_idx;
+  dg.outdeg = G.outdeg;
+  int L = 0;
+  for (;; ++L) {
+    const long long nf = (long long)__hip_atomic_load(&c->qn[L % 3], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+    const long long df = (long long)__hip_atomic_load(&c->ds[L % 3], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+    if (nf == 0) break;  // task-uniform: read after the same barrier by all
+    if (L > n) {         // more levels than vertices: a broken invariant
+      if (tid == 0) __hip_atomic_store(a.error, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    if (r == 0 && tid == 0) {
+      // read by every workgroup at the previous level, accumulated at the next
+      c->qn[(L + 2) % 3] = 0;
+      c->ds[(L + 2) % 3] = 0;
+    }
+    uint64_t* bclr = bv[(L + 2) % 3];
+    for (int w = w0 + tid; w < w1; w += kBB) bclr[w] = 0ull;
+    BfsArgs b{};
+    b.g = dg;
+    b.level = level;
+    b.parent = nullptr;
+    b.cur = DenseSet{bv[L % 3], nullptr};
+    b.next = DenseSet{bv[(L + 1) % 3], nullptr};
+    b.vis = t.vis;
+    long long found = 0, found_deg = 0;
+    if (hybrid_dense(nf, df, G.m, 20)) {
+      bfs_pull_range<kBB>(b, L + 1, w0, w1, (int)(threadIdx.x / kWave), kBB / kWave, G.outdeg,
+                          &found, &found_deg);
+    } else {
+      BfsVisit vis{G.out_idx, level, nullptr, L + 1, b.next, t.vis};
+      vis.deg = G.outdeg;
+      dense_push_range<kBB>(b.cur, v0, v1, 0, 1, G.out_off, vis);
+      found = vis.found;
+      found_deg = vis.found_deg;
+    }
+    const Part p = block_sum4<kBB>(Part{found, found_deg, 0, 0});
+    if (tid == 0 && p.a > 0) {
+      atomicAdd(&c->qn[(L + 1) % 3], (unsigned long long)p.a);
+      atomicAdd(&c->ds[(L + 1) % 3], (unsigned long long)p.b);
+    }
+    if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+  }
+  if (r == 0 && tid == 0) c->levels = L;
+}
+
+__device__ void pr_task(const BatchGraph& G, const BatchTask& t, int r, const BatchArgs& a,
+                        float* lds_val, int* lds_off) {
+  const int n = G.n, k = t.k, tid = threadIdx.x;
+  TaskCtl* c = t.ctl;
+  float* ranks = static_cast<float*>(t.out);
+  const int v0 = (int)((long long)n * r / k), v1 = (int)((long long)n * (r + 1) / k);
+  const double x0 = 1.0 / (double)n;
+  for (int v = v0 + tid; v < v1; v += kBB) {
+    if (t.iters == 0) {
+      ranks[v] = (float)x0;
+    } else {
+      const int d = G.outdeg[v];
+      t.c0[v] = d > 0 ? (float)(x0 / (double)d) : 0.0f;
+    }
+  }
+  for (int i = r * kBB + tid; i < G.n_long; i += k * kBB) {
+    t.lr_acc[i] = 0.0;
+    t.lr_cnt[i] = 0u;
+  }
+  if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+  PrVertex pv;
+  pv.outdeg = G.outdeg;
+  pv.alpha = (double)t.damping;
+  pv.base = (1.0 - (double)t.damping) / (double)n;
+  PrRows rows{G.pr_table, G.pr_ntab, G.in_off, G.in_idx, nullptr, t.lr_acc, t.lr_cnt,
+              G.lr_chunks};
+  for (int it = 0; it < t.iters; ++it) {
+    const float* cin = (it & 1) ? t.c1 : t.c0;
+    float* cout = (it & 1) ? t.c0 : t.c1;
+    float* rk = it == t.iters - 1 ? ranks : nullptr;
+    for (int tb = r; tb < G.pr_ntab; tb += k)
+      pr_rows_block<kBB>(rows, tb, G.pr_cap_e, cin, 0, pv, cout, rk, nullptr, lds_val, lds_off);
+    if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+  }
+  if (r == 0 && tid == 0) c->levels = t.iters;
+}
+
+__global__ __launch_bounds__(kBB) void k_batch(BatchArgs a) {
+  extern __shared__ float smem[];
+  float* lds_val = smem;
+  int* lds_off = reinterpret_cast<int*>(smem + a.lds_cap_e);
+  const int w = blockIdx.x;
+  for (int i = a.wg_off[w]; i < a.wg_off[w + 1]; ++i) {
+    const int2 it = a.items[i];
+    const BatchTask& t = a.tasks[it.x];
+    const BatchGraph& G = a.graphs[t.graph];
+    if (t.alg == ALG_BFS) bfs_task(G, t, it.y, a);
+    else pr_task(G, t, it.y, a, lds_val, lds_off);
+  }
+}
+
+// Reset of the task control blocks and the error flag (part of the same
+// stream order as the batch, and of its graph when captured).
+__global__ void k_batch_init(TaskCtl* ctl, int ntasks, int* error) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ntasks; i += gridDim.x * blockDim.x) {
+    TaskCtl z{};
+    ctl[i] = z;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *error = 0;
+}
+
+int batch_threads() { return kBB; }
+
+size_t batch_lds_bytes(int cap_e, int cap_v) {
+  return sizeof(float) * (size_t)cap_e + sizeof(int) * (size_t)(cap_v + 1);
+}
+
+int batch_occupancy(size_t lds) {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch, kBB, lds) != hipSuccess)
+    return -1;
+  return blocks;
+}
+
+int launch_batch(const BatchArgs& a, int grid, size_t lds, TaskCtl* ctl, int ntasks,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_init, dim3(std::max(1, std::min(64, (ntasks + 255) / 256))),
+                     dim3(256), 0, s, ctl, ntasks, a.error);
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBB), lds, s, a);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace gi

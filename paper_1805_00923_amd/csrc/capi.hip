@@ -81,7 +81,7 @@ struct gi_graph {
   gi_schedule sched{};
   // destination blocks of the in-rows (PageRank, CC pull pass 0) and out-rows
   int4* pr_table = nullptr;
-  int pr_ntab = 0, pr_cap_e = 0, pr_cap_v = 0;
+  int pr_ntab = 0, pr_cap_e = 0, pr_cap_v = 0, pr_nlong = 0;
   double* lr_acc = nullptr;
   unsigned* lr_cnt = nullptr;
   int32_t* lr_chunks = nullptr;
@@ -411,6 +411,7 @@ static gi_status apply_schedule(gi_graph* g, const gi_schedule& s) {
   gi_status st = dev_alloc(g, g->sched_allocs, &g->pr_table, tab.size());
   if (st != GI_OK) return st;
   if ((st = upload(tab.data(), g->pr_table, tab.size() * sizeof(int4))) != GI_OK) return st;
+  g->pr_nlong = (int)chunks.size();
   const size_t nl = std::max<size_t>(1, chunks.size());
   if ((st = dev_alloc(g, g->sched_allocs, &g->lr_acc, nl)) != GI_OK) return st;
   if ((st = dev_alloc(g, g->sched_allocs, &g->lr_cnt, nl)) != GI_OK) return st;
@@ -1599,5 +1600,457 @@ extern "C" gi_status gi_trace_exhaustive(gi_graph* g, int32_t algorithm, int32_t
     std::memcpy(&valid[(size_t)i * kOut], &ok[(size_t)i * kOut], kOut);
   }
   *count = k;
+  return GI_OK;
+}
+
+// ---------------------------------------------------------------- batch ----
+
+struct gi_batch {
+  std::vector<gi_graph*> graphs;
+  std::vector<gi_task> tasks;
+  std::vector<int> k;        // workgroups per task
+  std::vector<double> est;   // estimated time per task (ms, or a size proxy before tuning)
+  int max_grid = 0;          // resident workgroups of the batch kernel
+  int grid = 0;
+  size_t lds = 0;
+  int cap_e = 0;
+  long long spin_limit = 0;
+  BatchGraph* d_graphs = nullptr;
+  BatchTask* d_tasks = nullptr;
+  TaskCtl* d_ctl = nullptr;
+  int2* d_items = nullptr;
+  int* d_wg_off = nullptr;
+  int* d_err = nullptr;
+  std::vector<BatchTask> h_tasks;
+  std::vector<int2> shape;   // per graph at creation: PageRank block size, long rows
+  std::vector<void*> work;
+  hipStream_t gstream = nullptr;
+  hipGraph_t hg = nullptr;
+  hipGraphExec_t hx = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  float last_ms = 0.0f;
+};
+
+static void batch_drop_graph(gi_batch* b) {
+  if (b->hx) (void)hipGraphExecDestroy(b->hx);
+  if (b->hg) (void)hipGraphDestroy(b->hg);
+  b->hx = nullptr;
+  b->hg = nullptr;
+}
+
+extern "C" gi_status gi_batch_destroy(gi_batch* b) {
+  if (!b) return GI_OK;
+  (void)hipDeviceSynchronize();
+  batch_drop_graph(b);
+  for (void* q : b->work) (void)hipFree(q);
+  for (void* q : {(void*)b->d_graphs, (void*)b->d_tasks, (void*)b->d_ctl, (void*)b->d_items,
+                  (void*)b->d_wg_off, (void*)b->d_err})
+    if (q) (void)hipFree(q);
+  for (hipEvent_t e : b->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (b->gstream) (void)hipStreamDestroy(b->gstream);
+  delete b;
+  return GI_OK;
+}
+
+template <typename T>
+static gi_status batch_alloc(gi_batch* b, T** p, size_t count) {
+  void* q = nullptr;
+  if (hipMalloc(&q, std::max<size_t>(1, count * sizeof(T))) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(GI_ERR_OUT_OF_MEMORY, "batch workspace allocation failed");
+  }
+  b->work.push_back(q);
+  *p = static_cast<T*>(q);
+  return GI_OK;
+}
+
+static BatchGraph batch_graph(const gi_graph* g) {
+  BatchGraph d;
+  d.n = g->n;
+  d.m = g->m;
+  d.out_off = g->out_off;
+  d.out_idx = g->out_idx;
+  d.in_off = g->in_off;
+  d.in_idx = g->in_idx;
+  d.outdeg = g->outdeg;
+  d.pr_table = g->pr_table;
+  d.pr_ntab = g->pr_ntab;
+  d.pr_cap_e = g->pr_cap_e;
+  d.lr_chunks = g->lr_chunks;
+  d.n_long = g->pr_nlong;
+  return d;
+}
+
+// Workgroup lists: tasks in decreasing estimated time; each takes the k
+// workgroups with the least load so far.  Every list follows that one order.
+static gi_status batch_plan(gi_batch* b) {
+  const int nt = (int)b->tasks.size();
+  std::vector<int> order((size_t)nt);
+  for (int i = 0; i < nt; ++i) order[(size_t)i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return b->est[(size_t)x] > b->est[(size_t)y]; });
+  int maxk = 1;
+  for (int i = 0; i < nt; ++i) maxk = std::max(maxk, b->k[(size_t)i]);
+  b->grid = std::min(b->max_grid, std::max(maxk, 1));
+  // grow the grid to the resident limit when the work can use it
+  long long want = 0;
+  for (int i = 0; i < nt; ++i) want += b->k[(size_t)i];
+  b->grid = (int)std::min<long long>(b->max_grid, std::max<long long>(b->grid, want));
+  const int G = b->grid;
+  std::vector<double> load((size_t)G, 0.0);
+  std::vector<std::vector<int2>> lists((size_t)G);
+  std::vector<int> idx((size_t)G);
+  for (int t : order) {
+    const int k = std::min(b->k[(size_t)t], G);
+    b->k[(size_t)t] = k;
+    for (int w = 0; w < G; ++w) idx[(size_t)w] = w;
+    std::partial_sort(idx.begin(), idx.begin() + k, idx.end(), [&](int x, int y) {
+      return load[(size_t)x] < load[(size_t)y] || (load[(size_t)x] == load[(size_t)y] && x < y);
+    });
+    for (int r = 0; r < k; ++r) {
+      const int w = idx[(size_t)r];
+      lists[(size_t)w].push_back(make_int2(t, r));
+      load[(size_t)w] += b->est[(size_t)t];
+    }
+  }
+  std::vector<int> off((size_t)G + 1, 0);
+  std::vector<int2> items;
+  for (int w = 0; w < G; ++w) {
+    off[(size_t)w] = (int)items.size();
+    items.insert(items.end(), lists[(size_t)w].begin(), lists[(size_t)w].end());
+  }
+  off[(size_t)G] = (int)items.size();
+  for (void* q : {(void*)b->d_items, (void*)b->d_wg_off})
+    if (q) (void)hipFree(q);
+  b->d_items = nullptr;
+  b->d_wg_off = nullptr;
+  if (hipMalloc((void**)&b->d_items, sizeof(int2) * std::max<size_t>(1, items.size())) != hipSuccess ||
+      hipMalloc((void**)&b->d_wg_off, sizeof(int) * off.size()) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(GI_ERR_OUT_OF_MEMORY, "batch plan allocation failed");
+  }
+  HIP_TRY(hipMemcpy(b->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_wg_off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
+  for (int t = 0; t < nt; ++t) b->h_tasks[(size_t)t].k = b->k[(size_t)t];
+  HIP_TRY(hipMemcpy(b->d_tasks, b->h_tasks.data(), sizeof(BatchTask) * (size_t)nt,
+                    hipMemcpyHostToDevice));
+  batch_drop_graph(b);
+  return GI_OK;
+}
+
+extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, const gi_task* tasks,
+                                     int32_t ntasks, gi_batch** out) {
+  if (!out) return fail(GI_ERR_INVALID_ARG, "NULL output handle");
+  *out = nullptr;
+  if (!graphs || ngraphs < 1 || !tasks || ntasks < 1 || ntasks > (1 << 20))
+    return fail(GI_ERR_INVALID_ARG, "need graphs and tasks");
+  for (int i = 0; i < ngraphs; ++i)
+    if (!graphs[i]) return fail(GI_ERR_INVALID_ARG, "graph %d is NULL", i);
+  for (int i = 0; i < ntasks; ++i) {
+    const gi_task& t = tasks[i];
+    if (t.graph < 0 || t.graph >= ngraphs) return fail(GI_ERR_INVALID_ARG, "task %d: bad graph", i);
+    if (t.algorithm != GI_ALG_BFS && t.algorithm != GI_ALG_PAGERANK)
+      return fail(GI_ERR_INVALID_ARG, "task %d: algorithm must be BFS or PageRank", i);
+    if (!t.out) return fail(GI_ERR_INVALID_ARG, "task %d: NULL output", i);
+    const gi_graph* g = graphs[t.graph];
+    if (t.algorithm == GI_ALG_BFS && (t.src < 0 || t.src >= g->n))
+      return fail(GI_ERR_INVALID_ARG, "task %d: source outside the graph", i);
+    if (t.algorithm == GI_ALG_PAGERANK &&
+        (t.iters < 0 || !(t.damping >= 0.0f && t.damping <= 1.0f)))
+      return fail(GI_ERR_INVALID_ARG, "task %d: bad PageRank parameters", i);
+    if (t.workgroups < 0 || t.workgroups > 1024)
+      return fail(GI_ERR_INVALID_ARG, "task %d: workgroups outside [0, 1024]", i);
+  }
+  gi_batch* b = new (std::nothrow) gi_batch();
+  if (!b) return fail(GI_ERR_OUT_OF_MEMORY, "host allocation failed");
+  b->graphs.assign(graphs, graphs + ngraphs);
+  b->tasks.assign(tasks, tasks + ntasks);
+  auto bail = [&](gi_status st) {
+    gi_batch_destroy(b);
+    return st;
+  };
+  int cap_e = 256;
+  for (gi_graph* g : b->graphs) {
+    cap_e = std::max(cap_e, g->pr_cap_e);
+    b->shape.push_back(make_int2(g->pr_cap_e, g->pr_nlong));
+  }
+  b->cap_e = cap_e;
+  b->lds = batch_lds_bytes(cap_e, std::min(cap_e, 1024));
+  int dev = 0, cus = 0, rate = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate <= 0)
+    rate = 100000;  // kHz
+  b->spin_limit = 2000LL * rate;  // two seconds of wall clock
+  const int occ = batch_occupancy(b->lds);
+  if (occ < 1) return bail(fail(GI_ERR_DEVICE, "batch kernel does not fit on a compute unit"));
+  // resident by construction: at most the occupancy (and at most 4 per CU)
+  b->max_grid = cus * std::min(occ, 4);
+  gi_status st;
+  const size_t nt = (size_t)ntasks;
+  b->h_tasks.resize(nt);
+  b->k.resize(nt);
+  b->est.resize(nt);
+  for (size_t i = 0; i < nt; ++i) {
+    const gi_task& t = b->tasks[i];
+    const gi_graph* g = b->graphs[(size_t)t.graph];
+    BatchTask& d = b->h_tasks[i];
+    d = BatchTask{};
+    d.alg = t.algorithm == GI_ALG_BFS ? ALG_BFS : ALG_PR;
+    d.graph = t.graph;
+    d.src = t.src;
+    d.iters = t.iters;
+    d.damping = t.damping;
+    d.out = t.out;
+    const size_t W = ((size_t)g->n + 63) / 64;
+    if (d.alg == ALG_BFS) {
+      if ((st = batch_alloc(b, &d.vis, 4 * W)) != GI_OK) return bail(st);
+      d.bv0 = d.vis + W;
+      d.bv1 = d.vis + 2 * W;
+      d.bv2 = d.vis + 3 * W;
+    } else {
+      if ((st = batch_alloc(b, &d.c0, 2 * (size_t)g->n)) != GI_OK) return bail(st);
+      d.c1 = d.c0 + g->n;
+      if ((st = batch_alloc(b, &d.lr_acc, (size_t)std::max(1, g->pr_nlong))) != GI_OK) return bail(st);
+      if ((st = batch_alloc(b, &d.lr_cnt, (size_t)std::max(1, g->pr_nlong))) != GI_OK) return bail(st);
+    }
+    // default size: one workgroup per 64K edges of work, power of two <= 64
+    const double work = (double)std::max<int64_t>(g->m, g->n) * (d.alg == ALG_PR ? std::max(1, t.iters) : 1);
+    int k = 1;
+    while (k < 64 && (double)k * 65536.0 < (double)std::max<int64_t>(g->m, g->n)) k *= 2;
+    b->k[i] = t.workgroups > 0 ? t.workgroups : k;
+    b->est[i] = work / b->k[i];
+  }
+  if (hipMalloc((void**)&b->d_graphs, sizeof(BatchGraph) * (size_t)ngraphs) != hipSuccess ||
+      hipMalloc((void**)&b->d_tasks, sizeof(BatchTask) * nt) != hipSuccess ||
+      hipMalloc((void**)&b->d_ctl, sizeof(TaskCtl) * nt) != hipSuccess ||
+      hipMalloc((void**)&b->d_err, sizeof(int)) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(GI_ERR_OUT_OF_MEMORY, "batch allocation failed"));
+  }
+  for (size_t i = 0; i < nt; ++i) b->h_tasks[i].ctl = b->d_ctl + i;
+  for (hipEvent_t* e : {&b->ev[0], &b->ev[1]})
+    if (hipEventCreate(e) != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(fail(GI_ERR_DEVICE, "hipEventCreate failed"));
+    }
+  if (hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(GI_ERR_DEVICE, "stream creation failed"));
+  }
+  if ((st = batch_plan(b)) != GI_OK) return bail(st);
+  *out = b;
+  return GI_OK;
+}
+
+static BatchArgs batch_args(const gi_batch* b, const int2* items, const int* wg_off) {
+  BatchArgs a;
+  a.graphs = b->d_graphs;
+  a.tasks = b->d_tasks;
+  a.items = items;
+  a.wg_off = wg_off;
+  a.error = b->d_err;
+  a.spin_limit = b->spin_limit;
+  a.lds_cap_e = b->cap_e;
+  return a;
+}
+
+static gi_status batch_refresh_graphs(gi_batch* b) {
+  std::vector<BatchGraph> hg;
+  for (size_t i = 0; i < b->graphs.size(); ++i) {
+    const gi_graph* g = b->graphs[i];
+    if (g->pr_cap_e != b->shape[i].x || g->pr_nlong != b->shape[i].y)
+      return fail(GI_ERR_INVALID_ARG, "graph %zu changed its PageRank blocks after batch creation", i);
+    hg.push_back(batch_graph(g));
+  }
+  HIP_TRY(hipMemcpy(b->d_graphs, hg.data(), sizeof(BatchGraph) * hg.size(), hipMemcpyHostToDevice));
+  return GI_OK;
+}
+
+static gi_status batch_check_error(gi_batch* b) {
+  int err = 0;
+  HIP_TRY(hipMemcpy(&err, b->d_err, sizeof(int), hipMemcpyDeviceToHost));
+  if (err == 1) return fail(GI_ERR_DEVICE, "batch barrier wait timed out");
+  if (err) return fail(GI_ERR_DEVICE, "batch BFS exceeded n levels");
+  return GI_OK;
+}
+
+extern "C" gi_status gi_batch_run(gi_batch* b, int32_t use_graph, void* stream) {
+  if (!b) return fail(GI_ERR_INVALID_ARG, "NULL batch");
+  gi_status st = batch_refresh_graphs(b);
+  if (st != GI_OK) return st;
+  const int nt = (int)b->tasks.size();
+  const BatchArgs a = batch_args(b, b->d_items, b->d_wg_off);
+  if (use_graph) {
+    if (!b->hx) {
+      HIP_TRY(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal));
+      const int lr = launch_batch(a, b->grid, b->lds, b->d_ctl, nt, b->gstream);
+      hipGraph_t gcap = nullptr;
+      const hipError_t ce = hipStreamEndCapture(b->gstream, &gcap);
+      if (lr != 0 || ce != hipSuccess) {
+        if (gcap) (void)hipGraphDestroy(gcap);
+        (void)hipGetLastError();
+        return fail(GI_ERR_DEVICE, "batch graph capture failed");
+      }
+      b->hg = gcap;
+      if (hipGraphInstantiate(&b->hx, b->hg, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        batch_drop_graph(b);
+        return fail(GI_ERR_DEVICE, "batch graph instantiation failed");
+      }
+    }
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    HIP_TRY(hipEventRecord(b->ev[0], b->gstream));
+    HIP_TRY(hipGraphLaunch(b->hx, b->gstream));
+    HIP_TRY(hipEventRecord(b->ev[1], b->gstream));
+    HIP_TRY(hipEventSynchronize(b->ev[1]));
+  } else {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipEventRecord(b->ev[0], s));
+    LAUNCH_TRY(launch_batch(a, b->grid, b->lds, b->d_ctl, nt, s));
+    HIP_TRY(hipEventRecord(b->ev[1], s));
+    HIP_TRY(hipEventSynchronize(b->ev[1]));
+  }
+  HIP_TRY(hipEventElapsedTime(&b->last_ms, b->ev[0], b->ev[1]));
+  return batch_check_error(b);
+}
+
+// Time one task alone on k workgroups (median of reps launches).
+static gi_status batch_time_task(gi_batch* b, int t, int k, int reps, float* ms) {
+  std::vector<int2> items((size_t)k);
+  std::vector<int> off((size_t)k + 1);
+  for (int r = 0; r < k; ++r) {
+    items[(size_t)r] = make_int2(t, r);
+    off[(size_t)r] = r;
+  }
+  off[(size_t)k] = k;
+  BatchTask saved = b->h_tasks[(size_t)t];
+  b->h_tasks[(size_t)t].k = k;
+  HIP_TRY(hipMemcpy(b->d_tasks + t, &b->h_tasks[(size_t)t], sizeof(BatchTask), hipMemcpyHostToDevice));
+  int2* di = nullptr;
+  int* doff = nullptr;
+  gi_status st = GI_OK;
+  if (hipMalloc((void**)&di, sizeof(int2) * (size_t)k) != hipSuccess ||
+      hipMalloc((void**)&doff, sizeof(int) * (size_t)(k + 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    st = fail(GI_ERR_OUT_OF_MEMORY, "tuning buffers");
+  }
+  if (st == GI_OK && (hipMemcpy(di, items.data(), sizeof(int2) * (size_t)k, hipMemcpyHostToDevice) != hipSuccess ||
+                      hipMemcpy(doff, off.data(), sizeof(int) * (size_t)(k + 1), hipMemcpyHostToDevice) != hipSuccess))
+    st = fail(GI_ERR_DEVICE, "tuning upload failed");
+  std::vector<float> times;
+  const BatchArgs a = batch_args(b, di, doff);
+  for (int rep = 0; rep < reps && st == GI_OK; ++rep) {
+    float x = 0.0f;
+    if (hipEventRecord(b->ev[0], nullptr) != hipSuccess ||
+        launch_batch(a, k, b->lds, b->d_ctl, (int)b->tasks.size(), nullptr) != 0 ||
+        hipEventRecord(b->ev[1], nullptr) != hipSuccess ||
+        hipEventSynchronize(b->ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&x, b->ev[0], b->ev[1]) != hipSuccess) {
+      st = fail(GI_ERR_DEVICE, "tuning launch failed: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    if ((st = batch_check_error(b)) != GI_OK) break;
+    times.push_back(x);
+  }
+  if (di) (void)hipFree(di);
+  if (doff) (void)hipFree(doff);
+  b->h_tasks[(size_t)t] = saved;
+  if (hipMemcpy(b->d_tasks + t, &saved, sizeof(BatchTask), hipMemcpyHostToDevice) != hipSuccess && st == GI_OK)
+    st = fail(GI_ERR_DEVICE, "tuning restore failed");
+  if (st != GI_OK) return st;
+  std::sort(times.begin(), times.end());
+  *ms = times[times.size() / 2];
+  return GI_OK;
+}
+
+extern "C" gi_status gi_batch_autotune(gi_batch* b, int32_t reps) {
+  if (!b || reps < 1) return fail(GI_ERR_INVALID_ARG, "bad autotune arguments");
+  gi_status st = batch_refresh_graphs(b);
+  if (st != GI_OK) return st;
+  HIP_TRY(hipDeviceSynchronize());
+  const int nt = (int)b->tasks.size();
+  // one representative per (graph, algorithm, iterations) class
+  std::vector<int> rep_of((size_t)nt, -1);
+  std::vector<int> reps_list;
+  for (int t = 0; t < nt; ++t) {
+    const gi_task& x = b->tasks[(size_t)t];
+    for (int q : reps_list) {
+      const gi_task& y = b->tasks[(size_t)q];
+      if (x.graph == y.graph && x.algorithm == y.algorithm &&
+          (x.algorithm == GI_ALG_BFS || x.iters == y.iters)) {
+        rep_of[(size_t)t] = q;
+        break;
+      }
+    }
+    if (rep_of[(size_t)t] < 0) {
+      rep_of[(size_t)t] = t;
+      reps_list.push_back(t);
+    }
+  }
+  std::vector<int> best_k((size_t)nt, 1), fast_k((size_t)nt, 1);
+  std::vector<double> best_t((size_t)nt, 0.0), fast_t((size_t)nt, 0.0);
+  for (int q : reps_list) {
+    double bw = 1e300, bt = 0.0, ft = 1e300;
+    int bk = 1, fk = 1;
+    for (int k = 1; k <= std::min(64, b->max_grid); k *= 2) {
+      float ms = 0.0f;
+      if ((st = batch_time_task(b, q, k, reps, &ms)) != GI_OK) return st;
+      // least workgroup-time (throughput), unless more than twice as slow as the fastest
+      if ((double)k * ms < bw) {
+        bw = (double)k * ms;
+        bk = k;
+        bt = ms;
+      }
+      if (ms < ft) {
+        ft = ms;
+        fk = k;
+      }
+    }
+    if (bt > 2.0 * ft) {
+      bk = fk;
+      bt = ft;
+    }
+    best_k[(size_t)q] = bk;
+    best_t[(size_t)q] = bt;
+    fast_k[(size_t)q] = fk;
+    fast_t[(size_t)q] = ft;
+  }
+  double total = 0.0;
+  for (int t = 0; t < nt; ++t) {
+    if (b->tasks[(size_t)t].workgroups > 0) continue;
+    const int q = rep_of[(size_t)t];
+    b->k[(size_t)t] = best_k[(size_t)q];
+    b->est[(size_t)t] = best_t[(size_t)q];
+    total += best_k[(size_t)q] * best_t[(size_t)q];
+  }
+  // a task longer than the balanced share of the grid sets the makespan:
+  // give it its fastest size instead
+  const double share = total / std::max(1, b->max_grid);
+  for (int t = 0; t < nt; ++t) {
+    if (b->tasks[(size_t)t].workgroups > 0) continue;
+    const int q = rep_of[(size_t)t];
+    if (b->est[(size_t)t] > share && fast_t[(size_t)q] < b->est[(size_t)t]) {
+      b->k[(size_t)t] = fast_k[(size_t)q];
+      b->est[(size_t)t] = fast_t[(size_t)q];
+    }
+  }
+  return batch_plan(b);
+}
+
+extern "C" gi_status gi_batch_info(const gi_batch* b, float* last_ms, int32_t* grid,
+                                   int32_t* workgroups, int32_t* levels) {
+  if (!b) return fail(GI_ERR_INVALID_ARG, "NULL batch");
+  if (last_ms) *last_ms = b->last_ms;
+  if (grid) *grid = b->grid;
+  const size_t nt = b->tasks.size();
+  if (workgroups)
+    for (size_t i = 0; i < nt; ++i) workgroups[i] = b->k[i];
+  if (levels) {
+    std::vector<TaskCtl> c(nt);
+    HIP_TRY(hipMemcpy(c.data(), b->d_ctl, sizeof(TaskCtl) * nt, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < nt; ++i) levels[i] = c[i].levels;
+  }
   return GI_OK;
 }

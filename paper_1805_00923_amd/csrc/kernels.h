@@ -150,6 +150,66 @@ int launch_mlp_train(const TrainArgs& a, hipStream_t s);
 int launch_mlp_predict(const SelDev& sd, const float* x, long long n, bool bf16, float* out,
                        hipStream_t s);
 
+// Batched persistent execution (batch.hip).
+struct BatchGraph {
+  int n;
+  long long m;
+  const int32_t* out_off;
+  const int32_t* out_idx;
+  const int32_t* in_off;
+  const int32_t* in_idx;
+  const int32_t* outdeg;
+  const int4* pr_table;  // PageRank destination blocks (the graph's current schedule)
+  int pr_ntab;
+  int pr_cap_e;
+  const int32_t* lr_chunks;
+  int n_long;            // rows split into chunks
+};
+
+struct TaskCtl {
+  unsigned bar_cnt;
+  unsigned bar_gen;
+  unsigned long long qn[3];  // BFS frontier sizes, rotating
+  unsigned long long ds[3];  // their degree sums
+  int levels;                // BFS levels / PageRank iterations completed
+  int pad[9];
+};
+
+struct BatchTask {
+  int alg;      // ALG_BFS or ALG_PR
+  int graph;
+  int src;
+  int iters;
+  float damping;
+  int k;        // workgroups
+  void* out;    // int32 levels or float ranks
+  uint64_t* vis;
+  uint64_t* bv0;
+  uint64_t* bv1;
+  uint64_t* bv2;
+  float* c0;
+  float* c1;
+  double* lr_acc;
+  unsigned* lr_cnt;
+  TaskCtl* ctl;
+};
+
+struct BatchArgs {
+  const BatchGraph* graphs;
+  const BatchTask* tasks;
+  const int2* items;   // (task, rank) per workgroup list entry
+  const int* wg_off;   // list of workgroup w: items[wg_off[w] .. wg_off[w+1])
+  int* error;          // set when a barrier wait timed out
+  long long spin_limit;  // wall-clock ticks a barrier may wait
+  int lds_cap_e;
+};
+
+int batch_threads();
+size_t batch_lds_bytes(int cap_e, int cap_v);
+int batch_occupancy(size_t lds);
+int launch_batch(const BatchArgs& a, int grid, size_t lds, TaskCtl* ctl, int ntasks,
+                 hipStream_t s);
+
 int launch_pr_init(int n, const int32_t* outdeg, float* c0, float* rank, bool zero_iters,
                    hipStream_t s);
 int launch_pr_rows(const PrRows& r, int cap_e, int cap_v, int bt, int grid, const float* cin,

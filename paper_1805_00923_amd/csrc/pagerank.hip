@@ -21,113 +21,9 @@
 // the contrib gathers of one segment touch only |V_i| entries; a final pass
 // applies the vertex update.
 #include "kernels.h"
+#include "pr_block.h"
 
 namespace gi {
-
-template <int BT>
-__device__ __forceinline__ double block_sum(double v) {
-  __shared__ double part[BT / kWave];
-  v = wave_sum(v);
-  if (__lane_id() == 0) part[threadIdx.x / kWave] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x < kWave) {
-    t = threadIdx.x < BT / kWave ? part[threadIdx.x] : 0.0;
-    t = wave_sum(t);
-  }
-  __syncthreads();
-  return t;  // valid in thread 0
-}
-
-// Sum over the edge range [eb, ee) of cin[idx[e]] by the whole workgroup,
-// four independent loads in flight per thread; result valid in thread 0.
-template <int BT>
-__device__ __forceinline__ double range_sum(const int32_t* __restrict__ idx,
-                                            const float* __restrict__ cin, int eb, int ee) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int e = eb + (int)threadIdx.x;
-  for (; e + 3 * BT < ee; e += 4 * BT) {
-    const int a0 = idx[e], a1 = idx[e + BT], a2 = idx[e + 2 * BT], a3 = idx[e + 3 * BT];
-    s0 += (double)cin[a0];
-    s1 += (double)cin[a1];
-    s2 += (double)cin[a2];
-    s3 += (double)cin[a3];
-  }
-  for (; e < ee; e += BT) s0 += (double)cin[idx[e]];
-  return block_sum<BT>((s0 + s1) + (s2 + s3));
-}
-
-// mode 0: final vertex update from the full sum; mode 1: acc[dst] += sum.
-template <int BT>
-__device__ void pr_rows_block(const PrRows& r, int t, int cap_e, const float* __restrict__ cin,
-                              int mode, const PrVertex& pv, float* __restrict__ cout,
-                              float* __restrict__ rank, double* __restrict__ acc, float* lds_val,
-                              int* lds_off) {
-  const int4 en = r.table[t];
-  const int tid = threadIdx.x;
-  auto finish = [&](int row, double s) {
-    const int v = r.dst ? r.dst[row] : row;
-    if (mode == 1) {
-      acc[v] += s;
-    } else {
-      const double x = pv.base + pv.alpha * s;
-      if (rank) {
-        rank[v] = (float)x;
-      } else {
-        const int d = pv.outdeg[v];
-        cout[v] = d > 0 ? (float)(x / (double)d) : 0.0f;
-      }
-    }
-  };
-  if (en.z >= 0) {
-    // one chunk of a row longer than cap_e: partial sums meet in an FP64
-    // accumulator; the chunk that arrives last applies the vertex update
-    const int row = en.x;
-    const int rb = r.off[row], re = r.off[row + 1];
-    const int eb = rb + en.w * cap_e, ee = min(re, eb + cap_e);
-    const double s = range_sum<BT>(r.idx, cin, eb, ee);
-    if (tid == 0) {
-      if (mode == 1) {
-        atomicAdd(&acc[r.dst ? r.dst[row] : row], s);
-      } else {
-        atomicAdd(&r.lr_acc[en.z], s);
-        __threadfence();
-        const unsigned done = atomicAdd(&r.lr_cnt[en.z], 1u);
-        if (done == (unsigned)r.lr_chunks[en.z] - 1u) {
-          __threadfence();
-          const double tot = atomicAdd(&r.lr_acc[en.z], 0.0);
-          __hip_atomic_store(&r.lr_acc[en.z], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(&r.lr_cnt[en.z], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          finish(row, tot);
-        }
-      }
-    }
-    return;
-  }
-  const int kb = en.x, ke = en.y, nr = ke - kb;
-  const int e0 = r.off[kb], e1 = r.off[ke], ne = e1 - e0;
-  gather_block<BT, float>(r.idx, e0, ne, lds_val, [cin](int u) { return cin[u]; });
-  for (int k = tid; k <= nr; k += BT) lds_off[k] = r.off[kb + k] - e0;
-  __syncthreads();
-  int tpv = 1;
-  if (nr < BT) {
-    tpv = BT / (nr > 0 ? nr : 1);
-    tpv = 1 << (31 - __clz(tpv));
-    if (tpv > kWave) tpv = kWave;
-  }
-  const int groups = BT / tpv, grp = tid / tpv, gl = tid % tpv;
-  for (int k0 = 0; k0 < nr; k0 += groups) {
-    const int k = k0 + grp;
-    double s = 0.0;
-    if (k < nr) {
-      const int a = lds_off[k], b = lds_off[k + 1];
-      for (int j = a + gl; j < b; j += tpv) s += (double)lds_val[j];
-    }
-    for (int o = tpv >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
-    if (gl == 0 && k < nr) finish(kb + k, s);
-  }
-  __syncthreads();
-}
 
 // contrib_0[v] = (1/n)/outdeg(v); with zero iterations the ranks are 1/n.
 __device__ __forceinline__ void pr_init_range(int i0, int stride, int n, const int32_t* outdeg,

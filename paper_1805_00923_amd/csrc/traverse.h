@@ -330,15 +330,18 @@ __device__ void expand_chunks(const ExpandArgs& a, Visit& vis, int* lds) {
 // remaining short rows of a wave are gathered with a wave prefix sum so that
 // 64 consecutive lanes take 64 consecutive edge slots.
 
+// Vertices [vb, ve) are taken BT at a time by workgroups first_block,
+// first_block + nblocks, ...
 template <int BT, class Visit>
-__device__ void dense_push_expand(const DenseSet& fr, int n, const int32_t* off, Visit& vis) {
+__device__ void dense_push_range(const DenseSet& fr, int vb, int ve, int first_block, int nblocks,
+                                 const int32_t* off, Visit& vis) {
   __shared__ int sh_owner, sh_u, sh_b, sh_e;
   const int tid = threadIdx.x;
   const int lane = __lane_id();
-  for (int base = blockIdx.x * BT; base < n; base += gridDim.x * BT) {
+  for (int base = vb + first_block * BT; base < ve; base += nblocks * BT) {
     const int i = base + tid;
     int u = -1, beg = 0, end = 0;
-    if (i < n && fr.test(i)) {
+    if (i < ve && fr.test(i)) {
       u = i;
       beg = off[i];
       end = off[i + 1];
@@ -391,6 +394,11 @@ __device__ void dense_push_expand(const DenseSet& fr, int n, const int32_t* off,
       vis(cu, cb + (j - ex), j < total);
     }
   }
+}
+
+template <int BT, class Visit>
+__device__ void dense_push_expand(const DenseSet& fr, int n, const int32_t* off, Visit& vis) {
+  dense_push_range<BT>(fr, 0, n, blockIdx.x, gridDim.x, off, vis);
 }
 
 // --------------------------------------------------- row-block gathers ----

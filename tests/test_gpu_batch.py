@@ -1,0 +1,126 @@
+"""GPU parity of the batched persistent path: BFS levels of every task equal
+the oracle's, PageRank ranks are within 1e-6 of the fp64 oracle, on a pool of
+graphs of uneven size; the same after autotuning, launched directly and
+replayed from a HIP graph several times with other work in between."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from gpu_util import PR_RTOL, device_graph, pr_max_rel, say
+
+pytestmark = pytest.mark.gpu
+
+_POOL = None
+
+
+def pool():
+    global _POOL
+    if _POOL is None:
+        els = [gg.rmat(8, seed=101), gg.rmat(11, seed=102), gg.rmat(13, seed=103),
+               gg.grid(30, 41, 0.0, weighted=False), gg.path(500), gg.empty(33),
+               gg.uniform(20000, 90000, seed=104)]
+        _POOL = [(el, device_graph(el), oracle.Graph(el)) for el in els]
+    return _POOL
+
+
+def make_tasks(torch, ntasks, seed=0):
+    rng = np.random.default_rng(seed)
+    P = pool()
+    tasks = []
+    for i in range(ntasks):
+        gidx = int(rng.integers(len(P)))
+        el, g, og = P[gidx]
+        if i % 2 == 0:
+            src = int(rng.integers(g.n))
+            out = torch.full((g.n,), -9, dtype=torch.int32, device="cuda:0")
+            tasks.append(dict(graph=gidx, algorithm=1, src=src, out=out))
+        else:
+            iters = int(rng.choice([0, 1, 7, 20]))
+            out = torch.full((g.n,), -1.0, dtype=torch.float32, device="cuda:0")
+            tasks.append(dict(graph=gidx, algorithm=0, iters=iters, damping=0.85, out=out))
+    return tasks
+
+
+def check(tasks):
+    P = pool()
+    for i, t in enumerate(tasks):
+        el, g, og = P[t["graph"]]
+        got = t["out"].cpu().numpy()
+        if t["algorithm"] == 1:
+            ref = oracle.bfs(og, t["src"])[0]
+            assert np.array_equal(got, ref), (i, el.name, t["src"])
+        else:
+            ref = oracle.pagerank(og, t["iters"], 0.85)
+            assert pr_max_rel(got, ref) <= PR_RTOL, (i, el.name, t["iters"])
+
+
+def test_batch_matches_oracle():
+    import torch
+    import paper_1805_00923_amd as gi
+    P = pool()
+    tasks = make_tasks(torch, 40)
+    say("batch create 40 tasks")
+    b = gi.Batch([g for _, g, _ in P], tasks)
+    say("batch run direct")
+    b.run(use_graph=False)
+    torch.cuda.synchronize()
+    check(tasks)
+    info = b.info()
+    assert info["grid"] >= 1 and np.all(info["workgroups"] >= 1)
+    for i, t in enumerate(tasks):
+        if t["algorithm"] == 0:
+            assert info["levels"][i] == t["iters"]
+    b.close()
+
+
+def test_batch_fixed_workgroups_and_graph_replays():
+    import torch
+    import paper_1805_00923_amd as gi
+    P = pool()
+    tasks = make_tasks(torch, 24, seed=1)
+    for i, t in enumerate(tasks):
+        t["workgroups"] = [1, 2, 3, 5, 8, 16][i % 6]
+    b = gi.Batch([g for _, g, _ in P], tasks)
+    for rep in range(3):
+        for t in tasks:   # eager work between replays
+            t["out"].fill_(-5 if t["algorithm"] == 1 else -2.0)
+        torch.cuda.synchronize()
+        say("batch graph replay %d" % rep)
+        b.run(use_graph=True)
+        torch.cuda.synchronize()
+        check(tasks)
+    assert list(b.info()["workgroups"]) == [t["workgroups"] for t in tasks]
+    b.close()
+
+
+def test_batch_autotune_keeps_results():
+    import torch
+    import paper_1805_00923_amd as gi
+    P = pool()
+    tasks = make_tasks(torch, 32, seed=2)
+    b = gi.Batch([g for _, g, _ in P], tasks)
+    say("batch autotune")
+    b.autotune(reps=2)
+    for rep in range(2):
+        say("batch run after autotune %d" % rep)
+        b.run(use_graph=bool(rep))
+        torch.cuda.synchronize()
+        check(tasks)
+    b.close()
+
+
+def test_batch_argument_errors():
+    import torch
+    import paper_1805_00923_amd as gi
+    P = pool()
+    g = P[0][1]
+    out = torch.zeros(g.n, dtype=torch.int32, device="cuda:0")
+    with pytest.raises(gi.GiError):
+        gi.Batch([g], [dict(graph=1, algorithm=1, src=0, out=out)])
+    with pytest.raises(gi.GiError):
+        gi.Batch([g], [dict(graph=0, algorithm=1, src=g.n, out=out)])
+    with pytest.raises(gi.GiError):
+        gi.Batch([g], [dict(graph=0, algorithm=2, out=out)])
+    with pytest.raises(gi.GiError):
+        gi.Batch([g], [dict(graph=0, algorithm=0, iters=-1, out=out)])
