@@ -46,7 +46,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="bfs_cc_rmat22",
-                    choices=["bfs_cc_rmat22", "pr_rmat16", "pr_rmat22", "sssp_grid", "selector"])
+                    choices=["bfs_cc_rmat22", "pr_rmat16", "pr_rmat22", "sssp_grid", "selector",
+                             "batched"])
     ap.add_argument("--heldout", default="small", choices=["small", "full"],
                     help="selector workload: held-out Chung-Lu graph with 4M vertices (small) "
                          "or 41M vertices and ~1.4B edges (full)")
@@ -492,6 +493,103 @@ def run_selector(args, torch, dev):
         config, roof, None, detail
 
 
+def run_batched(args, torch, dev):
+    """256 instances (even: BFS, odd: 20-iteration PageRank) over a pool of 14
+    graphs: R-MAT scales 10..18 (seeds 100 + scale) and 4-neighbour grids
+    64^2 .. 1024^2; BFS sources seeded per instance (seed 200 + i).  One
+    persistent launch replayed from a HIP graph, workgroups autotuned, against
+    256 sequential calls of the plain entry points on the same stream."""
+    import numpy as np
+
+    import graphgen as gg
+    import paper_1805_00923_amd as gi
+    els = [gg.rmat(s, 16, seed=100 + s) for s in range(10, 19)]
+    els += [gg.grid(d, d, 0.0, weighted=False) for d in (64, 128, 256, 512, 1024)]
+    graphs = [gi.Graph.from_edges(el.n, el.src, el.dst) for el in els]
+    tasks, edges = [], 0
+    for i in range(256):
+        gidx = i % len(graphs)
+        g, el = graphs[gidx], els[gidx]
+        if i % 2 == 0:
+            src = int(gg.pick_sources(el, 1, 200 + i)[0])
+            out = torch.empty(g.n, dtype=torch.int32, device=dev)
+            tasks.append(dict(graph=gidx, algorithm=gi.ALG_BFS, src=src, out=out))
+        else:
+            out = torch.empty(g.n, dtype=torch.float32, device=dev)
+            tasks.append(dict(graph=gidx, algorithm=gi.ALG_PAGERANK, iters=20, damping=0.85,
+                              out=out))
+    # plain path: one call per instance, same stream
+    ref = [torch.empty_like(t["out"]) for t in tasks]
+
+    def plain():
+        for t, r in zip(tasks, ref):
+            g = graphs[t["graph"]]
+            if t["algorithm"] == gi.ALG_BFS:
+                g.bfs(t["src"], r)
+            else:
+                g.pagerank(r, 20, 0.85)
+        torch.cuda.synchronize()
+    # edges traversed per pass (TEPS convention: BFS m_reach, PageRank 20 m)
+    plain()
+    for t, r in zip(tasks, ref):
+        g = graphs[t["graph"]]
+        if t["algorithm"] == gi.ALG_BFS:
+            lv = r.cpu().numpy()
+            odeg = np.diff(g.out_off)
+            edges += int(odeg[lv >= 0].sum())
+        else:
+            edges += 20 * g.m
+    for _ in range(args.warmup):
+        plain()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plain()
+    t_plain = (time.perf_counter() - t0) / args.steps
+    b = gi.Batch(graphs, tasks)
+    t0 = time.perf_counter()
+    b.autotune(reps=3)
+    t_tune = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        b.run(use_graph=True)
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.run(use_graph=True)
+        kms.append(b.info()["ms"])
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    # outputs agree with the plain path
+    bad = 0
+    for t, r in zip(tasks, ref):
+        if t["algorithm"] == gi.ALG_BFS:
+            bad += int(not torch.equal(t["out"], r))
+        else:
+            x, y = t["out"].double(), r.double()
+            bad += int(((x - y).abs() / y).max().item() > 1e-6)
+    info = b.info()
+    value = edges / t_batch / 1e9
+    slow = np.argsort(-info["task_ms"])[:5]
+    detail = {"plain_ms": round(t_plain * 1e3, 3), "batched_ms": round(t_batch * 1e3, 3),
+              "batched_kernel_ms_median": round(float(np.median(kms)), 3),
+              "speedup_vs_plain": round(t_plain / t_batch, 3),
+              "plain_gteps": round(edges / t_plain / 1e9, 3),
+              "autotune_s": round(t_tune, 2), "grid": info["grid"],
+              "workgroups_per_graph": {els[i].name: sorted(set(int(info["workgroups"][j])
+                                                             for j in range(256)
+                                                             if tasks[j]["graph"] == i))
+                                       for i in range(len(els))},
+              "mismatches_vs_plain": bad, "edges_per_pass": edges,
+              "slowest_tasks": [{"graph": els[tasks[j]["graph"]].name,
+                                 "alg": "bfs" if tasks[j]["algorithm"] == gi.ALG_BFS else "pr",
+                                 "ms": round(float(info["task_ms"][j]), 3),
+                                 "levels": int(info["levels"][j]),
+                                 "workgroups": int(info["workgroups"][j])} for j in slow]}
+    config = {"workload": "batched256_bfs_pr20_rmat10-18_grid64-1024", "instances": 256,
+              "graphs": [el.name for el in els]}
+    return value, "GTEPS", t_batch * 1e3, "int32 / f32+f64", config, None, None, detail
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -512,6 +610,8 @@ def main():
         res = run_pr(args, torch, dev, 16)
     elif args.workload == "pr_rmat22":
         res = run_pr(args, torch, dev, 22)
+    elif args.workload == "batched":
+        res = run_batched(args, torch, dev)
     elif args.workload == "selector":
         res = run_selector(args, torch, dev)
     else:

@@ -394,10 +394,12 @@ gi_status gi_batch_autotune(gi_batch* b, int32_t reps);
 gi_status gi_batch_run(gi_batch* b, int32_t use_graph, void* stream);
 
 /* GPU time of the last run (ms), grid size, and per task (arrays of the
- * batch's task count, may be NULL) its workgroups and its completed BFS
- * levels or PageRank iterations.  Errors: INVALID_ARG, DEVICE. */
+ * batch's task count, may be NULL) its workgroups, its completed BFS
+ * levels or PageRank iterations, and its duration in the last run (ms, from
+ * the device wall clock, start to end of its first workgroup).
+ * Errors: INVALID_ARG, DEVICE. */
 gi_status gi_batch_info(const gi_batch* b, float* last_ms, int32_t* grid, int32_t* workgroups,
-                        int32_t* levels);
+                        int32_t* levels, float* task_ms);
 gi_status gi_batch_destroy(gi_batch* b);
 
 /* ---- frontier primitives (device, stream ordered) -------------------- */

@@ -121,7 +121,7 @@ _SIGS = {
     "gi_batch_create": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp]),
     "gi_batch_autotune": (ctypes.c_int, [_vp, _i32]),
     "gi_batch_run": (ctypes.c_int, [_vp, _i32, _vp]),
-    "gi_batch_info": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "gi_batch_info": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "gi_batch_destroy": (ctypes.c_int, [_vp]),
     "gi_get_step_times": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp]),
     "gi_frontier_sparse_to_bitvec": (ctypes.c_int, [_i32, _vp, _i32, _vp, _vp]),
@@ -481,6 +481,8 @@ class Batch:
         grid = ctypes.c_int32()
         wg = np.zeros(self.ntasks, np.int32)
         lv = np.zeros(self.ntasks, np.int32)
+        tm = np.zeros(self.ntasks, np.float32)
         _check(lib.gi_batch_info(self._h, ctypes.byref(ms), ctypes.byref(grid), wg.ctypes.data,
-                                 lv.ctypes.data))
-        return {"ms": ms.value, "grid": grid.value, "workgroups": wg, "levels": lv}
+                                 lv.ctypes.data, tm.ctypes.data))
+        return {"ms": ms.value, "grid": grid.value, "workgroups": wg, "levels": lv,
+                "task_ms": tm}

@@ -14,9 +14,10 @@
 //
 // BFS tasks: level-synchronous, direction chosen per level by the hybrid
 // rule of the frontier engine (DensePull when |F| + sum deg(F) > m / 20,
-// else push of the frontier members in the workgroup's vertex range with
-// degree binning); bitvector frontiers in three rotating buffers, so the
-// buffer cleared during a level is neither read nor written in it.
+// else push of the frontier members in the workgroup's word range, empty
+// words skipped, with degree binning); bitvector frontiers in three
+// rotating buffers, so the buffer cleared during a level is neither read
+// nor written in it.
 // PageRank tasks: the destination-block DensePull of pagerank.hip, blocks
 // dealt round-robin over the task's workgroups.
 #include "bfs_dev.h"
@@ -29,23 +30,31 @@ constexpr int kBB = 256;  // threads per workgroup
 
 __device__ __forceinline__ long long wall_ticks() { return (long long)wall_clock64(); }
 
-// Barrier of the k workgroups of one task.  Returns false once the batch
-// has failed (timeout here or elsewhere).
+// Barrier of the k workgroups of one task.  One 64-bit word holds
+// (generation << 32) | arrivals, so an arrival learns its generation from
+// the same atomic.  Every wave first waits for its own memory operations to
+// complete; then one thread per workgroup releases (writes its L2 back),
+// arrives, waits for the generation to move, and acquires (invalidates its
+// caches) for the whole workgroup: two cache maintenance operations per
+// workgroup and barrier rather than two per wave.  Returns false once the
+// batch has failed (timeout here or elsewhere).
 __device__ bool task_barrier(TaskCtl* c, int k, int* gerr, long long limit) {
   __shared__ int s_ok;
-  __threadfence();  // release this thread's writes
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     int ok = __hip_atomic_load(gerr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     if (ok && k > 1) {
-      const unsigned g = __hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned a = atomicAdd(&c->bar_cnt, 1u);
-      if (a == (unsigned)k - 1u) {
-        __hip_atomic_store(&c->bar_cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&c->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const unsigned long long old = atomicAdd(&c->bar, 1ull);
+      const unsigned long long gen = old >> 32;
+      if ((old & 0xffffffffull) == (unsigned long long)(k - 1)) {
+        __hip_atomic_store(&c->bar, (gen + 1ull) << 32, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
       } else {
         const long long t0 = wall_ticks();
-        while (__hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        while ((__hip_atomic_load(&c->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32) ==
+               gen) {
           if (__hip_atomic_load(gerr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
             ok = 0;
             break;
@@ -58,11 +67,12 @@ __device__ bool task_barrier(TaskCtl* c, int k, int* gerr, long long limit) {
           __builtin_amdgcn_s_sleep(2);
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __builtin_amdgcn_s_waitcnt(0);
     }
     s_ok = ok;
   }
   __syncthreads();
-  __threadfence();  // acquire: later loads see the other workgroups' writes
   return s_ok != 0;
 }
 
@@ -131,7 +141,7 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
     } else {
       BfsVisit vis{G.out_idx, level, nullptr, L + 1, b.next, t.vis};
       vis.deg = G.outdeg;
-      dense_push_range<kBB>(b.cur, v0, v1, 0, 1, G.out_off, vis);
+      push_words<kBB>(b.cur.bv, w0, w1, n, G.out_off, vis);
       found = vis.found;
       found_deg = vis.found_deg;
     }
@@ -191,8 +201,10 @@ __global__ __launch_bounds__(kBB) void k_batch(BatchArgs a) {
     const int2 it = a.items[i];
     const BatchTask& t = a.tasks[it.x];
     const BatchGraph& G = a.graphs[t.graph];
+    if (it.y == 0 && threadIdx.x == 0) t.ctl->t_begin = wall_ticks();
     if (t.alg == ALG_BFS) bfs_task(G, t, it.y, a);
     else pr_task(G, t, it.y, a, lds_val, lds_off);
+    if (it.y == 0 && threadIdx.x == 0) t.ctl->t_end = wall_ticks();
   }
 }
 

@@ -1615,6 +1615,7 @@ struct gi_batch {
   size_t lds = 0;
   int cap_e = 0;
   long long spin_limit = 0;
+  int clock_khz = 100000;
   BatchGraph* d_graphs = nullptr;
   BatchTask* d_tasks = nullptr;
   TaskCtl* d_ctl = nullptr;
@@ -1682,8 +1683,12 @@ static BatchGraph batch_graph(const gi_graph* g) {
   return d;
 }
 
-// Workgroup lists: tasks in decreasing estimated time; each takes the k
-// workgroups with the least load so far.  Every list follows that one order.
+// Workgroup lists: tasks in decreasing estimated time; a task of k
+// workgroups goes to the aligned block of pow2ceil(k) workgroups whose first
+// k have the least maximum load, and those k then all carry that maximum
+// plus the task's time, so a task's workgroups reach it together instead of
+// one waiting behind another's earlier work.  Every list follows the one
+// task order.
 static gi_status batch_plan(gi_batch* b) {
   const int nt = (int)b->tasks.size();
   std::vector<int> order((size_t)nt);
@@ -1700,18 +1705,25 @@ static gi_status batch_plan(gi_batch* b) {
   const int G = b->grid;
   std::vector<double> load((size_t)G, 0.0);
   std::vector<std::vector<int2>> lists((size_t)G);
-  std::vector<int> idx((size_t)G);
   for (int t : order) {
     const int k = std::min(b->k[(size_t)t], G);
     b->k[(size_t)t] = k;
-    for (int w = 0; w < G; ++w) idx[(size_t)w] = w;
-    std::partial_sort(idx.begin(), idx.begin() + k, idx.end(), [&](int x, int y) {
-      return load[(size_t)x] < load[(size_t)y] || (load[(size_t)x] == load[(size_t)y] && x < y);
-    });
+    int P = 1;
+    while (P < k) P <<= 1;
+    int best = 0;
+    double best_max = 1e300;
+    for (int w0 = 0; w0 + k <= G; w0 += std::min(P, G)) {
+      double mx = 0.0;
+      for (int r = 0; r < k; ++r) mx = std::max(mx, load[(size_t)(w0 + r)]);
+      if (mx < best_max) {
+        best_max = mx;
+        best = w0;
+      }
+    }
     for (int r = 0; r < k; ++r) {
-      const int w = idx[(size_t)r];
+      const int w = best + r;
       lists[(size_t)w].push_back(make_int2(t, r));
-      load[(size_t)w] += b->est[(size_t)t];
+      load[(size_t)w] = best_max + b->est[(size_t)t];
     }
   }
   std::vector<int> off((size_t)G + 1, 0);
@@ -1783,6 +1795,7 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
   if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev) != hipSuccess || rate <= 0)
     rate = 100000;  // kHz
   b->spin_limit = 2000LL * rate;  // two seconds of wall clock
+  b->clock_khz = rate;
   const int occ = batch_occupancy(b->lds);
   if (occ < 1) return bail(fail(GI_ERR_DEVICE, "batch kernel does not fit on a compute unit"));
   // resident by construction: at most the occupancy (and at most 4 per CU)
@@ -2040,17 +2053,20 @@ extern "C" gi_status gi_batch_autotune(gi_batch* b, int32_t reps) {
 }
 
 extern "C" gi_status gi_batch_info(const gi_batch* b, float* last_ms, int32_t* grid,
-                                   int32_t* workgroups, int32_t* levels) {
+                                   int32_t* workgroups, int32_t* levels, float* task_ms) {
   if (!b) return fail(GI_ERR_INVALID_ARG, "NULL batch");
   if (last_ms) *last_ms = b->last_ms;
   if (grid) *grid = b->grid;
   const size_t nt = b->tasks.size();
   if (workgroups)
     for (size_t i = 0; i < nt; ++i) workgroups[i] = b->k[i];
-  if (levels) {
+  if (levels || task_ms) {
     std::vector<TaskCtl> c(nt);
     HIP_TRY(hipMemcpy(c.data(), b->d_ctl, sizeof(TaskCtl) * nt, hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < nt; ++i) levels[i] = c[i].levels;
+    for (size_t i = 0; i < nt; ++i) {
+      if (levels) levels[i] = c[i].levels;
+      if (task_ms) task_ms[i] = (float)((double)(c[i].t_end - c[i].t_begin) / (double)b->clock_khz);
+    }
   }
   return GI_OK;
 }

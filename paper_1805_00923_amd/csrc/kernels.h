@@ -167,12 +167,14 @@ struct BatchGraph {
 };
 
 struct TaskCtl {
-  unsigned bar_cnt;
-  unsigned bar_gen;
+  unsigned long long bar;    // barrier: (generation << 32) | arrivals
   unsigned long long qn[3];  // BFS frontier sizes, rotating
   unsigned long long ds[3];  // their degree sums
   int levels;                // BFS levels / PageRank iterations completed
-  int pad[9];
+  int pad;
+  long long t_begin;         // wall clock at the task's start and end (rank 0)
+  long long t_end;
+  int pad2[4];
 };
 
 struct BatchTask {

@@ -330,14 +330,70 @@ __device__ void expand_chunks(const ExpandArgs& a, Visit& vis, int* lds) {
 // remaining short rows of a wave are gathered with a wave prefix sum so that
 // 64 consecutive lanes take 64 consecutive edge slots.
 
+// Expansion of the rows of one group of BT vertices (u = -1 for lanes
+// without a row): rows with >= BT edges by the whole workgroup, rows with
+// >= 64 edges by one wave, the remaining short rows of a wave with a wave
+// prefix sum.  Every thread of the workgroup must call it.
+template <int BT, class Visit>
+__device__ __forceinline__ void push_rows(int u, int beg, int end, Visit& vis, int* sh) {
+  const int tid = threadIdx.x;
+  const int lane = __lane_id();
+  while (__syncthreads_or(end - beg >= BT)) {
+    if (end - beg >= BT) sh[0] = tid;
+    __syncthreads();
+    if (tid == sh[0]) {
+      sh[1] = u;
+      sh[2] = beg;
+      sh[3] = end;
+      beg = end;
+    }
+    __syncthreads();
+    const int cu = sh[1], cb = sh[2], ce = sh[3];
+    for (int k = cb; k < ce; k += BT) {
+      const int e = k + tid;
+      vis(cu, e, e < ce);
+    }
+    __syncthreads();
+  }
+  for (;;) {
+    const unsigned long long mk = __ballot(end - beg >= kWave);
+    if (mk == 0ull) break;
+    const int leader = __ffsll((long long)mk) - 1;
+    const int cu = __shfl(u, leader, kWave);
+    const int cb = __shfl(beg, leader, kWave);
+    const int ce = __shfl(end, leader, kWave);
+    if (lane == leader) beg = end;
+    for (int k = cb; k < ce; k += kWave) {
+      const int e = k + lane;
+      vis(cu, e, e < ce);
+    }
+  }
+  int total;
+  const int deg = end - beg;
+  const int excl = wave_excl_scan(deg, &total);
+  for (int r = 0; r < total; r += kWave) {
+    const int j = r + lane;
+    int lo = 0;
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) {
+      const int cand = lo + s;
+      const int ex = __shfl(excl, cand, kWave);
+      if (ex <= j) lo = cand;
+    }
+    const int cu = __shfl(u, lo, kWave);
+    const int cb = __shfl(beg, lo, kWave);
+    const int ex = __shfl(excl, lo, kWave);
+    vis(cu, cb + (j - ex), j < total);
+  }
+}
+
 // Vertices [vb, ve) are taken BT at a time by workgroups first_block,
 // first_block + nblocks, ...
 template <int BT, class Visit>
 __device__ void dense_push_range(const DenseSet& fr, int vb, int ve, int first_block, int nblocks,
                                  const int32_t* off, Visit& vis) {
-  __shared__ int sh_owner, sh_u, sh_b, sh_e;
+  __shared__ int sh[4];
   const int tid = threadIdx.x;
-  const int lane = __lane_id();
   for (int base = vb + first_block * BT; base < ve; base += nblocks * BT) {
     const int i = base + tid;
     int u = -1, beg = 0, end = 0;
@@ -346,52 +402,49 @@ __device__ void dense_push_range(const DenseSet& fr, int vb, int ve, int first_b
       beg = off[i];
       end = off[i + 1];
     }
-    while (__syncthreads_or(end - beg >= BT)) {
-      if (end - beg >= BT) sh_owner = tid;
-      __syncthreads();
-      if (tid == sh_owner) {
-        sh_u = u;
-        sh_b = beg;
-        sh_e = end;
-        beg = end;
-      }
-      __syncthreads();
-      const int cu = sh_u, cb = sh_b, ce = sh_e;
-      for (int k = cb; k < ce; k += BT) {
-        const int e = k + tid;
-        vis(cu, e, e < ce);
-      }
-      __syncthreads();
-    }
-    for (;;) {
-      const unsigned long long mk = __ballot(end - beg >= kWave);
-      if (mk == 0ull) break;
-      const int leader = __ffsll((long long)mk) - 1;
-      const int cu = __shfl(u, leader, kWave);
-      const int cb = __shfl(beg, leader, kWave);
-      const int ce = __shfl(end, leader, kWave);
-      if (lane == leader) beg = end;
-      for (int k = cb; k < ce; k += kWave) {
-        const int e = k + lane;
-        vis(cu, e, e < ce);
-      }
-    }
+    push_rows<BT>(u, beg, end, vis, sh);
+  }
+}
+
+// One workgroup over the words [wb, we) of a sparse bitvector frontier:
+// BT words are read at a time, their members are listed in LDS (a
+// workgroup prefix sum of the words' popcounts gives each word its slots;
+// at most kList members per pass) and expanded BT members per group, so
+// empty stretches cost one read and sparse words no idle lanes.
+template <int BT, class Visit>
+__device__ void push_words(const uint64_t* bv, int wb, int we, int n, const int32_t* off,
+                           Visit& vis) {
+  constexpr int kList = 4096;
+  __shared__ int sh[4];
+  __shared__ int s_v[kList];
+  const int tid = threadIdx.x;
+  for (int tile = wb; tile < we; tile += BT) {
+    const int w = tile + tid;
+    const uint64_t x = w < we ? bv[w] : 0ull;
     int total;
-    const int deg = end - beg;
-    const int excl = wave_excl_scan(deg, &total);
-    for (int r = 0; r < total; r += kWave) {
-      const int j = r + lane;
-      int lo = 0;
-#pragma unroll
-      for (int s = 32; s > 0; s >>= 1) {
-        const int cand = lo + s;
-        const int ex = __shfl(excl, cand, kWave);
-        if (ex <= j) lo = cand;
+    const int first = block_excl_scan<BT, int>(__popcll(x), &total);
+    for (int base = 0; base < total; base += kList) {
+      // this thread's members with list index in [base, base + kList)
+      uint64_t y = x;
+      for (int j = first; y; ++j) {
+        const int b = __ffsll((long long)y) - 1;
+        y &= y - 1;
+        if (j >= base && j < base + kList) s_v[j - base] = (w << 6) + b;
       }
-      const int cu = __shfl(u, lo, kWave);
-      const int cb = __shfl(beg, lo, kWave);
-      const int ex = __shfl(excl, lo, kWave);
-      vis(cu, cb + (j - ex), j < total);
+      __syncthreads();
+      const int cnt = min(kList, total - base);
+      for (int g = 0; g < cnt; g += BT) {
+        int u = -1, beg = 0, end = 0;
+        if (g + tid < cnt) {
+          u = s_v[g + tid];
+          if (u < n) {
+            beg = off[u];
+            end = off[u + 1];
+          }
+        }
+        push_rows<BT>(u, beg, end, vis, sh);
+      }
+      __syncthreads();
     }
   }
 }
