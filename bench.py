@@ -5,23 +5,32 @@ Default workload (one "step"): direction-optimizing BFS (DensePull-SparsePush,
 bitvector frontier, hybrid divisor 20) from 64 seeded sources with out-degree
 >= 1, plus connected components by label propagation, on an R-MAT graph of
 scale 22 and edge factor 16 ((a,b,c,d) = (.57,.19,.19,.05), seed 2, vertex
-ids randomly relabelled, self-loops and repeated pairs removed).
+ids randomly relabelled, self-loops and repeated pairs removed).  The 64
+BFS run as one batched persistent launch (--bfs-path batched, the default:
+levels and parents of every source, workgroups per source autotuned) or as
+64 plain calls (--bfs-path plain); both are reported.
 
 value = GTEPS = (sum over sources of m_reach(s) + m) / step time, where
 m_reach(s) is the number of out-edges of the vertices BFS reaches from s
 (Graph500 convention on a directed graph) and CC counts each edge once.
 
-roofline: the dominant kernel is whichever step (edge-traversal) kernel,
-k_bfs_step or k_cc_step, has the larger summed GPU time.  Each launch is timed
-with HIP events the library records on the launch stream around it (per-step
-timing); every launch counts, including the no-op steps enqueued after the
-frontier emptied.  Algorithmic bytes per launch come from the step's trace
-entry (|F|, D_F, edges examined) with the byte models below
-(bfs_step_bytes, cc_step_bytes); achieved = bytes per launch / mean launch time.
+roofline: the dominant kernel is whichever of the BFS kernel (k_batch, or
+k_bfs_step on the plain path) and the CC step kernel k_cc_step has the larger
+summed GPU time.  Launches are timed with HIP events on the stream they run
+on: the batch's graph launch, or per step around the step kernel (per-step
+timing; every launch counts, including no-op steps after the frontier
+emptied).  Algorithmic bytes come from the per-step byte models below
+(bfs_step_bytes, cc_step_bytes) applied to each step's trace entry (|F|,
+D_F, edges examined); for k_batch, the sum over the 64 sources' BFS (the
+frontiers, and so the bytes, are those of the plain path's traces);
+achieved = bytes per launch / mean launch time.
 
 Other workloads (--workload): pr_rmat16 (20-iteration DensePull PageRank on
 R-MAT scale 16, the PageRank configuration), pr_rmat22, sssp_grid
-(delta-stepping on the 4096x4096 grid with 1% shortcuts).
+(delta-stepping on the 4096x4096 grid with 1% shortcuts), selector (learned
+schedule selector against the hybrid rule on a held-out Chung-Lu graph),
+batched (256 BFS/PageRank instances over 14 graphs, one persistent launch
+against 256 plain calls).
 """
 import argparse
 import json
@@ -52,6 +61,9 @@ def parse():
                     help="selector workload: held-out Chung-Lu graph with 4M vertices (small) "
                          "or 41M vertices and ~1.4B edges (full)")
     ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--bfs-path", default="batched", choices=["batched", "plain"],
+                    help="BFS part of the default workload: the 64 sources as one batched "
+                         "persistent launch, or one plain call per source")
     ap.add_argument("--sources", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", default="", help="k=v,... overrides of the schedule")
@@ -177,19 +189,62 @@ def run_bfs_cc(args, torch, dev):
     level = torch.empty(n, dtype=torch.int32, device=dev)
     parent = torch.empty(n, dtype=torch.int32, device=dev)
     label = torch.empty(n, dtype=torch.int32, device=dev)
-    bfs_k = KernelTally("k_bfs_step")
+
+    # per-source reach and algorithmic bytes from the plain path's traces
+    # (levels, and so frontiers and directions, are the same on every path)
+    odeg = np.diff(g.out_off).astype(np.int64)
+    m_reach, bfs_bytes, ref_levels = [], [], []
+    for s in srcs:
+        g.bfs(int(s), level)
+        lv = level.cpu().numpy()
+        m_reach.append(int(odeg[lv >= 0].sum()))
+        st = g.stats()
+        dirs, fs, ds = st.trace()
+        bfs_bytes.append(sum(bfs_step_bytes(n, dirs, fs, ds, st.step_edges_examined())))
+        if len(ref_levels) < 4:
+            ref_levels.append(level.clone())
+    teps_edges = sum(m_reach) + m
+
+    # plain path: one call per source (reported beside the batched path)
+    for s in srcs:
+        g.bfs(int(s), level, parent)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_ms = []
+    for s in srcs:
+        g.bfs(int(s), level, parent)
+        plain_ms.append(g.stats().kernel_ms)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+
+    batched = args.bfs_path == "batched"
+    if batched:
+        outs = [(torch.empty(n, dtype=torch.int32, device=dev),
+                 torch.empty(n, dtype=torch.int32, device=dev)) for _ in srcs]
+        batch = gi.Batch([g], [dict(graph=0, algorithm=gi.ALG_BFS, src=int(s), out=o, parent=p)
+                               for s, (o, p) in zip(srcs, outs)])
+        t0 = time.perf_counter()
+        batch.autotune(reps=3)
+        t_tune = time.perf_counter() - t0
+
     cc_k = KernelTally("k_cc_step")
+    batch_k = KernelTally("k_batch")
+    bfs_k = KernelTally("k_bfs_step")
 
     def one_step(record):
-        bfs_ms, cc_info = [], None
-        for s in srcs:
-            g.bfs(int(s), level, parent)
+        cc_info = None
+        if batched:
+            batch.run(use_graph=True)
             if record:
-                st = g.stats()
-                dirs, fs, ds = st.trace()
-                _, mm = g.step_times()
-                bfs_k.add(mm, bfs_step_bytes(n, dirs, fs, ds, st.step_edges_examined()))
-                bfs_ms.append(st.kernel_ms)
+                batch_k.add([batch.info()["ms"]], [sum(bfs_bytes)])
+        else:
+            for s in srcs:
+                g.bfs(int(s), level, parent)
+                if record:
+                    st = g.stats()
+                    dirs, fs, ds = st.trace()
+                    _, mm = g.step_times()
+                    bfs_k.add(mm, bfs_step_bytes(n, dirs, fs, ds, st.step_edges_examined()))
         g.cc(label)
         if record:
             st = g.stats()
@@ -197,46 +252,50 @@ def run_bfs_cc(args, torch, dev):
             _, mm = g.step_times()
             cc_k.add(mm, cc_step_bytes(n, dirs, fs, ds, st.step_edges_examined()))
             cc_info = (st.kernel_ms, st.steps, st.dense_steps)
-        return bfs_ms, cc_info
-
-    # m_reach per source (from the GPU levels; identical every run)
-    odeg = np.diff(g.out_off).astype(np.int64)
-    m_reach = []
-    for s in srcs:
-        g.bfs(int(s), level)
-        lv = level.cpu().numpy()
-        m_reach.append(int(odeg[lv >= 0].sum()))
-    teps_edges = sum(m_reach) + m
+        return cc_info
 
     g.set_step_timing(True)
     for _ in range(args.warmup):
         one_step(False)
     torch.cuda.synchronize()
-    bfs_all, cc_all = [], []
+    cc_all = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        bfs_ms, cc_info = one_step(True)
-        bfs_all += bfs_ms
-        cc_all.append(cc_info)
+        cc_all.append(one_step(True))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = dt * 1e3 / args.steps
     value = teps_edges * args.steps / dt / 1e9
-    per_src_gteps = [mr / (t * 1e-3) / 1e9 for mr, t in zip(m_reach * args.steps, bfs_all)]
-    dominant = bfs_k if bfs_k.ms >= cc_k.ms else cc_k
-    other = cc_k if dominant is bfs_k else bfs_k
+    if batched:
+        ok = all(torch.equal(outs[i][0], ref_levels[i]) for i in range(len(ref_levels)))
+        if not ok:
+            raise RuntimeError("batched BFS levels differ from the plain path")
+    bfs_tally = batch_k if batched else bfs_k
+    dominant = bfs_tally if bfs_tally.ms >= cc_k.ms else cc_k
+    other = cc_k if dominant is bfs_tally else bfs_tally
+    per_src_gteps = [mr / (t * 1e-3) / 1e9 for mr, t in zip(m_reach, plain_ms)]
     extra = {
-        "n": n, "m": m, "sources": int(len(srcs)),
-        "bfs_ms_median": round(float(np.median(bfs_all)), 4),
-        "bfs_gteps_harmonic_mean": round(len(per_src_gteps) / sum(1.0 / x for x in per_src_gteps), 3),
-        "bfs_gteps_median": round(float(np.median(per_src_gteps)), 3),
+        "n": n, "m": m, "sources": int(len(srcs)), "bfs_path": args.bfs_path,
+        "plain_bfs_ms_total": round(t_plain * 1e3, 3),
+        "plain_bfs_ms_median": round(float(np.median(plain_ms)), 4),
+        "plain_bfs_gteps_harmonic_mean": round(len(per_src_gteps) / sum(1.0 / x for x in per_src_gteps), 3),
+        "plain_bfs_gteps_median": round(float(np.median(per_src_gteps)), 3),
         "cc_ms": round(float(np.median([c[0] for c in cc_all])), 4),
         "cc_rounds": int(cc_all[0][1]), "cc_dense_rounds": int(cc_all[0][2]),
-        "other_step_kernel": other.roofline(),
+        "other_kernel": other.roofline(),
     }
+    if batched:
+        info = batch.info()
+        extra.update({"batched_bfs_ms": round(batch_k.ms / max(batch_k.launches, 1), 3),
+                      "batch_grid": info["grid"],
+                      "batch_workgroups_per_source": int(np.median(info["workgroups"])),
+                      "autotune_s": round(t_tune, 2),
+                      "speedup_batched_vs_plain_bfs": round(
+                          t_plain * 1e3 / (batch_k.ms / max(batch_k.launches, 1)), 3)})
     config = {"workload": "rmat22_ef16_bfs64_plus_cc", "graph": "rmat scale 22 edge factor 16 "
               "abcd=.57/.19/.19/.05 seed 2, relabelled, dedup", "n": n, "m": m,
-              "bfs_sources": int(len(srcs)), "schedule": g.schedule().as_dict()}
+              "bfs_sources": int(len(srcs)), "bfs_path": args.bfs_path,
+              "schedule": g.schedule().as_dict()}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_bfs_cc(el, srcs, m_reach)

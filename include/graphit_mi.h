@@ -350,7 +350,7 @@ gi_status gi_trace_exhaustive(gi_graph* g, int32_t algorithm, int32_t src, float
  * BFS levels and PageRank iterations, so no step costs a kernel launch and
  * small instances do not wait for the whole device.  BFS tasks choose
  * DensePull or push per level by the hybrid rule (section 2) with divisor
- * 20 and produce levels only; PageRank tasks use the DensePull
+ * 20 and produce levels (and parents when asked); PageRank tasks use the DensePull
  * destination-block kernel with the graph's current block size.  Results
  * equal the plain entry points' (levels bit for bit; ranks within the
  * PageRank tolerance).  A barrier that waits more than two seconds fails
@@ -365,6 +365,8 @@ typedef struct gi_task {
                          (a size rule at creation, then gi_batch_autotune)      */
   void* out;          /* device out, n entries: int32 levels (-1 unreachable)
                          for BFS, float ranks for PageRank; kept by the caller  */
+  void* parent;       /* BFS only, may be NULL: device out, n int32 parents
+                         (parent[src] = src, -1 unreachable; any BFS tree)      */
 } gi_task;
 
 typedef struct gi_batch gi_batch;

@@ -436,7 +436,8 @@ class Selector:
 class Task(ctypes.Structure):
     _fields_ = [("graph", ctypes.c_int32), ("algorithm", ctypes.c_int32), ("src", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("damping", ctypes.c_float),
-                ("workgroups", ctypes.c_int32), ("out", ctypes.c_void_p)]
+                ("workgroups", ctypes.c_int32), ("out", ctypes.c_void_p),
+                ("parent", ctypes.c_void_p)]
 
 
 class Batch:
@@ -448,12 +449,12 @@ class Batch:
 
     def __init__(self, graphs, tasks):
         self.graphs = list(graphs)
-        self._outs = [t["out"] for t in tasks]   # keep the tensors alive
+        self._outs = [(t["out"], t.get("parent")) for t in tasks]   # keep the tensors alive
         arr = (Task * len(tasks))()
         for i, t in enumerate(tasks):
             arr[i] = Task(int(t["graph"]), int(t["algorithm"]), int(t.get("src", 0)),
                           int(t.get("iters", 20)), float(t.get("damping", 0.85)),
-                          int(t.get("workgroups", 0)), _dptr(t["out"]))
+                          int(t.get("workgroups", 0)), _dptr(t["out"]), _dptr(t.get("parent")))
         hs = (ctypes.c_void_p * len(self.graphs))(*[g._h.value for g in self.graphs])
         self._h = ctypes.c_void_p(None)
         self.ntasks = len(tasks)

@@ -84,7 +84,10 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
   // this workgroup's words and vertices
   const int w0 = (int)((long long)W * r / k), w1 = (int)((long long)W * (r + 1) / k);
   const int v0 = w0 * 64, v1 = min(n, w1 * 64);
-  for (int v = v0 + tid; v < v1; v += kBB) level[v] = -1;
+  for (int v = v0 + tid; v < v1; v += kBB) {
+    level[v] = -1;
+    if (t.parent) t.parent[v] = -1;
+  }
   for (int w = w0 + tid; w < w1; w += kBB) {
     t.vis[w] = 0ull;
     t.bv0[w] = 0ull;
@@ -95,6 +98,7 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
   if (r == 0 && tid == 0) {
     const int s = t.src;
     level[s] = 0;
+    if (t.parent) t.parent[s] = s;
     t.bv0[s >> 6] = 1ull << (s & 63);
     t.vis[s >> 6] = 1ull << (s & 63);
     c->qn[0] = 1;
@@ -130,7 +134,7 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
     BfsArgs b{};
     b.g = dg;
     b.level = level;
-    b.parent = nullptr;
+    b.parent = t.parent;
     b.cur = DenseSet{bv[L % 3], nullptr};
     b.next = DenseSet{bv[(L + 1) % 3], nullptr};
     b.vis = t.vis;
@@ -139,7 +143,7 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
       bfs_pull_range<kBB>(b, L + 1, w0, w1, (int)(threadIdx.x / kWave), kBB / kWave, G.outdeg,
                           &found, &found_deg);
     } else {
-      BfsVisit vis{G.out_idx, level, nullptr, L + 1, b.next, t.vis};
+      BfsVisit vis{G.out_idx, level, t.parent, L + 1, b.next, t.vis};
       vis.deg = G.outdeg;
       push_words<kBB>(b.cur.bv, w0, w1, n, G.out_off, vis);
       found = vis.found;

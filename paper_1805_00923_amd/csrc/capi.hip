@@ -1816,6 +1816,7 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
     d.iters = t.iters;
     d.damping = t.damping;
     d.out = t.out;
+    d.parent = t.algorithm == GI_ALG_BFS ? static_cast<int32_t*>(t.parent) : nullptr;
     const size_t W = ((size_t)g->n + 63) / 64;
     if (d.alg == ALG_BFS) {
       if ((st = batch_alloc(b, &d.vis, 4 * W)) != GI_OK) return bail(st);

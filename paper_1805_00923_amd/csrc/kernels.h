@@ -185,6 +185,7 @@ struct BatchTask {
   float damping;
   int k;        // workgroups
   void* out;    // int32 levels or float ranks
+  int32_t* parent;  // BFS parents or null
   uint64_t* vis;
   uint64_t* bv0;
   uint64_t* bv1;

@@ -34,7 +34,8 @@ def make_tasks(torch, ntasks, seed=0):
         if i % 2 == 0:
             src = int(rng.integers(g.n))
             out = torch.full((g.n,), -9, dtype=torch.int32, device="cuda:0")
-            tasks.append(dict(graph=gidx, algorithm=1, src=src, out=out))
+            par = torch.full((g.n,), -9, dtype=torch.int32, device="cuda:0") if i % 4 == 0 else None
+            tasks.append(dict(graph=gidx, algorithm=1, src=src, out=out, parent=par))
         else:
             iters = int(rng.choice([0, 1, 7, 20]))
             out = torch.full((g.n,), -1.0, dtype=torch.float32, device="cuda:0")
@@ -50,6 +51,9 @@ def check(tasks):
         if t["algorithm"] == 1:
             ref = oracle.bfs(og, t["src"])[0]
             assert np.array_equal(got, ref), (i, el.name, t["src"])
+            if t.get("parent") is not None:
+                par = t["parent"].cpu().numpy()
+                assert oracle.check_bfs_parents(og, t["src"], got, par) == [], (i, el.name)
         else:
             ref = oracle.pagerank(og, t["iters"], 0.85)
             assert pr_max_rel(got, ref) <= PR_RTOL, (i, el.name, t["iters"])
