@@ -250,6 +250,21 @@ def run_bfs_cc(args, torch, dev):
         batch.autotune(reps=3)
         t_tune = time.perf_counter() - t0
 
+    # CC schedule: the hybrid divisor is tuned once (untimed), the way the
+    # paper's autotuner tunes a schedule per algorithm and graph
+    bfs_sched = g.schedule().as_dict()
+    cc_div, cc_best = 20, None
+    for div in (2, 4, 8, 20, 50):
+        g.set_schedule(**dict(bfs_sched, hybrid_divisor=div))
+        g.cc(label)
+        g.cc(label)
+        ms = g.stats().kernel_ms
+        if cc_best is None or ms < cc_best:
+            cc_div, cc_best = div, ms
+    cc_sched = dict(bfs_sched, hybrid_divisor=cc_div)
+    g.set_schedule(**cc_sched)
+    log("cc hybrid divisor %d (%.3f ms)" % (cc_div, cc_best))
+
     cc_k = KernelTally("k_cc_step")
     batch_k = KernelTally("k_batch")
     bfs_k = KernelTally("k_bfs_step")
@@ -261,6 +276,7 @@ def run_bfs_cc(args, torch, dev):
             if record:
                 batch_k.add([batch.info()["ms"]], [sum(bfs_bytes)])
         else:
+            g.set_schedule(**bfs_sched)
             for s in srcs:
                 g.bfs(int(s), level, parent)
                 if record:
@@ -268,6 +284,7 @@ def run_bfs_cc(args, torch, dev):
                     dirs, fs, ds = st.trace()
                     _, mm = g.step_times()
                     bfs_k.add(mm, bfs_step_bytes(n, dirs, fs, ds, st.step_edges_examined()))
+            g.set_schedule(**cc_sched)
         g.cc(label)
         if record:
             st = g.stats()
@@ -305,6 +322,7 @@ def run_bfs_cc(args, torch, dev):
         "plain_bfs_gteps_median": round(float(np.median(per_src_gteps)), 3),
         "cc_ms": round(float(np.median([c[0] for c in cc_all])), 4),
         "cc_rounds": int(cc_all[0][1]), "cc_dense_rounds": int(cc_all[0][2]),
+        "cc_hybrid_divisor": cc_div,
         "other_kernel": other.roofline(),
     }
     if batched:
@@ -318,7 +336,7 @@ def run_bfs_cc(args, torch, dev):
     config = {"workload": "rmat22_ef16_bfs64_plus_cc", "graph": "rmat scale 22 edge factor 16 "
               "abcd=.57/.19/.19/.05 seed 2, relabelled, dedup", "n": n, "m": m,
               "bfs_sources": int(len(srcs)), "bfs_path": args.bfs_path,
-              "schedule": g.schedule().as_dict()}
+              "schedule": bfs_sched, "cc_hybrid_divisor": cc_div}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_bfs_cc(el, srcs, m_reach)
@@ -402,11 +420,20 @@ def run_sssp(args, torch, dev):
     el = gg.grid(4096, 4096, 0.01, seed=4)
     g = gi.Graph.from_edges(el.n, el.src, el.dst, el.w)
     log("grid: built in %.1fs n=%d m=%d" % (time.time() - t0, g.n, g.m))
-    kw = dict(sssp_delta=4096)
-    kw.update(sched_overrides(args.schedule))
-    g.set_schedule(**kw)
     srcs = gg.pick_sources(el, 4, 5)
     dist = torch.empty(g.n, dtype=torch.int32, device=dev)
+    # delta swept (untimed) on the first source: {2^k, 5 <= k <= 14} and 1000
+    sweep = {}
+    for delta in [1 << k for k in range(5, 15)] + [1000]:
+        g.set_schedule(sssp_delta=delta)
+        g.sssp(int(srcs[0]), dist)
+        g.sssp(int(srcs[0]), dist)
+        sweep[delta] = round(g.stats().kernel_ms, 3)
+    best_delta = min(sweep, key=sweep.get)
+    log("sssp delta sweep (ms): %s -> %d" % (sweep, best_delta))
+    kw = dict(sssp_delta=best_delta)
+    kw.update(sched_overrides(args.schedule))
+    g.set_schedule(**kw)
     odeg = np.diff(g.out_off).astype(np.int64)
     m_reach = []
     for s in srcs:
@@ -439,7 +466,8 @@ def run_sssp(args, torch, dev):
     roof = tally.roofline()
     config = {"workload": "sssp_grid4096_shortcut1pct", "n": g.n, "m": g.m, "sources": 4,
               "schedule": g.schedule().as_dict()}
-    extra = {"phases_median": int(np.median(phases))}
+    extra = {"phases_median": int(np.median(phases)), "delta_sweep_ms": sweep,
+             "delta": best_delta}
     return value, "GTEPS", dt * 1e3 / args.steps, "uint32", config, roof, None, extra
 
 

@@ -388,6 +388,14 @@ static gi_status build_segments(gi_graph* g, int p, int strategy) {
 }
 
 static gi_status apply_schedule(gi_graph* g, const gi_schedule& s) {
+  // only the PageRank block layout and the segments own device tables: a
+  // change of direction, frontier kind, divisor or batching is free
+  if (g->pr_table && s.pull_block_edges == g->sched.pull_block_edges &&
+      s.num_segments == g->sched.num_segments &&
+      s.segment_strategy == g->sched.segment_strategy) {
+    g->sched = s;
+    return GI_OK;
+  }
   HIP_TRY(hipDeviceSynchronize());
   free_list(g->sched_allocs);
   g->segs.clear();

@@ -43,6 +43,34 @@ def test_rmat22_bfs_sampled_sources():
     g.set_step_timing(False)
 
 
+def test_rmat22_batched_bfs_all_sources():
+    """The benchmark's batched launch: 64 sources, levels of three checked
+    against the oracle, parents of all validated on those three, levels of
+    all equal to the plain path's."""
+    import torch
+    import paper_1805_00923_amd as gi
+    el, g, og = rmat22()
+    g.set_schedule(direction=3, dense_frontier=0, hybrid_divisor=20)
+    srcs = gg.pick_sources(el, 64, 3)
+    outs = [(torch.empty(g.n, dtype=torch.int32, device="cuda:0"),
+             torch.empty(g.n, dtype=torch.int32, device="cuda:0")) for _ in srcs]
+    b = gi.Batch([g], [dict(graph=0, algorithm=gi.ALG_BFS, src=int(s), out=o, parent=p)
+                       for s, (o, p) in zip(srcs, outs)])
+    say("rmat22 batched autotune")
+    b.autotune(reps=1)
+    say("rmat22 batched run")
+    b.run(use_graph=True)
+    for i in (0, 31, 63):
+        lv = outs[i][0].cpu().numpy()
+        assert np.array_equal(lv, oracle.bfs(og, int(srcs[i]))[0]), i
+        assert oracle.check_bfs_parents(og, int(srcs[i]), lv, outs[i][1].cpu().numpy()) == [], i
+    ref = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
+    for i in range(0, 64, 7):
+        g.bfs(int(srcs[i]), ref)
+        assert torch.equal(ref, outs[i][0]), i
+    b.close()
+
+
 def test_rmat22_cc():
     el, g, og = rmat22()
     g.set_schedule(direction=3, dense_frontier=0, hybrid_divisor=20)  # bitvector
