@@ -140,7 +140,7 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
     b.vis = t.vis;
     long long found = 0, found_deg = 0;
     if (hybrid_dense(nf, df, G.m, 20)) {
-      bfs_pull_range<kBB>(b, L + 1, w0, w1, (int)(threadIdx.x / kWave), kBB / kWave, G.outdeg,
+      bfs_pull_range<kBB, 2>(b, L + 1, w0, w1, (int)(threadIdx.x / kWave), kBB / kWave, G.outdeg,
                           &found, &found_deg);
     } else {
       BfsVisit vis{G.out_idx, level, t.parent, L + 1, b.next, t.vis};
