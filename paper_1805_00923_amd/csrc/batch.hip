@@ -196,7 +196,7 @@ __device__ void pr_task(const BatchGraph& G, const BatchTask& t, int r, const Ba
   if (r == 0 && tid == 0) c->levels = t.iters;
 }
 
-__global__ __launch_bounds__(kBB) void k_batch(BatchArgs a) {
+__global__ __launch_bounds__(kBB, 5) void k_batch(BatchArgs a) {
   extern __shared__ float smem[];
   float* lds_val = smem;
   int* lds_off = reinterpret_cast<int*>(smem + a.lds_cap_e);

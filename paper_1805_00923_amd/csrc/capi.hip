@@ -1806,8 +1806,8 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
   b->clock_khz = rate;
   const int occ = batch_occupancy(b->lds);
   if (occ < 1) return bail(fail(GI_ERR_DEVICE, "batch kernel does not fit on a compute unit"));
-  // resident by construction: at most the occupancy (and at most 4 per CU)
-  b->max_grid = cus * std::min(occ, 4);
+  // resident by construction: at most the occupancy (and at most 8 per CU)
+  b->max_grid = cus * std::min(occ, 8);
   gi_status st;
   const size_t nt = (size_t)ntasks;
   b->h_tasks.resize(nt);
