@@ -113,7 +113,7 @@ typedef struct gi_schedule {
 /* Per-run statistics of the last algorithm call on a graph. */
 #define GI_MAX_TRACE 4096
 typedef struct gi_run_stats {
-  int32_t algorithm;      /* 0 PageRank, 1 BFS, 2 CC, 3 SSSP                   */
+  int32_t algorithm;      /* 0 PageRank, 1 BFS, 2 CC, 3 SSSP, 4 PageRankDelta  */
   int32_t steps;          /* edgeset.apply steps executed                        */
   int32_t dense_steps;    /* of which dense (pull or dense push)                 */
   int32_t trace_len;      /* entries valid in the arrays below (<= GI_MAX_TRACE) */
@@ -233,6 +233,24 @@ gi_status gi_cc(gi_graph* g, int32_t* label, void* stream);
  * Errors: INVALID_ARG (unweighted graph, src out of range), OVERFLOW (a
  * finite distance reached UINT32_MAX), DEVICE. */
 gi_status gi_sssp(gi_graph* g, int32_t src, uint32_t* dist, void* stream);
+
+/* PageRankDelta, the paper's running example (section 2.1; its program in
+ * the algorithm-language section, its schedule in the scheduling section):
+ *   Rank = 0, Delta = 1/n, every vertex active; per round, active vertices
+ *   add Delta/OutDegree into DeltaSum of their out-neighbours, then every
+ *   vertex updates: in the first round Delta = a DeltaSum + (1-a)/n,
+ *   Rank += Delta, Delta -= 1/n; later Delta = a DeltaSum, Rank += Delta;
+ *   a vertex stays active when |Delta| > epsilon * Rank.
+ * Stops after `rounds` rounds or when no vertex is active.  The schedule's
+ * direction chooses SparsePush, DensePush, DensePull or the hybrid rule per
+ * round (bitvector frontier; the learned direction is UNSUPPORTED).  All
+ * arithmetic is FP64; with epsilon = 0 the ranks are the PageRank power
+ * iteration's.  The trace records each round's active set.
+ *   ranks   device out, n doubles.
+ * Errors: INVALID_ARG (rounds < 0, damping outside [0,1], epsilon < 0 or not
+ * finite), UNSUPPORTED, OUT_OF_MEMORY, DEVICE. */
+gi_status gi_prdelta(gi_graph* g, int32_t rounds, double damping, double epsilon, double* ranks,
+                     void* stream);
 
 /* Statistics of the last algorithm call on g. */
 gi_status gi_get_run_stats(const gi_graph* g, gi_run_stats* out);

@@ -107,6 +107,7 @@ _SIGS = {
     "gi_sssp": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
     "gi_get_run_stats": (ctypes.c_int, [_vp, _vp]),
     "gi_set_step_timing": (ctypes.c_int, [_vp, _i32]),
+    "gi_prdelta": (ctypes.c_int, [_vp, _i32, ctypes.c_double, ctypes.c_double, _vp, _vp]),
     "gi_selector_create": (ctypes.c_int, [ctypes.c_uint64, _vp]),
     "gi_selector_destroy": (ctypes.c_int, [_vp]),
     "gi_selector_get_params": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -326,6 +327,12 @@ class Graph:
         return a[:k], b[:k]
 
     # ---- algorithms: outputs are device tensors supplied by the caller ----
+    def prdelta(self, ranks, rounds=10, damping=0.85, eps=0.1, stream=None):
+        """PageRankDelta into a float64 device tensor of n entries."""
+        _check(lib.gi_prdelta(self._h, int(rounds), float(damping), float(eps), _dptr(ranks),
+                              _stream(stream)))
+        return ranks
+
     def pagerank(self, ranks, iters=20, damping=0.85, stream=None):
         _check(lib.gi_pagerank(self._h, int(iters), float(damping), _dptr(ranks), _stream(stream)))
         return ranks

@@ -24,6 +24,7 @@
 // the smallest far distance and the far set is split.
 #include "bfs_dev.h"
 #include "kernels.h"
+#include "pr_block.h"
 #include "traverse.h"
 
 namespace gi {
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(1024) void k_decide_frontier(FrontierArgs f, Decide
         if (k <= kMaxLog) c->host->log[k - 1].edges = work;
         c->edges_examined += work;
       }
-      if (tot.members == 0) {
+      if (tot.members == 0 || (d.max_steps > 0 && k >= d.max_steps)) {
         c->done = 1;
         publish_done(c, k);
       } else {
@@ -483,6 +484,108 @@ __global__ void k_sssp_init(SsspArgs s, int src) {
   for (int i = tid; i < kParts; i += nt) s.part[i] = Part{0, 0, 0, 0};
 }
 
+// ---------------------------------------------------------- PageRankDelta --
+//
+// The PageRankDelta program of the algorithm-language section, with its
+// DensePull-SparsePush schedule and bitvector frontier (scheduling section):
+// per round, the active vertices' Delta / OutDegree reaches DeltaSum of
+// their out-neighbours (push: FP64 atomic adds from the compacted
+// frontier; pull: the PageRank destination-block sum over in-edges, where an
+// inactive source contributes an exact zero), then every vertex updates:
+//   round 1: Delta = alpha DeltaSum + (1-alpha)/n, Rank += Delta, Delta -= 1/n
+//   later:   Delta = alpha DeltaSum,               Rank += Delta
+// and stays active when |Delta| > eps Rank.  Delta / OutDegree is kept as one
+// FP64 array, the fused layout of the paper's vertex-data optimization.
+
+struct PrdVisit {
+  const int32_t* idx;
+  const double* contrib;
+  double* dsum;
+  long long work = 0;
+  __device__ __forceinline__ void operator()(int u, int e, bool valid) {
+    if (!valid) return;
+    ++work;
+    atomicAdd(&dsum[idx[e]], contrib[u]);
+  }
+};
+
+template <int BT, int CH>
+__global__ __launch_bounds__(BT) void k_prd_step(PrdArgs a, ExpandArgs x) {
+  extern __shared__ int smem_i[];
+  const int mode = a.ctl->mode;
+  if (mode == MODE_NONE) return;
+  long long work = 0;
+  if (mode == MODE_DENSE_PULL) {
+    double* lds_val = reinterpret_cast<double*>(smem_i);
+    int* lds_off = reinterpret_cast<int*>(lds_val + a.cap_e);
+    PrVertex pv{a.g.outdeg, a.base, a.alpha};
+    for (int t = blockIdx.x; t < a.rows.ntab; t += gridDim.x) {
+      pr_rows_block<BT, double>(a.rows, t, a.cap_e, a.contrib, 1, pv, nullptr, nullptr, a.dsum,
+                                lds_val, lds_off);
+    }
+    if (threadIdx.x == 0) work = blockIdx.x == 0 ? a.g.m : 0;
+  } else {
+    PrdVisit vis{a.g.out_idx, a.contrib, a.dsum};
+    if (mode == MODE_SPARSE_PUSH) expand_chunks<BT, CH>(x, vis, smem_i);
+    else dense_push_expand<BT>(a.cur, a.g.n, a.g.out_off, vis);
+    work = vis.work;
+  }
+  const Part p = block_sum4<BT>(Part{0, 0, work, 0});
+  if (threadIdx.x == 0) a.part[blockIdx.x] = p;
+}
+
+// Vertex update and next frontier: one wave per 64-vertex word.
+__global__ __launch_bounds__(256) void k_prd_update(PrdArgs a) {
+  if (a.ctl->mode == MODE_NONE) return;
+  const int round = a.ctl->steps;  // 1-based
+  const int n = a.g.n, W = (n + 63) >> 6, lane = __lane_id();
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  const int nw = (int)((gridDim.x * blockDim.x) / kWave);
+  for (int w = wave; w < W; w += nw) {
+    const int v = (w << 6) + lane;
+    bool act = false;
+    if (v < n) {
+      const double ds = a.dsum[v];
+      double d, r = a.rank[v];
+      if (round == 1) {
+        d = a.alpha * ds + a.base;
+        r += d;
+        d -= a.inv_n;
+      } else {
+        d = a.alpha * ds;
+        r += d;
+      }
+      a.dsum[v] = 0.0;
+      a.delta[v] = d;
+      a.rank[v] = r;
+      act = fabs(d) > a.eps * r;
+      const int deg = a.g.outdeg[v];
+      a.contrib[v] = (act && deg > 0) ? d / (double)deg : 0.0;
+    }
+    const unsigned long long m = __ballot(act);
+    if (lane == 0) a.next.bv[w] = m;
+  }
+}
+
+// Initial state: Rank = 0, Delta = 1/n, every vertex active.
+__global__ void k_prd_init(PrdArgs a) {
+  const int n = a.g.n, W = (n + 63) >> 6;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
+  for (int v = tid; v < n; v += nt) {
+    a.rank[v] = 0.0;
+    a.delta[v] = a.inv_n;
+    a.dsum[v] = 0.0;
+    const int deg = a.g.outdeg[v];
+    a.contrib[v] = deg > 0 ? a.inv_n / (double)deg : 0.0;
+  }
+  for (int w = tid; w < W; w += nt) {
+    const int rem = n - (w << 6);
+    a.cur.bv[w] = rem >= 64 ? ~0ull : ((1ull << rem) - 1ull);
+    a.next.bv[w] = 0ull;
+  }
+  for (int i = tid; i < kParts; i += nt) a.part[i] = Part{0, 0, 0, 0};
+}
+
 // Control-block reset shared by the runs (one thread).
 __global__ void k_ctl_init(Control* c, HostFlags* host, unsigned long long delta) {
   c->mode = MODE_NONE;
@@ -617,6 +720,33 @@ int enqueue_sssp_step(const Engine& e, const FrontierArgs& f, const SsspArgs& sa
   mark(te, 1, s);
   hipLaunchKernelGGL((k_sssp_step<kBT, kCH>), dim3(kParts), dim3(kBT), 0, s, sa,
                      expand_args(e, sa.g.out_off));
+  mark(te, 2, s);
+  return GI_OK_LAUNCH();
+}
+
+static size_t prd_lds_bytes(int cap_e) {
+  const size_t pull = sizeof(double) * (size_t)cap_e + sizeof(int) * (size_t)(std::min(cap_e, 1024) + 1);
+  const size_t push = sizeof(int) * (size_t)expand_lds_ints<kCH>();
+  return std::max(pull, push);
+}
+
+int launch_prd_init(const PrdArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_prd_init, dim3(grid_for(a.g.n, 256, 2048)), dim3(256), 0, s, a);
+  return GI_OK_LAUNCH();
+}
+
+int enqueue_prd_step(const Engine& e, const FrontierArgs& f, const DecideArgs& d,
+                     const PrdArgs& a, const StepEvents* te, hipStream_t s) {
+  mark(te, 0, s);
+  hipLaunchKernelGGL(k_count<kBT>, dim3(e.cgrid), dim3(kBT), 0, s, f);
+  hipLaunchKernelGGL(k_decide_frontier, dim3(1), dim3(1024), 0, s, f, d);
+  hipLaunchKernelGGL((k_write<kBT, kCH>), dim3(e.cgrid), dim3(kBT), 0, s, f,
+                     (int)MODE_SPARSE_PUSH);
+  mark(te, 1, s);
+  hipLaunchKernelGGL((k_prd_step<kBT, kCH>), dim3(kParts), dim3(kBT), prd_lds_bytes(a.cap_e), s,
+                     a, expand_args(e, a.g.out_off));
+  hipLaunchKernelGGL(k_prd_update, dim3(grid_for((long long)((a.g.n + 63) / 64) * 64, 256, 2048)),
+                     dim3(256), 0, s, a);
   mark(te, 2, s);
   return GI_OK_LAUNCH();
 }

@@ -117,7 +117,8 @@ struct gi_graph {
   bool timing_failed = false;
   std::vector<StepEvents> tev;
   int tev_count = 0;        // steps of the last run that carry events
-  int last_steps[4] = {0, 0, 0, 0};  // steps of the previous run, per algorithm
+  int last_steps[5] = {0, 0, 0, 0, 0};  // steps of the previous run, per algorithm
+  double* prd = nullptr;  // PageRankDelta: delta, contrib, dsum (3 n doubles)
   // selector features (graph level) and the attached selector
   FeatConst fc_bfs{}, fc_cc{}, fc_pr{};
   float* sel_p = nullptr;      // fp32 parameters, then mu[12], isd[12]
@@ -885,6 +886,7 @@ static DecideArgs decide_args(const gi_graph* g, int alg) {
   d.forced_dir = -1;
   d.edges = alg == ALG_CC ? 2 * g->m : g->m;
   d.is_bfs = alg == ALG_BFS;
+  d.max_steps = 0;
   d.fc = alg == ALG_CC ? g->fc_cc : g->fc_bfs;
   d.sel = sel_dev(g);
   return d;
@@ -1139,6 +1141,61 @@ extern "C" gi_status gi_sssp(gi_graph* g, int32_t src, uint32_t* dist, void* str
   st = read_loop_stats(g, ALG_SSSP);
   g->stats.dense_steps = 0;
   return st;
+}
+
+extern "C" gi_status gi_prdelta(gi_graph* g, int32_t rounds, double damping, double epsilon,
+                                double* ranks, void* stream) {
+  if (!g || !ranks) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  if (rounds < 0) return fail(GI_ERR_INVALID_ARG, "rounds must be >= 0");
+  if (!(damping >= 0.0 && damping <= 1.0)) return fail(GI_ERR_INVALID_ARG, "damping outside [0,1]");
+  if (!(epsilon >= 0.0) || !std::isfinite(epsilon))
+    return fail(GI_ERR_INVALID_ARG, "epsilon must be finite and >= 0");
+  if (g->sched.direction == GI_DIR_LEARNED)
+    return fail(GI_ERR_UNSUPPORTED, "PageRankDelta has no learned direction");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  gi_status st;
+  if (!g->prd && (st = dev_alloc(g, g->allocs, &g->prd, 3 * (size_t)g->n)) != GI_OK) return st;
+  if ((st = start_run(g, 0, s)) != GI_OK) return st;
+  PrdArgs a;
+  a.g = dev_graph(g);
+  a.delta = g->prd;
+  a.contrib = g->prd + g->n;
+  a.dsum = g->prd + 2 * (size_t)g->n;
+  a.rank = ranks;
+  a.cur = DenseSet{g->fbv[0], nullptr};
+  a.next = DenseSet{g->fbv[1], nullptr};
+  a.rows = PrRows{g->pr_table, g->pr_ntab, g->in_off, g->in_idx, nullptr, g->lr_acc, g->lr_cnt,
+                  g->lr_chunks};
+  a.cap_e = g->pr_cap_e;
+  a.alpha = damping;
+  a.base = (1.0 - damping) / (double)g->n;
+  a.inv_n = 1.0 / (double)g->n;
+  a.eps = epsilon;
+  a.part = g->part;
+  a.ctl = g->ctl;
+  LAUNCH_TRY(launch_prd_init(a, s));
+  if (rounds == 0) {
+    HIP_TRY(hipStreamSynchronize(s));
+    g->stats = gi_run_stats{};
+    g->stats.algorithm = ALG_PRD;
+    return GI_OK;
+  }
+  DecideArgs d = decide_args(g, ALG_BFS);
+  d.is_bfs = 0;
+  d.fc = g->fc_pr;
+  d.max_steps = rounds;
+  st = run_frontier_loop(
+      g, s, ALG_PRD, 8, (long long)rounds + 2,
+      [&](long long k) {
+        PrdArgs ak = a;
+        ak.cur = DenseSet{g->fbv[k & 1], nullptr};
+        ak.next = DenseSet{g->fbv[(k + 1) & 1], nullptr};
+        const FrontierArgs f = frontier_args(g->eng, ak.cur, ak.next, g->outdeg, nullptr, nullptr);
+        return enqueue_prd_step(g->eng, f, d, ak, step_events(g, k), s) ? -1 : 5;
+      },
+      "PageRankDelta");
+  if (st != GI_OK) return st;
+  return read_loop_stats(g, ALG_PRD);
 }
 
 extern "C" gi_status gi_get_run_stats(const gi_graph* g, gi_run_stats* out) {

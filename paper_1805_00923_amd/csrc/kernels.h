@@ -7,7 +7,7 @@
 
 namespace gi {
 
-enum : int { ALG_PR = 0, ALG_BFS = 1, ALG_CC = 2, ALG_SSSP = 3 };
+enum : int { ALG_PR = 0, ALG_BFS = 1, ALG_CC = 2, ALG_SSSP = 3, ALG_PRD = 4 };
 
 // Rows of one adjacency split into destination blocks (PageRank and CC pull).
 struct RowBlocks {
@@ -63,6 +63,7 @@ struct DecideArgs {
   int forced_dir;  // >= 0: direction of every step
   long long edges; // m for BFS, 2m for CC (edges counted in both directions)
   int is_bfs;      // feature 7 is the unvisited fraction
+  int max_steps;   // > 0: the run ends after this many steps
   FeatConst fc;    // graph-level features
   SelDev sel;      // attached selector (GI_DIR_LEARNED)
 };
@@ -124,6 +125,28 @@ int enqueue_cc_step(const Engine& e, const FrontierArgs& f, const DecideArgs& d,
 int launch_sssp_init(const SsspArgs& sa, int src, hipStream_t s);
 int enqueue_sssp_step(const Engine& e, const FrontierArgs& f, const SsspArgs& sa,
                       const StepEvents* te, hipStream_t s);
+
+// PageRankDelta (algos.hip).
+struct PrdArgs {
+  DevGraph g;
+  double* delta;
+  double* contrib;  // delta / outdeg of active vertices, 0 otherwise
+  double* dsum;     // DeltaSum (zero between rounds)
+  double* rank;
+  DenseSet cur;
+  DenseSet next;
+  PrRows rows;      // in-row blocks for the pull
+  int cap_e;
+  double alpha;
+  double base;      // (1 - alpha) / n
+  double inv_n;
+  double eps;
+  Part* part;
+  Control* ctl;
+};
+int launch_prd_init(const PrdArgs& a, hipStream_t s);
+int enqueue_prd_step(const Engine& e, const FrontierArgs& f, const DecideArgs& d,
+                     const PrdArgs& a, const StepEvents* te, hipStream_t s);
 
 // Selector training (selector.hip): parameters, Adam moments and the
 // gradient buffer in device memory; records x[n][12], y[n][4] (log ms),

@@ -23,9 +23,9 @@ __device__ __forceinline__ double block_sum(double v) {
 
 // Sum over the edge range [eb, ee) of cin[idx[e]] by the whole workgroup,
 // four independent loads in flight per thread; result valid in thread 0.
-template <int BT>
+template <int BT, typename TC>
 __device__ __forceinline__ double range_sum(const int32_t* __restrict__ idx,
-                                            const float* __restrict__ cin, int eb, int ee) {
+                                            const TC* __restrict__ cin, int eb, int ee) {
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int e = eb + (int)threadIdx.x;
   for (; e + 3 * BT < ee; e += 4 * BT) {
@@ -40,10 +40,12 @@ __device__ __forceinline__ double range_sum(const int32_t* __restrict__ idx,
 }
 
 // mode 0: final vertex update from the full sum; mode 1: acc[dst] += sum.
-template <int BT>
-__device__ void pr_rows_block(const PrRows& r, int t, int cap_e, const float* __restrict__ cin,
+// TC: type of the gathered contributions (float for PageRank, double for
+// PageRankDelta's partial sums).
+template <int BT, typename TC = float>
+__device__ void pr_rows_block(const PrRows& r, int t, int cap_e, const TC* __restrict__ cin,
                               int mode, const PrVertex& pv, float* __restrict__ cout,
-                              float* __restrict__ rank, double* __restrict__ acc, float* lds_val,
+                              float* __restrict__ rank, double* __restrict__ acc, TC* lds_val,
                               int* lds_off) {
   const int4 en = r.table[t];
   const int tid = threadIdx.x;
@@ -67,7 +69,7 @@ __device__ void pr_rows_block(const PrRows& r, int t, int cap_e, const float* __
     const int row = en.x;
     const int rb = r.off[row], re = r.off[row + 1];
     const int eb = rb + en.w * cap_e, ee = min(re, eb + cap_e);
-    const double s = range_sum<BT>(r.idx, cin, eb, ee);
+    const double s = range_sum<BT, TC>(r.idx, cin, eb, ee);
     if (tid == 0) {
       if (mode == 1) {
         atomicAdd(&acc[r.dst ? r.dst[row] : row], s);
@@ -88,7 +90,7 @@ __device__ void pr_rows_block(const PrRows& r, int t, int cap_e, const float* __
   }
   const int kb = en.x, ke = en.y, nr = ke - kb;
   const int e0 = r.off[kb], e1 = r.off[ke], ne = e1 - e0;
-  gather_block<BT, float>(r.idx, e0, ne, lds_val, [cin](int u) { return cin[u]; });
+  gather_block<BT, TC>(r.idx, e0, ne, lds_val, [cin](int u) { return cin[u]; });
   for (int k = tid; k <= nr; k += BT) lds_off[k] = r.off[kb + k] - e0;
   __syncthreads();
   int tpv = 1;
