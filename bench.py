@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="bfs_cc_rmat22",
                     choices=["bfs_cc_rmat22", "pr_rmat16", "pr_rmat22", "sssp_grid", "selector",
-                             "batched"])
+                             "batched", "prdelta_rmat22"])
     ap.add_argument("--heldout", default="small", choices=["small", "full"],
                     help="selector workload: held-out Chung-Lu graph with 4M vertices (small) "
                          "or 41M vertices and ~1.4B edges (full)")
@@ -700,6 +700,50 @@ def run_batched(args, torch, dev):
     return value, "GTEPS", t_batch * 1e3, "int32 / f32+f64", config, None, None, detail
 
 
+def run_prdelta(args, torch, dev):
+    """PageRankDelta, 10 rounds, epsilon 0.1, damping 0.85, DensePull-SparsePush
+    with a bitvector frontier, on R-MAT scale 22 (seed 2).  GTEPS counts the
+    edges the rounds examined (push: out-edges of the active vertices; pull:
+    every in-edge)."""
+    import numpy as np
+    import paper_1805_00923_amd as gi
+    el, g = make_rmat_graph(22, 2)
+    g.set_schedule(direction=gi.DENSE_PULL_SPARSE_PUSH, dense_frontier=gi.BITVECTOR,
+                   **sched_overrides(args.schedule))
+    ranks = torch.empty(g.n, dtype=torch.float64, device=dev)
+    g.set_step_timing(True)
+    for _ in range(args.warmup):
+        g.prdelta(ranks, 10, 0.85, 0.1)
+    torch.cuda.synchronize()
+    edges, kms = 0, []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.prdelta(ranks, 10, 0.85, 0.1)
+        st = g.stats()
+        edges += int(st.edges_examined)
+        kms.append(st.kernel_ms)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = g.stats()
+    dirs, fs, ds = st.trace()
+    value = edges / dt / 1e9
+    detail = {"rounds": int(st.steps), "directions": [int(x) for x in dirs],
+              "frontiers": [int(x) for x in fs], "run_ms_median": round(float(np.median(kms)), 3)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        og = oracle.Graph(el)
+        t0 = time.perf_counter()
+        oracle.prdelta(og, 10, 0.85, 0.1)
+        dtc = time.perf_counter() - t0
+        cpu = {"value": round(edges / args.steps / dtc / 1e9, 5), "unit": "GTEPS", "cores": 1,
+               "kind": "oracle", "sample": "fp64 PageRankDelta, 10 rounds, full graph, one "
+                                           "thread, %.2f s (edges counted as on the GPU)" % dtc}
+    config = {"workload": "prdelta10_eps0.1_rmat22_ef16", "n": g.n, "m": g.m,
+              "schedule": g.schedule().as_dict()}
+    return value, "GTEPS", dt * 1e3 / args.steps, "f64", config, None, cpu, detail
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -720,6 +764,8 @@ def main():
         res = run_pr(args, torch, dev, 16)
     elif args.workload == "pr_rmat22":
         res = run_pr(args, torch, dev, 22)
+    elif args.workload == "prdelta_rmat22":
+        res = run_prdelta(args, torch, dev)
     elif args.workload == "batched":
         res = run_batched(args, torch, dev)
     elif args.workload == "selector":

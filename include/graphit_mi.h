@@ -95,6 +95,13 @@ enum { GI_SEG_FIXED_VERTEX_COUNT = 0, GI_SEG_EDGE_AWARE_VERTEX_COUNT = 1 };
  *   block_threads    threads per workgroup of the PageRank DensePull
  *                    kernel: 64, 128, 256 or 512 (0 = library default 256)
  *   sssp_delta       bucket width of delta-stepping (0 = library default)
+ *   segments_concurrent  PageRank with num_segments > 1: 0 processes the
+ *                    segments one after another (the paper's order); 1 runs
+ *                    them in one launch, workgroup b on segment b mod
+ *                    num_segments, each segment adding into its own FP64
+ *                    partial-sum buffer, then sums the partials (with 8
+ *                    segments each of the 8 XCDs gathers from one segment,
+ *                    which stays in its L2)
  * Use gi_schedule_init for defaults; gi_set_schedule returns
  * GI_ERR_UNSUPPORTED for a combination it does not offer. */
 typedef struct gi_schedule {
@@ -107,7 +114,8 @@ typedef struct gi_schedule {
   int32_t pull_block_edges;
   int32_t block_threads;
   uint32_t sssp_delta;
-  int32_t reserved[7];
+  int32_t segments_concurrent;
+  int32_t reserved[6];
 } gi_schedule;
 
 /* Per-run statistics of the last algorithm call on a graph. */

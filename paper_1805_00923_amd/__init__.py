@@ -61,7 +61,8 @@ class Schedule(ctypes.Structure):
                 ("num_segments", ctypes.c_int32), ("segment_strategy", ctypes.c_int32),
                 ("hybrid_divisor", ctypes.c_int32), ("steps_per_sync", ctypes.c_int32),
                 ("pull_block_edges", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("sssp_delta", ctypes.c_uint32), ("reserved", ctypes.c_int32 * 7)]
+                ("sssp_delta", ctypes.c_uint32), ("segments_concurrent", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

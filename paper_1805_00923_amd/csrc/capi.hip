@@ -92,6 +92,7 @@ struct gi_graph {
   int sym_ntab = 0;
   std::vector<SegDev> segs;
   double* pr_acc = nullptr;
+  PrRows* seg_rows = nullptr;  // device copy of the segments' row blocks
   // frontier-loop workspace
   uint64_t* fbv[2] = {nullptr, nullptr};  // dense frontiers (bitvectors)
   uint8_t* fbm[2] = {nullptr, nullptr};   // dense frontiers (bool maps, padded to 64)
@@ -382,10 +383,16 @@ static gi_status build_segments(gi_graph* g, int p, int strategy) {
     if ((st = upload(sdst.data(), s.dst, sdst.size() * 4)) != GI_OK) return st;
     if ((st = upload(tab.data(), s.table, tab.size() * sizeof(int4))) != GI_OK) return st;
   }
-  gi_status st = dev_alloc(g, g->sched_allocs, &g->pr_acc, (size_t)n);
+  // one partial-sum buffer per segment (the concurrent form needs them all;
+  // the sequential form uses the first)
+  gi_status st = dev_alloc(g, g->sched_allocs, &g->pr_acc, (size_t)n * (size_t)p);
   if (st != GI_OK) return st;
-  HIP_TRY(hipMemset(g->pr_acc, 0, sizeof(double) * (size_t)n));
-  return GI_OK;
+  HIP_TRY(hipMemset(g->pr_acc, 0, sizeof(double) * (size_t)n * (size_t)p));
+  std::vector<PrRows> rows;
+  for (const SegDev& sg : g->segs)
+    rows.push_back(PrRows{sg.table, sg.ntab, sg.off, sg.idx, sg.dst, nullptr, nullptr, nullptr});
+  if ((st = dev_alloc(g, g->sched_allocs, &g->seg_rows, rows.size())) != GI_OK) return st;
+  return upload(rows.data(), g->seg_rows, sizeof(PrRows) * rows.size());
 }
 
 static gi_status apply_schedule(gi_graph* g, const gi_schedule& s) {
@@ -401,6 +408,7 @@ static gi_status apply_schedule(gi_graph* g, const gi_schedule& s) {
   free_list(g->sched_allocs);
   g->segs.clear();
   g->pr_acc = nullptr;
+  g->seg_rows = nullptr;
   g->pr_table = nullptr;
   g->sched = s;
   if (s.pull_block_edges > 0) {
@@ -462,6 +470,8 @@ static gi_status validate_schedule(const gi_graph* g, const gi_schedule* s) {
     return fail(GI_ERR_UNSUPPORTED, "steps_per_sync outside [0, 4096]");
   if (s->pull_block_edges != 0 && (s->pull_block_edges < 64 || s->pull_block_edges > 8192))
     return fail(GI_ERR_UNSUPPORTED, "pull_block_edges outside [64, 8192]");
+  if (s->segments_concurrent != 0 && s->segments_concurrent != 1)
+    return fail(GI_ERR_UNSUPPORTED, "segments_concurrent must be 0 or 1");
   if (s->block_threads != 0 && s->block_threads != 64 && s->block_threads != 128 &&
       s->block_threads != 256 && s->block_threads != 512)
     return fail(GI_ERR_UNSUPPORTED, "block_threads must be 0, 64, 128, 256 or 512");
@@ -945,6 +955,13 @@ static gi_status pr_run(gi_graph* g, int32_t iters, float damping, float* ranks,
       LAUNCH_TRY(launch_pr_rows(r, g->pr_cap_e, g->pr_cap_v, bt, 0, cin, 0, pv, cout,
                                 last ? ranks : nullptr, nullptr, s));
       ++launches;
+    } else if (g->sched.segments_concurrent && g->segs.size() > 1) {
+      const int p = (int)g->segs.size();
+      LAUNCH_TRY(launch_pr_seg_concurrent(g->seg_rows, p, g->pr_cap_e, g->pr_cap_v, bt, cin, pv,
+                                          g->pr_acc, g->n, s));
+      LAUNCH_TRY(launch_pr_seg_final_multi(g->n, p, pv, g->pr_acc, cout, last ? ranks : nullptr,
+                                           s));
+      launches += 2;
     } else {
       for (const SegDev& sg : g->segs) {
         PrRows r{sg.table, sg.ntab, sg.off, sg.idx, sg.dst, nullptr, nullptr, nullptr};

@@ -236,6 +236,12 @@ int batch_occupancy(size_t lds);
 int launch_batch(const BatchArgs& a, int grid, size_t lds, TaskCtl* ctl, int ntasks,
                  hipStream_t s);
 
+int launch_pr_seg_concurrent(const PrRows* segs, int p, int cap_e, int cap_v, int bt,
+                             const float* cin, const PrVertex& pv, double* acc, int n,
+                             hipStream_t s);
+int launch_pr_seg_final_multi(int n, int p, const PrVertex& pv, double* acc, float* cout,
+                              float* rank, hipStream_t s);
+
 int launch_pr_init(int n, const int32_t* outdeg, float* c0, float* rank, bool zero_iters,
                    hipStream_t s);
 int launch_pr_rows(const PrRows& r, int cap_e, int cap_v, int bt, int grid, const float* cin,

@@ -68,6 +68,47 @@ __global__ void k_pr_seg_final(int n, PrVertex pv, double* acc, float* cout, flo
   }
 }
 
+// Concurrent segments (one per XCD): workgroup b works on segment b % p, so
+// with p = 8 and the round-robin dispatch of workgroups over the eight XCDs
+// every XCD gathers from one segment's contributions only, which then stay
+// in that XCD's L2.  Segment x adds its rows' partial sums into its own
+// FP64 buffer acc + x n; the final pass adds the p partials of each vertex
+// (and zeroes them).  Placement only affects speed, never the result.
+template <int BT>
+__global__ __launch_bounds__(BT) void k_pr_seg_concurrent(const PrRows* segs, int p, int cap_e,
+                                                          const float* cin, PrVertex pv,
+                                                          double* acc, int n) {
+  extern __shared__ float smem[];
+  float* lds_val = smem;
+  int* lds_off = reinterpret_cast<int*>(smem + cap_e);
+  const int x = (int)(blockIdx.x % (unsigned)p);
+  const int j = (int)(blockIdx.x / (unsigned)p);
+  const int nb = (int)(gridDim.x / (unsigned)p);
+  const PrRows r = segs[x];
+  double* ax = acc + (size_t)x * (size_t)n;
+  for (int t = j; t < r.ntab; t += nb)
+    pr_rows_block<BT>(r, t, cap_e, cin, 1, pv, nullptr, nullptr, ax, lds_val, lds_off);
+}
+
+__global__ void k_pr_seg_final_multi(int n, int p, PrVertex pv, double* acc, float* cout,
+                                     float* rank) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int x = 0; x < p; ++x) {
+      double* a = acc + (size_t)x * (size_t)n + v;
+      s += *a;
+      *a = 0.0;
+    }
+    const double y = pv.base + pv.alpha * s;
+    if (rank) {
+      rank[v] = (float)y;
+    } else {
+      const int d = pv.outdeg[v];
+      cout[v] = d > 0 ? (float)(y / (double)d) : 0.0f;
+    }
+  }
+}
+
 // ------------------------------------------------------- host launchers ----
 
 static size_t pr_lds_bytes(int cap_e, int cap_v) {
@@ -95,6 +136,29 @@ int launch_pr_rows(const PrRows& r, int cap_e, int cap_v, int bt, int grid, cons
     case 512: hipLaunchKernelGGL(k_pr_rows<512>, dim3(blocks), dim3(512), lds, s, r, cap_e, cin, mode, pv, cout, rank, acc); break;
     default: return -1;
   }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_pr_seg_concurrent(const PrRows* segs, int p, int cap_e, int cap_v, int bt,
+                             const float* cin, const PrVertex& pv, double* acc, int n,
+                             hipStream_t s) {
+  const size_t lds = pr_lds_bytes(cap_e, cap_v);
+  const int blocks = p * std::max(1, 2048 / p);
+  switch (bt) {
+    case 64: hipLaunchKernelGGL(k_pr_seg_concurrent<64>, dim3(blocks), dim3(64), lds, s, segs, p, cap_e, cin, pv, acc, n); break;
+    case 128: hipLaunchKernelGGL(k_pr_seg_concurrent<128>, dim3(blocks), dim3(128), lds, s, segs, p, cap_e, cin, pv, acc, n); break;
+    case 256: hipLaunchKernelGGL(k_pr_seg_concurrent<256>, dim3(blocks), dim3(256), lds, s, segs, p, cap_e, cin, pv, acc, n); break;
+    case 512: hipLaunchKernelGGL(k_pr_seg_concurrent<512>, dim3(blocks), dim3(512), lds, s, segs, p, cap_e, cin, pv, acc, n); break;
+    default: return -1;
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_pr_seg_final_multi(int n, int p, const PrVertex& pv, double* acc, float* cout,
+                              float* rank, hipStream_t s) {
+  const int blocks = (int)std::min<long long>(4096, ((long long)n + 255) / 256);
+  hipLaunchKernelGGL(k_pr_seg_final_multi, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, n, p,
+                     pv, acc, cout, rank);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -87,7 +87,9 @@ def test_pagerank_families_default():
     dict(pull_block_edges=8192, block_threads=512), dict(block_threads=64),
     dict(block_threads=128), dict(num_segments=2), dict(num_segments=3, segment_strategy=1),
     dict(num_segments=8, pull_block_edges=128), dict(num_segments=64, segment_strategy=1),
-], ids=lambda c: "_".join("%s%s" % (k[:6], v) for k, v in c.items()))
+    dict(num_segments=8, segments_concurrent=1),
+    dict(num_segments=3, segment_strategy=1, segments_concurrent=1, pull_block_edges=256),
+], ids=lambda c: "_".join("%s%s" % (k[:8], v) for k, v in c.items()))
 def test_pagerank_schedules(cfg):
     for el, g, og in fam_graphs():
         say("pr %s %s" % (el.name, cfg))

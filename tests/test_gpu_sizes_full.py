@@ -91,6 +91,10 @@ def test_rmat22_pagerank():
     say("rmat22 pagerank 8 segments")
     x = run_pr(g, 20)
     assert pr_max_rel(x, oracle.pagerank(og, 20, 0.85)) <= PR_RTOL
+    g.set_schedule(num_segments=8, segments_concurrent=1)
+    say("rmat22 pagerank 8 concurrent segments")
+    x = run_pr(g, 20)
+    assert pr_max_rel(x, oracle.pagerank(og, 20, 0.85)) <= PR_RTOL
     g.set_schedule()
     _G.pop("rmat22", None)
 
