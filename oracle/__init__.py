@@ -50,6 +50,8 @@ def _load():
         lib.or_cc.argtypes = [i32, vp, vp, vp]
         lib.or_dijkstra.restype = ctypes.c_int
         lib.or_dijkstra.argtypes = [i32, vp, vp, vp, i32, vp]
+        lib.or_bc.restype = i32
+        lib.or_bc.argtypes = [i32, vp, vp, i32, vp, vp]
         lib.or_bellman_ford.restype = i32
         lib.or_bellman_ford.argtypes = [i32, vp, vp, vp, i32, vp]
         _lib = lib
@@ -166,6 +168,16 @@ def bellman_ford(g: Graph, s):
     if r < 0:
         raise ValueError("or_bellman_ford failed")
     return dist, int(r)
+
+
+def bc(g: Graph, s):
+    """Single-source betweenness dependencies (Brandes) and path counts."""
+    delta = np.empty(g.n, np.float64)
+    sigma = np.empty(g.n, np.float64)
+    r = _load().or_bc(g.n, _ptr(g.out.off), _ptr(g.out.idx), int(s), _ptr(delta), _ptr(sigma))
+    if r < 0:
+        raise ValueError("or_bc failed")
+    return delta, sigma
 
 
 def check_bfs_parents(g: Graph, s, level, parent):

@@ -394,3 +394,86 @@ def test_sssp_overflow_detected():
         oracle.dijkstra(g, 0)
     with pytest.raises(OverflowError):
         oracle.bellman_ford(g, 0)
+
+
+# ---------------------------------------------------------------- betweenness
+
+def brute_bc(n, src, dst, s):
+    """Dependencies by definition: all-pairs shortest-path lengths and counts
+    (Floyd-Warshall over path counts), then
+    delta_s(v) = sum over t != s, v of sigma_st(v) / sigma_st,
+    sigma_st(v) = sigma_sv * sigma_vt when d(s,v) + d(v,t) = d(s,t)."""
+    INF = float("inf")
+    d = [[INF] * n for _ in range(n)]
+    c = [[0] * n for _ in range(n)]
+    for i in range(n):
+        d[i][i] = 0
+        c[i][i] = 1
+    for a, b in set(zip(src, dst)):
+        if a != b:
+            d[a][b] = 1
+            c[a][b] = 1
+    # path counts by BFS layers from every vertex (unit weights)
+    for i in range(n):
+        dist = [INF] * n
+        cnt = [0] * n
+        dist[i], cnt[i] = 0, 1
+        frontier = [i]
+        adj = {}
+        for a, b in set(zip(src, dst)):
+            if a != b:
+                adj.setdefault(a, []).append(b)
+        while frontier:
+            nxt = []
+            for u in frontier:
+                for w in adj.get(u, []):
+                    if dist[w] == INF:
+                        dist[w] = dist[u] + 1
+                        nxt.append(w)
+                    if dist[w] == dist[u] + 1:
+                        cnt[w] += cnt[u]
+            frontier = nxt
+        d[i], c[i] = dist, cnt
+    out = []
+    for v in range(n):
+        tot = Fraction(0)
+        if v != s:
+            for t in range(n):
+                if t in (s, v) or d[s][t] == INF:
+                    continue
+                if d[s][v] + d[v][t] == d[s][t]:
+                    tot += Fraction(c[s][v] * c[v][t], c[s][t])
+        out.append(float(tot))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_bc_matches_definition(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(5, 14))
+    el = gg.uniform(n, int(rng.integers(n, 4 * n)), seed=300 + seed)
+    g = oracle.Graph(el)
+    for s in range(min(n, 4)):
+        delta, sigma = oracle.bc(g, s)
+        ref = brute_bc(n, list(el.src), list(el.dst), s)
+        assert np.allclose(delta, ref, rtol=1e-12, atol=1e-12), (seed, s)
+
+
+def test_bc_closed_forms():
+    # path 0 -> 1 -> ... -> n-1 from 0: vertex v lies on the paths to the
+    # n-1-v vertices after it
+    n = 9
+    g = oracle.Graph(gg.path(n))
+    delta, sigma = oracle.bc(g, 0)
+    assert list(delta) == [0.0] + [float(n - 1 - v) for v in range(1, n)]
+    assert np.all(sigma == 1.0)
+    # star out of the center: every leaf has dependency 0
+    g = oracle.Graph(gg.star(7))
+    delta, _ = oracle.bc(g, 0)
+    assert np.all(delta == 0.0)
+    # diamond 0->1, 0->2, 1->3, 2->3: two shortest paths to 3, each middle
+    # vertex carries half of it
+    el = gg.from_pairs(4, [(0, 1), (0, 2), (1, 3), (2, 3)])
+    delta, sigma = oracle.bc(oracle.Graph(el), 0)
+    assert list(sigma) == [1.0, 1.0, 1.0, 2.0]
+    assert list(delta) == [0.0, 0.5, 0.5, 0.0]
