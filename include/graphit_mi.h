@@ -121,7 +121,8 @@ typedef struct gi_schedule {
 /* Per-run statistics of the last algorithm call on a graph. */
 #define GI_MAX_TRACE 4096
 typedef struct gi_run_stats {
-  int32_t algorithm;      /* 0 PageRank, 1 BFS, 2 CC, 3 SSSP, 4 PageRankDelta  */
+  int32_t algorithm;      /* 0 PageRank, 1 BFS, 2 CC, 3 SSSP, 4 PageRankDelta,
+                             5 betweenness                                     */
   int32_t steps;          /* edgeset.apply steps executed                        */
   int32_t dense_steps;    /* of which dense (pull or dense push)                 */
   int32_t trace_len;      /* entries valid in the arrays below (<= GI_MAX_TRACE) */
@@ -259,6 +260,21 @@ gi_status gi_sssp(gi_graph* g, int32_t src, uint32_t* dist, void* stream);
  * finite), UNSUPPORTED, OUT_OF_MEMORY, DEVICE. */
 gi_status gi_prdelta(gi_graph* g, int32_t rounds, double damping, double epsilon, double* ranks,
                      void* stream);
+
+/* Betweenness centrality from one source (the paper's BC: a forward apply
+ * counting shortest paths, then a backward apply of the dependencies, as
+ * defined by Brandes, J. Math. Sociol. 2001):
+ *   sigma[s] = 1, sigma[w] = sum of sigma[v] over edges v -> w with
+ *   level[v] = level[w] - 1;
+ *   dependency[v] = sum over v -> w with level[w] = level[v] + 1 of
+ *   sigma[v] / sigma[w] * (1 + dependency[w]); dependency[s] = 0.
+ * Forward levels are SparsePush with FP64 atomic adds; the trace records
+ * each level's size.  Summing the dependencies of every source gives the
+ * betweenness of every vertex.
+ *   dependency  device out, n doubles (0 where unreachable).
+ *   sigma       device out, n doubles, or NULL.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+gi_status gi_bc(gi_graph* g, int32_t src, double* dependency, double* sigma, void* stream);
 
 /* Statistics of the last algorithm call on g. */
 gi_status gi_get_run_stats(const gi_graph* g, gi_run_stats* out);

@@ -109,6 +109,7 @@ _SIGS = {
     "gi_get_run_stats": (ctypes.c_int, [_vp, _vp]),
     "gi_set_step_timing": (ctypes.c_int, [_vp, _i32]),
     "gi_prdelta": (ctypes.c_int, [_vp, _i32, ctypes.c_double, ctypes.c_double, _vp, _vp]),
+    "gi_bc": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp]),
     "gi_selector_create": (ctypes.c_int, [ctypes.c_uint64, _vp]),
     "gi_selector_destroy": (ctypes.c_int, [_vp]),
     "gi_selector_get_params": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -328,6 +329,11 @@ class Graph:
         return a[:k], b[:k]
 
     # ---- algorithms: outputs are device tensors supplied by the caller ----
+    def bc(self, src, dependency, sigma=None, stream=None):
+        """Single-source betweenness dependencies (float64 device tensors)."""
+        _check(lib.gi_bc(self._h, int(src), _dptr(dependency), _dptr(sigma), _stream(stream)))
+        return dependency
+
     def prdelta(self, ranks, rounds=10, damping=0.85, eps=0.1, stream=None):
         """PageRankDelta into a float64 device tensor of n entries."""
         _check(lib.gi_prdelta(self._h, int(rounds), float(damping), float(eps), _dptr(ranks),

@@ -586,6 +586,129 @@ __global__ void k_prd_init(PrdArgs a) {
   for (int i = tid; i < kParts; i += nt) a.part[i] = Part{0, 0, 0, 0};
 }
 
+// ----------------------------------------------------------- betweenness --
+//
+// Brandes' dependencies from one source as two labelled sweeps (the paper's
+// betweenness program: a forward apply that counts shortest paths, then a
+// backward apply over the levels in reverse).  Forward, level by level: the
+// listed vertices of level L push their path counts to out-neighbours; the
+// first to claim a vertex (compare-and-swap on its level) appends it to the
+// level-ordered list with one atomic per wave, and every edge into level
+// L+1 adds sigma[u] with an FP64 atomic.  Backward, for L from the deepest
+// level down: each vertex w of level L+1 sends (1 + delta[w]) / sigma[w] to
+// its in-neighbours at level L, which then set delta = sigma * the sum.
+
+struct BcFwdVisit {
+  const int32_t* idx;
+  int32_t* level;
+  double* sigma;
+  int32_t* order;
+  unsigned long long* count;
+  int l1;
+  __device__ __forceinline__ void operator()(int u, int e, bool valid) {
+    int v = -1;
+    bool win = false, add = false;
+    if (valid) {
+      v = idx[e];
+      const int lv = level[v];
+      if (lv < 0) {
+        const int old = atomicCAS(&level[v], -1, l1);
+        win = old == -1;
+        add = win || old == l1;
+      } else {
+        add = lv == l1;
+      }
+      if (add) atomicAdd(&sigma[v], sigma[u]);
+    }
+    // called by whole waves: one reservation per wave for the new vertices
+    const unsigned long long m = __ballot(win);
+    if (m) {
+      const int leader = __ffsll((long long)m) - 1;
+      unsigned long long base = 0;
+      if (__lane_id() == leader) base = atomicAdd(count, (unsigned long long)__popcll(m));
+      base = __shfl(base, leader, kWave);
+      if (win) order[base + __popcll(m & lanemask_lt())] = v;
+    }
+  }
+};
+
+struct BcBwdVisit {
+  const int32_t* idx;
+  const int32_t* level;
+  const double* sigma;
+  const double* delta;
+  double* acc;
+  int lb;
+  __device__ __forceinline__ void operator()(int w, int e, bool valid) {
+    if (!valid) return;
+    const int v = idx[e];
+    if (level[v] == lb) atomicAdd(&acc[v], (1.0 + delta[w]) / sigma[w]);
+  }
+};
+
+template <int BT>
+__global__ __launch_bounds__(BT) void k_bc_forward(BcArgs a) {
+  const Control* c = a.ctl;
+  if (c->done) return;
+  const int l1 = c->steps + 1;
+  BcFwdVisit vis{a.g.out_idx, a.level, a.sigma, a.order, &a.ctl->bc_count, l1};
+  push_list<BT>(a.order, (long long)c->bc_start, (long long)c->bc_end, a.g.out_off, vis);
+}
+
+// Close the level: log it, and either end the sweep or open the next level.
+__global__ void k_bc_advance(BcArgs a) {
+  Control* c = a.ctl;
+  if (c->done) return;
+  const int k = c->steps;
+  const unsigned long long cnt = __hip_atomic_load(&c->bc_count, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+  if (k < kMaxLog)
+    c->host->log[k] = StepLog{GI_DIR_SPARSE_PUSH, (int)(c->bc_end - c->bc_start), 0, 0};
+  c->steps = k + 1;
+  a.bounds[k + 1] = c->bc_end;
+  if (cnt == c->bc_end) {
+    c->done = 1;
+    publish_done(c, k + 1);
+  } else {
+    c->bc_start = c->bc_end;
+    c->bc_end = cnt;
+  }
+}
+
+template <int BT>
+__global__ __launch_bounds__(BT) void k_bc_backward(BcArgs a, long long nb, long long ne, int lb) {
+  BcBwdVisit vis{a.g.in_idx, a.level, a.sigma, a.delta, a.acc, lb};
+  push_list<BT>(a.order, nb, ne, a.g.in_off, vis);
+}
+
+__global__ void k_bc_finish(BcArgs a, long long b, long long e) {
+  for (long long i = b + blockIdx.x * (long long)blockDim.x + threadIdx.x; i < e;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int v = a.order[i];
+    a.delta[v] = v == a.src ? 0.0 : a.sigma[v] * a.acc[v];
+    a.acc[v] = 0.0;
+  }
+}
+
+__global__ void k_bc_init(BcArgs a) {
+  const int n = a.g.n;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x, nt = gridDim.x * blockDim.x;
+  for (int v = tid; v < n; v += nt) {
+    const bool s = v == a.src;
+    a.level[v] = s ? 0 : -1;
+    a.sigma[v] = s ? 1.0 : 0.0;
+    a.acc[v] = 0.0;
+    a.delta[v] = 0.0;
+  }
+  if (tid == 0) {
+    a.order[0] = a.src;
+    a.bounds[0] = 0;
+    a.ctl->bc_start = 0;
+    a.ctl->bc_end = 1;
+    a.ctl->bc_count = 1;
+  }
+}
+
 // Control-block reset shared by the runs (one thread).
 __global__ void k_ctl_init(Control* c, HostFlags* host, unsigned long long delta) {
   c->mode = MODE_NONE;
@@ -748,6 +871,31 @@ int enqueue_prd_step(const Engine& e, const FrontierArgs& f, const DecideArgs& d
   hipLaunchKernelGGL(k_prd_update, dim3(grid_for((long long)((a.g.n + 63) / 64) * 64, 256, 2048)),
                      dim3(256), 0, s, a);
   mark(te, 2, s);
+  return GI_OK_LAUNCH();
+}
+
+int launch_bc_init(const BcArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_bc_init, dim3(grid_for(a.g.n, 256, 2048)), dim3(256), 0, s, a);
+  return GI_OK_LAUNCH();
+}
+
+int enqueue_bc_forward(const BcArgs& a, const StepEvents* te, hipStream_t s) {
+  mark(te, 0, s);
+  mark(te, 1, s);
+  hipLaunchKernelGGL(k_bc_forward<kBT>, dim3(kParts), dim3(kBT), 0, s, a);
+  hipLaunchKernelGGL(k_bc_advance, dim3(1), dim3(1), 0, s, a);
+  mark(te, 2, s);
+  return GI_OK_LAUNCH();
+}
+
+int enqueue_bc_backward_level(const BcArgs& a, long long next_begin, long long next_end,
+                              long long begin, long long end, int level, hipStream_t s) {
+  const long long items = next_end - next_begin;
+  const int blocks = (int)std::max<long long>(1, std::min<long long>(kParts, (items + kBT - 1) / kBT));
+  hipLaunchKernelGGL(k_bc_backward<kBT>, dim3(blocks), dim3(kBT), 0, s, a, next_begin, next_end,
+                     level);
+  const int fb = (int)std::max<long long>(1, std::min<long long>(2048, (end - begin + 255) / 256));
+  hipLaunchKernelGGL(k_bc_finish, dim3(fb), dim3(256), 0, s, a, begin, end);
   return GI_OK_LAUNCH();
 }
 

@@ -118,7 +118,8 @@ struct gi_graph {
   bool timing_failed = false;
   std::vector<StepEvents> tev;
   int tev_count = 0;        // steps of the last run that carry events
-  int last_steps[5] = {0, 0, 0, 0, 0};  // steps of the previous run, per algorithm
+  int last_steps[6] = {0, 0, 0, 0, 0, 0};  // steps of the previous run, per algorithm
+  void* bc = nullptr;  // betweenness scratch: level, sigma, acc, order, bounds
   double* prd = nullptr;  // PageRankDelta: delta, contrib, dsum (3 n doubles)
   // selector features (graph level) and the attached selector
   FeatConst fc_bfs{}, fc_cc{}, fc_pr{};
@@ -1213,6 +1214,51 @@ extern "C" gi_status gi_prdelta(gi_graph* g, int32_t rounds, double damping, dou
       "PageRankDelta");
   if (st != GI_OK) return st;
   return read_loop_stats(g, ALG_PRD);
+}
+
+extern "C" gi_status gi_bc(gi_graph* g, int32_t src, double* dependency, double* sigma,
+                           void* stream) {
+  if (!g || !dependency) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  if (src < 0 || src >= g->n) return fail(GI_ERR_INVALID_ARG, "source %d outside [0, %d)", src, g->n);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t N = (size_t)g->n;
+  // level int32[n], sigma double[n], acc double[n], order int32[n], bounds u64[n + 2]
+  const size_t bytes = 4 * N + 8 * N + 8 * N + 4 * N + 8 * (N + 2);
+  gi_status st;
+  if (!g->bc) {
+    uint8_t* p = nullptr;
+    if ((st = dev_alloc(g, g->allocs, &p, bytes)) != GI_OK) return st;
+    g->bc = p;
+  }
+  uint8_t* base = static_cast<uint8_t*>(g->bc);
+  BcArgs a;
+  a.g = dev_graph(g);
+  a.src = src;
+  a.sigma = reinterpret_cast<double*>(base);
+  a.acc = reinterpret_cast<double*>(base + 8 * N);
+  a.bounds = reinterpret_cast<unsigned long long*>(base + 16 * N);
+  a.level = reinterpret_cast<int32_t*>(base + 16 * N + 8 * (N + 2));
+  a.order = reinterpret_cast<int32_t*>(base + 20 * N + 8 * (N + 2));
+  if (sigma) a.sigma = sigma;
+  a.delta = dependency;
+  a.ctl = g->ctl;
+  if ((st = start_run(g, 0, s)) != GI_OK) return st;
+  LAUNCH_TRY(launch_bc_init(a, s));
+  st = run_frontier_loop(
+      g, s, ALG_BC, 8, (long long)g->n + 2,
+      [&](long long k) { return enqueue_bc_forward(a, step_events(g, k), s) ? -1 : 2; },
+      "betweenness");
+  if (st != GI_OK) return st;
+  if ((st = read_loop_stats(g, ALG_BC)) != GI_OK) return st;
+  const int levels = ((const volatile HostFlags*)g->hflags)->steps;
+  std::vector<unsigned long long> bd((size_t)levels + 1);
+  HIP_TRY(hipMemcpy(bd.data(), a.bounds, 8 * bd.size(), hipMemcpyDeviceToHost));
+  for (int L = levels - 2; L >= 0; --L) {
+    LAUNCH_TRY(enqueue_bc_backward_level(a, (long long)bd[(size_t)L + 1], (long long)bd[(size_t)L + 2],
+                                         (long long)bd[(size_t)L], (long long)bd[(size_t)L + 1], L, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return GI_OK;
 }
 
 extern "C" gi_status gi_get_run_stats(const gi_graph* g, gi_run_stats* out) {

@@ -101,6 +101,11 @@ struct Control {
   long long nchunks;  // expansion chunks
   long long edges_examined;
   long long visited;  // sum of |F| over the steps decided so far (BFS)
+  // betweenness: the current level is order[bc_start, bc_end); bc_count
+  // vertices are listed so far
+  unsigned long long bc_start;
+  unsigned long long bc_end;
+  unsigned long long bc_count;
   // SSSP
   unsigned long long thresh;   // current bucket ends below thresh
   unsigned long long told;     // previous threshold (split phase)

@@ -7,7 +7,7 @@
 
 namespace gi {
 
-enum : int { ALG_PR = 0, ALG_BFS = 1, ALG_CC = 2, ALG_SSSP = 3, ALG_PRD = 4 };
+enum : int { ALG_PR = 0, ALG_BFS = 1, ALG_CC = 2, ALG_SSSP = 3, ALG_PRD = 4, ALG_BC = 5 };
 
 // Rows of one adjacency split into destination blocks (PageRank and CC pull).
 struct RowBlocks {
@@ -145,6 +145,23 @@ struct PrdArgs {
   Control* ctl;
 };
 int launch_prd_init(const PrdArgs& a, hipStream_t s);
+
+// Betweenness centrality, one source (algos.hip).
+struct BcArgs {
+  DevGraph g;
+  int src;
+  int32_t* level;
+  double* sigma;   // shortest-path counts
+  double* acc;     // backward partial sums (zero between levels)
+  double* delta;   // dependencies (output)
+  int32_t* order;  // vertices in discovery order, grouped by level
+  unsigned long long* bounds;  // bounds[k] = first list index of level k (k <= levels)
+  Control* ctl;
+};
+int launch_bc_init(const BcArgs& a, hipStream_t s);
+int enqueue_bc_forward(const BcArgs& a, const StepEvents* te, hipStream_t s);
+int enqueue_bc_backward_level(const BcArgs& a, long long next_begin, long long next_end,
+                              long long begin, long long end, int level, hipStream_t s);
 int enqueue_prd_step(const Engine& e, const FrontierArgs& f, const DecideArgs& d,
                      const PrdArgs& a, const StepEvents* te, hipStream_t s);
 

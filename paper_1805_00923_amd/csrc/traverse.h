@@ -449,6 +449,25 @@ __device__ void push_words(const uint64_t* bv, int wb, int we, int n, const int3
   }
 }
 
+// The rows of the listed vertices ids[begin, end), BT per group, groups
+// dealt over the grid.
+template <int BT, class Visit>
+__device__ void push_list(const int32_t* ids, long long begin, long long end, const int32_t* off,
+                          Visit& vis) {
+  __shared__ int sh[4];
+  for (long long base = begin + (long long)blockIdx.x * BT; base < end;
+       base += (long long)gridDim.x * BT) {
+    const long long i = base + threadIdx.x;
+    int u = -1, beg = 0, fin = 0;
+    if (i < end) {
+      u = ids[i];
+      beg = off[u];
+      fin = off[u + 1];
+    }
+    push_rows<BT>(u, beg, fin, vis, sh);
+  }
+}
+
 template <int BT, class Visit>
 __device__ void dense_push_expand(const DenseSet& fr, int n, const int32_t* off, Visit& vis) {
   dense_push_range<BT>(fr, 0, n, blockIdx.x, gridDim.x, off, vis);
