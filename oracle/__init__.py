@@ -25,7 +25,7 @@ def build(force: bool = True) -> str:
     """Compile liboracle.so (plain C, single-threaded, -O2)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-std=c11", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-std=c11", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -52,6 +52,8 @@ def _load():
         lib.or_dijkstra.argtypes = [i32, vp, vp, vp, i32, vp]
         lib.or_bc.restype = i32
         lib.or_bc.argtypes = [i32, vp, vp, i32, vp, vp]
+        lib.or_eigenvector.restype = ctypes.c_int
+        lib.or_eigenvector.argtypes = [i32, vp, vp, i32, vp]
         lib.or_bellman_ford.restype = i32
         lib.or_bellman_ford.argtypes = [i32, vp, vp, vp, i32, vp]
         _lib = lib
@@ -168,6 +170,14 @@ def bellman_ford(g: Graph, s):
     if r < 0:
         raise ValueError("or_bellman_ford failed")
     return dist, int(r)
+
+
+def eigenvector(g: Graph, iters=20):
+    """Eigenvector centrality by L2-normalised power iteration, fp64."""
+    x = np.empty(g.n, np.float64)
+    if _load().or_eigenvector(g.n, _ptr(g.inc.off), _ptr(g.inc.idx), int(iters), _ptr(x)):
+        raise ValueError("or_eigenvector failed")
+    return x
 
 
 def bc(g: Graph, s):

@@ -14,6 +14,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <math.h>
 
 /* ------------------------------------------------------------------------ */
 /* Adjacency build.                                                          */
@@ -404,4 +405,32 @@ int or_bc(int32_t n, const int32_t* off, const int32_t* idx, int32_t s, double* 
   free(order);
   free(sigma);
   return tail;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Eigenvector centrality by power iteration (the kernel the paper fuses    */
+/* with PageRank in its program-structure optimizations; the paper gives no */
+/* formula, this is the textbook one):                                      */
+/*   x_0[v] = 1/n;  y[v] = sum_{u -> v} x_k[u];  x_{k+1} = y / ||y||_2,     */
+/* and x_{k+1} = 0 when ||y|| = 0.  Pull order over the in-adjacency, fp64. */
+/* ------------------------------------------------------------------------ */
+int or_eigenvector(int32_t n, const int32_t* in_off, const int32_t* in_idx, int32_t iters,
+                   double* x) {
+  if (n <= 0 || iters < 0) return -1;
+  double* y = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!y) return -2;
+  for (int32_t v = 0; v < n; ++v) x[v] = 1.0 / (double)n;
+  for (int32_t k = 0; k < iters; ++k) {
+    double ss = 0.0;
+    for (int32_t v = 0; v < n; ++v) {
+      double s = 0.0;
+      for (int32_t e = in_off[v]; e < in_off[v + 1]; ++e) s += x[in_idx[e]];
+      y[v] = s;
+      ss += s * s;
+    }
+    const double norm = sqrt(ss);
+    for (int32_t v = 0; v < n; ++v) x[v] = norm > 0.0 ? y[v] / norm : 0.0;
+  }
+  free(y);
+  return 0;
 }

@@ -477,3 +477,40 @@ def test_bc_closed_forms():
     delta, sigma = oracle.bc(oracle.Graph(el), 0)
     assert list(sigma) == [1.0, 1.0, 1.0, 2.0]
     assert list(delta) == [0.0, 0.5, 0.5, 0.0]
+
+
+# -------------------------------------------------------- eigenvector centrality
+
+def dense_eigenvector(n, src, dst, iters):
+    A = np.zeros((n, n))
+    for a, b in set(zip(src, dst)):
+        if a != b:
+            A[a, b] = 1.0
+    x = np.full(n, 1.0 / n)
+    for _ in range(iters):
+        y = A.T @ x
+        nrm = np.linalg.norm(y)
+        x = y / nrm if nrm > 0 else np.zeros(n)
+    return x
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_eigenvector_matches_dense_power_iteration(seed):
+    el = gg.uniform(40 + 7 * seed, 200, seed=400 + seed)
+    x = oracle.eigenvector(oracle.Graph(el), 15)
+    assert np.allclose(x, dense_eigenvector(el.n, list(el.src), list(el.dst), 15), rtol=1e-12,
+                       atol=1e-15)
+
+
+def test_eigenvector_closed_forms():
+    n = 12
+    x = oracle.eigenvector(oracle.Graph(gg.cycle(n)), 7)          # stays uniform
+    assert np.allclose(x, 1.0 / np.sqrt(n), rtol=1e-14)
+    x = oracle.eigenvector(oracle.Graph(gg.complete(9)), 3)
+    assert np.allclose(x, 1.0 / 3.0, rtol=1e-14)
+    star_in = gg.star(10, out=False)                                # leaves -> centre 0
+    x1 = oracle.eigenvector(oracle.Graph(star_in), 1)
+    assert x1[0] == 1.0 and np.all(x1[1:] == 0.0)
+    x2 = oracle.eigenvector(oracle.Graph(star_in), 2)              # the centre points nowhere
+    assert np.all(x2 == 0.0)
+    assert np.all(oracle.eigenvector(oracle.Graph(gg.empty(5)), 4) == 0.0)
