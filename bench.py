@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="bfs_cc_rmat22",
                     choices=["bfs_cc_rmat22", "pr_rmat16", "pr_rmat22", "sssp_grid", "selector",
-                             "batched", "prdelta_rmat22"])
+                             "batched", "prdelta_rmat22", "prec_rmat22"])
     ap.add_argument("--heldout", default="small", choices=["small", "full"],
                     help="selector workload: held-out Chung-Lu graph with 4M vertices (small) "
                          "or 41M vertices and ~1.4B edges (full)")
@@ -764,6 +764,71 @@ def run_prdelta(args, torch, dev):
     return value, "GTEPS", dt * 1e3 / args.steps, "f64", config, None, cpu, detail
 
 
+def run_prec(args, torch, dev):
+    """PageRank and eigenvector centrality, 20 iterations each, on R-MAT scale
+    22 (seed 2): the fused pass (one traversal, (contribution, x) pairs)
+    timed against the two separate passes.  GTEPS counts the edges of both
+    kernels, 2 * 20 * m per run, either way."""
+    import numpy as np
+    import paper_1805_00923_amd as gi
+    el, g = make_rmat_graph(22, 2)
+    n, m = g.n, g.m
+    ranks = torch.empty(n, dtype=torch.float32, device=dev)
+    eigen = torch.empty(n, dtype=torch.float32, device=dev)
+    g.set_schedule(**sched_overrides(args.schedule))
+    g.set_step_timing(True)
+    res = {}
+    outs = {}
+    for fused in (False, True):
+        for _ in range(max(1, args.warmup)):
+            g.pagerank_eigenvector(ranks, eigen, 20, 0.85, fused)
+        torch.cuda.synchronize()
+        tally = KernelTally("k_prec_rows<fused>" if fused else "k_pr_rows + k_prec_rows<unfused>")
+        kms = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.pagerank_eigenvector(ranks, eigen, 20, 0.85, fused)
+            kms.append(g.stats().kernel_ms)
+            _, mm = g.step_times()
+            per = 4 * m + 24 * n if fused else 8 * m + 28 * n
+            tally.add(mm, [per] * len(mm))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        res[fused] = (dt, float(np.median(kms)), tally)
+        outs[fused] = (ranks.clone(), eigen.clone())
+    dt, kmed, tally = res[True]
+    dtu, kmedu, tallyu = res[False]
+    (rf, ef), (ru, eu) = outs[True], outs[False]
+    agree = {"pr_max_rel": float(((rf.double() - ru.double()).abs() / ru.double()).max().item()),
+             "ec_max_abs_over_max": float((ef.double() - eu.double()).abs().max().item()
+                                          / max(eu.double().abs().max().item(), 1e-30))}
+    value = 40.0 * m / dt / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        og = oracle.Graph(el)
+        t0 = time.perf_counter()
+        oracle.pagerank(og, 3, 0.85)
+        oracle.eigenvector(og, 3)
+        dtc = time.perf_counter() - t0
+        cpu = {"value": round(6.0 * m / dtc / 1e9, 5), "unit": "GTEPS", "cores": 1,
+               "kind": "oracle", "sample": "fp64 pull PageRank and power-iteration eigenvector "
+                                           "centrality, 3 iterations each on the full graph, "
+                                           "one thread, %.2f s" % dtc}
+    uroof = tallyu.roofline()
+    detail = {"fused_ms": round(dt * 1e3, 3), "unfused_ms": round(dtu * 1e3, 3),
+              "fused_kernel_ms_median": round(kmed, 3),
+              "unfused_kernel_ms_median": round(kmedu, 3),
+              "fusion_speedup": round(kmedu / kmed, 3),
+              "unfused_gteps": round(40.0 * m / dtu / 1e9, 3),
+              "unfused_roofline": uroof, "fused_vs_unfused": agree,
+              "bytes_per_iteration": {"fused": 4 * m + 24 * n, "unfused": 8 * m + 28 * n}}
+    config = {"workload": "pagerank20+eigenvector20_fused_rmat22_ef16", "n": n, "m": m,
+              "schedule": g.schedule().as_dict()}
+    return value, "GTEPS", dt * 1e3, "f32 storage / f64 accumulate", config, tally.roofline(), \
+        cpu, detail
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -786,6 +851,8 @@ def main():
         res = run_pr(args, torch, dev, 22)
     elif args.workload == "prdelta_rmat22":
         res = run_prdelta(args, torch, dev)
+    elif args.workload == "prec_rmat22":
+        res = run_prec(args, torch, dev)
     elif args.workload == "batched":
         res = run_batched(args, torch, dev)
     elif args.workload == "selector":

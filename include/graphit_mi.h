@@ -122,7 +122,7 @@ typedef struct gi_schedule {
 #define GI_MAX_TRACE 4096
 typedef struct gi_run_stats {
   int32_t algorithm;      /* 0 PageRank, 1 BFS, 2 CC, 3 SSSP, 4 PageRankDelta,
-                             5 betweenness                                     */
+                             5 betweenness, 6 PageRank + eigenvector           */
   int32_t steps;          /* edgeset.apply steps executed                        */
   int32_t dense_steps;    /* of which dense (pull or dense push)                 */
   int32_t trace_len;      /* entries valid in the arrays below (<= GI_MAX_TRACE) */
@@ -275,6 +275,21 @@ gi_status gi_prdelta(gi_graph* g, int32_t rounds, double damping, double epsilon
  *   sigma       device out, n doubles, or NULL.
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
 gi_status gi_bc(gi_graph* g, int32_t src, double* dependency, double* sigma, void* stream);
+
+/* PageRank and eigenvector centrality together, fused or not (the paper's
+ * loop fusion, apply-function fusion and vertex-data layout optimization,
+ * section 4.3 and its evaluation of the PageRank + eigenvector fusion).
+ * PageRank as gi_pagerank (DensePull, FP32 storage, FP64 sums); eigenvector
+ * centrality by L2-normalised power iteration:
+ *   x_0 = 1/n;  x_{k+1} = y / ||y||_2 with y[v] = sum_{u->v} x_k[u]
+ *   (x_{k+1} = 0 when ||y|| = 0).
+ * fused = 1: one pass over the in-edges per iteration gathers both values
+ * of each source from one array of (contribution, x) pairs; fused = 0: two
+ * passes over separate arrays.  Results agree either way.
+ *   ranks, eigen   device out, n floats each.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+gi_status gi_pagerank_eigenvector(gi_graph* g, int32_t iters, float damping, float* ranks,
+                                  float* eigen, int32_t fused, void* stream);
 
 /* Statistics of the last algorithm call on g. */
 gi_status gi_get_run_stats(const gi_graph* g, gi_run_stats* out);

@@ -110,6 +110,7 @@ _SIGS = {
     "gi_set_step_timing": (ctypes.c_int, [_vp, _i32]),
     "gi_prdelta": (ctypes.c_int, [_vp, _i32, ctypes.c_double, ctypes.c_double, _vp, _vp]),
     "gi_bc": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp]),
+    "gi_pagerank_eigenvector": (ctypes.c_int, [_vp, _i32, ctypes.c_float, _vp, _vp, _i32, _vp]),
     "gi_selector_create": (ctypes.c_int, [ctypes.c_uint64, _vp]),
     "gi_selector_destroy": (ctypes.c_int, [_vp]),
     "gi_selector_get_params": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -329,6 +330,12 @@ class Graph:
         return a[:k], b[:k]
 
     # ---- algorithms: outputs are device tensors supplied by the caller ----
+    def pagerank_eigenvector(self, ranks, eigen, iters=20, damping=0.85, fused=True,
+                             stream=None):
+        _check(lib.gi_pagerank_eigenvector(self._h, int(iters), float(damping), _dptr(ranks),
+                                           _dptr(eigen), 1 if fused else 0, _stream(stream)))
+        return ranks, eigen
+
     def bc(self, src, dependency, sigma=None, stream=None):
         """Single-source betweenness dependencies (float64 device tensors)."""
         _check(lib.gi_bc(self._h, int(src), _dptr(dependency), _dptr(sigma), _stream(stream)))

@@ -120,6 +120,12 @@ struct gi_graph {
   int tev_count = 0;        // steps of the last run that carry events
   int last_steps[6] = {0, 0, 0, 0, 0, 0};  // steps of the previous run, per algorithm
   void* bc = nullptr;  // betweenness scratch: level, sigma, acc, order, bounds
+  int2* prec_tab = nullptr;  // in-row blocks for PageRank + eigenvector
+  int prec_ntab = 0;
+  float2* prec_aos = nullptr;  // 2 n pairs
+  float* prec_y = nullptr;     // 2 n
+  double* prec_norm = nullptr;
+  int prec_norm_cap = 0;
   double* prd = nullptr;  // PageRankDelta: delta, contrib, dsum (3 n doubles)
   // selector features (graph level) and the attached selector
   FeatConst fc_bfs{}, fc_cc{}, fc_pr{};
@@ -1258,6 +1264,94 @@ extern "C" gi_status gi_bc(gi_graph* g, int32_t src, double* dependency, double*
                                          (long long)bd[(size_t)L], (long long)bd[(size_t)L + 1], L, s));
   }
   HIP_TRY(hipStreamSynchronize(s));
+  return GI_OK;
+}
+
+extern "C" gi_status gi_pagerank_eigenvector(gi_graph* g, int32_t iters, float damping,
+                                             float* ranks, float* eigen, int32_t fused,
+                                             void* stream) {
+  if (!g || !ranks || !eigen) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  if (iters < 0) return fail(GI_ERR_INVALID_ARG, "iters must be >= 0");
+  if (!(damping >= 0.0f && damping <= 1.0f)) return fail(GI_ERR_INVALID_ARG, "damping outside [0,1]");
+  if (fused != 0 && fused != 1) return fail(GI_ERR_INVALID_ARG, "fused must be 0 or 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t N = (size_t)g->n;
+  gi_status st;
+  if (!g->prec_tab) {
+    std::vector<int2> tab = make_row_blocks(g->h_in_off.data(), g->n, kPrEcCapE, kPrEcCapV);
+    if ((st = dev_alloc(g, g->allocs, &g->prec_tab, tab.size())) != GI_OK) return st;
+    if ((st = upload(tab.data(), g->prec_tab, tab.size() * sizeof(int2))) != GI_OK) return st;
+    g->prec_ntab = (int)tab.size();
+    if ((st = dev_alloc(g, g->allocs, &g->prec_aos, 2 * N)) != GI_OK) return st;
+    if ((st = dev_alloc(g, g->allocs, &g->prec_y, 2 * N)) != GI_OK) return st;
+  }
+  if (g->prec_norm_cap < iters + 1) {
+    const int cap = std::max(iters + 1, 64);
+    if ((st = dev_alloc(g, g->allocs, &g->prec_norm, (size_t)cap)) != GI_OK) return st;
+    g->prec_norm_cap = cap;
+  }
+  PrVertex pv;
+  pv.outdeg = g->outdeg;
+  pv.alpha = (double)damping;
+  pv.base = (1.0 - (double)damping) / (double)g->n;
+  PrEcArgs a;
+  a.rb = RowBlocks{g->prec_tab, g->prec_ntab, g->in_off, g->in_idx};
+  a.pv = pv;
+  int launches = 0;
+  HIP_TRY(hipEventRecord(g->ev[0], s));
+  if (fused) {
+    LAUNCH_TRY(launch_prec_init(g->n, g->outdeg, g->prec_aos, nullptr, g->prec_norm, iters + 1, s));
+  } else {
+    LAUNCH_TRY(launch_pr_init(g->n, g->outdeg, g->contrib[0], ranks, iters == 0, s));
+    LAUNCH_TRY(launch_prec_init(g->n, g->outdeg, nullptr, g->prec_y, g->prec_norm, iters + 1, s));
+    ++launches;
+  }
+  ++launches;
+  if (fused && iters == 0) LAUNCH_TRY(launch_pr_init(g->n, g->outdeg, g->contrib[0], ranks, true, s));
+  g->tev_count = 0;
+  const int bt = g->sched.block_threads > 0 ? g->sched.block_threads : 256;
+  for (int k = 0; k < iters; ++k) {
+    const bool last = k == iters - 1;
+    const StepEvents* te = step_events(g, k);
+    if (te) {
+      HIP_TRY(hipEventRecord(te->start, s));
+      HIP_TRY(hipEventRecord(te->main, s));
+    }
+    a.norm2_prev = g->prec_norm + k;
+    a.norm2_next = g->prec_norm + k + 1;
+    if (fused) {
+      a.aos_in = g->prec_aos + (k & 1) * N;
+      a.aos_out = g->prec_aos + ((k + 1) & 1) * N;
+      a.ranks = last ? ranks : nullptr;
+      LAUNCH_TRY(launch_prec_rows(a, true, s));
+      ++launches;
+    } else {
+      PrRows r{g->pr_table, g->pr_ntab, g->in_off, g->in_idx, nullptr, g->lr_acc, g->lr_cnt,
+               g->lr_chunks};
+      LAUNCH_TRY(launch_pr_rows(r, g->pr_cap_e, g->pr_cap_v, bt, 0, g->contrib[k & 1], 0, pv,
+                                g->contrib[(k + 1) & 1], last ? ranks : nullptr, nullptr, s));
+      a.y_in = g->prec_y + (k & 1) * N;
+      a.y_out = g->prec_y + ((k + 1) & 1) * N;
+      a.ranks = nullptr;
+      LAUNCH_TRY(launch_prec_rows(a, false, s));
+      launches += 2;
+    }
+    if (te) HIP_TRY(hipEventRecord(te->end, s));
+  }
+  LAUNCH_TRY(launch_ec_final(g->n, fused ? nullptr : g->prec_y + (iters & 1) * N,
+                             fused ? g->prec_aos + (iters & 1) * N : nullptr,
+                             g->prec_norm + iters, eigen, s));
+  ++launches;
+  HIP_TRY(hipEventRecord(g->ev[1], s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (g->timing_failed) return fail(GI_ERR_DEVICE, "could not create timing events");
+  if ((st = read_kernel_ms(g, launches)) != GI_OK) return st;
+  gi_run_stats& rs = g->stats;
+  rs.algorithm = 6;
+  rs.steps = iters;
+  rs.dense_steps = iters;
+  rs.edges_examined = (int64_t)iters * g->m * (fused ? 1 : 2);
+  rs.trace_len = 0;
   return GI_OK;
 }
 

@@ -259,6 +259,26 @@ int launch_pr_seg_concurrent(const PrRows* segs, int p, int cap_e, int cap_v, in
 int launch_pr_seg_final_multi(int n, int p, const PrVertex& pv, double* acc, float* cout,
                               float* rank, hipStream_t s);
 
+// PageRank and eigenvector centrality, fused or not (pagerank.hip).
+struct PrEcArgs {
+  RowBlocks rb;               // in-row blocks of at most kPrEcCapE edges (longer rows alone)
+  const float2* aos_in;       // fused: (PageRank contribution, eigenvector y) per vertex
+  float2* aos_out;
+  const float* y_in;          // eigenvector y alone (unfused)
+  float* y_out;
+  const double* norm2_prev;   // ||y_k||^2 (the next y is scaled by its inverse root)
+  double* norm2_next;         // accumulates ||y_{k+1}||^2
+  PrVertex pv;
+  float* ranks;               // fused, last iteration: PageRank out
+};
+constexpr int kPrEcCapE = 2048;
+constexpr int kPrEcCapV = 1024;
+int launch_prec_rows(const PrEcArgs& a, bool fused, hipStream_t s);
+int launch_prec_init(int n, const int32_t* outdeg, float2* aos, float* y, double* norm2,
+                     int nnorm, hipStream_t s);
+int launch_ec_final(int n, const float* y, const float2* aos, const double* norm2, float* out,
+                    hipStream_t s);
+
 int launch_pr_init(int n, const int32_t* outdeg, float* c0, float* rank, bool zero_iters,
                    hipStream_t s);
 int launch_pr_rows(const PrRows& r, int cap_e, int cap_v, int bt, int grid, const float* cin,

@@ -20,6 +20,8 @@
 // processed in order, each adding partial sums into an FP64 accumulator, so
 // the contrib gathers of one segment touch only |V_i| entries; a final pass
 // applies the vertex update.
+#include <type_traits>
+
 #include "kernels.h"
 #include "pr_block.h"
 
@@ -109,6 +111,136 @@ __global__ void k_pr_seg_final_multi(int n, int p, PrVertex pv, double* acc, flo
   }
 }
 
+// PageRank fused with eigenvector centrality (the paper's loop and apply
+// fusion plus its vertex-data layout optimization): one pass over the
+// in-edges gathers both kernels' per-source values from one array of
+// (contribution, y) pairs, so each edge fetches one 8-byte element instead
+// of two 4-byte elements in two arrays.  Eigenvector centrality is the
+// L2-normalised power iteration: y_{k+1}[v] = sum_{u->v} y_k[u] / ||y_k||,
+// the norm of each new y accumulated in FP64 as it is produced.  Unfused,
+// the same kernel gathers y alone and PageRank runs its own pass.
+template <int BT, bool FUSED>
+__global__ __launch_bounds__(BT) void k_prec_rows(PrEcArgs a) {
+  using V = typename std::conditional<FUSED, float2, float>::type;
+  __shared__ V lds_val[kPrEcCapE];
+  __shared__ int lds_off[kPrEcCapV + 1];
+  __shared__ double red[2][BT / kWave];
+  const int tid = threadIdx.x;
+  const double n2 = *a.norm2_prev;
+  const double inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+  double my_n2 = 0.0;
+  auto finish = [&](int v, double sp, double se) {
+    const double y = se * inv;
+    my_n2 += y * y;
+    if (FUSED) {
+      const double x = a.pv.base + a.pv.alpha * sp;
+      const int d = a.pv.outdeg[v];
+      a.aos_out[v] = make_float2(d > 0 ? (float)(x / (double)d) : 0.0f, (float)y);
+      if (a.ranks) a.ranks[v] = (float)x;
+    } else {
+      a.y_out[v] = (float)y;
+    }
+  };
+  auto fetch = [&](int u) -> V {
+    if constexpr (FUSED) return a.aos_in[u];
+    else return a.y_in[u];
+  };
+  for (int t = blockIdx.x; t < a.rb.ntab; t += gridDim.x) {
+    const int2 r = a.rb.table[t];
+    const int kb = r.x, ke = r.y, nr = ke - kb;
+    const int e0 = a.rb.off[kb], e1 = a.rb.off[ke], ne = e1 - e0;
+    if (ne > kPrEcCapE) {  // one long row: workgroup-wide sums
+      double sp = 0.0, se = 0.0;
+      for (int e = e0 + tid; e < e1; e += BT) {
+        const V c = fetch(a.rb.idx[e]);
+        if constexpr (FUSED) {
+          sp += (double)c.x;
+          se += (double)c.y;
+        } else {
+          se += (double)c;
+        }
+      }
+      sp = wave_sum(sp);
+      se = wave_sum(se);
+      if (__lane_id() == 0) {
+        red[0][tid / kWave] = sp;
+        red[1][tid / kWave] = se;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double tp = 0.0, te = 0.0;
+        for (int i = 0; i < BT / kWave; ++i) {
+          tp += red[0][i];
+          te += red[1][i];
+        }
+        finish(kb, tp, te);
+      }
+      __syncthreads();
+      continue;
+    }
+    gather_block<BT, V>(a.rb.idx, e0, ne, lds_val, fetch);
+    for (int k = tid; k <= nr; k += BT) lds_off[k] = a.rb.off[kb + k] - e0;
+    __syncthreads();
+    int tpv = 1;
+    if (nr < BT) {
+      tpv = BT / (nr > 0 ? nr : 1);
+      tpv = 1 << (31 - __clz(tpv));
+      if (tpv > kWave) tpv = kWave;
+    }
+    const int groups = BT / tpv, grp = tid / tpv, gl = tid % tpv;
+    for (int k0 = 0; k0 < nr; k0 += groups) {
+      const int k = k0 + grp;
+      double sp = 0.0, se = 0.0;
+      if (k < nr) {
+        const int lo = lds_off[k], hi = lds_off[k + 1];
+        for (int j = lo + gl; j < hi; j += tpv) {
+          if constexpr (FUSED) {
+            sp += (double)lds_val[j].x;
+            se += (double)lds_val[j].y;
+          } else {
+            se += (double)lds_val[j];
+          }
+        }
+      }
+      for (int o = tpv >> 1; o > 0; o >>= 1) {
+        sp += __shfl_xor(sp, o, kWave);
+        se += __shfl_xor(se, o, kWave);
+      }
+      if (gl == 0 && k < nr) finish(kb + k, sp, se);
+    }
+    __syncthreads();
+  }
+  const double tot = block_sum<BT>(my_n2);
+  if (tid == 0 && tot != 0.0) atomicAdd(a.norm2_next, tot);
+}
+
+// y_0 = 1/n (norm2[0] = 1 so that it is used unscaled), contributions of
+// x_0 = 1/n; the later norms start at 0.
+__global__ void k_prec_init(int n, const int32_t* outdeg, float2* aos, float* y, double* norm2,
+                            int nnorm) {
+  const double x0 = 1.0 / (double)n;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    if (aos) {
+      const int d = outdeg[v];
+      aos[v] = make_float2(d > 0 ? (float)(x0 / (double)d) : 0.0f, (float)x0);
+    }
+    if (y) y[v] = (float)x0;
+  }
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < nnorm; i += blockDim.x) norm2[i] = i == 0 ? 1.0 : 0.0;
+}
+
+// x_K = y_K / ||y_K|| (0 when the norm is 0).
+__global__ void k_ec_final(int n, const float* y, const float2* aos, const double* norm2,
+                           float* out) {
+  const double n2 = *norm2;
+  const double inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const double yv = aos ? (double)aos[v].y : (double)y[v];
+    out[v] = (float)(yv * inv);
+  }
+}
+
 // ------------------------------------------------------- host launchers ----
 
 static size_t pr_lds_bytes(int cap_e, int cap_v) {
@@ -167,6 +299,29 @@ int launch_pr_seg_final(int n, const PrVertex& pv, double* acc, float* cout, flo
   const int blocks = (int)std::min<long long>(4096, ((long long)n + 255) / 256);
   hipLaunchKernelGGL(k_pr_seg_final, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, n, pv, acc,
                      cout, rank);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_prec_rows(const PrEcArgs& a, bool fused, hipStream_t s) {
+  const int blocks = std::max(1, std::min(a.rb.ntab, 2048));
+  if (fused) hipLaunchKernelGGL((k_prec_rows<256, true>), dim3(blocks), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_prec_rows<256, false>), dim3(blocks), dim3(256), 0, s, a);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_prec_init(int n, const int32_t* outdeg, float2* aos, float* y, double* norm2,
+                     int nnorm, hipStream_t s) {
+  const int blocks = (int)std::min<long long>(2048, ((long long)n + 255) / 256);
+  hipLaunchKernelGGL(k_prec_init, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, n, outdeg, aos,
+                     y, norm2, nnorm);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_ec_final(int n, const float* y, const float2* aos, const double* norm2, float* out,
+                    hipStream_t s) {
+  const int blocks = (int)std::min<long long>(2048, ((long long)n + 255) / 256);
+  hipLaunchKernelGGL(k_ec_final, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, n, y, aos, norm2,
+                     out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
