@@ -437,13 +437,25 @@ typedef struct gi_batch gi_batch;
 gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, const gi_task* tasks,
                           int32_t ntasks, gi_batch** out);
 
-/* Autotuner: times each (graph, algorithm) class alone on 1, 2, 4, ... 64
- * workgroups (median of reps launches), keeps the size with the least
- * workgroup-time unless it is more than twice as slow as the fastest,
- * gives tasks longer than the balanced share of the grid their fastest
- * size, and re-plans.  Tasks with fixed workgroups keep them.
+/* Autotuner, for each workgroup size of 256, 512 and 1024 threads (only the
+ * pinned one after gi_batch_set_threads): times each (graph, algorithm)
+ * class alone on 1, 2, 4, ... 64 workgroups (median of reps launches),
+ * keeps the size with the least workgroup-time unless it is more than twice
+ * as slow as the fastest, gives tasks longer than the balanced share of the
+ * grid their fastest size, plans, and times the whole batch (median of reps
+ * launches).  Keeps the workgroup size and plan of the fastest whole batch.
+ * Tasks with fixed workgroups keep them.  The timing launches write the
+ * tasks' outputs (with correct results).
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
 gi_status gi_batch_autotune(gi_batch* b, int32_t reps);
+
+/* Threads per workgroup of the batch kernel: 256 (the default at creation),
+ * 512 or 1024; pins that size for gi_batch_autotune and re-plans (task
+ * workgroup counts are clamped to the resident grid of that size).
+ * threads = 0 unpins it.  gi_batch_get_threads reports the current size.
+ * Errors: INVALID_ARG (other sizes), OUT_OF_MEMORY, DEVICE. */
+gi_status gi_batch_set_threads(gi_batch* b, int32_t threads);
+gi_status gi_batch_get_threads(const gi_batch* b, int32_t* threads);
 
 /* Run every task once: one launch of the reset kernel and the persistent
  * kernel, captured once into a HIP graph and replayed when use_graph is

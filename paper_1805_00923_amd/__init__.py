@@ -127,6 +127,8 @@ _SIGS = {
     "gi_batch_run": (ctypes.c_int, [_vp, _i32, _vp]),
     "gi_batch_info": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "gi_batch_destroy": (ctypes.c_int, [_vp]),
+    "gi_batch_set_threads": (ctypes.c_int, [_vp, _i32]),
+    "gi_batch_get_threads": (ctypes.c_int, [_vp, _vp]),
     "gi_get_step_times": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp]),
     "gi_frontier_sparse_to_bitvec": (ctypes.c_int, [_i32, _vp, _i32, _vp, _vp]),
     "gi_frontier_bitvec_to_sparse": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp]),
@@ -494,6 +496,15 @@ class Batch:
 
     def autotune(self, reps=3):
         _check(lib.gi_batch_autotune(self._h, int(reps)))
+
+    def set_threads(self, threads):
+        """Pin the workgroup size (256, 512 or 1024); 0 lets the autotuner choose."""
+        _check(lib.gi_batch_set_threads(self._h, int(threads)))
+
+    def threads(self):
+        t = ctypes.c_int32(0)
+        _check(lib.gi_batch_get_threads(self._h, ctypes.byref(t)))
+        return t.value
 
     def run(self, use_graph=True, stream=None):
         _check(lib.gi_batch_run(self._h, 1 if use_graph else 0, _stream(stream)))

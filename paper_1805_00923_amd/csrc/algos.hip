@@ -185,66 +185,137 @@ struct CcVisit {
 };
 
 // Pull over destination blocks of the symmetric adjacency: the block's
-// neighbour labels are staged in LDS, then each row's minimum is taken by a
-// power-of-two group of threads; vertices whose label drops join the next
-// frontier.
+// neighbour labels are staged in LDS, then the rows' minima are taken by an
+// edge-parallel segmented minimum; vertices whose label drops join the next
+// frontier.  Block entries carry their edge range and the next one is
+// fetched ahead, and the block's row bounds and current labels are loaded
+// together with the gathers, so a block costs one memory latency.
 template <int BT>
 __device__ long long cc_pull(const CcArgs& c, int* lds) {
+  constexpr int kPer = (kCcCapV + 1 + BT - 1) / BT;
   int* lds_val = lds;
   int* lds_off = lds + kCcCapE;
+  int* lds_cur = lds_off + kCcCapV + 1;
+  int* lds_min = lds_cur + kCcCapV;
   __shared__ int red[BT / kWave];
   long long work = 0;
   const RowBlocks& rb = c.rows;
   const int32_t* cur = c.cur;
+  const int tid = threadIdx.x, lane = __lane_id();
   // In the first round every label is still the vertex id, so a
   // neighbour's label is its id and nothing needs gathering.  (A neighbour
   // outside the frontier cannot lower a label, but testing the frontier bit
   // before the gather measured slower than gathering every label.)
   const bool ids = c.ctl->steps == 1;
   auto label_of = [cur, ids](int u) -> int { return ids ? u : cur[u]; };
-  auto finish = [&](int v, int mn) {
-    const int lv = cur[v];
-    const int x = mn < lv ? mn : lv;
-    c.nxt[v] = x;
-    if (x < lv) c.next.insert(v);
-  };
+  // the next entry is fetched while the current block is processed
+  int4 nx = blockIdx.x < (unsigned)rb.ntab ? rb.table[blockIdx.x] : make_int4(0, 0, 0, 0);
   for (int t = blockIdx.x; t < rb.ntab; t += gridDim.x) {
-    const int2 r = rb.table[t];
-    const int kb = r.x, ke = r.y, nr = ke - kb;
-    const int e0 = rb.off[kb], e1 = rb.off[ke], ne = e1 - e0;
-    if (threadIdx.x == 0) work += ne;
-    if (ne > kCcCapE) {  // one long row: workgroup-wide minimum
-      int mn = 0x7fffffff;
-      for (int e = e0 + (int)threadIdx.x; e < e1; e += BT) mn = min(mn, label_of(rb.idx[e]));
-      mn = wave_min(mn);
-      if (__lane_id() == 0) red[threadIdx.x / kWave] = mn;
+    const int4 r = nx;
+    if (t + (int)gridDim.x < rb.ntab) nx = rb.table[t + gridDim.x];
+    if (r.y < 0) {
+      // chunk -(r.y + 1) of the long row r.x: workgroup minimum over at
+      // most kCcCapE edges (four loads in flight per thread), merged by an
+      // atomic minimum.  At the start of a round nxt equals cur for every
+      // vertex (the count pass restores the vertices that changed), so the
+      // chunk that first lowers nxt below cur adds the row to the frontier.
+      const int row = r.x, eb = r.z, ee = r.w;
+      int m0 = 0x7fffffff, m1 = 0x7fffffff;
+      int e = eb + tid;
+      for (; e + 3 * BT < ee; e += 4 * BT) {
+        const int a0 = rb.idx[e], a1 = rb.idx[e + BT], a2 = rb.idx[e + 2 * BT],
+                  a3 = rb.idx[e + 3 * BT];
+        m0 = min(m0, min(label_of(a0), label_of(a1)));
+        m1 = min(m1, min(label_of(a2), label_of(a3)));
+      }
+      for (; e < ee; e += BT) m0 = min(m0, label_of(rb.idx[e]));
+      int mn = wave_min(min(m0, m1));
+      if (lane == 0) red[tid / kWave] = mn;
       __syncthreads();
-      if (threadIdx.x == 0) {
+      if (tid == 0) {
+        work += ee - eb;
         for (int i = 0; i < BT / kWave; ++i) mn = min(mn, red[i]);
-        finish(kb, mn);
+        if (mn < c.nxt[row]) {
+          const int old = atomicMin(&c.nxt[row], mn);
+          if (mn < old && old == cur[row]) c.next.insert(row);
+        }
       }
       __syncthreads();
       continue;
     }
-    gather_block<BT, int>(rb.idx, e0, ne, lds_val, label_of);
-    for (int k = threadIdx.x; k <= nr; k += BT) lds_off[k] = rb.off[kb + k] - e0;
-    __syncthreads();
-    int tpv = 1;
-    if (nr < BT) {
-      tpv = BT / (nr > 0 ? nr : 1);
-      tpv = 1 << (31 - __clz(tpv));
-      if (tpv > kWave) tpv = kWave;
+    const int kb = r.x, ke = r.y, nr = ke - kb;
+    const int e0 = r.z, ne = r.w - r.z;
+    if (tid == 0) work += ne;
+    int offv[kPer], curv[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int k = tid + i * BT;
+      offv[i] = k <= nr ? rb.off[kb + k] : 0;
+      curv[i] = k < nr ? cur[kb + k] : 0;
     }
-    const int groups = BT / tpv, grp = threadIdx.x / tpv, gl = threadIdx.x % tpv;
-    for (int k0 = 0; k0 < nr; k0 += groups) {
-      const int k = k0 + grp;
-      int mn = 0x7fffffff;
+    gather_block<BT, int>(rb.idx, e0, ne, lds_val, label_of);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int k = tid + i * BT;
+      if (k <= nr) lds_off[k] = offv[i] - e0;
       if (k < nr) {
-        const int lo = lds_off[k], hi = lds_off[k + 1];
-        for (int j = lo + gl; j < hi; j += tpv) mn = min(mn, lds_val[j]);
+        lds_cur[k] = curv[i];
+        lds_min[k] = 0x7fffffff;
       }
-      for (int o = tpv >> 1; o > 0; o >>= 1) mn = min(mn, __shfl_xor(mn, o, kWave));
-      if (gl == 0 && k < nr) finish(kb + k, mn);
+    }
+    __syncthreads();
+    // Edge-parallel row minima: thread t takes a run of ceil(ne / BT)
+    // consecutive edges, finds the row of its first edge by binary search
+    // of the row bounds, and merges one partial minimum per row it touches
+    // with an LDS atomic.  The block's edges are spread evenly over the
+    // threads however skewed its rows are (a block can hold hundreds of
+    // empty rows and one row of a thousand edges).
+    {
+      const int ept = (ne + BT - 1) / BT;
+      const int eb = tid * ept, ee = min(ne, eb + ept);
+      if (eb < ee) {
+        int lo = 0, hi = nr;  // lds_off[lo] <= eb < lds_off[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (lds_off[mid] <= eb) lo = mid;
+          else hi = mid;
+        }
+        int k = lo, rend = lds_off[k + 1], m = 0x7fffffff;
+        for (int j = eb; j < ee; ++j) {
+          while (j >= rend) {
+            atomicMin(&lds_min[k], m);
+            m = 0x7fffffff;
+            ++k;
+            rend = lds_off[k + 1];
+          }
+          m = min(m, lds_val[j]);
+        }
+        atomicMin(&lds_min[k], m);
+      }
+    }
+    __syncthreads();
+    // vertex updates, one row per thread: the rows a wave finishes are
+    // consecutive, so their frontier bits take at most two atomic ORs
+    for (int k0 = 0; k0 < nr; k0 += BT) {
+      const int k = k0 + tid;
+      bool chg = false;
+      if (k < nr) {
+        const int lv = lds_cur[k], mn = lds_min[k];
+        const int x = mn < lv ? mn : lv;
+        c.nxt[kb + k] = x;
+        chg = x < lv;
+        if (chg && c.next.bm) c.next.bm[kb + k] = 1;
+      }
+      if (!c.next.bm) {
+        const unsigned long long m = __ballot(chg);
+        if (m != 0ull && lane == 0) {
+          const int r0 = kb + k0 + (tid - lane);
+          const int w = r0 >> 6, sh = r0 & 63;
+          atomicOr((unsigned long long*)&c.next.bv[w], m << sh);
+          if (sh != 0 && (m >> (64 - sh)) != 0ull)
+            atomicOr((unsigned long long*)&c.next.bv[w + 1], m >> (64 - sh));
+        }
+      }
     }
     __syncthreads();
   }
@@ -253,7 +324,7 @@ __device__ long long cc_pull(const CcArgs& c, int* lds) {
 
 template <int BT, int CH>
 __global__ __launch_bounds__(BT) void k_cc_step(CcArgs c, ExpandArgs x) {
-  static_assert(kCcCapE + kCcCapV + 1 <= expand_lds_ints<CH>(), "LDS too small");
+  static_assert(kCcCapE + 3 * kCcCapV + 1 <= expand_lds_ints<CH>(), "LDS too small");
   __shared__ int lds[expand_lds_ints<CH>()];
   const int mode = c.ctl->mode;
   if (mode == MODE_NONE) return;

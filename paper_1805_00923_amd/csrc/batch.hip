@@ -20,13 +20,24 @@
 // nor written in it.
 // PageRank tasks: the destination-block DensePull of pagerank.hip, blocks
 // dealt round-robin over the task's workgroups.
+//
+// The kernel comes in three workgroup sizes (256, 512 and 1024 threads).
+// Every workgroup that passes a barrier invalidates its L2 (agent-scope
+// acquire), which also drops the lines of the other tasks sharing that L2;
+// larger workgroups mean fewer barrier participants for the same threads,
+// so the autotuner weighs that against the finer granularity of small ones.
 #include "bfs_dev.h"
 #include "kernels.h"
 #include "pr_block.h"
 
 namespace gi {
 
-constexpr int kBB = 256;  // threads per workgroup
+// Minimum waves per SIMD for each workgroup size: 5 workgroups of 256, 2 of
+// 512 or 1 of 1024 threads per compute unit.
+template <int BT>
+constexpr int batch_min_waves() {
+  return BT == 256 ? 5 : 4;
+}
 
 __device__ __forceinline__ long long wall_ticks() { return (long long)wall_clock64(); }
 
@@ -76,6 +87,7 @@ __device__ bool task_barrier(TaskCtl* c, int k, int* gerr, long long limit) {
   return s_ok != 0;
 }
 
+template <int BT>
 __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const BatchArgs& a) {
   const int n = G.n, k = t.k, W = (n + 63) >> 6, tid = threadIdx.x;
   int32_t* level = static_cast<int32_t*>(t.out);
@@ -84,11 +96,11 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
   // this workgroup's words and vertices
   const int w0 = (int)((long long)W * r / k), w1 = (int)((long long)W * (r + 1) / k);
   const int v0 = w0 * 64, v1 = min(n, w1 * 64);
-  for (int v = v0 + tid; v < v1; v += kBB) {
+  for (int v = v0 + tid; v < v1; v += BT) {
     level[v] = -1;
     if (t.parent) t.parent[v] = -1;
   }
-  for (int w = w0 + tid; w < w1; w += kBB) {
+  for (int w = w0 + tid; w < w1; w += BT) {
     t.vis[w] = 0ull;
     t.bv0[w] = 0ull;
     t.bv1[w] = 0ull;
@@ -113,6 +125,7 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
   dg.in_off = G.in_off;
   dg.in_idx = G.in_idx;
   dg.outdeg = G.outdeg;
+  dg.in_probe = G.in_probe;
   int L = 0;
   for (;; ++L) {
     const long long nf = (long long)__hip_atomic_load(&c->qn[L % 3], __ATOMIC_RELAXED,
@@ -130,7 +143,7 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
       c->ds[(L + 2) % 3] = 0;
     }
     uint64_t* bclr = bv[(L + 2) % 3];
-    for (int w = w0 + tid; w < w1; w += kBB) bclr[w] = 0ull;
+    for (int w = w0 + tid; w < w1; w += BT) bclr[w] = 0ull;
     BfsArgs b{};
     b.g = dg;
     b.level = level;
@@ -140,16 +153,16 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
     b.vis = t.vis;
     long long found = 0, found_deg = 0;
     if (hybrid_dense(nf, df, G.m, 20)) {
-      bfs_pull_range<kBB, 2>(b, L + 1, w0, w1, (int)(threadIdx.x / kWave), kBB / kWave, G.outdeg,
+      bfs_pull_range<BT, 2>(b, L + 1, w0, w1, (int)(threadIdx.x / kWave), BT / kWave, G.outdeg,
                           &found, &found_deg);
     } else {
       BfsVisit vis{G.out_idx, level, t.parent, L + 1, b.next, t.vis};
       vis.deg = G.outdeg;
-      push_words<kBB>(b.cur.bv, w0, w1, n, G.out_off, vis);
+      push_words<BT>(b.cur.bv, w0, w1, n, G.out_off, vis);
       found = vis.found;
       found_deg = vis.found_deg;
     }
-    const Part p = block_sum4<kBB>(Part{found, found_deg, 0, 0});
+    const Part p = block_sum4<BT>(Part{found, found_deg, 0, 0});
     if (tid == 0 && p.a > 0) {
       atomicAdd(&c->qn[(L + 1) % 3], (unsigned long long)p.a);
       atomicAdd(&c->ds[(L + 1) % 3], (unsigned long long)p.b);
@@ -159,6 +172,7 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
   if (r == 0 && tid == 0) c->levels = L;
 }
 
+template <int BT>
 __device__ void pr_task(const BatchGraph& G, const BatchTask& t, int r, const BatchArgs& a,
                         float* lds_val, int* lds_off) {
   const int n = G.n, k = t.k, tid = threadIdx.x;
@@ -166,7 +180,7 @@ __device__ void pr_task(const BatchGraph& G, const BatchTask& t, int r, const Ba
   float* ranks = static_cast<float*>(t.out);
   const int v0 = (int)((long long)n * r / k), v1 = (int)((long long)n * (r + 1) / k);
   const double x0 = 1.0 / (double)n;
-  for (int v = v0 + tid; v < v1; v += kBB) {
+  for (int v = v0 + tid; v < v1; v += BT) {
     if (t.iters == 0) {
       ranks[v] = (float)x0;
     } else {
@@ -174,7 +188,7 @@ __device__ void pr_task(const BatchGraph& G, const BatchTask& t, int r, const Ba
       t.c0[v] = d > 0 ? (float)(x0 / (double)d) : 0.0f;
     }
   }
-  for (int i = r * kBB + tid; i < G.n_long; i += k * kBB) {
+  for (int i = r * BT + tid; i < G.n_long; i += k * BT) {
     t.lr_acc[i] = 0.0;
     t.lr_cnt[i] = 0u;
   }
@@ -190,13 +204,14 @@ __device__ void pr_task(const BatchGraph& G, const BatchTask& t, int r, const Ba
     float* cout = (it & 1) ? t.c0 : t.c1;
     float* rk = it == t.iters - 1 ? ranks : nullptr;
     for (int tb = r; tb < G.pr_ntab; tb += k)
-      pr_rows_block<kBB>(rows, tb, G.pr_cap_e, cin, 0, pv, cout, rk, nullptr, lds_val, lds_off);
+      pr_rows_block<BT>(rows, tb, G.pr_cap_e, cin, 0, pv, cout, rk, nullptr, lds_val, lds_off);
     if (!task_barrier(c, k, a.error, a.spin_limit)) return;
   }
   if (r == 0 && tid == 0) c->levels = t.iters;
 }
 
-__global__ __launch_bounds__(kBB, 5) void k_batch(BatchArgs a) {
+template <int BT>
+__global__ __launch_bounds__(BT, batch_min_waves<BT>()) void k_batch(BatchArgs a) {
   extern __shared__ float smem[];
   float* lds_val = smem;
   int* lds_off = reinterpret_cast<int*>(smem + a.lds_cap_e);
@@ -206,8 +221,8 @@ __global__ __launch_bounds__(kBB, 5) void k_batch(BatchArgs a) {
     const BatchTask& t = a.tasks[it.x];
     const BatchGraph& G = a.graphs[t.graph];
     if (it.y == 0 && threadIdx.x == 0) t.ctl->t_begin = wall_ticks();
-    if (t.alg == ALG_BFS) bfs_task(G, t, it.y, a);
-    else pr_task(G, t, it.y, a, lds_val, lds_off);
+    if (t.alg == ALG_BFS) bfs_task<BT>(G, t, it.y, a);
+    else pr_task<BT>(G, t, it.y, a, lds_val, lds_off);
     if (it.y == 0 && threadIdx.x == 0) t.ctl->t_end = wall_ticks();
   }
 }
@@ -222,24 +237,34 @@ __global__ void k_batch_init(TaskCtl* ctl, int ntasks, int* error) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *error = 0;
 }
 
-int batch_threads() { return kBB; }
-
 size_t batch_lds_bytes(int cap_e, int cap_v) {
   return sizeof(float) * (size_t)cap_e + sizeof(int) * (size_t)(cap_v + 1);
 }
 
-int batch_occupancy(size_t lds) {
+bool batch_threads_ok(int bt) { return bt == 256 || bt == 512 || bt == 1024; }
+
+int batch_occupancy(int bt, size_t lds) {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch, kBB, lds) != hipSuccess)
-    return -1;
-  return blocks;
+  hipError_t e = hipErrorInvalidValue;
+  switch (bt) {
+    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<256>, 256, lds); break;
+    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<512>, 512, lds); break;
+    case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<1024>, 1024, lds); break;
+    default: return -1;
+  }
+  return e == hipSuccess ? blocks : -1;
 }
 
-int launch_batch(const BatchArgs& a, int grid, size_t lds, TaskCtl* ctl, int ntasks,
+int launch_batch(const BatchArgs& a, int bt, int grid, size_t lds, TaskCtl* ctl, int ntasks,
                  hipStream_t s) {
   hipLaunchKernelGGL(k_batch_init, dim3(std::max(1, std::min(64, (ntasks + 255) / 256))),
                      dim3(256), 0, s, ctl, ntasks, a.error);
-  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBB), lds, s, a);
+  switch (bt) {
+    case 256: hipLaunchKernelGGL(k_batch<256>, dim3(grid), dim3(256), lds, s, a); break;
+    case 512: hipLaunchKernelGGL(k_batch<512>, dim3(grid), dim3(512), lds, s, a); break;
+    case 1024: hipLaunchKernelGGL(k_batch<1024>, dim3(grid), dim3(1024), lds, s, a); break;
+    default: return -1;
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -34,10 +34,15 @@ struct BfsVisit {
 // DensePull: a wave owns 64-vertex words and takes G of them at a time, so
 // the dependent load chains of G words (visited word -> in-row bounds ->
 // in-neighbour ids -> frontier bits) overlap instead of running one after
-// another.  Unvisited lanes test their first in-edges in two batches of
-// four independent loads; the rows still open are then concatenated and
-// walked 64 edges per round across the wave.  Every row stops at its first
-// source in the frontier, in in-edge order.  The next frontier word and the
+// another.  Each unvisited lane first tests its in-neighbour of largest
+// out-degree (`in_probe`, a coalesced load): an unvisited vertex's
+// in-neighbours are all either in the frontier or unvisited, and hubs are
+// reached early, so in the large pull levels this test usually succeeds
+// and the in-row, whose first line would otherwise be fetched for just one
+// or two ids, is never read.  Lanes still open test their first in-edges
+// in two batches of four independent loads; the rows still open are then
+// concatenated and walked 64 edges per round across the wave.  A row stops
+// at its first source in the frontier (the probe, else in in-edge order).  The next frontier word and the
 // visited word are written whole, without atomics.
 // Words [wbeg, wend) are covered by waves wave0, wave0 + nwaves, ...; with
 // `deg` set, the claimed vertices and their degrees are accumulated
@@ -65,12 +70,25 @@ __device__ long long bfs_pull_range(const BfsArgs& b, int l1, int wbeg, int wend
       j[q] = 0;
       e[q] = 0;
     }
+    int pb[G];
 #pragma unroll
     for (int q = 0; q < G; ++q) {
+      pb[q] = -1;
       if (cand[q]) {
         const int v = ((wb + q * nwaves) << 6) + lane;
+        if (g.in_probe) pb[q] = g.in_probe[v];
         j[q] = g.in_off[v];
         e[q] = g.in_off[v + 1];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      if (pb[q] >= 0) {
+        ++work;
+        if (cur.test(pb[q])) {
+          found[q] = true;
+          par[q] = pb[q];
+        }
       }
     }
 #pragma unroll

@@ -75,6 +75,7 @@ struct gi_graph {
   // adjacency on the device
   int32_t *out_off = nullptr, *out_idx = nullptr, *in_off = nullptr, *in_idx = nullptr;
   int32_t *outdeg = nullptr, *udeg = nullptr;
+  int32_t* in_probe = nullptr;  // in-neighbour of largest out-degree (BFS pull's first test)
   uint32_t *out_w = nullptr, *in_w = nullptr;
   // host copies of the offsets (destination blocks and segments are built from them)
   std::vector<int32_t> h_in_off, h_in_idx, h_out_off, h_outdeg;
@@ -88,7 +89,7 @@ struct gi_graph {
   // symmetric adjacency and its destination blocks (CC; built on first use)
   int32_t* sym_off = nullptr;
   int32_t* sym_idx = nullptr;
-  int2* sym_table = nullptr;
+  int4* sym_table = nullptr;
   int sym_ntab = 0;
   std::vector<SegDev> segs;
   double* pr_acc = nullptr;
@@ -120,7 +121,7 @@ struct gi_graph {
   int tev_count = 0;        // steps of the last run that carry events
   int last_steps[6] = {0, 0, 0, 0, 0, 0};  // steps of the previous run, per algorithm
   void* bc = nullptr;  // betweenness scratch: level, sigma, acc, order, bounds
-  int2* prec_tab = nullptr;  // in-row blocks for PageRank + eigenvector
+  int4* prec_tab = nullptr;  // in-row blocks for PageRank + eigenvector
   int prec_ntab = 0;
   float2* prec_aos = nullptr;  // 2 n pairs
   float* prec_y = nullptr;     // 2 n
@@ -271,6 +272,38 @@ static std::vector<int2> make_row_blocks(const int32_t* off, int nrows, int cap_
   }
   longs.insert(longs.end(), rest.begin(), rest.end());
   return longs;
+}
+
+// CC pull blocks: whole-row blocks as above, except that a row longer than
+// cap_e becomes ceil(len/cap_e) chunk entries (row, -(c+1)), listed first,
+// so that no workgroup walks a hub row alone.
+// Each entry also carries its edge range, so a kernel needs no dependent
+// load of the row offsets before fetching the edges.
+static std::vector<int4> make_cc_table(const int32_t* off, int nrows, int cap_e, int cap_v) {
+  std::vector<int2> tab = make_row_blocks(off, nrows, cap_e, cap_v);
+  std::vector<int4> out;
+  size_t i = 0;
+  for (; i < tab.size(); ++i) {
+    const int r = tab[i].x;
+    const int64_t d = (int64_t)off[r + 1] - off[r];
+    if (tab[i].y != r + 1 || d <= cap_e) break;  // past the long rows
+    const int64_t nc = (d + cap_e - 1) / cap_e;
+    for (int64_t c = 0; c < nc; ++c) {
+      const int64_t eb = off[r] + c * cap_e;
+      out.push_back(make_int4(r, -(int)(c + 1), (int)eb, (int)std::min<int64_t>(off[r + 1], eb + cap_e)));
+    }
+  }
+  for (; i < tab.size(); ++i)
+    out.push_back(make_int4(tab[i].x, tab[i].y, off[tab[i].x], off[tab[i].y]));
+  return out;
+}
+
+// Whole-row blocks with their edge ranges.
+static std::vector<int4> with_edges(const std::vector<int2>& tab, const int32_t* off) {
+  std::vector<int4> out;
+  out.reserve(tab.size());
+  for (const int2& b : tab) out.push_back(make_int4(b.x, b.y, off[b.x], off[b.y]));
+  return out;
 }
 
 // PageRank destination blocks: whole-row blocks as above, except that a
@@ -648,6 +681,27 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
   G_UP(g->h_in_idx.data(), g->in_idx, 4 * M);
   G_UP(g->h_outdeg.data(), g->outdeg, 4 * N);
   G_UP(h_udeg.data(), g->udeg, 4 * N);
+  {
+    // first in-neighbour a BFS pull tests: the one of largest out-degree
+    // (smallest id among equals).  Such hubs are reached early, so in the
+    // large pull levels this one test usually finds a parent without
+    // touching the in-row.
+    std::vector<int32_t> probe(N, -1);
+    const int32_t* io = g->h_in_off.data();
+    const int32_t* ii = g->h_in_idx.data();
+    const int32_t* od = g->h_outdeg.data();
+    for (size_t v = 0; v < N; ++v) {
+      int best = -1, bd = -1;
+      for (int32_t e = io[v]; e < io[v + 1]; ++e)
+        if (od[ii[e]] > bd) {
+          bd = od[ii[e]];
+          best = ii[e];
+        }
+      probe[v] = best;
+    }
+    G_ALLOC(g->in_probe, N);
+    G_UP(probe.data(), g->in_probe, 4 * N);
+  }
   if (out_w) {
     G_ALLOC(g->out_w, M);
     G_ALLOC(g->in_w, M);
@@ -751,6 +805,7 @@ static DevGraph dev_graph(const gi_graph* g) {
   d.in_w = g->in_w;
   d.outdeg = g->outdeg;
   d.udeg = g->udeg;
+  d.in_probe = g->in_probe;
   return d;
 }
 
@@ -1073,13 +1128,13 @@ static gi_status ensure_sym(gi_graph* g, hipStream_t s) {
   std::vector<int32_t> off(N + 1, 0);
   for (size_t v = 0; v < N; ++v)
     off[v + 1] = off[v] + g->h_outdeg[v] + (g->h_in_off[v + 1] - g->h_in_off[v]);
-  std::vector<int2> tab = make_row_blocks(off.data(), g->n, kCcCapE, kCcCapV);
+  std::vector<int4> tab = make_cc_table(off.data(), g->n, kCcCapE, kCcCapV);
   gi_status st;
   if ((st = dev_alloc(g, g->allocs, &g->sym_off, N + 1)) != GI_OK) return st;
   if ((st = dev_alloc(g, g->allocs, &g->sym_idx, (size_t)off[N])) != GI_OK) return st;
   if ((st = dev_alloc(g, g->allocs, &g->sym_table, tab.size())) != GI_OK) return st;
   if ((st = upload(off.data(), g->sym_off, 4 * (N + 1))) != GI_OK) return st;
-  if ((st = upload(tab.data(), g->sym_table, tab.size() * sizeof(int2))) != GI_OK) return st;
+  if ((st = upload(tab.data(), g->sym_table, tab.size() * sizeof(int4))) != GI_OK) return st;
   g->sym_ntab = (int)tab.size();
   LAUNCH_TRY(launch_build_sym(dev_graph(g), g->sym_off, g->sym_idx, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -1278,9 +1333,10 @@ extern "C" gi_status gi_pagerank_eigenvector(gi_graph* g, int32_t iters, float d
   const size_t N = (size_t)g->n;
   gi_status st;
   if (!g->prec_tab) {
-    std::vector<int2> tab = make_row_blocks(g->h_in_off.data(), g->n, kPrEcCapE, kPrEcCapV);
+    std::vector<int4> tab = with_edges(make_row_blocks(g->h_in_off.data(), g->n, kPrEcCapE, kPrEcCapV),
+                                       g->h_in_off.data());
     if ((st = dev_alloc(g, g->allocs, &g->prec_tab, tab.size())) != GI_OK) return st;
-    if ((st = upload(tab.data(), g->prec_tab, tab.size() * sizeof(int2))) != GI_OK) return st;
+    if ((st = upload(tab.data(), g->prec_tab, tab.size() * sizeof(int4))) != GI_OK) return st;
     g->prec_ntab = (int)tab.size();
     if ((st = dev_alloc(g, g->allocs, &g->prec_aos, 2 * N)) != GI_OK) return st;
     if ((st = dev_alloc(g, g->allocs, &g->prec_y, 2 * N)) != GI_OK) return st;
@@ -1834,6 +1890,9 @@ struct gi_batch {
   std::vector<double> est;   // estimated time per task (ms, or a size proxy before tuning)
   int max_grid = 0;          // resident workgroups of the batch kernel
   int grid = 0;
+  int bt = 256;              // threads per workgroup
+  bool bt_pinned = false;    // set by gi_batch_set_threads: the autotuner keeps it
+  int cus = 0;
   size_t lds = 0;
   int cap_e = 0;
   long long spin_limit = 0;
@@ -1888,6 +1947,17 @@ static gi_status batch_alloc(gi_batch* b, T** p, size_t count) {
   return GI_OK;
 }
 
+// Workgroup size: the resident grid follows from the kernel's occupancy at
+// that size (at most 8 workgroups per CU).
+static gi_status batch_set_bt(gi_batch* b, int bt) {
+  if (!batch_threads_ok(bt)) return fail(GI_ERR_INVALID_ARG, "threads must be 256, 512 or 1024");
+  const int occ = batch_occupancy(bt, b->lds);
+  if (occ < 1) return fail(GI_ERR_DEVICE, "batch kernel does not fit on a compute unit");
+  b->bt = bt;
+  b->max_grid = b->cus * std::min(occ, 8);
+  return GI_OK;
+}
+
 static BatchGraph batch_graph(const gi_graph* g) {
   BatchGraph d;
   d.n = g->n;
@@ -1897,6 +1967,7 @@ static BatchGraph batch_graph(const gi_graph* g) {
   d.in_off = g->in_off;
   d.in_idx = g->in_idx;
   d.outdeg = g->outdeg;
+  d.in_probe = g->in_probe;
   d.pr_table = g->pr_table;
   d.pr_ntab = g->pr_ntab;
   d.pr_cap_e = g->pr_cap_e;
@@ -2018,11 +2089,10 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
     rate = 100000;  // kHz
   b->spin_limit = 2000LL * rate;  // two seconds of wall clock
   b->clock_khz = rate;
-  const int occ = batch_occupancy(b->lds);
-  if (occ < 1) return bail(fail(GI_ERR_DEVICE, "batch kernel does not fit on a compute unit"));
+  b->cus = cus;
   // resident by construction: at most the occupancy (and at most 8 per CU)
-  b->max_grid = cus * std::min(occ, 8);
-  gi_status st;
+  gi_status st = batch_set_bt(b, 256);
+  if (st != GI_OK) return bail(st);
   const size_t nt = (size_t)ntasks;
   b->h_tasks.resize(nt);
   b->k.resize(nt);
@@ -2121,7 +2191,7 @@ extern "C" gi_status gi_batch_run(gi_batch* b, int32_t use_graph, void* stream) 
   if (use_graph) {
     if (!b->hx) {
       HIP_TRY(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal));
-      const int lr = launch_batch(a, b->grid, b->lds, b->d_ctl, nt, b->gstream);
+      const int lr = launch_batch(a, b->bt, b->grid, b->lds, b->d_ctl, nt, b->gstream);
       hipGraph_t gcap = nullptr;
       const hipError_t ce = hipStreamEndCapture(b->gstream, &gcap);
       if (lr != 0 || ce != hipSuccess) {
@@ -2144,7 +2214,7 @@ extern "C" gi_status gi_batch_run(gi_batch* b, int32_t use_graph, void* stream) 
   } else {
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipEventRecord(b->ev[0], s));
-    LAUNCH_TRY(launch_batch(a, b->grid, b->lds, b->d_ctl, nt, s));
+    LAUNCH_TRY(launch_batch(a, b->bt, b->grid, b->lds, b->d_ctl, nt, s));
     HIP_TRY(hipEventRecord(b->ev[1], s));
     HIP_TRY(hipEventSynchronize(b->ev[1]));
   }
@@ -2180,7 +2250,7 @@ static gi_status batch_time_task(gi_batch* b, int t, int k, int reps, float* ms)
   for (int rep = 0; rep < reps && st == GI_OK; ++rep) {
     float x = 0.0f;
     if (hipEventRecord(b->ev[0], nullptr) != hipSuccess ||
-        launch_batch(a, k, b->lds, b->d_ctl, (int)b->tasks.size(), nullptr) != 0 ||
+        launch_batch(a, b->bt, k, b->lds, b->d_ctl, (int)b->tasks.size(), nullptr) != 0 ||
         hipEventRecord(b->ev[1], nullptr) != hipSuccess ||
         hipEventSynchronize(b->ev[1]) != hipSuccess ||
         hipEventElapsedTime(&x, b->ev[0], b->ev[1]) != hipSuccess) {
@@ -2201,11 +2271,9 @@ static gi_status batch_time_task(gi_batch* b, int t, int k, int reps, float* ms)
   return GI_OK;
 }
 
-extern "C" gi_status gi_batch_autotune(gi_batch* b, int32_t reps) {
-  if (!b || reps < 1) return fail(GI_ERR_INVALID_ARG, "bad autotune arguments");
-  gi_status st = batch_refresh_graphs(b);
-  if (st != GI_OK) return st;
-  HIP_TRY(hipDeviceSynchronize());
+// Workgroups per task at the current workgroup size (see gi_batch_autotune).
+static gi_status batch_tune_sizes(gi_batch* b, int32_t reps) {
+  gi_status st;
   const int nt = (int)b->tasks.size();
   // one representative per (graph, algorithm, iterations) class
   std::vector<int> rep_of((size_t)nt, -1);
@@ -2273,6 +2341,76 @@ extern "C" gi_status gi_batch_autotune(gi_batch* b, int32_t reps) {
     }
   }
   return batch_plan(b);
+}
+
+// Median time of reps launches of the whole planned batch (stream 0).
+static gi_status batch_time_all(gi_batch* b, int reps, float* ms) {
+  const BatchArgs a = batch_args(b, b->d_items, b->d_wg_off);
+  std::vector<float> times;
+  for (int rep = 0; rep < reps; ++rep) {
+    float x = 0.0f;
+    HIP_TRY(hipEventRecord(b->ev[0], nullptr));
+    LAUNCH_TRY(launch_batch(a, b->bt, b->grid, b->lds, b->d_ctl, (int)b->tasks.size(), nullptr));
+    HIP_TRY(hipEventRecord(b->ev[1], nullptr));
+    HIP_TRY(hipEventSynchronize(b->ev[1]));
+    HIP_TRY(hipEventElapsedTime(&x, b->ev[0], b->ev[1]));
+    gi_status st = batch_check_error(b);
+    if (st != GI_OK) return st;
+    times.push_back(x);
+  }
+  std::sort(times.begin(), times.end());
+  *ms = times[times.size() / 2];
+  return GI_OK;
+}
+
+extern "C" gi_status gi_batch_autotune(gi_batch* b, int32_t reps) {
+  if (!b || reps < 1) return fail(GI_ERR_INVALID_ARG, "bad autotune arguments");
+  gi_status st = batch_refresh_graphs(b);
+  if (st != GI_OK) return st;
+  HIP_TRY(hipDeviceSynchronize());
+  const std::vector<int> k0 = b->k;
+  const std::vector<double> e0 = b->est;
+  int best_bt = b->bt;
+  float best_ms = 0.0f;
+  std::vector<int> best_k;
+  std::vector<double> best_est;
+  for (int bt : {256, 512, 1024}) {
+    if (b->bt_pinned && bt != b->bt) continue;
+    b->k = k0;
+    b->est = e0;
+    if ((st = batch_set_bt(b, bt)) != GI_OK) return st;
+    if ((st = batch_tune_sizes(b, reps)) != GI_OK) return st;
+    float ms = 0.0f;
+    if ((st = batch_time_all(b, reps, &ms)) != GI_OK) return st;
+    if (best_k.empty() || ms < best_ms) {
+      best_ms = ms;
+      best_bt = bt;
+      best_k = b->k;
+      best_est = b->est;
+    }
+  }
+  if ((st = batch_set_bt(b, best_bt)) != GI_OK) return st;
+  b->k = best_k;
+  b->est = best_est;
+  return batch_plan(b);
+}
+
+extern "C" gi_status gi_batch_set_threads(gi_batch* b, int32_t threads) {
+  if (!b) return fail(GI_ERR_INVALID_ARG, "NULL batch");
+  if (threads == 0) {
+    b->bt_pinned = false;
+    return GI_OK;
+  }
+  gi_status st = batch_set_bt(b, threads);
+  if (st != GI_OK) return st;
+  b->bt_pinned = true;
+  return batch_plan(b);
+}
+
+extern "C" gi_status gi_batch_get_threads(const gi_batch* b, int32_t* threads) {
+  if (!b || !threads) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  *threads = b->bt;
+  return GI_OK;
 }
 
 extern "C" gi_status gi_batch_info(const gi_batch* b, float* last_ms, int32_t* grid,

@@ -44,6 +44,7 @@ struct DevGraph {
   const uint32_t* in_w;
   const int32_t* outdeg;  // out_off[v+1]-out_off[v]
   const int32_t* udeg;    // out-degree + in-degree
+  const int32_t* in_probe;  // per vertex: its in-neighbour of largest out-degree, -1 if none
 };
 
 // Per-workgroup statistics of one phase.

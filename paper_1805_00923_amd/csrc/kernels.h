@@ -11,7 +11,8 @@ enum : int { ALG_PR = 0, ALG_BFS = 1, ALG_CC = 2, ALG_SSSP = 3, ALG_PRD = 4, ALG
 
 // Rows of one adjacency split into destination blocks (PageRank and CC pull).
 struct RowBlocks {
-  const int2* table;    // (first row, end row) per block
+  const int4* table;    // per block: (first row, end row, first edge, end edge);
+                        // a chunk of a long row: (row, -(chunk + 1), first edge, end edge)
   int ntab;
   const int32_t* off;
   const int32_t* idx;
@@ -199,6 +200,7 @@ struct BatchGraph {
   const int32_t* in_off;
   const int32_t* in_idx;
   const int32_t* outdeg;
+  const int32_t* in_probe;
   const int4* pr_table;  // PageRank destination blocks (the graph's current schedule)
   int pr_ntab;
   int pr_cap_e;
@@ -247,10 +249,10 @@ struct BatchArgs {
   int lds_cap_e;
 };
 
-int batch_threads();
+bool batch_threads_ok(int bt);  // 256, 512 or 1024 threads per workgroup
 size_t batch_lds_bytes(int cap_e, int cap_v);
-int batch_occupancy(size_t lds);
-int launch_batch(const BatchArgs& a, int grid, size_t lds, TaskCtl* ctl, int ntasks,
+int batch_occupancy(int bt, size_t lds);
+int launch_batch(const BatchArgs& a, int bt, int grid, size_t lds, TaskCtl* ctl, int ntasks,
                  hipStream_t s);
 
 int launch_pr_seg_concurrent(const PrRows* segs, int p, int cap_e, int cap_v, int bt,

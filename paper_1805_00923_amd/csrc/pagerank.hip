@@ -145,10 +145,12 @@ __global__ __launch_bounds__(BT) void k_prec_rows(PrEcArgs a) {
     if constexpr (FUSED) return a.aos_in[u];
     else return a.y_in[u];
   };
+  int4 nx = blockIdx.x < (unsigned)a.rb.ntab ? a.rb.table[blockIdx.x] : make_int4(0, 0, 0, 0);
   for (int t = blockIdx.x; t < a.rb.ntab; t += gridDim.x) {
-    const int2 r = a.rb.table[t];
+    const int4 r = nx;
+    if (t + (int)gridDim.x < a.rb.ntab) nx = a.rb.table[t + gridDim.x];
     const int kb = r.x, ke = r.y, nr = ke - kb;
-    const int e0 = a.rb.off[kb], e1 = a.rb.off[ke], ne = e1 - e0;
+    const int e0 = r.z, e1 = r.w, ne = e1 - e0;
     if (ne > kPrEcCapE) {  // one long row: workgroup-wide sums
       double sp = 0.0, se = 0.0;
       for (int e = e0 + tid; e < e1; e += BT) {

@@ -78,6 +78,39 @@ def test_batch_matches_oracle():
     b.close()
 
 
+@pytest.mark.parametrize("threads", [256, 512, 1024])
+def test_batch_workgroup_sizes(threads):
+    """Every workgroup size of the batch kernel, fixed and planned task sizes,
+    direct and graph launches."""
+    import torch
+    import paper_1805_00923_amd as gi
+    P = pool()
+    tasks = make_tasks(torch, 30, seed=10 + threads)
+    for i, t in enumerate(tasks):
+        if i % 3 == 0:
+            t["workgroups"] = [1, 2, 4, 7, 16][(i // 3) % 5]
+    b = gi.Batch([g for _, g, _ in P], tasks)
+    b.set_threads(threads)
+    assert b.threads() == threads
+    for use_graph in (False, True, True):
+        for t in tasks:
+            t["out"].fill_(-5 if t["algorithm"] == 1 else -2.0)
+        torch.cuda.synchronize()
+        say("batch threads=%d graph=%d" % (threads, use_graph))
+        b.run(use_graph=use_graph)
+        torch.cuda.synchronize()
+        check(tasks)
+    say("batch threads=%d autotune (pinned)" % threads)
+    b.autotune(reps=1)
+    assert b.threads() == threads
+    b.run(use_graph=True)
+    torch.cuda.synchronize()
+    check(tasks)
+    with pytest.raises(gi.GiError):
+        b.set_threads(384)
+    b.close()
+
+
 def test_batch_fixed_workgroups_and_graph_replays():
     import torch
     import paper_1805_00923_amd as gi
@@ -106,6 +139,7 @@ def test_batch_autotune_keeps_results():
     b = gi.Batch([g for _, g, _ in P], tasks)
     say("batch autotune")
     b.autotune(reps=2)
+    assert b.threads() in (256, 512, 1024)
     for rep in range(2):
         say("batch run after autotune %d" % rep)
         b.run(use_graph=bool(rep))
