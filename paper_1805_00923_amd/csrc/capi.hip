@@ -123,6 +123,9 @@ struct gi_graph {
   void* bc = nullptr;  // betweenness scratch: level, sigma, acc, order, bounds
   int4* prec_tab = nullptr;  // in-row blocks for PageRank + eigenvector
   int prec_ntab = 0;
+  int32_t* prec_lrow = nullptr;  // long rows (chunked) and their FP64 sum slots
+  double* prec_lacc = nullptr;
+  int prec_nlong = 0;
   float2* prec_aos = nullptr;  // 2 n pairs
   float* prec_y = nullptr;     // 2 n
   double* prec_norm = nullptr;
@@ -298,12 +301,18 @@ static std::vector<int4> make_cc_table(const int32_t* off, int nrows, int cap_e,
   return out;
 }
 
-// Whole-row blocks with their edge ranges.
-static std::vector<int4> with_edges(const std::vector<int2>& tab, const int32_t* off) {
-  std::vector<int4> out;
-  out.reserve(tab.size());
-  for (const int2& b : tab) out.push_back(make_int4(b.x, b.y, off[b.x], off[b.y]));
-  return out;
+// PageRank + eigenvector blocks: as make_cc_table, except that a chunk
+// entry names its row's long-row slot (rows in `lrow`) instead of the row.
+static std::vector<int4> make_prec_table(const int32_t* off, int nrows, int cap_e, int cap_v,
+                                         std::vector<int32_t>* lrow) {
+  std::vector<int4> tab = make_cc_table(off, nrows, cap_e, cap_v);
+  lrow->clear();
+  for (int4& e : tab) {
+    if (e.y >= 0) break;  // chunk entries come first
+    if (e.y == -1) lrow->push_back(e.x);
+    e.x = (int)lrow->size() - 1;
+  }
+  return tab;
 }
 
 // PageRank destination blocks: whole-row blocks as above, except that a
@@ -1333,8 +1342,15 @@ extern "C" gi_status gi_pagerank_eigenvector(gi_graph* g, int32_t iters, float d
   const size_t N = (size_t)g->n;
   gi_status st;
   if (!g->prec_tab) {
-    std::vector<int4> tab = with_edges(make_row_blocks(g->h_in_off.data(), g->n, kPrEcCapE, kPrEcCapV),
-                                       g->h_in_off.data());
+    std::vector<int32_t> lrow;
+    std::vector<int4> tab = make_prec_table(g->h_in_off.data(), g->n, kPrEcCapE, kPrEcCapV, &lrow);
+    g->prec_nlong = (int)lrow.size();
+    if ((st = dev_alloc(g, g->allocs, &g->prec_lrow, std::max<size_t>(1, lrow.size()))) != GI_OK) return st;
+    if ((st = dev_alloc(g, g->allocs, &g->prec_lacc, 2 * std::max<size_t>(1, lrow.size()))) != GI_OK) return st;
+    if (!lrow.empty() &&
+        (st = upload(lrow.data(), g->prec_lrow, lrow.size() * sizeof(int32_t))) != GI_OK)
+      return st;
+    HIP_TRY(hipMemset(g->prec_lacc, 0, sizeof(double) * 2 * std::max<size_t>(1, lrow.size())));
     if ((st = dev_alloc(g, g->allocs, &g->prec_tab, tab.size())) != GI_OK) return st;
     if ((st = upload(tab.data(), g->prec_tab, tab.size() * sizeof(int4))) != GI_OK) return st;
     g->prec_ntab = (int)tab.size();
@@ -1352,6 +1368,9 @@ extern "C" gi_status gi_pagerank_eigenvector(gi_graph* g, int32_t iters, float d
   pv.base = (1.0 - (double)damping) / (double)g->n;
   PrEcArgs a;
   a.rb = RowBlocks{g->prec_tab, g->prec_ntab, g->in_off, g->in_idx};
+  a.lacc = g->prec_lacc;
+  a.lrow = g->prec_lrow;
+  a.nlong = g->prec_nlong;
   a.pv = pv;
   int launches = 0;
   HIP_TRY(hipEventRecord(g->ev[0], s));
@@ -1380,7 +1399,7 @@ extern "C" gi_status gi_pagerank_eigenvector(gi_graph* g, int32_t iters, float d
       a.aos_out = g->prec_aos + ((k + 1) & 1) * N;
       a.ranks = last ? ranks : nullptr;
       LAUNCH_TRY(launch_prec_rows(a, true, s));
-      ++launches;
+      launches += a.nlong > 0 ? 2 : 1;
     } else {
       PrRows r{g->pr_table, g->pr_ntab, g->in_off, g->in_idx, nullptr, g->lr_acc, g->lr_cnt,
                g->lr_chunks};
@@ -1390,7 +1409,7 @@ extern "C" gi_status gi_pagerank_eigenvector(gi_graph* g, int32_t iters, float d
       a.y_out = g->prec_y + ((k + 1) & 1) * N;
       a.ranks = nullptr;
       LAUNCH_TRY(launch_prec_rows(a, false, s));
-      launches += 2;
+      launches += a.nlong > 0 ? 3 : 2;
     }
     if (te) HIP_TRY(hipEventRecord(te->end, s));
   }

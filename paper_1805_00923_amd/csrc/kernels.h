@@ -263,7 +263,11 @@ int launch_pr_seg_final_multi(int n, int p, const PrVertex& pv, double* acc, flo
 
 // PageRank and eigenvector centrality, fused or not (pagerank.hip).
 struct PrEcArgs {
-  RowBlocks rb;               // in-row blocks of at most kPrEcCapE edges (longer rows alone)
+  RowBlocks rb;               // in-row blocks of at most kPrEcCapE edges; a longer row
+                              // as chunk entries (slot, -(chunk + 1), first edge, end edge)
+  double* lacc;               // per long-row slot: (PageRank sum, eigenvector sum)
+  const int32_t* lrow;        // row of each long-row slot
+  int nlong;
   const float2* aos_in;       // fused: (PageRank contribution, eigenvector y) per vertex
   float2* aos_out;
   const float* y_in;          // eigenvector y alone (unfused)
@@ -275,7 +279,7 @@ struct PrEcArgs {
 };
 constexpr int kPrEcCapE = 2048;
 constexpr int kPrEcCapV = 1024;
-int launch_prec_rows(const PrEcArgs& a, bool fused, hipStream_t s);
+int launch_prec_rows(const PrEcArgs& a, bool fused, hipStream_t s);  // + long-row finish
 int launch_prec_init(int n, const int32_t* outdeg, float2* aos, float* y, double* norm2,
                      int nnorm, hipStream_t s);
 int launch_ec_final(int n, const float* y, const float2* aos, const double* norm2, float* out,

@@ -119,19 +119,18 @@ __global__ void k_pr_seg_final_multi(int n, int p, PrVertex pv, double* acc, flo
 // L2-normalised power iteration: y_{k+1}[v] = sum_{u->v} y_k[u] / ||y_k||,
 // the norm of each new y accumulated in FP64 as it is produced.  Unfused,
 // the same kernel gathers y alone and PageRank runs its own pass.
-template <int BT, bool FUSED>
-__global__ __launch_bounds__(BT) void k_prec_rows(PrEcArgs a) {
-  using V = typename std::conditional<FUSED, float2, float>::type;
-  __shared__ V lds_val[kPrEcCapE];
-  __shared__ int lds_off[kPrEcCapV + 1];
-  __shared__ double red[2][BT / kWave];
-  const int tid = threadIdx.x;
-  const double n2 = *a.norm2_prev;
-  const double inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
-  double my_n2 = 0.0;
-  auto finish = [&](int v, double sp, double se) {
+//
+// Blocks are reduced by the deterministic edge-parallel segmented sum of
+// the PageRank kernel; a row longer than a block is cut into chunks whose
+// sums meet in an FP64 slot, finished by k_prec_long after the pass.
+template <bool FUSED>
+struct PrEcVertex {
+  const PrEcArgs& a;
+  double inv;
+  double n2 = 0.0;
+  __device__ __forceinline__ void operator()(int v, double sp, double se) {
     const double y = se * inv;
-    my_n2 += y * y;
+    n2 += y * y;
     if (FUSED) {
       const double x = a.pv.base + a.pv.alpha * sp;
       const int d = a.pv.outdeg[v];
@@ -140,80 +139,134 @@ __global__ __launch_bounds__(BT) void k_prec_rows(PrEcArgs a) {
     } else {
       a.y_out[v] = (float)y;
     }
-  };
+  }
+};
+
+__device__ __forceinline__ double inv_norm(const double* n2p) {
+  const double n2 = *n2p;
+  return n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+}
+
+template <int BT, bool FUSED>
+__global__ __launch_bounds__(BT) void k_prec_rows(PrEcArgs a) {
+  using V = typename std::conditional<FUSED, float2, float>::type;
+  __shared__ V lds_val[kPrEcCapE];
+  __shared__ int lds_off[kPrEcCapV + 1];
+  __shared__ double head[2][BT], cont[2][BT];
+  const int tid = threadIdx.x;
+  PrEcVertex<FUSED> fin{a, inv_norm(a.norm2_prev)};
   auto fetch = [&](int u) -> V {
     if constexpr (FUSED) return a.aos_in[u];
     else return a.y_in[u];
+  };
+  auto add = [](double& sp, double& se, const V& c) {
+    if constexpr (FUSED) {
+      sp += (double)c.x;
+      se += (double)c.y;
+    } else {
+      se += (double)c;
+    }
   };
   int4 nx = blockIdx.x < (unsigned)a.rb.ntab ? a.rb.table[blockIdx.x] : make_int4(0, 0, 0, 0);
   for (int t = blockIdx.x; t < a.rb.ntab; t += gridDim.x) {
     const int4 r = nx;
     if (t + (int)gridDim.x < a.rb.ntab) nx = a.rb.table[t + gridDim.x];
-    const int kb = r.x, ke = r.y, nr = ke - kb;
-    const int e0 = r.z, e1 = r.w, ne = e1 - e0;
-    if (ne > kPrEcCapE) {  // one long row: workgroup-wide sums
-      double sp = 0.0, se = 0.0;
-      for (int e = e0 + tid; e < e1; e += BT) {
-        const V c = fetch(a.rb.idx[e]);
-        if constexpr (FUSED) {
-          sp += (double)c.x;
-          se += (double)c.y;
-        } else {
-          se += (double)c;
-        }
+    if (r.y < 0) {
+      // a chunk of a long row: workgroup sums into the row's FP64 slot
+      double sp = 0.0, se = 0.0, sp2 = 0.0, se2 = 0.0;
+      int e = r.z + tid;
+      for (; e + BT < r.w; e += 2 * BT) {
+        const int u0 = a.rb.idx[e], u1 = a.rb.idx[e + BT];
+        const V c0 = fetch(u0), c1 = fetch(u1);
+        add(sp, se, c0);
+        add(sp2, se2, c1);
       }
-      sp = wave_sum(sp);
-      se = wave_sum(se);
-      if (__lane_id() == 0) {
-        red[0][tid / kWave] = sp;
-        red[1][tid / kWave] = se;
-      }
-      __syncthreads();
+      if (e < r.w) add(sp, se, fetch(a.rb.idx[e]));
+      const double tp = block_sum<BT>(sp + sp2), te = block_sum<BT>(se + se2);
       if (tid == 0) {
-        double tp = 0.0, te = 0.0;
-        for (int i = 0; i < BT / kWave; ++i) {
-          tp += red[0][i];
-          te += red[1][i];
-        }
-        finish(kb, tp, te);
+        if (FUSED) atomicAdd(&a.lacc[2 * r.x], tp);
+        atomicAdd(&a.lacc[2 * r.x + 1], te);
       }
-      __syncthreads();
       continue;
     }
+    const int kb = r.x, ke = r.y, nr = ke - kb;
+    const int e0 = r.z, ne = r.w - r.z;
     gather_block<BT, V>(a.rb.idx, e0, ne, lds_val, fetch);
     for (int k = tid; k <= nr; k += BT) lds_off[k] = a.rb.off[kb + k] - e0;
     __syncthreads();
-    int tpv = 1;
-    if (nr < BT) {
-      tpv = BT / (nr > 0 ? nr : 1);
-      tpv = 1 << (31 - __clz(tpv));
-      if (tpv > kWave) tpv = kWave;
-    }
-    const int groups = BT / tpv, grp = tid / tpv, gl = tid % tpv;
-    for (int k0 = 0; k0 < nr; k0 += groups) {
-      const int k = k0 + grp;
+    const int ept = (ne + BT - 1) / BT;
+    const int eb = tid * ept, ee = min(ne, eb + ept);
+    int kl = -1, kl_end = 0;
+    if (eb < ee) {
+      int lo = 0, hi = nr;  // lds_off[lo] <= eb < lds_off[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (lds_off[mid] <= eb) lo = mid;
+        else hi = mid;
+      }
+      int k = lo, rs = lds_off[k], re = lds_off[k + 1];
       double sp = 0.0, se = 0.0;
-      if (k < nr) {
-        const int lo = lds_off[k], hi = lds_off[k + 1];
-        for (int j = lo + gl; j < hi; j += tpv) {
-          if constexpr (FUSED) {
-            sp += (double)lds_val[j].x;
-            se += (double)lds_val[j].y;
+      for (int j = eb; j < ee; ++j) {
+        if (j >= re) {
+          if (rs >= eb) {
+            fin(kb + k, sp, se);
           } else {
-            se += (double)lds_val[j];
+            cont[0][tid] = sp;
+            cont[1][tid] = se;
           }
+          sp = 0.0;
+          se = 0.0;
+          do {
+            ++k;
+          } while (lds_off[k + 1] <= j);
+          rs = lds_off[k];
+          re = lds_off[k + 1];
         }
+        add(sp, se, lds_val[j]);
       }
-      for (int o = tpv >> 1; o > 0; o >>= 1) {
-        sp += __shfl_xor(sp, o, kWave);
-        se += __shfl_xor(se, o, kWave);
+      if (re <= ee && rs >= eb) {
+        fin(kb + k, sp, se);
+      } else if (re > ee && rs >= eb) {
+        head[0][tid] = sp;
+        head[1][tid] = se;
+        kl = k;
+        kl_end = re;
+      } else {
+        cont[0][tid] = sp;
+        cont[1][tid] = se;
       }
-      if (gl == 0 && k < nr) finish(kb + k, sp, se);
     }
     __syncthreads();
+    if (kl >= 0) {
+      double sp = head[0][tid], se = head[1][tid];
+      const int t1 = (kl_end - 1) / ept;
+      for (int q = tid + 1; q <= t1; ++q) {
+        sp += cont[0][q];
+        se += cont[1][q];
+      }
+      fin(kb + kl, sp, se);
+    }
+    for (int k = tid; k < nr; k += BT)
+      if (lds_off[k] == lds_off[k + 1]) fin(kb + k, 0.0, 0.0);
+    __syncthreads();
   }
-  const double tot = block_sum<BT>(my_n2);
+  const double tot = block_sum<BT>(fin.n2);
   if (tid == 0 && tot != 0.0) atomicAdd(a.norm2_next, tot);
+}
+
+// Long rows after the pass: apply the vertex update from each slot's sums,
+// clear the slot, and add the new y values to the norm.
+template <bool FUSED>
+__global__ __launch_bounds__(256) void k_prec_long(PrEcArgs a) {
+  PrEcVertex<FUSED> fin{a, inv_norm(a.norm2_prev)};
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < a.nlong; i += gridDim.x * 256) {
+    const double sp = a.lacc[2 * i], se = a.lacc[2 * i + 1];
+    a.lacc[2 * i] = 0.0;
+    a.lacc[2 * i + 1] = 0.0;
+    fin(a.lrow[i], sp, se);
+  }
+  const double tot = block_sum<256>(fin.n2);
+  if (threadIdx.x == 0 && tot != 0.0) atomicAdd(a.norm2_next, tot);
 }
 
 // y_0 = 1/n (norm2[0] = 1 so that it is used unscaled), contributions of
@@ -308,6 +361,11 @@ int launch_prec_rows(const PrEcArgs& a, bool fused, hipStream_t s) {
   const int blocks = std::max(1, std::min(a.rb.ntab, 2048));
   if (fused) hipLaunchKernelGGL((k_prec_rows<256, true>), dim3(blocks), dim3(256), 0, s, a);
   else hipLaunchKernelGGL((k_prec_rows<256, false>), dim3(blocks), dim3(256), 0, s, a);
+  if (a.nlong > 0) {
+    const int lb = std::min(64, (a.nlong + 255) / 256);
+    if (fused) hipLaunchKernelGGL((k_prec_long<true>), dim3(lb), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_prec_long<false>), dim3(lb), dim3(256), 0, s, a);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

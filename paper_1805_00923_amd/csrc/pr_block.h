@@ -93,23 +93,58 @@ __device__ void pr_rows_block(const PrRows& r, int t, int cap_e, const TC* __res
   gather_block<BT, TC>(r.idx, e0, ne, lds_val, [cin](int u) { return cin[u]; });
   for (int k = tid; k <= nr; k += BT) lds_off[k] = r.off[kb + k] - e0;
   __syncthreads();
-  int tpv = 1;
-  if (nr < BT) {
-    tpv = BT / (nr > 0 ? nr : 1);
-    tpv = 1 << (31 - __clz(tpv));
-    if (tpv > kWave) tpv = kWave;
-  }
-  const int groups = BT / tpv, grp = tid / tpv, gl = tid % tpv;
-  for (int k0 = 0; k0 < nr; k0 += groups) {
-    const int k = k0 + grp;
-    double s = 0.0;
-    if (k < nr) {
-      const int a = lds_off[k], b = lds_off[k + 1];
-      for (int j = a + gl; j < b; j += tpv) s += (double)lds_val[j];
+  // Edge-parallel segmented sum, deterministic: thread t takes a run of
+  // ceil(ne / BT) consecutive edges and sums each row piece in order.  A row
+  // wholly inside the run is finished by that thread; a row crossing runs
+  // leaves its first piece in head[t0] and later pieces in cont[t], and
+  // thread t0 adds them in thread order.  The block's edges are spread
+  // evenly over the threads however skewed its rows are.
+  __shared__ double head[BT], cont[BT];
+  const int ept = (ne + BT - 1) / BT;
+  const int eb = tid * ept, ee = min(ne, eb + ept);
+  int kl = -1, kl_end = 0;  // row whose head this thread holds
+  if (eb < ee) {
+    int lo = 0, hi = nr;  // lds_off[lo] <= eb < lds_off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (lds_off[mid] <= eb) lo = mid;
+      else hi = mid;
     }
-    for (int o = tpv >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
-    if (gl == 0 && k < nr) finish(kb + k, s);
+    int k = lo, rs = lds_off[k], re = lds_off[k + 1];
+    double sum = 0.0;
+    for (int j = eb; j < ee; ++j) {
+      if (j >= re) {  // row k ends inside the run
+        if (rs >= eb) finish(kb + k, sum);
+        else cont[tid] = sum;
+        sum = 0.0;
+        do {
+          ++k;
+        } while (lds_off[k + 1] <= j);
+        rs = lds_off[k];
+        re = lds_off[k + 1];
+      }
+      sum += (double)lds_val[j];
+    }
+    if (re <= ee) {  // the last row ends with the run
+      if (rs >= eb) finish(kb + k, sum);
+      else cont[tid] = sum;
+    } else if (rs >= eb) {  // it starts here and runs on
+      head[tid] = sum;
+      kl = k;
+      kl_end = re;
+    } else {  // a run inside one row
+      cont[tid] = sum;
+    }
   }
+  __syncthreads();
+  if (kl >= 0) {
+    double sum = head[tid];
+    const int t1 = (kl_end - 1) / ept;
+    for (int t = tid + 1; t <= t1; ++t) sum += cont[t];
+    finish(kb + kl, sum);
+  }
+  for (int k = tid; k < nr; k += BT)
+    if (lds_off[k] == lds_off[k + 1]) finish(kb + k, 0.0);
   __syncthreads();
 }
 
