@@ -457,6 +457,20 @@ gi_status gi_batch_autotune(gi_batch* b, int32_t reps);
 gi_status gi_batch_set_threads(gi_batch* b, int32_t threads);
 gi_status gi_batch_get_threads(const gi_batch* b, int32_t* threads);
 
+/* Per-step trace of batch tasks (the batched counterpart of the per-step
+ * trace in gi_get_run_stats).  gi_batch_set_trace keeps up to cap records
+ * per task from the next run on (0 turns it off; it re-captures the HIP
+ * graph).  gi_batch_get_trace reads task's records of the last run: for
+ * each BFS level (PageRank iteration) its start on the device wall clock in
+ * ns from the task's first step, whether it pulled, and the frontier size
+ * (0 for PageRank); a final record marks the task's end (pull 0, frontier
+ * 0).  At most cap records are written to each non-NULL array; *count gets
+ * their number.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+gi_status gi_batch_set_trace(gi_batch* b, int32_t cap);
+gi_status gi_batch_get_trace(const gi_batch* b, int32_t task, int64_t* start_ns, int32_t* pull,
+                             int64_t* frontier, int32_t cap, int32_t* count);
+
 /* Run every task once: one launch of the reset kernel and the persistent
  * kernel, captured once into a HIP graph and replayed when use_graph is
  * nonzero (on the batch's own stream, after `stream` has drained), else

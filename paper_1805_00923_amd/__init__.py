@@ -129,6 +129,8 @@ _SIGS = {
     "gi_batch_destroy": (ctypes.c_int, [_vp]),
     "gi_batch_set_threads": (ctypes.c_int, [_vp, _i32]),
     "gi_batch_get_threads": (ctypes.c_int, [_vp, _vp]),
+    "gi_batch_set_trace": (ctypes.c_int, [_vp, _i32]),
+    "gi_batch_get_trace": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _i32, _vp]),
     "gi_get_step_times": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp]),
     "gi_frontier_sparse_to_bitvec": (ctypes.c_int, [_i32, _vp, _i32, _vp, _vp]),
     "gi_frontier_bitvec_to_sparse": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp]),
@@ -505,6 +507,22 @@ class Batch:
         t = ctypes.c_int32(0)
         _check(lib.gi_batch_get_threads(self._h, ctypes.byref(t)))
         return t.value
+
+    def set_trace(self, cap):
+        """Keep up to cap per-step records per task from the next run on."""
+        _check(lib.gi_batch_set_trace(self._h, int(cap)))
+
+    def trace(self, task, cap=4096):
+        """(start_ns, pull, frontier) arrays of task's steps in the last run,
+        the last record marking its end."""
+        t = np.zeros(cap, np.int64)
+        p = np.zeros(cap, np.int32)
+        f = np.zeros(cap, np.int64)
+        c = ctypes.c_int32(0)
+        _check(lib.gi_batch_get_trace(self._h, int(task), t.ctypes.data, p.ctypes.data,
+                                      f.ctypes.data, int(cap), ctypes.byref(c)))
+        k = c.value
+        return t[:k], p[:k], f[:k]
 
     def run(self, use_graph=True, stream=None):
         _check(lib.gi_batch_run(self._h, 1 if use_graph else 0, _stream(stream)))

@@ -88,7 +88,8 @@ __device__ bool task_barrier(TaskCtl* c, int k, int* gerr, long long limit) {
 }
 
 template <int BT>
-__device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const BatchArgs& a) {
+__device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const BatchArgs& a,
+                         int* lds) {
   const int n = G.n, k = t.k, W = (n + 63) >> 6, tid = threadIdx.x;
   int32_t* level = static_cast<int32_t*>(t.out);
   TaskCtl* c = t.ctl;
@@ -137,10 +138,16 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
       if (tid == 0) __hip_atomic_store(a.error, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
+    const bool pull = hybrid_dense(nf, df, G.m, 20);
     if (r == 0 && tid == 0) {
       // read by every workgroup at the previous level, accumulated at the next
       c->qn[(L + 2) % 3] = 0;
       c->ds[(L + 2) % 3] = 0;
+      if (L < a.trace_cap) {
+        long long* rec = a.trace + ((size_t)t.id * a.trace_cap + L) * 2;
+        rec[0] = wall_ticks();
+        rec[1] = ((long long)pull << 62) | nf;
+      }
     }
     uint64_t* bclr = bv[(L + 2) % 3];
     for (int w = w0 + tid; w < w1; w += BT) bclr[w] = 0ull;
@@ -152,13 +159,15 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
     b.next = DenseSet{bv[(L + 1) % 3], nullptr};
     b.vis = t.vis;
     long long found = 0, found_deg = 0;
-    if (hybrid_dense(nf, df, G.m, 20)) {
+    if (pull) {
       bfs_pull_range<BT, 2>(b, L + 1, w0, w1, (int)(threadIdx.x / kWave), BT / kWave, G.outdeg,
                           &found, &found_deg);
     } else {
       BfsVisit vis{G.out_idx, level, t.parent, L + 1, b.next, t.vis};
       vis.deg = G.outdeg;
-      push_words<BT>(b.cur.bv, w0, w1, n, G.out_off, vis);
+      // a frontier whose degree sum is at most kHubDeg holds no hub
+      if (df > kHubDeg) push_hubs<BT>(G.hubs, G.nhubs, b.cur, G.out_off, G.out_idx, r, k, vis);
+      push_words<BT>(b.cur.bv, w0, w1, n, G.out_off, vis, kHubDeg, lds);
       found = vis.found;
       found_deg = vis.found_deg;
     }
@@ -169,7 +178,14 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
     }
     if (!task_barrier(c, k, a.error, a.spin_limit)) return;
   }
-  if (r == 0 && tid == 0) c->levels = L;
+  if (r == 0 && tid == 0) {
+    c->levels = L;
+    if (L < a.trace_cap) {
+      long long* rec = a.trace + ((size_t)t.id * a.trace_cap + L) * 2;
+      rec[0] = wall_ticks();
+      rec[1] = 0;
+    }
+  }
 }
 
 template <int BT>
@@ -199,7 +215,13 @@ __device__ void pr_task(const BatchGraph& G, const BatchTask& t, int r, const Ba
   pv.base = (1.0 - (double)t.damping) / (double)n;
   PrRows rows{G.pr_table, G.pr_ntab, G.in_off, G.in_idx, nullptr, t.lr_acc, t.lr_cnt,
               G.lr_chunks};
-  for (int it = 0; it < t.iters; ++it) {
+  for (int it = 0; it <= t.iters; ++it) {
+    if (r == 0 && tid == 0 && it < a.trace_cap) {
+      long long* rec = a.trace + ((size_t)t.id * a.trace_cap + it) * 2;
+      rec[0] = wall_ticks();
+      rec[1] = it < t.iters ? (1ll << 62) : 0;
+    }
+    if (it == t.iters) break;
     const float* cin = (it & 1) ? t.c1 : t.c0;
     float* cout = (it & 1) ? t.c0 : t.c1;
     float* rk = it == t.iters - 1 ? ranks : nullptr;
@@ -221,7 +243,7 @@ __global__ __launch_bounds__(BT, batch_min_waves<BT>()) void k_batch(BatchArgs a
     const BatchTask& t = a.tasks[it.x];
     const BatchGraph& G = a.graphs[t.graph];
     if (it.y == 0 && threadIdx.x == 0) t.ctl->t_begin = wall_ticks();
-    if (t.alg == ALG_BFS) bfs_task<BT>(G, t, it.y, a);
+    if (t.alg == ALG_BFS) bfs_task<BT>(G, t, it.y, a, reinterpret_cast<int*>(smem));
     else pr_task<BT>(G, t, it.y, a, lds_val, lds_off);
     if (it.y == 0 && threadIdx.x == 0) t.ctl->t_end = wall_ticks();
   }
@@ -237,8 +259,11 @@ __global__ void k_batch_init(TaskCtl* ctl, int ntasks, int* error) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *error = 0;
 }
 
+// Dynamic LDS: the PageRank block staging or the BFS push member list,
+// whichever is larger (a workgroup runs one task at a time).
 size_t batch_lds_bytes(int cap_e, int cap_v) {
-  return sizeof(float) * (size_t)cap_e + sizeof(int) * (size_t)(cap_v + 1);
+  return std::max(sizeof(float) * (size_t)cap_e + sizeof(int) * (size_t)(cap_v + 1),
+                  sizeof(int) * (size_t)kPushList);
 }
 
 bool batch_threads_ok(int bt) { return bt == 256 || bt == 512 || bt == 1024; }

@@ -17,7 +17,9 @@ struct BfsVisit {
   long long work = 0, found = 0, found_deg = 0;
   __device__ __forceinline__ void operator()(int u, int e, bool valid) {
     if (!valid) return;
-    const int v = idx[e];
+    visit(u, idx[e]);
+  }
+  __device__ __forceinline__ void visit(int u, int v) {
     ++work;
     if (level[v] >= 0) return;
     if (atomicCAS(&level[v], -1, l1) != -1) return;
@@ -30,6 +32,40 @@ struct BfsVisit {
     }
   }
 };
+
+// Push of the frontier's hubs (rows longer than kHubDeg, listed per graph)
+// by all k workgroups of a batch task, workgroup r taking the r-th of k
+// equal slices of each row, four edges in flight per thread.  Without it a
+// hub's whole row falls to the one workgroup that owns its frontier word.
+template <int BT>
+__device__ void push_hubs(const int32_t* hubs, int nhubs, const DenseSet& cur,
+                          const int32_t* off, const int32_t* idx, int r, int k, BfsVisit& vis) {
+  __shared__ int s_h[BT];
+  __shared__ int s_cnt;
+  const int tid = threadIdx.x;
+  for (int h0 = 0; h0 < nhubs; h0 += BT) {
+    if (tid == 0) s_cnt = 0;
+    __syncthreads();
+    const int h = h0 + tid;
+    if (h < nhubs && cur.test(hubs[h])) s_h[atomicAdd(&s_cnt, 1)] = hubs[h];
+    __syncthreads();
+    const int cnt = s_cnt;
+    for (int i = 0; i < cnt; ++i) {
+      const int u = s_h[i];
+      const long long beg = off[u], len = (long long)off[u + 1] - beg;
+      const int s0 = (int)(beg + len * r / k), s1 = (int)(beg + len * (r + 1) / k);
+      for (int e = s0 + tid; e < s1; e += 4 * BT) {
+        int v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = e + q * BT < s1 ? idx[e + q * BT] : -1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (v[q] >= 0) vis.visit(u, v[q]);
+      }
+    }
+    __syncthreads();
+  }
+}
 
 // DensePull: a wave owns 64-vertex words and takes G of them at a time, so
 // the dependent load chains of G words (visited word -> in-row bounds ->
@@ -55,15 +91,28 @@ __device__ long long bfs_pull_range(const BfsArgs& b, int l1, int wbeg, int wend
   const int n = g.n, W = wend, lane = __lane_id();
   const DenseSet cur = b.cur, nxt = b.next;
   long long work = 0;
+  // visited words of the next group are loaded one group ahead (only this
+  // wave writes them in this step)
+  uint64_t vn[G];
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    const int w = wbeg + wave0 + q * nwaves;
+    vn[q] = w < W ? b.vis[w] : ~0ull;
+  }
   for (int wb = wbeg + wave0; wb < W; wb += G * nwaves) {
     uint64_t vw[G];
     bool cand[G], found[G];
     int j[G], e[G], par[G];
 #pragma unroll
     for (int q = 0; q < G; ++q) {
+      vw[q] = vn[q];
+      const int wn = wb + G * nwaves + q * nwaves;
+      vn[q] = wn < W ? b.vis[wn] : ~0ull;
+    }
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
       const int w = wb + q * nwaves;  // wave-uniform
       const int v = (w << 6) + lane;
-      vw[q] = w < W ? b.vis[w] : ~0ull;
       cand[q] = w < W && v < n && !((vw[q] >> lane) & 1ull);
       found[q] = false;
       par[q] = -1;

@@ -76,6 +76,8 @@ struct gi_graph {
   int32_t *out_off = nullptr, *out_idx = nullptr, *in_off = nullptr, *in_idx = nullptr;
   int32_t *outdeg = nullptr, *udeg = nullptr;
   int32_t* in_probe = nullptr;  // in-neighbour of largest out-degree (BFS pull's first test)
+  int32_t* hubs = nullptr;      // vertices with more than kHubDeg out-edges
+  int nhubs = 0;
   uint32_t *out_w = nullptr, *in_w = nullptr;
   // host copies of the offsets (destination blocks and segments are built from them)
   std::vector<int32_t> h_in_off, h_in_idx, h_out_off, h_outdeg;
@@ -710,6 +712,12 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
     }
     G_ALLOC(g->in_probe, N);
     G_UP(probe.data(), g->in_probe, 4 * N);
+    std::vector<int32_t> hubs;
+    for (size_t v = 0; v < N; ++v)
+      if (od[v] > kHubDeg) hubs.push_back((int32_t)v);
+    g->nhubs = (int)hubs.size();
+    G_ALLOC(g->hubs, std::max<size_t>(1, hubs.size()));
+    if (!hubs.empty()) G_UP(hubs.data(), g->hubs, 4 * hubs.size());
   }
   if (out_w) {
     G_ALLOC(g->out_w, M);
@@ -1910,6 +1918,8 @@ struct gi_batch {
   int max_grid = 0;          // resident workgroups of the batch kernel
   int grid = 0;
   int bt = 256;              // threads per workgroup
+  int trace_cap = 0;         // per-task step records (gi_batch_set_trace)
+  long long* d_trace = nullptr;
   bool bt_pinned = false;    // set by gi_batch_set_threads: the autotuner keeps it
   int cus = 0;
   size_t lds = 0;
@@ -1945,7 +1955,7 @@ extern "C" gi_status gi_batch_destroy(gi_batch* b) {
   batch_drop_graph(b);
   for (void* q : b->work) (void)hipFree(q);
   for (void* q : {(void*)b->d_graphs, (void*)b->d_tasks, (void*)b->d_ctl, (void*)b->d_items,
-                  (void*)b->d_wg_off, (void*)b->d_err})
+                  (void*)b->d_wg_off, (void*)b->d_err, (void*)b->d_trace})
     if (q) (void)hipFree(q);
   for (hipEvent_t e : b->ev)
     if (e) (void)hipEventDestroy(e);
@@ -1987,6 +1997,8 @@ static BatchGraph batch_graph(const gi_graph* g) {
   d.in_idx = g->in_idx;
   d.outdeg = g->outdeg;
   d.in_probe = g->in_probe;
+  d.hubs = g->hubs;
+  d.nhubs = g->nhubs;
   d.pr_table = g->pr_table;
   d.pr_ntab = g->pr_ntab;
   d.pr_cap_e = g->pr_cap_e;
@@ -2001,6 +2013,14 @@ static BatchGraph batch_graph(const gi_graph* g) {
 // plus the task's time, so a task's workgroups reach it together instead of
 // one waiting behind another's earlier work.  Every list follows the one
 // task order.
+//
+// XCD placement: workgroups are dispatched to the 8 XCDs round-robin by
+// index, so the plan works on logical slots l = x * (G / 8) + j that map to
+// workgroup j * 8 + x, and a block is placed inside one XCD's range when the
+// task fits in it.  A task's workgroups then share one L2: its frontier and
+// visited bitvectors stay cached there instead of competing with every
+// other task's in all eight.  (Placement affects speed only; the barriers
+// synchronise at device scope.)
 static gi_status batch_plan(gi_batch* b) {
   const int nt = (int)b->tasks.size();
   std::vector<int> order((size_t)nt);
@@ -2014,9 +2034,14 @@ static gi_status batch_plan(gi_batch* b) {
   long long want = 0;
   for (int i = 0; i < nt; ++i) want += b->k[(size_t)i];
   b->grid = (int)std::min<long long>(b->max_grid, std::max<long long>(b->grid, want));
+  constexpr int kXcd = 8;
+  if (b->grid >= kXcd && b->grid % kXcd != 0 && b->max_grid % kXcd == 0)
+    b->grid = std::min(b->max_grid, (b->grid + kXcd - 1) / kXcd * kXcd);
   const int G = b->grid;
+  const bool xcd = G >= kXcd && G % kXcd == 0;
+  const int per = xcd ? G / kXcd : G;  // logical slots per XCD
   std::vector<double> load((size_t)G, 0.0);
-  std::vector<std::vector<int2>> lists((size_t)G);
+  std::vector<std::vector<int2>> lists((size_t)G);  // by logical slot
   for (int t : order) {
     const int k = std::min(b->k[(size_t)t], G);
     b->k[(size_t)t] = k;
@@ -2024,13 +2049,19 @@ static gi_status batch_plan(gi_batch* b) {
     while (P < k) P <<= 1;
     int best = 0;
     double best_max = 1e300;
-    for (int w0 = 0; w0 + k <= G; w0 += std::min(P, G)) {
+    auto consider = [&](int w0) {
       double mx = 0.0;
       for (int r = 0; r < k; ++r) mx = std::max(mx, load[(size_t)(w0 + r)]);
       if (mx < best_max) {
         best_max = mx;
         best = w0;
       }
+    };
+    if (k <= per) {
+      for (int x = 0; x * per < G; ++x)
+        for (int w0 = x * per; w0 + k <= (x + 1) * per; w0 += std::min(P, per)) consider(w0);
+    } else {
+      for (int w0 = 0; w0 + k <= G; w0 += std::min(P, G)) consider(w0);
     }
     for (int r = 0; r < k; ++r) {
       const int w = best + r;
@@ -2041,8 +2072,10 @@ static gi_status batch_plan(gi_batch* b) {
   std::vector<int> off((size_t)G + 1, 0);
   std::vector<int2> items;
   for (int w = 0; w < G; ++w) {
+    // workgroup w runs the list of logical slot (w % 8) * per + w / 8
+    const int l = xcd ? (w % kXcd) * per + w / kXcd : w;
     off[(size_t)w] = (int)items.size();
-    items.insert(items.end(), lists[(size_t)w].begin(), lists[(size_t)w].end());
+    items.insert(items.end(), lists[(size_t)l].begin(), lists[(size_t)l].end());
   }
   off[(size_t)G] = (int)items.size();
   for (void* q : {(void*)b->d_items, (void*)b->d_wg_off})
@@ -2121,6 +2154,7 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
     const gi_graph* g = b->graphs[(size_t)t.graph];
     BatchTask& d = b->h_tasks[i];
     d = BatchTask{};
+    d.id = (int)i;
     d.alg = t.algorithm == GI_ALG_BFS ? ALG_BFS : ALG_PR;
     d.graph = t.graph;
     d.src = t.src;
@@ -2178,6 +2212,8 @@ static BatchArgs batch_args(const gi_batch* b, const int2* items, const int* wg_
   a.error = b->d_err;
   a.spin_limit = b->spin_limit;
   a.lds_cap_e = b->cap_e;
+  a.trace_cap = b->trace_cap;
+  a.trace = b->d_trace;
   return a;
 }
 
@@ -2424,6 +2460,49 @@ extern "C" gi_status gi_batch_set_threads(gi_batch* b, int32_t threads) {
   if (st != GI_OK) return st;
   b->bt_pinned = true;
   return batch_plan(b);
+}
+
+extern "C" gi_status gi_batch_set_trace(gi_batch* b, int32_t cap) {
+  if (!b || cap < 0 || cap > (1 << 20)) return fail(GI_ERR_INVALID_ARG, "bad trace capacity");
+  HIP_TRY(hipDeviceSynchronize());
+  if (b->d_trace) (void)hipFree(b->d_trace);
+  b->d_trace = nullptr;
+  b->trace_cap = 0;
+  if (cap > 0) {
+    const size_t cnt = b->tasks.size() * (size_t)cap * 2;
+    if (hipMalloc((void**)&b->d_trace, sizeof(long long) * cnt) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(GI_ERR_OUT_OF_MEMORY, "trace allocation failed");
+    }
+    HIP_TRY(hipMemset(b->d_trace, 0, sizeof(long long) * cnt));
+    b->trace_cap = cap;
+  }
+  batch_drop_graph(b);  // the captured launch holds the old arguments
+  return GI_OK;
+}
+
+extern "C" gi_status gi_batch_get_trace(const gi_batch* b, int32_t task, int64_t* start_ns,
+                                        int32_t* pull, int64_t* frontier, int32_t cap,
+                                        int32_t* count) {
+  if (!b || !count || task < 0 || task >= (int32_t)b->tasks.size() || cap < 0)
+    return fail(GI_ERR_INVALID_ARG, "bad trace arguments");
+  *count = 0;
+  if (b->trace_cap == 0) return GI_OK;
+  int levels = 0;
+  HIP_TRY(hipMemcpy(&levels, &b->d_ctl[task].levels, sizeof(int), hipMemcpyDeviceToHost));
+  const int nrec = std::min(levels + 1, b->trace_cap);
+  std::vector<long long> rec((size_t)nrec * 2);
+  HIP_TRY(hipMemcpy(rec.data(), b->d_trace + (size_t)task * b->trace_cap * 2,
+                    sizeof(long long) * rec.size(), hipMemcpyDeviceToHost));
+  const int n = std::min(nrec, cap);
+  for (int i = 0; i < n; ++i) {
+    if (start_ns)
+      start_ns[i] = (int64_t)((double)(rec[2 * i] - rec[0]) * 1e6 / (double)b->clock_khz);
+    if (pull) pull[i] = (int32_t)((unsigned long long)rec[2 * i + 1] >> 62);
+    if (frontier) frontier[i] = rec[2 * i + 1] & ((1ll << 62) - 1);
+  }
+  *count = n;
+  return GI_OK;
 }
 
 extern "C" gi_status gi_batch_get_threads(const gi_batch* b, int32_t* threads) {

@@ -22,6 +22,7 @@
 namespace gi {
 
 constexpr int kWave = 64;
+constexpr int kHubDeg = 4096;   // rows longer than this are hubs (batched BFS push)
 constexpr int kParts = 2048;     // step kernels run exactly this many workgroups,
                                  // one statistics slot each
 constexpr int kMaxCount = 2048;  // at most this many count/write workgroups

@@ -201,6 +201,8 @@ struct BatchGraph {
   const int32_t* in_idx;
   const int32_t* outdeg;
   const int32_t* in_probe;
+  const int32_t* hubs;   // vertices with more than kHubDeg out-edges
+  int nhubs;
   const int4* pr_table;  // PageRank destination blocks (the graph's current schedule)
   int pr_ntab;
   int pr_cap_e;
@@ -220,6 +222,7 @@ struct TaskCtl {
 };
 
 struct BatchTask {
+  int id;       // index in the batch
   int alg;      // ALG_BFS or ALG_PR
   int graph;
   int src;
@@ -247,6 +250,9 @@ struct BatchArgs {
   int* error;          // set when a barrier wait timed out
   long long spin_limit;  // wall-clock ticks a barrier may wait
   int lds_cap_e;
+  int trace_cap;         // per-task step records kept (0: no trace)
+  long long* trace;      // [task][trace_cap][2]: wall clock at the step's start,
+                         // (pull << 62) | frontier size (BFS) or 0 (PageRank)
 };
 
 bool batch_threads_ok(int bt);  // 256, 512 or 1024 threads per workgroup

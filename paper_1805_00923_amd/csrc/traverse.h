@@ -410,13 +410,14 @@ __device__ void dense_push_range(const DenseSet& fr, int vb, int ve, int first_b
 // BT words are read at a time, their members are listed in LDS (a
 // workgroup prefix sum of the words' popcounts gives each word its slots;
 // at most kList members per pass) and expanded BT members per group, so
-// empty stretches cost one read and sparse words no idle lanes.
+// empty stretches cost one read and sparse words no idle lanes.  s_v: LDS
+// for kPushList ints, supplied by the caller.
+constexpr int kPushList = 4096;
 template <int BT, class Visit>
 __device__ void push_words(const uint64_t* bv, int wb, int we, int n, const int32_t* off,
-                           Visit& vis) {
-  constexpr int kList = 4096;
+                           Visit& vis, int skip_deg, int* s_v) {
+  constexpr int kList = kPushList;
   __shared__ int sh[4];
-  __shared__ int s_v[kList];
   const int tid = threadIdx.x;
   for (int tile = wb; tile < we; tile += BT) {
     const int w = tile + tid;
@@ -440,6 +441,7 @@ __device__ void push_words(const uint64_t* bv, int wb, int we, int n, const int3
           if (u < n) {
             beg = off[u];
             end = off[u + 1];
+            if (end - beg > skip_deg) end = beg;  // pushed elsewhere
           }
         }
         push_rows<BT>(u, beg, end, vis, sh);

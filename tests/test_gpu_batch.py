@@ -17,9 +17,17 @@ _POOL = None
 def pool():
     global _POOL
     if _POOL is None:
+        # a hub with more out-edges than the batch's hub threshold (4096), so
+        # BFS tasks push it with all their workgroups
+        n = 9000
+        hub_src = np.concatenate([np.zeros(n - 1, np.int32), np.arange(1, n, dtype=np.int32)])
+        hub_dst = np.concatenate([np.arange(1, n, dtype=np.int32), np.zeros(n - 1, np.int32)])
+        extra = gg.uniform(n, 2 * n, seed=105)
+        hub = gg.EdgeList(n, np.concatenate([hub_src, extra.src]),
+                          np.concatenate([hub_dst, extra.dst]), name="hub9000")
         els = [gg.rmat(8, seed=101), gg.rmat(11, seed=102), gg.rmat(13, seed=103),
                gg.grid(30, 41, 0.0, weighted=False), gg.path(500), gg.empty(33),
-               gg.uniform(20000, 90000, seed=104)]
+               gg.uniform(20000, 90000, seed=104), hub]
         _POOL = [(el, device_graph(el), oracle.Graph(el)) for el in els]
     return _POOL
 
@@ -108,6 +116,43 @@ def test_batch_workgroup_sizes(threads):
     check(tasks)
     with pytest.raises(gi.GiError):
         b.set_threads(384)
+    b.close()
+
+
+def test_batch_trace_matches_levels():
+    """The per-step trace: one record per BFS level with the oracle's level
+    sizes as frontiers, the hybrid rule's direction, then an end record; one
+    record per PageRank iteration (pull) and an end record."""
+    import torch
+    import paper_1805_00923_amd as gi
+    P = pool()
+    tasks = make_tasks(torch, 16, seed=3)
+    b = gi.Batch([g for _, g, _ in P], tasks)
+    b.set_trace(4096)
+    say("batch trace run")
+    b.run(use_graph=True)
+    torch.cuda.synchronize()
+    check(tasks)
+    info = b.info()
+    for i, t in enumerate(tasks):
+        el, g, og = P[t["graph"]]
+        ts, pull, fr = b.trace(i)
+        assert len(ts) == info["levels"][i] + 1, (i, el.name)
+        assert np.all(np.diff(ts) >= 0) and pull[-1] == 0 and fr[-1] == 0
+        if t["algorithm"] == 1:
+            lv = t["out"].cpu().numpy()
+            sizes = np.bincount(lv[lv >= 0])
+            assert list(fr[:-1]) == list(sizes), (i, el.name)
+            outdeg = np.diff(og.out.off)
+            for L in range(len(sizes)):
+                deg = int(outdeg[lv == L].sum())
+                assert bool(pull[L]) == ((int(sizes[L]) + deg) * 20 > g.m), (i, L)
+        else:
+            assert np.all(pull[:-1] == 1) and len(ts) == t["iters"] + 1
+    b.set_trace(0)
+    b.run(use_graph=True)
+    torch.cuda.synchronize()
+    check(tasks)
     b.close()
 
 
