@@ -253,19 +253,21 @@ def run_bfs_cc(args, torch, dev):
     # CC schedule: the hybrid divisor is tuned once (untimed), the way the
     # paper's autotuner tunes a schedule per algorithm and graph
     bfs_sched = g.schedule().as_dict()
-    cc_div, cc_best = 20, None
-    for div in (2, 4, 8, 20, 50):
-        g.set_schedule(**dict(bfs_sched, hybrid_divisor=div))
-        g.cc(label)
-        g.cc(label)
-        ms = g.stats().kernel_ms
-        if cc_best is None or ms < cc_best:
-            cc_div, cc_best = div, ms
-    cc_sched = dict(bfs_sched, hybrid_divisor=cc_div)
+    cc_div, cc_seg, cc_best, cc_sweep = 20, {}, None, {}
+    for seg in ({}, {"num_segments": 8, "segment_strategy": 1}):
+        for div in (2, 4, 8, 20, 50):
+            g.set_schedule(**dict(bfs_sched, hybrid_divisor=div, **seg))
+            g.cc(label)
+            g.cc(label)
+            ms = g.stats().kernel_ms
+            cc_sweep["div%d%s" % (div, "_seg8" if seg else "")] = round(ms, 3)
+            if cc_best is None or ms < cc_best:
+                cc_div, cc_seg, cc_best = div, seg, ms
+    cc_sched = dict(bfs_sched, hybrid_divisor=cc_div, **cc_seg)
     g.set_schedule(**cc_sched)
-    log("cc hybrid divisor %d (%.3f ms)" % (cc_div, cc_best))
+    log("cc schedule sweep (ms): %s -> divisor %d %s (%.3f ms)" % (cc_sweep, cc_div, cc_seg, cc_best))
 
-    cc_k = KernelTally("k_cc_step")
+    cc_k = KernelTally("k_cc_step + k_cc_seg_merge" if cc_seg else "k_cc_step")
     batch_k = KernelTally("k_batch")
     bfs_k = KernelTally("k_bfs_step")
 
@@ -322,7 +324,7 @@ def run_bfs_cc(args, torch, dev):
         "plain_bfs_gteps_median": round(float(np.median(per_src_gteps)), 3),
         "cc_ms": round(float(np.median([c[0] for c in cc_all])), 4),
         "cc_rounds": int(cc_all[0][1]), "cc_dense_rounds": int(cc_all[0][2]),
-        "cc_hybrid_divisor": cc_div,
+        "cc_hybrid_divisor": cc_div, "cc_schedule": cc_sched, "cc_schedule_sweep_ms": cc_sweep,
         "other_kernel": other.roofline(),
     }
     if batched:

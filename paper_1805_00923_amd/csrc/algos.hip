@@ -322,6 +322,132 @@ __device__ long long cc_pull(const CcArgs& c, int* lds) {
   return work;
 }
 
+// Segmented pull (cache-segmented DensePull for CC): workgroup b serves
+// segment b mod p, so with p = 8 and the round-robin dispatch of workgroups
+// over the XCDs every XCD gathers labels from one segment only, which stays
+// in its L2.  Each segment block leaves its rows' minima in that segment's
+// partial array; k_cc_seg_merge then takes the minimum over the segments.
+template <int BT>
+__device__ long long cc_pull_seg(const CcArgs& c, int* lds) {
+  constexpr int kPer = (kCcCapV + 1 + BT - 1) / BT;
+  int* lds_val = lds;
+  int* lds_off = lds + kCcCapE;
+  int* lds_min = lds_off + kCcCapV + 1;
+  __shared__ int red[BT / kWave];
+  long long work = 0;
+  const int p = c.nseg, G = (int)gridDim.x / p;
+  if ((int)blockIdx.x >= G * p) return 0;
+  const int x = (int)blockIdx.x % p, b0 = (int)blockIdx.x / p;
+  const CcSeg sg = c.segs[x];
+  const RowBlocks& rb = sg.rows;
+  uint32_t* part = c.seg_min + (size_t)x * (size_t)c.g.n;
+  const int32_t* cur = c.cur;
+  const int tid = threadIdx.x, lane = __lane_id();
+  const bool ids = c.ctl->steps == 1;
+  auto label_of = [cur, ids](int u) -> int { return ids ? u : cur[u]; };
+  int4 nx = b0 < rb.ntab ? rb.table[b0] : make_int4(0, 0, 0, 0);
+  for (int t = b0; t < rb.ntab; t += G) {
+    const int4 r = nx;
+    if (t + G < rb.ntab) nx = rb.table[t + G];
+    if (r.y < 0) {  // chunk of a long row
+      int m0 = 0x7fffffff, m1 = 0x7fffffff;
+      int e = r.z + tid;
+      for (; e + 3 * BT < r.w; e += 4 * BT) {
+        const int a0 = rb.idx[e], a1 = rb.idx[e + BT], a2 = rb.idx[e + 2 * BT],
+                  a3 = rb.idx[e + 3 * BT];
+        m0 = min(m0, min(label_of(a0), label_of(a1)));
+        m1 = min(m1, min(label_of(a2), label_of(a3)));
+      }
+      for (; e < r.w; e += BT) m0 = min(m0, label_of(rb.idx[e]));
+      int mn = wave_min(min(m0, m1));
+      if (lane == 0) red[tid / kWave] = mn;
+      __syncthreads();
+      if (tid == 0) {
+        work += r.w - r.z;
+        for (int i = 0; i < BT / kWave; ++i) mn = min(mn, red[i]);
+        atomicMin(&part[sg.dst[r.x]], (uint32_t)mn);
+      }
+      __syncthreads();
+      continue;
+    }
+    const int kb = r.x, ke = r.y, nr = ke - kb;
+    const int e0 = r.z, ne = r.w - r.z;
+    if (tid == 0) work += ne;
+    int offv[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int k = tid + i * BT;
+      offv[i] = k <= nr ? rb.off[kb + k] : 0;
+    }
+    gather_block<BT, int>(rb.idx, e0, ne, lds_val, label_of);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int k = tid + i * BT;
+      if (k <= nr) lds_off[k] = offv[i] - e0;
+      if (k < nr) lds_min[k] = 0x7fffffff;
+    }
+    __syncthreads();
+    {
+      const int ept = (ne + BT - 1) / BT;
+      const int eb = tid * ept, ee = min(ne, eb + ept);
+      if (eb < ee) {
+        int lo = 0, hi = nr;  // lds_off[lo] <= eb < lds_off[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (lds_off[mid] <= eb) lo = mid;
+          else hi = mid;
+        }
+        int k = lo, rend = lds_off[k + 1], m = 0x7fffffff;
+        for (int j = eb; j < ee; ++j) {
+          while (j >= rend) {
+            atomicMin(&lds_min[k], m);
+            m = 0x7fffffff;
+            ++k;
+            rend = lds_off[k + 1];
+          }
+          m = min(m, lds_val[j]);
+        }
+        atomicMin(&lds_min[k], m);
+      }
+    }
+    __syncthreads();
+    // every row of a segment has a neighbour in it, so every row writes
+    for (int k = tid; k < nr; k += BT) part[sg.dst[kb + k]] = (uint32_t)lds_min[k];
+    __syncthreads();
+  }
+  return work;
+}
+
+// Merge of the segment minima (dense pull steps of the segmented form): new
+// label = min(old, minima), partial arrays reset, next frontier written one
+// whole word per wave.
+template <int BT>
+__global__ __launch_bounds__(BT) void k_cc_seg_merge(CcArgs c) {
+  if (c.ctl->mode != MODE_DENSE_PULL) return;
+  const int n = c.g.n, W = (n + 63) >> 6, lane = __lane_id();
+  const int wave = (int)((blockIdx.x * BT + threadIdx.x) / kWave);
+  const int nw = (int)(gridDim.x * BT / kWave);
+  for (int w = wave; w < W; w += nw) {
+    const int v = (w << 6) + lane;
+    bool chg = false;
+    if (v < n) {
+      uint32_t mn = 0xffffffffu;
+      for (int x = 0; x < c.nseg; ++x) {
+        uint32_t* q = c.seg_min + (size_t)x * (size_t)n + v;
+        mn = min(mn, *q);
+        *q = 0xffffffffu;
+      }
+      const int lv = c.cur[v];
+      const int nl = mn < (uint32_t)lv ? (int)mn : lv;
+      c.nxt[v] = nl;
+      chg = nl < lv;
+      if (c.next.bm) c.next.bm[v] = chg ? 1 : 0;
+    }
+    const unsigned long long m = __ballot(chg);
+    if (!c.next.bm && lane == 0) c.next.bv[w] = m;
+  }
+}
+
 template <int BT, int CH>
 __global__ __launch_bounds__(BT) void k_cc_step(CcArgs c, ExpandArgs x) {
   static_assert(kCcCapE + 3 * kCcCapV + 1 <= expand_lds_ints<CH>(), "LDS too small");
@@ -330,7 +456,7 @@ __global__ __launch_bounds__(BT) void k_cc_step(CcArgs c, ExpandArgs x) {
   if (mode == MODE_NONE) return;
   long long work = 0;
   if (mode == MODE_DENSE_PULL) {
-    work = cc_pull<BT>(c, lds);
+    work = c.nseg > 1 ? cc_pull_seg<BT>(c, lds) : cc_pull<BT>(c, lds);
   } else {
     CcVisit vis{c.sym_idx, c.cur, c.nxt, c.next};
     if (mode == MODE_SPARSE_PUSH) expand_chunks<BT, CH>(x, vis, lds);
@@ -895,6 +1021,10 @@ int enqueue_cc_step(const Engine& e, const FrontierArgs& f, const DecideArgs& d,
   mark(te, 1, s);
   hipLaunchKernelGGL((k_cc_step<kBT, kCH>), dim3(kParts), dim3(kBT), 0, s, c,
                      expand_args(e, c.sym_off));
+  if (c.nseg > 1)
+    hipLaunchKernelGGL(k_cc_seg_merge<256>,
+                       dim3((unsigned)std::max(1, std::min(4096, ((c.g.n + 63) / 64 + 3) / 4))),
+                       dim3(256), 0, s, c);
   mark(te, 2, s);
   return GI_OK_LAUNCH();
 }

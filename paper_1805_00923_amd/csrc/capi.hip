@@ -72,6 +72,12 @@ struct gi_graph {
   int device = 0;
   std::vector<void*> allocs;       // graph-lifetime device allocations
   std::vector<void*> sched_allocs; // schedule-lifetime device allocations
+  std::vector<void*> seg_allocs;   // PageRank segments (built on first segmented use)
+  int seg_p = 0, seg_strategy = -1, seg_cap = 0;
+  std::vector<void*> ccseg_allocs; // CC pull segments (built on first segmented use)
+  int ccseg_p = 0, ccseg_strategy = -1;
+  CcSeg* ccsegs = nullptr;
+  uint32_t* cc_segmin = nullptr;
   // adjacency on the device
   int32_t *out_off = nullptr, *out_idx = nullptr, *in_off = nullptr, *in_idx = nullptr;
   int32_t *outdeg = nullptr, *udeg = nullptr;
@@ -382,6 +388,12 @@ static gi_status upload(const void* h, void* d, size_t bytes) {
 // least one in-edge from the segment.
 static gi_status build_segments(gi_graph* g, int p, int strategy) {
   const int32_t n = g->n;
+  HIP_TRY(hipDeviceSynchronize());
+  free_list(g->seg_allocs);
+  g->segs.clear();
+  g->pr_acc = nullptr;
+  g->seg_rows = nullptr;
+  g->seg_p = 0;
   std::vector<int64_t> bound((size_t)p + 1, 0);
   if (strategy == GI_SEG_FIXED_VERTEX_COUNT) {
     const int64_t per = ((int64_t)n + p - 1) / p;
@@ -425,10 +437,10 @@ static gi_status build_segments(gi_graph* g, int p, int strategy) {
                                           &seg_chunks);
     s.ntab = (int)tab.size();
     gi_status st;
-    if ((st = dev_alloc(g, g->sched_allocs, &s.off, soff.size())) != GI_OK) return st;
-    if ((st = dev_alloc(g, g->sched_allocs, &s.idx, sidx.size())) != GI_OK) return st;
-    if ((st = dev_alloc(g, g->sched_allocs, &s.dst, sdst.size())) != GI_OK) return st;
-    if ((st = dev_alloc(g, g->sched_allocs, &s.table, tab.size())) != GI_OK) return st;
+    if ((st = dev_alloc(g, g->seg_allocs, &s.off, soff.size())) != GI_OK) return st;
+    if ((st = dev_alloc(g, g->seg_allocs, &s.idx, sidx.size())) != GI_OK) return st;
+    if ((st = dev_alloc(g, g->seg_allocs, &s.dst, sdst.size())) != GI_OK) return st;
+    if ((st = dev_alloc(g, g->seg_allocs, &s.table, tab.size())) != GI_OK) return st;
     if ((st = upload(soff.data(), s.off, soff.size() * 4)) != GI_OK) return st;
     if ((st = upload(sidx.data(), s.idx, sidx.size() * 4)) != GI_OK) return st;
     if ((st = upload(sdst.data(), s.dst, sdst.size() * 4)) != GI_OK) return st;
@@ -436,28 +448,42 @@ static gi_status build_segments(gi_graph* g, int p, int strategy) {
   }
   // one partial-sum buffer per segment (the concurrent form needs them all;
   // the sequential form uses the first)
-  gi_status st = dev_alloc(g, g->sched_allocs, &g->pr_acc, (size_t)n * (size_t)p);
+  gi_status st = dev_alloc(g, g->seg_allocs, &g->pr_acc, (size_t)n * (size_t)p);
   if (st != GI_OK) return st;
   HIP_TRY(hipMemset(g->pr_acc, 0, sizeof(double) * (size_t)n * (size_t)p));
   std::vector<PrRows> rows;
   for (const SegDev& sg : g->segs)
     rows.push_back(PrRows{sg.table, sg.ntab, sg.off, sg.idx, sg.dst, nullptr, nullptr, nullptr});
-  if ((st = dev_alloc(g, g->sched_allocs, &g->seg_rows, rows.size())) != GI_OK) return st;
-  return upload(rows.data(), g->seg_rows, sizeof(PrRows) * rows.size());
+  if ((st = dev_alloc(g, g->seg_allocs, &g->seg_rows, rows.size())) != GI_OK) return st;
+  if ((st = upload(rows.data(), g->seg_rows, sizeof(PrRows) * rows.size())) != GI_OK) return st;
+  g->seg_p = p;
+  g->seg_strategy = strategy;
+  g->seg_cap = g->pr_cap_e;
+  return GI_OK;
+}
+
+// The schedule's segments, built when a segmented PageRank first needs them
+// (a schedule change alone builds nothing, so alternating schedules between
+// algorithms costs nothing).
+static gi_status ensure_pr_segments(gi_graph* g, int p, int strategy) {
+  if (!g->segs.empty() && g->seg_p == p && g->seg_strategy == strategy &&
+      g->seg_cap == g->pr_cap_e)
+    return GI_OK;
+  return build_segments(g, p, strategy);
 }
 
 static gi_status apply_schedule(gi_graph* g, const gi_schedule& s) {
-  // only the PageRank block layout and the segments own device tables: a
-  // change of direction, frontier kind, divisor or batching is free
-  if (g->pr_table && s.pull_block_edges == g->sched.pull_block_edges &&
-      s.num_segments == g->sched.num_segments &&
-      s.segment_strategy == g->sched.segment_strategy) {
+  // only the PageRank block layout owns device tables here (segments are
+  // built on first use): any other change is free
+  if (g->pr_table && s.pull_block_edges == g->sched.pull_block_edges) {
     g->sched = s;
     return GI_OK;
   }
   HIP_TRY(hipDeviceSynchronize());
   free_list(g->sched_allocs);
+  free_list(g->seg_allocs);
   g->segs.clear();
+  g->seg_p = 0;
   g->pr_acc = nullptr;
   g->seg_rows = nullptr;
   g->pr_table = nullptr;
@@ -487,7 +513,6 @@ static gi_status apply_schedule(gi_graph* g, const gi_schedule& s) {
   HIP_TRY(hipMemset(g->lr_acc, 0, sizeof(double) * nl));
   HIP_TRY(hipMemset(g->lr_cnt, 0, sizeof(unsigned) * nl));
   if ((st = upload(chunks.data(), g->lr_chunks, 4 * chunks.size())) != GI_OK) return st;
-  if (s.num_segments > 1) return build_segments(g, s.num_segments, s.segment_strategy);
   return GI_OK;
 }
 
@@ -553,6 +578,8 @@ extern "C" gi_status gi_graph_destroy(gi_graph* g) {
   if (!g) return GI_OK;
   (void)hipDeviceSynchronize();
   free_list(g->sched_allocs);
+  free_list(g->seg_allocs);
+  free_list(g->ccseg_allocs);
   free_list(g->allocs);
   for (void* q : {(void*)g->sel_p, (void*)g->sel_wb, (void*)g->sel_io})
     if (q) (void)hipFree(q);
@@ -1089,6 +1116,9 @@ extern "C" gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, floa
   if (st != GI_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   bool segmented = g->sched.num_segments > 1;
+  if (segmented && g->sched.direction != GI_DIR_LEARNED &&
+      (st = ensure_pr_segments(g, g->sched.num_segments, g->sched.segment_strategy)) != GI_OK)
+    return st;
   if (g->sched.direction == GI_DIR_LEARNED) {
     // one inference for the whole run: every iteration meets the same state
     float io[kFeat + kOut];
@@ -1158,6 +1188,91 @@ static gi_status ensure_sym(gi_graph* g, hipStream_t s) {
   return GI_OK;
 }
 
+// Source segments of the symmetric adjacency for the segmented CC pull
+// (configApplyNumSSG applied to CC): p ranges of equal vertex count, or of
+// equal out+in degree sums (edge-aware); segment x keeps, for every vertex
+// with a neighbour in range x, those neighbours.  Built on first use from a
+// host copy of the symmetric adjacency.
+static gi_status ensure_cc_segments(gi_graph* g, int p, int strategy, hipStream_t s) {
+  if (g->ccsegs && g->ccseg_p == p && g->ccseg_strategy == strategy) return GI_OK;
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipDeviceSynchronize());
+  free_list(g->ccseg_allocs);
+  g->ccsegs = nullptr;
+  g->cc_segmin = nullptr;
+  g->ccseg_p = 0;
+  const int32_t n = g->n;
+  const size_t N = (size_t)n;
+  std::vector<int32_t> off(N + 1);
+  HIP_TRY(hipMemcpy(off.data(), g->sym_off, 4 * (N + 1), hipMemcpyDeviceToHost));
+  std::vector<int32_t> idx((size_t)off[N]);
+  if (!idx.empty())
+    HIP_TRY(hipMemcpy(idx.data(), g->sym_idx, 4 * idx.size(), hipMemcpyDeviceToHost));
+  // segment of each vertex
+  std::vector<int32_t> segof(N);
+  {
+    int64_t total = off[N], acc = 0;
+    int x = 0;
+    const int64_t per = ((int64_t)n + p - 1) / p;
+    for (int32_t v = 0; v < n; ++v) {
+      if (strategy == GI_SEG_FIXED_VERTEX_COUNT) {
+        x = (int)(v / per);
+      } else {
+        while (x < p - 1 && acc * p >= total * (x + 1)) ++x;
+        acc += off[(size_t)v + 1] - off[(size_t)v];
+      }
+      segof[(size_t)v] = x;
+    }
+  }
+  std::vector<std::vector<int32_t>> soff((size_t)p, std::vector<int32_t>(1, 0)), sidx((size_t)p),
+      sdst((size_t)p);
+  std::vector<int32_t> cnt((size_t)p, 0);
+  for (int32_t v = 0; v < n; ++v) {
+    const int32_t b = off[(size_t)v], e = off[(size_t)v + 1];
+    if (b == e) continue;
+    for (int32_t j = b; j < e; ++j) ++cnt[(size_t)segof[(size_t)idx[(size_t)j]]];
+    for (int x = 0; x < p; ++x)
+      if (cnt[(size_t)x]) {
+        sdst[(size_t)x].push_back(v);
+        soff[(size_t)x].push_back(soff[(size_t)x].back() + cnt[(size_t)x]);
+        cnt[(size_t)x] = 0;
+      }
+    for (int32_t j = b; j < e; ++j) {
+      const int32_t u = idx[(size_t)j];
+      sidx[(size_t)segof[(size_t)u]].push_back(u);
+    }
+  }
+  std::vector<CcSeg> hs((size_t)p);
+  gi_status st;
+  for (int x = 0; x < p; ++x) {
+    std::vector<int4> tab = make_cc_table(soff[(size_t)x].data(), (int)sdst[(size_t)x].size(),
+                                          kCcCapE, kCcCapV);
+    int32_t *doff = nullptr, *didx = nullptr, *ddst = nullptr;
+    int4* dtab = nullptr;
+    if ((st = dev_alloc(g, g->ccseg_allocs, &doff, soff[(size_t)x].size())) != GI_OK) return st;
+    if ((st = dev_alloc(g, g->ccseg_allocs, &didx, std::max<size_t>(1, sidx[(size_t)x].size()))) != GI_OK) return st;
+    if ((st = dev_alloc(g, g->ccseg_allocs, &ddst, std::max<size_t>(1, sdst[(size_t)x].size()))) != GI_OK) return st;
+    if ((st = dev_alloc(g, g->ccseg_allocs, &dtab, std::max<size_t>(1, tab.size()))) != GI_OK) return st;
+    if ((st = upload(soff[(size_t)x].data(), doff, 4 * soff[(size_t)x].size())) != GI_OK) return st;
+    if (!sidx[(size_t)x].empty() &&
+        (st = upload(sidx[(size_t)x].data(), didx, 4 * sidx[(size_t)x].size())) != GI_OK)
+      return st;
+    if (!sdst[(size_t)x].empty() &&
+        (st = upload(sdst[(size_t)x].data(), ddst, 4 * sdst[(size_t)x].size())) != GI_OK)
+      return st;
+    if (!tab.empty() && (st = upload(tab.data(), dtab, sizeof(int4) * tab.size())) != GI_OK)
+      return st;
+    hs[(size_t)x] = CcSeg{RowBlocks{dtab, (int)tab.size(), doff, didx}, ddst};
+  }
+  if ((st = dev_alloc(g, g->ccseg_allocs, &g->ccsegs, (size_t)p)) != GI_OK) return st;
+  if ((st = upload(hs.data(), g->ccsegs, sizeof(CcSeg) * (size_t)p)) != GI_OK) return st;
+  if ((st = dev_alloc(g, g->ccseg_allocs, &g->cc_segmin, (size_t)p * N)) != GI_OK) return st;
+  HIP_TRY(hipMemset(g->cc_segmin, 0xff, sizeof(uint32_t) * (size_t)p * N));
+  g->ccseg_p = p;
+  g->ccseg_strategy = strategy;
+  return GI_OK;
+}
+
 extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
   if (!g || !label) return fail(GI_ERR_INVALID_ARG, "NULL argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1165,6 +1280,9 @@ extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
   if (st != GI_OK) return st;
   st = ensure_sym(g, s);
   if (st != GI_OK) return st;
+  if (g->sched.num_segments > 1 &&
+      (st = ensure_cc_segments(g, g->sched.num_segments, g->sched.segment_strategy, s)) != GI_OK)
+    return st;
   if ((st = start_run(g, 0, s)) != GI_OK) return st;
   int32_t* labs[2] = {label, g->lab};
   CcArgs c;
@@ -1176,6 +1294,14 @@ extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
   c.sym_off = g->sym_off;
   c.sym_idx = g->sym_idx;
   c.rows = RowBlocks{g->sym_table, g->sym_ntab, g->sym_off, g->sym_idx};
+  c.segs = nullptr;
+  c.nseg = 1;
+  c.seg_min = nullptr;
+  if (g->sched.num_segments > 1) {
+    c.segs = g->ccsegs;
+    c.nseg = g->ccseg_p;
+    c.seg_min = g->cc_segmin;
+  }
   c.part = g->part;
   c.ctl = g->ctl;
   LAUNCH_TRY(launch_cc_init(c, frontier_set(g, 0), frontier_set(g, 1), labs[1], s));

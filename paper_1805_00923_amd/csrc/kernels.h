@@ -80,6 +80,14 @@ struct BfsArgs {
   Control* ctl;
 };
 
+// One source segment of the symmetric adjacency for the segmented CC pull:
+// the rows (destinations dst[k]) with at least one neighbour in the segment,
+// holding only those neighbours.
+struct CcSeg {
+  RowBlocks rows;
+  const int32_t* dst;
+};
+
 struct CcArgs {
   DevGraph g;
   int32_t* cur;            // labels L_k
@@ -89,6 +97,9 @@ struct CcArgs {
   const int32_t* sym_off;  // symmetric adjacency (out-row then in-row)
   const int32_t* sym_idx;
   RowBlocks rows;          // destination blocks of the symmetric adjacency
+  const CcSeg* segs;       // segmented pull: nseg source segments (nseg > 1), and
+  int nseg;                // their partial minima, nseg x n (0xffffffff: none)
+  uint32_t* seg_min;
   Part* part;
   Control* ctl;
 };

@@ -178,6 +178,27 @@ def test_cc_all_schedules(sched):
         g.set_schedule()
 
 
+@pytest.mark.parametrize("cfg", [
+    dict(num_segments=8), dict(num_segments=3, segment_strategy=1),
+    dict(num_segments=8, dense_frontier=1), dict(num_segments=2, direction=2),
+    dict(num_segments=64, hybrid_divisor=2),
+], ids=lambda c: "_".join("%s%s" % (k[:8], v) for k, v in c.items()))
+def test_cc_segmented_pull(cfg):
+    """The segmented CC pull (source segments, per-segment minima merged
+    after the step) gives the oracle's labels and round count."""
+    for el, g, og in fam_graphs():
+        say("cc segmented %s %s" % (el.name, cfg))
+        g.set_schedule(**cfg)
+        lab = run_cc(g)
+        ref, rounds = oracle.cc(og)
+        assert np.array_equal(lab, ref), el.name
+        assert g.stats().steps == rounds, el.name
+        lab = run_cc(g)  # partial minima were reset by the merge
+        assert np.array_equal(lab, ref), el.name
+    for el, g, _ in fam_graphs():
+        g.set_schedule()
+
+
 # ---------------------------------------------------------------------- SSSP
 
 def weighted_families():
