@@ -331,6 +331,7 @@ def run_bfs_cc(args, torch, dev):
         info = batch.info()
         extra.update({"batched_bfs_ms": round(batch_k.ms / max(batch_k.launches, 1), 3),
                       "batch_grid": info["grid"], "batch_threads": batch.threads(),
+                      "batch_xcd_local": batch.placement(),
                       "batch_workgroups_per_source": int(np.median(info["workgroups"])),
                       "autotune_s": round(t_tune, 2),
                       "speedup_batched_vs_plain_bfs": round(
@@ -707,6 +708,7 @@ def run_batched(args, torch, dev):
               "speedup_vs_plain": round(t_plain / t_batch, 3),
               "plain_gteps": round(edges / t_plain / 1e9, 3),
               "autotune_s": round(t_tune, 2), "grid": info["grid"], "threads": b.threads(),
+              "xcd_local": b.placement(),
               "workgroups_per_graph": {els[i].name: sorted(set(int(info["workgroups"][j])
                                                              for j in range(256)
                                                              if tasks[j]["graph"] == i))

@@ -442,8 +442,9 @@ gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, const gi_tas
  * class alone on 1, 2, 4, ... 64 workgroups (median of reps launches),
  * keeps the size with the least workgroup-time unless it is more than twice
  * as slow as the fastest, gives tasks longer than the balanced share of the
- * grid their fastest size, plans, and times the whole batch (median of reps
- * launches).  Keeps the workgroup size and plan of the fastest whole batch.
+ * grid their fastest size, plans with XCD-local and with spread placement,
+ * and times each whole batch (median of reps launches).  Keeps the
+ * workgroup size, placement and plan of the fastest whole batch.
  * Tasks with fixed workgroups keep them.  The timing launches write the
  * tasks' outputs (with correct results).
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
@@ -456,6 +457,15 @@ gi_status gi_batch_autotune(gi_batch* b, int32_t reps);
  * Errors: INVALID_ARG (other sizes), OUT_OF_MEMORY, DEVICE. */
 gi_status gi_batch_set_threads(gi_batch* b, int32_t threads);
 gi_status gi_batch_get_threads(const gi_batch* b, int32_t* threads);
+
+/* Placement of each task's workgroups: xcd_local = 1 (the default) keeps a
+ * task that fits on one XCD's share of the grid on that XCD (workgroups are
+ * dispatched to the 8 XCDs round-robin by index), so its workgroups share
+ * one L2; 0 spreads them.  Setting it re-plans; gi_batch_autotune tries
+ * both and keeps the faster.  Placement changes speed only.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+gi_status gi_batch_set_placement(gi_batch* b, int32_t xcd_local);
+gi_status gi_batch_get_placement(const gi_batch* b, int32_t* xcd_local);
 
 /* Per-step trace of batch tasks (the batched counterpart of the per-step
  * trace in gi_get_run_stats).  gi_batch_set_trace keeps up to cap records

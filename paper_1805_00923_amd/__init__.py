@@ -130,6 +130,8 @@ _SIGS = {
     "gi_batch_set_threads": (ctypes.c_int, [_vp, _i32]),
     "gi_batch_get_threads": (ctypes.c_int, [_vp, _vp]),
     "gi_batch_set_trace": (ctypes.c_int, [_vp, _i32]),
+    "gi_batch_set_placement": (ctypes.c_int, [_vp, _i32]),
+    "gi_batch_get_placement": (ctypes.c_int, [_vp, _vp]),
     "gi_batch_get_trace": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _i32, _vp]),
     "gi_get_step_times": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp]),
     "gi_frontier_sparse_to_bitvec": (ctypes.c_int, [_i32, _vp, _i32, _vp, _vp]),
@@ -507,6 +509,15 @@ class Batch:
         t = ctypes.c_int32(0)
         _check(lib.gi_batch_get_threads(self._h, ctypes.byref(t)))
         return t.value
+
+    def set_placement(self, xcd_local):
+        """1: keep each task's workgroups on one XCD when they fit; 0: spread."""
+        _check(lib.gi_batch_set_placement(self._h, 1 if xcd_local else 0))
+
+    def placement(self):
+        x = ctypes.c_int32(0)
+        _check(lib.gi_batch_get_placement(self._h, ctypes.byref(x)))
+        return x.value
 
     def set_trace(self, cap):
         """Keep up to cap per-step records per task from the next run on."""

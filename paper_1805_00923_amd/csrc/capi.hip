@@ -2047,6 +2047,7 @@ struct gi_batch {
   int trace_cap = 0;         // per-task step records (gi_batch_set_trace)
   long long* d_trace = nullptr;
   bool bt_pinned = false;    // set by gi_batch_set_threads: the autotuner keeps it
+  bool xcd_local = true;     // place each task's workgroups on one XCD when they fit
   int cus = 0;
   size_t lds = 0;
   int cap_e = 0;
@@ -2164,8 +2165,9 @@ static gi_status batch_plan(gi_batch* b) {
   if (b->grid >= kXcd && b->grid % kXcd != 0 && b->max_grid % kXcd == 0)
     b->grid = std::min(b->max_grid, (b->grid + kXcd - 1) / kXcd * kXcd);
   const int G = b->grid;
-  const bool xcd = G >= kXcd && G % kXcd == 0;
+  const bool xcd = b->xcd_local && G >= kXcd && G % kXcd == 0;
   const int per = xcd ? G / kXcd : G;  // logical slots per XCD
+  const int pal = per & -per;          // largest power of two dividing per
   std::vector<double> load((size_t)G, 0.0);
   std::vector<std::vector<int2>> lists((size_t)G);  // by logical slot
   for (int t : order) {
@@ -2184,8 +2186,11 @@ static gi_status batch_plan(gi_batch* b) {
       }
     };
     if (k <= per) {
+      // inside one XCD's range, starts aligned to min(P, pal) so that a
+      // range that is not a power of two still holds its share of blocks
+      const int step = std::min(P, pal);
       for (int x = 0; x * per < G; ++x)
-        for (int w0 = x * per; w0 + k <= (x + 1) * per; w0 += std::min(P, per)) consider(w0);
+        for (int w0 = x * per; w0 + k <= (x + 1) * per; w0 += step) consider(w0);
     } else {
       for (int w0 = 0; w0 + k <= G; w0 += std::min(P, G)) consider(w0);
     }
@@ -2555,22 +2560,34 @@ extern "C" gi_status gi_batch_autotune(gi_batch* b, int32_t reps) {
   float best_ms = 0.0f;
   std::vector<int> best_k;
   std::vector<double> best_est;
+  bool best_xcd = true;
   for (int bt : {256, 512, 1024}) {
     if (b->bt_pinned && bt != b->bt) continue;
     b->k = k0;
     b->est = e0;
     if ((st = batch_set_bt(b, bt)) != GI_OK) return st;
+    b->xcd_local = true;
     if ((st = batch_tune_sizes(b, reps)) != GI_OK) return st;
-    float ms = 0.0f;
-    if ((st = batch_time_all(b, reps, &ms)) != GI_OK) return st;
-    if (best_k.empty() || ms < best_ms) {
-      best_ms = ms;
-      best_bt = bt;
-      best_k = b->k;
-      best_est = b->est;
+    const std::vector<int> kt = b->k;
+    const std::vector<double> et = b->est;
+    for (bool xl : {true, false}) {
+      b->xcd_local = xl;
+      b->k = kt;
+      b->est = et;
+      if ((st = batch_plan(b)) != GI_OK) return st;
+      float ms = 0.0f;
+      if ((st = batch_time_all(b, reps, &ms)) != GI_OK) return st;
+      if (best_k.empty() || ms < best_ms) {
+        best_ms = ms;
+        best_bt = bt;
+        best_xcd = xl;
+        best_k = kt;
+        best_est = et;
+      }
     }
   }
   if ((st = batch_set_bt(b, best_bt)) != GI_OK) return st;
+  b->xcd_local = best_xcd;
   b->k = best_k;
   b->est = best_est;
   return batch_plan(b);
@@ -2628,6 +2645,18 @@ extern "C" gi_status gi_batch_get_trace(const gi_batch* b, int32_t task, int64_t
     if (frontier) frontier[i] = rec[2 * i + 1] & ((1ll << 62) - 1);
   }
   *count = n;
+  return GI_OK;
+}
+
+extern "C" gi_status gi_batch_set_placement(gi_batch* b, int32_t xcd_local) {
+  if (!b || (xcd_local != 0 && xcd_local != 1)) return fail(GI_ERR_INVALID_ARG, "bad placement");
+  b->xcd_local = xcd_local != 0;
+  return batch_plan(b);
+}
+
+extern "C" gi_status gi_batch_get_placement(const gi_batch* b, int32_t* xcd_local) {
+  if (!b || !xcd_local) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  *xcd_local = b->xcd_local ? 1 : 0;
   return GI_OK;
 }
 

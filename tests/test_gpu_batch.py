@@ -108,6 +108,13 @@ def test_batch_workgroup_sizes(threads):
         b.run(use_graph=use_graph)
         torch.cuda.synchronize()
         check(tasks)
+    b.set_placement(False)
+    assert b.placement() == 0
+    say("batch threads=%d spread placement" % threads)
+    b.run(use_graph=True)
+    torch.cuda.synchronize()
+    check(tasks)
+    b.set_placement(True)
     say("batch threads=%d autotune (pinned)" % threads)
     b.autotune(reps=1)
     assert b.threads() == threads
