@@ -160,7 +160,7 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
     b.vis = t.vis;
     long long found = 0, found_deg = 0;
     if (pull) {
-      bfs_pull_range<BT, 2>(b, L + 1, w0, w1, (int)(threadIdx.x / kWave), BT / kWave, G.outdeg,
+      bfs_pull_range<BT, (BT == 256 ? 2 : 4)>(b, L + 1, w0, w1, (int)(threadIdx.x / kWave), BT / kWave, G.outdeg,
                           &found, &found_deg);
     } else {
       BfsVisit vis{G.out_idx, level, t.parent, L + 1, b.next, t.vis};
