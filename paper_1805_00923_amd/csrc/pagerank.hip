@@ -7,8 +7,9 @@
 //
 // Destination blocks: the in-edge range of a run of consecutive destinations
 // (at most cap_e edges) is staged in LDS with coalesced index loads and
-// contrib gathers (four of each in flight per thread), then reduced per
-// destination by a power-of-two group of threads.  A destination with more
+// contrib gathers (four of each in flight per thread), then reduced by a
+// deterministic edge-parallel segmented sum (pr_block.h), so skewed rows in
+// one block spread over all its threads.  A destination with more
 // than cap_e in-edges is cut into chunks of cap_e edges, each summed by one
 // workgroup; the chunks' partial sums meet in an FP64 accumulator and the
 // last chunk to finish applies the vertex update.  Chunks of long rows come
@@ -19,7 +20,9 @@
 // in-edges whose source lies in V_i, grouped by destination.  Segments are
 // processed in order, each adding partial sums into an FP64 accumulator, so
 // the contrib gathers of one segment touch only |V_i| entries; a final pass
-// applies the vertex update.
+// applies the vertex update.  In the concurrent form workgroup b serves
+// segment b mod p into its own FP64 partial array (one segment per XCD for
+// p = 8), and the final pass sums the p partials.
 #include <type_traits>
 
 #include "kernels.h"
