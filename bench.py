@@ -510,16 +510,20 @@ def run_selector(args, torch, dev):
     import graphgen as gg
     import paper_1805_00923_amd as gi
     t_all = time.time()
+    # training graphs span the graph-level features of the held-out graph
+    # (degree exponent 2.0-3.0, 16-34 edges per vertex) without including it
     train = [("rmat", 16, 316), ("rmat", 18, 318), ("rmat", 20, 320), ("rmat", 22, 322),
              ("chunglu", 1 << 20, 2.2, 401), ("chunglu", 1 << 20, 2.5, 402),
-             ("chunglu", 1 << 21, 3.0, 403), ("chunglu", 1 << 22, 2.2, 404)]
+             ("chunglu", 1 << 21, 3.0, 403), ("chunglu", 1 << 22, 2.2, 404),
+             ("chunglu34", 1 << 20, 2.0, 405), ("chunglu34", 1 << 21, 2.0, 406)]
     F, Y, V = [], [], []
     for spec in train:
         if spec[0] == "rmat":
             el = gg.rmat(spec[1], 16, seed=spec[2])
         else:
             n = spec[1]
-            el = gg.chung_lu(n, 20 * n, spec[2], min(1e5, n / 8), seed=spec[3])
+            per = 34 if spec[0] == "chunglu34" else 20
+            el = gg.chung_lu(n, per * n, spec[2], min(1e5, n / 8), seed=spec[3])
         g = gi.Graph.from_edges(el.n, el.src, el.dst)
         g.set_schedule(direction=gi.DENSE_PULL_SPARSE_PUSH)
         for s in gg.pick_sources(el, 24, spec[-1]):
@@ -565,7 +569,7 @@ def run_selector(args, torch, dev):
             else:
                 g.pagerank(ranks, 20, 0.85)
             ms.append(g.stats().kernel_ms)
-            dirs = g.stats().trace()[0]
+            dirs = g.stats().step_schedules()
         return float(np.median(ms)), dirs
 
     rows = []
@@ -599,7 +603,10 @@ def run_selector(args, torch, dev):
         t_best += float(best.sum())
         rows.append({"alg": {0: "pagerank", 1: "bfs", 2: "cc"}[alg], "src": s,
                      "heuristic_ms": round(heur_ms, 4), "learned_ms": round(learn_ms, 4),
-                     "best_steps_ms": round(float(best.sum()), 4), "steps": k})
+                     "best_steps_ms": round(float(best.sum()), 4), "steps": k,
+                     "choices": {"heuristic": "".join(str(int(x)) for x in hchoice[:k]),
+                                 "learned": "".join(str(int(x)) for x in lchoice[:k]),
+                                 "best": "".join(str(int(x)) for x in tt.argmin(1))}})
     regret_l, regret_h = np.array(regret_l), np.array(regret_h)
     speedup = t_heur / t_learn
     detail = {
@@ -620,7 +627,8 @@ def run_selector(args, torch, dev):
     }
     config = {"workload": "selector_chunglu_g2.0_%s" % args.heldout, "n": g.n, "m": g.m,
               "train_graphs": ["rmat16", "rmat18", "rmat20", "rmat22", "chunglu1M_g2.2",
-                               "chunglu1M_g2.5", "chunglu2M_g3.0", "chunglu4M_g2.2"]}
+                               "chunglu1M_g2.5", "chunglu2M_g3.0", "chunglu4M_g2.2",
+                               "chunglu1M_g2.0_x34", "chunglu2M_g2.0_x34"]}
     roof = None
     return speedup, "x (heuristic time / learned time)", t_learn, "f32 train / bf16 infer", \
         config, roof, None, detail

@@ -136,6 +136,8 @@ typedef struct gi_run_stats {
   int64_t step_degree_sum[GI_MAX_TRACE]; /* sum of out-degrees of that frontier   */
   int64_t step_edges[GI_MAX_TRACE];      /* edges the step examined (pull: in-edges
                                             scanned up to the first frontier hit)  */
+  int8_t step_segmented[GI_MAX_TRACE];   /* 1: the pull read the source segments
+                                            (CC; schedule S3)                      */
 } gi_run_stats;
 
 /* ---- library ----------------------------------------------------------- */

@@ -76,7 +76,8 @@ class RunStats(ctypes.Structure):
                 ("step_direction", ctypes.c_int8 * MAX_TRACE),
                 ("step_frontier", ctypes.c_int32 * MAX_TRACE),
                 ("step_degree_sum", ctypes.c_int64 * MAX_TRACE),
-                ("step_edges", ctypes.c_int64 * MAX_TRACE)]
+                ("step_edges", ctypes.c_int64 * MAX_TRACE),
+                ("step_segmented", ctypes.c_int8 * MAX_TRACE)]
 
     def trace(self):
         k = self.trace_len
@@ -86,6 +87,14 @@ class RunStats(ctypes.Structure):
 
     def step_edges_examined(self):
         return np.frombuffer(self.step_edges, np.int64)[:self.trace_len].copy()
+
+    def step_schedules(self):
+        """Selector schedule index per step: the direction (S0..S2), or S3
+        for a pull over the source segments."""
+        k = self.trace_len
+        d = np.frombuffer(self.step_direction, np.int8)[:k].astype(np.int64)
+        seg = np.frombuffer(self.step_segmented, np.int8)[:k]
+        return np.where(seg != 0, 3, d)
 
 
 # every symbol the header declares, with its ctypes signature

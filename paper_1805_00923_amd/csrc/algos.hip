@@ -90,24 +90,34 @@ __global__ __launch_bounds__(1024) void k_decide_frontier(FrontierArgs f, Decide
     s_k = k;
   }
   __syncthreads();
+  __shared__ int s_seg;
+  if (threadIdx.x == 0) s_seg = s_mode == MODE_DENSE_PULL && d.seg_pull == 1;
   if (s_learn) {  // workgroup-uniform
     mlp_forward_block(d.sel, s_x, s_xn, s_h1, s_h2, s_y);
     if (threadIdx.x == 0) {
+      // S0..S2 are the three directions; S3, the pull over the source
+      // segments, when the run has them
+      const int last = d.seg_pull == 2 ? 3 : GI_DIR_DENSE_PULL;
       int best = GI_DIR_SPARSE_PUSH;
-      for (int q = GI_DIR_DENSE_PUSH; q <= GI_DIR_DENSE_PULL; ++q)
+      for (int q = GI_DIR_DENSE_PUSH; q <= last; ++q)
         if (s_y[q] < s_y[best]) best = q;
       // the hybrid rule stays unless the model predicts a clear gain
       const int h = hybrid_dense(tot.members, tot.degsum, d.edges, d.divisor) ? GI_DIR_DENSE_PULL
                                                                               : GI_DIR_SPARSE_PUSH;
-      s_mode = s_y[h] - s_y[best] > kLearnedMargin ? best : h;
+      const int pick = s_y[h] - s_y[best] > kLearnedMargin ? best : h;
+      s_mode = pick == 3 ? GI_DIR_DENSE_PULL : pick;
+      s_seg = pick == 3;
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     const int mode = s_mode;
+    c->seg = s_seg;
     if (mode >= 0) {
       const int k = s_k;
-      if (k < kMaxLog) c->host->log[k] = StepLog{mode, (int)tot.members, tot.degsum, 0};
+      if (k < kMaxLog)
+        c->host->log[k] = StepLog{mode + (s_seg ? kLogSegmented : 0), (int)tot.members,
+                                  tot.degsum, 0};
       c->steps = k + 1;
       if (mode != GI_DIR_SPARSE_PUSH) c->dense_steps++;
       c->nf = tot.members;
@@ -423,7 +433,7 @@ __device__ long long cc_pull_seg(const CcArgs& c, int* lds) {
 // whole word per wave.
 template <int BT>
 __global__ __launch_bounds__(BT) void k_cc_seg_merge(CcArgs c) {
-  if (c.ctl->mode != MODE_DENSE_PULL) return;
+  if (c.ctl->mode != MODE_DENSE_PULL || !c.ctl->seg) return;
   const int n = c.g.n, W = (n + 63) >> 6, lane = __lane_id();
   const int wave = (int)((blockIdx.x * BT + threadIdx.x) / kWave);
   const int nw = (int)(gridDim.x * BT / kWave);
@@ -456,7 +466,7 @@ __global__ __launch_bounds__(BT) void k_cc_step(CcArgs c, ExpandArgs x) {
   if (mode == MODE_NONE) return;
   long long work = 0;
   if (mode == MODE_DENSE_PULL) {
-    work = c.nseg > 1 ? cc_pull_seg<BT>(c, lds) : cc_pull<BT>(c, lds);
+    work = c.nseg > 1 && c.ctl->seg ? cc_pull_seg<BT>(c, lds) : cc_pull<BT>(c, lds);
   } else {
     CcVisit vis{c.sym_idx, c.cur, c.nxt, c.next};
     if (mode == MODE_SPARSE_PUSH) expand_chunks<BT, CH>(x, vis, lds);

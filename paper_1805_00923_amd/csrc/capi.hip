@@ -896,7 +896,8 @@ static gi_status read_loop_stats(gi_graph* g, int alg) {
   r.trace_len = std::min(r.steps, GI_MAX_TRACE);
   g->last_steps[alg] = r.steps;
   for (int i = 0; i < r.trace_len; ++i) {
-    r.step_direction[i] = (int8_t)h->log[i].dir;
+    r.step_direction[i] = (int8_t)(h->log[i].dir % kLogSegmented);
+    r.step_segmented[i] = (int8_t)(h->log[i].dir / kLogSegmented);
     r.step_frontier[i] = h->log[i].frontier;
     r.step_degree_sum[i] = h->log[i].degsum;
     r.step_edges[i] = h->log[i].edges;
@@ -1005,6 +1006,7 @@ static DecideArgs decide_args(const gi_graph* g, int alg) {
   d.max_steps = 0;
   d.fc = alg == ALG_CC ? g->fc_cc : g->fc_bfs;
   d.sel = sel_dev(g);
+  d.seg_pull = 0;
   return d;
 }
 
@@ -1093,6 +1095,7 @@ static gi_status pr_run(gi_graph* g, int32_t iters, float damping, float* ranks,
   st.trace_len = std::min(iters, GI_MAX_TRACE);
   for (int k = 0; k < st.trace_len; ++k) {
     st.step_direction[k] = GI_DIR_DENSE_PULL;
+    st.step_segmented[k] = segmented ? 1 : 0;
     st.step_frontier[k] = g->n;
     st.step_degree_sum[k] = g->m;
     st.step_edges[k] = g->m;
@@ -1280,9 +1283,19 @@ extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
   if (st != GI_OK) return st;
   st = ensure_sym(g, s);
   if (st != GI_OK) return st;
-  if (g->sched.num_segments > 1 &&
-      (st = ensure_cc_segments(g, g->sched.num_segments, g->sched.segment_strategy, s)) != GI_OK)
-    return st;
+  // segments: the schedule's, or for the learned choice the automatic
+  // count (2 MiB of labels each) that its S3 stands for
+  const bool learned = g->sched.direction == GI_DIR_LEARNED;
+  int seg_pull = 0;
+  if (learned) {
+    if ((st = ensure_cc_segments(g, auto_segments(g), GI_SEG_FIXED_VERTEX_COUNT, s)) != GI_OK)
+      return st;
+    seg_pull = 2;
+  } else if (g->sched.num_segments > 1) {
+    if ((st = ensure_cc_segments(g, g->sched.num_segments, g->sched.segment_strategy, s)) != GI_OK)
+      return st;
+    seg_pull = 1;
+  }
   if ((st = start_run(g, 0, s)) != GI_OK) return st;
   int32_t* labs[2] = {label, g->lab};
   CcArgs c;
@@ -1297,7 +1310,7 @@ extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
   c.segs = nullptr;
   c.nseg = 1;
   c.seg_min = nullptr;
-  if (g->sched.num_segments > 1) {
+  if (seg_pull) {
     c.segs = g->ccsegs;
     c.nseg = g->ccseg_p;
     c.seg_min = g->cc_segmin;
@@ -1305,7 +1318,8 @@ extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
   c.part = g->part;
   c.ctl = g->ctl;
   LAUNCH_TRY(launch_cc_init(c, frontier_set(g, 0), frontier_set(g, 1), labs[1], s));
-  const DecideArgs d = decide_args(g, ALG_CC);
+  DecideArgs d = decide_args(g, ALG_CC);
+  d.seg_pull = seg_pull;
   st = run_frontier_loop(
       g, s, ALG_CC, 8, (long long)g->n + 2,
       [&](long long k) {
@@ -1979,10 +1993,20 @@ extern "C" gi_status gi_trace_exhaustive(gi_graph* g, int32_t algorithm, int32_t
   std::vector<float> t((size_t)kMaxLog * kOut, 0.0f);
   std::vector<uint8_t> ok((size_t)kMaxLog * kOut, 0);
   std::vector<float> x((size_t)kMaxLog * kFeat, 0.0f);
-  const int nsched = algorithm == GI_ALG_PAGERANK ? 2 : 3;
+  // PageRank: S2, S3; BFS: S0..S2; CC: S0..S3 (S3 = pull over the
+  // automatic source segments)
+  const int nsched = algorithm == GI_ALG_PAGERANK ? 2 : algorithm == GI_ALG_CC ? 4 : 3;
   for (int q = 0; q < nsched && st == GI_OK; ++q) {
     const int sched = algorithm == GI_ALG_PAGERANK ? 2 + q : q;  // S index
-    if (algorithm == GI_ALG_PAGERANK) {
+    if (algorithm == GI_ALG_CC && sched == 3) {
+      g->sched.direction = GI_DIR_DENSE_PULL;
+      g->sched.dense_frontier = GI_FRONTIER_BITVECTOR;
+      g->sched.num_segments = auto_segments(g);
+      g->sched.segment_strategy = GI_SEG_FIXED_VERTEX_COUNT;
+      st = gi_cc(g, out, nullptr);
+      g->sched.num_segments = saved.num_segments;
+      g->sched.segment_strategy = saved.segment_strategy;
+    } else if (algorithm == GI_ALG_PAGERANK) {
       g->sched.direction = GI_DIR_DENSE_PULL;
       const bool seg = sched == 3;
       if (seg && (st = ensure_segments(g)) != GI_OK) break;
@@ -1990,7 +2014,9 @@ extern "C" gi_status gi_trace_exhaustive(gi_graph* g, int32_t algorithm, int32_t
     } else {
       g->sched.direction = sched;  // GI_DIR_SPARSE_PUSH, DENSE_PUSH, DENSE_PULL
       g->sched.dense_frontier = GI_FRONTIER_BITVECTOR;
+      g->sched.num_segments = 1;
       st = algorithm == GI_ALG_BFS ? gi_bfs(g, src, out, nullptr, nullptr) : gi_cc(g, out, nullptr);
+      g->sched.num_segments = saved.num_segments;
     }
     if (st != GI_OK) break;
     const gi_run_stats& rs = g->stats;

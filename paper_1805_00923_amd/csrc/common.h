@@ -22,6 +22,7 @@
 namespace gi {
 
 constexpr int kWave = 64;
+constexpr int kLogSegmented = 16;  // StepLog flag: the pull read the source segments
 constexpr int kHubDeg = 4096;   // rows longer than this are hubs (batched BFS push)
 constexpr int kParts = 2048;     // step kernels run exactly this many workgroups,
                                  // one statistics slot each
@@ -69,7 +70,8 @@ enum : int {
 
 // One entry of the per-step trace.
 struct StepLog {
-  int dir;          // GI_DIR_* run by the step
+  int dir;          // GI_DIR_* run by the step, + kLogSegmented for a pull over
+                    // the source segments
   int frontier;     // |F| entering the step
   long long degsum; // sum of degrees of F
   long long edges;  // edges the step examined
@@ -116,6 +118,7 @@ struct Control {
   int buckets;
   int error;          // an internal size invariant failed (the run is abandoned)
   int chunk;          // slots per expansion chunk of the current sparse step
+  int seg;            // the current pull step uses the source segments (CC)
   HostFlags* host;    // device address of the pinned host flags and trace
 };
 

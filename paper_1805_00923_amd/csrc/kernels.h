@@ -67,6 +67,8 @@ struct DecideArgs {
   int max_steps;   // > 0: the run ends after this many steps
   FeatConst fc;    // graph-level features
   SelDev sel;      // attached selector (GI_DIR_LEARNED)
+  int seg_pull;    // CC: 0 pulls unsegmented; 1 pulls over the source segments;
+                   // 2 the learned choice may take the segmented pull (S3)
 };
 
 struct BfsArgs {
