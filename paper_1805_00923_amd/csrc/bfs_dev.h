@@ -19,9 +19,12 @@ struct BfsVisit {
     if (!valid) return;
     visit(u, idx[e]);
   }
+  // The visited bitvector (n/8 bytes, cache resident) filters targets
+  // before the level array (4n bytes, a line per random access) is touched;
+  // a bit still clear from a stale copy only costs the CAS, which decides.
   __device__ __forceinline__ void visit(int u, int v) {
     ++work;
-    if (level[v] >= 0) return;
+    if ((vis[v >> 6] >> (v & 63)) & 1ull) return;
     if (atomicCAS(&level[v], -1, l1) != -1) return;
     if (parent) parent[v] = u;
     next.insert(v);
