@@ -1229,17 +1229,21 @@ static gi_status ensure_cc_segments(gi_graph* g, int p, int strategy, hipStream_
   }
   std::vector<std::vector<int32_t>> soff((size_t)p, std::vector<int32_t>(1, 0)), sidx((size_t)p),
       sdst((size_t)p);
-  std::vector<int32_t> cnt((size_t)p, 0);
+  std::vector<int32_t> cnt((size_t)p, 0), touched;
   for (int32_t v = 0; v < n; ++v) {
     const int32_t b = off[(size_t)v], e = off[(size_t)v + 1];
     if (b == e) continue;
-    for (int32_t j = b; j < e; ++j) ++cnt[(size_t)segof[(size_t)idx[(size_t)j]]];
-    for (int x = 0; x < p; ++x)
-      if (cnt[(size_t)x]) {
-        sdst[(size_t)x].push_back(v);
-        soff[(size_t)x].push_back(soff[(size_t)x].back() + cnt[(size_t)x]);
-        cnt[(size_t)x] = 0;
-      }
+    touched.clear();
+    for (int32_t j = b; j < e; ++j) {
+      const int32_t x = segof[(size_t)idx[(size_t)j]];
+      if (cnt[(size_t)x]++ == 0) touched.push_back(x);
+    }
+    std::sort(touched.begin(), touched.end());
+    for (int32_t x : touched) {
+      sdst[(size_t)x].push_back(v);
+      soff[(size_t)x].push_back(soff[(size_t)x].back() + cnt[(size_t)x]);
+      cnt[(size_t)x] = 0;
+    }
     for (int32_t j = b; j < e; ++j) {
       const int32_t u = idx[(size_t)j];
       sidx[(size_t)segof[(size_t)u]].push_back(u);
@@ -1292,8 +1296,9 @@ extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
       return st;
     seg_pull = 2;
   } else if (g->sched.num_segments > 1) {
-    if ((st = ensure_cc_segments(g, g->sched.num_segments, g->sched.segment_strategy, s)) != GI_OK)
-      return st;
+    // every segment needs at least one of the step kernel's kParts workgroups
+    const int p = std::min(g->sched.num_segments, kParts);
+    if ((st = ensure_cc_segments(g, p, g->sched.segment_strategy, s)) != GI_OK) return st;
     seg_pull = 1;
   }
   if ((st = start_run(g, 0, s)) != GI_OK) return st;

@@ -181,7 +181,7 @@ def test_cc_all_schedules(sched):
 @pytest.mark.parametrize("cfg", [
     dict(num_segments=8), dict(num_segments=3, segment_strategy=1),
     dict(num_segments=8, dense_frontier=1), dict(num_segments=2, direction=2),
-    dict(num_segments=64, hybrid_divisor=2),
+    dict(num_segments=64, hybrid_divisor=2), dict(num_segments=4096),
 ], ids=lambda c: "_".join("%s%s" % (k[:8], v) for k, v in c.items()))
 def test_cc_segmented_pull(cfg):
     """The segmented CC pull (source segments, per-segment minima merged
