@@ -91,7 +91,9 @@ __global__ __launch_bounds__(1024) void k_decide_frontier(FrontierArgs f, Decide
   }
   __syncthreads();
   __shared__ int s_seg;
-  if (threadIdx.x == 0) s_seg = s_mode == MODE_DENSE_PULL && d.seg_pull == 1;
+  // the first CC round gathers nothing (labels are still the ids), so
+  // segments would only add their merge
+  if (threadIdx.x == 0) s_seg = s_mode == MODE_DENSE_PULL && d.seg_pull == 1 && s_k > 0;
   if (s_learn) {  // workgroup-uniform
     mlp_forward_block(d.sel, s_x, s_xn, s_h1, s_h2, s_y);
     if (threadIdx.x == 0) {
