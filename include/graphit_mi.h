@@ -485,10 +485,22 @@ gi_status gi_batch_get_trace(const gi_batch* b, int32_t task, int64_t* start_ns,
 
 /* Run every task once: one launch of the reset kernel and the persistent
  * kernel, captured once into a HIP graph and replayed when use_graph is
- * nonzero (on the batch's own stream, after `stream` has drained), else
- * launched on `stream`.  Returns after completion.
+ * nonzero (on the batch's own stream, after the work enqueued on `stream`),
+ * else launched on `stream`.  Returns after completion.
  * Errors: INVALID_ARG, DEVICE (including a barrier timeout). */
 gi_status gi_batch_run(gi_batch* b, int32_t use_graph, void* stream);
+
+/* gi_batch_run in two halves, so that other work can run on the device
+ * while the batch does: gi_batch_launch enqueues the run (with use_graph,
+ * on the batch's own stream, ordered after the work already enqueued on
+ * `stream`; else on `stream`) and returns at once; gi_batch_wait waits for
+ * it, records its time and checks the error flag.  One launch may be in
+ * flight per batch; the outputs are not ready before gi_batch_wait returns.
+ * While a launch is in flight the other gi_batch_* calls that change the
+ * batch return INVALID_ARG.
+ * Errors: INVALID_ARG, DEVICE (including a barrier timeout, from wait). */
+gi_status gi_batch_launch(gi_batch* b, int32_t use_graph, void* stream);
+gi_status gi_batch_wait(gi_batch* b);
 
 /* GPU time of the last run (ms), grid size, and per task (arrays of the
  * batch's task count, may be NULL) its workgroups, its completed BFS

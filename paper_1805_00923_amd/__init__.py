@@ -134,6 +134,8 @@ _SIGS = {
     "gi_batch_create": (ctypes.c_int, [_vp, _i32, _vp, _i32, _vp]),
     "gi_batch_autotune": (ctypes.c_int, [_vp, _i32]),
     "gi_batch_run": (ctypes.c_int, [_vp, _i32, _vp]),
+    "gi_batch_launch": (ctypes.c_int, [_vp, _i32, _vp]),
+    "gi_batch_wait": (ctypes.c_int, [_vp]),
     "gi_batch_info": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "gi_batch_destroy": (ctypes.c_int, [_vp]),
     "gi_batch_set_threads": (ctypes.c_int, [_vp, _i32]),
@@ -546,6 +548,13 @@ class Batch:
 
     def run(self, use_graph=True, stream=None):
         _check(lib.gi_batch_run(self._h, 1 if use_graph else 0, _stream(stream)))
+
+    def launch(self, use_graph=True, stream=None):
+        """Enqueue a run and return at once; wait() completes it."""
+        _check(lib.gi_batch_launch(self._h, 1 if use_graph else 0, _stream(stream)))
+
+    def wait(self):
+        _check(lib.gi_batch_wait(self._h))
 
     def info(self):
         ms = ctypes.c_float()

@@ -2097,6 +2097,8 @@ struct gi_batch {
   hipGraph_t hg = nullptr;
   hipGraphExec_t hx = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t evw = nullptr;  // orders the batch's stream after the caller's
+  bool launched = false;     // gi_batch_launch done, gi_batch_wait not yet
   float last_ms = 0.0f;
 };
 
@@ -2117,6 +2119,7 @@ extern "C" gi_status gi_batch_destroy(gi_batch* b) {
     if (q) (void)hipFree(q);
   for (hipEvent_t e : b->ev)
     if (e) (void)hipEventDestroy(e);
+  if (b->evw) (void)hipEventDestroy(b->evw);
   if (b->gstream) (void)hipStreamDestroy(b->gstream);
   delete b;
   return GI_OK;
@@ -2356,6 +2359,10 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
       (void)hipGetLastError();
       return bail(fail(GI_ERR_DEVICE, "hipEventCreate failed"));
     }
+  if (hipEventCreateWithFlags(&b->evw, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(GI_ERR_DEVICE, "hipEventCreate failed"));
+  }
   if (hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking) != hipSuccess) {
     (void)hipGetLastError();
     return bail(fail(GI_ERR_DEVICE, "stream creation failed"));
@@ -2399,8 +2406,9 @@ static gi_status batch_check_error(gi_batch* b) {
   return GI_OK;
 }
 
-extern "C" gi_status gi_batch_run(gi_batch* b, int32_t use_graph, void* stream) {
+extern "C" gi_status gi_batch_launch(gi_batch* b, int32_t use_graph, void* stream) {
   if (!b) return fail(GI_ERR_INVALID_ARG, "NULL batch");
+  if (b->launched) return fail(GI_ERR_INVALID_ARG, "batch already launched (gi_batch_wait first)");
   gi_status st = batch_refresh_graphs(b);
   if (st != GI_OK) return st;
   const int nt = (int)b->tasks.size();
@@ -2423,20 +2431,35 @@ extern "C" gi_status gi_batch_run(gi_batch* b, int32_t use_graph, void* stream) 
         return fail(GI_ERR_DEVICE, "batch graph instantiation failed");
       }
     }
-    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    // the batch's stream waits for the work enqueued on `stream` so far
+    HIP_TRY(hipEventRecord(b->evw, static_cast<hipStream_t>(stream)));
+    HIP_TRY(hipStreamWaitEvent(b->gstream, b->evw, 0));
     HIP_TRY(hipEventRecord(b->ev[0], b->gstream));
     HIP_TRY(hipGraphLaunch(b->hx, b->gstream));
     HIP_TRY(hipEventRecord(b->ev[1], b->gstream));
-    HIP_TRY(hipEventSynchronize(b->ev[1]));
   } else {
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipEventRecord(b->ev[0], s));
     LAUNCH_TRY(launch_batch(a, b->bt, b->grid, b->lds, b->d_ctl, nt, s));
     HIP_TRY(hipEventRecord(b->ev[1], s));
-    HIP_TRY(hipEventSynchronize(b->ev[1]));
   }
+  b->launched = true;
+  return GI_OK;
+}
+
+extern "C" gi_status gi_batch_wait(gi_batch* b) {
+  if (!b) return fail(GI_ERR_INVALID_ARG, "NULL batch");
+  if (!b->launched) return fail(GI_ERR_INVALID_ARG, "batch not launched");
+  b->launched = false;
+  HIP_TRY(hipEventSynchronize(b->ev[1]));
   HIP_TRY(hipEventElapsedTime(&b->last_ms, b->ev[0], b->ev[1]));
   return batch_check_error(b);
+}
+
+extern "C" gi_status gi_batch_run(gi_batch* b, int32_t use_graph, void* stream) {
+  gi_status st = gi_batch_launch(b, use_graph, stream);
+  if (st != GI_OK) return st;
+  return gi_batch_wait(b);
 }
 
 // Time one task alone on k workgroups (median of reps launches).
@@ -2582,6 +2605,7 @@ static gi_status batch_time_all(gi_batch* b, int reps, float* ms) {
 
 extern "C" gi_status gi_batch_autotune(gi_batch* b, int32_t reps) {
   if (!b || reps < 1) return fail(GI_ERR_INVALID_ARG, "bad autotune arguments");
+  if (b->launched) return fail(GI_ERR_INVALID_ARG, "batch launch in flight (gi_batch_wait first)");
   gi_status st = batch_refresh_graphs(b);
   if (st != GI_OK) return st;
   HIP_TRY(hipDeviceSynchronize());
@@ -2626,6 +2650,7 @@ extern "C" gi_status gi_batch_autotune(gi_batch* b, int32_t reps) {
 
 extern "C" gi_status gi_batch_set_threads(gi_batch* b, int32_t threads) {
   if (!b) return fail(GI_ERR_INVALID_ARG, "NULL batch");
+  if (b->launched) return fail(GI_ERR_INVALID_ARG, "batch launch in flight (gi_batch_wait first)");
   if (threads == 0) {
     b->bt_pinned = false;
     return GI_OK;
@@ -2638,6 +2663,7 @@ extern "C" gi_status gi_batch_set_threads(gi_batch* b, int32_t threads) {
 
 extern "C" gi_status gi_batch_set_trace(gi_batch* b, int32_t cap) {
   if (!b || cap < 0 || cap > (1 << 20)) return fail(GI_ERR_INVALID_ARG, "bad trace capacity");
+  if (b->launched) return fail(GI_ERR_INVALID_ARG, "batch launch in flight (gi_batch_wait first)");
   HIP_TRY(hipDeviceSynchronize());
   if (b->d_trace) (void)hipFree(b->d_trace);
   b->d_trace = nullptr;
@@ -2681,6 +2707,7 @@ extern "C" gi_status gi_batch_get_trace(const gi_batch* b, int32_t task, int64_t
 
 extern "C" gi_status gi_batch_set_placement(gi_batch* b, int32_t xcd_local) {
   if (!b || (xcd_local != 0 && xcd_local != 1)) return fail(GI_ERR_INVALID_ARG, "bad placement");
+  if (b->launched) return fail(GI_ERR_INVALID_ARG, "batch launch in flight (gi_batch_wait first)");
   b->xcd_local = xcd_local != 0;
   return batch_plan(b);
 }

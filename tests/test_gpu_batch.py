@@ -200,6 +200,39 @@ def test_batch_autotune_keeps_results():
     b.close()
 
 
+def test_batch_launch_overlaps_other_work():
+    """gi_batch_launch returns at once; CC on the same graph runs on another
+    stream meanwhile; both results are exact after gi_batch_wait, and a
+    second launch before the wait is refused."""
+    import torch
+    import paper_1805_00923_amd as gi
+    P = pool()
+    el, g, og = P[2]
+    tasks = [dict(graph=2, algorithm=1, src=int(s),
+                  out=torch.full((g.n,), -9, dtype=torch.int32, device="cuda:0"))
+             for s in gg.pick_sources(el, 6, 11)]
+    b = gi.Batch([x for _, x, _ in P], tasks)
+    side = torch.cuda.Stream()
+    lab = torch.full((g.n,), -7, dtype=torch.int32, device="cuda:0")
+    for rep, use_graph in enumerate((True, True, False)):
+        say("batch launch + cc overlap %d" % rep)
+        torch.cuda.synchronize()
+        b.launch(use_graph=use_graph)
+        with pytest.raises(gi.GiError):
+            b.launch(use_graph=use_graph)
+        with pytest.raises(gi.GiError):
+            b.autotune(reps=1)
+        g.cc(lab, stream=side)
+        b.wait()
+        torch.cuda.synchronize()
+        for t in tasks:
+            assert np.array_equal(t["out"].cpu().numpy(), oracle.bfs(og, t["src"])[0])
+        assert np.array_equal(lab.cpu().numpy(), oracle.cc(og)[0])
+    with pytest.raises(gi.GiError):
+        b.wait()
+    b.close()
+
+
 def test_batch_argument_errors():
     import torch
     import paper_1805_00923_amd as gi
