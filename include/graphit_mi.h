@@ -444,9 +444,10 @@ gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, const gi_tas
  * class alone on 1, 2, 4, ... 64 workgroups (median of reps launches),
  * keeps the size with the least workgroup-time unless it is more than twice
  * as slow as the fastest, gives tasks longer than the balanced share of the
- * grid their fastest size, plans with XCD-local and with spread placement,
- * and times each whole batch (median of reps launches).  Keeps the
- * workgroup size, placement and plan of the fastest whole batch.
+ * grid their fastest size, caps those sizes at 64, 32 and 16, plans each
+ * with XCD-local and with spread placement, and times each whole batch
+ * (median of reps launches).  Keeps the workgroup size, task sizes,
+ * placement and plan of the fastest whole batch.
  * Tasks with fixed workgroups keep them.  The timing launches write the
  * tasks' outputs (with correct results).
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */

@@ -2625,19 +2625,35 @@ extern "C" gi_status gi_batch_autotune(gi_batch* b, int32_t reps) {
     if ((st = batch_tune_sizes(b, reps)) != GI_OK) return st;
     const std::vector<int> kt = b->k;
     const std::vector<double> et = b->est;
-    for (bool xl : {true, false}) {
-      b->xcd_local = xl;
-      b->k = kt;
-      b->est = et;
-      if ((st = batch_plan(b)) != GI_OK) return st;
-      float ms = 0.0f;
-      if ((st = batch_time_all(b, reps, &ms)) != GI_OK) return st;
-      if (best_k.empty() || ms < best_ms) {
-        best_ms = ms;
-        best_bt = bt;
-        best_xcd = xl;
-        best_k = kt;
-        best_est = et;
+    // the size rule picks per class in isolation; tasks running together
+    // also compete, so the whole batch is timed with the chosen sizes capped
+    // at 64, 32 and 16 workgroups as well
+    for (int cap : {64, 32, 16}) {
+      std::vector<int> kc = kt;
+      std::vector<double> ec = et;
+      bool changed = cap == 64;
+      for (size_t i = 0; i < kc.size(); ++i) {
+        if (b->tasks[i].workgroups > 0 || kc[i] <= cap) continue;
+        ec[i] = et[i] * (double)kc[i] / (double)cap;
+        kc[i] = cap;
+        changed = true;
+      }
+      if (!changed) continue;
+      for (bool xl : {true, false}) {
+        b->xcd_local = xl;
+        b->k = kc;
+        b->est = ec;
+        if ((st = batch_plan(b)) != GI_OK) return st;
+        const std::vector<int> kp = b->k;  // after the plan's clamp to the grid
+        float ms = 0.0f;
+        if ((st = batch_time_all(b, reps, &ms)) != GI_OK) return st;
+        if (best_k.empty() || ms < best_ms) {
+          best_ms = ms;
+          best_bt = bt;
+          best_xcd = xl;
+          best_k = kp;
+          best_est = ec;
+        }
       }
     }
   }
