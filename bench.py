@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="bfs_cc_rmat22",
                     choices=["bfs_cc_rmat22", "pr_rmat16", "pr_rmat22", "sssp_grid", "selector",
-                             "batched", "prdelta_rmat22", "prec_rmat22"])
+                             "batched", "prdelta_rmat22", "prec_rmat22", "bc_rmat22"])
     ap.add_argument("--heldout", default="small", choices=["small", "full"],
                     help="selector workload: held-out Chung-Lu graph with 4M vertices (small) "
                          "or 41M vertices and ~1.4B edges (full)")
@@ -792,6 +792,67 @@ def run_prdelta(args, torch, dev):
     return value, "GTEPS", dt * 1e3 / args.steps, "f64", config, None, cpu, detail
 
 
+def run_bc(args, torch, dev):
+    """Single-source betweenness dependencies (Brandes: forward path counts,
+    backward dependencies) from 8 sources on R-MAT scale 22 (seed 2).  GTEPS
+    counts each reached edge twice per source (forward and backward sweep).
+    Algorithmic bytes per source: 16 n_r + 36 m_r (n_r, m_r: reached vertices
+    and their out-edges; forward 8 n_r + 16 m_r: offsets, ids, level test,
+    fp64 path-count add; backward 8 n_r + 20 m_r: offsets, ids, level test,
+    fp64 path count and dependency), over the GPU span of the run measured
+    with HIP events on its stream."""
+    import numpy as np
+
+    import graphgen as gg
+    el, g = make_rmat_graph(22, 2)
+    n = g.n
+    srcs = [int(x) for x in gg.pick_sources(el, 8, 9)]
+    dep = torch.empty(n, dtype=torch.float64, device=dev)
+    sig = torch.empty(n, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    odeg = np.diff(g.out_off).astype(np.int64)
+    reach = []
+    for s_ in srcs:
+        g.bc(s_, dep, sig)
+        sg = sig.cpu().numpy()
+        r = sg > 0
+        reach.append((int(r.sum()), int(odeg[r].sum())))
+    for _ in range(args.warmup):
+        for s_ in srcs:
+            g.bc(s_, dep, sig)
+    torch.cuda.synchronize()
+    tally = KernelTally("k_bc_forward + k_bc_advance + k_bc_backward (one source)")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for s_, (nr, mr) in zip(srcs, reach):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            g.bc(s_, dep, sig)
+            e1.record(stream)
+            e1.synchronize()
+            tally.add([e0.elapsed_time(e1)], [16 * nr + 36 * mr])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    edges = 2 * sum(mr for _, mr in reach)
+    value = edges / dt / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        og = oracle.Graph(el)
+        t0 = time.perf_counter()
+        oracle.bc(og, srcs[0])
+        dtc = time.perf_counter() - t0
+        cpu = {"value": round(2 * reach[0][1] / dtc / 1e9, 5), "unit": "GTEPS", "cores": 1,
+               "kind": "oracle", "sample": "fp64 Brandes dependencies from the first source, "
+                                           "full graph, one thread, %.2f s" % dtc}
+    detail = {"sources": srcs, "reached_vertices": [nr for nr, _ in reach],
+              "reached_edges": [mr for _, mr in reach],
+              "ms_per_source": round(dt * 1e3 / len(srcs), 3)}
+    config = {"workload": "bc8_rmat22_ef16", "n": n, "m": g.m}
+    return value, "GTEPS", dt * 1e3, "f64", config, tally.roofline(), cpu, detail
+
+
 def run_prec(args, torch, dev):
     """PageRank and eigenvector centrality, 20 iterations each, on R-MAT scale
     22 (seed 2): the fused pass (one traversal, (contribution, x) pairs)
@@ -881,6 +942,8 @@ def main():
         res = run_prdelta(args, torch, dev)
     elif args.workload == "prec_rmat22":
         res = run_prec(args, torch, dev)
+    elif args.workload == "bc_rmat22":
+        res = run_bc(args, torch, dev)
     elif args.workload == "batched":
         res = run_batched(args, torch, dev)
     elif args.workload == "selector":

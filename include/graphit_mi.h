@@ -270,9 +270,13 @@ gi_status gi_prdelta(gi_graph* g, int32_t rounds, double damping, double epsilon
  *   level[v] = level[w] - 1;
  *   dependency[v] = sum over v -> w with level[w] = level[v] + 1 of
  *   sigma[v] / sigma[w] * (1 + dependency[w]); dependency[s] = 0.
- * Forward levels are SparsePush with FP64 atomic adds; the trace records
- * each level's size.  Summing the dependencies of every source gives the
- * betweenness of every vertex.
+ * Forward levels choose their direction by the hybrid rule (section 2,
+ * with the schedule's divisor): SparsePush with FP64 atomic adds for small
+ * frontiers, DensePull (every unvisited vertex sums the path counts of its
+ * in-neighbours in the frontier, atomic-free) for large ones.  The backward
+ * sweep pulls: each vertex sums over its own out-row, atomic-free.  The
+ * trace records each level's direction, size and out-degree sum.  Summing
+ * the dependencies of every source gives the betweenness of every vertex.
  *   dependency  device out, n doubles (0 where unreachable).
  *   sigma       device out, n doubles, or NULL.
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */

@@ -807,6 +807,14 @@ __global__ void k_prd_init(PrdArgs a) {
 // level down: each vertex w of level L+1 sends (1 + delta[w]) / sigma[w] to
 // its in-neighbours at level L, which then set delta = sigma * the sum.
 
+// Degree sum of the next level, for its direction: kept in the control
+// block's sa_slots, which the frontier engine's compaction uses and
+// betweenness does not.
+__device__ __forceinline__ void bc_add_degrees(Control* c, const int32_t* outdeg, bool win, int v) {
+  const long long d = wave_sum((long long)(win ? outdeg[v] : 0));
+  if (__lane_id() == 0 && d != 0) atomicAdd((unsigned long long*)&c->sa_slots, (unsigned long long)d);
+}
+
 struct BcFwdVisit {
   const int32_t* idx;
   int32_t* level;
@@ -814,6 +822,8 @@ struct BcFwdVisit {
   int32_t* order;
   unsigned long long* count;
   int l1;
+  Control* ctl;
+  const int32_t* outdeg;
   __device__ __forceinline__ void operator()(int u, int e, bool valid) {
     int v = -1;
     bool win = false, add = false;
@@ -837,34 +847,155 @@ struct BcFwdVisit {
       if (__lane_id() == leader) base = atomicAdd(count, (unsigned long long)__popcll(m));
       base = __shfl(base, leader, kWave);
       if (win) order[base + __popcll(m & lanemask_lt())] = v;
+      bc_add_degrees(ctl, outdeg, win, v);
     }
   }
 };
 
-struct BcBwdVisit {
-  const int32_t* idx;
-  const int32_t* level;
-  const double* sigma;
-  const double* delta;
-  double* acc;
-  int lb;
-  __device__ __forceinline__ void operator()(int w, int e, bool valid) {
-    if (!valid) return;
-    const int v = idx[e];
-    if (level[v] == lb) atomicAdd(&acc[v], (1.0 + delta[w]) / sigma[w]);
-  }
-};
-
+// Push level (small frontiers): the listed vertices push their path counts
+// to the next level with FP64 atomic adds.
 template <int BT>
 __global__ __launch_bounds__(BT) void k_bc_forward(BcArgs a) {
   const Control* c = a.ctl;
-  if (c->done) return;
+  if (c->done || c->mode != MODE_SPARSE_PUSH) return;
   const int l1 = c->steps + 1;
-  BcFwdVisit vis{a.g.out_idx, a.level, a.sigma, a.order, &a.ctl->bc_count, l1};
+  BcFwdVisit vis{a.g.out_idx, a.level, a.sigma, a.order, &a.ctl->bc_count, l1, a.ctl,
+                 a.g.outdeg};
   push_list<BT>(a.order, (long long)c->bc_start, (long long)c->bc_end, a.g.out_off, vis);
 }
 
-// Close the level: log it, and either end the sweep or open the next level.
+// fs for a pull level: the previous level's entries are cleared, the
+// current level's set to their path counts (so fs is nonzero exactly on
+// the frontier).
+__global__ void k_bc_fs(BcArgs a, int clear_only) {
+  const Control* c = a.ctl;
+  if (c->done) return;
+  const long long prev = a.bounds[c->steps > 0 ? c->steps - 1 : 0];
+  const long long b = (long long)c->bc_start, e = (long long)c->bc_end;
+  const bool set = !clear_only && c->mode == MODE_DENSE_PULL;
+  for (long long i = prev + blockIdx.x * (long long)blockDim.x + threadIdx.x; i < e;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int u = a.order[i];
+    a.fs[u] = (i >= b && set) ? a.sigma[u] : 0.0;
+  }
+}
+
+// Pull level (large frontiers): every unvisited vertex sums fs over its
+// in-edges, atomic-free: destination blocks staged in LDS, rows summed by
+// LDS atomics (path counts are integers, exact in any order below 2^53).
+// A vertex with a nonzero sum joins the next level.  Hub rows are chunk
+// entries whose partial sums meet in sigma by FP64 atomics; the chunk that
+// first claims the level appends the vertex.
+template <int BT>
+__global__ __launch_bounds__(BT) void k_bc_forward_pull(BcArgs a) {
+  constexpr int kPer = (kCcCapV + 1 + BT - 1) / BT;
+  __shared__ double s_val[kCcCapE];
+  __shared__ double s_sum[kCcCapV];
+  __shared__ int s_off[kCcCapV + 1];
+  __shared__ double red[BT / kWave];
+  const Control* c = a.ctl;
+  if (c->done || c->mode != MODE_DENSE_PULL) return;
+  const int l1 = c->steps + 1, tid = threadIdx.x, lane = __lane_id();
+  (void)c;
+  const RowBlocks& rb = a.in_rows;
+  unsigned long long* count = &a.ctl->bc_count;
+  auto append = [&](bool win, int v) {
+    const unsigned long long m = __ballot(win);
+    if (m) {
+      const int leader = __ffsll((long long)m) - 1;
+      unsigned long long base = 0;
+      if (lane == leader) base = atomicAdd(count, (unsigned long long)__popcll(m));
+      base = __shfl(base, leader, kWave);
+      if (win) a.order[base + __popcll(m & lanemask_lt())] = v;
+      bc_add_degrees(a.ctl, a.g.outdeg, win, v);
+    }
+  };
+  for (int t = blockIdx.x; t < rb.ntab; t += gridDim.x) {
+    const int4 r = rb.table[t];
+    if (r.y < 0) {  // chunk of a hub row
+      const int v = r.x;
+      double sum = 0.0;
+      const int lv = a.level[v];  // unvisited, or claimed by another chunk of this level
+      if (lv < 0 || lv == l1)
+        for (int e = r.z + tid; e < r.w; e += BT) sum += a.fs[rb.idx[e]];
+      sum = wave_sum(sum);
+      if (lane == 0) red[tid / kWave] = sum;
+      __syncthreads();
+      bool win = false;
+      if (tid < kWave) {
+        double tot = 0.0;
+        if (tid == 0)
+          for (int i = 0; i < BT / kWave; ++i) tot += red[i];
+        if (tid == 0 && tot > 0.0) {
+          atomicAdd(&a.sigma[v], tot);
+          win = atomicCAS(&a.level[v], -1, l1) == -1;
+        }
+        append(win, v);
+      }
+      __syncthreads();
+      continue;
+    }
+    const int kb = r.x, ke = r.y, nr = ke - kb, e0 = r.z, ne = r.w - r.z;
+    int offv[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int k = tid + i * BT;
+      offv[i] = k <= nr ? rb.off[kb + k] : 0;
+    }
+    gather_block<BT, double>(rb.idx, e0, ne, s_val, [&](int u) { return a.fs[u]; });
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int k = tid + i * BT;
+      if (k <= nr) s_off[k] = offv[i] - e0;
+      if (k < nr) s_sum[k] = 0.0;
+    }
+    __syncthreads();
+    {
+      const int ept = (ne + BT - 1) / BT;
+      const int eb = tid * ept, ee = min(ne, eb + ept);
+      if (eb < ee) {
+        int lo = 0, hi = nr;  // s_off[lo] <= eb < s_off[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_off[mid] <= eb) lo = mid;
+          else hi = mid;
+        }
+        int k = lo, rend = s_off[k + 1];
+        double m = 0.0;
+        for (int j = eb; j < ee; ++j) {
+          while (j >= rend) {
+            if (m != 0.0) atomicAdd(&s_sum[k], m);
+            m = 0.0;
+            ++k;
+            rend = s_off[k + 1];
+          }
+          m += s_val[j];
+        }
+        if (m != 0.0) atomicAdd(&s_sum[k], m);
+      }
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < nr; k0 += BT) {
+      const int k = k0 + tid;
+      bool win = false;
+      int v = -1;
+      if (k < nr) {
+        v = kb + k;
+        const double sum = s_sum[k];
+        if (sum > 0.0 && a.level[v] < 0) {  // rows are this block's alone
+          a.level[v] = l1;
+          a.sigma[v] = sum;
+          win = true;
+        }
+      }
+      append(win, v);
+    }
+    __syncthreads();
+  }
+}
+
+// Close the level: log it, and either end the sweep or open the next level,
+// choosing its direction by the hybrid rule |F| + sum deg(F) > m / divisor.
 __global__ void k_bc_advance(BcArgs a) {
   Control* c = a.ctl;
   if (c->done) return;
@@ -872,7 +1003,8 @@ __global__ void k_bc_advance(BcArgs a) {
   const unsigned long long cnt = __hip_atomic_load(&c->bc_count, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT);
   if (k < kMaxLog)
-    c->host->log[k] = StepLog{GI_DIR_SPARSE_PUSH, (int)(c->bc_end - c->bc_start), 0, 0};
+    c->host->log[k] = StepLog{c->mode, (int)(c->bc_end - c->bc_start), c->dsum, 0};
+  if (c->mode != MODE_SPARSE_PUSH) c->dense_steps++;
   c->steps = k + 1;
   a.bounds[k + 1] = c->bc_end;
   if (cnt == c->bc_end) {
@@ -881,23 +1013,96 @@ __global__ void k_bc_advance(BcArgs a) {
   } else {
     c->bc_start = c->bc_end;
     c->bc_end = cnt;
+    const long long nf = (long long)(cnt - c->bc_start);
+    c->dsum = c->sa_slots;
+    c->sa_slots = 0;
+    c->mode = hybrid_dense(nf, c->dsum, a.g.m, a.divisor) ? MODE_DENSE_PULL : MODE_SPARSE_PUSH;
   }
+}
+
+// Backward, level L (deepest first), atomic-free: each vertex u of the level
+// sums bw[w] over its out-neighbours w on level L+1 (its successors on
+// shortest paths), delta[u] = sigma[u] * sum, and publishes
+// bw[u] = (1 + delta[u]) / sigma[u] for level L-1.  A workgroup takes BT
+// listed vertices; their out-rows are concatenated (a prefix sum of the
+// degrees) and walked BT edges per round, each thread adding into its row's
+// LDS sum, so a hub row is shared by the whole workgroup.
+// Backward, level L (deepest first), atomic-free: each vertex u of the level
+// sums bw[w] over its out-neighbours w on level L+1 (its successors on
+// shortest paths), delta[u] = sigma[u] * sum, and publishes
+// bw[u] = (1 + delta[u]) / sigma[u] for level L-1.  Rows are binned by
+// out-degree: up to kBcSmall edges one thread per vertex, up to kHubDeg one
+// wave, longer ones the whole workgroup; each bin's kernel walks the whole
+// level list and takes its own vertices (a level of at most 64K vertices
+// uses the workgroup kernel for all).
+constexpr int kBcSmall = 32;
+
+__device__ __forceinline__ void bc_finish_vertex(const BcArgs& a, int u, double sum) {
+  const double dl = u == a.src ? 0.0 : a.sigma[u] * sum;
+  a.delta[u] = dl;
+  a.bw[u] = (1.0 + dl) / a.sigma[u];
+}
+
+__device__ __forceinline__ double bc_succ(const BcArgs& a, int w, int L) {
+  const int lw = a.level[w];
+  const double c = a.bw[w];
+  return lw == L + 1 ? c : 0.0;
 }
 
 template <int BT>
-__global__ __launch_bounds__(BT) void k_bc_backward(BcArgs a, long long nb, long long ne, int lb) {
-  BcBwdVisit vis{a.g.in_idx, a.level, a.sigma, a.delta, a.acc, lb};
-  push_list<BT>(a.order, nb, ne, a.g.in_off, vis);
-}
-
-__global__ void k_bc_finish(BcArgs a, long long b, long long e) {
-  for (long long i = b + blockIdx.x * (long long)blockDim.x + threadIdx.x; i < e;
-       i += (long long)gridDim.x * blockDim.x) {
-    const int v = a.order[i];
-    a.delta[v] = v == a.src ? 0.0 : a.sigma[v] * a.acc[v];
-    a.acc[v] = 0.0;
+__global__ __launch_bounds__(BT) void k_bc_backward_wg(BcArgs a, long long b, long long e, int L,
+                                                       int min_deg) {
+  for (long long i = b + blockIdx.x; i < e; i += gridDim.x) {
+    const int u = a.order[i];
+    const int rb = a.g.out_off[u], re = a.g.out_off[u + 1];
+    if (re - rb < min_deg) continue;  // workgroup-uniform
+    double sum = 0.0, sum2 = 0.0;
+    int j = rb + (int)threadIdx.x;
+    for (; j + BT < re; j += 2 * BT) {
+      const int w0 = a.g.out_idx[j], w1 = a.g.out_idx[j + BT];
+      sum += bc_succ(a, w0, L);
+      sum2 += bc_succ(a, w1, L);
+    }
+    if (j < re) sum += bc_succ(a, a.g.out_idx[j], L);
+    const double tot = block_sum<BT>(sum + sum2);
+    if (threadIdx.x == 0) bc_finish_vertex(a, u, tot);
   }
 }
+
+__global__ __launch_bounds__(256) void k_bc_backward_wave(BcArgs a, long long b, long long e,
+                                                          int L) {
+  const int lane = __lane_id();
+  const long long wave = (long long)(blockIdx.x * 256 + threadIdx.x) / kWave;
+  const long long nw = (long long)gridDim.x * (256 / kWave);
+  for (long long i = b + wave; i < e; i += nw) {
+    const int u = a.order[i];
+    const int rb = a.g.out_off[u], re = a.g.out_off[u + 1];
+    if (re - rb <= kBcSmall || re - rb > kHubDeg) continue;  // wave-uniform
+    double sum = 0.0;
+    for (int j = rb + lane; j < re; j += kWave) sum += bc_succ(a, a.g.out_idx[j], L);
+    sum = wave_sum(sum);
+    if (lane == 0) bc_finish_vertex(a, u, sum);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bc_backward_thread(BcArgs a, long long b, long long e,
+                                                            int L) {
+  for (long long i = b + blockIdx.x * 256LL + threadIdx.x; i < e; i += gridDim.x * 256LL) {
+    const int u = a.order[i];
+    const int rb = a.g.out_off[u], re = a.g.out_off[u + 1];
+    if (re - rb > kBcSmall) continue;
+    double s0 = 0.0, s1 = 0.0;
+    int j = rb;
+    for (; j + 1 < re; j += 2) {
+      const int w0 = a.g.out_idx[j], w1 = a.g.out_idx[j + 1];
+      s0 += bc_succ(a, w0, L);
+      s1 += bc_succ(a, w1, L);
+    }
+    if (j < re) s0 += bc_succ(a, a.g.out_idx[j], L);
+    bc_finish_vertex(a, u, s0 + s1);
+  }
+}
+
 
 __global__ void k_bc_init(BcArgs a) {
   const int n = a.g.n;
@@ -906,7 +1111,7 @@ __global__ void k_bc_init(BcArgs a) {
     const bool s = v == a.src;
     a.level[v] = s ? 0 : -1;
     a.sigma[v] = s ? 1.0 : 0.0;
-    a.acc[v] = 0.0;
+    a.fs[v] = 0.0;
     a.delta[v] = 0.0;
   }
   if (tid == 0) {
@@ -915,6 +1120,9 @@ __global__ void k_bc_init(BcArgs a) {
     a.ctl->bc_start = 0;
     a.ctl->bc_end = 1;
     a.ctl->bc_count = 1;
+    a.ctl->mode = MODE_SPARSE_PUSH;
+    a.ctl->dsum = a.g.outdeg[a.src];
+    a.ctl->sa_slots = 0;
   }
 }
 
@@ -1094,21 +1302,29 @@ int launch_bc_init(const BcArgs& a, hipStream_t s) {
 
 int enqueue_bc_forward(const BcArgs& a, const StepEvents* te, hipStream_t s) {
   mark(te, 0, s);
+  hipLaunchKernelGGL(k_bc_fs, dim3(512), dim3(256), 0, s, a, 0);
   mark(te, 1, s);
   hipLaunchKernelGGL(k_bc_forward<kBT>, dim3(kParts), dim3(kBT), 0, s, a);
+  hipLaunchKernelGGL(k_bc_forward_pull<kBT>, dim3(kParts), dim3(kBT), 0, s, a);
   hipLaunchKernelGGL(k_bc_advance, dim3(1), dim3(1), 0, s, a);
   mark(te, 2, s);
   return GI_OK_LAUNCH();
 }
 
-int enqueue_bc_backward_level(const BcArgs& a, long long next_begin, long long next_end,
-                              long long begin, long long end, int level, hipStream_t s) {
-  const long long items = next_end - next_begin;
-  const int blocks = (int)std::max<long long>(1, std::min<long long>(kParts, (items + kBT - 1) / kBT));
-  hipLaunchKernelGGL(k_bc_backward<kBT>, dim3(blocks), dim3(kBT), 0, s, a, next_begin, next_end,
-                     level);
-  const int fb = (int)std::max<long long>(1, std::min<long long>(2048, (end - begin + 255) / 256));
-  hipLaunchKernelGGL(k_bc_finish, dim3(fb), dim3(256), 0, s, a, begin, end);
+int enqueue_bc_backward_level(const BcArgs& a, long long begin, long long end, int level,
+                              hipStream_t s) {
+  const long long items = end - begin;
+  if (items <= 65536) {
+    const int blocks = (int)std::max<long long>(1, std::min<long long>(8192, items));
+    hipLaunchKernelGGL(k_bc_backward_wg<kBT>, dim3(blocks), dim3(kBT), 0, s, a, begin, end, level,
+                       0);
+  } else {
+    const int tb = (int)std::min<long long>(4096, (items + 255) / 256);
+    hipLaunchKernelGGL(k_bc_backward_thread, dim3(tb), dim3(256), 0, s, a, begin, end, level);
+    hipLaunchKernelGGL(k_bc_backward_wave, dim3(4096), dim3(256), 0, s, a, begin, end, level);
+    hipLaunchKernelGGL(k_bc_backward_wg<kBT>, dim3(2048), dim3(kBT), 0, s, a, begin, end, level,
+                       kHubDeg + 1);
+  }
   return GI_OK_LAUNCH();
 }
 

@@ -128,7 +128,9 @@ struct gi_graph {
   std::vector<StepEvents> tev;
   int tev_count = 0;        // steps of the last run that carry events
   int last_steps[6] = {0, 0, 0, 0, 0, 0};  // steps of the previous run, per algorithm
-  void* bc = nullptr;  // betweenness scratch: level, sigma, acc, order, bounds
+  void* bc = nullptr;  // betweenness scratch: sigma, fs, bw, bounds, level, order
+  int4* bc_tab = nullptr;  // in-row blocks for the betweenness pull levels
+  int bc_ntab = 0;
   int4* prec_tab = nullptr;  // in-row blocks for PageRank + eigenvector
   int prec_ntab = 0;
   int32_t* prec_lrow = nullptr;  // long rows (chunked) and their FP64 sum slots
@@ -1445,41 +1447,50 @@ extern "C" gi_status gi_bc(gi_graph* g, int32_t src, double* dependency, double*
   if (src < 0 || src >= g->n) return fail(GI_ERR_INVALID_ARG, "source %d outside [0, %d)", src, g->n);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t N = (size_t)g->n;
-  // level int32[n], sigma double[n], acc double[n], order int32[n], bounds u64[n + 2]
-  const size_t bytes = 4 * N + 8 * N + 8 * N + 4 * N + 8 * (N + 2);
+  // sigma, fs, bw double[n]; bounds u64[n + 2]; level, order int32[n]
+  const size_t bytes = 8 * 3 * N + 8 * (N + 2) + 4 * 2 * N;
   gi_status st;
   if (!g->bc) {
     uint8_t* p = nullptr;
     if ((st = dev_alloc(g, g->allocs, &p, bytes)) != GI_OK) return st;
     g->bc = p;
+    std::vector<int4> tab = make_cc_table(g->h_in_off.data(), g->n, kCcCapE, kCcCapV);
+    if ((st = dev_alloc(g, g->allocs, &g->bc_tab, std::max<size_t>(1, tab.size()))) != GI_OK)
+      return st;
+    if (!tab.empty() && (st = upload(tab.data(), g->bc_tab, tab.size() * sizeof(int4))) != GI_OK)
+      return st;
+    g->bc_ntab = (int)tab.size();
   }
   uint8_t* base = static_cast<uint8_t*>(g->bc);
   BcArgs a;
   a.g = dev_graph(g);
   a.src = src;
   a.sigma = reinterpret_cast<double*>(base);
-  a.acc = reinterpret_cast<double*>(base + 8 * N);
-  a.bounds = reinterpret_cast<unsigned long long*>(base + 16 * N);
-  a.level = reinterpret_cast<int32_t*>(base + 16 * N + 8 * (N + 2));
-  a.order = reinterpret_cast<int32_t*>(base + 20 * N + 8 * (N + 2));
+  a.fs = reinterpret_cast<double*>(base + 8 * N);
+  a.bw = reinterpret_cast<double*>(base + 16 * N);
+  a.bounds = reinterpret_cast<unsigned long long*>(base + 24 * N);
+  a.level = reinterpret_cast<int32_t*>(base + 24 * N + 8 * (N + 2));
+  a.order = reinterpret_cast<int32_t*>(base + 28 * N + 8 * (N + 2));
   if (sigma) a.sigma = sigma;
   a.delta = dependency;
+  a.in_rows = RowBlocks{g->bc_tab, g->bc_ntab, g->in_off, g->in_idx};
+  a.divisor = g->sched.hybrid_divisor;
   a.ctl = g->ctl;
   if ((st = start_run(g, 0, s)) != GI_OK) return st;
   LAUNCH_TRY(launch_bc_init(a, s));
   st = run_frontier_loop(
       g, s, ALG_BC, 8, (long long)g->n + 2,
-      [&](long long k) { return enqueue_bc_forward(a, step_events(g, k), s) ? -1 : 2; },
+      [&](long long k) { return enqueue_bc_forward(a, step_events(g, k), s) ? -1 : 4; },
       "betweenness");
   if (st != GI_OK) return st;
   if ((st = read_loop_stats(g, ALG_BC)) != GI_OK) return st;
   const int levels = ((const volatile HostFlags*)g->hflags)->steps;
   std::vector<unsigned long long> bd((size_t)levels + 1);
   HIP_TRY(hipMemcpy(bd.data(), a.bounds, 8 * bd.size(), hipMemcpyDeviceToHost));
-  for (int L = levels - 2; L >= 0; --L) {
-    LAUNCH_TRY(enqueue_bc_backward_level(a, (long long)bd[(size_t)L + 1], (long long)bd[(size_t)L + 2],
-                                         (long long)bd[(size_t)L], (long long)bd[(size_t)L + 1], L, s));
-  }
+  // deepest level first: each level's dependencies come from the next one's
+  for (int L = levels - 1; L >= 0; --L)
+    LAUNCH_TRY(enqueue_bc_backward_level(a, (long long)bd[(size_t)L], (long long)bd[(size_t)L + 1],
+                                         L, s));
   HIP_TRY(hipStreamSynchronize(s));
   return GI_OK;
 }

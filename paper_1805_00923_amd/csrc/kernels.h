@@ -166,16 +166,19 @@ struct BcArgs {
   int src;
   int32_t* level;
   double* sigma;   // shortest-path counts
-  double* acc;     // backward partial sums (zero between levels)
+  double* fs;      // sigma of the current frontier's vertices, 0 elsewhere (pull levels)
+  double* bw;      // (1 + delta[w]) / sigma[w], set when w's dependency is final
   double* delta;   // dependencies (output)
   int32_t* order;  // vertices in discovery order, grouped by level
   unsigned long long* bounds;  // bounds[k] = first list index of level k (k <= levels)
+  RowBlocks in_rows;  // in-row blocks (hub rows as chunks) for the pull levels
+  int divisor;     // pull when |F| * divisor * (m / n) > m
   Control* ctl;
 };
 int launch_bc_init(const BcArgs& a, hipStream_t s);
 int enqueue_bc_forward(const BcArgs& a, const StepEvents* te, hipStream_t s);
-int enqueue_bc_backward_level(const BcArgs& a, long long next_begin, long long next_end,
-                              long long begin, long long end, int level, hipStream_t s);
+int enqueue_bc_backward_level(const BcArgs& a, long long begin, long long end, int level,
+                              hipStream_t s);
 int enqueue_prd_step(const Engine& e, const FrontierArgs& f, const DecideArgs& d,
                      const PrdArgs& a, const StepEvents* te, hipStream_t s);
 
