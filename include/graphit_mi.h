@@ -343,7 +343,7 @@ gi_status gi_get_step_times(const gi_graph* g, float* step_ms, float* main_ms, i
 #define GI_SEL_SCHEDULES 4
 #define GI_SEL_PARAMS 5252
 
-enum { GI_ALG_PAGERANK = 0, GI_ALG_BFS = 1, GI_ALG_CC = 2 };
+enum { GI_ALG_PAGERANK = 0, GI_ALG_BFS = 1, GI_ALG_CC = 2, GI_ALG_SSSP = 3 };
 
 typedef struct gi_selector gi_selector;
 
@@ -407,7 +407,7 @@ gi_status gi_trace_exhaustive(gi_graph* g, int32_t algorithm, int32_t src, float
                               float* step_ms, uint8_t* valid, int32_t cap, int32_t* count);
 
 /* ---- batched persistent execution -------------------------------------- */
-/* Many BFS and PageRank instances over graphs of uneven size in one
+/* Many BFS, PageRank and SSSP instances over graphs of uneven size in one
  * persistent kernel launch (optionally replayed as a HIP graph).  Each task
  * runs on its own set of workgroups that meet at task-local barriers between
  * BFS levels and PageRank iterations, so no step costs a kernel launch and
@@ -416,20 +416,26 @@ gi_status gi_trace_exhaustive(gi_graph* g, int32_t algorithm, int32_t src, float
  * 20 and produce levels (and parents when asked); PageRank tasks use the DensePull
  * destination-block kernel with the graph's current block size.  Results
  * equal the plain entry points' (levels bit for bit; ranks within the
- * PageRank tolerance).  A barrier that waits more than two seconds fails
- * the batch (GI_ERR_DEVICE) instead of hanging. */
+ * PageRank tolerance).  SSSP tasks run delta-stepping (near/far buckets,
+ * as gi_sssp) with a task barrier per phase; distances equal gi_sssp's bit
+ * for bit (they are unique).  A barrier that waits more than two seconds
+ * fails the batch (GI_ERR_DEVICE) instead of hanging; a distance reaching
+ * UINT32_MAX fails it with GI_ERR_OVERFLOW. */
 typedef struct gi_task {
   int32_t graph;      /* index into the batch's graphs                          */
-  int32_t algorithm;  /* GI_ALG_BFS or GI_ALG_PAGERANK                          */
-  int32_t src;        /* BFS source                                             */
+  int32_t algorithm;  /* GI_ALG_BFS, GI_ALG_PAGERANK or GI_ALG_SSSP             */
+  int32_t src;        /* BFS / SSSP source                                      */
   int32_t iters;      /* PageRank iterations (>= 0)                             */
   float damping;      /* PageRank damping in [0, 1]                             */
   int32_t workgroups; /* workgroups of this task, 1..1024; 0 = the plan's choice
                          (a size rule at creation, then gi_batch_autotune)      */
   void* out;          /* device out, n entries: int32 levels (-1 unreachable)
-                         for BFS, float ranks for PageRank; kept by the caller  */
+                         for BFS, float ranks for PageRank, uint32 distances
+                         (UINT32_MAX unreachable) for SSSP; kept by the caller  */
   void* parent;       /* BFS only, may be NULL: device out, n int32 parents
                          (parent[src] = src, -1 unreachable; any BFS tree)      */
+  uint32_t sssp_delta; /* SSSP bucket width; 0 = the graph's schedule value
+                         (sssp_delta, else 512).  SSSP needs a weighted graph  */
 } gi_task;
 
 typedef struct gi_batch gi_batch;
@@ -445,7 +451,7 @@ gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, const gi_tas
 
 /* Autotuner, for each workgroup size of 256, 512 and 1024 threads (only the
  * pinned one after gi_batch_set_threads): times each (graph, algorithm)
- * class alone on 1, 2, 4, ... 64 workgroups (median of reps launches),
+ * class alone on 1, 2, 4, ... 256 workgroups (median of reps launches),
  * keeps the size with the least workgroup-time unless it is more than twice
  * as slow as the fastest, gives tasks longer than the balanced share of the
  * grid their fastest size, caps those sizes at 64, 32 and 16, plans each

@@ -40,6 +40,7 @@ DIRECTIONS = {
 ALG_PAGERANK = 0
 ALG_BFS = 1
 ALG_CC = 2
+ALG_SSSP = 3
 SEL_FEATURES = 12
 SEL_SCHEDULES = 4
 SEL_PARAMS = 5252
@@ -475,15 +476,16 @@ class Task(ctypes.Structure):
     _fields_ = [("graph", ctypes.c_int32), ("algorithm", ctypes.c_int32), ("src", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("damping", ctypes.c_float),
                 ("workgroups", ctypes.c_int32), ("out", ctypes.c_void_p),
-                ("parent", ctypes.c_void_p)]
+                ("parent", ctypes.c_void_p), ("sssp_delta", ctypes.c_uint32)]
 
 
 class Batch:
-    """Batched persistent execution of BFS / PageRank tasks.
+    """Batched persistent execution of BFS / PageRank / SSSP tasks.
 
-    tasks: sequence of dicts with keys graph (index), algorithm (ALG_BFS or
-    ALG_PAGERANK), out (device tensor of n int32 or float32), and src /
-    iters / damping / workgroups as needed."""
+    tasks: sequence of dicts with keys graph (index), algorithm (ALG_BFS,
+    ALG_PAGERANK or ALG_SSSP), out (device tensor of n int32, float32 or
+    int32-as-uint32 distances), and src / iters / damping / workgroups /
+    parent / sssp_delta as needed."""
 
     def __init__(self, graphs, tasks):
         self.graphs = list(graphs)
@@ -492,7 +494,8 @@ class Batch:
         for i, t in enumerate(tasks):
             arr[i] = Task(int(t["graph"]), int(t["algorithm"]), int(t.get("src", 0)),
                           int(t.get("iters", 20)), float(t.get("damping", 0.85)),
-                          int(t.get("workgroups", 0)), _dptr(t["out"]), _dptr(t.get("parent")))
+                          int(t.get("workgroups", 0)), _dptr(t["out"]), _dptr(t.get("parent")),
+                          int(t.get("sssp_delta", 0)))
         hs = (ctypes.c_void_p * len(self.graphs))(*[g._h.value for g in self.graphs])
         self._h = ctypes.c_void_p(None)
         self.ntasks = len(tasks)

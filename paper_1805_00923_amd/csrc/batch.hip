@@ -20,6 +20,9 @@
 // nor written in it.
 // PageRank tasks: the destination-block DensePull of pagerank.hip, blocks
 // dealt round-robin over the task's workgroups.
+// SSSP tasks: delta-stepping in the near/far form of the frontier engine
+// (relax the near set; when it empties, move the far members of the next
+// bucket into it), with task barriers in place of kernel launches.
 //
 // The kernel comes in three workgroup sizes (256, 512 and 1024 threads).
 // Every workgroup that passes a barrier invalidates its L2 (agent-scope
@@ -188,6 +191,173 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
   }
 }
 
+
+// Relaxation of a batch SSSP phase: push with weights, the improved vertex
+// goes to the next near set when its new distance is inside the bucket,
+// else to the far set; insertions are counted for the phase totals.
+struct BatchSsspVisit {
+  const int32_t* idx;
+  const uint32_t* w;
+  uint32_t* dist;
+  DenseSet near;
+  DenseSet far;
+  unsigned long long thresh;
+  int* overflow;
+  long long near_new = 0, far_new = 0;
+  __device__ __forceinline__ void operator()(int u, int e, bool valid) {
+    if (!valid) return;
+    const int v = idx[e];
+    const unsigned long long nd = (unsigned long long)dist[u] + (unsigned long long)w[e];
+    if (nd >= 0xFFFFFFFFull) {
+      __hip_atomic_store(overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    if ((uint32_t)nd >= dist[v]) return;
+    const uint32_t old = atomicMin(&dist[v], (uint32_t)nd);
+    if ((uint32_t)nd >= old) return;
+    if (nd < thresh) {
+      if (near.insert(v)) ++near_new;
+    } else if (far.insert(v)) {
+      ++far_new;
+    }
+  }
+};
+
+template <int BT>
+__device__ void sssp_task(const BatchGraph& G, const BatchTask& t, int r, const BatchArgs& a,
+                          int* lds) {
+  const int n = G.n, k = t.k, W = (n + 63) >> 6, tid = threadIdx.x;
+  uint32_t* dist = static_cast<uint32_t*>(t.out);
+  TaskCtl* c = t.ctl;
+  uint64_t* bv[3] = {t.bv0, t.bv1, t.bv2};
+  uint64_t* far = t.vis;
+  const unsigned long long delta = t.delta;
+  const int w0 = (int)((long long)W * r / k), w1 = (int)((long long)W * (r + 1) / k);
+  const int v0 = w0 * 64, v1 = min(n, w1 * 64);
+  for (int v = v0 + tid; v < v1; v += BT) dist[v] = 0xFFFFFFFFu;
+  for (int w = w0 + tid; w < w1; w += BT) {
+    far[w] = 0ull;
+    t.bv0[w] = 0ull;
+    t.bv1[w] = 0ull;
+    t.bv2[w] = 0ull;
+  }
+  if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+  if (r == 0 && tid == 0) {
+    dist[t.src] = 0u;
+    t.bv0[t.src >> 6] = 1ull << (t.src & 63);
+    c->qn[0] = 1;
+    c->thresh = delta;
+  }
+  if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+  __shared__ unsigned long long s_red[BT / kWave];
+  int P = 0;
+  for (;; ++P) {
+    const long long nf = (long long)__hip_atomic_load(&c->qn[P % 3], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long fc = __hip_atomic_load(&c->farc[P % 3], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long th = __hip_atomic_load(&c->thresh, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+    if (__hip_atomic_load(&c->overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      if (r == 0 && tid == 0) __hip_atomic_store(a.error, 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    if (nf == 0 && fc == 0) break;  // task-uniform: read after the same barrier by all
+    if (P > 2 * n + 2) {            // more phases than possible: a broken invariant
+      if (tid == 0) __hip_atomic_store(a.error, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    if (r == 0 && tid == 0) {
+      c->qn[(P + 2) % 3] = 0;
+      c->farc[(P + 2) % 3] = 0;
+      if (a.trace_cap > P) {
+        long long* rec = a.trace + ((size_t)t.id * a.trace_cap + P) * 2;
+        rec[0] = wall_ticks();
+        rec[1] = nf;
+      }
+    }
+    uint64_t* cur = bv[P % 3];
+    uint64_t* nxt = bv[(P + 1) % 3];
+    for (int w = w0 + tid; w < w1; w += BT) bv[(P + 2) % 3][w] = 0ull;
+    if (nf > 0) {
+      // relax the near set
+      if (r == 0 && tid == 0) {
+        c->fmin = ~0ull;
+        if (fc) atomicAdd(&c->farc[(P + 1) % 3], fc);  // far members carry over
+      }
+      BatchSsspVisit vis{G.out_idx, G.out_w, dist, DenseSet{nxt, nullptr},
+                         DenseSet{far, nullptr}, th, &c->overflow};
+      push_words<BT>(cur, w0, w1, n, G.out_off, vis, 0x7fffffff, lds);
+      const Part p = block_sum4<BT>(Part{vis.near_new, vis.far_new, 0, 0});
+      if (tid == 0) {
+        if (p.a) atomicAdd(&c->qn[(P + 1) % 3], (unsigned long long)p.a);
+        if (p.b) atomicAdd(&c->farc[(P + 1) % 3], (unsigned long long)p.b);
+      }
+      if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+      continue;
+    }
+    // split: the next bucket starts at the smallest far distance at or
+    // beyond the threshold
+    unsigned long long mn = ~0ull;
+    for (int w = w0 + tid; w < w1; w += BT) {
+      uint64_t x = far[w];
+      while (x) {
+        const int v = (w << 6) + __ffsll((long long)x) - 1;
+        x &= x - 1;
+        const unsigned long long d = dist[v];
+        if (d >= th && d < mn) mn = d;
+      }
+    }
+    mn = wave_min(mn);
+    if (__lane_id() == 0) s_red[tid / kWave] = mn;
+    __syncthreads();
+    if (tid == 0) {
+      for (int i = 0; i < BT / kWave; ++i) mn = s_red[i] < mn ? s_red[i] : mn;
+      if (mn != ~0ull) atomicMin(&c->fmin, mn);
+    }
+    if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+    const unsigned long long fm = __hip_atomic_load(&c->fmin, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long tnew = fm == ~0ull ? th : (fm / delta + 1ull) * delta;
+    long long moved = 0, kept = 0;
+    for (int w = w0 + tid; w < w1; w += BT) {
+      uint64_t x = far[w], keep = 0ull, mv = 0ull;
+      while (x) {
+        const int b = __ffsll((long long)x) - 1;
+        x &= x - 1;
+        const unsigned long long d = dist[(w << 6) + b];
+        if (d < th) continue;  // stale: relaxed in an earlier bucket
+        if (d < tnew) {
+          mv |= 1ull << b;
+          ++moved;
+        } else {
+          keep |= 1ull << b;
+          ++kept;
+        }
+      }
+      far[w] = keep;
+      nxt[w] = mv;  // this workgroup's words; cleared two phases ago
+    }
+    const Part p = block_sum4<BT>(Part{moved, kept, 0, 0});
+    if (tid == 0) {
+      if (p.a) atomicAdd(&c->qn[(P + 1) % 3], (unsigned long long)p.a);
+      if (p.b) atomicAdd(&c->farc[(P + 1) % 3], (unsigned long long)p.b);
+    }
+    // every workgroup has read the old threshold (it read fmin after the
+    // barrier above); rank 0 publishes the new one for the next phase
+    if (r == 0 && tid == 0) c->thresh = tnew;
+    if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+  }
+  if (r == 0 && tid == 0) {
+    c->levels = P;
+    if (P < a.trace_cap) {
+      long long* rec = a.trace + ((size_t)t.id * a.trace_cap + P) * 2;
+      rec[0] = wall_ticks();
+      rec[1] = 0;
+    }
+  }
+}
+
 template <int BT>
 __device__ void pr_task(const BatchGraph& G, const BatchTask& t, int r, const BatchArgs& a,
                         float* lds_val, int* lds_off) {
@@ -244,6 +414,7 @@ __global__ __launch_bounds__(BT, batch_min_waves<BT>()) void k_batch(BatchArgs a
     const BatchGraph& G = a.graphs[t.graph];
     if (it.y == 0 && threadIdx.x == 0) t.ctl->t_begin = wall_ticks();
     if (t.alg == ALG_BFS) bfs_task<BT>(G, t, it.y, a, reinterpret_cast<int*>(smem));
+    else if (t.alg == ALG_SSSP) sssp_task<BT>(G, t, it.y, a, reinterpret_cast<int*>(smem));
     else pr_task<BT>(G, t, it.y, a, lds_val, lds_off);
     if (it.y == 0 && threadIdx.x == 0) t.ctl->t_end = wall_ticks();
   }

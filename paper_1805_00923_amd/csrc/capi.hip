@@ -2168,6 +2168,7 @@ static BatchGraph batch_graph(const gi_graph* g) {
   d.in_off = g->in_off;
   d.in_idx = g->in_idx;
   d.outdeg = g->outdeg;
+  d.out_w = g->out_w;
   d.in_probe = g->in_probe;
   d.hubs = g->hubs;
   d.nhubs = g->nhubs;
@@ -2283,12 +2284,14 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
   for (int i = 0; i < ntasks; ++i) {
     const gi_task& t = tasks[i];
     if (t.graph < 0 || t.graph >= ngraphs) return fail(GI_ERR_INVALID_ARG, "task %d: bad graph", i);
-    if (t.algorithm != GI_ALG_BFS && t.algorithm != GI_ALG_PAGERANK)
-      return fail(GI_ERR_INVALID_ARG, "task %d: algorithm must be BFS or PageRank", i);
+    if (t.algorithm != GI_ALG_BFS && t.algorithm != GI_ALG_PAGERANK && t.algorithm != GI_ALG_SSSP)
+      return fail(GI_ERR_INVALID_ARG, "task %d: algorithm must be BFS, PageRank or SSSP", i);
     if (!t.out) return fail(GI_ERR_INVALID_ARG, "task %d: NULL output", i);
     const gi_graph* g = graphs[t.graph];
-    if (t.algorithm == GI_ALG_BFS && (t.src < 0 || t.src >= g->n))
+    if ((t.algorithm == GI_ALG_BFS || t.algorithm == GI_ALG_SSSP) && (t.src < 0 || t.src >= g->n))
       return fail(GI_ERR_INVALID_ARG, "task %d: source outside the graph", i);
+    if (t.algorithm == GI_ALG_SSSP && !g->weighted)
+      return fail(GI_ERR_INVALID_ARG, "task %d: SSSP needs a weighted graph", i);
     if (t.algorithm == GI_ALG_PAGERANK &&
         (t.iters < 0 || !(t.damping >= 0.0f && t.damping <= 1.0f)))
       return fail(GI_ERR_INVALID_ARG, "task %d: bad PageRank parameters", i);
@@ -2331,7 +2334,9 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
     BatchTask& d = b->h_tasks[i];
     d = BatchTask{};
     d.id = (int)i;
-    d.alg = t.algorithm == GI_ALG_BFS ? ALG_BFS : ALG_PR;
+    d.alg = t.algorithm == GI_ALG_BFS ? ALG_BFS : t.algorithm == GI_ALG_SSSP ? ALG_SSSP : ALG_PR;
+    d.delta = t.sssp_delta > 0 ? t.sssp_delta
+                               : (g->sched.sssp_delta > 0 ? g->sched.sssp_delta : 512u);
     d.graph = t.graph;
     d.src = t.src;
     d.iters = t.iters;
@@ -2339,7 +2344,7 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
     d.out = t.out;
     d.parent = t.algorithm == GI_ALG_BFS ? static_cast<int32_t*>(t.parent) : nullptr;
     const size_t W = ((size_t)g->n + 63) / 64;
-    if (d.alg == ALG_BFS) {
+    if (d.alg == ALG_BFS || d.alg == ALG_SSSP) {
       if ((st = batch_alloc(b, &d.vis, 4 * W)) != GI_OK) return bail(st);
       d.bv0 = d.vis + W;
       d.bv1 = d.vis + 2 * W;
@@ -2413,7 +2418,8 @@ static gi_status batch_check_error(gi_batch* b) {
   int err = 0;
   HIP_TRY(hipMemcpy(&err, b->d_err, sizeof(int), hipMemcpyDeviceToHost));
   if (err == 1) return fail(GI_ERR_DEVICE, "batch barrier wait timed out");
-  if (err) return fail(GI_ERR_DEVICE, "batch BFS exceeded n levels");
+  if (err == 3) return fail(GI_ERR_OVERFLOW, "batch SSSP: a distance reached UINT32_MAX");
+  if (err) return fail(GI_ERR_DEVICE, "batch task exceeded its step bound");
   return GI_OK;
 }
 
@@ -2534,7 +2540,9 @@ static gi_status batch_tune_sizes(gi_batch* b, int32_t reps) {
     for (int q : reps_list) {
       const gi_task& y = b->tasks[(size_t)q];
       if (x.graph == y.graph && x.algorithm == y.algorithm &&
-          (x.algorithm == GI_ALG_BFS || x.iters == y.iters)) {
+          (x.algorithm == GI_ALG_BFS ||
+           (x.algorithm == GI_ALG_SSSP && x.sssp_delta == y.sssp_delta) ||
+           (x.algorithm == GI_ALG_PAGERANK && x.iters == y.iters))) {
         rep_of[(size_t)t] = q;
         break;
       }
@@ -2549,7 +2557,7 @@ static gi_status batch_tune_sizes(gi_batch* b, int32_t reps) {
   for (int q : reps_list) {
     double bw = 1e300, bt = 0.0, ft = 1e300;
     int bk = 1, fk = 1;
-    for (int k = 1; k <= std::min(64, b->max_grid); k *= 2) {
+    for (int k = 1; k <= std::min(256, b->max_grid); k *= 2) {
       float ms = 0.0f;
       if ((st = batch_time_task(b, q, k, reps, &ms)) != GI_OK) return st;
       // least workgroup-time (throughput), unless more than twice as slow as the fastest
@@ -2639,10 +2647,10 @@ extern "C" gi_status gi_batch_autotune(gi_batch* b, int32_t reps) {
     // the size rule picks per class in isolation; tasks running together
     // also compete, so the whole batch is timed with the chosen sizes capped
     // at 64, 32 and 16 workgroups as well
-    for (int cap : {64, 32, 16}) {
+    for (int cap : {1 << 30, 64, 32, 16}) {
       std::vector<int> kc = kt;
       std::vector<double> ec = et;
-      bool changed = cap == 64;
+      bool changed = cap == (1 << 30);
       for (size_t i = 0; i < kc.size(); ++i) {
         if (b->tasks[i].workgroups > 0 || kc[i] <= cap) continue;
         ec[i] = et[i] * (double)kc[i] / (double)cap;

@@ -216,6 +216,7 @@ struct BatchGraph {
   const int32_t* in_off;
   const int32_t* in_idx;
   const int32_t* outdeg;
+  const uint32_t* out_w;  // edge weights (weighted graphs; SSSP tasks)
   const int32_t* in_probe;
   const int32_t* hubs;   // vertices with more than kHubDeg out-edges
   int nhubs;
@@ -230,19 +231,22 @@ struct TaskCtl {
   unsigned long long bar;    // barrier: (generation << 32) | arrivals
   unsigned long long qn[3];  // BFS frontier sizes, rotating
   unsigned long long ds[3];  // their degree sums
-  int levels;                // BFS levels / PageRank iterations completed
-  int pad;
+  int levels;                // BFS levels / PageRank iterations / SSSP phases completed
+  int overflow;              // SSSP: a distance reached UINT32_MAX
   long long t_begin;         // wall clock at the task's start and end (rank 0)
   long long t_end;
-  int pad2[4];
+  unsigned long long thresh; // SSSP: the current bucket ends below thresh
+  unsigned long long fmin;   // SSSP: smallest far distance at or beyond thresh
+  unsigned long long farc[3];  // SSSP: far-set sizes, rotating like qn
 };
 
 struct BatchTask {
   int id;       // index in the batch
-  int alg;      // ALG_BFS or ALG_PR
+  int alg;      // ALG_BFS, ALG_PR or ALG_SSSP
   int graph;
   int src;
   int iters;
+  unsigned delta;  // SSSP bucket width
   float damping;
   int k;        // workgroups
   void* out;    // int32 levels or float ranks

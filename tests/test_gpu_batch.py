@@ -247,3 +247,83 @@ def test_batch_argument_errors():
         gi.Batch([g], [dict(graph=0, algorithm=2, out=out)])
     with pytest.raises(gi.GiError):
         gi.Batch([g], [dict(graph=0, algorithm=0, iters=-1, out=out)])
+
+
+_WPOOL = None
+
+
+def weighted_pool():
+    global _WPOOL
+    if _WPOOL is None:
+        els = [gg.grid(30, 41, 0.01, seed=4), gg.grid(64, 64, 0.0, seed=7)]
+        for sc, seed in ((10, 31), (13, 32)):
+            el = gg.rmat(sc, seed=seed)
+            el.w = gg.uniform_weights(el.m, seed, 1, 1000)
+            els.append(el)
+        el = gg.path(800)
+        el.w = gg.uniform_weights(el.m, 5, 1, 1000)
+        els.append(el)
+        el = gg.rmat(11, seed=33)
+        el.w = np.ones(el.m, np.uint32)
+        els.append(el)
+        _WPOOL = [(el, device_graph(el), oracle.Graph(el)) for el in els]
+    return _WPOOL
+
+
+@pytest.mark.parametrize("threads", [256, 512])
+def test_batch_sssp_matches_dijkstra(threads):
+    """SSSP tasks (delta-stepping with task barriers) over weighted graphs,
+    several bucket widths, mixed with BFS tasks on the same graphs: distances
+    bit-exact against Dijkstra, levels exact, under every placement."""
+    import torch
+    import paper_1805_00923_amd as gi
+    P = weighted_pool()
+    tasks = []
+    deltas = [1, 7, 100, 1000, 1 << 20]
+    for gidx, (el, g, og) in enumerate(P):
+        for j, s in enumerate(list(gg.pick_sources(el, 3, 40 + gidx)) or [0]):
+            tasks.append(dict(graph=gidx, algorithm=gi.ALG_SSSP, src=int(s),
+                              sssp_delta=deltas[(gidx + j) % len(deltas)],
+                              out=torch.full((g.n,), 7, dtype=torch.int32, device="cuda:0"),
+                              workgroups=[1, 3, 8, 0][j % 4]))
+        s = int((list(gg.pick_sources(el, 1, 90 + gidx)) or [0])[0])
+        tasks.append(dict(graph=gidx, algorithm=gi.ALG_BFS, src=s,
+                          out=torch.full((g.n,), -9, dtype=torch.int32, device="cuda:0")))
+    b = gi.Batch([g for _, g, _ in P], tasks)
+    b.set_threads(threads)
+    b.set_trace(8192)
+    for placement in (1, 0):
+        b.set_placement(placement)
+        for use_graph in (False, True):
+            say("batch sssp threads=%d placement=%d graph=%d" % (threads, placement, use_graph))
+            for t in tasks:
+                t["out"].fill_(7)
+            b.run(use_graph=use_graph)
+            torch.cuda.synchronize()
+            info = b.info()
+            for i, t in enumerate(tasks):
+                el, g, og = P[t["graph"]]
+                got = t["out"].cpu().numpy()
+                if t["algorithm"] == gi.ALG_SSSP:
+                    ref = oracle.dijkstra(og, t["src"])
+                    assert np.array_equal(got.view(np.uint32), ref), (el.name, t["src"],
+                                                                     t["sssp_delta"])
+                    ts, pull, fr = b.trace(i, 8192)
+                    assert len(ts) == info["levels"][i] + 1 and fr[0] == 1 and fr[-1] == 0
+                else:
+                    assert np.array_equal(got, oracle.bfs(og, t["src"])[0]), el.name
+    b.close()
+
+
+def test_batch_sssp_errors():
+    import torch
+    import paper_1805_00923_amd as gi
+    P = pool()
+    g = P[0][1]
+    out = torch.zeros(g.n, dtype=torch.int32, device="cuda:0")
+    with pytest.raises(gi.GiError):   # unweighted graph
+        gi.Batch([g], [dict(graph=0, algorithm=gi.ALG_SSSP, src=0, out=out)])
+    el, wg, og = weighted_pool()[0]
+    out = torch.zeros(wg.n, dtype=torch.int32, device="cuda:0")
+    with pytest.raises(gi.GiError):   # source outside the graph
+        gi.Batch([wg], [dict(graph=0, algorithm=gi.ALG_SSSP, src=wg.n, out=out)])
