@@ -27,10 +27,12 @@ achieved = bytes per launch / mean launch time.
 
 Other workloads (--workload): pr_rmat16 (20-iteration DensePull PageRank on
 R-MAT scale 16, the PageRank configuration), pr_rmat22, sssp_grid
-(delta-stepping on the 4096x4096 grid with 1% shortcuts), selector (learned
-schedule selector against the hybrid rule on a held-out Chung-Lu graph),
-batched (256 BFS/PageRank instances over 14 graphs, one persistent launch
-against 256 plain calls).
+(delta-stepping on the 4096x4096 grid with 1% shortcuts, or with none:
+--grid-shortcuts 0), selector (learned schedule selector against the hybrid
+rule on a held-out Chung-Lu graph), batched (256 BFS/PageRank instances over
+14 graphs, one persistent launch against 256 plain calls), prdelta_rmat22,
+prec_rmat22 (PageRank fused with eigenvector centrality), bc_rmat22
+(betweenness from 8 sources).
 """
 import argparse
 import json
@@ -61,6 +63,9 @@ def parse():
                     help="selector workload: held-out Chung-Lu graph with 4M vertices (small) "
                          "or 41M vertices and ~1.4B edges (full)")
     ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--grid-shortcuts", type=float, default=0.01,
+                    help="sssp_grid: shortcut pairs as a fraction of the vertices (0: the "
+                         "plain grid, diameter 8190, the many-phase regime of road graphs)")
     ap.add_argument("--sssp-path", default="batched", choices=["batched", "plain"],
                     help="sssp_grid: the 4 sources as one batched launch, or 4 engine runs")
     ap.add_argument("--overlap", type=int, default=1, choices=[0, 1],
@@ -458,7 +463,7 @@ def run_sssp(args, torch, dev):
     import graphgen as gg
     import paper_1805_00923_amd as gi
     t0 = time.time()
-    el = gg.grid(4096, 4096, 0.01, seed=4)
+    el = gg.grid(4096, 4096, args.grid_shortcuts, seed=4)
     g = gi.Graph.from_edges(el.n, el.src, el.dst, el.w)
     log("grid: built in %.1fs n=%d m=%d" % (time.time() - t0, g.n, g.m))
     srcs = gg.pick_sources(el, 4, 5)
@@ -505,7 +510,9 @@ def run_sssp(args, torch, dev):
     value = sum(m_reach) * args.steps / dt / 1e9
     kmed = float(np.median(kms))
     roof = tally.roofline()
-    config = {"workload": "sssp_grid4096_shortcut1pct", "n": g.n, "m": g.m, "sources": 4,
+    wname = ("sssp_grid4096_noshortcut" if args.grid_shortcuts == 0 else
+             "sssp_grid4096_shortcut%gpct" % (100 * args.grid_shortcuts))
+    config = {"workload": wname, "n": g.n, "m": g.m, "sources": 4,
               "schedule": g.schedule().as_dict(), "sssp_path": args.sssp_path}
     extra = {"phases_median": int(np.median(phases)), "delta_sweep_ms": sweep,
              "delta": best_delta, "plain_ms": round(dt * 1e3 / args.steps, 3),
@@ -626,6 +633,7 @@ def run_selector(args, torch, dev):
         n_h, samples, dmax = 1 << 22, 34 * (1 << 22), 1e6 * (1 << 22) / 41e6
     t0 = time.time()
     el = gg.chung_lu(n_h, samples, 2.0, dmax, seed=999)
+    log("held-out records generated in %.1fs; building the adjacency" % (time.time() - t0))
     g = gi.Graph.from_edges(el.n, el.src, el.dst)
     log("held-out %s: n=%d m=%d built in %.1fs" % (el.name, g.n, g.m, time.time() - t0))
     srcs = gg.pick_sources(el, 16, 1000)
@@ -650,6 +658,11 @@ def run_selector(args, torch, dev):
 
     rows = []
     cases = [(gi.ALG_BFS, int(s)) for s in srcs] + [(gi.ALG_CC, 0), (gi.ALG_PAGERANK, 0)]
+    skipped = {}
+    if 2 * g.m > 2**31 - 1:
+        # CC runs over the symmetric adjacency, 2m entries under 32-bit offsets
+        cases.remove((gi.ALG_CC, 0))
+        skipped["cc"] = "2m = %d exceeds the symmetric adjacency's 32-bit offsets" % (2 * g.m)
     regret_l, regret_h, best_steps = [], [], []
     t_heur = t_learn = t_best = 0.0
     for alg, s in cases:
@@ -699,7 +712,7 @@ def run_selector(args, torch, dev):
                                 "p50": round(1e3 * float(np.percentile(regret_h, 50)), 3),
                                 "p95": round(1e3 * float(np.percentile(regret_h, 95)), 3),
                                 "total_pct": round(100 * regret_h.sum() / sum(best_steps), 2)},
-        "per_case": rows, "wall_s": round(time.time() - t_all, 1),
+        "per_case": rows, "skipped": skipped, "wall_s": round(time.time() - t_all, 1),
     }
     config = {"workload": "selector_chunglu_g2.0_%s" % args.heldout, "n": g.n, "m": g.m,
               "train_graphs": ["rmat16", "rmat18", "rmat20", "rmat22", "chunglu1M_g2.2",

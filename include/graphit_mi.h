@@ -233,7 +233,10 @@ gi_status gi_bfs(gi_graph* g, int32_t src, int32_t* level, int32_t* parent, void
  * in both directions (evaluation, algorithms paragraph):
  *   label   device out, n int32: smallest vertex id of v's weakly
  *           connected component.
- * Errors: INVALID_ARG, DEVICE. */
+ * The first call builds the symmetric adjacency (2m entries, 32-bit
+ * offsets) on the device.
+ * Errors: INVALID_ARG, OVERFLOW (2m > 2^31 - 1, refused before any device
+ * work), DEVICE. */
 gi_status gi_cc(gi_graph* g, int32_t* label, void* stream);
 
 /* Single-source shortest paths over uint32 weights by delta-stepping

@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <thread>
 #include <vector>
@@ -193,7 +194,7 @@ static gi_status check_adjacency(int32_t n, int64_t m, const int32_t* off, const
 
 // Adjacency from raw records: rows bucketed by source, each row sorted by
 // (neighbour, weight) packed into 64-bit keys, repeated neighbours dropped so
-// that the smallest weight survives.  Rows are sorted by worker threads.
+// that the smallest weight survives.
 extern "C" gi_status gi_build_adjacency(int32_t n, int64_t nrec, const int32_t* src,
                                         const int32_t* dst, const uint32_t* w, int32_t* off,
                                         int32_t* idx, uint32_t* w_out, int64_t* m_out) {
@@ -202,12 +203,38 @@ extern "C" gi_status gi_build_adjacency(int32_t n, int64_t nrec, const int32_t* 
   if ((nrec > 0 && (!src || !dst || !idx)) || !off || !m_out)
     return fail(GI_ERR_INVALID_ARG, "NULL array");
   if (w_out && !w) return fail(GI_ERR_INVALID_ARG, "w_out given without input weights");
-  for (int64_t k = 0; k < nrec; ++k)
-    if ((uint32_t)src[k] >= (uint32_t)n || (uint32_t)dst[k] >= (uint32_t)n)
-      return fail(GI_ERR_INVALID_ARG, "record %lld has an endpoint outside [0, %d)", (long long)k, n);
+  // Worker threads: records are checked in slices; rows are split into
+  // contiguous ranges, and each worker scans every record but counts and
+  // places only those of its own rows, so the random writes stay private
+  // to a worker and the placement order within a row is the record order.
+  const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  auto run = [nth](const std::function<void(unsigned)>& fn) {
+    std::vector<std::thread> pool;
+    for (unsigned t = 1; t < nth; ++t) pool.emplace_back(fn, t);
+    fn(0);
+    for (auto& th : pool) th.join();
+  };
+  auto row_lo = [&](unsigned t) { return (int32_t)((int64_t)n * t / nth); };
+  std::vector<int64_t> first_bad(nth, nrec);
+  run([&](unsigned t) {
+    const int64_t lo = nrec * (int64_t)t / nth, hi = nrec * (int64_t)(t + 1) / nth;
+    for (int64_t k = lo; k < hi; ++k)
+      if ((uint32_t)src[k] >= (uint32_t)n || (uint32_t)dst[k] >= (uint32_t)n) {
+        first_bad[t] = k;
+        break;
+      }
+  });
+  const int64_t bad = *std::min_element(first_bad.begin(), first_bad.end());
+  if (bad < nrec)
+    return fail(GI_ERR_INVALID_ARG, "record %lld has an endpoint outside [0, %d)", (long long)bad, n);
   std::vector<int64_t> start((size_t)n + 1, 0);
-  for (int64_t k = 0; k < nrec; ++k)
-    if (src[k] != dst[k]) start[(size_t)src[k] + 1]++;
+  run([&](unsigned t) {
+    const int32_t r0 = row_lo(t), r1 = row_lo(t + 1);
+    for (int64_t k = 0; k < nrec; ++k) {
+      const int32_t u = src[k];
+      if (u >= r0 && u < r1 && u != dst[k]) start[(size_t)u + 1]++;
+    }
+  });
   for (int32_t v = 0; v < n; ++v) start[(size_t)v + 1] += start[(size_t)v];
   std::vector<uint64_t> keys;
   try {
@@ -215,18 +242,19 @@ extern "C" gi_status gi_build_adjacency(int32_t n, int64_t nrec, const int32_t* 
   } catch (...) {
     return fail(GI_ERR_OUT_OF_MEMORY, "host allocation failed");
   }
-  {
-    std::vector<int64_t> cur(start.begin(), start.end() - 1);
+  run([&](unsigned t) {
+    const int32_t r0 = row_lo(t), r1 = row_lo(t + 1);
+    std::vector<int64_t> cur(start.begin() + r0, start.begin() + r1);
     for (int64_t k = 0; k < nrec; ++k) {
-      if (src[k] == dst[k]) continue;
-      const uint64_t key = ((uint64_t)(uint32_t)dst[k] << 32) | (uint64_t)(w ? w[k] : 0u);
-      keys[(size_t)cur[(size_t)src[k]]++] = key;
+      const int32_t u = src[k];
+      if (u < r0 || u >= r1 || u == dst[k]) continue;
+      keys[(size_t)cur[(size_t)(u - r0)]++] =
+          ((uint64_t)(uint32_t)dst[k] << 32) | (uint64_t)(w ? w[k] : 0u);
     }
-  }
-  // sort and de-duplicate rows in parallel; kept[v] = distinct neighbours of v
+  });
+  // sort and de-duplicate rows; kept[v] = distinct neighbours of v
   std::vector<int64_t> kept((size_t)n, 0);
-  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  auto work = [&](unsigned t) {
+  run([&](unsigned t) {
     for (int32_t v = (int32_t)t; v < n; v += (int32_t)nth) {
       uint64_t* b = keys.data() + start[(size_t)v];
       uint64_t* e = keys.data() + start[(size_t)v + 1];
@@ -236,23 +264,23 @@ extern "C" gi_status gi_build_adjacency(int32_t n, int64_t nrec, const int32_t* 
         if (k == 0 || (b[k - 1] >> 32) != (*p >> 32)) b[k++] = *p;
       kept[(size_t)v] = k;
     }
-  };
-  std::vector<std::thread> pool;
-  for (unsigned t = 1; t < nth; ++t) pool.emplace_back(work, t);
-  work(0);
-  for (auto& th : pool) th.join();
+  });
   int64_t m = 0;
   off[0] = 0;
   for (int32_t v = 0; v < n; ++v) {
-    const uint64_t* b = keys.data() + start[(size_t)v];
-    for (int64_t k = 0; k < kept[(size_t)v]; ++k) {
-      idx[m] = (int32_t)(b[k] >> 32);
-      if (w_out) w_out[m] = (uint32_t)(b[k] & 0xffffffffu);
-      ++m;
-    }
+    m += kept[(size_t)v];
     if (m > INT32_MAX) return fail(GI_ERR_OVERFLOW, "more than 2^31-1 edges");
     off[v + 1] = (int32_t)m;
   }
+  run([&](unsigned t) {
+    for (int32_t v = row_lo(t); v < row_lo(t + 1); ++v) {
+      const uint64_t* b = keys.data() + start[(size_t)v];
+      for (int64_t k = 0; k < kept[(size_t)v]; ++k) {
+        idx[off[v] + k] = (int32_t)(b[k] >> 32);
+        if (w_out) w_out[off[v] + k] = (uint32_t)(b[k] & 0xffffffffu);
+      }
+    }
+  });
   *m_out = m;
   return GI_OK;
 }
@@ -1177,6 +1205,12 @@ extern "C" gi_status gi_bfs(gi_graph* g, int32_t src, int32_t* level, int32_t* p
 static gi_status ensure_sym(gi_graph* g, hipStream_t s) {
   if (g->sym_idx) return GI_OK;
   const size_t N = (size_t)g->n;
+  // 2m entries under int32 offsets: larger graphs are refused before any
+  // allocation or launch
+  if (2 * g->m > (int64_t)INT32_MAX)
+    return fail(GI_ERR_OVERFLOW,
+                "connected components needs the symmetric adjacency (2m = %lld entries), "
+                "which exceeds 32-bit offsets", (long long)(2 * g->m));
   std::vector<int32_t> off(N + 1, 0);
   for (size_t v = 0; v < N; ++v)
     off[v + 1] = off[v] + g->h_outdeg[v] + (g->h_in_off[v + 1] - g->h_in_off[v]);

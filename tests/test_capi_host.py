@@ -60,6 +60,31 @@ def test_host_ingest_rmat_and_grid():
             assert np.array_equal(ww, og.w)
 
 
+def test_host_ingest_weighted_rmat16_with_repeats():
+    """Rows split over all worker threads, repeated pairs with different
+    weights (the smallest survives), self-loops dropped."""
+    gi = _gi()
+    el = gg.rmat(16, seed=8)
+    src = np.concatenate([el.src, el.dst[::3], np.arange(0, el.n, 97, dtype=np.int32)])
+    dst = np.concatenate([el.dst, el.src[::3], np.arange(0, el.n, 97, dtype=np.int32)])
+    w = gg.uniform_weights(len(src), 12, 1, 50)
+    og = oracle.build_adj(el.n, src, dst, w)
+    off, idx, ww = gi.build_adjacency(el.n, src, dst, w)
+    assert np.array_equal(off, og.off) and np.array_equal(idx, og.idx)
+    assert np.array_equal(ww, og.w)
+
+
+def test_ingest_reports_first_bad_record():
+    gi = _gi()
+    src = np.zeros(100000, np.int32)
+    dst = np.ones(100000, np.int32)
+    src[77777] = 9
+    dst[99998] = -1
+    with pytest.raises(gi.GiError) as e:
+        gi.build_adjacency(4, src, dst)
+    assert e.value.status == gi.GI_ERR_INVALID_ARG and "77777" in str(e.value)
+
+
 def test_ingest_rejects_bad_records():
     gi = _gi()
     with pytest.raises(gi.GiError) as e:

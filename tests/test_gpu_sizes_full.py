@@ -2,8 +2,9 @@
 times (default hybrid schedule, bitvector frontier, adaptive batching,
 per-step timing on): RMAT scale 22 BFS from sampled sources and CC, checked
 exactly against the oracle; PageRank on RMAT scale 22 within 1e-6; and
-delta-stepping on the 4096 x 4096 grid with 1% shortcuts against Dijkstra
-from sampled sources."""
+delta-stepping on the 4096 x 4096 grid (1% shortcuts, and none) against
+Dijkstra from sampled sources, on the plain path and as the benchmark's
+batched SSSP tasks."""
 import numpy as np
 import pytest
 
@@ -113,3 +114,37 @@ def test_grid4096_sssp_sampled_sources():
             d = run_sssp(g, s)
             assert np.array_equal(d, oracle.dijkstra(og, int(s)))
     g.set_step_timing(False)
+
+
+@pytest.mark.parametrize("frac", [0.01, 0.0])
+def test_grid4096_batched_sssp(frac):
+    """The benchmark's batched SSSP launch (4 sources as SSSP tasks,
+    autotuned): distances of two sources bit-exact against Dijkstra, all four
+    equal to the plain path's; with no shortcuts the diameter is 8190 hops
+    and each task runs thousands of delta-stepping phases."""
+    import torch
+    import paper_1805_00923_amd as gi
+    say("building grid4096 frac=%g" % frac)
+    el = gg.grid(4096, 4096, frac, seed=4)
+    g = device_graph(el)
+    og = oracle.Graph(el)
+    srcs = gg.pick_sources(el, 4, 5)
+    outs = [torch.empty(g.n, dtype=torch.int32, device="cuda:0") for _ in srcs]
+    b = gi.Batch([g], [dict(graph=0, algorithm=gi.ALG_SSSP, src=int(s), sssp_delta=8192,
+                            out=o) for s, o in zip(srcs, outs)])
+    say("grid4096 batched sssp autotune")
+    b.autotune(reps=1)
+    say("grid4096 batched sssp run")
+    b.run(use_graph=True)
+    torch.cuda.synchronize()
+    for i in (0, 3):
+        say("grid4096 dijkstra src=%d" % srcs[i])
+        d = outs[i].cpu().numpy().view(np.uint32)
+        assert np.array_equal(d, oracle.dijkstra(og, int(srcs[i]))), i
+    g.set_schedule(sssp_delta=8192)
+    for i, s in enumerate(srcs):
+        say("grid4096 plain sssp src=%d" % s)
+        assert np.array_equal(run_sssp(g, s), outs[i].cpu().numpy().view(np.uint32)), i
+    g.set_schedule()
+    b.close()
+    g.close()
