@@ -534,6 +534,7 @@ def run_sssp(args, torch, dev):
             b.run()
             b.run()
             bsweep[delta] = round(b.info()["ms"], 3)
+            log("batched sssp delta %d: %.3f ms (%d threads)" % (delta, bsweep[delta], b.threads()))
             if best is None or bsweep[delta] < bsweep[best[0]]:
                 if best is not None:
                     best[1].close()

@@ -454,9 +454,10 @@ gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, const gi_tas
 
 /* Autotuner, for each workgroup size of 256, 512 and 1024 threads (only the
  * pinned one after gi_batch_set_threads): times each (graph, algorithm)
- * class alone on 1, 2, 4, ... 256 workgroups (median of reps launches),
- * keeps the size with the least workgroup-time unless it is more than twice
- * as slow as the fastest, gives tasks longer than the balanced share of the
+ * class alone on 256, 128, 64, ... workgroups (median of reps launches),
+ * stopping at the first size more than twice as slow as the fastest so far;
+ * keeps, among the sizes within twice the fastest, the one with the least
+ * workgroup-time; gives tasks longer than the balanced share of the
  * grid their fastest size, caps those sizes at 64, 32 and 16, plans each
  * with XCD-local and with spread placement, and times each whole batch
  * (median of reps launches).  Keeps the workgroup size, task sizes,

@@ -2589,20 +2589,26 @@ static gi_status batch_tune_sizes(gi_batch* b, int32_t reps) {
   std::vector<int> best_k((size_t)nt, 1), fast_k((size_t)nt, 1);
   std::vector<double> best_t((size_t)nt, 0.0), fast_t((size_t)nt, 0.0);
   for (int q : reps_list) {
+    // sizes from the largest down: among the sizes within twice the fastest
+    // time, the least workgroup-time (throughput); the sweep stops at the
+    // first size slower than that, so a large task is never timed on a
+    // handful of workgroups
+    int kmax = 1;
+    while (kmax * 2 <= std::min(256, b->max_grid)) kmax *= 2;
     double bw = 1e300, bt = 0.0, ft = 1e300;
-    int bk = 1, fk = 1;
-    for (int k = 1; k <= std::min(256, b->max_grid); k *= 2) {
+    int bk = kmax, fk = kmax;
+    for (int k = kmax; k >= 1; k /= 2) {
       float ms = 0.0f;
       if ((st = batch_time_task(b, q, k, reps, &ms)) != GI_OK) return st;
-      // least workgroup-time (throughput), unless more than twice as slow as the fastest
+      if (ms < ft) {
+        ft = ms;
+        fk = k;
+      }
+      if ((double)ms > 2.0 * ft) break;
       if ((double)k * ms < bw) {
         bw = (double)k * ms;
         bk = k;
         bt = ms;
-      }
-      if (ms < ft) {
-        ft = ms;
-        fk = k;
       }
     }
     if (bt > 2.0 * ft) {
