@@ -442,39 +442,53 @@ static gi_status build_segments(gi_graph* g, int p, int strategy) {
   const int32_t* off = g->h_in_off.data();
   const int32_t* idx = g->h_in_idx.data();
   g->segs.assign((size_t)p, SegDev());
-  std::vector<int32_t> soff, sidx, sdst;
-  for (int i = 0; i < p; ++i) {
-    const int32_t lo = (int32_t)bound[(size_t)i], hi = (int32_t)bound[(size_t)i + 1];
-    soff.clear();
-    sidx.clear();
-    sdst.clear();
-    soff.push_back(0);
-    for (int32_t v = 0; v < n; ++v) {
-      const int32_t* b = idx + off[v];
-      const int32_t* e = idx + off[v + 1];
-      const int32_t* a = std::lower_bound(b, e, lo);
-      const int32_t* z = std::lower_bound(a, e, hi);
-      if (a == z) continue;
-      sidx.insert(sidx.end(), a, z);
-      sdst.push_back(v);
-      soff.push_back((int32_t)sidx.size());
+  // host arrays of a wave of segments are built by worker threads, one
+  // segment each, then uploaded in segment order
+  struct HostSeg {
+    std::vector<int32_t> soff, sidx, sdst, chunks;
+    std::vector<int4> tab;
+  };
+  const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  for (int w0 = 0; w0 < p; w0 += nth) {
+    const int w1 = std::min(p, w0 + nth);
+    std::vector<HostSeg> hs((size_t)(w1 - w0));
+    auto work = [&](int i) {
+      HostSeg& h = hs[(size_t)(i - w0)];
+      const int32_t lo = (int32_t)bound[(size_t)i], hi = (int32_t)bound[(size_t)i + 1];
+      h.soff.push_back(0);
+      for (int32_t v = 0; v < n; ++v) {
+        const int32_t* rb = idx + off[v];
+        const int32_t* re = idx + off[v + 1];
+        const int32_t* a = std::lower_bound(rb, re, lo);
+        const int32_t* z = std::lower_bound(a, re, hi);
+        if (a == z) continue;
+        h.sidx.insert(h.sidx.end(), a, z);
+        h.sdst.push_back(v);
+        h.soff.push_back((int32_t)h.sidx.size());
+      }
+      h.tab = make_pr_table(h.soff.data(), (int)h.sdst.size(), g->pr_cap_e, g->pr_cap_v,
+                            &h.chunks);
+    };
+    std::vector<std::thread> pool;
+    for (int i = w0 + 1; i < w1; ++i) pool.emplace_back(work, i);
+    work(w0);
+    for (auto& th : pool) th.join();
+    for (int i = w0; i < w1; ++i) {
+      const HostSeg& h = hs[(size_t)(i - w0)];
+      SegDev& sg = g->segs[(size_t)i];
+      sg.nrows = (int)h.sdst.size();
+      sg.nnz = (int64_t)h.sidx.size();
+      sg.ntab = (int)h.tab.size();
+      gi_status st;
+      if ((st = dev_alloc(g, g->seg_allocs, &sg.off, h.soff.size())) != GI_OK) return st;
+      if ((st = dev_alloc(g, g->seg_allocs, &sg.idx, h.sidx.size())) != GI_OK) return st;
+      if ((st = dev_alloc(g, g->seg_allocs, &sg.dst, h.sdst.size())) != GI_OK) return st;
+      if ((st = dev_alloc(g, g->seg_allocs, &sg.table, h.tab.size())) != GI_OK) return st;
+      if ((st = upload(h.soff.data(), sg.off, h.soff.size() * 4)) != GI_OK) return st;
+      if ((st = upload(h.sidx.data(), sg.idx, h.sidx.size() * 4)) != GI_OK) return st;
+      if ((st = upload(h.sdst.data(), sg.dst, h.sdst.size() * 4)) != GI_OK) return st;
+      if ((st = upload(h.tab.data(), sg.table, h.tab.size() * sizeof(int4))) != GI_OK) return st;
     }
-    SegDev& s = g->segs[(size_t)i];
-    s.nrows = (int)sdst.size();
-    s.nnz = (int64_t)sidx.size();
-    std::vector<int32_t> seg_chunks;
-    std::vector<int4> tab = make_pr_table(soff.data(), s.nrows, g->pr_cap_e, g->pr_cap_v,
-                                          &seg_chunks);
-    s.ntab = (int)tab.size();
-    gi_status st;
-    if ((st = dev_alloc(g, g->seg_allocs, &s.off, soff.size())) != GI_OK) return st;
-    if ((st = dev_alloc(g, g->seg_allocs, &s.idx, sidx.size())) != GI_OK) return st;
-    if ((st = dev_alloc(g, g->seg_allocs, &s.dst, sdst.size())) != GI_OK) return st;
-    if ((st = dev_alloc(g, g->seg_allocs, &s.table, tab.size())) != GI_OK) return st;
-    if ((st = upload(soff.data(), s.off, soff.size() * 4)) != GI_OK) return st;
-    if ((st = upload(sidx.data(), s.idx, sidx.size() * 4)) != GI_OK) return st;
-    if ((st = upload(sdst.data(), s.dst, sdst.size() * 4)) != GI_OK) return st;
-    if ((st = upload(tab.data(), s.table, tab.size() * sizeof(int4))) != GI_OK) return st;
   }
   // one partial-sum buffer per segment (the concurrent form needs them all;
   // the sequential form uses the first)
