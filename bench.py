@@ -634,8 +634,13 @@ def run_selector(args, torch, dev):
         n_h, samples, dmax = 1 << 22, 34 * (1 << 22), 1e6 * (1 << 22) / 41e6
     t0 = time.time()
     el = gg.chung_lu(n_h, samples, 2.0, dmax, seed=999)
-    log("held-out records generated in %.1fs; building the adjacency" % (time.time() - t0))
-    g = gi.Graph.from_edges(el.n, el.src, el.dst)
+    log("held-out records generated in %.1fs" % (time.time() - t0))
+    off, idx, _ = gi.build_adjacency(el.n, el.src, el.dst)
+    log("held-out out-adjacency built (%.1fs)" % (time.time() - t0))
+    ioff, iidx, _ = gi.build_adjacency(el.n, el.dst, el.src)
+    log("held-out in-adjacency built (%.1fs)" % (time.time() - t0))
+    g = gi.Graph(el.n, off, idx, None, ioff, iidx, None)
+    del off, idx, ioff, iidx
     log("held-out %s: n=%d m=%d built in %.1fs" % (el.name, g.n, g.m, time.time() - t0))
     srcs = gg.pick_sources(el, 16, 1000)
     del el
@@ -688,6 +693,8 @@ def run_selector(args, torch, dev):
         regret_l += list(rl)
         regret_h += list(rh)
         best_steps += list(best)
+        log("held-out %s src=%d: heuristic %.3f ms, learned %.3f ms, per-step best %.3f ms" %
+            ({0: "pagerank", 1: "bfs", 2: "cc"}[alg], s, heur_ms, learn_ms, float(best.sum())))
         t_heur += heur_ms
         t_learn += learn_ms
         t_best += float(best.sum())

@@ -167,6 +167,25 @@ static void free_list(std::vector<void*>& list) {
   list.clear();
 }
 
+// Host worker threads for the O(m) ingest and set-up passes: fn(t) runs on
+// worker t of host_workers(), worker 0 on the calling thread.
+static unsigned host_workers() {
+  return std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+}
+
+static void run_workers(const std::function<void(unsigned)>& fn) {
+  const unsigned nth = host_workers();
+  std::vector<std::thread> pool;
+  for (unsigned t = 1; t < nth; ++t) pool.emplace_back(fn, t);
+  fn(0);
+  for (auto& th : pool) th.join();
+}
+
+// Row range [lo, hi) of worker t out of nth over n rows.
+static inline int32_t worker_row(int32_t n, unsigned t, unsigned nth) {
+  return (int32_t)((int64_t)n * t / nth);
+}
+
 // ------------------------------------------------------ adjacency checks --
 
 static gi_status check_adjacency(int32_t n, int64_t m, const int32_t* off, const int32_t* idx,
@@ -207,14 +226,9 @@ extern "C" gi_status gi_build_adjacency(int32_t n, int64_t nrec, const int32_t* 
   // contiguous ranges, and each worker scans every record but counts and
   // places only those of its own rows, so the random writes stay private
   // to a worker and the placement order within a row is the record order.
-  const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  auto run = [nth](const std::function<void(unsigned)>& fn) {
-    std::vector<std::thread> pool;
-    for (unsigned t = 1; t < nth; ++t) pool.emplace_back(fn, t);
-    fn(0);
-    for (auto& th : pool) th.join();
-  };
-  auto row_lo = [&](unsigned t) { return (int32_t)((int64_t)n * t / nth); };
+  const unsigned nth = host_workers();
+  const auto& run = run_workers;
+  auto row_lo = [&](unsigned t) { return worker_row(n, t, nth); };
   std::vector<int64_t> first_bad(nth, nrec);
   run([&](unsigned t) {
     const int64_t lo = nrec * (int64_t)t / nth, hi = nrec * (int64_t)(t + 1) / nth;
@@ -677,22 +691,37 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
         return st;
       }
       // every in-edge u->v must be an out-edge of u (with degrees equal below,
-      // the two adjacencies then hold the same edge set)
-      for (int32_t v = 0; v < n; ++v)
-        for (int32_t k = in_off[v]; k < in_off[v + 1]; ++k) {
-          const int32_t u = in_idx[k];
-          const int32_t* b = out_idx + out_off[u];
-          const int32_t* e = out_idx + out_off[u + 1];
-          const int32_t* f = std::lower_bound(b, e, v);
-          if (f == e || *f != v) {
-            delete g;
-            return fail(GI_ERR_INVALID_ARG, "in-edge %d->%d is not an out-edge", u, v);
+      // the two adjacencies then hold the same edge set); workers check row
+      // ranges and report their first bad in-edge (position, kind)
+      const unsigned nth = host_workers();
+      std::vector<int64_t> bad_k(nth, -1);
+      std::vector<int> bad_kind(nth, 0);
+      run_workers([&](unsigned t) {
+        for (int32_t v = worker_row(n, t, nth); v < worker_row(n, t + 1, nth); ++v)
+          for (int32_t k = in_off[v]; k < in_off[v + 1]; ++k) {
+            const int32_t u = in_idx[k];
+            const int32_t* b = out_idx + out_off[u];
+            const int32_t* e = out_idx + out_off[u + 1];
+            const int32_t* f = std::lower_bound(b, e, v);
+            const int kind = (f == e || *f != v) ? 1
+                             : (in_w && out_w && in_w[k] != out_w[f - out_idx]) ? 2 : 0;
+            if (kind) {
+              bad_k[t] = k;
+              bad_kind[t] = kind;
+              return;
+            }
           }
-          if (in_w && out_w && in_w[k] != out_w[f - out_idx]) {
-            delete g;
-            return fail(GI_ERR_INVALID_ARG, "weight of %d->%d differs between adjacencies", u, v);
-          }
-        }
+      });
+      for (unsigned t = 0; t < nth; ++t) {
+        if (!bad_kind[t]) continue;
+        const int64_t k = bad_k[t];
+        const int32_t v = (int32_t)(std::upper_bound(in_off, in_off + n + 1, (int32_t)k) - in_off - 1);
+        const int32_t u = in_idx[k];
+        delete g;
+        if (bad_kind[t] == 1)
+          return fail(GI_ERR_INVALID_ARG, "in-edge %d->%d is not an out-edge", u, v);
+        return fail(GI_ERR_INVALID_ARG, "weight of %d->%d differs between adjacencies", u, v);
+      }
       std::memcpy(g->h_in_off.data(), in_off, sizeof(int32_t) * ((size_t)n + 1));
       g->h_in_idx.assign(in_idx, in_idx + m);
     } else {
@@ -716,7 +745,14 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
   // in-degrees of the two adjacencies must agree (CSC is the transpose)
   {
     std::vector<int32_t> indeg((size_t)n, 0);
-    for (int64_t k = 0; k < m; ++k) indeg[(size_t)out_idx[k]]++;
+    const unsigned nth = host_workers();
+    run_workers([&](unsigned t) {
+      const int32_t r0 = worker_row(n, t, nth), r1 = worker_row(n, t + 1, nth);
+      for (int64_t k = 0; k < m; ++k) {
+        const int32_t v = out_idx[k];
+        if (v >= r0 && v < r1) indeg[(size_t)v]++;
+      }
+    });
     for (int32_t v = 0; v < n; ++v) {
       if (indeg[(size_t)v] != g->h_in_off[(size_t)v + 1] - g->h_in_off[(size_t)v]) {
         delete g;
@@ -772,15 +808,18 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
     const int32_t* io = g->h_in_off.data();
     const int32_t* ii = g->h_in_idx.data();
     const int32_t* od = g->h_outdeg.data();
-    for (size_t v = 0; v < N; ++v) {
-      int best = -1, bd = -1;
-      for (int32_t e = io[v]; e < io[v + 1]; ++e)
-        if (od[ii[e]] > bd) {
-          bd = od[ii[e]];
-          best = ii[e];
-        }
-      probe[v] = best;
-    }
+    const unsigned nth = host_workers();
+    run_workers([&](unsigned t) {
+      for (int32_t v = worker_row(n, t, nth); v < worker_row(n, t + 1, nth); ++v) {
+        int best = -1, bd = -1;
+        for (int32_t e = io[v]; e < io[v + 1]; ++e)
+          if (od[ii[e]] > bd) {
+            bd = od[ii[e]];
+            best = ii[e];
+          }
+        probe[(size_t)v] = best;
+      }
+    });
     G_ALLOC(g->in_probe, N);
     G_UP(probe.data(), g->in_probe, 4 * N);
     std::vector<int32_t> hubs;

@@ -127,6 +127,40 @@ def test_graph_create_validates_before_device_work():
     assert st == gi.GI_ERR_INVALID_ARG
 
 
+def test_graph_create_names_the_first_bad_in_edge():
+    """In-adjacency checked by worker threads over row ranges: the error
+    names the first bad in-edge in row order, for a missing edge and for a
+    weight that differs between the two adjacencies."""
+    gi = _gi()
+    el = gg.rmat(12, seed=5)
+    w = gg.uniform_weights(el.m, 3, 1, 100)
+    off, idx, ww = gi.build_adjacency(el.n, el.src, el.dst, w)
+    ioff, iidx, iw = gi.build_adjacency(el.n, el.dst, el.src, w)
+    m = len(idx)
+    rows = np.repeat(np.arange(el.n), np.diff(ioff))
+    late = int(np.nonzero(rows > 3 * el.n // 4)[0][0])      # an in-edge in a late row
+    early = int(np.nonzero(rows > el.n // 3)[0][0])         # and one in an earlier row
+    p = lambda a: a.ctypes.data
+    h = ctypes.c_void_p()
+    bad = iidx.copy()
+    for k in (late, early):
+        v, u = int(rows[k]), int(iidx[k])
+        # a source that is not an in-neighbour of v keeps the degrees equal
+        bad[k] = next(x for x in range(el.n) if x != u and x not in set(iidx[ioff[v]:ioff[v + 1]]))
+    st = gi.lib.gi_graph_create(el.n, m, p(off), p(idx), None, p(ioff), p(bad), None,
+                                ctypes.byref(h))
+    v, u = int(rows[early]), int(bad[early])
+    assert st == gi.GI_ERR_INVALID_ARG
+    assert "in-edge %d->%d is not an out-edge" % (u, v) in gi.last_error()
+    badw = iw.copy()
+    badw[late] += 1
+    st = gi.lib.gi_graph_create(el.n, m, p(off), p(idx), p(ww), p(ioff), p(iidx), p(badw),
+                                ctypes.byref(h))
+    v, u = int(rows[late]), int(iidx[late])
+    assert st == gi.GI_ERR_INVALID_ARG
+    assert "weight of %d->%d differs" % (u, v) in gi.last_error()
+
+
 def test_null_handles_rejected():
     gi = _gi()
     assert gi.lib.gi_bfs(None, 0, None, None, None) == gi.GI_ERR_INVALID_ARG
