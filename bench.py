@@ -599,7 +599,8 @@ def run_selector(args, torch, dev):
     train = [("rmat", 16, 316), ("rmat", 18, 318), ("rmat", 20, 320), ("rmat", 22, 322),
              ("chunglu", 1 << 20, 2.2, 401), ("chunglu", 1 << 20, 2.5, 402),
              ("chunglu", 1 << 21, 3.0, 403), ("chunglu", 1 << 22, 2.2, 404),
-             ("chunglu34", 1 << 20, 2.0, 405), ("chunglu34", 1 << 21, 2.0, 406)]
+             ("chunglu34", 1 << 20, 2.0, 405), ("chunglu34", 1 << 21, 2.0, 406),
+             ("rmat", 24, 324), ("chunglu34", 1 << 24, 2.0, 407)]
     F, Y, V = [], [], []
     for spec in train:
         if spec[0] == "rmat":
@@ -725,7 +726,8 @@ def run_selector(args, torch, dev):
     config = {"workload": "selector_chunglu_g2.0_%s" % args.heldout, "n": g.n, "m": g.m,
               "train_graphs": ["rmat16", "rmat18", "rmat20", "rmat22", "chunglu1M_g2.2",
                                "chunglu1M_g2.5", "chunglu2M_g3.0", "chunglu4M_g2.2",
-                               "chunglu1M_g2.0_x34", "chunglu2M_g2.0_x34"]}
+                               "chunglu1M_g2.0_x34", "chunglu2M_g2.0_x34", "rmat24",
+                               "chunglu16M_g2.0_x34"]}
     roof = None
     return speedup, "x (heuristic time / learned time)", t_learn, "f32 train / bf16 infer", \
         config, roof, None, detail
