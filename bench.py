@@ -63,6 +63,9 @@ def parse():
                     help="selector workload: held-out Chung-Lu graph with 4M vertices (small) "
                          "or 41M vertices and ~1.4B edges (full)")
     ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--selector-dump", default="",
+                    help="selector workload: write the training records, the trained "
+                         "parameters and the held-out per-step timings to this .npz")
     ap.add_argument("--grid-shortcuts", type=float, default=0.01,
                     help="sssp_grid: shortcut pairs as a fraction of the vertices (0: the "
                          "plain grid, diameter 8190, the many-phase regime of road graphs)")
@@ -672,9 +675,11 @@ def run_selector(args, torch, dev):
         skipped["cc"] = "2m = %d exceeds the symmetric adjacency's 32-bit offsets" % (2 * g.m)
     regret_l, regret_h, best_steps = [], [], []
     t_heur = t_learn = t_best = 0.0
+    dump = {}
     for alg, s in cases:
         g.set_schedule(direction=gi.DENSE_PULL_SPARSE_PUSH)
-        _, _, v, tt = selector_records(g, gi, alg, s)
+        hf, _, v, tt = selector_records(g, gi, alg, s)
+        dump["case_%d_%d" % (alg, s)] = np.concatenate([hf, tt, v.astype(np.float32)], 1)
         tt = np.where(v > 0, tt, np.inf)
         best = tt.min(1)
         if alg == gi.ALG_PAGERANK:
@@ -705,6 +710,9 @@ def run_selector(args, torch, dev):
                      "choices": {"heuristic": "".join(str(int(x)) for x in hchoice[:k]),
                                  "learned": "".join(str(int(x)) for x in lchoice[:k]),
                                  "best": "".join(str(int(x)) for x in tt.argmin(1))}})
+    if args.selector_dump:
+        p, mu, sd = sel.params()
+        np.savez_compressed(args.selector_dump, X=X, Y=Yl, V=Vm, params=p, mu=mu, sd=sd, **dump)
     regret_l, regret_h = np.array(regret_l), np.array(regret_h)
     speedup = t_heur / t_learn
     detail = {

@@ -363,11 +363,24 @@ gi_status gi_selector_get_params(const gi_selector* s, float* params, float* mu,
 gi_status gi_selector_set_params(gi_selector* s, const float* params, const float* mu,
                                  const float* sd);
 
+/* Inference range of the features (GI_SEL_FEATURES floats each; any
+ * pointer may be NULL): every inference (gi_selector_predict, the learned
+ * schedule) clamps feature f to [lo[f], hi[f]] before standardising it, so
+ * a graph larger or more skewed than the training graphs is read as the
+ * nearest edge of the training range rather than extrapolated.  A new
+ * selector has lo = -FLT_MAX, hi = FLT_MAX (no clamp); training with
+ * standardise sets the records' minimum and maximum; training itself does
+ * not clamp.  set: NULL leaves that bound unchanged; lo[f] <= hi[f], no NaN.
+ * Errors: INVALID_ARG, DEVICE. */
+gi_status gi_selector_get_range(const gi_selector* s, float* lo, float* hi);
+gi_status gi_selector_set_range(gi_selector* s, const float* lo, const float* hi);
+
 /* Train on `count` host records: feats[count][12], log_ms[count][4],
  * valid[count][4] (nonzero where the schedule was timed; rows need at least
  * one).  Minibatches of 32 records in a seeded order (the same order every
  * epoch); one device launch runs all epochs.  If standardise is nonzero, mu
- * and sd are first set from the records (sd of a constant feature = 1).
+ * and sd are first set from the records (sd of a constant feature = 1), and
+ * the inference range to the records' per-feature minimum and maximum.
  * loss (host, may be NULL) receives the mean loss of each epoch.
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
 gi_status gi_selector_train(gi_selector* s, const float* feats, const float* log_ms,

@@ -34,10 +34,18 @@ def pack(d):
     return np.concatenate([np.asarray(d[name], np.float64).ravel() for name, _ in SIZES])
 
 
-def forward(p, mu, sd, x):
-    """Predicted log-times [N, 4] and the intermediate activations."""
+def forward(p, mu, sd, x, lo=None, hi=None):
+    """Predicted log-times [N, 4] and the intermediate activations.  With
+    lo/hi given, each raw feature is first clamped to [lo, hi] (the range
+    of the training records), so that inputs outside it are read as its
+    nearest edge instead of being extrapolated."""
     w = unpack(p)
-    xn = (np.asarray(x, np.float64) - np.asarray(mu, np.float64)) / np.asarray(sd, np.float64)
+    x = np.asarray(x, np.float64)
+    if lo is not None:
+        x = np.maximum(x, np.asarray(lo, np.float64))
+    if hi is not None:
+        x = np.minimum(x, np.asarray(hi, np.float64))
+    xn = (x - np.asarray(mu, np.float64)) / np.asarray(sd, np.float64)
     z1 = xn @ w["W1"] + w["b1"]
     h1 = np.maximum(z1, 0.0)
     z2 = h1 @ w["W2"] + w["b2"]

@@ -125,6 +125,8 @@ _SIGS = {
     "gi_selector_destroy": (ctypes.c_int, [_vp]),
     "gi_selector_get_params": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "gi_selector_set_params": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "gi_selector_get_range": (ctypes.c_int, [_vp, _vp, _vp]),
+    "gi_selector_set_range": (ctypes.c_int, [_vp, _vp, _vp]),
     "gi_selector_train": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, ctypes.c_float,
                                          ctypes.c_uint64, _i32, _vp]),
     "gi_selector_gradient": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _vp, _vp]),
@@ -438,6 +440,17 @@ class Selector:
     def set_params(self, params=None, mu=None, sd=None):
         arrs = [None if a is None else np.ascontiguousarray(a, np.float32) for a in (params, mu, sd)]
         _check(lib.gi_selector_set_params(self._h, *[_hptr(a) for a in arrs]))
+
+    def range(self):
+        """(lo, hi): the per-feature range inference clamps to."""
+        lo = np.zeros(SEL_FEATURES, np.float32)
+        hi = np.zeros(SEL_FEATURES, np.float32)
+        _check(lib.gi_selector_get_range(self._h, lo.ctypes.data, hi.ctypes.data))
+        return lo, hi
+
+    def set_range(self, lo=None, hi=None):
+        arrs = [None if a is None else np.ascontiguousarray(a, np.float32) for a in (lo, hi)]
+        _check(lib.gi_selector_set_range(self._h, *[_hptr(a) for a in arrs]))
 
     @staticmethod
     def _records(feats, log_ms, valid):

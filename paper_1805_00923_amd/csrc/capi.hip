@@ -2,6 +2,7 @@
 // each algorithm.  Everything here is host code; the per-step work runs in
 // the kernels of bfs_cc.hip, pagerank.hip, sssp.hip and frontier.hip.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdarg>
 #include <cstddef>
@@ -1074,6 +1075,8 @@ static SelDev sel_dev(const gi_graph* g) {
   d.wb = g->sel_wb;
   d.mu = g->sel_p ? g->sel_p + kParams : nullptr;
   d.isd = g->sel_p ? g->sel_p + kParams + kFeat : nullptr;
+  d.lo = g->sel_p ? g->sel_p + kParams + 2 * kFeat : nullptr;
+  d.hi = g->sel_p ? g->sel_p + kParams + 3 * kFeat : nullptr;
   return d;
 }
 
@@ -1760,7 +1763,8 @@ extern "C" gi_status gi_frontier_degree_sum(const gi_graph* g, const int32_t* id
 struct gi_selector {
   std::vector<float> p;   // host copy of the parameters
   std::vector<float> mu, sd;
-  float* d_p = nullptr;   // parameters, then mu[12], isd[12]
+  std::vector<float> lo, hi;  // inference clamps each feature to [lo, hi]
+  float* d_p = nullptr;   // parameters, then mu[12], isd[12], lo[12], hi[12]
   float* d_m1 = nullptr;  // Adam moments
   float* d_m2 = nullptr;
   float* d_grad = nullptr;
@@ -1789,6 +1793,8 @@ static gi_status sel_upload(gi_selector* s) {
   std::vector<float> buf(s->p);
   for (int i = 0; i < kFeat; ++i) buf.push_back(s->mu[(size_t)i]);
   for (int i = 0; i < kFeat; ++i) buf.push_back(1.0f / s->sd[(size_t)i]);
+  for (int i = 0; i < kFeat; ++i) buf.push_back(s->lo[(size_t)i]);
+  for (int i = 0; i < kFeat; ++i) buf.push_back(s->hi[(size_t)i]);
   HIP_TRY(hipMemcpy(s->d_p, buf.data(), sizeof(float) * buf.size(), hipMemcpyHostToDevice));
   std::vector<uint16_t> wb((size_t)kParams);
   for (int i = 0; i < kParams; ++i) wb[(size_t)i] = f32_to_bf16(s->p[(size_t)i]);
@@ -1819,6 +1825,8 @@ extern "C" gi_status gi_selector_create(uint64_t seed, gi_selector** out) {
   s->p.assign((size_t)kParams, 0.0f);
   s->mu.assign((size_t)kFeat, 0.0f);
   s->sd.assign((size_t)kFeat, 1.0f);
+  s->lo.assign((size_t)kFeat, -FLT_MAX);
+  s->hi.assign((size_t)kFeat, FLT_MAX);
   // He-uniform weights: U(-b, b), b = sqrt(6 / fan_in); zero biases
   auto fill = [&](int off, int count, int fan_in) {
     const double b = std::sqrt(6.0 / fan_in);
@@ -1831,7 +1839,7 @@ extern "C" gi_status gi_selector_create(uint64_t seed, gi_selector** out) {
   fill(kOffW1, kFeat * kHid, kFeat);
   fill(kOffW2, kHid * kHid, kHid);
   fill(kOffW3, kHid * kOut, kHid);
-  if (hipMalloc((void**)&s->d_p, sizeof(float) * (kParams + 2 * kFeat)) != hipSuccess ||
+  if (hipMalloc((void**)&s->d_p, sizeof(float) * kSelBuf) != hipSuccess ||
       hipMalloc((void**)&s->d_m1, sizeof(float) * kParams) != hipSuccess ||
       hipMalloc((void**)&s->d_m2, sizeof(float) * kParams) != hipSuccess ||
       hipMalloc((void**)&s->d_grad, sizeof(float) * kParams) != hipSuccess ||
@@ -1870,6 +1878,25 @@ extern "C" gi_status gi_selector_set_params(gi_selector* s, const float* params,
   if (sd) std::memcpy(s->sd.data(), sd, sizeof(float) * kFeat);
   gi_status st = sel_upload(s);
   return st != GI_OK ? st : sel_reset_moments(s);
+}
+
+extern "C" gi_status gi_selector_get_range(const gi_selector* s, float* lo, float* hi) {
+  if (!s) return fail(GI_ERR_INVALID_ARG, "NULL selector");
+  if (lo) std::memcpy(lo, s->lo.data(), sizeof(float) * kFeat);
+  if (hi) std::memcpy(hi, s->hi.data(), sizeof(float) * kFeat);
+  return GI_OK;
+}
+
+extern "C" gi_status gi_selector_set_range(gi_selector* s, const float* lo, const float* hi) {
+  if (!s) return fail(GI_ERR_INVALID_ARG, "NULL selector");
+  for (int i = 0; i < kFeat; ++i) {
+    const float a = lo ? lo[i] : s->lo[(size_t)i], b = hi ? hi[i] : s->hi[(size_t)i];
+    if (std::isnan(a) || std::isnan(b) || a > b)
+      return fail(GI_ERR_INVALID_ARG, "feature %d: range [%g, %g] is empty or NaN", i, a, b);
+  }
+  if (lo) std::memcpy(s->lo.data(), lo, sizeof(float) * kFeat);
+  if (hi) std::memcpy(s->hi.data(), hi, sizeof(float) * kFeat);
+  return sel_upload(s);
 }
 
 // Device copies of training records, released on scope exit.
@@ -1968,6 +1995,13 @@ extern "C" gi_status gi_selector_train(gi_selector* s, const float* feats, const
       const double mean = sum / count, var = std::max(0.0, sq / count - mean * mean);
       s->mu[(size_t)f] = (float)mean;
       s->sd[(size_t)f] = var > 1e-12 ? (float)std::sqrt(var) : 1.0f;
+      float lo = feats[f], hi = feats[f];
+      for (int64_t r = 1; r < count; ++r) {
+        lo = std::min(lo, feats[r * kFeat + f]);
+        hi = std::max(hi, feats[r * kFeat + f]);
+      }
+      s->lo[(size_t)f] = lo;
+      s->hi[(size_t)f] = hi;
     }
     if ((st = sel_upload(s)) != GI_OK) return st;
   }
@@ -2026,6 +2060,8 @@ extern "C" gi_status gi_selector_predict(const gi_selector* s, const float* feat
   d.wb = s->d_wb;
   d.mu = s->d_p + kParams;
   d.isd = s->d_p + kParams + kFeat;
+  d.lo = s->d_p + kParams + 2 * kFeat;
+  d.hi = s->d_p + kParams + 3 * kFeat;
   gi_status st = GI_OK;
   if (hipMemcpy(dx, feats, sizeof(float) * (size_t)count * kFeat, hipMemcpyHostToDevice) != hipSuccess)
     st = fail(GI_ERR_DEVICE, "copy of features failed");
@@ -2047,13 +2083,13 @@ extern "C" gi_status gi_selector_attach(gi_graph* g, const gi_selector* s) {
   g->sel_wb = nullptr;
   g->sel_io = nullptr;
   if (!s) return GI_OK;
-  if (hipMalloc((void**)&g->sel_p, sizeof(float) * (kParams + 2 * kFeat)) != hipSuccess ||
+  if (hipMalloc((void**)&g->sel_p, sizeof(float) * kSelBuf) != hipSuccess ||
       hipMalloc((void**)&g->sel_wb, 2 * (size_t)kParams) != hipSuccess ||
       hipMalloc((void**)&g->sel_io, sizeof(float) * (kFeat + kOut)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(GI_ERR_OUT_OF_MEMORY, "selector copy allocation failed");
   }
-  HIP_TRY(hipMemcpy(g->sel_p, s->d_p, sizeof(float) * (kParams + 2 * kFeat),
+  HIP_TRY(hipMemcpy(g->sel_p, s->d_p, sizeof(float) * kSelBuf,
                     hipMemcpyDeviceToDevice));
   HIP_TRY(hipMemcpy(g->sel_wb, s->d_wb, 2 * (size_t)kParams, hipMemcpyDeviceToDevice));
   return GI_OK;

@@ -11,7 +11,11 @@
 //
 // Parameter layout (fp32, row-major):
 //   W1[12][64] b1[64] W2[64][64] b2[64] W3[64][4] b3[4]   (5252 values)
-// Features are standardised, x' = (x - mu) * isd, before the first layer.
+// Features are clamped to the range of the training records, [lo, hi], and
+// standardised, x' = (clamp(x) - mu) * isd, before the first layer; the
+// clamp keeps the model from extrapolating to graphs larger or more skewed
+// than those it was trained on.  Device buffer: parameters, then mu[12],
+// isd[12], lo[12], hi[12].
 #pragma once
 
 #include "common.h"
@@ -40,7 +44,16 @@ struct SelDev {
   const uint16_t* wb;  // bf16 copy of the parameters (weights are read from here)
   const float* mu;     // feature means
   const float* isd;    // reciprocal feature standard deviations
+  const float* lo;     // feature range of the training records
+  const float* hi;
 };
+
+constexpr int kSelBuf = kParams + 4 * kFeat;  // floats of a selector's device buffer
+
+// Clamped, standardised feature f.
+__device__ __forceinline__ float sel_input(const SelDev& s, int f, float x) {
+  return (fminf(fmaxf(x, s.lo[f]), s.hi[f]) - s.mu[f]) * s.isd[f];
+}
 
 __device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) {
   return __uint_as_float((unsigned)h << 16);
@@ -52,7 +65,7 @@ __device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) {
 __device__ __forceinline__ void mlp_forward_block(const SelDev& s, const float* x, float* xn,
                                                   float* h1, float* h2, float* y) {
   const int t = threadIdx.x;
-  if (t < kFeat) xn[t] = (x[t] - s.mu[t]) * s.isd[t];
+  if (t < kFeat) xn[t] = sel_input(s, t, x[t]);
   __syncthreads();
   if (t < kHid) {
     float a = s.p[kOffB1 + t];

@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kWave) void k_mlp_predict(SelDev s, const float* x,
       mlp_forward_block(s, sx, xn, h1, h2, y);
     } else {
       // same network with the fp32 weights
-      if (t < kFeat) xn[t] = (sx[t] - s.mu[t]) * s.isd[t];
+      if (t < kFeat) xn[t] = sel_input(s, t, sx[t]);
       __syncthreads();
       float acc = s.p[kOffB1 + t];
       for (int f = 0; f < kFeat; ++f) acc += xn[f] * s.p[kOffW1 + f * kHid + t];

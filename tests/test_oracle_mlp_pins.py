@@ -66,6 +66,33 @@ def test_zero_weights_closed_form():
         assert np.all(gd[name] == 0.0)
 
 
+def test_clamped_input_closed_form():
+    """One path through the network, W1[3,0] = W2[0,0] = 1 and W3[0,:] = 1,
+    zero biases: y_s = max((clamp(x_3, lo, hi) - mu_3) / sd_3, 0).  The
+    clamp applies to the raw feature, before standardisation, and leaves
+    features inside the range untouched."""
+    d = {name: np.zeros(shape) for name, shape in mlp.SIZES}
+    d["W1"][3, 0] = 1.0
+    d["W2"][0, 0] = 1.0
+    d["W3"][0, :] = 1.0
+    p = mlp.pack(d)
+    mu = np.zeros(12)
+    sd = np.ones(12)
+    mu[3], sd[3] = 1.0, 2.0
+    lo, hi = np.full(12, -np.inf), np.full(12, np.inf)
+    lo[3], hi[3] = 2.0, 9.0
+    x = np.zeros((5, 12))
+    x[:, 3] = [-4.0, 2.0, 5.0, 9.0, 30.0]
+    x[:, 5] = 1e6   # other features do not reach the output
+    y, _ = mlp.forward(p, mu, sd, x, lo, hi)
+    want = np.maximum((np.clip(x[:, 3], 2.0, 9.0) - 1.0) / 2.0, 0.0)
+    assert np.array_equal(y, np.repeat(want[:, None], 4, 1))
+    assert list(want) == [0.5, 0.5, 2.0, 4.0, 4.0]
+    # no range: the plain network
+    y0, _ = mlp.forward(p, mu, sd, x)
+    assert list(y0[:, 0]) == [0.0, 0.5, 2.0, 4.0, 14.5]
+
+
 def test_first_adam_step_is_lr_times_sign():
     """After one step from zero moments, bias correction gives m_hat = g and
     v_hat = g^2, so the update is lr * g / (|g| + eps)."""
