@@ -267,13 +267,13 @@ def run_bfs_cc(args, torch, dev):
     # paper's autotuner tunes a schedule per algorithm and graph
     bfs_sched = g.schedule().as_dict()
     cc_div, cc_seg, cc_best, cc_sweep = 20, {}, None, {}
-    for seg in ({}, {"num_segments": 8, "segment_strategy": 1}):
+    for seg in ({}, *({"num_segments": p, "segment_strategy": 1} for p in (4, 8, 16))):
         for div in (2, 4, 8, 20, 50):
             g.set_schedule(**dict(bfs_sched, hybrid_divisor=div, **seg))
             g.cc(label)
             g.cc(label)
             ms = g.stats().kernel_ms
-            cc_sweep["div%d%s" % (div, "_seg8" if seg else "")] = round(ms, 3)
+            cc_sweep["div%d%s" % (div, "_seg%d" % seg["num_segments"] if seg else "")] = round(ms, 3)
             if cc_best is None or ms < cc_best:
                 cc_div, cc_seg, cc_best = div, seg, ms
     cc_sched = dict(bfs_sched, hybrid_divisor=cc_div, **cc_seg)
