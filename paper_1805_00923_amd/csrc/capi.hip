@@ -174,12 +174,23 @@ static unsigned host_workers() {
   return std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
 }
 
-static void run_workers(const std::function<void(unsigned)>& fn) {
+// Returns false if a worker ran out of host memory (its exception is caught
+// in the worker, so it cannot end the process).
+static bool run_workers(const std::function<void(unsigned)>& fn) {
   const unsigned nth = host_workers();
+  std::vector<char> ok(nth, 1);
+  auto guarded = [&](unsigned t) {
+    try {
+      fn(t);
+    } catch (...) {
+      ok[t] = 0;
+    }
+  };
   std::vector<std::thread> pool;
-  for (unsigned t = 1; t < nth; ++t) pool.emplace_back(fn, t);
-  fn(0);
+  for (unsigned t = 1; t < nth; ++t) pool.emplace_back(guarded, t);
+  guarded(0);
   for (auto& th : pool) th.join();
+  return std::all_of(ok.begin(), ok.end(), [](char c) { return c != 0; });
 }
 
 // Row range [lo, hi) of worker t out of nth over n rows.
@@ -257,7 +268,7 @@ extern "C" gi_status gi_build_adjacency(int32_t n, int64_t nrec, const int32_t* 
   } catch (...) {
     return fail(GI_ERR_OUT_OF_MEMORY, "host allocation failed");
   }
-  run([&](unsigned t) {
+  if (!run([&](unsigned t) {
     const int32_t r0 = row_lo(t), r1 = row_lo(t + 1);
     std::vector<int64_t> cur(start.begin() + r0, start.begin() + r1);
     for (int64_t k = 0; k < nrec; ++k) {
@@ -266,7 +277,8 @@ extern "C" gi_status gi_build_adjacency(int32_t n, int64_t nrec, const int32_t* 
       keys[(size_t)cur[(size_t)(u - r0)]++] =
           ((uint64_t)(uint32_t)dst[k] << 32) | (uint64_t)(w ? w[k] : 0u);
     }
-  });
+  }))
+    return fail(GI_ERR_OUT_OF_MEMORY, "host allocation failed");
   // sort and de-duplicate rows; kept[v] = distinct neighbours of v
   std::vector<int64_t> kept((size_t)n, 0);
   run([&](unsigned t) {
@@ -462,12 +474,13 @@ static gi_status build_segments(gi_graph* g, int p, int strategy) {
   struct HostSeg {
     std::vector<int32_t> soff, sidx, sdst, chunks;
     std::vector<int4> tab;
+    bool failed = false;
   };
   const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   for (int w0 = 0; w0 < p; w0 += nth) {
     const int w1 = std::min(p, w0 + nth);
     std::vector<HostSeg> hs((size_t)(w1 - w0));
-    auto work = [&](int i) {
+    auto build_one = [&](int i) {
       HostSeg& h = hs[(size_t)(i - w0)];
       const int32_t lo = (int32_t)bound[(size_t)i], hi = (int32_t)bound[(size_t)i + 1];
       h.soff.push_back(0);
@@ -484,10 +497,19 @@ static gi_status build_segments(gi_graph* g, int p, int strategy) {
       h.tab = make_pr_table(h.soff.data(), (int)h.sdst.size(), g->pr_cap_e, g->pr_cap_v,
                             &h.chunks);
     };
+    auto work = [&](int i) {
+      try {
+        build_one(i);
+      } catch (...) {
+        hs[(size_t)(i - w0)].failed = true;
+      }
+    };
     std::vector<std::thread> pool;
     for (int i = w0 + 1; i < w1; ++i) pool.emplace_back(work, i);
     work(w0);
     for (auto& th : pool) th.join();
+    for (const HostSeg& h : hs)
+      if (h.failed) return fail(GI_ERR_OUT_OF_MEMORY, "host allocation failed (segments)");
     for (int i = w0; i < w1; ++i) {
       const HostSeg& h = hs[(size_t)(i - w0)];
       SegDev& sg = g->segs[(size_t)i];
