@@ -406,31 +406,48 @@ __device__ void dense_push_range(const DenseSet& fr, int vb, int ve, int first_b
   }
 }
 
-// One workgroup over the words [wb, we) of a sparse bitvector frontier:
-// BT words are read at a time, their members are listed in LDS (a
-// workgroup prefix sum of the words' popcounts gives each word its slots;
-// at most kList members per pass) and expanded BT members per group, so
-// empty stretches cost one read and sparse words no idle lanes.  s_v: LDS
-// for kPushList ints, supplied by the caller.
+// One workgroup over the words [wb, we) of a sparse bitvector frontier.
+// Words are read kPushGroup * BT at a time (kPushGroup independent loads in
+// flight per thread); a workgroup prefix sum of their popcounts gives each
+// member a slot in an LDS list, and the list is expanded BT members per
+// group, so one dependent chain (word, list, row bounds, edges) serves the
+// whole group and sparse words leave no lanes idle.  Groups with more than
+// kList members are listed and expanded in passes of kList.  s_v: LDS for
+// kPushList ints, supplied by the caller.
 constexpr int kPushList = 4096;
+constexpr int kPushGroup = 4;
+
 template <int BT, class Visit>
 __device__ void push_words(const uint64_t* bv, int wb, int we, int n, const int32_t* off,
                            Visit& vis, int skip_deg, int* s_v) {
   constexpr int kList = kPushList;
+  constexpr int G = kPushGroup;
   __shared__ int sh[4];
   const int tid = threadIdx.x;
-  for (int tile = wb; tile < we; tile += BT) {
-    const int w = tile + tid;
-    const uint64_t x = w < we ? bv[w] : 0ull;
+  for (int grp = wb; grp < we; grp += G * BT) {
+    uint64_t x[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      const int w = grp + q * BT + tid;
+      x[q] = w < we ? bv[w] : 0ull;
+    }
+    int own = 0;
+#pragma unroll
+    for (int q = 0; q < G; ++q) own += __popcll(x[q]);
     int total;
-    const int first = block_excl_scan<BT, int>(__popcll(x), &total);
+    const int first = block_excl_scan<BT, int>(own, &total);  // total: workgroup-uniform
     for (int base = 0; base < total; base += kList) {
       // this thread's members with list index in [base, base + kList)
-      uint64_t y = x;
-      for (int j = first; y; ++j) {
-        const int b = __ffsll((long long)y) - 1;
-        y &= y - 1;
-        if (j >= base && j < base + kList) s_v[j - base] = (w << 6) + b;
+      int j = first;
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        uint64_t y = x[q];
+        const int w = grp + q * BT + tid;
+        for (; y; ++j) {
+          const int b = __ffsll((long long)y) - 1;
+          y &= y - 1;
+          if (j >= base && j < base + kList) s_v[j - base] = (w << 6) + b;
+        }
       }
       __syncthreads();
       const int cnt = min(kList, total - base);
