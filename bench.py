@@ -1009,12 +1009,33 @@ def run_prec(args, torch, dev):
         cpu, detail
 
 
+def gpu_clocks():
+    """Current shader and memory clock levels as rocm-smi reports them (clocks
+    are not pinned).  Read in a child process before this process touches
+    the GPU; any failure is reported as text."""
+    import shutil
+    import subprocess
+    exe = shutil.which("rocm-smi") or "/opt/rocm/bin/rocm-smi"
+    try:
+        r = subprocess.run([exe, "--showclocks", "--json"], capture_output=True,
+                           text=True, timeout=30)
+        data = json.loads(r.stdout)
+    except Exception as e:  # noqa: BLE001 - the reading is informational
+        return {"error": str(e)[:200]}
+    out = {}
+    for card, kv in data.items():
+        if isinstance(kv, dict):
+            out[card] = {k: v for k, v in kv.items() if "sclk" in k or "mclk" in k}
+    return out or {"error": (r.stderr or r.stdout)[:200]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported (the library is a "
               "single-device build)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    clocks = gpu_clocks()
     import torch
     dev = torch.device("cuda:0")
     if args.copy_calib_mb > 0:
@@ -1042,6 +1063,7 @@ def main():
     else:
         res = run_sssp(args, torch, dev)
     value, unit, ms_step, dtype, config, roof, cpu, extra = res
+    extra = dict(extra or {}, gpu_clocks_at_start=clocks)
     if roof and roof.get("traffic") is None:
         roof["traffic"] = profile_traffic(roof["kernel"])
     line = {"metric": METRIC, "value": round(value, 4), "unit": unit, "n_gpus": 1,
