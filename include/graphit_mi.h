@@ -474,7 +474,11 @@ gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, const gi_tas
  * grid their fastest size, caps those sizes at 64, 32 and 16, plans each
  * with XCD-local and with spread placement, and times each whole batch
  * (median of reps launches).  Keeps the workgroup size, task sizes,
- * placement and plan of the fastest whole batch.
+ * placement and plan of the fastest whole batch, then refines it along
+ * the critical path: tasks that end in the last tenth of a timed launch
+ * and take at least a third of it get twice the workgroups (at most 256),
+ * the plan is rebuilt from the measured task durations, and the change is
+ * kept while the whole batch gets at least 1% faster (up to four rounds).
  * Tasks with fixed workgroups keep them.  The timing launches write the
  * tasks' outputs (with correct results).
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
