@@ -2774,11 +2774,13 @@ static gi_status batch_time_all(gi_batch* b, int reps, float* ms) {
 }
 
 // Critical-path refinement of a timed plan: the batch ends when its last
-// task ends, so the tasks that finish in the last tenth of the run and
-// take at least a third of it get twice the workgroups (up to 256, tasks
-// with fixed workgroups excepted), the plan is rebuilt with every task's
-// measured duration as its estimate, and the change is kept only if the
-// whole batch gets at least 1% faster.  At most four rounds.
+// task ends, so the tasks that finish in the last tenth of the run and take
+// at least a third of it are resized: first to twice their workgroups (up
+// to 256), else to half (a task whose steps are bound by its own barriers
+// can finish sooner on fewer workgroups); tasks with fixed workgroups keep
+// them.  The plan is rebuilt with every task's measured duration as its
+// estimate, and a resize is kept only if the whole batch gets at least 1%
+// faster.  At most four rounds.
 static gi_status batch_refine_critical(gi_batch* b, int reps) {
   gi_status st;
   const size_t nt = b->tasks.size();
@@ -2798,31 +2800,45 @@ static gi_status batch_refine_critical(gi_batch* b, int reps) {
     if (!(span > 0.0)) return GI_OK;
     const std::vector<int> k_old = b->k;
     const std::vector<double> est_old = b->est;
-    bool boosted = false;
+    std::vector<double> dur(nt);
+    std::vector<char> crit(nt, 0);
+    bool any = false;
     for (size_t i = 0; i < nt; ++i) {
-      const double d = (double)(c[i].t_end - c[i].t_begin);
-      b->est[i] = std::max(d, 0.0) / (double)b->clock_khz;  // ms
-      if (b->tasks[i].workgroups > 0 || b->k[i] >= kmax) continue;
-      if ((double)(c[i].t_end - t0) > 0.9 * span && d > span / 3.0) {
-        b->k[i] = std::min(kmax, 2 * b->k[i]);
-        b->est[i] *= (double)k_old[i] / (double)b->k[i];
-        boosted = true;
+      const double d = std::max(0.0, (double)(c[i].t_end - c[i].t_begin));
+      dur[i] = d / (double)b->clock_khz;  // ms
+      crit[i] = b->tasks[i].workgroups == 0 && (double)(c[i].t_end - t0) > 0.9 * span &&
+                d > span / 3.0;
+      any = any || crit[i];
+    }
+    if (!any) return GI_OK;
+    bool kept = false;
+    for (int dir : {2, -2}) {  // double, else halve
+      bool changed = false;
+      for (size_t i = 0; i < nt; ++i) {
+        b->k[i] = k_old[i];
+        b->est[i] = dur[i];
+        if (!crit[i]) continue;
+        const int k2 = dir > 0 ? std::min(kmax, 2 * k_old[i]) : std::max(1, k_old[i] / 2);
+        if (k2 == k_old[i]) continue;
+        b->k[i] = k2;
+        b->est[i] = dur[i] * (double)k_old[i] / (double)k2;
+        changed = true;
+      }
+      if (!changed) continue;
+      float ms2 = 0.0f;
+      if ((st = batch_plan(b)) != GI_OK) return st;
+      if ((st = batch_time_all(b, reps, &ms2)) != GI_OK) return st;
+      if (ms2 < 0.99f * ms) {
+        ms = ms2;
+        kept = true;
+        break;
       }
     }
-    if (!boosted) {
-      b->k = k_old;
-      b->est = est_old;
-      return GI_OK;
-    }
-    float ms2 = 0.0f;
-    if ((st = batch_plan(b)) != GI_OK) return st;
-    if ((st = batch_time_all(b, reps, &ms2)) != GI_OK) return st;
-    if (!(ms2 < 0.99f * ms)) {
+    if (!kept) {
       b->k = k_old;
       b->est = est_old;
       return batch_plan(b);
     }
-    ms = ms2;
   }
   return GI_OK;
 }
