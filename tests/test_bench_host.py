@@ -1,0 +1,73 @@
+"""Host-side logic of bench.py: the algorithmic byte counts per step (the
+formulas of the measurement plan, checked on hand-made traces), the lookup
+of committed hardware-counter figures (valid only while the kernel sources
+hash to the recorded value), the clock reading's failure path, and the
+single-GPU contract."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_bfs_step_bytes_push_and_pull():
+    n = 1024
+    # step 0 push: |F| = 1, D_F = 10, |F'| = 10
+    # step 1 pull: |F| = 10, so 11 vertices are visited and U = n - 11;
+    #   E = 300 in-edges scanned, |F'| = 500
+    # step 2 push: |F| = 500, D_F = 40, |F'| = 0 (last step)
+    dirs, fs, ds, es = [0, 2, 0], [1, 10, 500], [10, 4000, 40], [10, 300, 40]
+    got = bench.bfs_step_bytes(n, dirs, fs, ds, es)
+    assert got[0] == 12 * 1 + 8 * 10 + 8 * 10
+    assert got[1] == 3 * n // 8 + 8 * (n - 11) + 4 * 300 + 4 * 500
+    assert got[2] == 12 * 500 + 8 * 40 + 0
+
+
+def test_cc_step_bytes_push_and_pull():
+    n = 4096
+    dirs, fs, ds, es = [2, 0], [n, 7], [0, 0], [50000, 30]
+    got = bench.cc_step_bytes(n, dirs, fs, ds, es)
+    assert got[0] == 4 * (n + 1) + 4 * 50000 + 12 * n + n // 4
+    assert got[1] == 16 * 7 + 8 * 30 + 0
+
+
+def test_sssp_step_bytes():
+    assert bench.sssp_step_bytes([0, 0], [3, 5], [0, 0], [12, 20]) == [12 * 3 + 12 * 12,
+                                                                       12 * 5 + 12 * 20]
+
+
+def test_profile_traffic_follows_the_source_hash(tmp_path, monkeypatch):
+    # the committed figure is read while the sources match
+    real = bench.profile_traffic("k_batch")
+    assert real is None or real > 0
+    assert bench.profile_traffic("no_such_kernel") is None
+    # a copy of the tree whose batch source differs: the figure is stale
+    csrc = os.path.join(ROOT, "paper_1805_00923_amd", "csrc")
+    fake = tmp_path / "paper_1805_00923_amd" / "csrc"
+    shutil.copytree(csrc, fake)
+    shutil.copytree(os.path.join(ROOT, "profiles"), tmp_path / "profiles")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    if real is not None:
+        assert bench.profile_traffic("k_batch") == real
+    with open(fake / "batch.hip", "a") as f:
+        f.write("\n// changed\n")
+    assert bench.profile_traffic("k_batch") is None
+
+
+def test_gpu_clocks_reports_failure_as_text():
+    c = bench.gpu_clocks()
+    assert isinstance(c, dict) and c
+    if "error" in c:
+        assert isinstance(c["error"], str)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
