@@ -1029,6 +1029,26 @@ def gpu_clocks():
     return out or {"error": (r.stderr or r.stdout)[:200]}
 
 
+def host_info():
+    """Logical core count, CPU model and memory of the host (the oracle's
+    baseline uses one thread of it)."""
+    model, mem_gb = "unknown CPU", 0.0
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal:"):
+                    mem_gb = int(line.split()[1]) / 1024.0 / 1024.0
+                    break
+    except OSError:
+        pass
+    return "%d logical cores, %s, %.0f GiB RAM" % (os.cpu_count() or 0, model, mem_gb)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -1064,6 +1084,8 @@ def main():
         res = run_sssp(args, torch, dev)
     value, unit, ms_step, dtype, config, roof, cpu, extra = res
     extra = dict(extra or {}, gpu_clocks_at_start=clocks)
+    if cpu:
+        cpu = dict(cpu, sample=cpu["sample"] + "; host: " + host_info())
     if roof and roof.get("traffic") is None:
         roof["traffic"] = profile_traffic(roof["kernel"])
     line = {"metric": METRIC, "value": round(value, 4), "unit": unit, "n_gpus": 1,

@@ -66,6 +66,11 @@ def test_gpu_clocks_reports_failure_as_text():
         assert isinstance(c["error"], str)
 
 
+def test_host_info_names_cores_and_memory():
+    h = bench.host_info()
+    assert "logical cores" in h and "GiB RAM" in h
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
