@@ -1015,6 +1015,10 @@ def gpu_clocks():
     the GPU; any failure is reported as text."""
     import shutil
     import subprocess
+    # under rocprofv3 a child would inherit the profiler's preloaded library
+    if "rocprof" in os.environ.get("LD_PRELOAD", "") or any(
+            k.startswith("ROCPROF") for k in os.environ):
+        return {"skipped": "running under a profiler"}
     exe = shutil.which("rocm-smi") or "/opt/rocm/bin/rocm-smi"
     try:
         r = subprocess.run([exe, "--showclocks", "--json"], capture_output=True,

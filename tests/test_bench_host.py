@@ -59,11 +59,17 @@ def test_profile_traffic_follows_the_source_hash(tmp_path, monkeypatch):
     assert bench.profile_traffic("k_batch") is None
 
 
-def test_gpu_clocks_reports_failure_as_text():
+def test_gpu_clocks_reports_failure_as_text(monkeypatch):
+    monkeypatch.delenv("LD_PRELOAD", raising=False)
     c = bench.gpu_clocks()
     assert isinstance(c, dict) and c
     if "error" in c:
         assert isinstance(c["error"], str)
+
+
+def test_gpu_clocks_skipped_under_a_profiler(monkeypatch):
+    monkeypatch.setenv("ROCPROF_OUTPUT_PATH", "/tmp/x")
+    assert bench.gpu_clocks() == {"skipped": "running under a profiler"}
 
 
 def test_host_info_names_cores_and_memory():
