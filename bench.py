@@ -1015,9 +1015,9 @@ def gpu_clocks():
     the GPU; any failure is reported as text."""
     import shutil
     import subprocess
-    # under rocprofv3 a child would inherit the profiler's preloaded library
-    if "rocprof" in os.environ.get("LD_PRELOAD", "") or any(
-            k.startswith("ROCPROF") for k in os.environ):
+    # under rocprofv3 (which sets ROCPROF* variables) a child would inherit
+    # the profiler's preloaded library
+    if any(k.startswith("ROCPROF") for k in os.environ):
         return {"skipped": "running under a profiler"}
     exe = shutil.which("rocm-smi") or "/opt/rocm/bin/rocm-smi"
     try:
