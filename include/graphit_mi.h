@@ -477,8 +477,9 @@ gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, const gi_tas
  * placement and plan of the fastest whole batch, then refines it along
  * the critical path: tasks that end in the last tenth of a timed launch
  * and take at least a third of it get twice the workgroups (at most 256),
- * the plan is rebuilt from the measured task durations, and the change is
- * kept while the whole batch gets at least 1% faster (up to four rounds).
+ * else half, the plan is rebuilt from the measured task durations, and a
+ * resize is kept only if the whole batch gets at least 1% faster (up to
+ * four rounds).
  * Tasks with fixed workgroups keep them.  The timing launches write the
  * tasks' outputs (with correct results).
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
