@@ -6,10 +6,11 @@ log step time over the valid schedules, with Adam (Kingma and Ba, "Adam: A
 Method for Stochastic Optimization", ICLR 2015, Algorithm 1 with bias
 correction).  The forward pass is three matrix products; the backward pass
 is the chain rule written out layer by layer.  Pinned by finite differences
-and closed forms in tests/test_oracle_pins.py.
+and closed forms in tests/test_oracle_mlp_pins.py.
 
 Parameter vector layout (row-major): W1[12][64] b1[64] W2[64][64] b2[64]
-W3[64][4] b3[4].  Features are standardised, (x - mu) / sd, before W1.
+W3[64][4] b3[4].  Features are standardised, (x - mu) / sd, before W1; at
+inference they may first be clamped to the training records' range.
 Also: the per-step selector features of BFS and CC, recomputed from the
 oracle's own traversal.
 """
