@@ -102,8 +102,19 @@ enum { GI_SEG_FIXED_VERTEX_COUNT = 0, GI_SEG_EDGE_AWARE_VERTEX_COUNT = 1 };
  *                    partial-sum buffer, then sums the partials (with 8
  *                    segments each of the 8 XCDs gathers from one segment,
  *                    which stays in its L2)
+ *   cc_adjacency     how connected components reads edges both ways
+ *                    (GI_CC_ADJ_*): AUTO (0) uses the symmetric copy when its
+ *                    2m entries fit 32-bit offsets and the direct form
+ *                    otherwise; SYMMETRIC (1) builds on first use a device
+ *                    copy holding each vertex's out-row then its in-row
+ *                    (2m entries; GI_ERR_OVERFLOW from gi_cc above 2^31-1);
+ *                    DIRECT (2) builds no copy: push expands a frontier
+ *                    vertex's out-row and in-row where they are, pull
+ *                    reduces the CSR and CSC destination blocks separately
+ *                    and merges the two minima of a vertex by atomic minimum
  * Use gi_schedule_init for defaults; gi_set_schedule returns
  * GI_ERR_UNSUPPORTED for a combination it does not offer. */
+enum { GI_CC_ADJ_AUTO = 0, GI_CC_ADJ_SYMMETRIC = 1, GI_CC_ADJ_DIRECT = 2 };
 typedef struct gi_schedule {
   int32_t direction;
   int32_t dense_frontier;
@@ -115,7 +126,8 @@ typedef struct gi_schedule {
   int32_t block_threads;
   uint32_t sssp_delta;
   int32_t segments_concurrent;
-  int32_t reserved[6];
+  int32_t cc_adjacency;
+  int32_t reserved[5];
 } gi_schedule;
 
 /* Per-run statistics of the last algorithm call on a graph. */

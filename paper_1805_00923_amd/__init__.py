@@ -48,6 +48,9 @@ BITVECTOR = 0
 BOOLMAP = 1
 FIXED_VERTEX_COUNT = 0
 EDGE_AWARE_VERTEX_COUNT = 1
+CC_ADJ_AUTO = 0
+CC_ADJ_SYMMETRIC = 1
+CC_ADJ_DIRECT = 2
 MAX_TRACE = 4096
 
 
@@ -63,7 +66,7 @@ class Schedule(ctypes.Structure):
                 ("hybrid_divisor", ctypes.c_int32), ("steps_per_sync", ctypes.c_int32),
                 ("pull_block_edges", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("sssp_delta", ctypes.c_uint32), ("segments_concurrent", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("cc_adjacency", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

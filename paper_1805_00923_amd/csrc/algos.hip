@@ -196,6 +196,31 @@ struct CcVisit {
   }
 };
 
+// SparsePush over the direct adjacency: slot j of vertex u's row is its
+// j-th out-neighbour for j < outdeg(u), else its (j - outdeg(u))-th
+// in-neighbour, so the frontier's out+in degrees give the slots as with the
+// symmetric copy.
+struct CcVisitDirect {
+  const int32_t* out_off;
+  const int32_t* out_idx;
+  const int32_t* in_off;
+  const int32_t* in_idx;
+  const int32_t* cur;
+  int32_t* nxt;
+  DenseSet next;
+  long long work = 0;
+  __device__ __forceinline__ void operator()(int u, int j, bool valid) {
+    if (!valid) return;
+    const int ob = out_off[u], od = out_off[u + 1] - ob;
+    const int v = j < od ? out_idx[ob + j] : in_idx[in_off[u] + (j - od)];
+    ++work;
+    const int lu = cur[u];
+    if (lu >= nxt[v]) return;
+    const int old = atomicMin(&nxt[v], lu);
+    if (lu < old && old == cur[v]) next.insert(v);
+  }
+};
+
 // Pull over destination blocks of the symmetric adjacency: the block's
 // neighbour labels are staged in LDS, then the rows' minima are taken by an
 // edge-parallel segmented minimum; vertices whose label drops join the next
@@ -211,7 +236,13 @@ __device__ long long cc_pull(const CcArgs& c, int* lds) {
   int* lds_min = lds_cur + kCcCapV;
   __shared__ int red[BT / kWave];
   long long work = 0;
-  const RowBlocks& rb = c.rows;
+  // With the direct adjacency the entries of the out-row blocks come first,
+  // then those of the in-row blocks; a vertex's two rows are then reduced by
+  // different blocks, which merge by atomic minimum.
+  const int nt1 = c.rows.ntab, ntab = nt1 + (c.direct ? c.rows_in.ntab : 0);
+  auto entry = [&](int t) -> int4 {
+    return t < nt1 ? c.rows.table[t] : c.rows_in.table[t - nt1];
+  };
   const int32_t* cur = c.cur;
   const int tid = threadIdx.x, lane = __lane_id();
   // In the first round every label is still the vertex id, so a
@@ -221,10 +252,11 @@ __device__ long long cc_pull(const CcArgs& c, int* lds) {
   const bool ids = c.ctl->steps == 1;
   auto label_of = [cur, ids](int u) -> int { return ids ? u : cur[u]; };
   // the next entry is fetched while the current block is processed
-  int4 nx = blockIdx.x < (unsigned)rb.ntab ? rb.table[blockIdx.x] : make_int4(0, 0, 0, 0);
-  for (int t = blockIdx.x; t < rb.ntab; t += gridDim.x) {
+  int4 nx = (int)blockIdx.x < ntab ? entry(blockIdx.x) : make_int4(0, 0, 0, 0);
+  for (int t = blockIdx.x; t < ntab; t += gridDim.x) {
     const int4 r = nx;
-    if (t + (int)gridDim.x < rb.ntab) nx = rb.table[t + gridDim.x];
+    if (t + (int)gridDim.x < ntab) nx = entry(t + gridDim.x);
+    const RowBlocks& rb = t < nt1 ? c.rows : c.rows_in;
     if (r.y < 0) {
       // chunk -(r.y + 1) of the long row r.x: workgroup minimum over at
       // most kCcCapE edges (four loads in flight per thread), merged by an
@@ -306,6 +338,20 @@ __device__ long long cc_pull(const CcArgs& c, int* lds) {
       }
     }
     __syncthreads();
+    if (c.direct) {
+      // the vertex's other row may be reduced concurrently: only a lower
+      // label is written, by atomic minimum (nxt equals cur at the start of
+      // the round, so the first lowering sees cur and adds the vertex)
+      for (int k = tid; k < nr; k += BT) {
+        const int lv = lds_cur[k], mn = lds_min[k];
+        if (mn < lv) {
+          const int old = atomicMin(&c.nxt[kb + k], mn);
+          if (mn < old && old == lv) c.next.insert(kb + k);
+        }
+      }
+      __syncthreads();
+      continue;
+    }
     // vertex updates, one row per thread: the rows a wave finishes are
     // consecutive, so their frontier bits take at most two atomic ORs
     for (int k0 = 0; k0 < nr; k0 += BT) {
@@ -469,6 +515,19 @@ __global__ __launch_bounds__(BT) void k_cc_step(CcArgs c, ExpandArgs x) {
   long long work = 0;
   if (mode == MODE_DENSE_PULL) {
     work = c.nseg > 1 && c.ctl->seg ? cc_pull_seg<BT>(c, lds) : cc_pull<BT>(c, lds);
+  } else if (c.direct) {
+    if (mode == MODE_SPARSE_PUSH) {
+      CcVisitDirect vis{c.g.out_off, c.g.out_idx, c.g.in_off, c.g.in_idx, c.cur, c.nxt, c.next};
+      expand_chunks<BT, CH>(x, vis, lds);
+      work = vis.work;
+    } else {
+      // DensePush over the out-rows, then over the in-rows
+      CcVisit vo{c.g.out_idx, c.cur, c.nxt, c.next};
+      dense_push_expand<BT>(c.fr, c.g.n, c.g.out_off, vo);
+      CcVisit vi{c.g.in_idx, c.cur, c.nxt, c.next};
+      dense_push_expand<BT>(c.fr, c.g.n, c.g.in_off, vi);
+      work = vo.work + vi.work;
+    }
   } else {
     CcVisit vis{c.sym_idx, c.cur, c.nxt, c.next};
     if (mode == MODE_SPARSE_PUSH) expand_chunks<BT, CH>(x, vis, lds);

@@ -101,6 +101,10 @@ struct gi_graph {
   int32_t* sym_idx = nullptr;
   int4* sym_table = nullptr;
   int sym_ntab = 0;
+  // CC over the CSR and CSC rows directly: their destination blocks
+  int4* ccd_out_table = nullptr;
+  int4* ccd_in_table = nullptr;
+  int ccd_out_ntab = 0, ccd_in_ntab = 0;
   std::vector<SegDev> segs;
   double* pr_acc = nullptr;
   PrRows* seg_rows = nullptr;  // device copy of the segments' row blocks
@@ -629,6 +633,8 @@ static gi_status validate_schedule(const gi_graph* g, const gi_schedule* s) {
     return fail(GI_ERR_UNSUPPORTED, "pull_block_edges outside [64, 8192]");
   if (s->segments_concurrent != 0 && s->segments_concurrent != 1)
     return fail(GI_ERR_UNSUPPORTED, "segments_concurrent must be 0 or 1");
+  if (s->cc_adjacency < GI_CC_ADJ_AUTO || s->cc_adjacency > GI_CC_ADJ_DIRECT)
+    return fail(GI_ERR_UNSUPPORTED, "cc_adjacency %d not offered", s->cc_adjacency);
   if (s->block_threads != 0 && s->block_threads != 64 && s->block_threads != 128 &&
       s->block_threads != 256 && s->block_threads != 512)
     return fail(GI_ERR_UNSUPPORTED, "block_threads must be 0, 64, 128, 256 or 512");
@@ -1279,16 +1285,44 @@ extern "C" gi_status gi_bfs(gi_graph* g, int32_t src, int32_t* level, int32_t* p
   return read_loop_stats(g, ALG_BFS);
 }
 
+// Whether CC reads the CSR and CSC rows directly (no symmetric copy).
+static bool cc_direct(const gi_graph* g) {
+  if (g->sched.cc_adjacency == GI_CC_ADJ_DIRECT) return true;
+  if (g->sched.cc_adjacency == GI_CC_ADJ_SYMMETRIC) return false;
+  return 2 * g->m > (int64_t)INT32_MAX;
+}
+
+// Destination blocks of the CSR and CSC rows for the direct CC pull, built
+// on first use.
+static gi_status ensure_cc_direct(gi_graph* g) {
+  if (g->ccd_out_table) return GI_OK;
+  std::vector<int32_t> out_off((size_t)g->n + 1, 0);
+  for (size_t v = 0; v < (size_t)g->n; ++v) out_off[v + 1] = out_off[v] + g->h_outdeg[v];
+  std::vector<int4> to = make_cc_table(out_off.data(), g->n, kCcCapE, kCcCapV);
+  std::vector<int4> ti = make_cc_table(g->h_in_off.data(), g->n, kCcCapE, kCcCapV);
+  gi_status st;
+  int4 *dto = nullptr, *dti = nullptr;
+  if ((st = dev_alloc(g, g->allocs, &dto, std::max<size_t>(1, to.size()))) != GI_OK) return st;
+  if ((st = dev_alloc(g, g->allocs, &dti, std::max<size_t>(1, ti.size()))) != GI_OK) return st;
+  if (!to.empty() && (st = upload(to.data(), dto, to.size() * sizeof(int4))) != GI_OK) return st;
+  if (!ti.empty() && (st = upload(ti.data(), dti, ti.size() * sizeof(int4))) != GI_OK) return st;
+  g->ccd_out_table = dto;
+  g->ccd_in_table = dti;
+  g->ccd_out_ntab = (int)to.size();
+  g->ccd_in_ntab = (int)ti.size();
+  return GI_OK;
+}
+
 // Symmetric adjacency for CC, built on the device on first use.
 static gi_status ensure_sym(gi_graph* g, hipStream_t s) {
   if (g->sym_idx) return GI_OK;
   const size_t N = (size_t)g->n;
-  // 2m entries under int32 offsets: larger graphs are refused before any
-  // allocation or launch
+  // 2m entries under int32 offsets: larger graphs take the direct form
   if (2 * g->m > (int64_t)INT32_MAX)
     return fail(GI_ERR_OVERFLOW,
-                "connected components needs the symmetric adjacency (2m = %lld entries), "
-                "which exceeds 32-bit offsets", (long long)(2 * g->m));
+                "the symmetric adjacency (2m = %lld entries) exceeds 32-bit offsets; "
+                "schedule cc_adjacency AUTO or DIRECT reads the rows directly",
+                (long long)(2 * g->m));
   std::vector<int32_t> off(N + 1, 0);
   for (size_t v = 0; v < N; ++v)
     off[v + 1] = off[v] + g->h_outdeg[v] + (g->h_in_off[v + 1] - g->h_in_off[v]);
@@ -1305,11 +1339,12 @@ static gi_status ensure_sym(gi_graph* g, hipStream_t s) {
   return GI_OK;
 }
 
-// Source segments of the symmetric adjacency for the segmented CC pull
-// (configApplyNumSSG applied to CC): p ranges of equal vertex count, or of
-// equal out+in degree sums (edge-aware); segment x keeps, for every vertex
-// with a neighbour in range x, those neighbours.  Built on first use from a
-// host copy of the symmetric adjacency.
+// Source segments for the segmented CC pull (configApplyNumSSG applied to
+// CC): p ranges of equal vertex count, or of equal out+in degree sums
+// (edge-aware); segment x keeps, for every vertex with a neighbour (out- or
+// in-) in range x, those neighbours, out-row first.  Built on first use on
+// the host from the CSR and CSC rows, so it needs no symmetric copy; each
+// segment's entries must fit 32-bit offsets.
 static gi_status ensure_cc_segments(gi_graph* g, int p, int strategy, hipStream_t s) {
   if (g->ccsegs && g->ccseg_p == p && g->ccseg_strategy == strategy) return GI_OK;
   HIP_TRY(hipStreamSynchronize(s));
@@ -1320,15 +1355,20 @@ static gi_status ensure_cc_segments(gi_graph* g, int p, int strategy, hipStream_
   g->ccseg_p = 0;
   const int32_t n = g->n;
   const size_t N = (size_t)n;
-  std::vector<int32_t> off(N + 1);
-  HIP_TRY(hipMemcpy(off.data(), g->sym_off, 4 * (N + 1), hipMemcpyDeviceToHost));
-  std::vector<int32_t> idx((size_t)off[N]);
-  if (!idx.empty())
-    HIP_TRY(hipMemcpy(idx.data(), g->sym_idx, 4 * idx.size(), hipMemcpyDeviceToHost));
+  const int32_t* ooff = g->h_out_off.data();
+  const int32_t* ioff = g->h_in_off.data();
+  const int32_t* iidx = g->h_in_idx.data();
+  std::vector<int32_t> oidx((size_t)g->m);
+  if (!oidx.empty())
+    HIP_TRY(hipMemcpy(oidx.data(), g->out_idx, 4 * oidx.size(), hipMemcpyDeviceToHost));
+  auto udeg = [&](size_t v) -> int64_t {
+    return (int64_t)(ooff[v + 1] - ooff[v]) + (int64_t)(ioff[v + 1] - ioff[v]);
+  };
   // segment of each vertex
   std::vector<int32_t> segof(N);
   {
-    int64_t total = off[N], acc = 0;
+    const int64_t total = 2 * g->m;
+    int64_t acc = 0;
     int x = 0;
     const int64_t per = ((int64_t)n + p - 1) / p;
     for (int32_t v = 0; v < n; ++v) {
@@ -1336,7 +1376,7 @@ static gi_status ensure_cc_segments(gi_graph* g, int p, int strategy, hipStream_
         x = (int)(v / per);
       } else {
         while (x < p - 1 && acc * p >= total * (x + 1)) ++x;
-        acc += off[(size_t)v + 1] - off[(size_t)v];
+        acc += udeg((size_t)v);
       }
       segof[(size_t)v] = x;
     }
@@ -1345,24 +1385,34 @@ static gi_status ensure_cc_segments(gi_graph* g, int p, int strategy, hipStream_
       sdst((size_t)p);
   std::vector<int32_t> cnt((size_t)p, 0), touched;
   for (int32_t v = 0; v < n; ++v) {
-    const int32_t b = off[(size_t)v], e = off[(size_t)v + 1];
-    if (b == e) continue;
+    const int32_t ob = ooff[v], oe = ooff[v + 1], ib = ioff[v], ie = ioff[v + 1];
+    if (ob == oe && ib == ie) continue;
     touched.clear();
-    for (int32_t j = b; j < e; ++j) {
-      const int32_t x = segof[(size_t)idx[(size_t)j]];
+    auto count = [&](int32_t u) {
+      const int32_t x = segof[(size_t)u];
       if (cnt[(size_t)x]++ == 0) touched.push_back(x);
-    }
+    };
+    for (int32_t j = ob; j < oe; ++j) count(oidx[(size_t)j]);
+    for (int32_t j = ib; j < ie; ++j) count(iidx[(size_t)j]);
     std::sort(touched.begin(), touched.end());
     for (int32_t x : touched) {
+      std::vector<int32_t>& so = soff[(size_t)x];
+      if ((int64_t)so.back() + cnt[(size_t)x] > (int64_t)INT32_MAX)
+        return fail(GI_ERR_OVERFLOW, "CC segment %d exceeds 2^31-1 entries; use more segments", x);
       sdst[(size_t)x].push_back(v);
-      soff[(size_t)x].push_back(soff[(size_t)x].back() + cnt[(size_t)x]);
+      so.push_back(so.back() + cnt[(size_t)x]);
       cnt[(size_t)x] = 0;
     }
-    for (int32_t j = b; j < e; ++j) {
-      const int32_t u = idx[(size_t)j];
+    for (int32_t j = ob; j < oe; ++j) {
+      const int32_t u = oidx[(size_t)j];
+      sidx[(size_t)segof[(size_t)u]].push_back(u);
+    }
+    for (int32_t j = ib; j < ie; ++j) {
+      const int32_t u = iidx[(size_t)j];
       sidx[(size_t)segof[(size_t)u]].push_back(u);
     }
   }
+  std::vector<int32_t>().swap(oidx);
   std::vector<CcSeg> hs((size_t)p);
   gi_status st;
   for (int x = 0; x < p; ++x) {
@@ -1399,7 +1449,8 @@ extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   gi_status st = check_learned(g);
   if (st != GI_OK) return st;
-  st = ensure_sym(g, s);
+  const bool direct = cc_direct(g);
+  st = direct ? ensure_cc_direct(g) : ensure_sym(g, s);
   if (st != GI_OK) return st;
   // segments: the schedule's, or for the learned choice the automatic
   // count (2 MiB of labels each) that its S3 stands for
@@ -1423,9 +1474,18 @@ extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
   c.nxt = labs[1];
   c.fr = frontier_set(g, 0);
   c.next = frontier_set(g, 1);
-  c.sym_off = g->sym_off;
-  c.sym_idx = g->sym_idx;
-  c.rows = RowBlocks{g->sym_table, g->sym_ntab, g->sym_off, g->sym_idx};
+  c.direct = direct ? 1 : 0;
+  if (direct) {
+    c.sym_off = nullptr;
+    c.sym_idx = nullptr;
+    c.rows = RowBlocks{g->ccd_out_table, g->ccd_out_ntab, g->out_off, g->out_idx};
+    c.rows_in = RowBlocks{g->ccd_in_table, g->ccd_in_ntab, g->in_off, g->in_idx};
+  } else {
+    c.sym_off = g->sym_off;
+    c.sym_idx = g->sym_idx;
+    c.rows = RowBlocks{g->sym_table, g->sym_ntab, g->sym_off, g->sym_idx};
+    c.rows_in = RowBlocks{nullptr, 0, nullptr, nullptr};
+  }
   c.segs = nullptr;
   c.nseg = 1;
   c.seg_min = nullptr;

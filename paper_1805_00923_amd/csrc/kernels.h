@@ -96,9 +96,13 @@ struct CcArgs {
   int32_t* nxt;            // labels L_{k+1}
   DenseSet fr;             // vertices whose label changed in the previous round
   DenseSet next;           // vertices whose label changes in this round
-  const int32_t* sym_off;  // symmetric adjacency (out-row then in-row)
-  const int32_t* sym_idx;
-  RowBlocks rows;          // destination blocks of the symmetric adjacency
+  const int32_t* sym_off;  // symmetric adjacency (out-row then in-row); NULL
+  const int32_t* sym_idx;  // when `direct`
+  RowBlocks rows;          // destination blocks of the symmetric adjacency, or
+                           // with `direct` of the out-rows (CSR)
+  RowBlocks rows_in;       // with `direct`: destination blocks of the in-rows (CSC)
+  int direct;              // 1: no symmetric copy; every round reads a vertex's
+                           // out-row and in-row where they are (CSR and CSC)
   const CcSeg* segs;       // segmented pull: nseg source segments (nseg > 1), and
   int nseg;                // their partial minima, nseg x n (0xffffffff: none)
   uint32_t* seg_min;

@@ -280,7 +280,8 @@ struct ExpandArgs {
   const int32_t* ids;
   const long long* excl;
   const int32_t* chunk_item;
-  const int32_t* off;     // row offsets of the adjacency being expanded
+  const int32_t* off;     // row offsets of the adjacency being expanded; NULL:
+                          // vis(u, j) gets the slot j within u's row instead
   Control* ctl;
 };
 
@@ -306,7 +307,7 @@ __device__ void expand_chunks(const ExpandArgs& a, Visit& vis, int* lds) {
       const int u = a.ids[i0 + k];
       s_u[k] = u;
       s_start[k] = (int)(a.excl[i0 + k] - s0);
-      s_row[k] = a.off[u];
+      s_row[k] = a.off ? a.off[u] : 0;  // NULL off: visitors get the slot within the row
     }
     __syncthreads();
     for (int r = 0; r < s_end; r += BT) {

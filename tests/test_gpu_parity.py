@@ -199,6 +199,31 @@ def test_cc_segmented_pull(cfg):
         g.set_schedule()
 
 
+DIRECT_CC_SCHEDULES = [dict(direction=d, dense_frontier=f) for d in range(5) for f in (0, 1)] + [
+    dict(num_segments=8), dict(num_segments=3, segment_strategy=1, direction=2),
+    dict(num_segments=64, hybrid_divisor=2, dense_frontier=1)]
+
+
+@pytest.mark.parametrize("sched", DIRECT_CC_SCHEDULES,
+                         ids=lambda c: "_".join("%s%s" % (k[:8], v) for k, v in c.items()))
+def test_cc_direct_adjacency(sched):
+    """CC over the CSR and CSC rows directly (no symmetric copy: push
+    expands both rows of a frontier vertex, pull reduces the out-row and
+    in-row blocks separately and merges them by atomic minimum) gives the
+    oracle's labels and round count under every direction, frontier kind
+    and segmentation."""
+    gi = _gi()
+    for el, g, og in fam_graphs():
+        say("cc direct %s %s" % (el.name, sched))
+        g.set_schedule(cc_adjacency=gi.CC_ADJ_DIRECT, **sched)
+        lab = run_cc(g)
+        ref, rounds = oracle.cc(og)
+        assert np.array_equal(lab, ref), el.name
+        assert g.stats().steps == rounds, el.name
+    for el, g, _ in fam_graphs():
+        g.set_schedule()
+
+
 # ---------------------------------------------------------------------- SSSP
 
 def weighted_families():

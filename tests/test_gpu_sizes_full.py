@@ -82,6 +82,26 @@ def test_rmat22_cc():
     assert g.stats().steps == rounds
 
 
+@pytest.mark.parametrize("sched", [dict(direction=d) for d in range(5)] + [
+    dict(direction=3, dense_frontier=1), dict(num_segments=8, segment_strategy=1, hybrid_divisor=4)],
+    ids=lambda c: "_".join("%s%s" % (k[:8], v) for k, v in c.items()))
+def test_rmat22_cc_direct(sched):
+    """CC without the symmetric copy (the form graphs with 2m > 2^31 - 1
+    take) at RMAT-22 under every direction, both frontier kinds and the
+    benchmark's segmented schedule."""
+    import paper_1805_00923_amd as gi
+    el, g, og = rmat22()
+    if "rmat22_cc" not in _G:
+        _G["rmat22_cc"] = oracle.cc(og)
+    ref, rounds = _G["rmat22_cc"]
+    g.set_schedule(cc_adjacency=gi.CC_ADJ_DIRECT, **sched)
+    say("rmat22 cc direct %s" % sched)
+    lab = run_cc(g)
+    assert np.array_equal(lab, ref)
+    assert g.stats().steps == rounds
+    g.set_schedule()
+
+
 def test_rmat22_pagerank():
     el, g, og = rmat22()
     g.set_schedule()
