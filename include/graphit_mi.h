@@ -570,6 +570,23 @@ gi_status gi_frontier_sparse_to_bitvec(int32_t n, const int32_t* ids, int32_t co
  * number of members.  ids needs room for every member. */
 gi_status gi_frontier_bitvec_to_sparse(int32_t n, const uint64_t* bv, int32_t* ids,
                                        int32_t* count_dev, void* stream);
+/* Allocation-free variant of gi_frontier_bitvec_to_sparse, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, layout and result
+ * as gi_frontier_bitvec_to_sparse; the caller still owns bv, ids and
+ * *count_dev.  Its scratch (one int32 per bitvector word) is a fixed device
+ * array of GI_NOALLOC_MAX_WORDS words (8 MiB) inside the library, one copy
+ * per GPU, held until the process ends; no call allocates or frees memory.
+ * n above 64 * GI_NOALLOC_MAX_WORDS (134,217,728 vertices) is refused with
+ * GI_ERR_UNSUPPORTED before any device work, as is a device ordinal of
+ * GI_NOALLOC_MAX_DEVICES or more.  All calls on one GPU share that GPU's
+ * scratch: calls that overlap on one GPU (different streams, or host threads
+ * without ordering between them) race and give undefined results; calls on
+ * one stream are ordered and safe. */
+#define GI_NOALLOC_MAX_WORDS (1 << 21)
+#define GI_NOALLOC_MAX_DEVICES 64
+gi_status gi_frontier_bitvec_to_sparse_noalloc(int32_t n, const uint64_t* bv, int32_t* ids,
+                                               int32_t* count_dev, void* stream);
 /* Bitvector <-> bool map. */
 gi_status gi_frontier_bitvec_to_boolmap(int32_t n, const uint64_t* bv, uint8_t* bm, void* stream);
 gi_status gi_frontier_boolmap_to_bitvec(int32_t n, const uint8_t* bm, uint64_t* bv, void* stream);

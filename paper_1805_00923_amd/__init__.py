@@ -52,6 +52,7 @@ CC_ADJ_AUTO = 0
 CC_ADJ_SYMMETRIC = 1
 CC_ADJ_DIRECT = 2
 MAX_TRACE = 4096
+NOALLOC_MAX_WORDS = 1 << 21
 
 
 class GiError(RuntimeError):
@@ -153,6 +154,7 @@ _SIGS = {
     "gi_get_step_times": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp]),
     "gi_frontier_sparse_to_bitvec": (ctypes.c_int, [_i32, _vp, _i32, _vp, _vp]),
     "gi_frontier_bitvec_to_sparse": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp]),
+    "gi_frontier_bitvec_to_sparse_noalloc": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp]),
     "gi_frontier_bitvec_to_boolmap": (ctypes.c_int, [_i32, _vp, _vp, _vp]),
     "gi_frontier_boolmap_to_bitvec": (ctypes.c_int, [_i32, _vp, _vp, _vp]),
     "gi_frontier_degree_sum": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp]),
@@ -401,6 +403,14 @@ def sparse_to_bitvec(n, ids, count, bv, stream=None):
 def bitvec_to_sparse(n, bv, ids, count_dev, stream=None):
     _check(lib.gi_frontier_bitvec_to_sparse(int(n), _dptr(bv), _dptr(ids), _dptr(count_dev),
                                             _stream(stream)))
+    return ids
+
+
+def bitvec_to_sparse_noalloc(n, bv, ids, count_dev, stream=None):
+    """gi_frontier_bitvec_to_sparse_noalloc: the same conversion with the
+    library's fixed scratch (no device allocation)."""
+    _check(lib.gi_frontier_bitvec_to_sparse_noalloc(int(n), _dptr(bv), _dptr(ids),
+                                                    _dptr(count_dev), _stream(stream)))
     return ids
 
 

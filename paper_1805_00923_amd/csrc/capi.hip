@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -1815,6 +1816,53 @@ extern "C" gi_status gi_frontier_bitvec_to_sparse(int32_t n, const uint64_t* bv,
   const int rc = launch_bitvec_to_sparse(n, bv, ids, count_dev, scratch, s);
   HIP_TRY(hipFreeAsync(scratch, s));
   if (rc != 0) return fail(GI_ERR_DEVICE, "bitvector compaction launch failed");
+  return GI_OK;
+}
+
+// Scratch of the allocation-free conversion: one count per bitvector word,
+// in a file-scope device array of fixed size.  Every GPU the library runs
+// on holds its own copy until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is a stand-in, not a device
+// address): it looks up each device's address once with
+// hipGetSymbolAddress and passes that.
+static __device__ __align__(256) int32_t scratch[GI_NOALLOC_MAX_WORDS];
+
+static std::mutex g_noalloc_mu;
+static int32_t* g_noalloc_ptr[GI_NOALLOC_MAX_DEVICES] = {};
+
+static gi_status noalloc_scratch(int32_t** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= GI_NOALLOC_MAX_DEVICES)
+    return fail(GI_ERR_UNSUPPORTED, "device %d beyond the %d the allocation-free calls serve", dev,
+                GI_NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(GI_ERR_DEVICE, "hipGetSymbolAddress returned no address for the scratch");
+    g_noalloc_ptr[dev] = static_cast<int32_t*>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return GI_OK;
+}
+
+extern "C" gi_status gi_frontier_bitvec_to_sparse_noalloc(int32_t n, const uint64_t* bv,
+                                                          int32_t* ids, int32_t* count_dev,
+                                                          void* stream) {
+  if (n < 1 || !bv || !ids || !count_dev) return fail(GI_ERR_INVALID_ARG, "bad frontier arguments");
+  const int64_t W = ((int64_t)n + 63) / 64;
+  if (W > GI_NOALLOC_MAX_WORDS)
+    return fail(GI_ERR_UNSUPPORTED,
+                "n = %d needs %lld bitvector words; the allocation-free conversion holds at most "
+                "%d (n <= %lld)",
+                n, (long long)W, GI_NOALLOC_MAX_WORDS, 64LL * GI_NOALLOC_MAX_WORDS);
+  int32_t* sc = nullptr;
+  gi_status st = noalloc_scratch(&sc);
+  if (st != GI_OK) return st;
+  // every word count is written before it is read: nothing to clear
+  if (launch_bitvec_to_sparse(n, bv, ids, count_dev, sc, static_cast<hipStream_t>(stream)) != 0)
+    return fail(GI_ERR_DEVICE, "bitvector compaction launch failed");
   return GI_OK;
 }
 
