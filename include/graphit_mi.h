@@ -112,9 +112,28 @@ enum { GI_SEG_FIXED_VERTEX_COUNT = 0, GI_SEG_EDGE_AWARE_VERTEX_COUNT = 1 };
  *                    vertex's out-row and in-row where they are, pull
  *                    reduces the CSR and CSC destination blocks separately
  *                    and merges the two minima of a vertex by atomic minimum
+ *   vertex_order     PageRank DensePull (GI_ORDER_*): GIVEN (0) pulls over
+ *                    the caller's numbering; OUT_DEGREE (1) pulls over a copy
+ *                    of the in-adjacency renumbered by decreasing out-degree
+ *                    (built on first use, 4(n + 1) + 4m + 8n bytes), so that
+ *                    the sources gathered most often share cache lines and
+ *                    the hottest sit in LDS; ranks come back under the
+ *                    caller's numbering.  Unsegmented only (num_segments 1):
+ *                    the ordering replaces the id-range segments
+ *   pull_hot_sources with OUT_DEGREE: the highest-out-degree sources whose
+ *                    contributions every workgroup copies into LDS per
+ *                    iteration (-1 = library default, the most that fits
+ *                    beside the waves' tile buffers in one workgroup's LDS;
+ *                    0 = none; else rounded down to a multiple of 64 and
+ *                    capped the same way)
+ *   pull_items_per_thread with OUT_DEGREE: merge-path items (row ends plus
+ *                    edges) per thread, 4, 8 or 16 (0 = library default 8;
+ *                    16 only with block_threads <= 512)
+ * block_threads may also be 1024 with vertex_order OUT_DEGREE.
  * Use gi_schedule_init for defaults; gi_set_schedule returns
  * GI_ERR_UNSUPPORTED for a combination it does not offer. */
 enum { GI_CC_ADJ_AUTO = 0, GI_CC_ADJ_SYMMETRIC = 1, GI_CC_ADJ_DIRECT = 2 };
+enum { GI_ORDER_GIVEN = 0, GI_ORDER_OUT_DEGREE = 1 };
 typedef struct gi_schedule {
   int32_t direction;
   int32_t dense_frontier;
@@ -127,7 +146,10 @@ typedef struct gi_schedule {
   uint32_t sssp_delta;
   int32_t segments_concurrent;
   int32_t cc_adjacency;
-  int32_t reserved[5];
+  int32_t vertex_order;
+  int32_t pull_hot_sources;
+  int32_t pull_items_per_thread;
+  int32_t reserved[2];
 } gi_schedule;
 
 /* Per-run statistics of the last algorithm call on a graph. */

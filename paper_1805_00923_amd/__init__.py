@@ -51,6 +51,8 @@ EDGE_AWARE_VERTEX_COUNT = 1
 CC_ADJ_AUTO = 0
 CC_ADJ_SYMMETRIC = 1
 CC_ADJ_DIRECT = 2
+ORDER_GIVEN = 0
+ORDER_OUT_DEGREE = 1
 MAX_TRACE = 4096
 NOALLOC_MAX_WORDS = 1 << 21
 
@@ -67,7 +69,9 @@ class Schedule(ctypes.Structure):
                 ("hybrid_divisor", ctypes.c_int32), ("steps_per_sync", ctypes.c_int32),
                 ("pull_block_edges", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("sssp_delta", ctypes.c_uint32), ("segments_concurrent", ctypes.c_int32),
-                ("cc_adjacency", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("cc_adjacency", ctypes.c_int32), ("vertex_order", ctypes.c_int32),
+                ("pull_hot_sources", ctypes.c_int32), ("pull_items_per_thread", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -107,6 +107,18 @@ struct gi_graph {
   int4* ccd_in_table = nullptr;
   int ccd_out_ntab = 0, ccd_in_ntab = 0;
   std::vector<SegDev> segs;
+  // degree-ordered in-adjacency and its merge-path tiles (PageRank with
+  // vertex_order = GI_ORDER_OUT_DEGREE; built on first use)
+  std::vector<void*> ord_allocs;  // the ordered copy (graph lifetime once built)
+  std::vector<void*> ordt_allocs; // tiles and split slots (rebuilt when the tile size changes)
+  int32_t *ord_off = nullptr, *ord_idx = nullptr, *ord_outdeg = nullptr, *ord_old = nullptr;
+  std::vector<int32_t> h_ord_off;
+  int32_t ord_nsrc = 0;            // vertices with out-degree > 0 (new ids [0, ord_nsrc))
+  int2 *ord_tiles = nullptr, *ord_tslot = nullptr;
+  int32_t* ord_srow = nullptr;
+  double* ord_sacc = nullptr;
+  int ord_ntiles = 0, ord_T = 0, ord_nslots = 0;
+  int ncu = 0;                     // compute units of the device
   double* pr_acc = nullptr;
   PrRows* seg_rows = nullptr;  // device copy of the segments' row blocks
   // frontier-loop workspace
@@ -558,6 +570,137 @@ static gi_status ensure_pr_segments(gi_graph* g, int p, int strategy) {
   return build_segments(g, p, strategy);
 }
 
+// Degree-ordered copy of the in-adjacency (PageRank, vertex_order =
+// GI_ORDER_OUT_DEGREE): new ids by decreasing out-degree, ties by id; row r
+// holds the new ids of the in-neighbours of old_id[r], sorted.
+static gi_status ensure_pr_order(gi_graph* g) {
+  if (g->ord_off) return GI_OK;
+  const int32_t n = g->n;
+  const int64_t m = g->m;
+  std::vector<int32_t> old_id((size_t)n), new_id((size_t)n), deg((size_t)n);
+  {
+    // counting sort by out-degree, highest first, stable in the old id
+    std::vector<int64_t> start((size_t)g->max_out + 2, 0);
+    for (int32_t v = 0; v < n; ++v) ++start[(size_t)(g->max_out - g->h_outdeg[(size_t)v]) + 1];
+    for (size_t b = 1; b < start.size(); ++b) start[b] += start[b - 1];
+    for (int32_t v = 0; v < n; ++v) {
+      const int64_t r = start[(size_t)(g->max_out - g->h_outdeg[(size_t)v])]++;
+      old_id[(size_t)r] = v;
+      new_id[(size_t)v] = (int32_t)r;
+    }
+  }
+  int32_t nsrc = 0;
+  for (int32_t r = 0; r < n; ++r) {
+    deg[(size_t)r] = g->h_outdeg[(size_t)old_id[(size_t)r]];
+    if (deg[(size_t)r] > 0) nsrc = r + 1;
+  }
+  std::vector<int32_t>& off = g->h_ord_off;
+  off.assign((size_t)n + 1, 0);
+  for (int32_t r = 0; r < n; ++r) {
+    const int32_t v = old_id[(size_t)r];
+    off[(size_t)r + 1] = off[(size_t)r] + (g->h_in_off[(size_t)v + 1] - g->h_in_off[(size_t)v]);
+  }
+  std::vector<int32_t> idx((size_t)m);
+  const unsigned nth = host_workers();
+  const bool ok = run_workers([&](unsigned t) {
+    const int32_t lo = worker_row(n, t, nth), hi = worker_row(n, t + 1, nth);
+    for (int32_t r = lo; r < hi; ++r) {
+      const int32_t v = old_id[(size_t)r];
+      int32_t* dst = idx.data() + off[(size_t)r];
+      const int32_t b = g->h_in_off[(size_t)v], e = g->h_in_off[(size_t)v + 1];
+      for (int32_t k = b; k < e; ++k) dst[k - b] = new_id[(size_t)g->h_in_idx[(size_t)k]];
+      std::sort(dst, dst + (e - b));
+    }
+  });
+  if (!ok) return fail(GI_ERR_OUT_OF_MEMORY, "host allocation failed (ordered in-adjacency)");
+  gi_status st;
+  if ((st = dev_alloc(g, g->ord_allocs, &g->ord_off, (size_t)n + 1)) != GI_OK ||
+      (st = dev_alloc(g, g->ord_allocs, &g->ord_idx, std::max<size_t>(1, (size_t)m))) != GI_OK ||
+      (st = dev_alloc(g, g->ord_allocs, &g->ord_outdeg, (size_t)n)) != GI_OK ||
+      (st = dev_alloc(g, g->ord_allocs, &g->ord_old, (size_t)n)) != GI_OK) {
+    free_list(g->ord_allocs);
+    g->ord_off = nullptr;
+    return st;
+  }
+  if ((st = upload(off.data(), g->ord_off, 4 * ((size_t)n + 1))) != GI_OK ||
+      (st = upload(idx.data(), g->ord_idx, 4 * (size_t)m)) != GI_OK ||
+      (st = upload(deg.data(), g->ord_outdeg, 4 * (size_t)n)) != GI_OK ||
+      (st = upload(old_id.data(), g->ord_old, 4 * (size_t)n)) != GI_OK) {
+    free_list(g->ord_allocs);
+    g->ord_off = nullptr;
+    return st;
+  }
+  g->ord_nsrc = nsrc;
+  return GI_OK;
+}
+
+// Merge-path tiles of T items over the ordered in-adjacency (n row ends and
+// m edges; the end of row r is item off[r + 1] + r).  Tile t starts at the
+// row r holding item t T and the edge t T - r.  A row with edges in one tile
+// and its end (or more edges) in a later one gets a split slot.
+static gi_status ensure_pr_order_tiles(gi_graph* g, int T) {
+  if (g->ord_tiles && g->ord_T == T) return GI_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  free_list(g->ordt_allocs);
+  g->ord_tiles = nullptr;
+  const int32_t n = g->n;
+  const int64_t items = (int64_t)n + g->m;
+  const int64_t nt64 = (items + T - 1) / T;
+  if (nt64 > INT32_MAX - 1) return fail(GI_ERR_OVERFLOW, "too many PageRank tiles");
+  const int nt = (int)nt64;
+  const int32_t* off = g->h_ord_off.data();
+  std::vector<int2> tiles((size_t)nt + 1);
+  for (int t = 0; t < nt; ++t) {
+    const int64_t d = (int64_t)t * T;
+    // rows whose end item lies before d
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+      const int32_t mid = lo + (hi - lo) / 2;
+      if ((int64_t)off[(size_t)mid + 1] + mid < d) lo = mid + 1;
+      else hi = mid;
+    }
+    tiles[(size_t)t] = make_int2(lo, (int32_t)(d - lo));
+  }
+  tiles[(size_t)nt] = make_int2(n, (int32_t)g->m);
+  std::vector<int2> tslot((size_t)nt, make_int2(-1, -1));
+  std::vector<int32_t> srow;
+  for (int t = 0; t < nt; ++t) {
+    const int32_t r0 = tiles[(size_t)t].x, e0 = tiles[(size_t)t].y;
+    const int32_t r1 = tiles[(size_t)t + 1].x, e1 = tiles[(size_t)t + 1].y;
+    if (r0 < n && off[(size_t)r0] < e0) {
+      if (srow.empty() || srow.back() != r0)
+        return fail(GI_ERR_DEVICE, "PageRank tiles: inconsistent split row");
+      tslot[(size_t)t].x = (int32_t)srow.size() - 1;
+    }
+    if (r1 < n && off[(size_t)r1] < e1) {
+      if (srow.empty() || srow.back() != r1) srow.push_back(r1);
+      tslot[(size_t)t].y = (int32_t)srow.size() - 1;
+    }
+  }
+  const size_t ns = std::max<size_t>(1, srow.size());
+  gi_status st;
+  if ((st = dev_alloc(g, g->ordt_allocs, &g->ord_tiles, tiles.size())) != GI_OK ||
+      (st = dev_alloc(g, g->ordt_allocs, &g->ord_tslot, tslot.size())) != GI_OK ||
+      (st = dev_alloc(g, g->ordt_allocs, &g->ord_srow, ns)) != GI_OK ||
+      (st = dev_alloc(g, g->ordt_allocs, &g->ord_sacc, ns)) != GI_OK) {
+    free_list(g->ordt_allocs);
+    g->ord_tiles = nullptr;
+    return st;
+  }
+  if ((st = upload(tiles.data(), g->ord_tiles, sizeof(int2) * tiles.size())) != GI_OK ||
+      (st = upload(tslot.data(), g->ord_tslot, sizeof(int2) * tslot.size())) != GI_OK ||
+      (st = upload(srow.data(), g->ord_srow, 4 * srow.size())) != GI_OK) {
+    free_list(g->ordt_allocs);
+    g->ord_tiles = nullptr;
+    return st;
+  }
+  HIP_TRY(hipMemset(g->ord_sacc, 0, sizeof(double) * ns));
+  g->ord_ntiles = nt;
+  g->ord_nslots = (int)srow.size();
+  g->ord_T = T;
+  return GI_OK;
+}
+
 static gi_status apply_schedule(gi_graph* g, const gi_schedule& s) {
   // only the PageRank block layout owns device tables here (segments are
   // built on first use): any other change is free
@@ -636,9 +779,32 @@ static gi_status validate_schedule(const gi_graph* g, const gi_schedule* s) {
     return fail(GI_ERR_UNSUPPORTED, "segments_concurrent must be 0 or 1");
   if (s->cc_adjacency < GI_CC_ADJ_AUTO || s->cc_adjacency > GI_CC_ADJ_DIRECT)
     return fail(GI_ERR_UNSUPPORTED, "cc_adjacency %d not offered", s->cc_adjacency);
-  if (s->block_threads != 0 && s->block_threads != 64 && s->block_threads != 128 &&
-      s->block_threads != 256 && s->block_threads != 512)
-    return fail(GI_ERR_UNSUPPORTED, "block_threads must be 0, 64, 128, 256 or 512");
+  if (s->vertex_order != GI_ORDER_GIVEN && s->vertex_order != GI_ORDER_OUT_DEGREE)
+    return fail(GI_ERR_UNSUPPORTED, "vertex_order %d not offered", s->vertex_order);
+  if (s->vertex_order == GI_ORDER_OUT_DEGREE) {
+    if (s->num_segments != 1)
+      return fail(GI_ERR_UNSUPPORTED, "vertex_order OUT_DEGREE pulls unsegmented (num_segments 1)");
+    if (s->block_threads != 0 && s->block_threads != 256 && s->block_threads != 512 &&
+        s->block_threads != 1024)
+      return fail(GI_ERR_UNSUPPORTED,
+                  "block_threads must be 0, 256, 512 or 1024 with vertex_order OUT_DEGREE");
+    if (s->pull_items_per_thread != 0 && s->pull_items_per_thread != 4 &&
+        s->pull_items_per_thread != 8 && s->pull_items_per_thread != 16)
+      return fail(GI_ERR_UNSUPPORTED, "pull_items_per_thread must be 0, 4, 8 or 16");
+    if (s->pull_items_per_thread == 16 && s->block_threads == 1024)
+      return fail(GI_ERR_UNSUPPORTED, "pull_items_per_thread 16 needs block_threads <= 512");
+    if (s->pull_hot_sources < -1)
+      return fail(GI_ERR_UNSUPPORTED, "pull_hot_sources must be -1, 0 or a count");
+  } else {
+    if (s->block_threads != 0 && s->block_threads != 64 && s->block_threads != 128 &&
+        s->block_threads != 256 && s->block_threads != 512)
+      return fail(GI_ERR_UNSUPPORTED, "block_threads must be 0, 64, 128, 256 or 512");
+    if (s->pull_items_per_thread != 0 || s->pull_hot_sources != 0)
+      return fail(GI_ERR_UNSUPPORTED,
+                  "pull_items_per_thread and pull_hot_sources need vertex_order OUT_DEGREE");
+  }
+  if (s->reserved[0] != 0 || s->reserved[1] != 0)
+    return fail(GI_ERR_UNSUPPORTED, "reserved schedule fields must be 0");
   (void)g;
   return GI_OK;
 }
@@ -668,6 +834,8 @@ extern "C" gi_status gi_graph_destroy(gi_graph* g) {
   free_list(g->sched_allocs);
   free_list(g->seg_allocs);
   free_list(g->ccseg_allocs);
+  free_list(g->ordt_allocs);
+  free_list(g->ord_allocs);
   free_list(g->allocs);
   for (void* q : {(void*)g->sel_p, (void*)g->sel_wb, (void*)g->sel_io})
     if (q) (void)hipFree(q);
@@ -876,8 +1044,10 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
   G_ALLOC(g->vis, W);
   G_ALLOC(g->far, W);
   G_ALLOC(g->lab, N);
-  G_ALLOC(g->contrib[0], N);
-  G_ALLOC(g->contrib[1], N);
+  // one slot past n: the ordered PageRank pull sends the stores of lanes
+  // without a row there, so that every lane issues the same stores
+  G_ALLOC(g->contrib[0], N + 1);
+  G_ALLOC(g->contrib[1], N + 1);
   G_ALLOC(g->part, kParts);
   G_ALLOC(g->blk, kMaxCount);
   G_ALLOC(g->fmin, kMaxCount);
@@ -1152,6 +1322,109 @@ static void pr_features(const gi_graph* g, float* x) {
 
 // 20-iteration (or `iters`) DensePull PageRank, unsegmented or over the
 // graph's segments.
+// Launch shape of the ordered pull: threads, items per thread, LDS sources
+// and workgroups.
+struct PrOrdShape {
+  int bt, u, hot, grid;
+};
+
+static gi_status pr_ord_shape(gi_graph* g, PrOrdShape* sh) {
+  sh->bt = g->sched.block_threads > 0 ? g->sched.block_threads : 256;
+  sh->u = g->sched.pull_items_per_thread > 0 ? g->sched.pull_items_per_thread : 8;
+  if (!g->ncu) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&g->ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  int maxlds = 0, dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  // LDS of the kernel besides the hot sources: per wave, the tile's row
+  // offsets, gathered contributions and FP64 row sums
+  const long long fixed = 4LL * (sh->bt / 64) * (4LL * 64 * sh->u + 2);
+  long long cap = ((long long)maxlds - fixed) / 4;
+  // never more than the sources that are gathered at all (rounded up to 64),
+  // nor past the end of the contribution array
+  const long long useful = ((long long)g->ord_nsrc + 63) / 64 * 64;
+  cap = std::min<long long>(cap, std::min<long long>(useful, (long long)g->n / 4 * 4));
+  cap = std::max<long long>(0, cap / 64 * 64);
+  long long hot = g->sched.pull_hot_sources;
+  if (hot < 0) {
+    // the most that one workgroup per CU leaves (LDS is per CU; the
+    // workgroup's waves share the hot sources, so one large workgroup
+    // beats several with smaller copies)
+    hot = cap;
+  }
+  hot = std::min<long long>(std::max<long long>(0, hot) / 64 * 64, cap);
+  sh->hot = (int)hot;
+  const int per = pr_ord_occupancy(sh->hot, sh->bt, sh->u);
+  if (per <= 0) return fail(GI_ERR_DEVICE, "occupancy query for the ordered PageRank pull failed");
+  sh->grid = per * g->ncu;
+  return GI_OK;
+}
+
+// DensePull PageRank over the degree-ordered in-adjacency (pr_order.hip).
+static gi_status pr_run_ordered(gi_graph* g, int32_t iters, float damping, float* ranks,
+                                hipStream_t s) {
+  gi_status st = ensure_pr_order(g);
+  if (st != GI_OK) return st;
+  PrOrdShape sh;
+  if ((st = pr_ord_shape(g, &sh)) != GI_OK) return st;
+  if ((st = ensure_pr_order_tiles(g, 64 * sh.u)) != GI_OK) return st;
+  PrOrdArgs a{};
+  a.off = g->ord_off;
+  a.idx = g->ord_idx;
+  a.tiles = g->ord_tiles;
+  a.tslot = g->ord_tslot;
+  a.srow = g->ord_srow;
+  a.sacc = g->ord_sacc;
+  a.nslots = g->ord_nslots;
+  a.outdeg = g->ord_outdeg;
+  a.old_id = g->ord_old;
+  a.n = g->n;
+  a.m = (int)g->m;
+  a.ntiles = g->ord_ntiles;
+  a.hot = sh.hot;
+  a.alpha = (double)damping;
+  a.base = (1.0 - (double)damping) / (double)g->n;
+  int launches = 1;
+  HIP_TRY(hipEventRecord(g->ev[0], s));
+  LAUNCH_TRY(launch_pr_init(g->n, g->ord_outdeg, g->contrib[0], ranks, iters == 0, s));
+  g->tev_count = 0;
+  for (int k = 0; k < iters; ++k) {
+    const bool last = k == iters - 1;
+    const StepEvents* te = step_events(g, k);
+    if (te) {
+      HIP_TRY(hipEventRecord(te->start, s));
+      HIP_TRY(hipEventRecord(te->main, s));
+    }
+    LAUNCH_TRY(launch_pr_ord(a, sh.bt, sh.u, sh.grid, g->contrib[k & 1], g->contrib[(k + 1) & 1],
+                             last ? ranks : nullptr, s));
+    LAUNCH_TRY(launch_pr_ord_split(a, g->contrib[(k + 1) & 1], last ? ranks : nullptr, s));
+    launches += a.nslots > 0 ? 2 : 1;
+    if (te) HIP_TRY(hipEventRecord(te->end, s));
+  }
+  HIP_TRY(hipEventRecord(g->ev[1], s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (g->timing_failed) return fail(GI_ERR_DEVICE, "PageRank: could not create timing events");
+  gi_status ts = read_kernel_ms(g, launches);
+  if (ts != GI_OK) return ts;
+  gi_run_stats& rs = g->stats;
+  rs.algorithm = ALG_PR;
+  rs.steps = iters;
+  rs.dense_steps = iters;
+  rs.edges_examined = (int64_t)iters * g->m;
+  rs.trace_len = std::min(iters, GI_MAX_TRACE);
+  for (int k = 0; k < rs.trace_len; ++k) {
+    rs.step_direction[k] = GI_DIR_DENSE_PULL;
+    rs.step_segmented[k] = 0;
+    rs.step_frontier[k] = g->n;
+    rs.step_degree_sum[k] = g->m;
+    rs.step_edges[k] = g->m;
+  }
+  return GI_OK;
+}
+
 static gi_status pr_run(gi_graph* g, int32_t iters, float damping, float* ranks, hipStream_t s,
                         bool segmented) {
   PrVertex pv;
@@ -1249,6 +1522,8 @@ extern "C" gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, floa
     segmented = io[kFeat + 2] - io[kFeat + 3] > kLearnedMargin;
     if (segmented && (st = ensure_segments(g)) != GI_OK) return st;
   }
+  if (g->sched.vertex_order == GI_ORDER_OUT_DEGREE && g->sched.direction != GI_DIR_LEARNED)
+    return pr_run_ordered(g, iters, damping, ranks, s);
   return pr_run(g, iters, damping, ranks, s, segmented);
 }
 

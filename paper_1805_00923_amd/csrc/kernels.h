@@ -323,6 +323,34 @@ int launch_pr_rows(const PrRows& r, int cap_e, int cap_v, int bt, int grid, cons
 int launch_pr_seg_final(int n, const PrVertex& pv, double* acc, float* cout, float* rank,
                         hipStream_t s);
 
+// PageRank over the degree-ordered in-adjacency, merge-path work split
+// (pr_order.hip).
+struct PrOrdArgs {
+  const int32_t* off;     // degree-ordered in-row offsets (n + 1)
+  const int32_t* idx;     // degree-ordered in-row source ids (m)
+  const int2* tiles;      // per tile (first row, first edge); entry ntiles = (n, m)
+  const int2* tslot;      // per tile: split slot of its first row (if that row
+                          // began in an earlier tile) and of its last row (if
+                          // it goes on in a later tile); -1 for none
+  const int32_t* srow;    // per split slot: its row
+  double* sacc;           // per split slot: parts summed so far (zero between passes)
+  int nslots;
+  const int32_t* outdeg;  // out-degree by new id
+  const int32_t* old_id;  // new id -> caller's id
+  int n;
+  int m;
+  int ntiles;
+  int hot;                // sources [0, hot) are read from LDS (multiple of 4)
+  double base;            // (1 - alpha) / n
+  double alpha;
+};
+
+size_t pr_ord_lds_bytes(int hot, int bt, int u);
+int pr_ord_occupancy(int hot, int bt, int u);  // workgroups per CU, -1 on error
+int launch_pr_ord(const PrOrdArgs& a, int bt, int u, int grid, const float* cin, float* cout,
+                  float* rank, hipStream_t s);
+int launch_pr_ord_split(const PrOrdArgs& a, float* cout, float* rank, hipStream_t s);
+
 int launch_sparse_to_bitvec(int n, const int32_t* ids, int count, uint64_t* bv, hipStream_t s);
 int launch_bitvec_to_sparse(int n, const uint64_t* bv, int32_t* ids, int32_t* count,
                             int32_t* scratch, hipStream_t s);

@@ -89,6 +89,13 @@ def test_pagerank_families_default():
     dict(num_segments=8, pull_block_edges=128), dict(num_segments=64, segment_strategy=1),
     dict(num_segments=8, segments_concurrent=1),
     dict(num_segments=3, segment_strategy=1, segments_concurrent=1, pull_block_edges=256),
+    # degree-ordered pull: LDS sources none, a few, default; every tile shape
+    dict(vertex_order=1), dict(vertex_order=1, pull_hot_sources=0),
+    dict(vertex_order=1, pull_hot_sources=64, pull_items_per_thread=4),
+    dict(vertex_order=1, pull_items_per_thread=16, block_threads=512),
+    dict(vertex_order=1, block_threads=1024, pull_items_per_thread=8),
+    dict(vertex_order=1, block_threads=1024, pull_items_per_thread=4, pull_hot_sources=0),
+    dict(vertex_order=1, block_threads=512, pull_items_per_thread=4, pull_hot_sources=100000),
 ], ids=lambda c: "_".join("%s%s" % (k[:8], v) for k, v in c.items()))
 def test_pagerank_schedules(cfg):
     for el, g, og in fam_graphs():
@@ -106,7 +113,12 @@ def test_pagerank_rmat16_workload():
     og = oracle.Graph(el)
     g = device_graph(el)
     ref = oracle.pagerank(og, 20, 0.85)
-    for cfg in (dict(), dict(num_segments=4), dict(num_segments=4, segment_strategy=1)):
+    for cfg in (dict(), dict(num_segments=4), dict(num_segments=4, segment_strategy=1),
+                dict(num_segments=8, segments_concurrent=1),
+                dict(num_segments=16, segments_concurrent=1),
+                dict(num_segments=8, segments_concurrent=1, segment_strategy=1),
+                dict(vertex_order=1), dict(vertex_order=1, block_threads=1024),
+                dict(vertex_order=1, pull_items_per_thread=16)):
         say("pr rmat16 %s" % cfg)
         g.set_schedule(**cfg)
         x = run_pr(g, 20)
@@ -379,3 +391,21 @@ def test_step_timing_covers_every_step_and_changes_nothing():
         g.set_schedule()
     g.bfs(int(s), __import__("torch").empty(g.n, dtype=__import__("torch").int32, device="cuda:0"))
     assert len(g.step_times()[0]) == 0
+
+
+def test_pagerank_ordered_schedule_checks():
+    """Combinations the degree-ordered pull does not offer are refused."""
+    gi = _gi()
+    el, g, og = fam_graphs()[8]
+    bad = [dict(vertex_order=2), dict(vertex_order=1, num_segments=4),
+           dict(vertex_order=1, block_threads=128), dict(vertex_order=1, pull_items_per_thread=5),
+           dict(vertex_order=1, block_threads=1024, pull_items_per_thread=16),
+           dict(vertex_order=1, pull_hot_sources=-2), dict(pull_hot_sources=64),
+           dict(pull_items_per_thread=8)]
+    for cfg in bad:
+        with pytest.raises(gi.GiError) as e:
+            g.set_schedule(**cfg)
+        assert e.value.status == gi.GI_ERR_UNSUPPORTED, cfg
+    g.set_schedule()
+    x = run_pr(g, 20)
+    assert pr_max_rel(x, oracle.pagerank(og, 20)) <= PR_RTOL

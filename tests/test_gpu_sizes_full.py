@@ -116,6 +116,12 @@ def test_rmat22_pagerank():
     say("rmat22 pagerank 8 concurrent segments")
     x = run_pr(g, 20)
     assert pr_max_rel(x, oracle.pagerank(og, 20, 0.85)) <= PR_RTOL
+    for cfg in (dict(vertex_order=1), dict(vertex_order=1, block_threads=1024),
+                dict(vertex_order=1, block_threads=512, pull_items_per_thread=16)):
+        g.set_schedule(**cfg)
+        say("rmat22 pagerank %s" % cfg)
+        x = run_pr(g, 20)
+        assert pr_max_rel(x, oracle.pagerank(og, 20, 0.85)) <= PR_RTOL, cfg
     g.set_schedule()
     _G.pop("rmat22", None)
 
