@@ -15,13 +15,29 @@
  *   any device work; on error nothing is enqueued and outputs are left
  *   unspecified.  gi_last_error() gives a message for the calling thread's
  *   last failing call.
- * - Algorithm calls enqueue their kernels on the given stream and then wait
- *   for that stream before returning (frontier loops read a completion flag
- *   back once per steps_per_sync steps); their device outputs are complete
- *   on return.
+ * - Stream order.  gi_pagerank and gi_batch_launch return once their
+ *   kernels are enqueued on the given stream; their outputs are complete
+ *   when that stream reaches them, and gi_sync_status (or reading the run's
+ *   statistics) waits for them.  The other algorithm calls return when
+ *   their outputs are complete: the frontier algorithms (gi_bfs, gi_cc,
+ *   gi_sssp, gi_prdelta, gi_bc) enqueue steps in batches and read a
+ *   completion flag back once per steps_per_sync steps, and
+ *   gi_pagerank_eigenvector reads its norms back; the batched persistent
+ *   kernel is the enqueue-only form of BFS, PageRank and SSSP
+ *   (gi_batch_launch).
+ * - Device memory.  Every device allocation of the library goes through one
+ *   path: a graph's core arrays come from the caller's workspace when one is
+ *   given to gi_graph_create_ex; everything else comes from the allocator
+ *   registered with gi_set_allocator (a torch program registers torch's
+ *   caching allocator, so torch owns that memory), or from hipMalloc when
+ *   none is registered.  The one exception is the per-call scratch of
+ *   gi_frontier_bitvec_to_sparse, taken stream-ordered with hipMallocAsync
+ *   (gi_frontier_bitvec_to_sparse_noalloc takes none).
  * - A gi_graph owns device copies of its adjacency and a workspace sized at
- *   creation.  It is not thread-safe: one call at a time per graph.  Distinct
- *   graphs may be used from distinct threads and streams.
+ *   creation.  It is not thread-safe: one call at a time per graph, and the
+ *   device work of one call must be ordered before the next call's (same
+ *   stream, or the caller synchronizes).  Distinct graphs may be used from
+ *   distinct threads and streams.
  * - Vertex ids are int32 in [0, n); edge counts are limited to 2^31-1 so that
  *   int32 offsets suffice (the evaluation notes the same 32-bit limit).
  */
@@ -202,6 +218,24 @@ gi_status gi_build_adjacency(int32_t n, int64_t nrec, const int32_t* src, const 
                              const uint32_t* w, int32_t* off, int32_t* idx, uint32_t* w_out,
                              int64_t* m_out);
 
+/* ---- device memory ----------------------------------------------------- */
+
+/* Allocator the library takes device memory from (see the conventions above).
+ *   alloc(bytes, device, ctx)   returns device memory of at least `bytes`
+ *                               bytes on HIP device `device`, 256-byte
+ *                               aligned, or NULL when it cannot
+ *   release(ptr, device, ctx)   gives back memory alloc returned
+ * Memory is released through the functions that allocated it, even if
+ * another allocator is registered meanwhile.  Pass NULL, NULL to go back to
+ * hipMalloc and hipFree.  Errors: INVALID_ARG when only one is NULL. */
+typedef void* (*gi_alloc_fn)(size_t bytes, int32_t device, void* ctx);
+typedef void (*gi_free_fn)(void* ptr, int32_t device, void* ctx);
+gi_status gi_set_allocator(gi_alloc_fn alloc, gi_free_fn release, void* ctx);
+
+/* Live device allocations of the library (workspace arrays not counted), and
+ * how many of them came from a registered allocator (may be NULL). */
+gi_status gi_live_allocations(int64_t* count, int64_t* from_registered);
+
 /* ---- graph on the device ---------------------------------------------- */
 
 /* Copy an adjacency to the device (section 3: edgeset with getOutNgh and
@@ -219,8 +253,45 @@ gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_off, const in
                           const uint32_t* out_w, const int32_t* in_off, const int32_t* in_idx,
                           const uint32_t* in_w, gi_graph** out);
 
+/* Where the adjacency arrays given to gi_graph_create_ex live. */
+enum { GI_PTR_HOST = 0, GI_PTR_DEVICE = 1 };
+
+/* Bytes of device memory gi_graph_create_ex takes from a caller's workspace
+ * for a graph of n vertices and m edges (weighted: nonzero when weights are
+ * given): the adjacency in both directions, degrees, and the frontier-loop
+ * buffers, each rounded up to 256 bytes.  An upper bound (it allows for the
+ * most hub vertices m edges can make).  Errors: INVALID_ARG, OVERFLOW. */
+gi_status gi_graph_workspace_size(int32_t n, int64_t m, int32_t weighted, size_t* bytes);
+
+/* gi_graph_create with the arrays on the host or the device, the graph's
+ * core arrays in a caller's workspace, and the copies on a caller's stream
+ * (same adjacency model as gi_graph_create, section 3).
+ *   ptr_kind         GI_PTR_HOST or GI_PTR_DEVICE: where out_off ... in_w
+ *                    live (all in the same place); device arrays are read
+ *                    on `stream` and staged to the host once, where they
+ *                    are validated and the schedule tables are built
+ *   workspace        device memory for the core arrays, 256-byte aligned,
+ *                    of workspace_bytes >= gi_graph_workspace_size(...), or
+ *                    NULL to take them from the allocator.  The caller keeps
+ *                    it alive until gi_graph_destroy; structures built on
+ *                    first use (segments, ordered copies, tables) still
+ *                    come from the allocator
+ *   stream           hipStream_t for the copies; the call returns when they
+ *                    are complete (the caller may free its arrays then)
+ * Errors: as gi_graph_create; INVALID_ARG for a bad ptr_kind, a misaligned
+ * workspace, or one smaller than the graph needs; DEVICE for a failed copy. */
+gi_status gi_graph_create_ex(int32_t n, int64_t m, const int32_t* out_off, const int32_t* out_idx,
+                             const uint32_t* out_w, const int32_t* in_off, const int32_t* in_idx,
+                             const uint32_t* in_w, int32_t ptr_kind, void* workspace,
+                             size_t workspace_bytes, void* stream, gi_graph** out);
+
 /* Release the graph and its device memory (NULL is a no-op). */
 gi_status gi_graph_destroy(gi_graph* g);
+
+/* Wait for the graph's last enqueued run (a call that returned after
+ * enqueue) and report a device error it met.  Errors: INVALID_ARG (NULL),
+ * DEVICE. */
+gi_status gi_sync_status(gi_graph* g);
 
 /* n, m, and the largest out- and in-degree. */
 gi_status gi_graph_info(const gi_graph* g, int32_t* n, int64_t* m, int32_t* max_out_degree,
@@ -249,7 +320,9 @@ int32_t gi_hybrid_choose_dense(int64_t frontier_size, int64_t frontier_degree_su
  * iterations, damping 0.85):
  *   x_0 = 1/n;  x_{k+1}[v] = (1-damping)/n + damping * sum_{u->v} x_k[u]/outdeg(u).
  * Runs DensePull (optionally segmented, num_segments > 1) regardless of the
- * direction field.  FP32 storage, FP64 accumulation.
+ * direction field.  FP32 storage, FP64 accumulation.  Returns once the
+ * iterations are enqueued on `stream` (ranks are complete when the stream
+ * reaches them; gi_get_run_stats and gi_sync_status wait for them).
  *   ranks  device out, n floats: x_iters.
  * Errors: INVALID_ARG (iters < 0, damping outside [0,1], NULL), DEVICE. */
 gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, float* ranks, void* stream);

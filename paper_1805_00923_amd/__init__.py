@@ -8,8 +8,11 @@ or ``__graft_entry__.build()``); importing this package without it raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -108,11 +111,20 @@ class RunStats(ctypes.Structure):
 
 # every symbol the header declares, with its ctypes signature
 _vp, _i32, _i64, _u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+# gi_alloc_fn / gi_free_fn
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p)
 _SIGS = {
     "gi_last_error": (ctypes.c_char_p, []),
     "gi_abi_version": (_i32, []),
     "gi_build_adjacency": (ctypes.c_int, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gi_graph_create": (ctypes.c_int, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "gi_graph_create_ex": (ctypes.c_int, [_i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp,
+                                          ctypes.c_size_t, _vp, _vp]),
+    "gi_graph_workspace_size": (ctypes.c_int, [_i32, _i64, _i32, _vp]),
+    "gi_set_allocator": (ctypes.c_int, [_ALLOC_FN, _FREE_FN, _vp]),
+    "gi_live_allocations": (ctypes.c_int, [_vp, _vp]),
+    "gi_sync_status": (ctypes.c_int, [_vp]),
     "gi_graph_destroy": (ctypes.c_int, [_vp]),
     "gi_graph_info": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "gi_graph_copy_in_adjacency": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
@@ -193,6 +205,62 @@ def _check(st):
         raise GiError(st, last_error())
 
 
+# ---- device memory: torch's caching allocator serves the library ---------
+
+def _torch_alloc(nbytes, device, ctx):
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), int(device))
+    except Exception:
+        return None  # the library reports GI_ERR_OUT_OF_MEMORY
+
+
+def _torch_free(ptr, device, ctx):
+    if sys.is_finalizing():
+        return  # the process is ending; torch may already be gone
+    import torch
+    try:
+        torch.cuda.caching_allocator_delete(ptr)
+    except Exception:
+        pass
+
+
+_TORCH_ALLOC = _ALLOC_FN(_torch_alloc)
+_TORCH_FREE = _FREE_FN(_torch_free)
+
+
+def use_torch_allocator(on=True):
+    """Take the library's device memory from torch's caching allocator (the
+    default for this binding), or from hipMalloc (on=False)."""
+    if on:
+        _check(lib.gi_set_allocator(_TORCH_ALLOC, _TORCH_FREE, None))
+    else:
+        _check(lib.gi_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
+
+
+def live_allocations():
+    """(live device allocations of the library, how many came from the
+    registered allocator)."""
+    c, r = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.gi_live_allocations(ctypes.byref(c), ctypes.byref(r)))
+    return c.value, r.value
+
+
+use_torch_allocator(True)
+
+# objects holding device memory, released before torch shuts down at exit
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _release_at_exit():
+    for obj in list(_LIVE):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
 def _dptr(x):
     """Device address of a torch CUDA tensor (or an int address)."""
     if x is None:
@@ -254,10 +322,26 @@ def default_schedule(**kw):
     return s
 
 
-class Graph:
-    """A graph on the device (CSR + CSC, optional uint32 weights)."""
+PTR_HOST = 0
+PTR_DEVICE = 1
 
-    def __init__(self, n, out_off, out_idx, out_w=None, in_off=None, in_idx=None, in_w=None):
+
+def workspace_size(n, m, weighted=False):
+    """Bytes gi_graph_create_ex takes from a caller's workspace."""
+    b = ctypes.c_size_t()
+    _check(lib.gi_graph_workspace_size(int(n), int(m), int(bool(weighted)), ctypes.byref(b)))
+    return b.value
+
+
+class Graph:
+    """A graph on the device (CSR + CSC, optional uint32 weights).
+
+    workspace: an optional torch CUDA tensor of at least workspace_size(n, m,
+    weighted) bytes holding the graph's core arrays (kept alive with the
+    graph); stream: the stream of the adjacency copies."""
+
+    def __init__(self, n, out_off, out_idx, out_w=None, in_off=None, in_idx=None, in_w=None,
+                 workspace=None, stream=None):
         self._h = ctypes.c_void_p(None)
         out_off = np.ascontiguousarray(out_off, np.int32)
         out_idx = np.ascontiguousarray(out_idx, np.int32)
@@ -266,13 +350,48 @@ class Graph:
         in_idx = None if in_idx is None else np.ascontiguousarray(in_idx, np.int32)
         in_w = None if in_w is None else np.ascontiguousarray(in_w, np.uint32)
         m = int(out_idx.shape[0])
-        _check(lib.gi_graph_create(int(n), m, _hptr(out_off), _hptr(out_idx), _hptr(out_w),
-                                   _hptr(in_off), _hptr(in_idx), _hptr(in_w),
-                                   ctypes.byref(self._h)))
-        self.n = int(n)
-        self.m = m
+        self._create(int(n), m, PTR_HOST, _hptr(out_off), _hptr(out_idx), _hptr(out_w),
+                     _hptr(in_off), _hptr(in_idx), _hptr(in_w), workspace, stream)
         self.weighted = out_w is not None
         self.out_off = out_off  # host copy of the row offsets (out-degrees)
+
+    def _create(self, n, m, kind, oo, oi, ow, io, ii, iw, workspace, stream):
+        ws, wsb = None, 0
+        if workspace is not None:
+            ws, wsb = _dptr(workspace), workspace.numel() * workspace.element_size()
+        # host arrays: copies on the NULL stream unless one is given; device
+        # arrays: read in the order of torch's current stream by default
+        st = _stream(stream) if (stream is not None or kind == PTR_DEVICE) else None
+        _check(lib.gi_graph_create_ex(n, m, oo, oi, ow, io, ii, iw, kind, ws, wsb, st,
+                                      ctypes.byref(self._h)))
+        self._workspace = workspace  # kept alive with the graph
+        self.n = n
+        self.m = m
+        _LIVE.add(self)
+
+    @classmethod
+    def from_tensors(cls, n, out_off, out_idx, out_w=None, in_off=None, in_idx=None, in_w=None,
+                     workspace=None, stream=None):
+        """A graph from adjacency arrays in device memory (torch CUDA tensors,
+        int32 offsets and ids, int32 or uint32 weights)."""
+        import torch
+        ok = {torch.int32} | ({torch.uint32} if hasattr(torch, "uint32") else set())
+        for t in (out_off, out_idx, out_w, in_off, in_idx, in_w):
+            if t is not None and (not t.is_cuda or not t.is_contiguous() or t.dtype not in ok):
+                raise ValueError("adjacency tensors must be contiguous 32-bit CUDA tensors")
+        g = cls.__new__(cls)
+        g._h = ctypes.c_void_p(None)
+        m = int(out_idx.numel())
+        g._create(int(n), m, PTR_DEVICE, _dptr(out_off), _dptr(out_idx), _dptr(out_w),
+                  _dptr(in_off), _dptr(in_idx), _dptr(in_w), workspace, stream)
+        g.weighted = out_w is not None
+        g.out_off = out_off.cpu().numpy()
+        return g
+
+    def sync(self):
+        """gi_sync_status: wait for the last enqueued run, raise on a device
+        error."""
+        _check(lib.gi_sync_status(self._h))
 
     @classmethod
     def from_edges(cls, n, src, dst, w=None, build_in=True):
@@ -435,6 +554,7 @@ class Selector:
     def __init__(self, seed=1):
         self._h = ctypes.c_void_p(None)
         _check(lib.gi_selector_create(int(seed), ctypes.byref(self._h)))
+        _LIVE.add(self)
 
     def close(self):
         if self._h:
@@ -530,6 +650,7 @@ class Batch:
         self._h = ctypes.c_void_p(None)
         self.ntasks = len(tasks)
         _check(lib.gi_batch_create(hs, len(self.graphs), arr, len(tasks), ctypes.byref(self._h)))
+        _LIVE.add(self)
 
     def close(self):
         if self._h:

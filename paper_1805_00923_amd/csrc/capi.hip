@@ -12,6 +12,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "kernels.h"
@@ -51,6 +52,128 @@ static gi_status fail(gi_status st, const char* fmt, ...) {
 extern "C" const char* gi_last_error(void) { return g_err.c_str(); }
 extern "C" int32_t gi_abi_version(void) { return GI_ABI_VERSION; }
 
+// ------------------------------------------------------- device memory --
+//
+// Every device allocation of the library goes through dmem_alloc and every
+// release through dmem_free.  Sources, in order: the graph's workspace, when
+// the caller gave one to gi_graph_create_ex (bump-allocated in 256-byte
+// steps, released with the graph); the allocator registered with
+// gi_set_allocator (the Python binding registers torch's caching allocator);
+// hipMalloc.  The source of each live allocation is recorded, so a release
+// goes back where the memory came from even if the registered allocator
+// changed meanwhile.
+
+namespace {
+
+struct Provider {
+  gi_alloc_fn alloc = nullptr;
+  gi_free_fn release = nullptr;
+  void* ctx = nullptr;
+};
+
+struct LiveAlloc {
+  Provider from;
+  int device;
+};
+
+std::mutex g_dmem_mu;
+Provider g_provider;
+std::unordered_map<void*, LiveAlloc> g_dmem_live;
+
+// A caller-given region for a graph's core arrays.
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0;
+  size_t used = 0;
+};
+
+constexpr size_t kArenaAlign = 256;
+
+size_t arena_round(size_t bytes) {
+  return (std::max<size_t>(1, bytes) + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+}
+
+}  // namespace
+
+static void* dmem_alloc(size_t bytes, Arena* arena) {
+  bytes = std::max<size_t>(1, bytes);
+  if (arena && arena->base) {
+    if (arena->used + arena_round(bytes) <= arena->size) {
+      void* p = arena->base + arena->used;
+      arena->used += arena_round(bytes);
+      return p;
+    }
+    return nullptr;  // the workspace was sized for exactly these arrays
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  Provider pv;
+  {
+    std::lock_guard<std::mutex> lock(g_dmem_mu);
+    pv = g_provider;
+  }
+  void* p = nullptr;
+  if (pv.alloc) {
+    p = pv.alloc(bytes, dev, pv.ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  if (p) {
+    std::lock_guard<std::mutex> lock(g_dmem_mu);
+    g_dmem_live[p] = LiveAlloc{pv, dev};
+  }
+  return p;
+}
+
+// Memory from a graph's workspace is not recorded and is left alone here.
+static void dmem_free(void* p) {
+  if (!p) return;
+  LiveAlloc la;
+  {
+    std::lock_guard<std::mutex> lock(g_dmem_mu);
+    auto it = g_dmem_live.find(p);
+    if (it == g_dmem_live.end()) return;
+    la = it->second;
+    g_dmem_live.erase(it);
+  }
+  if (la.from.release) la.from.release(p, la.device, la.from.ctx);
+  else (void)hipFree(p);
+}
+
+template <typename T>
+static bool dmem_alloc_n(T** p, size_t count) {
+  *p = static_cast<T*>(dmem_alloc(count * sizeof(T), nullptr));
+  return *p != nullptr;
+}
+
+// hipMalloc-shaped: hipSuccess, or hipErrorOutOfMemory with *p = NULL.
+static hipError_t dmem_get(void** p, size_t bytes) {
+  *p = dmem_alloc(bytes, nullptr);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+extern "C" gi_status gi_set_allocator(gi_alloc_fn alloc, gi_free_fn release, void* ctx) {
+  if ((alloc == nullptr) != (release == nullptr))
+    return fail(GI_ERR_INVALID_ARG, "give both allocator functions or neither");
+  std::lock_guard<std::mutex> lock(g_dmem_mu);
+  g_provider = Provider{alloc, release, ctx};
+  return GI_OK;
+}
+
+extern "C" gi_status gi_live_allocations(int64_t* count, int64_t* from_registered) {
+  if (!count) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lock(g_dmem_mu);
+  int64_t r = 0;
+  for (const auto& kv : g_dmem_live) r += kv.second.from.alloc != nullptr;
+  *count = (int64_t)g_dmem_live.size();
+  if (from_registered) *from_registered = r;
+  return GI_OK;
+}
+
 // ------------------------------------------------------------ the graph --
 
 namespace {
@@ -70,6 +193,9 @@ struct SegDev {
 struct gi_graph {
   int32_t n = 0;
   int64_t m = 0;
+  Arena arena;               // caller-given workspace for the core arrays (may be empty)
+  int stats_pending = 0;     // launches of an enqueued run whose times are not read yet
+  hipStream_t last_stream = nullptr;
   int32_t max_out = 0, max_in = 0;
   bool weighted = false;
   int device = 0;
@@ -167,12 +293,18 @@ struct gi_graph {
   float* sel_io = nullptr;     // PageRank decision: 12 features in, 4 predictions out
 };
 
+// A device array of the graph, listed for release; from the graph's
+// workspace when `core` (the arrays gi_graph_create_ex sizes) and the graph
+// has one.
 template <typename T>
-static gi_status dev_alloc(gi_graph* g, std::vector<void*>& list, T** p, size_t count) {
-  void* q = nullptr;
+static gi_status dev_alloc(gi_graph* g, std::vector<void*>& list, T** p, size_t count,
+                           bool core = false) {
   const size_t bytes = std::max<size_t>(1, count * sizeof(T));
-  if (hipMalloc(&q, bytes) != hipSuccess) {
-    (void)hipGetLastError();
+  void* q = dmem_alloc(bytes, core ? &g->arena : nullptr);
+  if (!q) {
+    if (core && g->arena.base)
+      return fail(GI_ERR_INVALID_ARG, "workspace of %zu bytes too small for the graph",
+                  g->arena.size);
     return fail(GI_ERR_OUT_OF_MEMORY, "device allocation of %zu bytes failed", bytes);
   }
   list.push_back(q);
@@ -181,7 +313,7 @@ static gi_status dev_alloc(gi_graph* g, std::vector<void*>& list, T** p, size_t 
 }
 
 static void free_list(std::vector<void*>& list) {
-  for (void* p : list) (void)hipFree(p);
+  for (void* p : list) dmem_free(p);
   list.clear();
 }
 
@@ -837,8 +969,7 @@ extern "C" gi_status gi_graph_destroy(gi_graph* g) {
   free_list(g->ordt_allocs);
   free_list(g->ord_allocs);
   free_list(g->allocs);
-  for (void* q : {(void*)g->sel_p, (void*)g->sel_wb, (void*)g->sel_io})
-    if (q) (void)hipFree(q);
+  for (void* q : {(void*)g->sel_p, (void*)g->sel_wb, (void*)g->sel_io}) dmem_free(q);
   if (g->hflags) (void)hipHostFree(g->hflags);
   for (hipEvent_t e : g->ev)
     if (e) (void)hipEventDestroy(e);
@@ -853,10 +984,120 @@ extern "C" gi_status gi_graph_destroy(gi_graph* g) {
   return GI_OK;
 }
 
+// Slots of a chunked expansion (frontier loops): at least kMinChunk slots
+// each, at most kParts of them below the largest chunk size.
+static size_t expand_chunks(size_t m) {
+  return std::max((2 * m) / (size_t)expand_chunk_size(), (size_t)kParts) + 2;
+}
+
+// Bytes of the arrays gi_graph_create_ex places in a caller's workspace, each
+// rounded up to 256 bytes, for a graph with `nhubs` vertices of out-degree
+// above kHubDeg.  Must list exactly the G_ALLOC calls of create_graph.
+static size_t core_bytes(int32_t n, int64_t m, bool weighted, size_t nhubs) {
+  const size_t N = (size_t)n, M = (size_t)m, W = (N + 63) / 64;
+  const size_t sizes[] = {
+      4 * (N + 1), 4 * M, 4 * (N + 1), 4 * M, 4 * N, 4 * N,  // CSR, CSC, degrees
+      4 * N, 4 * std::max<size_t>(1, nhubs),                 // probe, hubs
+      weighted ? 4 * M : 0, weighted ? 4 * M : 0,            // weights
+      8 * W, 64 * W, 8 * W, 64 * W, 8 * W, 8 * W,            // frontiers, visited, far
+      4 * N, 4 * (N + 1), 4 * (N + 1),                       // labels, contributions
+      sizeof(Part) * kParts, sizeof(Blk) * kMaxCount, 8 * (size_t)kMaxCount,
+      4 * N, 8 * (N + 1), 4 * expand_chunks(M), sizeof(Control)};
+  size_t total = 0;
+  for (size_t b : sizes)
+    if (b) total += arena_round(b);
+  return total;
+}
+
+extern "C" gi_status gi_graph_workspace_size(int32_t n, int64_t m, int32_t weighted,
+                                             size_t* bytes) {
+  if (!bytes) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  if (n < 1) return fail(GI_ERR_INVALID_ARG, "n must be >= 1 (got %d)", n);
+  if (n > INT32_MAX - 64) return fail(GI_ERR_OVERFLOW, "n too large");
+  if (m < 0) return fail(GI_ERR_INVALID_ARG, "negative edge count");
+  if (m > INT32_MAX) return fail(GI_ERR_OVERFLOW, "m = %lld exceeds 2^31-1", (long long)m);
+  // at most m / (kHubDeg + 1) vertices have more than kHubDeg out-edges
+  const size_t hub_bound = std::min<size_t>((size_t)n, (size_t)m / (kHubDeg + 1));
+  *bytes = core_bytes(n, m, weighted != 0, hub_bound);
+  return GI_OK;
+}
+
+static gi_status create_graph(int32_t n, int64_t m, const int32_t* out_off,
+                              const int32_t* out_idx, const uint32_t* out_w,
+                              const int32_t* in_off, const int32_t* in_idx,
+                              const uint32_t* in_w, void* workspace, size_t ws_bytes,
+                              hipStream_t stream, gi_graph** out);
+
 extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_off,
                                      const int32_t* out_idx, const uint32_t* out_w,
                                      const int32_t* in_off, const int32_t* in_idx,
                                      const uint32_t* in_w, gi_graph** out) {
+  return create_graph(n, m, out_off, out_idx, out_w, in_off, in_idx, in_w, nullptr, 0, nullptr,
+                      out);
+}
+
+extern "C" gi_status gi_graph_create_ex(int32_t n, int64_t m, const int32_t* out_off,
+                                        const int32_t* out_idx, const uint32_t* out_w,
+                                        const int32_t* in_off, const int32_t* in_idx,
+                                        const uint32_t* in_w, int32_t ptr_kind, void* workspace,
+                                        size_t workspace_bytes, void* stream, gi_graph** out) {
+  if (!out) return fail(GI_ERR_INVALID_ARG, "NULL output handle");
+  *out = nullptr;
+  if (ptr_kind != GI_PTR_HOST && ptr_kind != GI_PTR_DEVICE)
+    return fail(GI_ERR_INVALID_ARG, "ptr_kind %d is neither GI_PTR_HOST nor GI_PTR_DEVICE",
+                ptr_kind);
+  if (workspace && ((uintptr_t)workspace % kArenaAlign) != 0)
+    return fail(GI_ERR_INVALID_ARG, "workspace must be %zu-byte aligned", kArenaAlign);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ptr_kind == GI_PTR_HOST)
+    return create_graph(n, m, out_off, out_idx, out_w, in_off, in_idx, in_w, workspace,
+                        workspace_bytes, s, out);
+  // device arrays: staged to the host once (validation and the schedule
+  // tables are built there), in the caller's stream order
+  if (n < 1) return fail(GI_ERR_INVALID_ARG, "n must be >= 1 (got %d)", n);
+  if (n > INT32_MAX - 64) return fail(GI_ERR_OVERFLOW, "n too large");
+  if (m < 0) return fail(GI_ERR_INVALID_ARG, "negative edge count");
+  if (m > INT32_MAX) return fail(GI_ERR_OVERFLOW, "m = %lld exceeds 2^31-1", (long long)m);
+  if (!out_off || (m > 0 && !out_idx)) return fail(GI_ERR_INVALID_ARG, "out-adjacency: NULL array");
+  if ((!in_off && in_idx) || (in_off && m > 0 && !in_idx))
+    return fail(GI_ERR_INVALID_ARG, "in_off and in_idx must both be given or both be NULL");
+  std::vector<int32_t> h_oo, h_oi, h_io, h_ii;
+  std::vector<uint32_t> h_ow, h_iw;
+  try {
+    h_oo.resize((size_t)n + 1);
+    h_oi.resize((size_t)m);
+    if (out_w) h_ow.resize((size_t)m);
+    if (in_off) {
+      h_io.resize((size_t)n + 1);
+      h_ii.resize((size_t)m);
+      if (in_w) h_iw.resize((size_t)m);
+    }
+  } catch (...) {
+    return fail(GI_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+  auto d2h = [&](void* h, const void* d, size_t bytes) -> hipError_t {
+    return bytes ? hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s) : hipSuccess;
+  };
+  const size_t N = (size_t)n, M = (size_t)m;
+  HIP_TRY(d2h(h_oo.data(), out_off, 4 * (N + 1)));
+  HIP_TRY(d2h(h_oi.data(), out_idx, 4 * M));
+  if (out_w) HIP_TRY(d2h(h_ow.data(), out_w, 4 * M));
+  if (in_off) {
+    HIP_TRY(d2h(h_io.data(), in_off, 4 * (N + 1)));
+    HIP_TRY(d2h(h_ii.data(), in_idx, 4 * M));
+    if (in_w) HIP_TRY(d2h(h_iw.data(), in_w, 4 * M));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return create_graph(n, m, h_oo.data(), h_oi.data(), out_w ? h_ow.data() : nullptr,
+                      in_off ? h_io.data() : nullptr, in_off ? h_ii.data() : nullptr,
+                      in_w ? h_iw.data() : nullptr, workspace, workspace_bytes, s, out);
+}
+
+static gi_status create_graph(int32_t n, int64_t m, const int32_t* out_off,
+                              const int32_t* out_idx, const uint32_t* out_w,
+                              const int32_t* in_off, const int32_t* in_idx,
+                              const uint32_t* in_w, void* workspace, size_t ws_bytes,
+                              hipStream_t stream, gi_graph** out) {
   if (!out) return fail(GI_ERR_INVALID_ARG, "NULL output handle");
   *out = nullptr;
   if (n < 1) return fail(GI_ERR_INVALID_ARG, "n must be >= 1 (got %d)", n);
@@ -876,6 +1117,8 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
   g->n = n;
   g->m = m;
   g->weighted = out_w != nullptr;
+  g->arena.base = static_cast<char*>(workspace);
+  g->arena.size = workspace ? ws_bytes : 0;
   // in-adjacency: given, or transposed here from the out-adjacency
   std::vector<int32_t> t_idx;
   std::vector<uint32_t> t_w;
@@ -973,18 +1216,33 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
   const size_t N = (size_t)n, M = (size_t)m, W = (N + 63) / 64;
 #define G_ALLOC(ptr, cnt)                                             \
   do {                                                                \
-    if ((st = dev_alloc(g, g->allocs, &(ptr), (cnt))) != GI_OK) {     \
+    if ((st = dev_alloc(g, g->allocs, &(ptr), (cnt), true)) != GI_OK) { \
       gi_graph_destroy(g);                                            \
       return st;                                                      \
     }                                                                 \
   } while (0)
+// copies in the caller's stream order; each waits for its own completion
+// (some host arrays are scoped to a block below)
 #define G_UP(h, d, bytes)                                             \
   do {                                                                \
-    if ((st = upload((h), (d), (bytes))) != GI_OK) {                  \
+    if ((bytes) > 0 &&                                                \
+        (hipMemcpyAsync((d), (h), (bytes), hipMemcpyHostToDevice, stream) != hipSuccess || \
+         hipStreamSynchronize(stream) != hipSuccess)) {               \
+      (void)hipGetLastError();                                        \
       gi_graph_destroy(g);                                            \
-      return st;                                                      \
+      return fail(GI_ERR_DEVICE, "host-to-device copy of %zu bytes failed", (size_t)(bytes)); \
     }                                                                 \
   } while (0)
+  if (g->arena.base) {
+    size_t nh = 0;
+    for (size_t v = 0; v < N; ++v) nh += g->h_outdeg[v] > kHubDeg;
+    const size_t need = core_bytes(n, m, out_w != nullptr, nh);
+    if (g->arena.size < need) {
+      gi_graph_destroy(g);
+      return fail(GI_ERR_INVALID_ARG, "workspace of %zu bytes, the graph needs %zu "
+                  "(gi_graph_workspace_size)", g->arena.size, need);
+    }
+  }
   G_ALLOC(g->out_off, N + 1);
   G_ALLOC(g->out_idx, M);
   G_ALLOC(g->in_off, N + 1);
@@ -1036,7 +1294,7 @@ extern "C" gi_status gi_graph_create(int32_t n, int64_t m, const int32_t* out_of
   // frontier-loop workspace
   // chunks of at least kMinChunk slots, at most kParts of them below the
   // largest chunk size
-  const size_t nchunk = std::max((2 * M) / (size_t)expand_chunk_size(), (size_t)kParts) + 2;
+  const size_t nchunk = expand_chunks(M);
   for (int k = 0; k < 2; ++k) {
     G_ALLOC(g->fbv[k], W);
     G_ALLOC(g->fbm[k], W * 64);
@@ -1194,6 +1452,24 @@ static gi_status read_kernel_ms(gi_graph* g, int launches) {
   HIP_TRY(hipEventElapsedTime(&ms, g->ev[0], g->ev[1]));
   g->stats.kernel_ms = ms;
   g->stats.launches = launches;
+  g->stats_pending = 0;
+  return GI_OK;
+}
+
+// Wait for the graph's last enqueued run (its end event) and read its time
+// if a call returned before its work finished.
+static gi_status finish_pending(gi_graph* g) {
+  HIP_TRY(hipEventSynchronize(g->ev[1]));
+  if (g->stats_pending) return read_kernel_ms(g, g->stats_pending);
+  return GI_OK;
+}
+
+extern "C" gi_status gi_sync_status(gi_graph* g) {
+  if (!g) return fail(GI_ERR_INVALID_ARG, "NULL graph");
+  gi_status st = finish_pending(g);
+  if (st != GI_OK) return st;
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GI_ERR_DEVICE, "device error: %s", hipGetErrorString(e));
   return GI_OK;
 }
 
@@ -1405,10 +1681,10 @@ static gi_status pr_run_ordered(gi_graph* g, int32_t iters, float damping, float
     if (te) HIP_TRY(hipEventRecord(te->end, s));
   }
   HIP_TRY(hipEventRecord(g->ev[1], s));
-  HIP_TRY(hipStreamSynchronize(s));
   if (g->timing_failed) return fail(GI_ERR_DEVICE, "PageRank: could not create timing events");
-  gi_status ts = read_kernel_ms(g, launches);
-  if (ts != GI_OK) return ts;
+  // returns after enqueue: the run's time is read when it is asked for
+  g->stats_pending = launches;
+  g->last_stream = s;
   gi_run_stats& rs = g->stats;
   rs.algorithm = ALG_PR;
   rs.steps = iters;
@@ -1471,10 +1747,10 @@ static gi_status pr_run(gi_graph* g, int32_t iters, float damping, float* ranks,
     if (te) HIP_TRY(hipEventRecord(te->end, s));
   }
   HIP_TRY(hipEventRecord(g->ev[1], s));
-  HIP_TRY(hipStreamSynchronize(s));
   if (g->timing_failed) return fail(GI_ERR_DEVICE, "PageRank: could not create timing events");
-  gi_status ts = read_kernel_ms(g, launches);
-  if (ts != GI_OK) return ts;
+  // returns after enqueue: the run's time is read when it is asked for
+  g->stats_pending = launches;
+  g->last_stream = s;
   gi_run_stats& st = g->stats;
   st.algorithm = ALG_PR;
   st.steps = iters;
@@ -2042,8 +2318,14 @@ extern "C" gi_status gi_pagerank_eigenvector(gi_graph* g, int32_t iters, float d
   return GI_OK;
 }
 
+// Reading a run's statistics waits for the run if its call returned after
+// enqueue (the handle's timing state is updated then, hence the cast).
 extern "C" gi_status gi_get_run_stats(const gi_graph* g, gi_run_stats* out) {
   if (!g || !out) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  if (g->stats_pending) {
+    gi_status st = finish_pending(const_cast<gi_graph*>(g));
+    if (st != GI_OK) return st;
+  }
   *out = g->stats;
   return GI_OK;
 }
@@ -2061,6 +2343,10 @@ extern "C" gi_status gi_get_step_times(const gi_graph* g, float* step_ms, float*
                                        int32_t cap, int32_t* count) {
   if (!g || !count || cap < 0 || (cap > 0 && (!step_ms || !main_ms)))
     return fail(GI_ERR_INVALID_ARG, "bad step-time arguments");
+  if (g->stats_pending) {
+    gi_status st = finish_pending(const_cast<gi_graph*>(g));
+    if (st != GI_OK) return st;
+  }
   const int nk = std::min(g->tev_count, (int)cap);
   for (int k = 0; k < nk; ++k) {
     const StepEvents& t = g->tev[(size_t)k];
@@ -2217,7 +2503,7 @@ static gi_status sel_reset_moments(gi_selector* s) {
 extern "C" gi_status gi_selector_destroy(gi_selector* s) {
   if (!s) return GI_OK;
   for (void* q : {(void*)s->d_p, (void*)s->d_m1, (void*)s->d_m2, (void*)s->d_grad, (void*)s->d_wb})
-    if (q) (void)hipFree(q);
+    if (q) dmem_free(q);
   delete s;
   return GI_OK;
 }
@@ -2244,11 +2530,11 @@ extern "C" gi_status gi_selector_create(uint64_t seed, gi_selector** out) {
   fill(kOffW1, kFeat * kHid, kFeat);
   fill(kOffW2, kHid * kHid, kHid);
   fill(kOffW3, kHid * kOut, kHid);
-  if (hipMalloc((void**)&s->d_p, sizeof(float) * kSelBuf) != hipSuccess ||
-      hipMalloc((void**)&s->d_m1, sizeof(float) * kParams) != hipSuccess ||
-      hipMalloc((void**)&s->d_m2, sizeof(float) * kParams) != hipSuccess ||
-      hipMalloc((void**)&s->d_grad, sizeof(float) * kParams) != hipSuccess ||
-      hipMalloc((void**)&s->d_wb, 2 * (size_t)kParams) != hipSuccess) {
+  if (dmem_get((void**)&s->d_p, sizeof(float) * kSelBuf) != hipSuccess ||
+      dmem_get((void**)&s->d_m1, sizeof(float) * kParams) != hipSuccess ||
+      dmem_get((void**)&s->d_m2, sizeof(float) * kParams) != hipSuccess ||
+      dmem_get((void**)&s->d_grad, sizeof(float) * kParams) != hipSuccess ||
+      dmem_get((void**)&s->d_wb, 2 * (size_t)kParams) != hipSuccess) {
     (void)hipGetLastError();
     gi_selector_destroy(s);
     return fail(GI_ERR_OUT_OF_MEMORY, "selector device allocation failed");
@@ -2313,7 +2599,7 @@ struct DevRecords {
   float* loss = nullptr;
   ~DevRecords() {
     for (void* q : {(void*)x, (void*)y, (void*)v, (void*)order, (void*)loss})
-      if (q) (void)hipFree(q);
+      if (q) dmem_free(q);
   }
 };
 
@@ -2321,11 +2607,11 @@ static gi_status sel_records(DevRecords& r, const float* feats, const float* log
                              const uint8_t* valid, int64_t count, const std::vector<int32_t>& order,
                              int loss_len) {
   const size_t n = (size_t)count;
-  if (hipMalloc((void**)&r.x, sizeof(float) * n * kFeat) != hipSuccess ||
-      hipMalloc((void**)&r.y, sizeof(float) * n * kOut) != hipSuccess ||
-      hipMalloc((void**)&r.v, n * kOut) != hipSuccess ||
-      hipMalloc((void**)&r.order, sizeof(int32_t) * n) != hipSuccess ||
-      hipMalloc((void**)&r.loss, sizeof(float) * (size_t)std::max(loss_len, 1)) != hipSuccess) {
+  if (dmem_get((void**)&r.x, sizeof(float) * n * kFeat) != hipSuccess ||
+      dmem_get((void**)&r.y, sizeof(float) * n * kOut) != hipSuccess ||
+      dmem_get((void**)&r.v, n * kOut) != hipSuccess ||
+      dmem_get((void**)&r.order, sizeof(int32_t) * n) != hipSuccess ||
+      dmem_get((void**)&r.loss, sizeof(float) * (size_t)std::max(loss_len, 1)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(GI_ERR_OUT_OF_MEMORY, "selector record allocation failed");
   }
@@ -2454,10 +2740,10 @@ extern "C" gi_status gi_selector_predict(const gi_selector* s, const float* feat
   if (count == 0) return GI_OK;
   float* dx = nullptr;
   float* dy = nullptr;
-  if (hipMalloc((void**)&dx, sizeof(float) * (size_t)count * kFeat) != hipSuccess ||
-      hipMalloc((void**)&dy, sizeof(float) * (size_t)count * kOut) != hipSuccess) {
+  if (dmem_get((void**)&dx, sizeof(float) * (size_t)count * kFeat) != hipSuccess ||
+      dmem_get((void**)&dy, sizeof(float) * (size_t)count * kOut) != hipSuccess) {
     (void)hipGetLastError();
-    if (dx) (void)hipFree(dx);
+    if (dx) dmem_free(dx);
     return fail(GI_ERR_OUT_OF_MEMORY, "prediction buffers");
   }
   SelDev d;
@@ -2474,8 +2760,8 @@ extern "C" gi_status gi_selector_predict(const gi_selector* s, const float* feat
     st = fail(GI_ERR_DEVICE, "prediction launch failed: %s", hipGetErrorString(hipGetLastError()));
   else if (hipMemcpy(out, dy, sizeof(float) * (size_t)count * kOut, hipMemcpyDeviceToHost) != hipSuccess)
     st = fail(GI_ERR_DEVICE, "copy of predictions failed");
-  (void)hipFree(dx);
-  (void)hipFree(dy);
+  dmem_free(dx);
+  dmem_free(dy);
   return st;
 }
 
@@ -2483,14 +2769,14 @@ extern "C" gi_status gi_selector_attach(gi_graph* g, const gi_selector* s) {
   if (!g) return fail(GI_ERR_INVALID_ARG, "NULL graph");
   HIP_TRY(hipDeviceSynchronize());
   for (void* q : {(void*)g->sel_p, (void*)g->sel_wb, (void*)g->sel_io})
-    if (q) (void)hipFree(q);
+    if (q) dmem_free(q);
   g->sel_p = nullptr;
   g->sel_wb = nullptr;
   g->sel_io = nullptr;
   if (!s) return GI_OK;
-  if (hipMalloc((void**)&g->sel_p, sizeof(float) * kSelBuf) != hipSuccess ||
-      hipMalloc((void**)&g->sel_wb, 2 * (size_t)kParams) != hipSuccess ||
-      hipMalloc((void**)&g->sel_io, sizeof(float) * (kFeat + kOut)) != hipSuccess) {
+  if (dmem_get((void**)&g->sel_p, sizeof(float) * kSelBuf) != hipSuccess ||
+      dmem_get((void**)&g->sel_wb, 2 * (size_t)kParams) != hipSuccess ||
+      dmem_get((void**)&g->sel_io, sizeof(float) * (kFeat + kOut)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(GI_ERR_OUT_OF_MEMORY, "selector copy allocation failed");
   }
@@ -2523,7 +2809,7 @@ extern "C" gi_status gi_trace_exhaustive(gi_graph* g, int32_t algorithm, int32_t
   if (algorithm == GI_ALG_BFS && (src < 0 || src >= g->n))
     return fail(GI_ERR_INVALID_ARG, "source %d outside [0, %d)", src, g->n);
   int32_t* out = nullptr;
-  if (hipMalloc((void**)&out, sizeof(float) * (size_t)g->n) != hipSuccess) {
+  if (dmem_get((void**)&out, sizeof(float) * (size_t)g->n) != hipSuccess) {
     (void)hipGetLastError();
     return fail(GI_ERR_OUT_OF_MEMORY, "trace output buffer");
   }
@@ -2555,6 +2841,7 @@ extern "C" gi_status gi_trace_exhaustive(gi_graph* g, int32_t algorithm, int32_t
       const bool seg = sched == 3;
       if (seg && (st = ensure_segments(g)) != GI_OK) break;
       st = pr_run(g, 20, 0.85f, reinterpret_cast<float*>(out), nullptr, seg);
+      if (st == GI_OK) st = finish_pending(g);  // the run returned after enqueue
     } else {
       g->sched.direction = sched;  // GI_DIR_SPARSE_PUSH, DENSE_PUSH, DENSE_PULL
       g->sched.dense_frontier = GI_FRONTIER_BITVECTOR;
@@ -2592,7 +2879,7 @@ extern "C" gi_status gi_trace_exhaustive(gi_graph* g, int32_t algorithm, int32_t
   }
   g->sched = saved;
   g->step_timing = saved_timing;
-  (void)hipFree(out);
+  dmem_free(out);
   if (st != GI_OK) return st;
   const int k = std::max(steps, 0);
   for (int i = 0; i < std::min(k, (int)cap); ++i) {
@@ -2652,10 +2939,10 @@ extern "C" gi_status gi_batch_destroy(gi_batch* b) {
   if (!b) return GI_OK;
   (void)hipDeviceSynchronize();
   batch_drop_graph(b);
-  for (void* q : b->work) (void)hipFree(q);
+  for (void* q : b->work) dmem_free(q);
   for (void* q : {(void*)b->d_graphs, (void*)b->d_tasks, (void*)b->d_ctl, (void*)b->d_items,
                   (void*)b->d_wg_off, (void*)b->d_err, (void*)b->d_trace})
-    if (q) (void)hipFree(q);
+    if (q) dmem_free(q);
   for (hipEvent_t e : b->ev)
     if (e) (void)hipEventDestroy(e);
   if (b->evw) (void)hipEventDestroy(b->evw);
@@ -2667,7 +2954,7 @@ extern "C" gi_status gi_batch_destroy(gi_batch* b) {
 template <typename T>
 static gi_status batch_alloc(gi_batch* b, T** p, size_t count) {
   void* q = nullptr;
-  if (hipMalloc(&q, std::max<size_t>(1, count * sizeof(T))) != hipSuccess) {
+  if (dmem_get(&q, std::max<size_t>(1, count * sizeof(T))) != hipSuccess) {
     (void)hipGetLastError();
     return fail(GI_ERR_OUT_OF_MEMORY, "batch workspace allocation failed");
   }
@@ -2784,11 +3071,11 @@ static gi_status batch_plan(gi_batch* b) {
   }
   off[(size_t)G] = (int)items.size();
   for (void* q : {(void*)b->d_items, (void*)b->d_wg_off})
-    if (q) (void)hipFree(q);
+    if (q) dmem_free(q);
   b->d_items = nullptr;
   b->d_wg_off = nullptr;
-  if (hipMalloc((void**)&b->d_items, sizeof(int2) * std::max<size_t>(1, items.size())) != hipSuccess ||
-      hipMalloc((void**)&b->d_wg_off, sizeof(int) * off.size()) != hipSuccess) {
+  if (dmem_get((void**)&b->d_items, sizeof(int2) * std::max<size_t>(1, items.size())) != hipSuccess ||
+      dmem_get((void**)&b->d_wg_off, sizeof(int) * off.size()) != hipSuccess) {
     (void)hipGetLastError();
     return fail(GI_ERR_OUT_OF_MEMORY, "batch plan allocation failed");
   }
@@ -2890,10 +3177,10 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
     b->k[i] = t.workgroups > 0 ? t.workgroups : k;
     b->est[i] = work / b->k[i];
   }
-  if (hipMalloc((void**)&b->d_graphs, sizeof(BatchGraph) * (size_t)ngraphs) != hipSuccess ||
-      hipMalloc((void**)&b->d_tasks, sizeof(BatchTask) * nt) != hipSuccess ||
-      hipMalloc((void**)&b->d_ctl, sizeof(TaskCtl) * nt) != hipSuccess ||
-      hipMalloc((void**)&b->d_err, sizeof(int)) != hipSuccess) {
+  if (dmem_get((void**)&b->d_graphs, sizeof(BatchGraph) * (size_t)ngraphs) != hipSuccess ||
+      dmem_get((void**)&b->d_tasks, sizeof(BatchTask) * nt) != hipSuccess ||
+      dmem_get((void**)&b->d_ctl, sizeof(TaskCtl) * nt) != hipSuccess ||
+      dmem_get((void**)&b->d_err, sizeof(int)) != hipSuccess) {
     (void)hipGetLastError();
     return bail(fail(GI_ERR_OUT_OF_MEMORY, "batch allocation failed"));
   }
@@ -3022,8 +3309,8 @@ static gi_status batch_time_task(gi_batch* b, int t, int k, int reps, float* ms)
   int2* di = nullptr;
   int* doff = nullptr;
   gi_status st = GI_OK;
-  if (hipMalloc((void**)&di, sizeof(int2) * (size_t)k) != hipSuccess ||
-      hipMalloc((void**)&doff, sizeof(int) * (size_t)(k + 1)) != hipSuccess) {
+  if (dmem_get((void**)&di, sizeof(int2) * (size_t)k) != hipSuccess ||
+      dmem_get((void**)&doff, sizeof(int) * (size_t)(k + 1)) != hipSuccess) {
     (void)hipGetLastError();
     st = fail(GI_ERR_OUT_OF_MEMORY, "tuning buffers");
   }
@@ -3045,8 +3332,8 @@ static gi_status batch_time_task(gi_batch* b, int t, int k, int reps, float* ms)
     if ((st = batch_check_error(b)) != GI_OK) break;
     times.push_back(x);
   }
-  if (di) (void)hipFree(di);
-  if (doff) (void)hipFree(doff);
+  if (di) dmem_free(di);
+  if (doff) dmem_free(doff);
   b->h_tasks[(size_t)t] = saved;
   if (hipMemcpy(b->d_tasks + t, &saved, sizeof(BatchTask), hipMemcpyHostToDevice) != hipSuccess && st == GI_OK)
     st = fail(GI_ERR_DEVICE, "tuning restore failed");
@@ -3305,12 +3592,12 @@ extern "C" gi_status gi_batch_set_trace(gi_batch* b, int32_t cap) {
   if (!b || cap < 0 || cap > (1 << 20)) return fail(GI_ERR_INVALID_ARG, "bad trace capacity");
   if (b->launched) return fail(GI_ERR_INVALID_ARG, "batch launch in flight (gi_batch_wait first)");
   HIP_TRY(hipDeviceSynchronize());
-  if (b->d_trace) (void)hipFree(b->d_trace);
+  if (b->d_trace) dmem_free(b->d_trace);
   b->d_trace = nullptr;
   b->trace_cap = 0;
   if (cap > 0) {
     const size_t cnt = b->tasks.size() * (size_t)cap * 2;
-    if (hipMalloc((void**)&b->d_trace, sizeof(long long) * cnt) != hipSuccess) {
+    if (dmem_get((void**)&b->d_trace, sizeof(long long) * cnt) != hipSuccess) {
       (void)hipGetLastError();
       return fail(GI_ERR_OUT_OF_MEMORY, "trace allocation failed");
     }

@@ -188,3 +188,48 @@ def test_hybrid_rule_as_written():
             assert gi.hybrid_choose_dense(nf, d, m, 20) == ((nf + d) * 20 > m)
     assert not gi.hybrid_choose_dense(25, 25, 1000, 20)   # exactly m/20 stays sparse
     assert gi.hybrid_choose_dense(25, 26, 1000, 20)
+
+
+def test_allocator_registration_and_exit_release():
+    """The binding registers torch's caching allocator with the library and,
+    at interpreter exit, closes every object still holding device memory
+    before torch shuts down (a close after that could reach a torch or HIP
+    runtime already torn down)."""
+    gi = _gi()
+    c = ctypes.c_int64()
+    assert gi.lib.gi_live_allocations(ctypes.byref(c), None) == gi.GI_OK and c.value >= 0
+    # only one of the two functions is refused; NULL, NULL goes back to hipMalloc
+    assert gi.lib.gi_set_allocator(gi._TORCH_ALLOC, gi._FREE_FN(), None) == gi.GI_ERR_INVALID_ARG
+    gi.use_torch_allocator(False)
+    gi.use_torch_allocator(True)
+
+    class Holder:
+        closed = 0
+
+        def close(self):
+            Holder.closed += 1
+
+    h = Holder()
+    gi._LIVE.add(h)
+    gi._release_at_exit()
+    assert Holder.closed == 1
+    gi._LIVE.discard(h)
+    # the release callback does nothing while the interpreter finalizes
+    import sys
+    assert hasattr(sys, "is_finalizing")
+
+
+def test_workspace_size_arguments():
+    gi = _gi()
+    b = ctypes.c_size_t()
+    assert gi.lib.gi_graph_workspace_size(0, 0, 0, ctypes.byref(b)) == gi.GI_ERR_INVALID_ARG
+    assert gi.lib.gi_graph_workspace_size(10, -1, 0, ctypes.byref(b)) == gi.GI_ERR_INVALID_ARG
+    assert gi.lib.gi_graph_workspace_size(10, 2**31, 0, ctypes.byref(b)) == gi.GI_ERR_OVERFLOW
+    small = gi.workspace_size(1000, 5000)
+    assert small % 256 == 0 and small >= 4 * (2 * 1001 + 2 * 5000)
+    assert gi.workspace_size(1000, 5000, weighted=True) >= small + 2 * 4 * 5000
+    # a NULL handle is refused before anything else
+    h = ctypes.c_void_p(None)
+    assert gi.lib.gi_graph_create_ex(10, 0, None, None, None, None, None, None, 5, None, 0,
+                                     None, ctypes.byref(h)) == gi.GI_ERR_INVALID_ARG
+    assert gi.lib.gi_sync_status(None) == gi.GI_ERR_INVALID_ARG
