@@ -195,6 +195,39 @@ class KernelTally:
                 "bytes_per_launch": int(bpl), "launches": self.launches}
 
 
+class one_core:
+    """Pin this process to one host core (the first it may run on) while the
+    oracle is timed, as `taskset -c <core>` would; the previous affinity is
+    restored afterwards."""
+
+    def __enter__(self):
+        self.prev = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {min(self.prev)})
+        return self
+
+    def __exit__(self, *exc):
+        os.sched_setaffinity(0, self.prev)
+        return False
+
+
+def copy_peak_gbs(torch, dev, mib=1024, reps=10):
+    """Practical HBM peak: a device-to-device copy of `mib` MiB (read once and
+    written once), timed with HIP events; bytes moved = 2 x size."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return round(2 * (mib << 20) / (ms * 1e-3) / 1e9, 1)
+
+
 # ------------------------------------------------------------- workloads --
 
 def make_rmat_graph(scale, seed, weighted=False):
@@ -340,13 +373,24 @@ def run_bfs_cc(args, torch, dev):
     bfs_tally = batch_k if batched else bfs_k
     dominant = bfs_tally if bfs_tally.ms >= cc_k.ms else cc_k
     other = cc_k if dominant is bfs_tally else bfs_tally
-    per_src_gteps = [mr / (t * 1e-3) / 1e9 for mr, t in zip(m_reach, plain_ms)]
+    per_src_gteps = np.array([mr / (t * 1e-3) / 1e9 for mr, t in zip(m_reach, plain_ms)])
+    # sources whose BFS reaches under 1% of the edges finish in a few steps
+    # of fixed cost: their TEPS say nothing about traversal speed, so the
+    # distribution is reported with them counted apart
+    big = np.array(m_reach) >= 0.01 * m
     extra = {
         "n": n, "m": m, "sources": int(len(srcs)), "bfs_path": args.bfs_path,
         "plain_bfs_ms_total": round(t_plain * 1e3, 3),
         "plain_bfs_ms_median": round(float(np.median(plain_ms)), 4),
-        "plain_bfs_gteps_harmonic_mean": round(len(per_src_gteps) / sum(1.0 / x for x in per_src_gteps), 3),
-        "plain_bfs_gteps_median": round(float(np.median(per_src_gteps)), 3),
+        "plain_bfs_gteps_per_source": {
+            "min": round(float(per_src_gteps.min()), 3),
+            "p10": round(float(np.percentile(per_src_gteps, 10)), 3),
+            "median": round(float(np.median(per_src_gteps)), 3),
+            "p90": round(float(np.percentile(per_src_gteps, 90)), 3),
+            "max": round(float(per_src_gteps.max()), 3),
+            "harmonic_mean_reach_ge_1pct": round(float(big.sum() / (1.0 / per_src_gteps[big]).sum()), 3)
+            if big.any() else None,
+            "sources_reach_under_1pct_of_m": int((~big).sum())},
         "cc_ms": round(float(np.median([c[0] for c in cc_all])), 4),
         "cc_rounds": int(cc_all[0][1]), "cc_dense_rounds": int(cc_all[0][2]),
         "cc_hybrid_divisor": cc_div, "cc_schedule": cc_sched, "cc_schedule_sweep_ms": cc_sweep,
@@ -366,10 +410,32 @@ def run_bfs_cc(args, torch, dev):
               "bfs_sources": int(len(srcs)), "bfs_path": args.bfs_path,
               "cc_overlaps_bfs_batch": overlap,
               "schedule": bfs_sched, "cc_hybrid_divisor": cc_div}
+    # PageRank legs (the PageRank configuration on R-MAT 16, and R-MAT 22 on
+    # this graph), each tuned and timed on its own with its own roofline
+    extra["pagerank"] = pagerank_legs(torch, dev, g)
+    extra["hbm_copy_gbs"] = copy_peak_gbs(torch, dev)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_bfs_cc(el, srcs, m_reach)
     return value, "GTEPS", ms_step, "int32", config, dominant.roofline(), cpu, extra
+
+
+def pagerank_legs(torch, dev, g22, steps=5):
+    """20-iteration PageRank on R-MAT 16 (seed 1) and on the R-MAT 22 graph of
+    the default workload: tuned schedule, GTEPS and roofline of each."""
+    import numpy as np
+    legs = {}
+    el16, g16 = make_rmat_graph(16, 1)
+    for name, g in (("rmat16", g16), ("rmat22", g22)):
+        ranks = torch.empty(g.n, dtype=torch.float32, device=dev)
+        kw, tuned, kms, dt, tally = pr_tune_and_time(g, torch, ranks, steps, 1)
+        kmed = float(np.median(kms))
+        legs[name] = {"n": g.n, "m": g.m, "schedule": kw, "run_ms_median": round(kmed, 4),
+                      "gteps": round(20.0 * g.m / (kmed * 1e-3) / 1e9, 3),
+                      "roofline": tally.roofline(), "schedule_sweep_ms": tuned}
+        log("pagerank %s: %s, %.3f ms per 20 iterations" % (name, kw, kmed))
+    g16.close()
+    return legs
 
 
 def cpu_baseline_bfs_cc(el, srcs, m_reach, budget_s=12.0):
@@ -381,19 +447,77 @@ def cpu_baseline_bfs_cc(el, srcs, m_reach, budget_s=12.0):
     t0 = time.time()
     og = oracle.Graph(el)
     log("oracle graph built in %.1fs" % (time.time() - t0))
-    t0 = time.perf_counter()
-    done = 0
-    for s in srcs:
-        oracle.bfs(og, int(s))
-        done += 1
-        if done >= 2 and time.perf_counter() - t0 > budget_s:
-            break
-    oracle.cc(og)
-    dt = time.perf_counter() - t0
+    with one_core():
+        t0 = time.perf_counter()
+        done = 0
+        for s in srcs:
+            oracle.bfs(og, int(s))
+            done += 1
+            if done >= 2 and time.perf_counter() - t0 > budget_s:
+                break
+        oracle.cc(og)
+        dt = time.perf_counter() - t0
     edges = sum(m_reach[:done]) + og.m
     return {"value": round(edges / dt / 1e9, 5), "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": "oracle FIFO BFS from the first %d of the 64 sources + one label-"
-                      "propagation CC on the same RMAT-22 graph, one thread, %.1f s" % (done, dt)}
+                      "propagation CC on the same RMAT-22 graph, one thread pinned to one core, "
+                      "%.1f s" % (done, dt)}
+
+
+# PageRank schedules the autotuner tries (untimed), as the paper's autotuner
+# does per algorithm and graph: id-order block size and id-range segments
+# (sequential or concurrent), and the degree-ordered pull with its tile shape
+# and LDS source count.
+PR_CANDIDATES = [
+    dict(), dict(pull_block_edges=512), dict(pull_block_edges=1024), dict(num_segments=4),
+    dict(num_segments=8, segments_concurrent=1), dict(num_segments=16, segments_concurrent=1),
+    dict(vertex_order=1, block_threads=1024, pull_items_per_thread=4, pull_hot_sources=-1),
+    dict(vertex_order=1, block_threads=1024, pull_items_per_thread=8, pull_hot_sources=-1),
+    dict(vertex_order=1, block_threads=1024, pull_items_per_thread=4, pull_hot_sources=0),
+    dict(vertex_order=1, block_threads=512, pull_items_per_thread=4, pull_hot_sources=0),
+    dict(vertex_order=1, block_threads=512, pull_items_per_thread=8, pull_hot_sources=-1),
+]
+
+
+def pr_kernel_name(sch):
+    if sch.vertex_order == 1:
+        return "k_pr_ord + k_pr_ord_split"
+    if sch.num_segments <= 1:
+        return "k_pr_rows"
+    return ("k_pr_seg_concurrent + k_pr_seg_final_multi" if sch.segments_concurrent
+            else "k_pr_rows per segment + k_pr_seg_final")
+
+
+def pr_tune_and_time(g, torch, ranks, steps, warmup, overrides=None, cands=PR_CANDIDATES):
+    """Tune the PageRank schedule of `g` over `cands` (two 20-iteration runs
+    each, the second timed), then time `steps` runs with per-iteration HIP
+    events.  Returns (schedule, sweep, run ms list, wall seconds, tally)."""
+    n, m = g.n, g.m
+    tuned = {}
+    for c in cands:
+        g.set_schedule(**c)
+        g.pagerank(ranks, 20, 0.85)
+        g.pagerank(ranks, 20, 0.85)
+        tuned[json.dumps(c)] = round(g.stats().kernel_ms, 4)
+    kw = dict(json.loads(min(tuned, key=tuned.get)))
+    kw.update(overrides or {})
+    g.set_schedule(**kw)
+    g.set_step_timing(True)
+    for _ in range(warmup):
+        g.pagerank(ranks, 20, 0.85)
+    torch.cuda.synchronize()
+    kms = []
+    tally = KernelTally(pr_kernel_name(g.schedule()))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.pagerank(ranks, 20, 0.85)
+        kms.append(g.stats().kernel_ms)
+        _, mm = g.step_times()
+        tally.add(mm, [4 * m + 16 * n] * len(mm))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g.set_step_timing(False)
+    return kw, tuned, kms, dt, tally
 
 
 def run_pr(args, torch, dev, scale):
@@ -401,41 +525,9 @@ def run_pr(args, torch, dev, scale):
     el, g = make_rmat_graph(scale, 1 if scale == 16 else 2)
     n, m = g.n, g.m
     ranks = torch.empty(n, dtype=torch.float32, device=dev)
-    # schedule autotuning (untimed), as the paper's autotuner does per
-    # algorithm and graph: block size, and sequential or concurrent segments
-    cands = [dict(), dict(pull_block_edges=256), dict(pull_block_edges=512),
-             dict(pull_block_edges=1024), dict(num_segments=4),
-             dict(num_segments=8, segments_concurrent=1),
-             dict(num_segments=8, segments_concurrent=1, segment_strategy=1),
-             dict(num_segments=16, segments_concurrent=1)]
-    tuned = {}
-    for c in cands:
-        g.set_schedule(**c)
-        g.pagerank(ranks, 20, 0.85)
-        g.pagerank(ranks, 20, 0.85)
-        tuned[json.dumps(c)] = round(g.stats().kernel_ms, 4)
-    best = json.loads(min(tuned, key=tuned.get))
-    kw = dict(best)
-    kw.update(sched_overrides(args.schedule))
-    g.set_schedule(**kw)
+    kw, tuned, kms, dt, tally = pr_tune_and_time(g, torch, ranks, args.steps, args.warmup,
+                                                 sched_overrides(args.schedule))
     log("pagerank schedule sweep (ms per 20 iterations): %s -> %s" % (tuned, kw))
-    g.set_step_timing(True)
-    for _ in range(args.warmup):
-        g.pagerank(ranks, 20, 0.85)
-    torch.cuda.synchronize()
-    kms = []
-    sch = g.schedule()
-    tally = KernelTally("k_pr_rows" if sch.num_segments <= 1 else
-                        ("k_pr_seg_concurrent + k_pr_seg_final_multi" if sch.segments_concurrent
-                         else "k_pr_rows per segment + k_pr_seg_final"))
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g.pagerank(ranks, 20, 0.85)
-        kms.append(g.stats().kernel_ms)
-        _, mm = g.step_times()
-        tally.add(mm, [4 * m + 16 * n] * len(mm))
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
     ms_step = dt * 1e3 / args.steps
     value = 20.0 * m * args.steps / dt / 1e9
     kmed = float(np.median(kms))
@@ -446,13 +538,14 @@ def run_pr(args, torch, dev, scale):
         import oracle
         og = oracle.Graph(el)
         reps = 1 if scale > 18 else 3
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            oracle.pagerank(og, 20, 0.85)
-        dt_c = (time.perf_counter() - t0) / reps
+        with one_core():
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                oracle.pagerank(og, 20, 0.85)
+            dt_c = (time.perf_counter() - t0) / reps
         cpu = {"value": round(20.0 * og.m / dt_c / 1e9, 5), "unit": "GTEPS", "cores": 1,
                "kind": "oracle", "sample": "FP64 pull PageRank, 20 iterations, full graph, "
-                                           "one thread, %.3f s per run" % dt_c}
+                                           "one thread pinned to one core, %.3f s per run" % dt_c}
     extra = {"schedule_sweep_ms": tuned,
              "run_ms_median": round(kmed, 4),
              "gteps_kernel": round(20.0 * m / (kmed * 1e-3) / 1e9, 3),

@@ -81,3 +81,29 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_oracle_timing_pins_one_core_and_restores():
+    before = os.sched_getaffinity(0)
+    with bench.one_core():
+        inside = os.sched_getaffinity(0)
+        assert len(inside) == 1 and inside <= before
+    assert os.sched_getaffinity(0) == before
+
+
+def test_pagerank_kernel_names_follow_the_schedule():
+    class S:
+        vertex_order, num_segments, segments_concurrent = 0, 1, 0
+    s = S()
+    assert bench.pr_kernel_name(s) == "k_pr_rows"
+    s.num_segments = 4
+    assert bench.pr_kernel_name(s) == "k_pr_rows per segment + k_pr_seg_final"
+    s.segments_concurrent = 1
+    assert bench.pr_kernel_name(s) == "k_pr_seg_concurrent + k_pr_seg_final_multi"
+    s.vertex_order = 1
+    assert bench.pr_kernel_name(s) == "k_pr_ord + k_pr_ord_split"
+    # every candidate the autotuner tries is a dict of known schedule fields
+    import paper_1805_00923_amd as gi
+    names = {f for f, _ in gi.Schedule._fields_}
+    for c in bench.PR_CANDIDATES:
+        assert set(c) <= names, c
