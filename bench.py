@@ -150,10 +150,21 @@ def sssp_step_bytes(dirs, fs, ds, es):
     return [12 * int(f) + 12 * int(e) for f, e in zip(fs, es)]
 
 
-def profile_traffic(kernel):
+SCHED_KEY_FIELDS = ("vertex_order", "num_segments", "segments_concurrent", "block_threads",
+                    "pull_items_per_thread", "pull_hot_sources", "pull_block_edges")
+
+
+def sched_key(sched):
+    """The schedule fields that change a PageRank kernel's traffic, as text."""
+    return ",".join("%s=%d" % (k, int(sched.get(k, 0))) for k in SCHED_KEY_FIELDS)
+
+
+def profile_traffic(kernel, workload=None, schedule=None):
     """HBM bytes per launch of `kernel` from the hardware-counter figures
-    committed under profiles/, or None when there are none or the kernel's
-    sources changed since the counters were taken (sha256 mismatch)."""
+    committed under profiles/, or None when there are none for this kernel
+    (and workload and schedule, where the figures name them) or the
+    kernel's sources changed since the counters were taken (sha256
+    mismatch)."""
     import glob
     import hashlib
     import re
@@ -163,6 +174,10 @@ def profile_traffic(kernel):
             continue
         kv = dict(re.findall(r"^(\w+): (.+)$", m.group(0), re.M))
         if kv.get("kernel") != kernel:
+            continue
+        if "workload" in kv and kv["workload"] != workload:
+            continue
+        if "schedule" in kv and (schedule is None or kv["schedule"] != sched_key(schedule)):
             continue
         h = hashlib.sha256()
         for f in kv.get("sources", "").split():
@@ -430,9 +445,12 @@ def pagerank_legs(torch, dev, g22, steps=5):
         ranks = torch.empty(g.n, dtype=torch.float32, device=dev)
         kw, tuned, kms, dt, tally = pr_tune_and_time(g, torch, ranks, steps, 1)
         kmed = float(np.median(kms))
+        roof = tally.roofline()
+        roof["traffic"] = profile_traffic(roof["kernel"], "pagerank20_%s_ef16" % name,
+                                          g.schedule().as_dict())
         legs[name] = {"n": g.n, "m": g.m, "schedule": kw, "run_ms_median": round(kmed, 4),
                       "gteps": round(20.0 * g.m / (kmed * 1e-3) / 1e9, 3),
-                      "roofline": tally.roofline(), "schedule_sweep_ms": tuned}
+                      "roofline": roof, "schedule_sweep_ms": tuned}
         log("pagerank %s: %s, %.3f ms per 20 iterations" % (name, kw, kmed))
     g16.close()
     return legs
@@ -1184,7 +1202,8 @@ def main():
     if cpu:
         cpu = dict(cpu, sample=cpu["sample"] + "; host: " + host_info())
     if roof and roof.get("traffic") is None:
-        roof["traffic"] = profile_traffic(roof["kernel"])
+        roof["traffic"] = profile_traffic(roof["kernel"], config.get("workload"),
+                                          config.get("schedule"))
     line = {"metric": METRIC, "value": round(value, 4), "unit": unit, "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,

@@ -42,21 +42,31 @@ def test_sssp_step_bytes():
 
 
 def test_profile_traffic_follows_the_source_hash(tmp_path, monkeypatch):
-    # the committed figure is read while the sources match
-    real = bench.profile_traffic("k_batch")
-    assert real is None or real > 0
+    # the committed figure is read while the sources match, and only for the
+    # workload (and, where the figures name one, the schedule) it was taken on
+    wl = "rmat22_ef16_bfs64_plus_cc"
+    real = bench.profile_traffic("k_batch", wl)
+    assert real is not None and real > 0
+    assert bench.profile_traffic("k_batch", "some_other_workload") is None
     assert bench.profile_traffic("no_such_kernel") is None
+    pr = "k_pr_ord + k_pr_ord_split"
+    s22 = dict(vertex_order=1, num_segments=1, block_threads=1024, pull_items_per_thread=4,
+               pull_hot_sources=-1)
+    t22 = bench.profile_traffic(pr, "pagerank20_rmat22_ef16", s22)
+    t16 = bench.profile_traffic(pr, "pagerank20_rmat16_ef16", dict(s22, pull_hot_sources=0))
+    assert t22 and t16 and t22 > 100 * t16
+    assert bench.profile_traffic(pr, "pagerank20_rmat22_ef16", dict(s22, block_threads=512)) is None
+    assert bench.profile_traffic(pr, "pagerank20_rmat22_ef16", None) is None
     # a copy of the tree whose batch source differs: the figure is stale
     csrc = os.path.join(ROOT, "paper_1805_00923_amd", "csrc")
     fake = tmp_path / "paper_1805_00923_amd" / "csrc"
     shutil.copytree(csrc, fake)
     shutil.copytree(os.path.join(ROOT, "profiles"), tmp_path / "profiles")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    if real is not None:
-        assert bench.profile_traffic("k_batch") == real
+    assert bench.profile_traffic("k_batch", wl) == real
     with open(fake / "batch.hip", "a") as f:
         f.write("\n// changed\n")
-    assert bench.profile_traffic("k_batch") is None
+    assert bench.profile_traffic("k_batch", wl) is None
 
 
 def test_gpu_clocks_reports_failure_as_text():
