@@ -78,6 +78,9 @@ def parse():
                     help="BFS part of the default workload: the 64 sources as one batched "
                          "persistent launch, or one plain call per source")
     ap.add_argument("--sources", type=int, default=64)
+    ap.add_argument("--batch-barrier", default="xcd", choices=["xcd", "agent"],
+                    help="barrier of batched tasks: one-XCD tasks only invalidate L1 (xcd, "
+                         "the default) or every barrier writes back and invalidates L2 (agent)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--schedule", default="", help="k=v,... overrides of the schedule")
     ap.add_argument("--json-out", default="")
@@ -85,6 +88,11 @@ def parse():
                     help="first run one elementwise copy of this many MiB (read once, written "
                          "once), a reference dispatch for hardware byte counters")
     return ap.parse_args()
+
+
+def barrier_scope(args):
+    import paper_1805_00923_amd as gi
+    return gi.BARRIER_XCD if args.batch_barrier == "xcd" else gi.BARRIER_AGENT
 
 
 def sched_overrides(text):
@@ -307,6 +315,7 @@ def run_bfs_cc(args, torch, dev):
                  torch.empty(n, dtype=torch.int32, device=dev)) for _ in srcs]
         batch = gi.Batch([g], [dict(graph=0, algorithm=gi.ALG_BFS, src=int(s), out=o, parent=p)
                                for s, (o, p) in zip(srcs, outs)])
+        batch.set_barrier_scope(barrier_scope(args))
         t0 = time.perf_counter()
         batch.autotune(reps=3)
         t_tune = time.perf_counter() - t0
@@ -416,6 +425,7 @@ def run_bfs_cc(args, torch, dev):
         extra.update({"batched_bfs_ms": round(batch_k.ms / max(batch_k.launches, 1), 3),
                       "batch_grid": info["grid"], "batch_threads": batch.threads(),
                       "batch_xcd_local": batch.placement(),
+                      "batch_barrier": args.batch_barrier,
                       "batch_workgroups_per_source": int(np.median(info["workgroups"])),
                       "autotune_s": round(t_tune, 2),
                       "speedup_batched_vs_plain_bfs": round(
@@ -644,6 +654,7 @@ def run_sssp(args, torch, dev):
         for delta in (4096, 8192, 16384, 32768):
             b = gi.Batch([g], [dict(graph=0, algorithm=gi.ALG_SSSP, src=int(s_), sssp_delta=delta,
                                     out=o) for s_, o in zip(srcs, outs)])
+            b.set_barrier_scope(barrier_scope(args))
             b.autotune(reps=1)
             b.run()
             b.run()
@@ -905,6 +916,7 @@ def run_batched(args, torch, dev):
         plain()
     t_plain = (time.perf_counter() - t0) / args.steps
     b = gi.Batch(graphs, tasks)
+    b.set_barrier_scope(barrier_scope(args))
     t0 = time.perf_counter()
     b.autotune(reps=3)
     t_tune = time.perf_counter() - t0

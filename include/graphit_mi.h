@@ -609,6 +609,19 @@ gi_status gi_batch_get_threads(const gi_batch* b, int32_t* threads);
 gi_status gi_batch_set_placement(gi_batch* b, int32_t xcd_local);
 gi_status gi_batch_get_placement(const gi_batch* b, int32_t* xcd_local);
 
+/* Barrier of a task's workgroups between BFS levels, PageRank iterations and
+ * SSSP phases.  GI_BARRIER_XCD (the default): a task whose workgroups all
+ * run on one XCD (each workgroup reads its XCD from the hardware when the
+ * task starts, so a placement the dispatcher did not keep is detected) skips
+ * the L2 write-back before arriving: the XCD's L2 is shared by its
+ * workgroups and the L1 writes through to it; the cache invalidation after
+ * the wait is kept.  Other tasks, and every task under GI_BARRIER_AGENT, use
+ * agent scope: the L2 is written back before arriving and invalidated
+ * after.  Results do not depend on the scope.  Errors: INVALID_ARG (another value, NULL, a launch in flight). */
+enum { GI_BARRIER_AGENT = 0, GI_BARRIER_XCD = 1 };
+gi_status gi_batch_set_barrier_scope(gi_batch* b, int32_t scope);
+gi_status gi_batch_get_barrier_scope(const gi_batch* b, int32_t* scope);
+
 /* Per-step trace of batch tasks (the batched counterpart of the per-step
  * trace in gi_get_run_stats).  gi_batch_set_trace keeps up to cap records
  * per task from the next run on (0 turns it off; it re-captures the HIP

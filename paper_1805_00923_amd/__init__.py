@@ -55,6 +55,8 @@ CC_ADJ_AUTO = 0
 CC_ADJ_SYMMETRIC = 1
 CC_ADJ_DIRECT = 2
 ORDER_GIVEN = 0
+BARRIER_AGENT = 0
+BARRIER_XCD = 1
 ORDER_OUT_DEGREE = 1
 MAX_TRACE = 4096
 NOALLOC_MAX_WORDS = 1 << 21
@@ -166,6 +168,8 @@ _SIGS = {
     "gi_batch_set_trace": (ctypes.c_int, [_vp, _i32]),
     "gi_batch_set_placement": (ctypes.c_int, [_vp, _i32]),
     "gi_batch_get_placement": (ctypes.c_int, [_vp, _vp]),
+    "gi_batch_set_barrier_scope": (ctypes.c_int, [_vp, _i32]),
+    "gi_batch_get_barrier_scope": (ctypes.c_int, [_vp, _vp]),
     "gi_batch_get_trace": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _i32, _vp]),
     "gi_get_step_times": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp]),
     "gi_frontier_sparse_to_bitvec": (ctypes.c_int, [_i32, _vp, _i32, _vp, _vp]),
@@ -682,6 +686,17 @@ class Batch:
     def placement(self):
         x = ctypes.c_int32(0)
         _check(lib.gi_batch_get_placement(self._h, ctypes.byref(x)))
+        return x.value
+
+    def set_barrier_scope(self, scope):
+        """BARRIER_XCD (default): tasks on one XCD only invalidate L1 at their
+        barriers; BARRIER_AGENT: every barrier writes back and invalidates
+        the L2."""
+        _check(lib.gi_batch_set_barrier_scope(self._h, int(scope)))
+
+    def barrier_scope(self):
+        x = ctypes.c_int32(0)
+        _check(lib.gi_batch_get_barrier_scope(self._h, ctypes.byref(x)))
         return x.value
 
     def set_trace(self, cap):

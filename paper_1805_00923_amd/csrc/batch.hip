@@ -44,22 +44,52 @@ constexpr int batch_min_waves() {
 
 __device__ __forceinline__ long long wall_ticks() { return (long long)wall_clock64(); }
 
+// XCD (XCC) of the calling wave, from the hardware register XCC_ID.
+__device__ __forceinline__ unsigned xcc_id() {
+  return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xfu;  // XCC_ID[3:0]
+}
+
+// Record this workgroup's XCD in the task's mask; called by every workgroup
+// of the task before the task's first barrier.
+__device__ __forceinline__ void task_join(TaskCtl* c) {
+  if (threadIdx.x == 0) atomicOr(&c->xcds, 1u << xcc_id());
+}
+
+// After the task's first barrier: true when every workgroup of the task runs
+// on one XCD, so that they share one L2.  Read by all workgroups after the
+// same barrier, so all take the same barrier form.
+__device__ __forceinline__ bool task_on_one_xcd(const TaskCtl* c) {
+  const unsigned m = __hip_atomic_load(&c->xcds, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __popc(m) == 1;
+}
+
 // Barrier of the k workgroups of one task.  One 64-bit word holds
 // (generation << 32) | arrivals, so an arrival learns its generation from
 // the same atomic.  Every wave first waits for its own memory operations to
-// complete; then one thread per workgroup releases (writes its L2 back),
-// arrives, waits for the generation to move, and acquires (invalidates its
-// caches) for the whole workgroup: two cache maintenance operations per
-// workgroup and barrier rather than two per wave.  Returns false once the
-// batch has failed (timeout here or elsewhere).
-__device__ bool task_barrier(TaskCtl* c, int k, int* gerr, long long limit) {
+// complete; then one thread per workgroup releases, arrives, waits for the
+// generation to move, and acquires for the whole workgroup: two cache
+// maintenance operations per workgroup and barrier rather than two per
+// wave.
+//   Agent scope (the task's workgroups may sit on different XCDs, whose L2s
+//   are not coherent with each other): release writes the L2 back, acquire
+//   invalidates L1 and L2.
+//   One XCD (`local`): the task's workgroups share one L2, and the vector L1
+//   writes through to it, so a wave's completed stores are already in the
+//   L2 every participant reads: the release's L2 write-back is skipped.
+//   The acquire stays the device-scope invalidate: it is the one that drops
+//   the CU's stale L1 lines (a group-scope invalidate leaves them outside
+//   thread-group-split mode, as a probe of a pre-cached line showed), and
+//   it leaves dirty L2 lines in place.  Lines written at several levels are
+//   then written back to memory once, not at every barrier.
+// Returns false once the batch has failed (timeout here or elsewhere).
+__device__ bool task_barrier(TaskCtl* c, int k, int* gerr, long long limit, bool local = false) {
   __shared__ int s_ok;
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     int ok = __hip_atomic_load(gerr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     if (ok && k > 1) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const unsigned long long old = atomicAdd(&c->bar, 1ull);
       const unsigned long long gen = old >> 32;
       if ((old & 0xffffffffull) == (unsigned long long)(k - 1)) {
@@ -110,7 +140,9 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
     t.bv1[w] = 0ull;
     t.bv2[w] = 0ull;
   }
+  task_join(c);
   if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+  const bool local = a.xcd_barrier && task_on_one_xcd(c);
   if (r == 0 && tid == 0) {
     const int s = t.src;
     level[s] = 0;
@@ -120,7 +152,7 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
     c->qn[0] = 1;
     c->ds[0] = G.outdeg[s];
   }
-  if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+  if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
   DevGraph dg{};
   dg.n = n;
   dg.m = G.m;
@@ -179,7 +211,7 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
       atomicAdd(&c->qn[(L + 1) % 3], (unsigned long long)p.a);
       atomicAdd(&c->ds[(L + 1) % 3], (unsigned long long)p.b);
     }
-    if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+    if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
   }
   if (r == 0 && tid == 0) {
     c->levels = L;
@@ -241,14 +273,16 @@ __device__ void sssp_task(const BatchGraph& G, const BatchTask& t, int r, const 
     t.bv1[w] = 0ull;
     t.bv2[w] = 0ull;
   }
+  task_join(c);
   if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+  const bool local = a.xcd_barrier && task_on_one_xcd(c);
   if (r == 0 && tid == 0) {
     dist[t.src] = 0u;
     t.bv0[t.src >> 6] = 1ull << (t.src & 63);
     c->qn[0] = 1;
     c->thresh = delta;
   }
-  if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+  if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
   __shared__ unsigned long long s_red[BT / kWave];
   int P = 0;
   for (;; ++P) {
@@ -293,7 +327,7 @@ __device__ void sssp_task(const BatchGraph& G, const BatchTask& t, int r, const 
         if (p.a) atomicAdd(&c->qn[(P + 1) % 3], (unsigned long long)p.a);
         if (p.b) atomicAdd(&c->farc[(P + 1) % 3], (unsigned long long)p.b);
       }
-      if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+      if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
       continue;
     }
     // split: the next bucket starts at the smallest far distance at or
@@ -315,7 +349,7 @@ __device__ void sssp_task(const BatchGraph& G, const BatchTask& t, int r, const 
       for (int i = 0; i < BT / kWave; ++i) mn = s_red[i] < mn ? s_red[i] : mn;
       if (mn != ~0ull) atomicMin(&c->fmin, mn);
     }
-    if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+    if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
     const unsigned long long fm = __hip_atomic_load(&c->fmin, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
     const unsigned long long tnew = fm == ~0ull ? th : (fm / delta + 1ull) * delta;
@@ -346,7 +380,7 @@ __device__ void sssp_task(const BatchGraph& G, const BatchTask& t, int r, const 
     // every workgroup has read the old threshold (it read fmin after the
     // barrier above); rank 0 publishes the new one for the next phase
     if (r == 0 && tid == 0) c->thresh = tnew;
-    if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+    if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
   }
   if (r == 0 && tid == 0) {
     c->levels = P;
@@ -378,7 +412,9 @@ __device__ void pr_task(const BatchGraph& G, const BatchTask& t, int r, const Ba
     t.lr_acc[i] = 0.0;
     t.lr_cnt[i] = 0u;
   }
+  task_join(c);
   if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+  const bool local = a.xcd_barrier && task_on_one_xcd(c);
   PrVertex pv;
   pv.outdeg = G.outdeg;
   pv.alpha = (double)t.damping;
@@ -397,7 +433,7 @@ __device__ void pr_task(const BatchGraph& G, const BatchTask& t, int r, const Ba
     float* rk = it == t.iters - 1 ? ranks : nullptr;
     for (int tb = r; tb < G.pr_ntab; tb += k)
       pr_rows_block<BT>(rows, tb, G.pr_cap_e, cin, 0, pv, cout, rk, nullptr, lds_val, lds_off);
-    if (!task_barrier(c, k, a.error, a.spin_limit)) return;
+    if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
   }
   if (r == 0 && tid == 0) c->levels = t.iters;
 }

@@ -2905,6 +2905,7 @@ struct gi_batch {
   long long* d_trace = nullptr;
   bool bt_pinned = false;    // set by gi_batch_set_threads: the autotuner keeps it
   bool xcd_local = true;     // place each task's workgroups on one XCD when they fit
+  int xcd_barrier = 1;       // one-XCD task barriers where a task's workgroups share an L2
   int cus = 0;
   size_t lds = 0;
   int cap_e = 0;
@@ -3214,6 +3215,7 @@ static BatchArgs batch_args(const gi_batch* b, const int2* items, const int* wg_
   a.lds_cap_e = b->cap_e;
   a.trace_cap = b->trace_cap;
   a.trace = b->d_trace;
+  a.xcd_barrier = b->xcd_barrier;
   return a;
 }
 
@@ -3637,6 +3639,21 @@ extern "C" gi_status gi_batch_set_placement(gi_batch* b, int32_t xcd_local) {
   if (b->launched) return fail(GI_ERR_INVALID_ARG, "batch launch in flight (gi_batch_wait first)");
   b->xcd_local = xcd_local != 0;
   return batch_plan(b);
+}
+
+extern "C" gi_status gi_batch_set_barrier_scope(gi_batch* b, int32_t scope) {
+  if (!b || (scope != GI_BARRIER_AGENT && scope != GI_BARRIER_XCD))
+    return fail(GI_ERR_INVALID_ARG, "bad barrier scope");
+  if (b->launched) return fail(GI_ERR_INVALID_ARG, "batch launch in flight (gi_batch_wait first)");
+  b->xcd_barrier = scope == GI_BARRIER_XCD ? 1 : 0;
+  batch_drop_graph(b);  // the captured launch holds the old arguments
+  return GI_OK;
+}
+
+extern "C" gi_status gi_batch_get_barrier_scope(const gi_batch* b, int32_t* scope) {
+  if (!b || !scope) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  *scope = b->xcd_barrier ? GI_BARRIER_XCD : GI_BARRIER_AGENT;
+  return GI_OK;
 }
 
 extern "C" gi_status gi_batch_get_placement(const gi_batch* b, int32_t* xcd_local) {

@@ -242,6 +242,7 @@ struct TaskCtl {
   unsigned long long thresh; // SSSP: the current bucket ends below thresh
   unsigned long long fmin;   // SSSP: smallest far distance at or beyond thresh
   unsigned long long farc[3];  // SSSP: far-set sizes, rotating like qn
+  unsigned xcds;             // XCDs the task's workgroups run on (bit per XCC id)
 };
 
 struct BatchTask {
@@ -275,6 +276,8 @@ struct BatchArgs {
   long long spin_limit;  // wall-clock ticks a barrier may wait
   int lds_cap_e;
   int trace_cap;         // per-task step records kept (0: no trace)
+  int xcd_barrier;       // 1: a task whose workgroups all run on one XCD uses the
+                         // one-XCD barrier (L1 invalidate only); 0: agent scope
   long long* trace;      // [task][trace_cap][2]: wall clock at the step's start,
                          // (pull << 62) | frontier size (BFS) or 0 (PageRank)
 };

@@ -42,31 +42,35 @@ def test_sssp_step_bytes():
 
 
 def test_profile_traffic_follows_the_source_hash(tmp_path, monkeypatch):
-    # the committed figure is read while the sources match, and only for the
-    # workload (and, where the figures name one, the schedule) it was taken on
-    wl = "rmat22_ef16_bfs64_plus_cc"
-    real = bench.profile_traffic("k_batch", wl)
-    assert real is not None and real > 0
-    assert bench.profile_traffic("k_batch", "some_other_workload") is None
-    assert bench.profile_traffic("no_such_kernel") is None
-    pr = "k_pr_ord + k_pr_ord_split"
-    s22 = dict(vertex_order=1, num_segments=1, block_threads=1024, pull_items_per_thread=4,
-               pull_hot_sources=-1)
-    t22 = bench.profile_traffic(pr, "pagerank20_rmat22_ef16", s22)
-    t16 = bench.profile_traffic(pr, "pagerank20_rmat16_ef16", dict(s22, pull_hot_sources=0))
-    assert t22 and t16 and t22 > 100 * t16
-    assert bench.profile_traffic(pr, "pagerank20_rmat22_ef16", dict(s22, block_threads=512)) is None
-    assert bench.profile_traffic(pr, "pagerank20_rmat22_ef16", None) is None
-    # a copy of the tree whose batch source differs: the figure is stale
-    csrc = os.path.join(ROOT, "paper_1805_00923_amd", "csrc")
-    fake = tmp_path / "paper_1805_00923_amd" / "csrc"
-    shutil.copytree(csrc, fake)
-    shutil.copytree(os.path.join(ROOT, "profiles"), tmp_path / "profiles")
+    """A committed figure is read only for its kernel, workload and (where
+    named) schedule, and only while the kernel's sources hash to the value
+    recorded with it."""
+    import hashlib
+    csrc = tmp_path / "paper_1805_00923_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (csrc / "a.hip").write_text("kernel a\n")
+    (csrc / "b.h").write_text("header b\n")
+    sha = hashlib.sha256(b"kernel a\nheader b\n").hexdigest()
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    sched = dict(vertex_order=1, num_segments=1, block_threads=1024, pull_items_per_thread=4,
+                 pull_hot_sources=-1)
+    (prof / "x.md").write_text(
+        "text\n<!-- figures\nkernel: kx\nworkload: w1\nschedule: %s\nsource_sha256: %s\n"
+        "sources: a.hip b.h\ntraffic_bytes_per_launch: 1234\n-->\n" % (bench.sched_key(sched), sha))
+    (prof / "y.md").write_text(
+        "<!-- figures\nkernel: ky\nsource_sha256: %s\nsources: a.hip b.h\n"
+        "traffic_bytes_per_launch: 99\n-->\n" % sha)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.profile_traffic("k_batch", wl) == real
-    with open(fake / "batch.hip", "a") as f:
-        f.write("\n// changed\n")
-    assert bench.profile_traffic("k_batch", wl) is None
+    assert bench.profile_traffic("kx", "w1", sched) == 1234
+    assert bench.profile_traffic("kx", "w2", sched) is None          # other workload
+    assert bench.profile_traffic("kx", "w1", dict(sched, block_threads=512)) is None
+    assert bench.profile_traffic("kx", "w1", None) is None           # schedule required
+    assert bench.profile_traffic("ky", "anything") == 99             # names neither
+    assert bench.profile_traffic("kz") is None
+    (csrc / "b.h").write_text("header b, changed\n")
+    assert bench.profile_traffic("kx", "w1", sched) is None          # sources changed
+    assert bench.profile_traffic("ky") is None
 
 
 def test_gpu_clocks_reports_failure_as_text():

@@ -67,17 +67,34 @@ def check(tasks):
             assert pr_max_rel(got, ref) <= PR_RTOL, (i, el.name, t["iters"])
 
 
-def test_batch_matches_oracle():
+@pytest.mark.parametrize("scope", [1, 0], ids=["xcd_barrier", "agent_barrier"])
+def test_batch_matches_oracle(scope):
     import torch
     import paper_1805_00923_amd as gi
     P = pool()
     tasks = make_tasks(torch, 40)
-    say("batch create 40 tasks")
+    say("batch create 40 tasks, barrier scope %d" % scope)
     b = gi.Batch([g for _, g, _ in P], tasks)
+    assert b.barrier_scope() == gi.BARRIER_XCD
+    b.set_barrier_scope(scope)
+    assert b.barrier_scope() == scope
     say("batch run direct")
     b.run(use_graph=False)
     torch.cuda.synchronize()
     check(tasks)
+    # both scopes from one batch, replayed from a graph (the graph is
+    # recaptured when the scope changes), with eager writes in between
+    for sc in (1 - scope, scope):
+        b.set_barrier_scope(sc)
+        for _ in range(2):
+            for t in tasks:
+                t["out"].fill_(-5 if t["algorithm"] == 1 else -2.0)
+            say("batch graph replay, barrier scope %d" % sc)
+            b.run(use_graph=True)
+            torch.cuda.synchronize()
+            check(tasks)
+    with pytest.raises(gi.GiError):
+        b.set_barrier_scope(2)
     info = b.info()
     assert info["grid"] >= 1 and np.all(info["workgroups"] >= 1)
     for i, t in enumerate(tasks):
