@@ -151,11 +151,13 @@ def cc_step_bytes(n, dirs, fs, ds, es):
     return out
 
 
-def sssp_step_bytes(dirs, fs, ds, es):
-    """Per-step bytes of the SSSP step kernel: a relaxation step reads the
-    items' ids and offsets and the distances of F (12|F|) and per edge the
-    index, the weight and the atomic-min target (12 E)."""
-    return [12 * int(f) + 12 * int(e) for f, e in zip(fs, es)]
+def sssp_label_setting_bytes(m_reach, n_reach):
+    """Algorithmic bytes of one SSSP run: the label-setting minimum, which
+    relaxes every edge out of a reached vertex once (index, weight, target
+    distance: 12 m_reach) and reads each reached vertex's offsets and
+    distance once (12 n_reach).  Work beyond it is the re-relaxation factor,
+    reported apart."""
+    return 12 * int(m_reach) + 12 * int(n_reach)
 
 
 SCHED_KEY_FIELDS = ("vertex_order", "num_segments", "segments_concurrent", "block_threads",
@@ -581,7 +583,17 @@ def run_pr(args, torch, dev, scale):
     return value, "GTEPS", ms_step, "f32 storage / f64 accumulate", config, tally.roofline(), cpu, extra
 
 
+SSSP_BATCH_DELTAS = (1000, 1 << 10, 1 << 11, 1 << 12, 1 << 13, 1 << 14)
+
+
 def run_sssp(args, torch, dev):
+    """Delta-stepping SSSP from 4 sources on the 4096 x 4096 grid: the
+    engine's per-phase launches (delta swept over {2^k, 5 <= k <= 14} and
+    1000), and the 4 sources as SSSP tasks of one persistent launch (delta
+    swept over the upper part of the same set).  Bytes are the label-setting
+    minimum; the re-relaxation factor (edges relaxed / m_reach) is reported
+    beside it, as are the phases and the time per delta-stepping phase of
+    the engine at the same delta."""
     import numpy as np
 
     import graphgen as gg
@@ -605,53 +617,52 @@ def run_sssp(args, torch, dev):
     kw.update(sched_overrides(args.schedule))
     g.set_schedule(**kw)
     odeg = np.diff(g.out_off).astype(np.int64)
-    m_reach = []
+    m_reach, n_reach, refs = [], [], []
     for s in srcs:
         g.sssp(int(s), dist)
+        refs.append(dist.clone())
         d = dist.cpu().numpy().view(np.uint32)
-        m_reach.append(int(odeg[d != 0xFFFFFFFF].sum()))
-    g.set_step_timing(True)
+        reached = d != 0xFFFFFFFF
+        m_reach.append(int(odeg[reached].sum()))
+        n_reach.append(int(reached.sum()))
+    run_bytes = [sssp_label_setting_bytes(mr, nr) for mr, nr in zip(m_reach, n_reach)]
     for _ in range(args.warmup):
         for s in srcs:
             g.sssp(int(s), dist)
     torch.cuda.synchronize()
-    kms, phases = [], []
-    tally = KernelTally("k_sssp_step")
+    phases, relaxed = [], 0
+    tally = KernelTally("sssp engine (all kernels of a run)")
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        for s in srcs:
+        for i, s in enumerate(srcs):
             g.sssp(int(s), dist)
             st = g.stats()
-            kms.append(st.kernel_ms)
             phases.append(st.steps)
-            dirs, fs, ds = st.trace()
-            _, mm = g.step_times()
-            sb = sssp_step_bytes(dirs, fs, ds, st.step_edges_examined())
-            if len(mm) >= len(sb):   # traces longer than the event capacity are skipped
-                tally.add(mm, sb)
+            relaxed += int(sum(st.step_edges_examined()))
+            tally.add([st.kernel_ms], [run_bytes[i]])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = sum(m_reach) * args.steps / dt / 1e9
-    kmed = float(np.median(kms))
     roof = tally.roofline()
     wname = ("sssp_grid4096_noshortcut" if args.grid_shortcuts == 0 else
              "sssp_grid4096_shortcut%gpct" % (100 * args.grid_shortcuts))
     config = {"workload": wname, "n": g.n, "m": g.m, "sources": 4,
               "schedule": g.schedule().as_dict(), "sssp_path": args.sssp_path}
+    plain_ms = dt * 1e3 / args.steps
     extra = {"phases_median": int(np.median(phases)), "delta_sweep_ms": sweep,
-             "delta": best_delta, "plain_ms": round(dt * 1e3 / args.steps, 3),
-             "plain_gteps": round(value, 3)}
-    ms_step = dt * 1e3 / args.steps
+             "delta": best_delta, "plain_ms": round(plain_ms, 3),
+             "plain_gteps": round(value, 3),
+             "plain_us_per_phase": round(plain_ms * 1e3 / (sum(phases) / args.steps), 3),
+             "plain_rerelaxation": round(relaxed / (args.steps * sum(m_reach)), 4),
+             "plain_roofline": roof, "m_reach": m_reach, "n_reach": n_reach,
+             "label_setting_bytes_per_step": int(sum(run_bytes))}
+    ms_step = plain_ms
     if args.sssp_path == "batched":
         # the 4 sources as SSSP tasks of one persistent launch (task barriers
         # instead of per-phase kernel launches); bucket width swept untimed
-        refs = []
-        for s_ in srcs:
-            g.sssp(int(s_), dist)
-            refs.append(dist.clone())
         outs = [torch.empty(g.n, dtype=torch.int32, device=dev) for _ in srcs]
         bsweep, best = {}, None
-        for delta in (4096, 8192, 16384, 32768):
+        for delta in SSSP_BATCH_DELTAS:
             b = gi.Batch([g], [dict(graph=0, algorithm=gi.ALG_SSSP, src=int(s_), sssp_delta=delta,
                                     out=o) for s_, o in zip(srcs, outs)])
             b.set_barrier_scope(barrier_scope(args))
@@ -668,14 +679,14 @@ def run_sssp(args, torch, dev):
                 b.close()
         bdelta, b = best
         log("batched sssp delta sweep (ms): %s -> %d" % (bsweep, bdelta))
-        # algorithmic bytes of the same phases: the plain path at that delta
+        # the engine's phases at the same delta: the rounds a delta-stepping
+        # schedule needs, against which the launch's time per phase is taken
         g.set_schedule(**dict(kw, sssp_delta=bdelta))
-        bbytes = 0
+        eng_phases = []
         for s_ in srcs:
             g.sssp(int(s_), dist)
-            st = g.stats()
-            dirs, fs, ds = st.trace()
-            bbytes += int(sum(sssp_step_bytes(dirs, fs, ds, st.step_edges_examined())))
+            eng_phases.append(int(g.stats().steps))
+        g.set_schedule(**kw)
         for _ in range(args.warmup):
             b.run()
         torch.cuda.synchronize()
@@ -683,7 +694,7 @@ def run_sssp(args, torch, dev):
         t0 = time.perf_counter()
         for _ in range(args.steps):
             b.run()
-            btally.add([b.info()["ms"]], [bbytes])
+            btally.add([b.info()["ms"]], [sum(run_bytes)])
         torch.cuda.synchronize()
         dtb = time.perf_counter() - t0
         bad = sum(int(not torch.equal(o, r)) for o, r in zip(outs, refs))
@@ -691,12 +702,18 @@ def run_sssp(args, torch, dev):
             raise RuntimeError("batched SSSP distances differ from the plain path")
         value = sum(m_reach) * args.steps / dtb / 1e9
         ms_step = dtb * 1e3 / args.steps
-        roof = btally.roofline()
+        extra["batched_roofline"] = roof = btally.roofline()
         info = b.info()
+        bedges = b.edges()
+        task_us = [float(x) * 1e3 for x in info["task_ms"]]
         extra.update({"batched_ms": round(ms_step, 3), "batched_delta": bdelta,
                       "batched_delta_sweep_ms": bsweep, "batch_threads": b.threads(),
                       "batch_workgroups": [int(x) for x in info["workgroups"]],
                       "batch_phases": [int(x) for x in info["levels"]],
+                      "engine_phases_at_batched_delta": eng_phases,
+                      "batched_us_per_engine_phase": [round(t / p, 3) for t, p in
+                                                      zip(task_us, eng_phases)],
+                      "batched_rerelaxation": round(float(bedges.sum()) / sum(m_reach), 4),
                       "speedup_vs_plain": round(dt / dtb, 3)})
         config["batched_delta"] = bdelta
         b.close()

@@ -662,6 +662,15 @@ gi_status gi_batch_wait(gi_batch* b);
  * Errors: INVALID_ARG, DEVICE. */
 gi_status gi_batch_info(const gi_batch* b, float* last_ms, int32_t* grid, int32_t* workgroups,
                         int32_t* levels, float* task_ms);
+
+/* Edges relaxed by each task in the last run (edges: host array of the
+ * batch's task count): for an SSSP task, every edge of every near-set
+ * member each time that member was relaxed, so edges / (edges out of the
+ * reached vertices) is the re-relaxation factor of delta-stepping (Meyer
+ * and Sanders): its work beyond a label-setting order, which relaxes each
+ * reached edge once; 0 for BFS and PageRank tasks.
+ * Errors: INVALID_ARG (also while a launch is in flight), DEVICE. */
+gi_status gi_batch_edges(const gi_batch* b, int64_t* edges);
 gi_status gi_batch_destroy(gi_batch* b);
 
 /* ---- frontier primitives (device, stream ordered) -------------------- */

@@ -162,6 +162,7 @@ _SIGS = {
     "gi_batch_launch": (ctypes.c_int, [_vp, _i32, _vp]),
     "gi_batch_wait": (ctypes.c_int, [_vp]),
     "gi_batch_info": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "gi_batch_edges": (ctypes.c_int, [_vp, _vp]),
     "gi_batch_destroy": (ctypes.c_int, [_vp]),
     "gi_batch_set_threads": (ctypes.c_int, [_vp, _i32]),
     "gi_batch_get_threads": (ctypes.c_int, [_vp, _vp]),
@@ -735,3 +736,9 @@ class Batch:
                                  lv.ctypes.data, tm.ctypes.data))
         return {"ms": ms.value, "grid": grid.value, "workgroups": wg, "levels": lv,
                 "task_ms": tm}
+
+    def edges(self):
+        """Edges each task relaxed in the last run (SSSP tasks; 0 for others)."""
+        e = np.zeros(self.ntasks, np.int64)
+        _check(lib.gi_batch_edges(self._h, e.ctypes.data))
+        return e

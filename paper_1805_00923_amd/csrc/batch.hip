@@ -224,19 +224,58 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
 }
 
 
-// Relaxation of a batch SSSP phase: push with weights, the improved vertex
-// goes to the next near set when its new distance is inside the bucket,
-// else to the far set; insertions are counted for the phase totals.
+// Appends v of each lane that holds one (v >= 0; -1: none) to q, at
+// positions taken from *tail by one atomic per wave.
+__device__ __forceinline__ void wave_append(int32_t* q, unsigned long long* tail, int v) {
+  const unsigned long long mk = __ballot(v >= 0);
+  if (mk == 0ull) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)mk) - 1;
+  int base = 0;
+  if (lane == leader) base = (int)atomicAdd(tail, (unsigned long long)__popcll(mk));
+  base = __shfl(base, leader, kWave);
+  if (v >= 0) q[base + __popcll(mk & ((1ull << lane) - 1ull))] = v;
+}
+
+// Appends the members of word w held in bits (each lane its own word; 0:
+// none) to q, at positions taken from *tail by one atomic per wave.
+__device__ __forceinline__ void wave_append_bits(int32_t* q, unsigned long long* tail, int w,
+                                                 uint64_t bits) {
+  int tot;
+  const int ex = wave_excl_scan((int)__popcll(bits), &tot);
+  if (tot == 0) return;
+  int base = 0;
+  if (__lane_id() == 0) base = (int)atomicAdd(tail, (unsigned long long)tot);
+  base = __shfl(base, 0, kWave) + ex;
+  while (bits) {
+    q[base++] = (w << 6) + __ffsll((long long)bits) - 1;
+    bits &= bits - 1;
+  }
+}
+
+// Relaxation of a scanned (word by word) batch SSSP phase: push with
+// weights, the improved vertex goes to the next near set when its new
+// distance is inside the bucket, else to the far set.  A vertex newly
+// entered into a set is also written to that set's workgroup buffer in LDS
+// (cap entries each; the counters keep counting past it), which the phase
+// appends to the set's list at its end: the lists cost no round trip per
+// edge.
 struct BatchSsspVisit {
   const int32_t* idx;
   const uint32_t* w;
   uint32_t* dist;
   DenseSet near;
   DenseSet far;
+  int* qbuf;  // LDS: new near members
+  int* qcnt;
+  int* fbuf;  // LDS: new far members
+  int* fcnt;
+  int cap;
   unsigned long long thresh;
   int* overflow;
-  long long near_new = 0, far_new = 0;
+  long long far_new = 0, edges = 0;
   __device__ __forceinline__ void operator()(int u, int e, bool valid) {
+    edges += valid;
     if (!valid) return;
     const int v = idx[e];
     const unsigned long long nd = (unsigned long long)dist[u] + (unsigned long long)w[e];
@@ -248,12 +287,204 @@ struct BatchSsspVisit {
     const uint32_t old = atomicMin(&dist[v], (uint32_t)nd);
     if ((uint32_t)nd >= old) return;
     if (nd < thresh) {
-      if (near.insert(v)) ++near_new;
+      if (near.insert(v)) {
+        const int p = atomicAdd(qcnt, 1);
+        if (p < cap) qbuf[p] = v;
+      }
     } else if (far.insert(v)) {
       ++far_new;
+      const int p = atomicAdd(fcnt, 1);
+      if (p < cap) fbuf[p] = v;
     }
   }
 };
+
+// A set of at most n / 64 members is cleared through its list: the list is
+// no longer than the bitvector's words.
+__device__ __forceinline__ bool sssp_list_clear(long long members, int n) {
+  return members * 64 <= (long long)n;
+}
+
+// Local lists of a walked phase, in the kernel's dynamic LDS (int words):
+// two lists of C entries (vertex, distance, row start, degree), the degree
+// prefix of the list being expanded, and CF far candidates.
+template <int BT>
+struct WalkLds {
+  static constexpr int C = BT < 384 ? BT : 384;
+  static constexpr int CF = 512;
+  static constexpr int kInts = 9 * C + 1 + CF;
+  static_assert(kInts <= kPushList, "walk lists exceed the batch LDS");
+};
+
+// A near set that gives each of the task's k workgroups at most one local
+// list (C members) is walked: such phases are few vertices deep and bound by
+// memory latency, which the walk's local rounds pay without task barriers.
+// Larger sets are scanned word by word in vertex order, all workgroups busy.
+template <int BT>
+__device__ __forceinline__ bool sssp_walk(long long members, int k) {
+  return members <= (long long)k * WalkLds<BT>::C;
+}
+
+// One walked phase of a workgroup: its share ids[lo, hi) of the near set is
+// relaxed, and so is every vertex those relaxations move into the current
+// bucket, round after round from a workgroup-local list, until the list is
+// empty (label-correcting inside the bucket, as the phases of the bucket
+// are; every improvement is relaxed by the workgroup that made it, with the
+// distance it wrote).  A round needs two dependent memory trips (the edge,
+// then the atomic minimum together with the target's row bounds) and no
+// task barrier.  Entries beyond the list's capacity go to the next phase's
+// near set (nxt and its list); far improvements are gathered in LDS and
+// entered into the far set once at the end.  Returns the far insertions;
+// *edges (thread 0) counts the edges relaxed.
+template <int BT>
+__device__ long long sssp_walk_phase(const BatchGraph& G, uint32_t* dist, const int32_t* ids,
+                                     long long lo, long long hi, unsigned long long th,
+                                     DenseSet nxt, int32_t* near_q, unsigned long long* near_tail,
+                                     DenseSet far, int32_t* far_q, unsigned long long* far_tail,
+                                     int* overflow, int* lds, long long* edges) {
+  using L = WalkLds<BT>;
+  constexpr int C = L::C, CF = L::CF;
+  int* Lv = lds;              // [2][C] vertex
+  int* Ld = lds + 2 * C;      // [2][C] distance it was given
+  int* Lb = lds + 4 * C;      // [2][C] row start
+  int* Lg = lds + 6 * C;      // [2][C] degree
+  int* pre = lds + 8 * C;     // [C + 1] degree prefix of the list in expansion
+  int* fbuf = lds + 9 * C + 1;  // [CF] far candidates
+  __shared__ int s_cnt[2], s_fcnt;
+  const int tid = threadIdx.x, lane = __lane_id();
+  const int32_t* off = G.out_off;
+  const int32_t* idx = G.out_idx;
+  const uint32_t* wt = G.out_w;
+  long long far_new = 0;
+  if (tid == 0) s_fcnt = 0;
+  for (long long c0 = lo; c0 < hi; c0 += C) {  // block-uniform
+    const int cnt0 = (int)min((long long)C, hi - c0);
+    if (tid < cnt0) {
+      const int v = ids[c0 + tid];
+      const int b = off[v], e = off[v + 1];
+      Lv[tid] = v;
+      Ld[tid] = (int)dist[v];
+      Lb[tid] = b;
+      Lg[tid] = e - b;
+    }
+    if (tid == 0) s_cnt[0] = cnt0;
+    int a = 0;
+    __syncthreads();
+    for (;;) {
+      const int cnt = min(s_cnt[a], C);
+      if (cnt == 0) break;  // block-uniform: read after a barrier, written before it
+      int E;
+      const int ex = block_excl_scan<BT>(tid < cnt ? Lg[a * C + tid] : 0, &E);
+      if (tid < cnt) pre[tid] = ex;
+      if (tid == 0) {
+        s_cnt[a ^ 1] = 0;
+        *edges += E;
+      }
+      __syncthreads();
+      const int b = a ^ 1;
+      for (int t0 = 0; t0 < E; t0 += BT) {  // block-uniform: the appends are wave-wide
+        const int t = t0 + tid;
+        int to_loc = -1, to_far = -1, nb = 0, ng = 0;
+        unsigned ndv = 0;
+        if (t < E) {
+          int jl = 0, jh = cnt - 1;  // the last entry whose prefix is <= t
+          while (jl < jh) {
+            const int mid = (jl + jh + 1) >> 1;
+            if (pre[mid] <= t) jl = mid;
+            else jh = mid - 1;
+          }
+          const int e = Lb[a * C + jl] + (t - pre[jl]);
+          const int v = idx[e];
+          const unsigned long long nd =
+              (unsigned long long)(unsigned)Ld[a * C + jl] + (unsigned long long)wt[e];
+          if (nd >= 0xFFFFFFFFull) {
+            __hip_atomic_store(overflow, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } else {
+            // the row bounds are loaded before the atomic: one round trip for both
+            nb = off[v];
+            const int ne = off[v + 1];
+            const uint32_t old = atomicMin(&dist[v], (uint32_t)nd);
+            if ((uint32_t)nd < old) {
+              if (nd < th) {
+                to_loc = v;
+                ndv = (unsigned)nd;
+                ng = ne - nb;
+              } else {
+                to_far = v;
+              }
+            }
+          }
+        }
+        // into the next local list; past its capacity into the next phase
+        int spill = -1;
+        unsigned long long mk = __ballot(to_loc >= 0);
+        if (mk) {
+          const int leader = __ffsll((long long)mk) - 1;
+          int base = 0;
+          if (lane == leader) base = atomicAdd(&s_cnt[b], __popcll(mk));
+          base = __shfl(base, leader, kWave);
+          if (to_loc >= 0) {
+            const int pos = base + __popcll(mk & ((1ull << lane) - 1ull));
+            if (pos < C) {
+              Lv[b * C + pos] = to_loc;
+              Ld[b * C + pos] = (int)ndv;
+              Lb[b * C + pos] = nb;
+              Lg[b * C + pos] = ng;
+            } else {
+              spill = to_loc;
+            }
+          }
+          if (__ballot(spill >= 0)) {
+            const int ins = (spill >= 0 && nxt.insert(spill)) ? spill : -1;
+            wave_append(near_q, near_tail, ins);
+          }
+        }
+        // far candidates wait in LDS for one insertion pass at the end
+        int fspill = -1;
+        mk = __ballot(to_far >= 0);
+        if (mk) {
+          const int leader = __ffsll((long long)mk) - 1;
+          int base = 0;
+          if (lane == leader) base = atomicAdd(&s_fcnt, __popcll(mk));
+          base = __shfl(base, leader, kWave);
+          if (to_far >= 0) {
+            const int pos = base + __popcll(mk & ((1ull << lane) - 1ull));
+            if (pos < CF) fbuf[pos] = to_far;
+            else fspill = to_far;
+          }
+          if (__ballot(fspill >= 0)) {
+            const int ins = (fspill >= 0 && far.insert(fspill)) ? fspill : -1;
+            wave_append(far_q, far_tail, ins);
+            far_new += ins >= 0;
+          }
+        }
+      }
+      __syncthreads();
+      a = b;
+    }
+    __syncthreads();  // every thread has seen the empty list before the next chunk
+  }
+  __syncthreads();  // s_fcnt is final (also when the share was empty)
+  const int fc = min(s_fcnt, CF);
+  for (int i0 = 0; i0 < fc; i0 += BT) {  // block-uniform: the appends are wave-wide
+    const int i = i0 + tid;
+    int ins = -1;
+    if (i < fc) {
+      const int v = fbuf[i];
+      if (far.insert(v)) ins = v;
+    }
+    wave_append(far_q, far_tail, ins);
+    far_new += ins >= 0;
+  }
+  return far_new;
+}
+
+// Rank r's share [lo, hi) of len list entries split over k workgroups.
+__device__ __forceinline__ void list_share(long long len, int r, int k, long long* lo,
+                                           long long* hi) {
+  *lo = len * r / k;
+  *hi = len * (r + 1) / k;
+}
 
 template <int BT>
 __device__ void sssp_task(const BatchGraph& G, const BatchTask& t, int r, const BatchArgs& a,
@@ -262,6 +493,8 @@ __device__ void sssp_task(const BatchGraph& G, const BatchTask& t, int r, const 
   uint32_t* dist = static_cast<uint32_t*>(t.out);
   TaskCtl* c = t.ctl;
   uint64_t* bv[3] = {t.bv0, t.bv1, t.bv2};
+  int32_t* nq[3] = {t.q, t.q + (size_t)n, t.q + 2 * (size_t)n};  // member lists of bv[]
+  int32_t* fl[2] = {t.q + 3 * (size_t)n, t.q + 4 * (size_t)n};    // far lists, alternating
   uint64_t* far = t.vis;
   const unsigned long long delta = t.delta;
   const int w0 = (int)((long long)W * r / k), w1 = (int)((long long)W * (r + 1) / k);
@@ -279,15 +512,27 @@ __device__ void sssp_task(const BatchGraph& G, const BatchTask& t, int r, const 
   if (r == 0 && tid == 0) {
     dist[t.src] = 0u;
     t.bv0[t.src >> 6] = 1ull << (t.src & 63);
+    nq[0][0] = t.src;
     c->qn[0] = 1;
     c->thresh = delta;
   }
   if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
   __shared__ unsigned long long s_red[BT / kWave];
+  // scanned phases: the new members of the next near set and of the far set
+  constexpr int kBuf = 512;
+  __shared__ int s_qbuf[kBuf], s_fbuf[kBuf];
+  __shared__ int s_qcnt, s_fcnt;
+  __shared__ long long s_base[2];
+  long long relaxed = 0;  // edges this workgroup relaxed (thread 0)
+  long long prev = 0;     // members of the previous phase's near set
+  bool prev_listed = true;  // ... and whether its list was complete
+  int fs = 0;             // far list in use
   int P = 0;
   for (;; ++P) {
     const long long nf = (long long)__hip_atomic_load(&c->qn[P % 3], __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
+    const bool listed = __hip_atomic_load(&c->qbad[P % 3], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT) == 0;
     const unsigned long long fc = __hip_atomic_load(&c->farc[P % 3], __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
     const unsigned long long th = __hip_atomic_load(&c->thresh, __ATOMIC_RELAXED,
@@ -302,7 +547,9 @@ __device__ void sssp_task(const BatchGraph& G, const BatchTask& t, int r, const 
       return;
     }
     if (r == 0 && tid == 0) {
+      // the counters of the phase after next (read by all in the previous phase)
       c->qn[(P + 2) % 3] = 0;
+      c->qbad[(P + 2) % 3] = 0;
       c->farc[(P + 2) % 3] = 0;
       if (a.trace_cap > P) {
         long long* rec = a.trace + ((size_t)t.id * a.trace_cap + P) * 2;
@@ -312,34 +559,85 @@ __device__ void sssp_task(const BatchGraph& G, const BatchTask& t, int r, const 
     }
     uint64_t* cur = bv[P % 3];
     uint64_t* nxt = bv[(P + 1) % 3];
-    for (int w = w0 + tid; w < w1; w += BT) bv[(P + 2) % 3][w] = 0ull;
+    // the previous phase's near set is cleared for the next phase to fill:
+    // through its list when short and complete, else word by word
+    uint64_t* bclr = bv[(P + 2) % 3];
+    long long lo, hi;
+    if (prev_listed && sssp_list_clear(prev, n)) {
+      const int32_t* q = nq[(P + 2) % 3];
+      list_share(prev, r, k, &lo, &hi);
+      for (long long i = lo + tid; i < hi; i += BT) bclr[q[i] >> 6] = 0ull;
+    } else {
+      for (int w = w0 + tid; w < w1; w += BT) bclr[w] = 0ull;
+    }
+    prev = nf;
+    prev_listed = listed;
     if (nf > 0) {
       // relax the near set
       if (r == 0 && tid == 0) {
         c->fmin = ~0ull;
         if (fc) atomicAdd(&c->farc[(P + 1) % 3], fc);  // far members carry over
       }
-      BatchSsspVisit vis{G.out_idx, G.out_w, dist, DenseSet{nxt, nullptr},
-                         DenseSet{far, nullptr}, th, &c->overflow};
-      push_words<BT>(cur, w0, w1, n, G.out_off, vis, 0x7fffffff, lds);
-      const Part p = block_sum4<BT>(Part{vis.near_new, vis.far_new, 0, 0});
-      if (tid == 0) {
-        if (p.a) atomicAdd(&c->qn[(P + 1) % 3], (unsigned long long)p.a);
-        if (p.b) atomicAdd(&c->farc[(P + 1) % 3], (unsigned long long)p.b);
+      long long far_new, edges = 0;
+      if (listed && sssp_walk<BT>(nf, k)) {
+        list_share(nf, r, k, &lo, &hi);
+        far_new = sssp_walk_phase<BT>(G, dist, nq[P % 3], lo, hi, th, DenseSet{nxt, nullptr},
+                                      nq[(P + 1) % 3], &c->qn[(P + 1) % 3],
+                                      DenseSet{far, nullptr}, fl[fs], &c->ft[fs], &c->overflow,
+                                      lds, &edges);
+      } else {
+        if (tid == 0) s_qcnt = s_fcnt = 0;
+        __syncthreads();
+        BatchSsspVisit vis{G.out_idx, G.out_w, dist, DenseSet{nxt, nullptr},
+                           DenseSet{far, nullptr}, s_qbuf, &s_qcnt, s_fbuf, &s_fcnt, kBuf, th,
+                           &c->overflow};
+        push_words<BT>(cur, w0, w1, n, G.out_off, vis, 0x7fffffff, lds);
+        far_new = vis.far_new;
+        edges = vis.edges;
+        // the buffers go to the lists; a buffer that overflowed leaves its
+        // list incomplete, which the flags record
+        __syncthreads();
+        const int qn_ = s_qcnt, fn_ = s_fcnt;
+        if (tid == 0) {
+          s_base[0] = qn_ ? (long long)atomicAdd(&c->qn[(P + 1) % 3], (unsigned long long)qn_) : 0;
+          s_base[1] = fn_ ? (long long)atomicAdd(&c->ft[fs], (unsigned long long)min(fn_, kBuf)) : 0;
+          if (qn_ > kBuf) __hip_atomic_store(&c->qbad[(P + 1) % 3], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (fn_ > kBuf) __hip_atomic_store(&c->fbad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        for (int i = tid; i < min(qn_, kBuf); i += BT) nq[(P + 1) % 3][s_base[0] + i] = s_qbuf[i];
+        for (int i = tid; i < min(fn_, kBuf); i += BT) fl[fs][s_base[1] + i] = s_fbuf[i];
       }
+      const Part p = block_sum4<BT>(Part{far_new, edges, 0, 0});
+      if (tid == 0 && p.a) atomicAdd(&c->farc[(P + 1) % 3], (unsigned long long)p.a);
+      relaxed += p.b;  // thread 0's sum
       if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
       continue;
     }
     // split: the next bucket starts at the smallest far distance at or
-    // beyond the threshold
+    // beyond the threshold.  The far set is walked from its list when the
+    // list is complete, else scanned word by word; a scan rebuilds the list
+    // when the set is short enough to be walked next time.
+    const bool fwalk = __hip_atomic_load(&c->fbad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    const bool rebuild = fwalk || sssp_list_clear((long long)fc, n);
+    const long long flen = (long long)__hip_atomic_load(&c->ft[fs], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t* fcur = fl[fs];
+    list_share(flen, r, k, &lo, &hi);
     unsigned long long mn = ~0ull;
-    for (int w = w0 + tid; w < w1; w += BT) {
-      uint64_t x = far[w];
-      while (x) {
-        const int v = (w << 6) + __ffsll((long long)x) - 1;
-        x &= x - 1;
-        const unsigned long long d = dist[v];
+    if (fwalk) {
+      for (long long i = lo + tid; i < hi; i += BT) {
+        const unsigned long long d = dist[fcur[i]];
         if (d >= th && d < mn) mn = d;
+      }
+    } else {
+      for (int w = w0 + tid; w < w1; w += BT) {
+        uint64_t x = far[w];
+        while (x) {
+          const unsigned long long d = dist[(w << 6) + __ffsll((long long)x) - 1];
+          x &= x - 1;
+          if (d >= th && d < mn) mn = d;
+        }
       }
     }
     mn = wave_min(mn);
@@ -349,39 +647,67 @@ __device__ void sssp_task(const BatchGraph& G, const BatchTask& t, int r, const 
       for (int i = 0; i < BT / kWave; ++i) mn = s_red[i] < mn ? s_red[i] : mn;
       if (mn != ~0ull) atomicMin(&c->fmin, mn);
     }
+    if (r == 0 && tid == 0) c->ft[fs ^ 1] = 0;  // the list the kept members go to
     if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
+    // every workgroup has read fbad above
+    if (r == 0 && tid == 0) c->fbad = rebuild ? 0 : 1;
     const unsigned long long fm = __hip_atomic_load(&c->fmin, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
     const unsigned long long tnew = fm == ~0ull ? th : (fm / delta + 1ull) * delta;
-    long long moved = 0, kept = 0;
-    for (int w = w0 + tid; w < w1; w += BT) {
-      uint64_t x = far[w], keep = 0ull, mv = 0ull;
-      while (x) {
-        const int b = __ffsll((long long)x) - 1;
-        x &= x - 1;
-        const unsigned long long d = dist[(w << 6) + b];
-        if (d < th) continue;  // stale: relaxed in an earlier bucket
-        if (d < tnew) {
-          mv |= 1ull << b;
-          ++moved;
-        } else {
-          keep |= 1ull << b;
-          ++kept;
+    long long kept = 0;
+    if (fwalk) {
+      for (long long b0 = lo; b0 < hi; b0 += BT) {  // block-uniform: the appends are wave-wide
+        const long long i = b0 + tid;
+        int mv = -1, kp = -1;
+        if (i < hi) {
+          const int v = fcur[i];
+          const unsigned long long d = dist[v];
+          const unsigned long long bit = 1ull << (v & 63);
+          if (d < tnew) {
+            atomicAnd((unsigned long long*)&far[v >> 6], ~bit);
+            if (d >= th) {  // below th: stale, relaxed in an earlier bucket
+              atomicOr((unsigned long long*)&nxt[v >> 6], bit);
+              mv = v;
+            }
+          } else {
+            kp = v;
+          }
         }
+        wave_append(nq[(P + 1) % 3], &c->qn[(P + 1) % 3], mv);
+        wave_append(fl[fs ^ 1], &c->ft[fs ^ 1], kp);
+        kept += kp >= 0;
       }
-      far[w] = keep;
-      nxt[w] = mv;  // this workgroup's words; cleared two phases ago
+    } else {
+      for (int b0 = w0; b0 < w1; b0 += BT) {  // block-uniform: the appends are wave-wide
+        const int w = b0 + tid;
+        uint64_t keep = 0ull, mv = 0ull;
+        if (w < w1) {
+          uint64_t x = far[w];
+          while (x) {
+            const int b = __ffsll((long long)x) - 1;
+            x &= x - 1;
+            const unsigned long long d = dist[(w << 6) + b];
+            if (d < th) continue;  // stale: relaxed in an earlier bucket
+            if (d < tnew) mv |= 1ull << b;
+            else keep |= 1ull << b;
+          }
+          far[w] = keep;
+          nxt[w] = mv;  // this workgroup's words; cleared in the previous phase
+        }
+        wave_append_bits(nq[(P + 1) % 3], &c->qn[(P + 1) % 3], w, mv);
+        if (rebuild) wave_append_bits(fl[fs ^ 1], &c->ft[fs ^ 1], w, keep);
+        kept += __popcll(keep);
+      }
     }
-    const Part p = block_sum4<BT>(Part{moved, kept, 0, 0});
-    if (tid == 0) {
-      if (p.a) atomicAdd(&c->qn[(P + 1) % 3], (unsigned long long)p.a);
-      if (p.b) atomicAdd(&c->farc[(P + 1) % 3], (unsigned long long)p.b);
-    }
+    const Part p = block_sum4<BT>(Part{kept, 0, 0, 0});
+    if (tid == 0 && p.a) atomicAdd(&c->farc[(P + 1) % 3], (unsigned long long)p.a);
     // every workgroup has read the old threshold (it read fmin after the
     // barrier above); rank 0 publishes the new one for the next phase
     if (r == 0 && tid == 0) c->thresh = tnew;
+    fs ^= 1;
     if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
   }
+  if (tid == 0 && relaxed) atomicAdd(&c->relaxed, (unsigned long long)relaxed);
   if (r == 0 && tid == 0) {
     c->levels = P;
     if (P < a.trace_cap) {

@@ -3165,6 +3165,8 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
       d.bv0 = d.vis + W;
       d.bv1 = d.vis + 2 * W;
       d.bv2 = d.vis + 3 * W;
+      if (d.alg == ALG_SSSP && (st = batch_alloc(b, &d.q, 5 * (size_t)g->n)) != GI_OK)
+        return bail(st);
     } else {
       if ((st = batch_alloc(b, &d.c0, 2 * (size_t)g->n)) != GI_OK) return bail(st);
       d.c1 = d.c0 + g->n;
@@ -3665,6 +3667,16 @@ extern "C" gi_status gi_batch_get_placement(const gi_batch* b, int32_t* xcd_loca
 extern "C" gi_status gi_batch_get_threads(const gi_batch* b, int32_t* threads) {
   if (!b || !threads) return fail(GI_ERR_INVALID_ARG, "NULL argument");
   *threads = b->bt;
+  return GI_OK;
+}
+
+extern "C" gi_status gi_batch_edges(const gi_batch* b, int64_t* edges) {
+  if (!b || !edges) return fail(GI_ERR_INVALID_ARG, "bad batch edge-count arguments");
+  if (b->launched) return fail(GI_ERR_INVALID_ARG, "batch launch in flight (gi_batch_wait first)");
+  const size_t nt = b->tasks.size();
+  std::vector<TaskCtl> c(nt);
+  HIP_TRY(hipMemcpy(c.data(), b->d_ctl, sizeof(TaskCtl) * nt, hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < nt; ++i) edges[i] = (int64_t)c[i].relaxed;
   return GI_OK;
 }
 

@@ -242,6 +242,10 @@ struct TaskCtl {
   unsigned long long thresh; // SSSP: the current bucket ends below thresh
   unsigned long long fmin;   // SSSP: smallest far distance at or beyond thresh
   unsigned long long farc[3];  // SSSP: far-set sizes, rotating like qn
+  unsigned long long ft[2];  // SSSP: lengths of the two far lists
+  unsigned long long relaxed;  // SSSP: edges relaxed, summed over the workgroups
+  int qbad[3];               // SSSP: the near set's list is incomplete, rotating like qn
+  int fbad;                  // SSSP: the far list is incomplete
   unsigned xcds;             // XCDs the task's workgroups run on (bit per XCC id)
 };
 
@@ -264,6 +268,7 @@ struct BatchTask {
   float* c1;
   double* lr_acc;
   unsigned* lr_cnt;
+  int32_t* q;   // SSSP: member lists of bv0..bv2, then the two far lists (5 n)
   TaskCtl* ctl;
 };
 

@@ -470,13 +470,13 @@ __device__ void push_words(const uint64_t* bv, int wb, int we, int n, const int3
 }
 
 // The rows of the listed vertices ids[begin, end), BT per group, groups
-// dealt over the grid.
+// dealt to workgroups first_block, first_block + nblocks, ...
 template <int BT, class Visit>
-__device__ void push_list(const int32_t* ids, long long begin, long long end, const int32_t* off,
-                          Visit& vis) {
+__device__ void push_list_range(const int32_t* ids, long long begin, long long end,
+                                int first_block, int nblocks, const int32_t* off, Visit& vis) {
   __shared__ int sh[4];
-  for (long long base = begin + (long long)blockIdx.x * BT; base < end;
-       base += (long long)gridDim.x * BT) {
+  for (long long base = begin + (long long)first_block * BT; base < end;
+       base += (long long)nblocks * BT) {
     const long long i = base + threadIdx.x;
     int u = -1, beg = 0, fin = 0;
     if (i < end) {
@@ -486,6 +486,13 @@ __device__ void push_list(const int32_t* ids, long long begin, long long end, co
     }
     push_rows<BT>(u, beg, fin, vis, sh);
   }
+}
+
+// The same with the groups dealt over the grid.
+template <int BT, class Visit>
+__device__ void push_list(const int32_t* ids, long long begin, long long end, const int32_t* off,
+                          Visit& vis) {
+  push_list_range<BT>(ids, begin, end, blockIdx.x, gridDim.x, off, vis);
 }
 
 template <int BT, class Visit>

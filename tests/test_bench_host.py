@@ -36,9 +36,11 @@ def test_cc_step_bytes_push_and_pull():
     assert got[1] == 16 * 7 + 8 * 30 + 0
 
 
-def test_sssp_step_bytes():
-    assert bench.sssp_step_bytes([0, 0], [3, 5], [0, 0], [12, 20]) == [12 * 3 + 12 * 12,
-                                                                       12 * 5 + 12 * 20]
+def test_sssp_label_setting_bytes():
+    # a run that reaches 3 vertices with 5 edges out of them: each edge's
+    # index, weight and target distance, each vertex's offsets and distance
+    assert bench.sssp_label_setting_bytes(5, 3) == 12 * 5 + 12 * 3
+    assert bench.sssp_label_setting_bytes(0, 1) == 12
 
 
 def test_profile_traffic_follows_the_source_hash(tmp_path, monkeypatch):
