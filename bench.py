@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--grid-shortcuts", type=float, default=0.01,
                     help="sssp_grid: shortcut pairs as a fraction of the vertices (0: the "
                          "plain grid, diameter 8190, the many-phase regime of road graphs)")
+    ap.add_argument("--delta-sweep", default="",
+                    help="sssp_grid: comma-separated bucket widths for the engine's sweep "
+                         "(default: 2^5 ... 2^14 and 1000)")
     ap.add_argument("--sssp-path", default="batched", choices=["batched", "plain"],
                     help="sssp_grid: the 4 sources as one batched launch, or 4 engine runs")
     ap.add_argument("--overlap", type=int, default=1, choices=[0, 1],
@@ -606,7 +609,9 @@ def run_sssp(args, torch, dev):
     dist = torch.empty(g.n, dtype=torch.int32, device=dev)
     # delta swept (untimed) on the first source: {2^k, 5 <= k <= 14} and 1000
     sweep = {}
-    for delta in [1 << k for k in range(5, 15)] + [1000]:
+    deltas = ([int(x) for x in args.delta_sweep.split(",")] if args.delta_sweep else
+              [1 << k for k in range(5, 15)] + [1000])
+    for delta in deltas:
         g.set_schedule(sssp_delta=delta)
         g.sssp(int(srcs[0]), dist)
         g.sssp(int(srcs[0]), dist)
