@@ -732,22 +732,52 @@ def selector_records(g, gi, alg, src=0):
     return f, y, v, t
 
 
+# fixed schedules the selector is compared against (direction 0 SparsePush,
+# 2 DensePull, 3 the hybrid rule DensePull/SparsePush, 4 DensePush/SparsePush)
+SEL_FIXED_BFS = ([dict(direction=3, hybrid_divisor=d) for d in (5, 10, 20, 40)] +
+                 [dict(direction=0), dict(direction=2), dict(direction=4)])
+SEL_FIXED_CC = ([dict(direction=0), dict(direction=2)] +
+                [dict(direction=3, hybrid_divisor=d, **seg)
+                 for seg in ({}, dict(num_segments=4, segment_strategy=1),
+                             dict(num_segments=16, segment_strategy=1))
+                 for d in (2, 8, 20)])   # one segment layout after another
+SEL_FIXED_PR = PR_CANDIDATES + [dict(num_segments=p) for p in (32, 64, 128)]
+
+
+def bf16_fp32_regret(sel, feats, times, valid):
+    """Per-step schedule choices (least predicted time among the valid
+    schedules) with BF16 and with FP32 inference on the same records: the
+    records where they differ and the time the BF16 choices cost beyond the
+    FP32 ones, in % of the FP32 choices' time."""
+    import numpy as np
+    ok = valid > 0
+    pb = np.where(ok, sel.predict(feats, bf16=True), np.inf)
+    pf = np.where(ok, sel.predict(feats, bf16=False), np.inf)
+    cb, cf = pb.argmin(1), pf.argmin(1)
+    r = np.arange(len(cb))
+    tb, tf = times[r, cb], times[r, cf]
+    return int(len(cb)), int((cb != cf).sum()), float(tb.sum()), float(tf.sum())
+
+
 def run_selector(args, torch, dev):
     """Train the selector on exhaustive per-step timings of training graphs,
-    then compare, on a held-out Chung-Lu graph (exponent 2.0), the hybrid
-    heuristic, the learned selector and the per-step best schedule."""
+    then compare, on a held-out Chung-Lu graph (exponent 2.0), per algorithm:
+    the hybrid heuristic, the best fixed schedule (autotuned on the held-out
+    graph itself), the learned selector and the per-step best schedule; and
+    check that BF16 inference chooses within 5% of FP32's choices."""
     import numpy as np
 
     import graphgen as gg
     import paper_1805_00923_amd as gi
     t_all = time.time()
-    # training graphs span the graph-level features of the held-out graph
-    # (degree exponent 2.0-3.0, 16-34 edges per vertex) without including it
+    # training graphs: R-MAT and Chung-Lu graphs with degree exponents 2.2,
+    # 2.5 and 3.0 and 20-34 edges per vertex; the held-out exponent (2.0)
+    # is not among them
     train = [("rmat", 16, 316), ("rmat", 18, 318), ("rmat", 20, 320), ("rmat", 22, 322),
              ("chunglu", 1 << 20, 2.2, 401), ("chunglu", 1 << 20, 2.5, 402),
              ("chunglu", 1 << 21, 3.0, 403), ("chunglu", 1 << 22, 2.2, 404),
-             ("chunglu34", 1 << 20, 2.0, 405), ("chunglu34", 1 << 21, 2.0, 406),
-             ("rmat", 24, 324), ("chunglu34", 1 << 24, 2.0, 407)]
+             ("chunglu34", 1 << 20, 2.2, 405), ("chunglu34", 1 << 21, 2.5, 406),
+             ("rmat", 24, 324), ("chunglu34", 1 << 24, 2.2, 407)]
     F, Y, V = [], [], []
     for spec in train:
         if spec[0] == "rmat":
@@ -812,18 +842,16 @@ def run_selector(args, torch, dev):
 
     rows = []
     cases = [(gi.ALG_BFS, int(s)) for s in srcs] + [(gi.ALG_CC, 0), (gi.ALG_PAGERANK, 0)]
-    skipped = {}
-    if 2 * g.m > 2**31 - 1:
-        # CC runs over the symmetric adjacency, 2m entries under 32-bit offsets
-        cases.remove((gi.ALG_CC, 0))
-        skipped["cc"] = "2m = %d exceeds the symmetric adjacency's 32-bit offsets" % (2 * g.m)
     regret_l, regret_h, best_steps = [], [], []
+    prec = [0, 0, 0.0, 0.0]  # records, BF16/FP32 disagreements, BF16 and FP32 choice times
     t_heur = t_learn = t_best = 0.0
     dump = {}
     for alg, s in cases:
         g.set_schedule(direction=gi.DENSE_PULL_SPARSE_PUSH)
         hf, _, v, tt = selector_records(g, gi, alg, s)
         dump["case_%d_%d" % (alg, s)] = np.concatenate([hf, tt, v.astype(np.float32)], 1)
+        rec, dis, tb, tf = bf16_fp32_regret(sel, hf, np.where(v > 0, tt, 0.0), v)
+        prec = [prec[0] + rec, prec[1] + dis, prec[2] + tb, prec[3] + tf]
         tt = np.where(v > 0, tt, np.inf)
         best = tt.min(1)
         if alg == gi.ALG_PAGERANK:
@@ -854,16 +882,112 @@ def run_selector(args, torch, dev):
                      "choices": {"heuristic": "".join(str(int(x)) for x in hchoice[:k]),
                                  "learned": "".join(str(int(x)) for x in lchoice[:k]),
                                  "best": "".join(str(int(x)) for x in tt.argmin(1))}})
+    # the best fixed schedule per algorithm, autotuned on the held-out graph:
+    # every candidate run once over the algorithm's cases (after one
+    # untimed run), the fastest then timed like the other columns
+    g.attach_selector(None)
+    names = {0: "pagerank", 1: "bfs", 2: "cc"}
+    fixed = {}
+    for alg, cands in ((gi.ALG_BFS, SEL_FIXED_BFS), (gi.ALG_CC, SEL_FIXED_CC),
+                       (gi.ALG_PAGERANK, SEL_FIXED_PR)):
+        acase = [s for a, s in cases if a == alg]
+        sweep = {}
+        for c in cands:
+            g.set_schedule(**c)
+            tot = 0.0
+            for i, s in enumerate(acase):
+                if alg == gi.ALG_BFS:
+                    if i == 0:
+                        g.bfs(int(s), out)
+                    g.bfs(int(s), out)
+                elif alg == gi.ALG_CC:
+                    g.cc(out)
+                    g.cc(out)
+                else:
+                    g.pagerank(ranks, 20, 0.85)
+                    g.pagerank(ranks, 20, 0.85)
+                tot += g.stats().kernel_ms
+            sweep[json.dumps(c)] = round(tot, 3)
+            log("held-out fixed %s %s: %.3f ms" % (names[alg], c, tot))
+        bc = json.loads(min(sweep, key=sweep.get))
+        tot = 0.0
+        for s in acase:
+            g.set_schedule(**bc)
+            ms = []
+            for _ in range(3):
+                if alg == gi.ALG_BFS:
+                    g.bfs(int(s), out)
+                elif alg == gi.ALG_CC:
+                    g.cc(out)
+                else:
+                    g.pagerank(ranks, 20, 0.85)
+                ms.append(g.stats().kernel_ms)
+            tot += float(np.median(ms))
+        fixed[names[alg]] = {"schedule": bc, "ms": round(tot, 3), "sweep_ms": sweep}
+        log("held-out best fixed %s: %s %.3f ms" % (names[alg], bc, tot))
+    # the learned direction on the autotuned layout: the best fixed schedule's
+    # layout fields (segments, vertex order, pull shape) with the learned
+    # per-step choice in place of its direction rule
+    g.attach_selector(sel)
+    layout_keys = ("num_segments", "segment_strategy", "segments_concurrent", "vertex_order",
+                   "block_threads", "pull_items_per_thread", "pull_hot_sources",
+                   "pull_block_edges")
+    for alg in (gi.ALG_BFS, gi.ALG_CC, gi.ALG_PAGERANK):
+        lay = {k: v for k, v in fixed[names[alg]]["schedule"].items() if k in layout_keys}
+        tot = 0.0
+        for s in [s for a, s in cases if a == alg]:
+            g.set_schedule(direction=gi.LEARNED, **lay)
+            ms = []
+            for _ in range(4):
+                if alg == gi.ALG_BFS:
+                    g.bfs(int(s), out)
+                elif alg == gi.ALG_CC:
+                    g.cc(out)
+                else:
+                    g.pagerank(ranks, 20, 0.85)
+                ms.append(g.stats().kernel_ms)
+            tot += float(np.median(ms[1:]))
+        fixed[names[alg]]["learned_on_layout_ms"] = round(tot, 3)
+        fixed[names[alg]]["layout"] = lay
+        log("held-out learned on the tuned layout %s %s: %.3f ms" % (names[alg], lay, tot))
+    per_alg = {}
+    for alg in ("bfs", "cc", "pagerank"):
+        rs = [r for r in rows if r["alg"] == alg]
+        h = sum(r["heuristic_ms"] for r in rs)
+        le = sum(r["learned_ms"] for r in rs)
+        b = sum(r["best_steps_ms"] for r in rs)
+        f = fixed[alg]["ms"]
+        per_alg[alg] = {"cases": len(rs), "heuristic_ms": round(h, 3),
+                        "best_fixed_ms": f, "best_fixed": fixed[alg]["schedule"],
+                        "learned_ms": round(le, 3), "per_step_best_ms": round(b, 3),
+                        "learned_vs_heuristic": round(h / le, 3),
+                        "learned_vs_best_fixed": round(f / le, 3),
+                        "tuned_layout": fixed[alg]["layout"],
+                        "learned_on_tuned_layout_ms": fixed[alg]["learned_on_layout_ms"],
+                        "learned_on_tuned_layout_vs_best_fixed":
+                            round(f / fixed[alg]["learned_on_layout_ms"], 3)}
+    t_fixed = sum(fixed[a]["ms"] for a in fixed)
+    t_learn_lay = sum(fixed[a]["learned_on_layout_ms"] for a in fixed)
     if args.selector_dump:
         p, mu, sd = sel.params()
         np.savez_compressed(args.selector_dump, X=X, Y=Yl, V=Vm, params=p, mu=mu, sd=sd, **dump)
     regret_l, regret_h = np.array(regret_l), np.array(regret_h)
-    speedup = t_heur / t_learn
+    speedup = t_fixed / t_learn
+    prec_pct = 100.0 * (prec[2] - prec[3]) / prec[3] if prec[3] > 0 else 0.0
     detail = {
+        "learned_vs_heuristic": round(t_heur / t_learn, 3),
+        "learned_vs_best_fixed": round(t_fixed / t_learn, 3),
+        "learned_on_tuned_layout_vs_best_fixed": round(t_fixed / t_learn_lay, 3),
+        "per_algorithm": per_alg,
+        "best_fixed_sweeps_ms": {a: fixed[a]["sweep_ms"] for a in fixed},
+        "bf16_vs_fp32": {"records": prec[0], "disagree": prec[1],
+                         "regret_pct": round(prec_pct, 3), "bound_pct": 5.0,
+                         "within_bound": bool(prec_pct <= 5.0)},
         "train_records": int(len(X)), "epochs": args.epochs, "train_s": round(t_train, 2),
         "loss_first_last": [round(float(loss[0]), 4), round(float(loss[-1]), 4)],
         "heldout": {"n": g.n, "m": g.m, "gamma": 2.0, "bfs_sources": int(len(srcs))},
-        "total_ms": {"heuristic": round(t_heur, 3), "learned": round(t_learn, 3),
+        "total_ms": {"heuristic": round(t_heur, 3), "best_fixed": round(t_fixed, 3),
+                     "learned": round(t_learn, 3), "learned_on_tuned_layout": round(t_learn_lay, 3),
                      "per_step_best": round(t_best, 3)},
         "regret_learned_us": {"mean": round(1e3 * regret_l.mean(), 3),
                               "p50": round(1e3 * float(np.percentile(regret_l, 50)), 3),
@@ -873,15 +997,16 @@ def run_selector(args, torch, dev):
                                 "p50": round(1e3 * float(np.percentile(regret_h, 50)), 3),
                                 "p95": round(1e3 * float(np.percentile(regret_h, 95)), 3),
                                 "total_pct": round(100 * regret_h.sum() / sum(best_steps), 2)},
-        "per_case": rows, "skipped": skipped, "wall_s": round(time.time() - t_all, 1),
+        "per_case": rows, "wall_s": round(time.time() - t_all, 1),
     }
     config = {"workload": "selector_chunglu_g2.0_%s" % args.heldout, "n": g.n, "m": g.m,
               "train_graphs": ["rmat16", "rmat18", "rmat20", "rmat22", "chunglu1M_g2.2",
                                "chunglu1M_g2.5", "chunglu2M_g3.0", "chunglu4M_g2.2",
-                               "chunglu1M_g2.0_x34", "chunglu2M_g2.0_x34", "rmat24",
-                               "chunglu16M_g2.0_x34"]}
+                               "chunglu1M_g2.2_x34", "chunglu2M_g2.5_x34", "rmat24",
+                               "chunglu16M_g2.2_x34"]}
     roof = None
-    return speedup, "x (heuristic time / learned time)", t_learn, "f32 train / bf16 infer", \
+    return speedup, "x (best fixed schedule time / learned time)", t_learn, \
+        "f32 train / bf16 infer", \
         config, roof, None, detail
 
 

@@ -73,12 +73,18 @@ enum {
   GI_DIR_DENSE_PULL_SPARSE_PUSH = 3, /* per step: DensePull if frontier is large        */
   GI_DIR_DENSE_PUSH_SPARSE_PUSH = 4, /* per step: DensePush if frontier is large        */
   GI_DIR_LEARNED = 5                 /* per step: the attached selector's choice among
-                                        SparsePush, DensePush and DensePull (BFS, CC);
+                                        SparsePush, DensePush and DensePull (BFS, CC;
+                                        CC also the segmented DensePull);
                                         PageRank: unsegmented or segmented DensePull.
                                         The fallback (the hybrid rule with the
                                         schedule's divisor; unsegmented for PageRank)
                                         is kept unless the selector predicts it to be
-                                        more than 15% slower (log-time margin 0.14) */
+                                        more than 15% slower (log-time margin 0.14).
+                                        The choice is the direction only: the layout
+                                        is the schedule's (segmented pulls use its
+                                        segments, the automatic count when it has
+                                        one; PageRank's unsegmented pull follows its
+                                        vertex_order) */
 };
 
 /* Dense vertexset representation: configApplyDenseVertexSet options. */
@@ -517,8 +523,10 @@ gi_status gi_get_step_features(const gi_graph* g, float* feats, int32_t cap, int
 
 /* Exhaustive per-step timing for selector training.  Runs `algorithm` on g
  * once per schedule S0..S3 that it offers, with per-step timing on (BFS and
- * CC: S0, S1, S2 with a bitvector frontier; PageRank, 20 iterations: S2 and
- * S3 with the graph's num_segments, or n*4/2 MiB segments when that is 1).
+ * CC: S0, S1, S2 with a bitvector frontier; CC's S3 and PageRank's S3: the
+ * DensePull over the schedule's segments, or n*4/2 MiB segments when it has
+ * one; PageRank, 20 iterations: S2 in the schedule's vertex_order, and S3),
+ * the layout GI_DIR_LEARNED runs on.
  * The frontiers of BFS and of synchronous CC do not depend on the schedule,
  * so step k of every run meets the same frontier (checked: a mismatch is
  * GI_ERR_DEVICE).  Writes per step k < min(cap, *count): feats[k][12],

@@ -48,6 +48,8 @@ def _load():
         lib.or_bfs.argtypes = [i32, vp, vp, i32, vp, vp]
         lib.or_cc.restype = i32
         lib.or_cc.argtypes = [i32, vp, vp, vp]
+        lib.or_cc_union_find.restype = i64
+        lib.or_cc_union_find.argtypes = [i32, i64, vp, vp, vp]
         lib.or_dijkstra.restype = ctypes.c_int
         lib.or_dijkstra.argtypes = [i32, vp, vp, vp, i32, vp]
         lib.or_bc.restype = i32
@@ -145,6 +147,20 @@ def cc(g: Graph):
     r = _load().or_cc(g.n, _ptr(g.out.off), _ptr(g.out.idx), _ptr(label))
     if r < 0:
         raise ValueError("or_cc failed")
+    return label, int(r)
+
+
+def cc_union_find(n, src, dst):
+    """Weak-component labels (least vertex id) of the raw records src[i] ->
+    dst[i] by union-find; returns (label, number of components)."""
+    src = np.ascontiguousarray(src, np.int32)
+    dst = np.ascontiguousarray(dst, np.int32)
+    if src.shape != dst.shape:
+        raise ValueError("src and dst differ in length")
+    label = np.empty(int(n), np.int32)
+    r = _load().or_cc_union_find(int(n), int(src.size), _ptr(src), _ptr(dst), _ptr(label))
+    if r < 0:
+        raise ValueError("or_cc_union_find failed")
     return label, int(r)
 
 

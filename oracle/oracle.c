@@ -240,6 +240,45 @@ int32_t or_cc(int32_t n, const int32_t* off, const int32_t* idx, int32_t* label)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Connected components by union-find over the raw edge records: the        */
+/* alternative algorithm the paper names for CC, with the same unique       */
+/* result as or_cc (weak components, label = least vertex id of the         */
+/* component).  Every record {u, v} joins the sets of u and v.  A set's     */
+/* root is kept at its least id (the larger root is linked under the        */
+/* smaller), and path halving only moves a parent pointer to a smaller id,  */
+/* so every parent id is at most the vertex's own: one pass in increasing   */
+/* id then sets each label from its parent's final label.  Needs no         */
+/* adjacency, so it also serves graphs too large for the CSR oracles.       */
+/* Returns the number of components, -1 on bad input.                       */
+/* ------------------------------------------------------------------------ */
+static int32_t uf_find(int32_t* p, int32_t x) {
+  while (p[x] != x) {
+    p[x] = p[p[x]];
+    x = p[x];
+  }
+  return x;
+}
+
+int64_t or_cc_union_find(int32_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                         int32_t* label) {
+  if (n <= 0 || m < 0) return -1;
+  for (int32_t v = 0; v < n; ++v) label[v] = v;
+  for (int64_t e = 0; e < m; ++e) {
+    const int32_t u = src[e], v = dst[e];
+    if (u < 0 || u >= n || v < 0 || v >= n) return -1;
+    const int32_t ru = uf_find(label, u), rv = uf_find(label, v);
+    if (ru < rv) label[rv] = ru;
+    else if (rv < ru) label[ru] = rv;
+  }
+  int64_t comps = 0;
+  for (int32_t v = 0; v < n; ++v) {
+    label[v] = label[label[v]];
+    comps += label[v] == v;
+  }
+  return comps;
+}
+
+/* ------------------------------------------------------------------------ */
 /* SSSP reference: Dijkstra with a binary heap and 64-bit tentative         */
 /* distances.  dist[v] = least total weight of an s -> v path, UINT32_MAX   */
 /* when unreachable.  Returns 0, or -5 when a finite distance does not fit  */

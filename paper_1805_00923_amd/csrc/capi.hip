@@ -1767,11 +1767,11 @@ static gi_status pr_run(gi_graph* g, int32_t iters, float damping, float* ranks,
   return GI_OK;
 }
 
-// Segments for the segmented schedule (built on first use when the
-// schedule itself has one segment).
+// The automatic segments (2 MiB of contributions each) for a segmented
+// choice when the schedule itself has one segment; rebuilt when the graph
+// holds segments of another count from an earlier schedule.
 static gi_status ensure_segments(gi_graph* g) {
-  if (!g->segs.empty()) return GI_OK;
-  return build_segments(g, auto_segments(g), GI_SEG_FIXED_VERTEX_COUNT);
+  return ensure_pr_segments(g, auto_segments(g), GI_SEG_FIXED_VERTEX_COUNT);
 }
 
 extern "C" gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, float* ranks,
@@ -1796,7 +1796,17 @@ extern "C" gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, floa
                            hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     segmented = io[kFeat + 2] - io[kFeat + 3] > kLearnedMargin;
-    if (segmented && (st = ensure_segments(g)) != GI_OK) return st;
+    // the choice is the direction; the layout is the schedule's: its
+    // segments for the segmented pull (else the automatic count), its
+    // vertex order for the unsegmented one
+    if (segmented) {
+      st = g->sched.num_segments > 1
+               ? ensure_pr_segments(g, g->sched.num_segments, g->sched.segment_strategy)
+               : ensure_segments(g);
+      if (st != GI_OK) return st;
+    } else if (g->sched.vertex_order == GI_ORDER_OUT_DEGREE) {
+      return pr_run_ordered(g, iters, damping, ranks, s);
+    }
   }
   if (g->sched.vertex_order == GI_ORDER_OUT_DEGREE && g->sched.direction != GI_DIR_LEARNED)
     return pr_run_ordered(g, iters, damping, ranks, s);
@@ -2004,12 +2014,16 @@ extern "C" gi_status gi_cc(gi_graph* g, int32_t* label, void* stream) {
   const bool direct = cc_direct(g);
   st = direct ? ensure_cc_direct(g) : ensure_sym(g, s);
   if (st != GI_OK) return st;
-  // segments: the schedule's, or for the learned choice the automatic
-  // count (2 MiB of labels each) that its S3 stands for
+  // segments: the schedule's; the learned choice's S3 pulls over them too,
+  // or over the automatic count (2 MiB of labels each) when the schedule
+  // has none
   const bool learned = g->sched.direction == GI_DIR_LEARNED;
   int seg_pull = 0;
   if (learned) {
-    if ((st = ensure_cc_segments(g, auto_segments(g), GI_SEG_FIXED_VERTEX_COUNT, s)) != GI_OK)
+    const bool own = g->sched.num_segments > 1;
+    if ((st = ensure_cc_segments(g, own ? std::min(g->sched.num_segments, kParts) : auto_segments(g),
+                                 own ? g->sched.segment_strategy : GI_SEG_FIXED_VERTEX_COUNT, s)) !=
+        GI_OK)
       return st;
     seg_pull = 2;
   } else if (g->sched.num_segments > 1) {
@@ -2823,24 +2837,33 @@ extern "C" gi_status gi_trace_exhaustive(gi_graph* g, int32_t algorithm, int32_t
   std::vector<float> t((size_t)kMaxLog * kOut, 0.0f);
   std::vector<uint8_t> ok((size_t)kMaxLog * kOut, 0);
   std::vector<float> x((size_t)kMaxLog * kFeat, 0.0f);
-  // PageRank: S2, S3; BFS: S0..S2; CC: S0..S3 (S3 = pull over the
-  // automatic source segments)
+  // PageRank: S2, S3; BFS: S0..S2; CC: S0..S3.  S3 pulls over the
+  // schedule's source segments (the automatic count when it has none), and
+  // PageRank's S2 follows the schedule's vertex order: the same layout the
+  // learned choice runs on
   const int nsched = algorithm == GI_ALG_PAGERANK ? 2 : algorithm == GI_ALG_CC ? 4 : 3;
   for (int q = 0; q < nsched && st == GI_OK; ++q) {
     const int sched = algorithm == GI_ALG_PAGERANK ? 2 + q : q;  // S index
     if (algorithm == GI_ALG_CC && sched == 3) {
       g->sched.direction = GI_DIR_DENSE_PULL;
       g->sched.dense_frontier = GI_FRONTIER_BITVECTOR;
-      g->sched.num_segments = auto_segments(g);
-      g->sched.segment_strategy = GI_SEG_FIXED_VERTEX_COUNT;
+      if (saved.num_segments <= 1) {
+        g->sched.num_segments = auto_segments(g);
+        g->sched.segment_strategy = GI_SEG_FIXED_VERTEX_COUNT;
+      }
       st = gi_cc(g, out, nullptr);
       g->sched.num_segments = saved.num_segments;
       g->sched.segment_strategy = saved.segment_strategy;
     } else if (algorithm == GI_ALG_PAGERANK) {
       g->sched.direction = GI_DIR_DENSE_PULL;
       const bool seg = sched == 3;
-      if (seg && (st = ensure_segments(g)) != GI_OK) break;
-      st = pr_run(g, 20, 0.85f, reinterpret_cast<float*>(out), nullptr, seg);
+      if (seg && (st = saved.num_segments > 1 ? ensure_pr_segments(g, saved.num_segments,
+                                                                   saved.segment_strategy)
+                                              : ensure_segments(g)) != GI_OK)
+        break;
+      st = !seg && saved.vertex_order == GI_ORDER_OUT_DEGREE
+               ? pr_run_ordered(g, 20, 0.85f, reinterpret_cast<float*>(out), nullptr)
+               : pr_run(g, 20, 0.85f, reinterpret_cast<float*>(out), nullptr, seg);
       if (st == GI_OK) st = finish_pending(g);  // the run returned after enqueue
     } else {
       g->sched.direction = sched;  // GI_DIR_SPARSE_PUSH, DENSE_PUSH, DENSE_PULL

@@ -335,6 +335,46 @@ def test_cc_closed_forms():
         assert np.all(lab[members] == members.min())
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_cc_union_find_oracle_exhaustive(n):
+    """The oracle's union-find CC (raw records, no adjacency) gives the
+    least-id labels and the component count of every graph on n <= 4."""
+    for edges in all_graphs(n):
+        src = np.array([u for u, _ in edges], np.int32)
+        dst = np.array([v for _, v in edges], np.int32)
+        lab, comps = oracle.cc_union_find(n, src, dst)
+        ref = union_find_labels(n, edges)
+        assert np.array_equal(lab, ref), edges
+        assert comps == len(set(ref.tolist()))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_cc_union_find_oracle_vs_label_propagation(seed):
+    """Shuffled records (with repeats, self-loops and ids in any order) give
+    the labels of the label-propagation oracle."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 400))
+    m = int(rng.integers(0, 3 * n))
+    src = rng.integers(0, n, m).astype(np.int32)
+    dst = rng.integers(0, n, m).astype(np.int32)
+    lab, comps = oracle.cc_union_find(n, src, dst)
+    ref, _ = oracle.cc(oracle.Graph(gg.EdgeList(n, src, dst)))
+    assert np.array_equal(lab, ref)
+    assert comps == len(np.unique(ref))
+
+
+def test_cc_union_find_oracle_closed_forms():
+    # a path whose records run from the largest id down: every link goes
+    # under a smaller root, the final pass resolves chains of any length
+    n = 1000
+    lab, comps = oracle.cc_union_find(n, np.arange(n - 1, 0, -1), np.arange(n - 2, -1, -1))
+    assert np.all(lab == 0) and comps == 1
+    lab, comps = oracle.cc_union_find(7, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert np.array_equal(lab, np.arange(7)) and comps == 7
+    with pytest.raises(ValueError):
+        oracle.cc_union_find(4, np.array([0, 4], np.int32), np.array([1, 2], np.int32))
+
+
 def test_cc_rmat_vs_union_find():
     el = gg.rmat(12, seed=9)
     g = oracle.Graph(el)
