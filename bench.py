@@ -134,6 +134,45 @@ def bfs_step_bytes(n, dirs, fs, ds, es):
     return out
 
 
+class PullScanReplay:
+    """E_scan of BFS DensePull steps by a host replay in CSC order: at step k
+    (frontier: the vertices of level k) every vertex not yet visited scans
+    its in-edges in CSC order up to and including the first whose source is
+    in the frontier, or all of them when none is.  From the final levels:
+    a vertex of level k + 1 stops at its first in-edge from level k; one of
+    a later level, or unreached, finds none (an in-neighbour of level k
+    would have put it at level k + 1) and scans its whole row."""
+
+    def __init__(self, in_off, in_idx):
+        import numpy as np
+        self.n = len(in_off) - 1
+        self.m = int(in_off[-1])
+        self.idx = np.ascontiguousarray(in_idx[:self.m], np.int32)
+        self.deg = np.diff(np.asarray(in_off, np.int64))
+        self.row = np.repeat(np.arange(self.n, dtype=np.int32), self.deg)
+        self.pos = (np.arange(self.m, dtype=np.int64) -
+                    np.repeat(np.asarray(in_off[:-1], np.int64), self.deg)).astype(np.int32)
+        self.starts = np.minimum(np.asarray(in_off[:-1], np.int64), max(self.m - 1, 0))
+
+    def step_edges(self, level, dirs):
+        """{k: E_scan} for the steps k with dirs[k] == 2 (DensePull)."""
+        import numpy as np
+        level = np.asarray(level, np.int32)
+        pulls = [k for k, d in enumerate(dirs) if int(d) == 2]
+        if not pulls or self.m == 0:
+            return {k: 0 for k in pulls}
+        lv_dst = level[self.row]
+        hit = (level[self.idx] == lv_dst - 1) & (lv_dst > 0)
+        first = np.minimum.reduceat(np.where(hit, self.pos, np.int32(2**31 - 1)), self.starts)
+        first = np.where(self.deg > 0, first, 0).astype(np.int64)
+        top = int(level.max()) + 2
+        lv = np.where(level < 0, top, level)          # unreached: after every level
+        stop = np.bincount(lv, weights=np.minimum(first + 1, self.deg), minlength=top + 1)
+        full = np.bincount(lv, weights=self.deg, minlength=top + 1)
+        later = np.cumsum(full[::-1])[::-1]           # later[L] = rows of level >= L
+        return {k: int(stop[k + 1] + later[k + 2]) for k in pulls}
+
+
 def cc_step_bytes(n, dirs, fs, ds, es):
     """Per-step bytes of the CC step kernel (symmetric adjacency, E = edges
     examined, both directions of every edge).
@@ -288,18 +327,35 @@ def run_bfs_cc(args, torch, dev):
     label = torch.empty(n, dtype=torch.int32, device=dev)
 
     # per-source reach and algorithmic bytes from the plain path's traces
-    # (levels, and so frontiers and directions, are the same on every path)
+    # (levels, and so frontiers and directions, are the same on every path);
+    # the pull steps' E_scan comes from a host replay in CSC order
     odeg = np.diff(g.out_off).astype(np.int64)
-    m_reach, bfs_bytes, ref_levels = [], [], []
+    m_reach, runs, ref_levels = [], [], []
     for s in srcs:
         g.bfs(int(s), level)
         lv = level.cpu().numpy()
         m_reach.append(int(odeg[lv >= 0].sum()))
         st = g.stats()
         dirs, fs, ds = st.trace()
-        bfs_bytes.append(sum(bfs_step_bytes(n, dirs, fs, ds, st.step_edges_examined())))
+        runs.append((lv, dirs, fs, ds, list(st.step_edges_examined())))
         if len(ref_levels) < 4:
             ref_levels.append(level.clone())
+    t0 = time.time()
+    ioff, iidx, _ = gi.build_adjacency(el.n, el.dst, el.src)
+    replay = PullScanReplay(ioff, iidx)
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(min(8, os.cpu_count() or 1)) as ex:
+        scans = list(ex.map(lambda r: replay.step_edges(r[0], r[1]), runs))
+    bfs_bytes, kernel_e, replay_e = [], 0, 0
+    for (lv, dirs, fs, ds, es), sc in zip(runs, scans):
+        for k, e in sc.items():
+            kernel_e += int(es[k])
+            replay_e += e
+            es[k] = e
+        bfs_bytes.append(sum(bfs_step_bytes(n, dirs, fs, ds, es)))
+    del replay, ioff, iidx, runs
+    log("pull E_scan replayed in CSC order (%.1fs): %d edges, kernel count %d" %
+        (time.time() - t0, replay_e, kernel_e))
     teps_edges = sum(m_reach) + m
 
     # plain path: one call per source (reported beside the batched path)
@@ -424,6 +480,7 @@ def run_bfs_cc(args, torch, dev):
         "cc_rounds": int(cc_all[0][1]), "cc_dense_rounds": int(cc_all[0][2]),
         "cc_hybrid_divisor": cc_div, "cc_schedule": cc_sched, "cc_schedule_sweep_ms": cc_sweep,
         "other_kernel": other.roofline(),
+        "pull_escan": {"replayed_csc_order": replay_e, "kernel_count": kernel_e},
     }
     if batched:
         info = batch.info()
@@ -1086,6 +1143,9 @@ def run_batched(args, torch, dev):
             x, y = t["out"].double(), r.double()
             bad += int(((x - y).abs() / y).max().item() > 1e-6)
     info = b.info()
+    bar = b.barrier_ms().astype(np.float64)
+    wgs = info["workgroups"].astype(np.float64)
+    is_bfs = np.array([t["algorithm"] == gi.ALG_BFS for t in tasks])
     value = edges / t_batch / 1e9
     slow = np.argsort(-info["task_ms"])[:5]
     detail = {"plain_ms": round(t_plain * 1e3, 3), "batched_ms": round(t_batch * 1e3, 3),
@@ -1099,11 +1159,25 @@ def run_batched(args, torch, dev):
                                                              if tasks[j]["graph"] == i))
                                        for i in range(len(els))},
               "mismatches_vs_plain": bad, "edges_per_pass": edges,
+              "pr_block_edges_per_graph": {els[i].name: int(c)
+                                           for i, c in enumerate(b.pr_block_edges()) if c},
               "slowest_tasks": [{"graph": els[tasks[j]["graph"]].name,
                                  "alg": "bfs" if tasks[j]["algorithm"] == gi.ALG_BFS else "pr",
                                  "ms": round(float(info["task_ms"][j]), 3),
                                  "levels": int(info["levels"][j]),
-                                 "workgroups": int(info["workgroups"][j])} for j in slow]}
+                                 "workgroups": int(info["workgroups"][j]),
+                                 "barrier_ms": round(float(bar[j]), 3),
+                                 "barrier_fraction": round(float(bar[j] / max(info["task_ms"][j], 1e-9)), 3)}
+                                for j in slow],
+              # synchronisation in place of the plain path's launches: the
+              # workgroup-time the tasks spent in their barriers, and the
+              # launch's host-side overhead beyond the kernel's own time
+              "barrier_fraction_of_workgroup_time": round(float(
+                  (bar * wgs).sum() / max(float((info["task_ms"] * wgs).sum()), 1e-9)), 4),
+              "barrier_fraction_by_algorithm": {
+                  a: round(float((bar * wgs)[sel].sum() / max(float((info["task_ms"] * wgs)[sel].sum()), 1e-9)), 4)
+                  for a, sel in (("bfs", is_bfs), ("pagerank", ~is_bfs))},
+              "launch_overhead_fraction": round(max(0.0, 1.0 - float(np.median(kms)) / (t_batch * 1e3)), 4)}
     config = {"workload": "batched256_bfs_pr20_rmat10-18_grid64-1024", "instances": 256,
               "graphs": [el.name for el in els]}
     return value, "GTEPS", t_batch * 1e3, "int32 / f32+f64", config, None, None, detail

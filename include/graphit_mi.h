@@ -581,7 +581,11 @@ gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, const gi_tas
                           int32_t ntasks, gi_batch** out);
 
 /* Autotuner, for each workgroup size of 256, 512 and 1024 threads (only the
- * pinned one after gi_batch_set_threads): times each (graph, algorithm)
+ * pinned one after gi_batch_set_threads): first the PageRank block size of
+ * each graph that has PageRank tasks (the batch's own destination blocks of
+ * 256, 512, 1024, 2048 or 4096 edges; the graph's schedule is untouched),
+ * timing the graph's first PageRank task alone with each and keeping the
+ * fastest; then times each (graph, algorithm)
  * class alone on 256, 128, 64, ... workgroups (median of reps launches),
  * stopping at the first size more than twice as slow as the fastest so far;
  * keeps, among the sizes within twice the fastest, the one with the least
@@ -599,6 +603,14 @@ gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, const gi_tas
  * tasks' outputs (with correct results).
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
 gi_status gi_batch_autotune(gi_batch* b, int32_t reps);
+
+/* PageRank destination-block size (edges per block) the batch uses for each
+ * graph (host array of the batch's graph count): the graph's own block size
+ * at creation, the autotuner's choice after gi_batch_autotune; 0 for graphs
+ * without PageRank tasks.  Source segments are not used inside the batch:
+ * a pool graph's contributions fit one XCD's L2.
+ * Errors: INVALID_ARG. */
+gi_status gi_batch_pr_block_edges(const gi_batch* b, int32_t* edges_per_block);
 
 /* Threads per workgroup of the batch kernel: 256 (the default at creation),
  * 512 or 1024; pins that size for gi_batch_autotune and re-plans (task
@@ -671,14 +683,20 @@ gi_status gi_batch_wait(gi_batch* b);
 gi_status gi_batch_info(const gi_batch* b, float* last_ms, int32_t* grid, int32_t* workgroups,
                         int32_t* levels, float* task_ms);
 
-/* Edges relaxed by each task in the last run (edges: host array of the
- * batch's task count): for an SSSP task, every edge of every near-set
- * member each time that member was relaxed, so edges / (edges out of the
- * reached vertices) is the re-relaxation factor of delta-stepping (Meyer
- * and Sanders): its work beyond a label-setting order, which relaxes each
- * reached edge once; 0 for BFS and PageRank tasks.
+/* Per-task counters of the last run (host arrays of the batch's task count;
+ * either may be NULL, not both):
+ *   edges: edges relaxed.  For an SSSP task, every edge of every near-set
+ *     member each time that member was relaxed, so edges / (edges out of
+ *     the reached vertices) is the re-relaxation factor of delta-stepping
+ *     (Meyer and Sanders): its work beyond a label-setting order, which
+ *     relaxes each reached edge once.  0 for BFS and PageRank tasks.
+ *   barrier_ms: time a workgroup of the task spent in task barriers, from
+ *     its arrival to its release (device wall clock, mean over the task's
+ *     workgroups; 0 for one-workgroup tasks, which need none).  Divided by
+ *     the task's duration (gi_batch_info) it is the task's barrier-overhead
+ *     fraction: the synchronisation that replaces the plain path's launches.
  * Errors: INVALID_ARG (also while a launch is in flight), DEVICE. */
-gi_status gi_batch_edges(const gi_batch* b, int64_t* edges);
+gi_status gi_batch_task_counters(const gi_batch* b, int64_t* edges, float* barrier_ms);
 gi_status gi_batch_destroy(gi_batch* b);
 
 /* ---- frontier primitives (device, stream ordered) -------------------- */

@@ -162,7 +162,8 @@ _SIGS = {
     "gi_batch_launch": (ctypes.c_int, [_vp, _i32, _vp]),
     "gi_batch_wait": (ctypes.c_int, [_vp]),
     "gi_batch_info": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
-    "gi_batch_edges": (ctypes.c_int, [_vp, _vp]),
+    "gi_batch_task_counters": (ctypes.c_int, [_vp, _vp, _vp]),
+    "gi_batch_pr_block_edges": (ctypes.c_int, [_vp, _vp]),
     "gi_batch_destroy": (ctypes.c_int, [_vp]),
     "gi_batch_set_threads": (ctypes.c_int, [_vp, _i32]),
     "gi_batch_get_threads": (ctypes.c_int, [_vp, _vp]),
@@ -740,5 +741,19 @@ class Batch:
     def edges(self):
         """Edges each task relaxed in the last run (SSSP tasks; 0 for others)."""
         e = np.zeros(self.ntasks, np.int64)
-        _check(lib.gi_batch_edges(self._h, e.ctypes.data))
+        _check(lib.gi_batch_task_counters(self._h, e.ctypes.data, None))
         return e
+
+    def pr_block_edges(self):
+        """Per graph: the PageRank block size (edges) the batch uses; 0 for
+        graphs without PageRank tasks."""
+        e = np.zeros(len(self.graphs), np.int32)
+        _check(lib.gi_batch_pr_block_edges(self._h, e.ctypes.data))
+        return e
+
+    def barrier_ms(self):
+        """Per task: mean time a workgroup spent in task barriers in the last
+        run (ms; 0 for one-workgroup tasks)."""
+        t = np.zeros(self.ntasks, np.float32)
+        _check(lib.gi_batch_task_counters(self._h, None, t.ctypes.data))
+        return t

@@ -63,6 +63,13 @@ __device__ __forceinline__ bool task_on_one_xcd(const TaskCtl* c) {
   return __popc(m) == 1;
 }
 
+// Wall-clock ticks the calling workgroup has spent in task barriers during
+// its current task (thread 0 keeps it; k_batch resets and reports it).
+__device__ __forceinline__ long long& barrier_ticks() {
+  __shared__ long long s_ticks;
+  return s_ticks;
+}
+
 // Barrier of the k workgroups of one task.  One 64-bit word holds
 // (generation << 32) | arrivals, so an arrival learns its generation from
 // the same atomic.  Every wave first waits for its own memory operations to
@@ -89,6 +96,7 @@ __device__ bool task_barrier(TaskCtl* c, int k, int* gerr, long long limit, bool
   if (threadIdx.x == 0) {
     int ok = __hip_atomic_load(gerr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     if (ok && k > 1) {
+      const long long t0 = wall_ticks();
       if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       const unsigned long long old = atomicAdd(&c->bar, 1ull);
       const unsigned long long gen = old >> 32;
@@ -96,7 +104,6 @@ __device__ bool task_barrier(TaskCtl* c, int k, int* gerr, long long limit, bool
         __hip_atomic_store(&c->bar, (gen + 1ull) << 32, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
       } else {
-        const long long t0 = wall_ticks();
         while ((__hip_atomic_load(&c->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32) ==
                gen) {
           if (__hip_atomic_load(gerr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
@@ -113,6 +120,7 @@ __device__ bool task_barrier(TaskCtl* c, int k, int* gerr, long long limit, bool
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       __builtin_amdgcn_s_waitcnt(0);
+      barrier_ticks() += wall_ticks() - t0;
     }
     s_ok = ok;
   }
@@ -774,11 +782,14 @@ __global__ __launch_bounds__(BT, batch_min_waves<BT>()) void k_batch(BatchArgs a
     const int2 it = a.items[i];
     const BatchTask& t = a.tasks[it.x];
     const BatchGraph& G = a.graphs[t.graph];
+    if (threadIdx.x == 0) barrier_ticks() = 0;
     if (it.y == 0 && threadIdx.x == 0) t.ctl->t_begin = wall_ticks();
     if (t.alg == ALG_BFS) bfs_task<BT>(G, t, it.y, a, reinterpret_cast<int*>(smem));
     else if (t.alg == ALG_SSSP) sssp_task<BT>(G, t, it.y, a, reinterpret_cast<int*>(smem));
     else pr_task<BT>(G, t, it.y, a, lds_val, lds_off);
     if (it.y == 0 && threadIdx.x == 0) t.ctl->t_end = wall_ticks();
+    if (threadIdx.x == 0 && barrier_ticks() > 0)
+      atomicAdd(&t.ctl->bar_ticks, (unsigned long long)barrier_ticks());
   }
 }
 

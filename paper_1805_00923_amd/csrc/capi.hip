@@ -2941,7 +2941,15 @@ struct gi_batch {
   int* d_wg_off = nullptr;
   int* d_err = nullptr;
   std::vector<BatchTask> h_tasks;
-  std::vector<int2> shape;   // per graph at creation: PageRank block size, long rows
+  // per graph: the batch's own PageRank destination blocks (block size
+  // chosen per graph by the autotuner; the graph's own schedule untouched)
+  struct PrLayout {
+    int cap_e = 0, cap_v = 0, ntab = 0, nlong = 0;
+    int4* table = nullptr;
+    int32_t* chunks = nullptr;
+  };
+  std::vector<PrLayout> lay;
+  std::vector<int> lr_max;   // per graph: long-row slots at the smallest block size
   std::vector<void*> work;
   hipStream_t gstream = nullptr;
   hipGraph_t hg = nullptr;
@@ -2959,10 +2967,18 @@ static void batch_drop_graph(gi_batch* b) {
   b->hg = nullptr;
 }
 
+static void batch_free_layout(gi_batch::PrLayout* l) {
+  if (l->table) dmem_free(l->table);
+  if (l->chunks) dmem_free(l->chunks);
+  l->table = nullptr;
+  l->chunks = nullptr;
+}
+
 extern "C" gi_status gi_batch_destroy(gi_batch* b) {
   if (!b) return GI_OK;
   (void)hipDeviceSynchronize();
   batch_drop_graph(b);
+  for (gi_batch::PrLayout& l : b->lay) batch_free_layout(&l);
   for (void* q : b->work) dmem_free(q);
   for (void* q : {(void*)b->d_graphs, (void*)b->d_tasks, (void*)b->d_ctl, (void*)b->d_items,
                   (void*)b->d_wg_off, (void*)b->d_err, (void*)b->d_trace})
@@ -2987,6 +3003,42 @@ static gi_status batch_alloc(gi_batch* b, T** p, size_t count) {
   return GI_OK;
 }
 
+// PageRank block sizes (edges per destination block) the autotuner tries for
+// a graph's PageRank tasks; a batch's long-row slots are sized for the
+// smallest.
+static const int kBatchCaps[] = {256, 512, 1024, 2048, 4096};
+constexpr int kBatchCapMin = 256, kBatchCapMax = 4096;
+
+// The batch's destination blocks of graph i at cap_e edges per block.
+static gi_status batch_set_layout(gi_batch* b, size_t i, int cap_e) {
+  gi_batch::PrLayout& l = b->lay[i];
+  if (l.table && l.cap_e == cap_e) return GI_OK;
+  const gi_graph* g = b->graphs[i];
+  std::vector<int32_t> chunks;
+  const int cap_v = std::min(cap_e, 1024);
+  const std::vector<int4> tab = make_pr_table(g->h_in_off.data(), g->n, cap_e, cap_v, &chunks);
+  if ((int)chunks.size() > b->lr_max[i] || cap_e > b->cap_e)
+    return fail(GI_ERR_INVALID_ARG, "PageRank block size %d outside the batch's range", cap_e);
+  HIP_TRY(hipDeviceSynchronize());  // no launch reads the old blocks any more
+  batch_free_layout(&l);
+  if (dmem_get((void**)&l.table, sizeof(int4) * std::max<size_t>(1, tab.size())) != hipSuccess ||
+      dmem_get((void**)&l.chunks, sizeof(int32_t) * std::max<size_t>(1, chunks.size())) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    batch_free_layout(&l);
+    return fail(GI_ERR_OUT_OF_MEMORY, "batch PageRank blocks");
+  }
+  HIP_TRY(hipMemcpy(l.table, tab.data(), sizeof(int4) * tab.size(), hipMemcpyHostToDevice));
+  if (!chunks.empty())
+    HIP_TRY(hipMemcpy(l.chunks, chunks.data(), sizeof(int32_t) * chunks.size(),
+                      hipMemcpyHostToDevice));
+  l.cap_e = cap_e;
+  l.cap_v = cap_v;
+  l.ntab = (int)tab.size();
+  l.nlong = (int)chunks.size();
+  return GI_OK;
+}
+
 // Workgroup size: the resident grid follows from the kernel's occupancy at
 // that size (at most 8 workgroups per CU).
 static gi_status batch_set_bt(gi_batch* b, int bt) {
@@ -2998,7 +3050,7 @@ static gi_status batch_set_bt(gi_batch* b, int bt) {
   return GI_OK;
 }
 
-static BatchGraph batch_graph(const gi_graph* g) {
+static BatchGraph batch_graph(const gi_graph* g, const gi_batch::PrLayout& l) {
   BatchGraph d;
   d.n = g->n;
   d.m = g->m;
@@ -3011,11 +3063,11 @@ static BatchGraph batch_graph(const gi_graph* g) {
   d.in_probe = g->in_probe;
   d.hubs = g->hubs;
   d.nhubs = g->nhubs;
-  d.pr_table = g->pr_table;
-  d.pr_ntab = g->pr_ntab;
-  d.pr_cap_e = g->pr_cap_e;
-  d.lr_chunks = g->lr_chunks;
-  d.n_long = g->pr_nlong;
+  d.pr_table = l.table;
+  d.pr_ntab = l.ntab;
+  d.pr_cap_e = l.cap_e;
+  d.lr_chunks = l.chunks;
+  d.n_long = l.nlong;
   return d;
 }
 
@@ -3145,13 +3197,29 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
     gi_batch_destroy(b);
     return st;
   };
-  int cap_e = 256;
-  for (gi_graph* g : b->graphs) {
+  // PageRank blocks: the batch's own, at first the graph's block size, any
+  // of kBatchCaps after tuning; LDS and long-row slots sized for all of them
+  int cap_e = kBatchCapMax;
+  std::vector<bool> has_pr((size_t)ngraphs, false);
+  for (int32_t i = 0; i < ntasks; ++i)
+    if (tasks[i].algorithm == GI_ALG_PAGERANK) has_pr[(size_t)tasks[i].graph] = true;
+  b->lay.resize((size_t)ngraphs);
+  b->lr_max.assign((size_t)ngraphs, 0);
+  for (size_t i = 0; i < (size_t)ngraphs; ++i) {
+    const gi_graph* g = b->graphs[i];
     cap_e = std::max(cap_e, g->pr_cap_e);
-    b->shape.push_back(make_int2(g->pr_cap_e, g->pr_nlong));
+    const int lo = std::min(kBatchCapMin, g->pr_cap_e);
+    int nl = 0;
+    for (int32_t v = 0; v < g->n; ++v) nl += g->h_in_off[(size_t)v + 1] - g->h_in_off[(size_t)v] > lo;
+    b->lr_max[i] = nl;
   }
   b->cap_e = cap_e;
   b->lds = batch_lds_bytes(cap_e, std::min(cap_e, 1024));
+  for (size_t i = 0; i < (size_t)ngraphs; ++i) {
+    if (!has_pr[i]) continue;
+    gi_status sl = batch_set_layout(b, i, b->graphs[i]->pr_cap_e);
+    if (sl != GI_OK) return bail(sl);
+  }
   int dev = 0, cus = 0, rate = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -3193,8 +3261,9 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
     } else {
       if ((st = batch_alloc(b, &d.c0, 2 * (size_t)g->n)) != GI_OK) return bail(st);
       d.c1 = d.c0 + g->n;
-      if ((st = batch_alloc(b, &d.lr_acc, (size_t)std::max(1, g->pr_nlong))) != GI_OK) return bail(st);
-      if ((st = batch_alloc(b, &d.lr_cnt, (size_t)std::max(1, g->pr_nlong))) != GI_OK) return bail(st);
+      const size_t nl = (size_t)std::max(1, b->lr_max[(size_t)t.graph]);
+      if ((st = batch_alloc(b, &d.lr_acc, nl)) != GI_OK) return bail(st);
+      if ((st = batch_alloc(b, &d.lr_cnt, nl)) != GI_OK) return bail(st);
     }
     // default size: one workgroup per 64K edges of work, power of two <= 64
     const double work = (double)std::max<int64_t>(g->m, g->n) * (d.alg == ALG_PR ? std::max(1, t.iters) : 1);
@@ -3246,12 +3315,7 @@ static BatchArgs batch_args(const gi_batch* b, const int2* items, const int* wg_
 
 static gi_status batch_refresh_graphs(gi_batch* b) {
   std::vector<BatchGraph> hg;
-  for (size_t i = 0; i < b->graphs.size(); ++i) {
-    const gi_graph* g = b->graphs[i];
-    if (g->pr_cap_e != b->shape[i].x || g->pr_nlong != b->shape[i].y)
-      return fail(GI_ERR_INVALID_ARG, "graph %zu changed its PageRank blocks after batch creation", i);
-    hg.push_back(batch_graph(g));
-  }
+  for (size_t i = 0; i < b->graphs.size(); ++i) hg.push_back(batch_graph(b->graphs[i], b->lay[i]));
   HIP_TRY(hipMemcpy(b->d_graphs, hg.data(), sizeof(BatchGraph) * hg.size(), hipMemcpyHostToDevice));
   return GI_OK;
 }
@@ -3368,6 +3432,35 @@ static gi_status batch_time_task(gi_batch* b, int t, int k, int reps, float* ms)
   std::sort(times.begin(), times.end());
   *ms = times[times.size() / 2];
   return GI_OK;
+}
+
+// PageRank block size per graph at the current workgroup size: the graph's
+// first PageRank task is timed alone, on its current workgroups, with each
+// of kBatchCaps; the fastest stays.  Returns the chosen sizes.
+static gi_status batch_tune_layouts(gi_batch* b, int32_t reps, std::vector<int>* caps) {
+  gi_status st;
+  caps->assign(b->graphs.size(), 0);
+  for (size_t i = 0; i < b->graphs.size(); ++i) {
+    int q = -1;
+    for (size_t t = 0; t < b->tasks.size() && q < 0; ++t)
+      if (b->tasks[t].algorithm == GI_ALG_PAGERANK && b->tasks[t].graph == (int32_t)i) q = (int)t;
+    if (q < 0) continue;
+    float best = 0.0f;
+    int best_cap = 0;
+    for (int cap : kBatchCaps) {
+      if ((st = batch_set_layout(b, i, cap)) != GI_OK) return st;
+      if ((st = batch_refresh_graphs(b)) != GI_OK) return st;
+      float ms = 0.0f;
+      if ((st = batch_time_task(b, q, std::max(1, b->k[(size_t)q]), reps, &ms)) != GI_OK) return st;
+      if (best_cap == 0 || ms < best) {
+        best = ms;
+        best_cap = cap;
+      }
+    }
+    if ((st = batch_set_layout(b, i, best_cap)) != GI_OK) return st;
+    (*caps)[i] = best_cap;
+  }
+  return batch_refresh_graphs(b);
 }
 
 // Workgroups per task at the current workgroup size (see gi_batch_autotune).
@@ -3552,6 +3645,7 @@ extern "C" gi_status gi_batch_autotune(gi_batch* b, int32_t reps) {
   float best_ms = 0.0f;
   std::vector<int> best_k;
   std::vector<double> best_est;
+  std::vector<int> best_caps, caps;
   bool best_xcd = true;
   for (int bt : {256, 512, 1024}) {
     if (b->bt_pinned && bt != b->bt) continue;
@@ -3559,6 +3653,7 @@ extern "C" gi_status gi_batch_autotune(gi_batch* b, int32_t reps) {
     b->est = e0;
     if ((st = batch_set_bt(b, bt)) != GI_OK) return st;
     b->xcd_local = true;
+    if ((st = batch_tune_layouts(b, reps, &caps)) != GI_OK) return st;
     if ((st = batch_tune_sizes(b, reps)) != GI_OK) return st;
     const std::vector<int> kt = b->k;
     const std::vector<double> et = b->est;
@@ -3590,16 +3685,27 @@ extern "C" gi_status gi_batch_autotune(gi_batch* b, int32_t reps) {
           best_xcd = xl;
           best_k = kp;
           best_est = ec;
+          best_caps = caps;
         }
       }
     }
   }
   if ((st = batch_set_bt(b, best_bt)) != GI_OK) return st;
+  for (size_t i = 0; i < best_caps.size(); ++i)
+    if (best_caps[i] > 0 && (st = batch_set_layout(b, i, best_caps[i])) != GI_OK) return st;
+  if ((st = batch_refresh_graphs(b)) != GI_OK) return st;
   b->xcd_local = best_xcd;
   b->k = best_k;
   b->est = best_est;
   if ((st = batch_plan(b)) != GI_OK) return st;
   return batch_refine_critical(b, reps);
+}
+
+extern "C" gi_status gi_batch_pr_block_edges(const gi_batch* b, int32_t* edges_per_block) {
+  if (!b || !edges_per_block) return fail(GI_ERR_INVALID_ARG, "NULL argument");
+  for (size_t i = 0; i < b->lay.size(); ++i)
+    edges_per_block[i] = b->lay[i].table ? b->lay[i].cap_e : 0;
+  return GI_OK;
 }
 
 extern "C" gi_status gi_batch_set_threads(gi_batch* b, int32_t threads) {
@@ -3693,13 +3799,18 @@ extern "C" gi_status gi_batch_get_threads(const gi_batch* b, int32_t* threads) {
   return GI_OK;
 }
 
-extern "C" gi_status gi_batch_edges(const gi_batch* b, int64_t* edges) {
-  if (!b || !edges) return fail(GI_ERR_INVALID_ARG, "bad batch edge-count arguments");
+extern "C" gi_status gi_batch_task_counters(const gi_batch* b, int64_t* edges, float* barrier_ms) {
+  if (!b || (!edges && !barrier_ms)) return fail(GI_ERR_INVALID_ARG, "bad batch counter arguments");
   if (b->launched) return fail(GI_ERR_INVALID_ARG, "batch launch in flight (gi_batch_wait first)");
   const size_t nt = b->tasks.size();
   std::vector<TaskCtl> c(nt);
   HIP_TRY(hipMemcpy(c.data(), b->d_ctl, sizeof(TaskCtl) * nt, hipMemcpyDeviceToHost));
-  for (size_t i = 0; i < nt; ++i) edges[i] = (int64_t)c[i].relaxed;
+  for (size_t i = 0; i < nt; ++i) {
+    if (edges) edges[i] = (int64_t)c[i].relaxed;
+    if (barrier_ms)
+      barrier_ms[i] = (float)((double)c[i].bar_ticks / (double)std::max(1, b->k[i]) /
+                              (double)b->clock_khz);
+  }
   return GI_OK;
 }
 

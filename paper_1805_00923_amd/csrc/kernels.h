@@ -244,6 +244,7 @@ struct TaskCtl {
   unsigned long long farc[3];  // SSSP: far-set sizes, rotating like qn
   unsigned long long ft[2];  // SSSP: lengths of the two far lists
   unsigned long long relaxed;  // SSSP: edges relaxed, summed over the workgroups
+  unsigned long long bar_ticks;  // wall-clock ticks the workgroups spent in task barriers
   int qbad[3];               // SSSP: the near set's list is incomplete, rotating like qn
   int fbad;                  // SSSP: the far list is incomplete
   unsigned xcds;             // XCDs the task's workgroups run on (bit per XCC id)

@@ -123,3 +123,35 @@ def test_pagerank_kernel_names_follow_the_schedule():
     names = {f for f, _ in gi.Schedule._fields_}
     for c in bench.PR_CANDIDATES:
         assert set(c) <= names, c
+
+
+def _brute_pull_scan(in_off, in_idx, level, k):
+    e = 0
+    for v in range(len(in_off) - 1):
+        if 0 <= level[v] <= k:
+            continue                      # visited before step k
+        for j in range(in_off[v], in_off[v + 1]):
+            e += 1
+            if level[in_idx[j]] == k:     # first in-edge from the frontier
+                break
+    return e
+
+
+def test_pull_scan_replay_matches_brute_force():
+    """The host replay of E_scan (in-edges scanned in CSC order up to the
+    first frontier member) equals a literal scan, for every step taken as a
+    pull, on an R-MAT graph and a grid from several sources."""
+    import numpy as np
+    import graphgen as gg
+    import oracle
+    for el in (gg.rmat(9, seed=21), gg.grid(9, 13, 0.05, seed=3, weighted=False)):
+        og = oracle.Graph(el)
+        rep = bench.PullScanReplay(og.inc.off, og.inc.idx)
+        for s in gg.pick_sources(el, 3, 5):
+            level = oracle.bfs(og, int(s))[0]
+            steps = int(level.max()) + 1
+            got = rep.step_edges(level, [2] * steps)
+            for k in range(steps):
+                assert got[k] == _brute_pull_scan(og.inc.off, og.inc.idx, level, k), (el.name, s, k)
+            # only the steps marked as pulls are replayed
+            assert set(rep.step_edges(level, [0, 2] + [0] * (steps - 2))) == {1}

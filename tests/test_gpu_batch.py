@@ -324,6 +324,11 @@ def test_batch_sssp_matches_dijkstra(threads):
             torch.cuda.synchronize()
             info = b.info()
             edges = b.edges()
+            bms = b.barrier_ms()
+            # barrier time: none for one-workgroup tasks, within the launch
+            assert np.all(bms >= 0)
+            assert np.all(bms[info["workgroups"] == 1] == 0)
+            assert np.all(bms <= info["ms"] * 1.01 + 0.01)
             for i, t in enumerate(tasks):
                 el, g, og = P[t["graph"]]
                 got = t["out"].cpu().numpy()
