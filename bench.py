@@ -85,6 +85,12 @@ def parse():
                     help="barrier of batched tasks: one-XCD tasks only invalidate L1 (xcd, "
                          "the default) or every barrier writes back and invalidates L2 (agent)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-threads", type=int, default=0, choices=[0, 256, 512, 1024],
+                    help="default workload: pin the BFS batch's workgroup size (0: autotuned)")
+    ap.add_argument("--batch-workgroups", type=int, default=0,
+                    help="default workload: pin each BFS task's workgroups (0: autotuned)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="default workload: skip the batched and road-like SSSP legs")
     ap.add_argument("--schedule", default="", help="k=v,... overrides of the schedule")
     ap.add_argument("--json-out", default="")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
@@ -211,25 +217,27 @@ def sched_key(sched):
     return ",".join("%s=%d" % (k, int(sched.get(k, 0))) for k in SCHED_KEY_FIELDS)
 
 
-def profile_traffic(kernel, workload=None, schedule=None):
+def profile_traffic(kernel, workload=None, schedule=None, plan=None):
     """HBM bytes per launch of `kernel` from the hardware-counter figures
     committed under profiles/, or None when there are none for this kernel
-    (and workload and schedule, where the figures name them) or the
-    kernel's sources changed since the counters were taken (sha256
+    (and workload, schedule and batch plan, where the figures name them) or
+    the kernel's sources changed since the counters were taken (sha256
     mismatch)."""
     import glob
     import hashlib
     import re
+    blocks = []
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
-        m = re.search(r"<!-- figures.*?-->", open(path).read(), re.S)
-        if not m:
-            continue
-        kv = dict(re.findall(r"^(\w+): (.+)$", m.group(0), re.M))
+        blocks += re.findall(r"<!-- figures.*?-->", open(path).read(), re.S)
+    for b in blocks:
+        kv = dict(re.findall(r"^(\w+): (.+)$", b, re.M))
         if kv.get("kernel") != kernel:
             continue
         if "workload" in kv and kv["workload"] != workload:
             continue
         if "schedule" in kv and (schedule is None or kv["schedule"] != sched_key(schedule)):
+            continue
+        if "plan" in kv and kv["plan"] != plan:
             continue
         h = hashlib.sha256()
         for f in kv.get("sources", "").split():
@@ -316,6 +324,12 @@ def run_bfs_cc(args, torch, dev):
 
     import graphgen as gg
     import paper_1805_00923_amd as gi
+    # the batched and road-like SSSP configurations, each a launch of its own,
+    # measured first so that the last batch launches are this workload's
+    legs = {}
+    if not args.no_legs:
+        legs["batched"] = batched_pool_leg(torch, dev)
+        legs["sssp_road"] = sssp_road_leg(torch, dev)
     el, g = make_rmat_graph(22, 2)
     kw = dict(direction=gi.DENSE_PULL_SPARSE_PUSH, dense_frontier=gi.BITVECTOR, hybrid_divisor=20)
     kw.update(sched_overrides(args.schedule))
@@ -374,9 +388,12 @@ def run_bfs_cc(args, torch, dev):
     if batched:
         outs = [(torch.empty(n, dtype=torch.int32, device=dev),
                  torch.empty(n, dtype=torch.int32, device=dev)) for _ in srcs]
-        batch = gi.Batch([g], [dict(graph=0, algorithm=gi.ALG_BFS, src=int(s), out=o, parent=p)
+        batch = gi.Batch([g], [dict(graph=0, algorithm=gi.ALG_BFS, src=int(s), out=o, parent=p,
+                                    workgroups=args.batch_workgroups)
                                for s, (o, p) in zip(srcs, outs)])
         batch.set_barrier_scope(barrier_scope(args))
+        if args.batch_threads:
+            batch.set_threads(args.batch_threads)
         t0 = time.perf_counter()
         batch.autotune(reps=3)
         t_tune = time.perf_counter() - t0
@@ -497,9 +514,14 @@ def run_bfs_cc(args, torch, dev):
               "bfs_sources": int(len(srcs)), "bfs_path": args.bfs_path,
               "cc_overlaps_bfs_batch": overlap,
               "schedule": bfs_sched, "cc_hybrid_divisor": cc_div}
+    if batched:
+        # the batch plan the traffic figures are keyed by
+        config["batch_plan"] = "threads=%d,workgroups=%d" % (
+            batch.threads(), int(np.median(batch.info()["workgroups"])))
     # PageRank legs (the PageRank configuration on R-MAT 16, and R-MAT 22 on
     # this graph), each tuned and timed on its own with its own roofline
     extra["pagerank"] = pagerank_legs(torch, dev, g)
+    extra.update(legs)
     extra["hbm_copy_gbs"] = copy_peak_gbs(torch, dev)
     cpu = None
     if not args.no_cpu_baseline:
@@ -526,6 +548,118 @@ def pagerank_legs(torch, dev, g22, steps=5):
         log("pagerank %s: %s, %.3f ms per 20 iterations" % (name, kw, kmed))
     g16.close()
     return legs
+
+
+def batched_pool_leg(torch, dev, steps=3, warmup=1):
+    """The batched workload's launch alone (256 BFS / PageRank instances over
+    the 14-graph pool, autotuned, replayed from a HIP graph): time, aggregate
+    GTEPS over the launch's own outputs, overhead fractions.  The comparison
+    with 256 plain calls is the batched workload's own (`--workload
+    batched`)."""
+    import numpy as np
+
+    import graphgen as gg
+    import paper_1805_00923_amd as gi
+    t_all = time.time()
+    els = [gg.rmat(s, 16, seed=100 + s) for s in range(10, 19)]
+    els += [gg.grid(d, d, 0.0, weighted=False) for d in (64, 128, 256, 512, 1024)]
+    graphs = [gi.Graph.from_edges(el.n, el.src, el.dst) for el in els]
+    tasks = []
+    for i in range(256):
+        gidx = i % len(graphs)
+        g, el = graphs[gidx], els[gidx]
+        if i % 2 == 0:
+            tasks.append(dict(graph=gidx, algorithm=gi.ALG_BFS,
+                              src=int(gg.pick_sources(el, 1, 200 + i)[0]),
+                              out=torch.empty(g.n, dtype=torch.int32, device=dev)))
+        else:
+            tasks.append(dict(graph=gidx, algorithm=gi.ALG_PAGERANK, iters=20, damping=0.85,
+                              out=torch.empty(g.n, dtype=torch.float32, device=dev)))
+    b = gi.Batch(graphs, tasks)
+    b.autotune(reps=3)
+    for _ in range(warmup):
+        b.run(use_graph=True)
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run(use_graph=True)
+        kms.append(b.info()["ms"])
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    edges = 0
+    for t in tasks:
+        g = graphs[t["graph"]]
+        if t["algorithm"] == gi.ALG_BFS:
+            edges += int(np.diff(g.out_off)[t["out"].cpu().numpy() >= 0].sum())
+        else:
+            edges += 20 * g.m
+    info = b.info()
+    bar = b.barrier_ms().astype(np.float64)
+    wgs = info["workgroups"].astype(np.float64)
+    leg = {"workload": "batched256_bfs_pr20_rmat10-18_grid64-1024", "ms_per_launch": round(t_batch * 1e3, 3),
+           "kernel_ms_median": round(float(np.median(kms)), 3),
+           "gteps": round(edges / t_batch / 1e9, 3), "threads": b.threads(), "grid": info["grid"],
+           "pr_block_edges_per_graph": {els[i].name: int(c) for i, c in enumerate(b.pr_block_edges()) if c},
+           "barrier_fraction_of_workgroup_time": round(float(
+               (bar * wgs).sum() / max(float((info["task_ms"] * wgs).sum()), 1e-9)), 4),
+           "launch_overhead_fraction": round(max(0.0, 1.0 - float(np.median(kms)) / (t_batch * 1e3)), 4),
+           "wall_s": round(time.time() - t_all, 1)}
+    b.close()
+    for g in graphs:
+        g.close()
+    log("batched leg: %.3f ms per launch, %.1f GTEPS" % (leg["ms_per_launch"], leg["gteps"]))
+    return leg
+
+
+def sssp_road_leg(torch, dev, delta=4096, steps=3, warmup=1):
+    """Delta-stepping from the 4 benchmark sources on the 4096 x 4096 grid
+    without shortcuts (the road-like regime) as 4 SSSP tasks of one batched
+    launch at bucket width 4096 (the width the SSSP workload's sweep picks),
+    autotuned: time, GTEPS, label-setting roofline, re-relaxation.  The
+    distances are checked against Dijkstra in the tests and against the
+    engine in the SSSP workload."""
+    import numpy as np
+
+    import graphgen as gg
+    import paper_1805_00923_amd as gi
+    t_all = time.time()
+    el = gg.grid(4096, 4096, 0.0, seed=4)
+    g = gi.Graph.from_edges(el.n, el.src, el.dst, el.w)
+    srcs = gg.pick_sources(el, 4, 5)
+    del el
+    outs = [torch.empty(g.n, dtype=torch.int32, device=dev) for _ in srcs]
+    b = gi.Batch([g], [dict(graph=0, algorithm=gi.ALG_SSSP, src=int(s), sssp_delta=delta, out=o)
+                       for s, o in zip(srcs, outs)])
+    b.autotune(reps=1)
+    for _ in range(warmup):
+        b.run()
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run()
+        kms.append(b.info()["ms"])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    odeg = np.diff(g.out_off).astype(np.int64)
+    m_reach, n_reach = [], []
+    for o in outs:
+        reached = o.cpu().numpy().view(np.uint32) != 0xFFFFFFFF
+        m_reach.append(int(odeg[reached].sum()))
+        n_reach.append(int(reached.sum()))
+    tally = KernelTally("k_batch (4 SSSP tasks)")
+    tally.add(kms, [sum(sssp_label_setting_bytes(mr, nr) for mr, nr in zip(m_reach, n_reach))] * len(kms))
+    info = b.info()
+    leg = {"workload": "sssp_grid4096_noshortcut", "delta": delta, "ms_per_launch": round(dt * 1e3, 3),
+           "gteps": round(sum(m_reach) / dt / 1e9, 3), "roofline": tally.roofline(),
+           "rerelaxation": round(float(b.edges().sum()) / sum(m_reach), 4),
+           "phases": [int(x) for x in info["levels"]], "threads": b.threads(),
+           "workgroups": [int(x) for x in info["workgroups"]], "wall_s": round(time.time() - t_all, 1)}
+    b.close()
+    g.close()
+    log("sssp road leg: %.3f ms per launch, %.2f GTEPS" % (leg["ms_per_launch"], leg["gteps"]))
+    return leg
 
 
 def cpu_baseline_bfs_cc(el, srcs, m_reach, budget_s=12.0):
@@ -1436,7 +1570,7 @@ def main():
         cpu = dict(cpu, sample=cpu["sample"] + "; host: " + host_info())
     if roof and roof.get("traffic") is None:
         roof["traffic"] = profile_traffic(roof["kernel"], config.get("workload"),
-                                          config.get("schedule"))
+                                          config.get("schedule"), config.get("batch_plan"))
     line = {"metric": METRIC, "value": round(value, 4), "unit": unit, "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,

@@ -70,6 +70,14 @@ def test_profile_traffic_follows_the_source_hash(tmp_path, monkeypatch):
     assert bench.profile_traffic("kx", "w1", None) is None           # schedule required
     assert bench.profile_traffic("ky", "anything") == 99             # names neither
     assert bench.profile_traffic("kz") is None
+    (prof / "z.md").write_text(
+        "<!-- figures\nkernel: kp\nplan: threads=512,workgroups=32\nsource_sha256: %s\n"
+        "sources: a.hip b.h\ntraffic_bytes_per_launch: 7\n-->\n"
+        "<!-- figures\nkernel: kp\nplan: threads=256,workgroups=32\nsource_sha256: %s\n"
+        "sources: a.hip b.h\ntraffic_bytes_per_launch: 8\n-->\n" % (sha, sha))
+    assert bench.profile_traffic("kp", plan="threads=512,workgroups=32") == 7
+    assert bench.profile_traffic("kp", plan="threads=256,workgroups=32") == 8   # second block
+    assert bench.profile_traffic("kp", plan="threads=1024,workgroups=16") is None
     (csrc / "b.h").write_text("header b, changed\n")
     assert bench.profile_traffic("kx", "w1", sched) is None          # sources changed
     assert bench.profile_traffic("ky") is None
