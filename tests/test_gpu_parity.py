@@ -393,6 +393,32 @@ def test_step_timing_covers_every_step_and_changes_nothing():
     assert len(g.step_times()[0]) == 0
 
 
+@pytest.mark.parametrize("leaves", [100_000, 300_000])
+def test_pagerank_ordered_split_rows(leaves):
+    """A row split over many tiles: an in-star (every leaf points to the
+    centre) plus a cycle over the leaves.  The centre's row spans leaves /
+    (64 u) tiles (about 195 to 1,170 here), whose parts meet in one FP64
+    slot that the split pass turns into the row's update; the slot is left
+    clear for the next run."""
+    import numpy as np
+    gi = _gi()
+    n = leaves + 1
+    src = np.concatenate([np.arange(1, n), np.arange(1, n)]).astype(np.int32)
+    dst = np.concatenate([np.zeros(leaves), np.roll(np.arange(1, n), 1)]).astype(np.int32)
+    el = gg.EdgeList(n, src, dst)
+    g = device_graph(el)
+    og = oracle.Graph(el)
+    ref = oracle.pagerank(og, 20, 0.85)
+    for u in (4, 8):
+        g.set_schedule(vertex_order=1, block_threads=256, pull_items_per_thread=u)
+        say("ordered pagerank in-star leaves=%d u=%d" % (leaves, u))
+        x = run_pr(g, 20)
+        assert pr_max_rel(x, ref) <= PR_RTOL, u
+        x = run_pr(g, 20)   # the slots were left clear for the next run
+        assert pr_max_rel(x, ref) <= PR_RTOL, u
+    g.set_schedule()
+
+
 def test_pagerank_ordered_schedule_checks():
     """Combinations the degree-ordered pull does not offer are refused."""
     gi = _gi()
