@@ -546,6 +546,8 @@ def pagerank_legs(torch, dev, g22, steps=5):
                       "gteps": round(20.0 * g.m / (kmed * 1e-3) / 1e9, 3),
                       "roofline": roof, "schedule_sweep_ms": tuned}
         log("pagerank %s: %s, %.3f ms per 20 iterations" % (name, kw, kmed))
+        if name == "rmat16":
+            legs[name]["persistent"] = persistent_pagerank(torch, dev, g)
     g16.close()
     return legs
 
@@ -662,6 +664,32 @@ def sssp_road_leg(torch, dev, delta=4096, steps=3, warmup=1):
     return leg
 
 
+def persistent_pagerank(torch, dev, g, steps=5):
+    """The same 20 iterations as one persistent launch (a single batched
+    PageRank task, workgroups and block size autotuned): its time and the
+    split between work and the task barriers between iterations."""
+    import numpy as np
+
+    import paper_1805_00923_amd as gi
+    out = torch.empty(g.n, dtype=torch.float32, device=dev)
+    b = gi.Batch([g], [dict(graph=0, algorithm=gi.ALG_PAGERANK, iters=20, damping=0.85, out=out)])
+    b.autotune(reps=3)
+    b.run()
+    ms, bar = [], []
+    for _ in range(steps):
+        b.run()
+        ms.append(b.info()["ms"])
+        bar.append(float(b.barrier_ms()[0]))
+    info = b.info()
+    res = {"ms_per_20_iterations": round(float(np.median(ms)), 4),
+           "barrier_ms": round(float(np.median(bar)), 4),
+           "barrier_fraction": round(float(np.median(bar)) / max(float(info["task_ms"][0]), 1e-9), 3),
+           "workgroups": int(info["workgroups"][0]), "threads": b.threads(),
+           "pr_block_edges": int(b.pr_block_edges()[0])}
+    b.close()
+    return res
+
+
 def cpu_baseline_bfs_cc(el, srcs, m_reach, budget_s=12.0):
     """The oracle, single-threaded, on a bounded sample of the same workload:
     BFS from the sources in order until the budget is spent (at least 2),
@@ -761,19 +789,24 @@ def run_pr(args, torch, dev, scale):
     if not args.no_cpu_baseline:
         import oracle
         og = oracle.Graph(el)
-        reps = 1 if scale > 18 else 3
+        # whole runs until about 10 s are spent (at least one)
+        reps = 0
         with one_core():
             t0 = time.perf_counter()
-            for _ in range(reps):
+            while reps < 1 or time.perf_counter() - t0 < 10.0:
                 oracle.pagerank(og, 20, 0.85)
+                reps += 1
             dt_c = (time.perf_counter() - t0) / reps
         cpu = {"value": round(20.0 * og.m / dt_c / 1e9, 5), "unit": "GTEPS", "cores": 1,
                "kind": "oracle", "sample": "FP64 pull PageRank, 20 iterations, full graph, "
-                                           "one thread pinned to one core, %.3f s per run" % dt_c}
+                                           "one thread pinned to one core, %d runs, %.3f s per "
+                                           "run" % (reps, dt_c)}
     extra = {"schedule_sweep_ms": tuned,
              "run_ms_median": round(kmed, 4),
              "gteps_kernel": round(20.0 * m / (kmed * 1e-3) / 1e9, 3),
              "bytes_per_run": 20 * (4 * m + 16 * n) + 4 * n}
+    if scale == 16:
+        extra["persistent"] = persistent_pagerank(torch, dev, g)
     return value, "GTEPS", ms_step, "f32 storage / f64 accumulate", config, tally.roofline(), cpu, extra
 
 
