@@ -664,7 +664,7 @@ def sssp_road_leg(torch, dev, delta=4096, steps=3, warmup=1):
     return leg
 
 
-def persistent_pagerank(torch, dev, g, steps=5):
+def persistent_pagerank(torch, dev, g, steps=5, scope=None):
     """The same 20 iterations as one persistent launch (a single batched
     PageRank task, workgroups and block size autotuned): its time and the
     split between work and the task barriers between iterations."""
@@ -673,6 +673,8 @@ def persistent_pagerank(torch, dev, g, steps=5):
     import paper_1805_00923_amd as gi
     out = torch.empty(g.n, dtype=torch.float32, device=dev)
     b = gi.Batch([g], [dict(graph=0, algorithm=gi.ALG_PAGERANK, iters=20, damping=0.85, out=out)])
+    if scope is not None:
+        b.set_barrier_scope(scope)
     b.autotune(reps=3)
     b.run()
     ms, bar = [], []
@@ -806,7 +808,7 @@ def run_pr(args, torch, dev, scale):
              "gteps_kernel": round(20.0 * m / (kmed * 1e-3) / 1e9, 3),
              "bytes_per_run": 20 * (4 * m + 16 * n) + 4 * n}
     if scale == 16:
-        extra["persistent"] = persistent_pagerank(torch, dev, g)
+        extra["persistent"] = persistent_pagerank(torch, dev, g, scope=barrier_scope(args))
     return value, "GTEPS", ms_step, "f32 storage / f64 accumulate", config, tally.roofline(), cpu, extra
 
 

@@ -635,9 +635,12 @@ gi_status gi_batch_get_placement(const gi_batch* b, int32_t* xcd_local);
  * task starts, so a placement the dispatcher did not keep is detected) skips
  * the L2 write-back before arriving: the XCD's L2 is shared by its
  * workgroups and the L1 writes through to it; the cache invalidation after
- * the wait is kept.  Other tasks, and every task under GI_BARRIER_AGENT, use
- * agent scope: the L2 is written back before arriving and invalidated
- * after.  Results do not depend on the scope.  Errors: INVALID_ARG (another value, NULL, a launch in flight). */
+ * the wait is kept.  A task spread over several XCDs counts its arrivals
+ * per XCD first (one counter line per XCD; each XCD's last arrival arrives
+ * for it at the task's word), so at most 8 arrivals meet on one line.
+ * Under GI_BARRIER_AGENT every task uses one counter at agent scope: the
+ * L2 is written back before arriving and invalidated after.  Results do not
+ * depend on the scope.  Errors: INVALID_ARG (another value, NULL, a launch in flight). */
 enum { GI_BARRIER_AGENT = 0, GI_BARRIER_XCD = 1 };
 gi_status gi_batch_set_barrier_scope(gi_batch* b, int32_t scope);
 gi_status gi_batch_get_barrier_scope(const gi_batch* b, int32_t* scope);

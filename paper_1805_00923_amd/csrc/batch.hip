@@ -49,18 +49,27 @@ __device__ __forceinline__ unsigned xcc_id() {
   return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xfu;  // XCC_ID[3:0]
 }
 
-// Record this workgroup's XCD in the task's mask; called by every workgroup
-// of the task before the task's first barrier.
+// Record this workgroup's XCD in the task's mask and count; called by every
+// workgroup of the task before the task's first barrier.
 __device__ __forceinline__ void task_join(TaskCtl* c) {
-  if (threadIdx.x == 0) atomicOr(&c->xcds, 1u << xcc_id());
+  if (threadIdx.x == 0) {
+    const unsigned x = xcc_id() & 7u;
+    atomicOr(&c->xcds, 1u << x);
+    atomicAdd(&c->xcnt[x], 1u);
+  }
 }
 
-// After the task's first barrier: true when every workgroup of the task runs
-// on one XCD, so that they share one L2.  Read by all workgroups after the
-// same barrier, so all take the same barrier form.
-__device__ __forceinline__ bool task_on_one_xcd(const TaskCtl* c) {
+// Barrier forms after the task's first barrier (which is always the agent
+// form: the XCD counts are final only after it).
+enum { kBarAgent = 0, kBarLocal = 1, kBarTree = 2 };
+
+// The form for the task's later barriers, from its XCDs: one XCD shares one
+// L2 (kBarLocal); several count their arrivals per XCD first (kBarTree).
+// Read by all workgroups after the same barrier, so all take the same form.
+__device__ __forceinline__ int task_barrier_form(const TaskCtl* c, int xcd_barrier) {
+  if (!xcd_barrier) return kBarAgent;
   const unsigned m = __hip_atomic_load(&c->xcds, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return __popc(m) == 1;
+  return __popc(m) == 1 ? kBarLocal : kBarTree;
 }
 
 // Wall-clock ticks the calling workgroup has spent in task barriers during
@@ -80,6 +89,10 @@ __device__ __forceinline__ long long& barrier_ticks() {
 //   Agent scope (the task's workgroups may sit on different XCDs, whose L2s
 //   are not coherent with each other): release writes the L2 back, acquire
 //   invalidates L1 and L2.
+//   Tree (several XCDs): as agent scope, but the arrivals meet first in a
+//   counter of their XCD (a line of its own), and only each XCD's last
+//   arrival goes on to the task's word: at most 8 arrivals meet there
+//   instead of k, and the k atomics on one line no longer serialise.
 //   One XCD (`local`): the task's workgroups share one L2, and the vector L1
 //   writes through to it, so a wave's completed stores are already in the
 //   L2 every participant reads: the release's L2 write-back is skipped.
@@ -89,7 +102,8 @@ __device__ __forceinline__ long long& barrier_ticks() {
 //   it leaves dirty L2 lines in place.  Lines written at several levels are
 //   then written back to memory once, not at every barrier.
 // Returns false once the batch has failed (timeout here or elsewhere).
-__device__ bool task_barrier(TaskCtl* c, int k, int* gerr, long long limit, bool local = false) {
+__device__ bool task_barrier(TaskCtl* c, int k, int* gerr, long long limit,
+                             int form = kBarAgent) {
   __shared__ int s_ok;
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
@@ -97,10 +111,30 @@ __device__ bool task_barrier(TaskCtl* c, int k, int* gerr, long long limit, bool
     int ok = __hip_atomic_load(gerr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     if (ok && k > 1) {
       const long long t0 = wall_ticks();
-      if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      const unsigned long long old = atomicAdd(&c->bar, 1ull);
-      const unsigned long long gen = old >> 32;
-      if ((old & 0xffffffffull) == (unsigned long long)(k - 1)) {
+      if (form != kBarLocal) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      unsigned long long gen;
+      bool last = false;
+      if (form == kBarTree) {
+        // the generation cannot move before this workgroup arrives
+        gen = __hip_atomic_load(&c->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32;
+        const unsigned x = xcc_id() & 7u;
+        const unsigned here = __hip_atomic_load(&c->xcnt[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (atomicAdd(&c->xarr[x][0], 1ull) == (unsigned long long)here - 1ull) {
+          // this XCD's last arrival: clear its counter for the next barrier
+          // (done before the task's word moves, so no later arrival misses
+          // it) and arrive for the XCD
+          __hip_atomic_store(&c->xarr[x][0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __builtin_amdgcn_s_waitcnt(0);
+          const unsigned nx = __popc(__hip_atomic_load(&c->xcds, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT));
+          last = (atomicAdd(&c->bar, 1ull) & 0xffffffffull) == (unsigned long long)(nx - 1);
+        }
+      } else {
+        const unsigned long long old = atomicAdd(&c->bar, 1ull);
+        gen = old >> 32;
+        last = (old & 0xffffffffull) == (unsigned long long)(k - 1);
+      }
+      if (last) {
         __hip_atomic_store(&c->bar, (gen + 1ull) << 32, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
       } else {
@@ -150,7 +184,7 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
   }
   task_join(c);
   if (!task_barrier(c, k, a.error, a.spin_limit)) return;
-  const bool local = a.xcd_barrier && task_on_one_xcd(c);
+  const int bform = task_barrier_form(c, a.xcd_barrier);
   if (r == 0 && tid == 0) {
     const int s = t.src;
     level[s] = 0;
@@ -160,7 +194,7 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
     c->qn[0] = 1;
     c->ds[0] = G.outdeg[s];
   }
-  if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
+  if (!task_barrier(c, k, a.error, a.spin_limit, bform)) return;
   DevGraph dg{};
   dg.n = n;
   dg.m = G.m;
@@ -219,7 +253,7 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
       atomicAdd(&c->qn[(L + 1) % 3], (unsigned long long)p.a);
       atomicAdd(&c->ds[(L + 1) % 3], (unsigned long long)p.b);
     }
-    if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
+    if (!task_barrier(c, k, a.error, a.spin_limit, bform)) return;
   }
   if (r == 0 && tid == 0) {
     c->levels = L;
@@ -516,7 +550,7 @@ __device__ void sssp_task(const BatchGraph& G, const BatchTask& t, int r, const 
   }
   task_join(c);
   if (!task_barrier(c, k, a.error, a.spin_limit)) return;
-  const bool local = a.xcd_barrier && task_on_one_xcd(c);
+  const int bform = task_barrier_form(c, a.xcd_barrier);
   if (r == 0 && tid == 0) {
     dist[t.src] = 0u;
     t.bv0[t.src >> 6] = 1ull << (t.src & 63);
@@ -524,7 +558,7 @@ __device__ void sssp_task(const BatchGraph& G, const BatchTask& t, int r, const 
     c->qn[0] = 1;
     c->thresh = delta;
   }
-  if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
+  if (!task_barrier(c, k, a.error, a.spin_limit, bform)) return;
   __shared__ unsigned long long s_red[BT / kWave];
   // scanned phases: the new members of the next near set and of the far set
   constexpr int kBuf = 512;
@@ -619,7 +653,7 @@ __device__ void sssp_task(const BatchGraph& G, const BatchTask& t, int r, const 
       const Part p = block_sum4<BT>(Part{far_new, edges, 0, 0});
       if (tid == 0 && p.a) atomicAdd(&c->farc[(P + 1) % 3], (unsigned long long)p.a);
       relaxed += p.b;  // thread 0's sum
-      if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
+      if (!task_barrier(c, k, a.error, a.spin_limit, bform)) return;
       continue;
     }
     // split: the next bucket starts at the smallest far distance at or
@@ -656,7 +690,7 @@ __device__ void sssp_task(const BatchGraph& G, const BatchTask& t, int r, const 
       if (mn != ~0ull) atomicMin(&c->fmin, mn);
     }
     if (r == 0 && tid == 0) c->ft[fs ^ 1] = 0;  // the list the kept members go to
-    if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
+    if (!task_barrier(c, k, a.error, a.spin_limit, bform)) return;
     // every workgroup has read fbad above
     if (r == 0 && tid == 0) c->fbad = rebuild ? 0 : 1;
     const unsigned long long fm = __hip_atomic_load(&c->fmin, __ATOMIC_RELAXED,
@@ -713,7 +747,7 @@ __device__ void sssp_task(const BatchGraph& G, const BatchTask& t, int r, const 
     // barrier above); rank 0 publishes the new one for the next phase
     if (r == 0 && tid == 0) c->thresh = tnew;
     fs ^= 1;
-    if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
+    if (!task_barrier(c, k, a.error, a.spin_limit, bform)) return;
   }
   if (tid == 0 && relaxed) atomicAdd(&c->relaxed, (unsigned long long)relaxed);
   if (r == 0 && tid == 0) {
@@ -748,7 +782,7 @@ __device__ void pr_task(const BatchGraph& G, const BatchTask& t, int r, const Ba
   }
   task_join(c);
   if (!task_barrier(c, k, a.error, a.spin_limit)) return;
-  const bool local = a.xcd_barrier && task_on_one_xcd(c);
+  const int bform = task_barrier_form(c, a.xcd_barrier);
   PrVertex pv;
   pv.outdeg = G.outdeg;
   pv.alpha = (double)t.damping;
@@ -767,7 +801,7 @@ __device__ void pr_task(const BatchGraph& G, const BatchTask& t, int r, const Ba
     float* rk = it == t.iters - 1 ? ranks : nullptr;
     for (int tb = r; tb < G.pr_ntab; tb += k)
       pr_rows_block<BT>(rows, tb, G.pr_cap_e, cin, 0, pv, cout, rk, nullptr, lds_val, lds_off);
-    if (!task_barrier(c, k, a.error, a.spin_limit, local)) return;
+    if (!task_barrier(c, k, a.error, a.spin_limit, bform)) return;
   }
   if (r == 0 && tid == 0) c->levels = t.iters;
 }

@@ -248,6 +248,10 @@ struct TaskCtl {
   int qbad[3];               // SSSP: the near set's list is incomplete, rotating like qn
   int fbad;                  // SSSP: the far list is incomplete
   unsigned xcds;             // XCDs the task's workgroups run on (bit per XCC id)
+  unsigned xcnt[8];          // the task's workgroups on each XCD
+  // arrivals per XCD at a barrier of a task spread over several XCDs, one
+  // 128-byte line each
+  alignas(128) unsigned long long xarr[8][16];
 };
 
 struct BatchTask {
