@@ -567,6 +567,10 @@ typedef struct gi_task {
                          (parent[src] = src, -1 unreachable; any BFS tree)      */
   uint32_t sssp_delta; /* SSSP bucket width; 0 = the graph's schedule value
                          (sssp_delta, else 512).  SSSP needs a weighted graph  */
+  int32_t hybrid_divisor; /* BFS: a level pulls when |F| + sum deg(F) > m / this
+                         (section 2, direction optimization); 0 = the graph's
+                         schedule value at creation (hybrid_divisor, 20 by
+                         default).  Levels and parents do not depend on it   */
 } gi_task;
 
 typedef struct gi_batch gi_batch;

@@ -632,7 +632,8 @@ class Task(ctypes.Structure):
     _fields_ = [("graph", ctypes.c_int32), ("algorithm", ctypes.c_int32), ("src", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("damping", ctypes.c_float),
                 ("workgroups", ctypes.c_int32), ("out", ctypes.c_void_p),
-                ("parent", ctypes.c_void_p), ("sssp_delta", ctypes.c_uint32)]
+                ("parent", ctypes.c_void_p), ("sssp_delta", ctypes.c_uint32),
+                ("hybrid_divisor", ctypes.c_int32)]
 
 
 class Batch:
@@ -641,7 +642,7 @@ class Batch:
     tasks: sequence of dicts with keys graph (index), algorithm (ALG_BFS,
     ALG_PAGERANK or ALG_SSSP), out (device tensor of n int32, float32 or
     int32-as-uint32 distances), and src / iters / damping / workgroups /
-    parent / sssp_delta as needed."""
+    parent / sssp_delta / hybrid_divisor as needed."""
 
     def __init__(self, graphs, tasks):
         self.graphs = list(graphs)
@@ -651,7 +652,7 @@ class Batch:
             arr[i] = Task(int(t["graph"]), int(t["algorithm"]), int(t.get("src", 0)),
                           int(t.get("iters", 20)), float(t.get("damping", 0.85)),
                           int(t.get("workgroups", 0)), _dptr(t["out"]), _dptr(t.get("parent")),
-                          int(t.get("sssp_delta", 0)))
+                          int(t.get("sssp_delta", 0)), int(t.get("hybrid_divisor", 0)))
         hs = (ctypes.c_void_p * len(self.graphs))(*[g._h.value for g in self.graphs])
         self._h = ctypes.c_void_p(None)
         self.ntasks = len(tasks)

@@ -215,7 +215,7 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
       if (tid == 0) __hip_atomic_store(a.error, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
-    const bool pull = hybrid_dense(nf, df, G.m, 20);
+    const bool pull = hybrid_dense(nf, df, G.m, t.div);
     if (r == 0 && tid == 0) {
       // read by every workgroup at the previous level, accumulated at the next
       c->qn[(L + 2) % 3] = 0;

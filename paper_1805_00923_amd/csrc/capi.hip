@@ -3188,6 +3188,7 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
       return fail(GI_ERR_INVALID_ARG, "task %d: bad PageRank parameters", i);
     if (t.workgroups < 0 || t.workgroups > 1024)
       return fail(GI_ERR_INVALID_ARG, "task %d: workgroups outside [0, 1024]", i);
+    if (t.hybrid_divisor < 0) return fail(GI_ERR_INVALID_ARG, "task %d: hybrid_divisor < 0", i);
   }
   gi_batch* b = new (std::nothrow) gi_batch();
   if (!b) return fail(GI_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -3244,6 +3245,7 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
     d.alg = t.algorithm == GI_ALG_BFS ? ALG_BFS : t.algorithm == GI_ALG_SSSP ? ALG_SSSP : ALG_PR;
     d.delta = t.sssp_delta > 0 ? t.sssp_delta
                                : (g->sched.sssp_delta > 0 ? g->sched.sssp_delta : 512u);
+    d.div = t.hybrid_divisor > 0 ? t.hybrid_divisor : g->sched.hybrid_divisor;
     d.graph = t.graph;
     d.src = t.src;
     d.iters = t.iters;

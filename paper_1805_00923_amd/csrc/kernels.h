@@ -261,6 +261,7 @@ struct BatchTask {
   int src;
   int iters;
   unsigned delta;  // SSSP bucket width
+  int div;         // BFS hybrid divisor: pull when |F| + deg(F) > m / div
   float damping;
   int k;        // workgroups
   void* out;    // int32 levels or float ranks

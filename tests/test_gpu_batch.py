@@ -180,6 +180,46 @@ def test_batch_trace_matches_levels():
     b.close()
 
 
+def test_batch_bfs_hybrid_divisor_per_task():
+    """Each BFS task's own hybrid divisor decides its directions (the trace
+    follows |F| + deg(F) > m / divisor level by level: 1 never pulls, a huge
+    divisor pulls at every non-empty level), levels equal the oracle's and
+    the parents form a BFS tree whatever the directions."""
+    import torch
+    import paper_1805_00923_amd as gi
+    P = pool()
+    tasks, divs = [], []
+    for gidx in (0, 1, 2, 3, 7):
+        el, g, og = P[gidx]
+        for div in (1, 5, 20, 1 << 30):
+            src = (97 * gidx + div) % g.n
+            tasks.append(dict(graph=gidx, algorithm=1, src=src, hybrid_divisor=div,
+                              out=torch.full((g.n,), -9, dtype=torch.int32, device="cuda:0"),
+                              parent=torch.full((g.n,), -9, dtype=torch.int32, device="cuda:0")))
+            divs.append(div)
+    b = gi.Batch([g for _, g, _ in P], tasks)
+    b.set_trace(4096)
+    say("batch BFS per-task divisors")
+    b.run(use_graph=True)
+    torch.cuda.synchronize()
+    check(tasks)
+    for i, (t, div) in enumerate(zip(tasks, divs)):
+        el, g, og = P[t["graph"]]
+        _, pull, fr = b.trace(i)
+        lv = t["out"].cpu().numpy()
+        sizes = np.bincount(lv[lv >= 0])
+        outdeg = np.diff(og.out.off)
+        for L in range(len(sizes)):
+            deg = int(outdeg[lv == L].sum())
+            assert bool(pull[L]) == ((int(sizes[L]) + deg) * div > g.m), (i, el.name, div, L)
+        if div == 1:
+            assert not np.any(pull[:-1]), (i, el.name)
+    with pytest.raises(gi.GiError):
+        gi.Batch([P[0][1]], [dict(graph=0, algorithm=1, src=0, hybrid_divisor=-1,
+                                  out=torch.zeros(P[0][1].n, dtype=torch.int32, device="cuda:0"))])
+    b.close()
+
+
 def test_batch_fixed_workgroups_and_graph_replays():
     import torch
     import paper_1805_00923_amd as gi
