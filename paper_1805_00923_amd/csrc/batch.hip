@@ -204,6 +204,7 @@ __device__ void bfs_task(const BatchGraph& G, const BatchTask& t, int r, const B
   dg.in_idx = G.in_idx;
   dg.outdeg = G.outdeg;
   dg.in_probe = G.in_probe;
+  dg.bfs_idx = G.bfs_idx;
   int L = 0;
   for (;; ++L) {
     const long long nf = (long long)__hip_atomic_load(&c->qn[L % 3], __ATOMIC_RELAXED,

@@ -81,8 +81,13 @@ __device__ void push_hubs(const int32_t* hubs, int nhubs, const DenseSet& cur,
 // or two ids, is never read.  Lanes still open test their first in-edges
 // in two batches of four independent loads; the rows still open are then
 // concatenated and walked 64 edges per round across the wave.  A row stops
-// at its first source in the frontier (the probe, else in in-edge order).  The next frontier word and the
-// visited word are written whole, without atomics.
+// at its first source in the frontier (the probe, else in scan order).
+// The scan order is the graph's BFS copy of the in-rows when it has one:
+// sources by decreasing out-degree, so a row begins with its probe (skipped)
+// and goes on with the sources most likely to be on the frontier; on R-MAT
+// 22 that halves the edges scanned after a probe miss and the rows that
+// need the round loop.  The next frontier word and the visited word are
+// written whole, without atomics.
 // Words [wbeg, wend) are covered by waves wave0, wave0 + nwaves, ...; with
 // `deg` set, the claimed vertices and their degrees are accumulated
 // degrees (*nfound, *nfound_deg).
@@ -92,6 +97,9 @@ __device__ long long bfs_pull_range(const BfsArgs& b, int l1, int wbeg, int wend
                                     long long* nfound_deg) {
   const DevGraph& g = b.g;
   const int n = g.n, W = wend, lane = __lane_id();
+  // rows led by their probe: the scan starts after it
+  const int32_t* in_idx = g.bfs_idx ? g.bfs_idx : g.in_idx;
+  const int skip = g.bfs_idx ? 1 : 0;
   const DenseSet cur = b.cur, nxt = b.next;
   long long work = 0;
   // visited words of the next group are loaded one group ahead (only this
@@ -131,6 +139,7 @@ __device__ long long bfs_pull_range(const BfsArgs& b, int l1, int wbeg, int wend
         if (g.in_probe) pb[q] = g.in_probe[v];
         j[q] = g.in_off[v];
         e[q] = g.in_off[v + 1];
+        if (pb[q] >= 0) j[q] += skip;
       }
     }
 #pragma unroll
@@ -150,7 +159,7 @@ __device__ long long bfs_pull_range(const BfsArgs& b, int l1, int wbeg, int wend
       for (int q = 0; q < G; ++q)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          u[q][r] = (cand[q] && !found[q] && j[q] + r < e[q]) ? g.in_idx[j[q] + r] : -1;
+          u[q][r] = (cand[q] && !found[q] && j[q] + r < e[q]) ? in_idx[j[q] + r] : -1;
       bool h[G][4];
 #pragma unroll
       for (int q = 0; q < G; ++q)
@@ -200,7 +209,7 @@ __device__ long long bfs_pull_range(const BfsArgs& b, int l1, int wbeg, int wend
         const int jo = __shfl(j[q], own, kWave);
         const int eo = __shfl(ex[q], own, kWave);
         const bool act = lane < tot[q];
-        uu[q] = act ? g.in_idx[jo + (lane - eo)] : 0;
+        uu[q] = act ? in_idx[jo + (lane - eo)] : 0;
       }
 #pragma unroll
       for (int q = 0; q < G; ++q) hit[q] = lane < tot[q] && cur.test(uu[q]);

@@ -235,6 +235,10 @@ struct gi_graph {
   std::vector<SegDev> segs;
   // degree-ordered in-adjacency and its merge-path tiles (PageRank with
   // vertex_order = GI_ORDER_OUT_DEGREE; built on first use)
+  // in-rows by decreasing source out-degree, ties by id (the BFS pull's scan
+  // order: a row starts with its probe; built on first use)
+  std::vector<void*> bfsr_allocs;
+  int32_t* bfs_idx = nullptr;
   std::vector<void*> ord_allocs;  // the ordered copy (graph lifetime once built)
   std::vector<void*> ordt_allocs; // tiles and split slots (rebuilt when the tile size changes)
   int32_t *ord_off = nullptr, *ord_idx = nullptr, *ord_outdeg = nullptr, *ord_old = nullptr;
@@ -702,6 +706,37 @@ static gi_status ensure_pr_segments(gi_graph* g, int p, int strategy) {
   return build_segments(g, p, strategy);
 }
 
+// The BFS pull's copy of the in-rows: each row ordered by decreasing source
+// out-degree, ties by id, so it starts with the probe (in_probe) and goes on
+// with the next most connected sources, the ones most likely to be on the
+// frontier.  Same rows, same edges; only the order of a pull's scan changes
+// (and with it which frontier in-neighbour becomes the parent).
+static gi_status ensure_bfs_rows(gi_graph* g) {
+  if (g->bfs_idx) return GI_OK;
+  const int32_t n = g->n;
+  const size_t m = (size_t)g->m;
+  std::vector<int32_t> idx(g->h_in_idx.begin(), g->h_in_idx.begin() + (ptrdiff_t)m);
+  const int32_t* io = g->h_in_off.data();
+  const int32_t* od = g->h_outdeg.data();
+  const unsigned nth = host_workers();
+  const bool ok = run_workers([&](unsigned t) {
+    for (int32_t v = worker_row(n, t, nth); v < worker_row(n, t + 1, nth); ++v)
+      std::sort(idx.data() + io[v], idx.data() + io[v + 1], [od](int32_t a, int32_t b) {
+        return od[a] != od[b] ? od[a] > od[b] : a < b;
+      });
+  });
+  if (!ok) return fail(GI_ERR_OUT_OF_MEMORY, "host allocation failed (BFS in-rows)");
+  int32_t* d = nullptr;
+  gi_status st = dev_alloc(g, g->bfsr_allocs, &d, std::max<size_t>(1, m));
+  if (st == GI_OK) st = upload(idx.data(), d, 4 * m);
+  if (st != GI_OK) {
+    free_list(g->bfsr_allocs);
+    return st;
+  }
+  g->bfs_idx = d;
+  return GI_OK;
+}
+
 // Degree-ordered copy of the in-adjacency (PageRank, vertex_order =
 // GI_ORDER_OUT_DEGREE): new ids by decreasing out-degree, ties by id; row r
 // holds the new ids of the in-neighbours of old_id[r], sorted.
@@ -968,6 +1003,7 @@ extern "C" gi_status gi_graph_destroy(gi_graph* g) {
   free_list(g->ccseg_allocs);
   free_list(g->ordt_allocs);
   free_list(g->ord_allocs);
+  free_list(g->bfsr_allocs);
   free_list(g->allocs);
   for (void* q : {(void*)g->sel_p, (void*)g->sel_wb, (void*)g->sel_io}) dmem_free(q);
   if (g->hflags) (void)hipHostFree(g->hflags);
@@ -1391,6 +1427,7 @@ static DevGraph dev_graph(const gi_graph* g) {
   d.outdeg = g->outdeg;
   d.udeg = g->udeg;
   d.in_probe = g->in_probe;
+  d.bfs_idx = g->bfs_idx;
   return d;
 }
 
@@ -1820,6 +1857,11 @@ extern "C" gi_status gi_bfs(gi_graph* g, int32_t src, int32_t* level, int32_t* p
   hipStream_t s = static_cast<hipStream_t>(stream);
   gi_status st = check_learned(g);
   if (st != GI_OK) return st;
+  const int dir = g->sched.direction;
+  if (dir == GI_DIR_DENSE_PULL || dir == GI_DIR_DENSE_PULL_SPARSE_PUSH || dir == GI_DIR_LEARNED) {
+    st = ensure_bfs_rows(g);
+    if (st != GI_OK) return st;
+  }
   st = start_run(g, 0, s);
   if (st != GI_OK) return st;
   BfsArgs b;
@@ -3061,6 +3103,7 @@ static BatchGraph batch_graph(const gi_graph* g, const gi_batch::PrLayout& l) {
   d.outdeg = g->outdeg;
   d.out_w = g->out_w;
   d.in_probe = g->in_probe;
+  d.bfs_idx = g->bfs_idx;
   d.hubs = g->hubs;
   d.nhubs = g->nhubs;
   d.pr_table = l.table;
@@ -3220,6 +3263,11 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
     if (!has_pr[i]) continue;
     gi_status sl = batch_set_layout(b, i, b->graphs[i]->pr_cap_e);
     if (sl != GI_OK) return bail(sl);
+  }
+  for (int32_t i = 0; i < ntasks; ++i) {
+    if (tasks[i].algorithm != GI_ALG_BFS) continue;
+    gi_status sb = ensure_bfs_rows(b->graphs[(size_t)tasks[i].graph]);
+    if (sb != GI_OK) return bail(sb);
   }
   int dev = 0, cus = 0, rate = 0;
   HIP_TRY(hipGetDevice(&dev));

@@ -47,6 +47,9 @@ struct DevGraph {
   const int32_t* outdeg;  // out_off[v+1]-out_off[v]
   const int32_t* udeg;    // out-degree + in-degree
   const int32_t* in_probe;  // per vertex: its in-neighbour of largest out-degree, -1 if none
+  const int32_t* bfs_idx = nullptr;  // in-rows by decreasing source out-degree (ties by
+                                     // id), so each row starts with its probe; null: the
+                                     // BFS pull scans in_idx
 };
 
 // Per-workgroup statistics of one phase.

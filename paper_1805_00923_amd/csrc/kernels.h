@@ -222,6 +222,7 @@ struct BatchGraph {
   const int32_t* outdeg;
   const uint32_t* out_w;  // edge weights (weighted graphs; SSSP tasks)
   const int32_t* in_probe;
+  const int32_t* bfs_idx;  // in-rows starting with their probe (BFS pull), or null
   const int32_t* hubs;   // vertices with more than kHubDeg out-edges
   int nhubs;
   const int4* pr_table;  // PageRank destination blocks (the graph's current schedule)
