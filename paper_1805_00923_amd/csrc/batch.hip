@@ -807,7 +807,10 @@ __device__ void pr_task(const BatchGraph& G, const BatchTask& t, int r, const Ba
   if (r == 0 && tid == 0) c->levels = t.iters;
 }
 
-template <int BT>
+// ALGS: the task bodies built in (kBatchBfs, or kBatchAll).  Without the
+// SSSP and PageRank bodies the BFS path keeps more of its values in
+// registers.
+template <int BT, int ALGS>
 __global__ __launch_bounds__(BT, batch_min_waves<BT>()) void k_batch(BatchArgs a) {
   extern __shared__ float smem[];
   float* lds_val = smem;
@@ -819,9 +822,15 @@ __global__ __launch_bounds__(BT, batch_min_waves<BT>()) void k_batch(BatchArgs a
     const BatchGraph& G = a.graphs[t.graph];
     if (threadIdx.x == 0) barrier_ticks() = 0;
     if (it.y == 0 && threadIdx.x == 0) t.ctl->t_begin = wall_ticks();
-    if (t.alg == ALG_BFS) bfs_task<BT>(G, t, it.y, a, reinterpret_cast<int*>(smem));
-    else if (t.alg == ALG_SSSP) sssp_task<BT>(G, t, it.y, a, reinterpret_cast<int*>(smem));
-    else pr_task<BT>(G, t, it.y, a, lds_val, lds_off);
+    if (t.alg == ALG_BFS) {
+      if constexpr ((ALGS & kBatchBfs) != 0)
+        bfs_task<BT>(G, t, it.y, a, reinterpret_cast<int*>(smem));
+    } else if (t.alg == ALG_SSSP) {
+      if constexpr ((ALGS & kBatchSssp) != 0)
+        sssp_task<BT>(G, t, it.y, a, reinterpret_cast<int*>(smem));
+    } else {
+      if constexpr ((ALGS & kBatchPr) != 0) pr_task<BT>(G, t, it.y, a, lds_val, lds_off);
+    }
     if (it.y == 0 && threadIdx.x == 0) t.ctl->t_end = wall_ticks();
     if (threadIdx.x == 0 && barrier_ticks() > 0)
       atomicAdd(&t.ctl->bar_ticks, (unsigned long long)barrier_ticks());
@@ -847,13 +856,19 @@ size_t batch_lds_bytes(int cap_e, int cap_v) {
 
 bool batch_threads_ok(int bt) { return bt == 256 || bt == 512 || bt == 1024; }
 
-int batch_occupancy(int bt, size_t lds) {
+template <int BT, int ALGS>
+static hipError_t batch_occ(int* blocks, size_t lds) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch<BT, ALGS>, BT, lds);
+}
+
+int batch_occupancy(int bt, size_t lds, int algs) {
   int blocks = 0;
   hipError_t e = hipErrorInvalidValue;
+  const bool bfs = algs == kBatchBfs;
   switch (bt) {
-    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<256>, 256, lds); break;
-    case 512: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<512>, 512, lds); break;
-    case 1024: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch<1024>, 1024, lds); break;
+    case 256: e = bfs ? batch_occ<256, kBatchBfs>(&blocks, lds) : batch_occ<256, kBatchAll>(&blocks, lds); break;
+    case 512: e = bfs ? batch_occ<512, kBatchBfs>(&blocks, lds) : batch_occ<512, kBatchAll>(&blocks, lds); break;
+    case 1024: e = bfs ? batch_occ<1024, kBatchBfs>(&blocks, lds) : batch_occ<1024, kBatchAll>(&blocks, lds); break;
     default: return -1;
   }
   return e == hipSuccess ? blocks : -1;
@@ -863,13 +878,19 @@ int launch_batch(const BatchArgs& a, int bt, int grid, size_t lds, TaskCtl* ctl,
                  hipStream_t s) {
   hipLaunchKernelGGL(k_batch_init, dim3(std::max(1, std::min(64, (ntasks + 255) / 256))),
                      dim3(256), 0, s, ctl, ntasks, a.error);
-  switch (bt) {
-    case 256: hipLaunchKernelGGL(k_batch<256>, dim3(grid), dim3(256), lds, s, a); break;
-    case 512: hipLaunchKernelGGL(k_batch<512>, dim3(grid), dim3(512), lds, s, a); break;
-    case 1024: hipLaunchKernelGGL(k_batch<1024>, dim3(grid), dim3(1024), lds, s, a); break;
-    default: return -1;
+#define GI_BATCH_LAUNCH(B)                                                         \
+  if (bt == B) {                                                                   \
+    if (a.algs == kBatchBfs)                                                       \
+      hipLaunchKernelGGL((k_batch<B, kBatchBfs>), dim3(grid), dim3(B), lds, s, a); \
+    else                                                                           \
+      hipLaunchKernelGGL((k_batch<B, kBatchAll>), dim3(grid), dim3(B), lds, s, a); \
+    return hipGetLastError() == hipSuccess ? 0 : -1;                               \
   }
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+  GI_BATCH_LAUNCH(256)
+  GI_BATCH_LAUNCH(512)
+  GI_BATCH_LAUNCH(1024)
+#undef GI_BATCH_LAUNCH
+  return -1;
 }
 
 }  // namespace gi

@@ -2966,6 +2966,7 @@ struct gi_batch {
   int max_grid = 0;          // resident workgroups of the batch kernel
   int grid = 0;
   int bt = 256;              // threads per workgroup
+  int algs = kBatchAll;      // algorithms among the tasks (selects the kernel build)
   int trace_cap = 0;         // per-task step records (gi_batch_set_trace)
   long long* d_trace = nullptr;
   bool bt_pinned = false;    // set by gi_batch_set_threads: the autotuner keeps it
@@ -3085,7 +3086,7 @@ static gi_status batch_set_layout(gi_batch* b, size_t i, int cap_e) {
 // that size (at most 8 workgroups per CU).
 static gi_status batch_set_bt(gi_batch* b, int bt) {
   if (!batch_threads_ok(bt)) return fail(GI_ERR_INVALID_ARG, "threads must be 256, 512 or 1024");
-  const int occ = batch_occupancy(bt, b->lds);
+  const int occ = batch_occupancy(bt, b->lds, b->algs);
   if (occ < 1) return fail(GI_ERR_DEVICE, "batch kernel does not fit on a compute unit");
   b->bt = bt;
   b->max_grid = b->cus * std::min(occ, 8);
@@ -3237,6 +3238,11 @@ extern "C" gi_status gi_batch_create(gi_graph* const* graphs, int32_t ngraphs, c
   if (!b) return fail(GI_ERR_OUT_OF_MEMORY, "host allocation failed");
   b->graphs.assign(graphs, graphs + ngraphs);
   b->tasks.assign(tasks, tasks + ntasks);
+  b->algs = 0;
+  for (int32_t i = 0; i < ntasks; ++i)
+    b->algs |= tasks[i].algorithm == GI_ALG_BFS    ? kBatchBfs
+               : tasks[i].algorithm == GI_ALG_SSSP ? kBatchSssp
+                                                   : kBatchPr;
   auto bail = [&](gi_status st) {
     gi_batch_destroy(b);
     return st;
@@ -3360,6 +3366,7 @@ static BatchArgs batch_args(const gi_batch* b, const int2* items, const int* wg_
   a.trace_cap = b->trace_cap;
   a.trace = b->d_trace;
   a.xcd_barrier = b->xcd_barrier;
+  a.algs = b->algs;
   return a;
 }
 

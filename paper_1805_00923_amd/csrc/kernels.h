@@ -292,11 +292,16 @@ struct BatchArgs {
                          // one-XCD barrier (L1 invalidate only); 0: agent scope
   long long* trace;      // [task][trace_cap][2]: wall clock at the step's start,
                          // (pull << 62) | frontier size (BFS) or 0 (PageRank)
+  int algs;              // host side: the algorithms among the tasks (kBatchBfs |
+                         // kBatchSssp | kBatchPr); a BFS-only batch launches a
+                         // kernel built without the other task bodies
 };
+
+enum { kBatchBfs = 1, kBatchSssp = 2, kBatchPr = 4, kBatchAll = 7 };
 
 bool batch_threads_ok(int bt);  // 256, 512 or 1024 threads per workgroup
 size_t batch_lds_bytes(int cap_e, int cap_v);
-int batch_occupancy(int bt, size_t lds);
+int batch_occupancy(int bt, size_t lds, int algs);
 int launch_batch(const BatchArgs& a, int bt, int grid, size_t lds, TaskCtl* ctl, int ntasks,
                  hipStream_t s);
 
