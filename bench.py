@@ -86,9 +86,13 @@ def parse():
                          "the default) or every barrier writes back and invalidates L2 (agent)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-threads", type=int, default=0, choices=[0, 256, 512, 1024],
-                    help="default workload: pin the BFS batch's workgroup size (0: autotuned)")
+                    help="default and sssp_grid workloads: pin the batch's workgroup size "
+                         "(0: autotuned)")
     ap.add_argument("--batch-workgroups", type=int, default=0,
-                    help="default workload: pin each BFS task's workgroups (0: autotuned)")
+                    help="default and sssp_grid workloads: pin each task's workgroups "
+                         "(0: autotuned)")
+    ap.add_argument("--sssp-batch-delta", type=int, default=0,
+                    help="sssp_grid: the batched path's bucket width (0: swept)")
     ap.add_argument("--no-legs", action="store_true",
                     help="default workload: skip the batched, road-like SSSP and persistent "
                          "PageRank legs (which launch their own k_batch before this workload's)")
@@ -657,8 +661,11 @@ def sssp_road_leg(torch, dev, delta=4096, steps=3, warmup=1):
     tally = KernelTally("k_batch (4 SSSP tasks)")
     tally.add(kms, [sum(sssp_label_setting_bytes(mr, nr) for mr, nr in zip(m_reach, n_reach))] * len(kms))
     info = b.info()
+    roof = tally.roofline()
+    roof["traffic"] = profile_traffic(roof["kernel"], "sssp_grid4096_noshortcut", None,
+                                      sssp_batch_plan(b, delta))
     leg = {"workload": "sssp_grid4096_noshortcut", "delta": delta, "ms_per_launch": round(dt * 1e3, 3),
-           "gteps": round(sum(m_reach) / dt / 1e9, 3), "roofline": tally.roofline(),
+           "gteps": round(sum(m_reach) / dt / 1e9, 3), "roofline": roof,
            "rerelaxation": round(float(b.edges().sum()) / sum(m_reach), 4),
            "phases": [int(x) for x in info["levels"]], "threads": b.threads(),
            "workgroups": [int(x) for x in info["workgroups"]], "wall_s": round(time.time() - t_all, 1)}
@@ -819,6 +826,13 @@ def run_pr(args, torch, dev, scale):
 SSSP_BATCH_DELTAS = (1000, 1 << 10, 1 << 11, 1 << 12, 1 << 13, 1 << 14)
 
 
+def sssp_batch_plan(b, delta):
+    """Key of a batched SSSP launch's plan in the committed counter figures:
+    workgroup size, each task's workgroups, bucket width."""
+    wg = "/".join(str(int(x)) for x in b.info()["workgroups"])
+    return "threads=%d,workgroups=%s,delta=%d" % (b.threads(), wg, delta)
+
+
 def run_sssp(args, torch, dev):
     """Delta-stepping SSSP from 4 sources on the 4096 x 4096 grid: the
     engine's per-phase launches (delta swept over {2^k, 5 <= k <= 14} and
@@ -897,10 +911,13 @@ def run_sssp(args, torch, dev):
         # instead of per-phase kernel launches); bucket width swept untimed
         outs = [torch.empty(g.n, dtype=torch.int32, device=dev) for _ in srcs]
         bsweep, best = {}, None
-        for delta in SSSP_BATCH_DELTAS:
+        for delta in ((args.sssp_batch_delta,) if args.sssp_batch_delta else SSSP_BATCH_DELTAS):
             b = gi.Batch([g], [dict(graph=0, algorithm=gi.ALG_SSSP, src=int(s_), sssp_delta=delta,
-                                    out=o) for s_, o in zip(srcs, outs)])
+                                    out=o, workgroups=args.batch_workgroups)
+                               for s_, o in zip(srcs, outs)])
             b.set_barrier_scope(barrier_scope(args))
+            if args.batch_threads:
+                b.set_threads(args.batch_threads)
             b.autotune(reps=1)
             b.run()
             b.run()
@@ -951,6 +968,7 @@ def run_sssp(args, torch, dev):
                       "batched_rerelaxation": round(float(bedges.sum()) / sum(m_reach), 4),
                       "speedup_vs_plain": round(dt / dtb, 3)})
         config["batched_delta"] = bdelta
+        config["batch_plan"] = sssp_batch_plan(b, bdelta)
         b.close()
     return value, "GTEPS", ms_step, "uint32", config, roof, None, extra
 
