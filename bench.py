@@ -756,7 +756,10 @@ def pr_kernel_name(sch):
 def pr_tune_and_time(g, torch, ranks, steps, warmup, overrides=None, cands=PR_CANDIDATES):
     """Tune the PageRank schedule of `g` over `cands` (two 20-iteration runs
     each, the second timed), then time `steps` runs with per-iteration HIP
-    events.  Returns (schedule, sweep, run ms list, wall seconds, tally)."""
+    events (the kernels' times, for the roofline) and `steps` whole runs
+    (the run's time: repeated arguments, so the degree-ordered run replays
+    from a HIP graph).  Returns (schedule, sweep, run ms list, wall seconds
+    of the whole runs, tally)."""
     n, m = g.n, g.m
     tuned = {}
     for c in cands:
@@ -771,17 +774,22 @@ def pr_tune_and_time(g, torch, ranks, steps, warmup, overrides=None, cands=PR_CA
     for _ in range(warmup):
         g.pagerank(ranks, 20, 0.85)
     torch.cuda.synchronize()
-    kms = []
     tally = KernelTally(pr_kernel_name(g.schedule()))
+    for _ in range(steps):
+        g.pagerank(ranks, 20, 0.85)
+        _, mm = g.step_times()
+        tally.add(mm, [4 * m + 16 * n] * len(mm))
+    g.set_step_timing(False)
+    for _ in range(max(warmup, 1)):
+        g.pagerank(ranks, 20, 0.85)
+    torch.cuda.synchronize()
+    kms = []
     t0 = time.perf_counter()
     for _ in range(steps):
         g.pagerank(ranks, 20, 0.85)
         kms.append(g.stats().kernel_ms)
-        _, mm = g.step_times()
-        tally.add(mm, [4 * m + 16 * n] * len(mm))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    g.set_step_timing(False)
     return kw, tuned, kms, dt, tally
 
 

@@ -328,7 +328,12 @@ int32_t gi_hybrid_choose_dense(int64_t frontier_size, int64_t frontier_degree_su
  * Runs DensePull (optionally segmented, num_segments > 1) regardless of the
  * direction field.  FP32 storage, FP64 accumulation.  Returns once the
  * iterations are enqueued on `stream` (ranks are complete when the stream
- * reaches them; gi_get_run_stats and gi_sync_status wait for them).
+ * reaches them; gi_get_run_stats and gi_sync_status wait for them).  With
+ * vertex_order = GI_ORDER_OUT_DEGREE, a call that repeats the previous
+ * call's ranks, iters, damping and layout (step timing off) replays the run
+ * as a HIP graph on the graph's own stream, which waits for `stream` and
+ * which `stream` then waits for: same kernels, same stream order, fewer
+ * launch gaps.
  *   ranks  device out, n floats: x_iters.
  * Errors: INVALID_ARG (iters < 0, damping outside [0,1], NULL), DEVICE. */
 gi_status gi_pagerank(gi_graph* g, int32_t iters, float damping, float* ranks, void* stream);

@@ -109,6 +109,63 @@ def test_pagerank_returns_after_enqueue_and_stats_wait():
     g.close()
 
 
+def test_pagerank_ordered_replays_from_a_graph():
+    """A degree-ordered PageRank call that repeats the previous call's
+    arguments replays the run from a HIP graph: every replay, with the
+    program's own eager work and synchronizations in between, on the default
+    stream and on a side stream, matches the oracle and the direct run; a
+    changed argument (output, iterations) or step timing runs directly."""
+    gi = _gi()
+    torch, dev = torch_dev()
+    el = gg.rmat(14, seed=34)
+    og = oracle.Graph(el)
+    ref = oracle.pagerank(og, 20, 0.85)
+    g = gi.Graph.from_edges(el.n, el.src, el.dst)
+    g.set_schedule(vertex_order=1)
+    x = torch.full((el.n,), -1.0, dtype=torch.float32, device=dev)
+    g.pagerank(x, 20, 0.85)  # direct (new arguments)
+    g.sync()
+    direct = x.cpu().numpy()
+    assert pr_max_rel(direct, ref) <= PR_RTOL
+    launches = g.stats().launches
+    side = torch.cuda.Stream()
+    lv = torch.empty(el.n, dtype=torch.int32, device=dev)
+    for rep in range(4):
+        say("boundary: ordered pagerank replay %d" % rep)
+        x.fill_(-3.0)  # eager work on the stream before the replay
+        if rep % 2:
+            with torch.cuda.stream(side):
+                side.wait_stream(torch.cuda.current_stream())
+                g.pagerank(x, 20, 0.85, stream=side)
+            torch.cuda.current_stream().wait_stream(side)
+        else:
+            g.pagerank(x, 20, 0.85)
+        y = x.clone()  # read on the caller's stream after the run
+        st = g.stats()
+        assert st.kernel_ms > 0 and st.steps == 20 and st.launches == launches
+        torch.cuda.synchronize()
+        got = y.cpu().numpy()
+        assert pr_max_rel(got, ref) <= PR_RTOL, rep
+        assert np.max(np.abs(got - direct) / np.maximum(np.abs(direct), 1e-30)) <= 1e-5, rep
+        g.bfs(int(rep), lv)  # other work of the graph between replays
+        torch.cuda.synchronize()
+    # changed arguments: a direct run, then replays of the new arguments
+    z = torch.full((el.n,), -1.0, dtype=torch.float32, device=dev)
+    ref7 = oracle.pagerank(og, 7, 0.85)
+    for _ in range(3):
+        z.fill_(-2.0)
+        g.pagerank(z, 7, 0.85)
+        g.sync()
+        assert pr_max_rel(z.cpu().numpy(), ref7) <= PR_RTOL
+    g.set_step_timing(True)
+    x.fill_(-4.0)
+    g.pagerank(x, 20, 0.85)
+    g.sync()
+    assert len(g.step_times()[0]) == 20
+    assert pr_max_rel(x.cpu().numpy(), ref) <= PR_RTOL
+    g.close()
+
+
 def test_workspace_refusals():
     gi = _gi()
     torch, dev = torch_dev()
