@@ -560,6 +560,38 @@ def pagerank_legs(torch, dev, g22, steps=5, persistent=None):
     return legs
 
 
+POOL_KERNEL = "k_batch (128 BFS + 128 PageRank tasks)"
+
+
+def pool_launch_bytes(gi, graphs, els, tasks, outs):
+    """Algorithmic bytes of one launch of the 256-instance pool: each BFS
+    task's levels (from its output; BFS levels are unique) under the hybrid
+    rule at divisor 20, the pull levels' scans by a host replay in CSC order
+    (bfs_step_bytes); 20 iterations of 4m + 16n per PageRank task."""
+    import numpy as np
+    replays, total = {}, 0
+    for t, r in zip(tasks, outs):
+        gx = t["graph"]
+        g, el = graphs[gx], els[gx]
+        if t["algorithm"] != gi.ALG_BFS:
+            total += 20 * (4 * g.m + 16 * g.n)
+            continue
+        if gx not in replays:
+            ioff, iidx, _ = gi.build_adjacency(el.n, el.dst, el.src)
+            replays[gx] = PullScanReplay(ioff, iidx)
+        lv = r.cpu().numpy()
+        odeg = np.diff(g.out_off).astype(np.int64)
+        nl = int(lv.max()) + 1
+        fs = np.bincount(lv[lv >= 0], minlength=nl).astype(np.int64)
+        ds = np.bincount(lv[lv >= 0], weights=odeg[lv >= 0], minlength=nl).astype(np.int64)
+        dirs = [2 if (int(fs[k]) + int(ds[k])) * 20 > g.m else 0 for k in range(nl)]
+        es = [0] * nl
+        for k, e in replays[gx].step_edges(lv, dirs).items():
+            es[k] = e
+        total += sum(bfs_step_bytes(g.n, dirs, fs, ds, es))
+    return total
+
+
 def batched_pool_leg(torch, dev, steps=3, warmup=1):
     """The batched workload's launch alone (256 BFS / PageRank instances over
     the 14-graph pool, autotuned, replayed from a HIP graph): time, aggregate
@@ -607,9 +639,12 @@ def batched_pool_leg(torch, dev, steps=3, warmup=1):
     info = b.info()
     bar = b.barrier_ms().astype(np.float64)
     wgs = info["workgroups"].astype(np.float64)
+    tally = KernelTally(POOL_KERNEL)
+    tally.add(kms, [pool_launch_bytes(gi, graphs, els, tasks, [t["out"] for t in tasks])] * len(kms))
     leg = {"workload": "batched256_bfs_pr20_rmat10-18_grid64-1024", "ms_per_launch": round(t_batch * 1e3, 3),
            "kernel_ms_median": round(float(np.median(kms)), 3),
-           "gteps": round(edges / t_batch / 1e9, 3), "threads": b.threads(), "grid": info["grid"],
+           "gteps": round(edges / t_batch / 1e9, 3), "roofline": tally.roofline(),
+           "threads": b.threads(), "grid": info["grid"],
            "pr_block_edges_per_graph": {els[i].name: int(c) for i, c in enumerate(b.pr_block_edges()) if c},
            "barrier_fraction_of_workgroup_time": round(float(
                (bar * wgs).sum() / max(float((info["task_ms"] * wgs).sum()), 1e-9)), 4),
@@ -1346,6 +1381,9 @@ def run_batched(args, torch, dev):
     wgs = info["workgroups"].astype(np.float64)
     is_bfs = np.array([t["algorithm"] == gi.ALG_BFS for t in tasks])
     value = edges / t_batch / 1e9
+    tally = KernelTally(POOL_KERNEL)
+    tally.add(kms, [pool_launch_bytes(gi, graphs, els, tasks, ref)] * len(kms))
+    roof = tally.roofline()
     slow = np.argsort(-info["task_ms"])[:5]
     detail = {"plain_ms": round(t_plain * 1e3, 3), "batched_ms": round(t_batch * 1e3, 3),
               "batched_kernel_ms_median": round(float(np.median(kms)), 3),
@@ -1379,7 +1417,7 @@ def run_batched(args, torch, dev):
               "launch_overhead_fraction": round(max(0.0, 1.0 - float(np.median(kms)) / (t_batch * 1e3)), 4)}
     config = {"workload": "batched256_bfs_pr20_rmat10-18_grid64-1024", "instances": 256,
               "graphs": [el.name for el in els]}
-    return value, "GTEPS", t_batch * 1e3, "int32 / f32+f64", config, None, None, detail
+    return value, "GTEPS", t_batch * 1e3, "int32 / f32+f64", config, roof, None, detail
 
 
 def run_prdelta(args, torch, dev):

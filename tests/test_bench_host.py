@@ -163,3 +163,52 @@ def test_pull_scan_replay_matches_brute_force():
                 assert got[k] == _brute_pull_scan(og.inc.off, og.inc.idx, level, k), (el.name, s, k)
             # only the steps marked as pulls are replayed
             assert set(rep.step_edges(level, [0, 2] + [0] * (steps - 2))) == {1}
+
+
+def test_pool_launch_bytes_bfs_and_pagerank():
+    """The pool's launch bytes: a BFS task's levels under the hybrid rule at
+    divisor 20 with CSC-order pull scans, plus 20 (4m + 16n) per PageRank
+    task, on a path (push only) and a star (one pull level)."""
+    import types
+    import numpy as np
+    import graphgen as gg
+    import paper_1805_00923_amd as gi
+    path, star = gg.path(6), gg.star(9)
+    els = [path, star]
+
+    def host_graph(el):
+        off, idx, _ = gi.build_adjacency(el.n, el.src, el.dst)
+        return types.SimpleNamespace(n=el.n, m=int(off[-1]), out_off=off)
+    graphs = [host_graph(el) for el in els]
+    Out = types.SimpleNamespace
+    arr = lambda a: Out(cpu=lambda: Out(numpy=lambda: np.asarray(a, np.int32)))
+    tasks = [dict(graph=0, algorithm=gi.ALG_BFS), dict(graph=1, algorithm=gi.ALG_BFS),
+             dict(graph=0, algorithm=gi.ALG_PAGERANK)]
+    outs = [arr([0, 1, 2, 3, 4, 5]), arr([0] + [1] * 8), None]
+    got = bench.pool_launch_bytes(gi, graphs, els, tasks, outs)
+    # path 0->1->...->5, m = 5: level k holds one vertex of out-degree 1 (the
+    # last none); (1 + 1) * 20 > 5 pulls every level but the last
+    n0, m0 = 6, 5
+    lv0 = np.arange(6)
+    fs0 = np.ones(6, np.int64)
+    ds0 = np.array([1, 1, 1, 1, 1, 0])
+    dirs0 = [2 if (fs0[k] + ds0[k]) * 20 > m0 else 0 for k in range(6)]
+    ioff0, iidx0, _ = gi.build_adjacency(path.n, path.dst, path.src)
+    es0 = [0] * 6
+    for k, e in bench.PullScanReplay(ioff0, iidx0).step_edges(lv0, dirs0).items():
+        es0[k] = e
+    want = sum(bench.bfs_step_bytes(n0, dirs0, fs0, ds0, es0))
+    # star 0 -> 1..8, m = 8: level 0 has degree 8, (1 + 8) * 20 > 8 pulls;
+    # level 1 has no out-edges and 8 * 20 > 8 pulls too
+    lv1 = np.array([0] + [1] * 8)
+    fs1 = np.array([1, 8])
+    ds1 = np.array([8, 0])
+    dirs1 = [2, 2]
+    ioff1, iidx1, _ = gi.build_adjacency(star.n, star.dst, star.src)
+    es1 = [0, 0]
+    for k, e in bench.PullScanReplay(ioff1, iidx1).step_edges(lv1, dirs1).items():
+        es1[k] = e
+    assert es1 == [8, 0]  # each leaf stops at its only in-edge; nothing left after
+    want += sum(bench.bfs_step_bytes(9, dirs1, fs1, ds1, es1))
+    want += 20 * (4 * m0 + 16 * n0)
+    assert got == want
