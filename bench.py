@@ -204,6 +204,28 @@ def cc_step_bytes(n, dirs, fs, ds, es):
     return out
 
 
+def prdelta_round_bytes(n, m, dirs, fs, ds):
+    """Per-round bytes of PageRankDelta (fp64 vertex data).
+      DensePull   4(n+1) + 4m + 8n + 8n   (offsets, index stream, each source's
+                                          contribution once, DeltaSum written)
+      SparsePush  12|F| + 12 D_F + n/8    (ids, offsets and contributions of
+                                          the active sources, index stream and
+                                          fp64 atomic add per edge, frontier)
+      vertex update, every round: 52n + n/8 (DeltaSum, Rank and out-degree
+                                          read; DeltaSum cleared, Delta, Rank
+                                          and the next contribution written;
+                                          next frontier)"""
+    out = []
+    for i in range(len(fs)):
+        f, d = int(fs[i]), int(ds[i])
+        if dirs[i] == 2:
+            step = 4 * (n + 1) + 4 * m + 16 * n
+        else:
+            step = 12 * f + 12 * d + n // 8
+        out.append(step + 52 * n + n // 8)
+    return out
+
+
 def sssp_label_setting_bytes(m_reach, n_reach):
     """Algorithmic bytes of one SSSP run: the label-setting minimum, which
     relaxes every edge out of a reached vertex once (index, weight, target
@@ -1447,6 +1469,11 @@ def run_prdelta(args, torch, dev):
     st = g.stats()
     dirs, fs, ds = st.trace()
     value = edges / dt / 1e9
+    # roofline per run: every kernel of the 10 rounds (frontier bookkeeping
+    # included) against the rounds' algorithmic bytes
+    tally = KernelTally("prdelta run (all kernels of its rounds)")
+    tally.add(kms, [sum(prdelta_round_bytes(g.n, g.m, dirs, fs, ds))] * len(kms))
+    roof = tally.roofline()
     detail = {"rounds": int(st.steps), "directions": [int(x) for x in dirs],
               "frontiers": [int(x) for x in fs], "run_ms_median": round(float(np.median(kms)), 3)}
     cpu = None
@@ -1461,7 +1488,7 @@ def run_prdelta(args, torch, dev):
                                            "thread, %.2f s (edges counted as on the GPU)" % dtc}
     config = {"workload": "prdelta10_eps0.1_rmat22_ef16", "n": g.n, "m": g.m,
               "schedule": g.schedule().as_dict()}
-    return value, "GTEPS", dt * 1e3 / args.steps, "f64", config, None, cpu, detail
+    return value, "GTEPS", dt * 1e3 / args.steps, "f64", config, roof, cpu, detail
 
 
 def run_bc(args, torch, dev):

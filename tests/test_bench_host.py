@@ -212,3 +212,13 @@ def test_pool_launch_bytes_bfs_and_pagerank():
     want += sum(bench.bfs_step_bytes(9, dirs1, fs1, ds1, es1))
     want += 20 * (4 * m0 + 16 * n0)
     assert got == want
+
+
+def test_prdelta_round_bytes_by_hand():
+    """PageRankDelta's round bytes on n = 64, m = 100: a pull round and a
+    push round of 3 active vertices with 7 out-edges, each with the vertex
+    update of every round."""
+    n, m = 64, 100
+    got = bench.prdelta_round_bytes(n, m, [2, 0], [64, 3], [100, 7])
+    update = 52 * 64 + 8
+    assert got == [4 * 65 + 400 + 16 * 64 + update, 36 + 84 + 8 + update]
