@@ -412,7 +412,10 @@ gi_status gi_bc(gi_graph* g, int32_t src, double* dependency, double* sigma, voi
  *   (x_{k+1} = 0 when ||y|| = 0).
  * fused = 1: one pass over the in-edges per iteration gathers both values
  * of each source from one array of (contribution, x) pairs; fused = 0: two
- * passes over separate arrays.  Results agree either way.
+ * passes over separate arrays.  Results agree either way.  With fused = 1
+ * and the schedule's vertex_order = GI_ORDER_OUT_DEGREE the fused pass runs
+ * over the degree-ordered in-adjacency (built on first use, shared with
+ * gi_pagerank) and the results are written back under the caller's ids.
  *   ranks, eigen   device out, n floats each.
  * Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
 gi_status gi_pagerank_eigenvector(gi_graph* g, int32_t iters, float damping, float* ranks,

@@ -307,6 +307,15 @@ struct gi_graph {
   int prec_nlong = 0;
   float2* prec_aos = nullptr;  // 2 n pairs
   float* prec_y = nullptr;     // 2 n
+  // the fused pass over the degree-ordered in-adjacency: its blocks, long
+  // rows and sum slots, and the results before they return to caller ids
+  // (2 n floats); built on first use, freed with the ordered copy
+  int4* preco_tab = nullptr;
+  int preco_ntab = 0;
+  int32_t* preco_lrow = nullptr;
+  double* preco_lacc = nullptr;
+  int preco_nlong = 0;
+  float* preco_tmp = nullptr;
   double* prec_norm = nullptr;
   int prec_norm_cap = 0;
   double* prd = nullptr;  // PageRankDelta: delta, contrib, dsum (3 n doubles)
@@ -2403,20 +2412,63 @@ extern "C" gi_status gi_pagerank_eigenvector(gi_graph* g, int32_t iters, float d
     if ((st = dev_alloc(g, g->allocs, &g->prec_norm, (size_t)cap)) != GI_OK) return st;
     g->prec_norm_cap = cap;
   }
+  // the fused pass over the degree-ordered in-adjacency (vertex_order =
+  // GI_ORDER_OUT_DEGREE): the same kernel over the ordered rows, pairs and
+  // out-degrees in the new numbering, results returned to the caller's ids
+  const bool ordered = fused && g->sched.vertex_order == GI_ORDER_OUT_DEGREE;
+  if (ordered) {
+    if ((st = ensure_pr_order(g)) != GI_OK) return st;
+    if (!g->preco_tab) {
+      std::vector<int32_t> lrow;
+      std::vector<int4> tab =
+          make_prec_table(g->h_ord_off.data(), g->n, kPrEcCapE, kPrEcCapV, &lrow);
+      const size_t nl = std::max<size_t>(1, lrow.size());
+      int32_t* d_lrow = nullptr;
+      double* d_lacc = nullptr;
+      int4* d_tab = nullptr;
+      float* d_tmp = nullptr;
+      if ((st = dev_alloc(g, g->ord_allocs, &d_lrow, nl)) != GI_OK ||
+          (st = dev_alloc(g, g->ord_allocs, &d_lacc, 2 * nl)) != GI_OK ||
+          (st = dev_alloc(g, g->ord_allocs, &d_tab, std::max<size_t>(1, tab.size()))) != GI_OK ||
+          (st = dev_alloc(g, g->ord_allocs, &d_tmp, 2 * N)) != GI_OK)
+        return st;
+      if (!lrow.empty() && (st = upload(lrow.data(), d_lrow, lrow.size() * sizeof(int32_t))) != GI_OK)
+        return st;
+      HIP_TRY(hipMemset(d_lacc, 0, sizeof(double) * 2 * nl));
+      if (!tab.empty() && (st = upload(tab.data(), d_tab, tab.size() * sizeof(int4))) != GI_OK)
+        return st;
+      g->preco_lrow = d_lrow;
+      g->preco_lacc = d_lacc;
+      g->preco_tmp = d_tmp;
+      g->preco_nlong = (int)lrow.size();
+      g->preco_ntab = (int)tab.size();
+      g->preco_tab = d_tab;
+    }
+  }
+  const int32_t* outdeg = ordered ? g->ord_outdeg : g->outdeg;
   PrVertex pv;
-  pv.outdeg = g->outdeg;
+  pv.outdeg = outdeg;
   pv.alpha = (double)damping;
   pv.base = (1.0 - (double)damping) / (double)g->n;
   PrEcArgs a;
-  a.rb = RowBlocks{g->prec_tab, g->prec_ntab, g->in_off, g->in_idx};
-  a.lacc = g->prec_lacc;
-  a.lrow = g->prec_lrow;
-  a.nlong = g->prec_nlong;
+  if (ordered) {
+    a.rb = RowBlocks{g->preco_tab, g->preco_ntab, g->ord_off, g->ord_idx};
+    a.lacc = g->preco_lacc;
+    a.lrow = g->preco_lrow;
+    a.nlong = g->preco_nlong;
+  } else {
+    a.rb = RowBlocks{g->prec_tab, g->prec_ntab, g->in_off, g->in_idx};
+    a.lacc = g->prec_lacc;
+    a.lrow = g->prec_lrow;
+    a.nlong = g->prec_nlong;
+  }
   a.pv = pv;
+  float* ranks_out = ordered ? g->preco_tmp : ranks;  // last iteration's ranks
+  float* eigen_out = ordered ? g->preco_tmp + N : eigen;
   int launches = 0;
   HIP_TRY(hipEventRecord(g->ev[0], s));
   if (fused) {
-    LAUNCH_TRY(launch_prec_init(g->n, g->outdeg, g->prec_aos, nullptr, g->prec_norm, iters + 1, s));
+    LAUNCH_TRY(launch_prec_init(g->n, outdeg, g->prec_aos, nullptr, g->prec_norm, iters + 1, s));
   } else {
     LAUNCH_TRY(launch_pr_init(g->n, g->outdeg, g->contrib[0], ranks, iters == 0, s));
     LAUNCH_TRY(launch_prec_init(g->n, g->outdeg, nullptr, g->prec_y, g->prec_norm, iters + 1, s));
@@ -2438,7 +2490,7 @@ extern "C" gi_status gi_pagerank_eigenvector(gi_graph* g, int32_t iters, float d
     if (fused) {
       a.aos_in = g->prec_aos + (k & 1) * N;
       a.aos_out = g->prec_aos + ((k + 1) & 1) * N;
-      a.ranks = last ? ranks : nullptr;
+      a.ranks = last ? ranks_out : nullptr;
       LAUNCH_TRY(launch_prec_rows(a, true, s));
       launches += a.nlong > 0 ? 2 : 1;
     } else {
@@ -2456,8 +2508,14 @@ extern "C" gi_status gi_pagerank_eigenvector(gi_graph* g, int32_t iters, float d
   }
   LAUNCH_TRY(launch_ec_final(g->n, fused ? nullptr : g->prec_y + (iters & 1) * N,
                              fused ? g->prec_aos + (iters & 1) * N : nullptr,
-                             g->prec_norm + iters, eigen, s));
+                             g->prec_norm + iters, eigen_out, s));
   ++launches;
+  if (ordered) {
+    // with no iteration the ranks are x_0, already written under caller ids
+    LAUNCH_TRY(launch_prec_remap(g->n, g->ord_old, iters > 0 ? ranks_out : nullptr, ranks,
+                                 eigen_out, eigen, s));
+    ++launches;
+  }
   HIP_TRY(hipEventRecord(g->ev[1], s));
   HIP_TRY(hipStreamSynchronize(s));
   if (g->timing_failed) return fail(GI_ERR_DEVICE, "could not create timing events");

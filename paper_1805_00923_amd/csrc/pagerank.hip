@@ -299,6 +299,17 @@ __global__ void k_ec_final(int n, const float* y, const float2* aos, const doubl
   }
 }
 
+// Results of a run over the degree-ordered numbering back under the
+// caller's ids: out[old_id[r]] = tmp[r] (a and b; a may be skipped).
+__global__ void k_prec_remap(int n, const int32_t* old_id, const float* ta, float* oa,
+                             const float* tb, float* ob) {
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const int v = old_id[r];
+    if (ta) oa[v] = ta[r];
+    ob[v] = tb[r];
+  }
+}
+
 // ------------------------------------------------------- host launchers ----
 
 static size_t pr_lds_bytes(int cap_e, int cap_v) {
@@ -377,6 +388,14 @@ int launch_prec_init(int n, const int32_t* outdeg, float2* aos, float* y, double
   const int blocks = (int)std::min<long long>(2048, ((long long)n + 255) / 256);
   hipLaunchKernelGGL(k_prec_init, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, n, outdeg, aos,
                      y, norm2, nnorm);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_prec_remap(int n, const int32_t* old_id, const float* ta, float* oa, const float* tb,
+                      float* ob, hipStream_t s) {
+  const int blocks = (int)std::min<long long>(2048, ((long long)n + 255) / 256);
+  hipLaunchKernelGGL(k_prec_remap, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, n, old_id, ta,
+                     oa, tb, ob);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

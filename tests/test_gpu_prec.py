@@ -68,6 +68,30 @@ def test_prec_matches_oracle(fused, iters):
         assert g.stats().algorithm == 6
 
 
+@pytest.mark.parametrize("iters", [0, 1, 3, 20])
+def test_prec_fused_degree_ordered_matches_oracle(iters):
+    """The fused pass over the degree-ordered in-adjacency (vertex_order = 1)
+    returns the ranks and the eigenvector under the caller's vertex ids,
+    within the same tolerances, and agrees with the id-order fused pass."""
+    for el, g, og in graphs():
+        say("prec ordered %s iters=%d" % (el.name, iters))
+        ri, ei = run(g, iters, True)
+        g.set_schedule(vertex_order=1)
+        try:
+            r, e = run(g, iters, True)
+        finally:
+            g.set_schedule(vertex_order=0)
+        pr = oracle.pagerank(og, iters, 0.85)
+        ec = oracle.eigenvector(og, iters)
+        assert pr_max_rel(r, pr) <= PR_RTOL, el.name
+        assert np.max(np.abs(r - ri) / np.maximum(np.abs(ri), 1e-30)) <= 2 * PR_RTOL, el.name
+        if np.all(ec == 0.0):
+            assert np.all(e == 0.0), el.name
+        else:
+            assert ec_err(e, ec) <= EC_TOL, (el.name, ec_err(e, ec))
+            assert ec_err(e, ei.astype(np.float64)) <= EC_TOL, el.name
+
+
 def test_prec_fused_equals_unfused_and_pagerank():
     """The fused pass changes the memory layout, not the values: both
     variants agree to FP32 rounding, and the PageRank part agrees with
