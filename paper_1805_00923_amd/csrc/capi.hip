@@ -1710,6 +1710,14 @@ static gi_status pr_ord_shape(gi_graph* g, PrOrdShape* sh) {
 }
 
 // DensePull PageRank over the degree-ordered in-adjacency (pr_order.hip).
+namespace gi {
+// Writes a run's results computed in the degree-ordered numbering back under
+// the caller's ids (pagerank.hip): oa[old_id[r]] = ta[r] (when ta is set),
+// ob[old_id[r]] = tb[r].
+int launch_prec_remap(int n, const int32_t* old_id, const float* ta, float* oa, const float* tb,
+                      float* ob, hipStream_t s);
+}  // namespace gi
+
 // The ordered run's launches: contributions from the ranks' initial value,
 // then per iteration the pass and the split rows' finish (the last
 // iteration writes the ranks).  With `events`, each iteration is bracketed

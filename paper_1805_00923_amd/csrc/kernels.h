@@ -332,8 +332,6 @@ constexpr int kPrEcCapV = 1024;
 int launch_prec_rows(const PrEcArgs& a, bool fused, hipStream_t s);  // + long-row finish
 int launch_prec_init(int n, const int32_t* outdeg, float2* aos, float* y, double* norm2,
                      int nnorm, hipStream_t s);
-int launch_prec_remap(int n, const int32_t* old_id, const float* ta, float* oa, const float* tb,
-                      float* ob, hipStream_t s);
 int launch_ec_final(int n, const float* y, const float2* aos, const double* norm2, float* out,
                     hipStream_t s);
 

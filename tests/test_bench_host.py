@@ -222,3 +222,26 @@ def test_prdelta_round_bytes_by_hand():
     got = bench.prdelta_round_bytes(n, m, [2, 0], [64, 3], [100, 7])
     update = 52 * 64 + 8
     assert got == [4 * 65 + 400 + 16 * 64 + update, 36 + 84 + 8 + update]
+
+
+def test_profile_figures_match_the_kernel_sources():
+    """Every counter figure committed under profiles/ was taken on the kernel
+    sources as they are: the sha256 of the sources a block lists equals the
+    one it records (a kernel changed since its counters were taken would have
+    the benchmark report its traffic as null)."""
+    import glob
+    import hashlib
+    import os
+    import re
+    blocks = []
+    for path in sorted(glob.glob(os.path.join(bench.ROOT, "profiles", "*.md"))):
+        for b in re.findall(r"<!-- figures.*?-->", open(path).read(), re.S):
+            blocks.append((os.path.basename(path), dict(re.findall(r"^(\w+): (.+)$", b, re.M))))
+    assert blocks
+    for name, kv in blocks:
+        h = hashlib.sha256()
+        for f in kv["sources"].split():
+            with open(os.path.join(bench.ROOT, "paper_1805_00923_amd", "csrc", f), "rb") as fh:
+                h.update(fh.read())
+        assert h.hexdigest() == kv["source_sha256"], (name, kv.get("kernel"), kv.get("plan"))
+        assert int(kv["traffic_bytes_per_launch"]) > 0, name
