@@ -1742,6 +1742,8 @@ static int pr_ord_enqueue(gi_graph* g, const PrOrdArgs& a, const PrOrdShape& sh,
 }
 
 static void pr_drop_graph(gi_graph* g) {
+  // a replay may still run on the graph's stream
+  if (g->prg_exec && g->prg_stream) (void)hipStreamSynchronize(g->prg_stream);
   if (g->prg_exec) (void)hipGraphExecDestroy(g->prg_exec);
   if (g->prg_graph) (void)hipGraphDestroy(g->prg_graph);
   g->prg_exec = nullptr;
